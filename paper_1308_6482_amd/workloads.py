@@ -1,0 +1,291 @@
+"""Seeded synthetic suspensions shaped like the paper's workloads.
+
+The paper (Sec. IV) simulates spheres and spheroids (aspect ratios 1/3 and
+3, radii of a few lattice units) at volume fractions 0.1-0.5 in periodic
+boxes, sheared; it uses no public dataset.  These generators produce inputs
+of that shape.  They hold none of the lubrication method's arithmetic: the
+only geometry here is an overlap test for placement, the Perram-Wertheim
+contact function of two ellipsoids (a 1-D concave maximisation), which the
+method itself never uses.
+
+Every array is float64, C-contiguous:
+  r    (n,3) centres          q (n,4) unit quaternions (w,x,y,z), body z =
+  semi (n,2) (R_par, R_perp)  symmetry axis
+  v    (n,3) velocities       w (n,3) angular velocities
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# cut-offs of the paper's sphere validation (Eq. results:cutoffs) with the
+# normal cut-off written as 0.67 lattice units
+DELTA_N, DELTA_T, DELTA_R = 0.67, 0.5, 0.25
+MU = 1.0 / 6.0          # tau = 1, rho = 1
+H_C, EPS_C = 0.01, 100.0  # production contact parameters (Sec. IV.C)
+
+
+@dataclass
+class Workload:
+    name: str
+    r: np.ndarray
+    q: np.ndarray
+    semi: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    L: tuple
+    periodic: tuple
+    n_walls: int = 0
+    wall_vel: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    params: dict = field(default_factory=lambda: dict(
+        mu=MU, delta_n=DELTA_N, delta_t=DELTA_T, delta_r=DELTA_R, h_c=H_C,
+        eps_c=EPS_C))
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.r.shape[0]
+
+    def domain(self) -> dict:
+        return dict(L=self.L, periodic=self.periodic, n_walls=self.n_walls,
+                    wall_vel=self.wall_vel)
+
+    def with_params(self, **kw) -> "Workload":
+        p = dict(self.params)
+        p.update(kw)
+        return Workload(self.name, self.r, self.q, self.semi, self.v, self.w,
+                        self.L, self.periodic, self.n_walls, self.wall_vel, p,
+                        dict(self.meta))
+
+
+# ---------------------------------------------------------------------------
+# elementary random draws
+# ---------------------------------------------------------------------------
+
+def random_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform on SO(3): normalised 4-D Gaussian, sign fixed to w >= 0."""
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1.0
+    return q
+
+
+def quat_matrix(q: np.ndarray) -> np.ndarray:
+    """Rotation matrices (n,3,3) of unit quaternions (w,x,y,z)."""
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((q.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def shape_matrices(q: np.ndarray, semi: np.ndarray) -> np.ndarray:
+    """Q diag(R_perp^2, R_perp^2, R_par^2) Q^T for each particle."""
+    R = quat_matrix(q)
+    d2 = np.stack([semi[:, 1] ** 2, semi[:, 1] ** 2, semi[:, 0] ** 2], axis=1)
+    return np.einsum("nik,nk,njk->nij", R, d2, R)
+
+
+def shear_velocities(rng: np.random.Generator, r: np.ndarray,
+                     gamma_dot: float = 1e-3, sigma: float = 1e-4):
+    """Simple shear v = gamma_dot z x + noise, omega = gamma_dot/2 y + noise
+    (the vorticity of the shear field)."""
+    n = r.shape[0]
+    v = rng.normal(scale=sigma, size=(n, 3))
+    v[:, 0] += gamma_dot * r[:, 2]
+    w = rng.normal(scale=sigma, size=(n, 3))
+    w[:, 1] += gamma_dot / 2.0
+    return v, w
+
+
+# ---------------------------------------------------------------------------
+# Perram-Wertheim overlap test
+# ---------------------------------------------------------------------------
+
+def pw_contact(d: np.ndarray, MA: np.ndarray, MB: np.ndarray,
+               iters: int = 48) -> np.ndarray:
+    """max over l in [0,1] of l(1-l) d^T [(1-l) MA + l MB]^{-1} d for each
+    row (Perram & Wertheim 1985).  The ellipsoids x^T MA^{-1} x <= 1 and
+    (x-d)^T MB^{-1} (x-d) <= 1 overlap iff the value is < 1.  Golden-section
+    search: the value returned never exceeds the true maximum."""
+    def F(lam):
+        Cm = (1 - lam)[:, None, None] * MA + lam[:, None, None] * MB
+        x = np.linalg.solve(Cm, d[..., None])[..., 0]
+        return lam * (1 - lam) * np.einsum("ni,ni->n", d, x)
+
+    g = (np.sqrt(5.0) - 1.0) / 2.0
+    a = np.zeros(d.shape[0])
+    b = np.ones(d.shape[0])
+    for _ in range(iters):
+        c1 = b - g * (b - a)
+        c2 = a + g * (b - a)
+        left = F(c1) > F(c2)   # concave: the maximum lies in [a, c2]
+        b = np.where(left, c2, b)
+        a = np.where(left, a, c1)
+    return F(0.5 * (a + b))
+
+
+# ---------------------------------------------------------------------------
+# random sequential addition in a box
+# ---------------------------------------------------------------------------
+
+_GEN_SO = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib",
+                       "librsagen.so")
+_gen = None
+
+
+def build_generator(force: bool = True) -> str:
+    """Compile the placement routine (csrc/rsa_gen.c) with gcc."""
+    if force or not os.path.exists(_GEN_SO):
+        os.makedirs(os.path.dirname(_GEN_SO), exist_ok=True)
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc",
+                           "rsa_gen.c")
+        tmp = _GEN_SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               src, "-o", tmp, "-lm"])
+        os.replace(tmp, _GEN_SO)
+    return _GEN_SO
+
+
+def _genlib():
+    global _gen
+    if _gen is None:
+        if not os.path.exists(_GEN_SO):
+            build_generator(force=True)
+        g = ctypes.CDLL(_GEN_SO)
+        D = ctypes.POINTER(ctypes.c_double)
+        g.rsa_create.restype = ctypes.c_void_p
+        g.rsa_create.argtypes = [ctypes.c_int64, D, D,
+                                 ctypes.POINTER(ctypes.c_int32)]
+        g.rsa_run.restype = ctypes.c_int64
+        g.rsa_run.argtypes = [ctypes.c_void_p, ctypes.c_int64, D, D,
+                              ctypes.c_double]
+        g.rsa_placed.restype = ctypes.c_int64
+        g.rsa_placed.argtypes = [ctypes.c_void_p]
+        g.rsa_fetch.argtypes = [ctypes.c_void_p, D, D]
+        g.rsa_destroy.argtypes = [ctypes.c_void_p]
+        _gen = g
+    return _gen
+
+
+def rsa(rng: np.random.Generator, semi: np.ndarray, L, periodic,
+        max_trials: int = 10_000_000, wall_margin: float = 0.0,
+        chunk: int = 65536):
+    """Random sequential addition: place the particles with the given
+    semi-axes one after the other at uniform random positions and
+    orientations, rejecting every trial that overlaps an accepted particle
+    (Perram-Wertheim test) or crosses a wall on a non-periodic axis.
+    Returns (r, q, trials); fewer particles than requested if max_trials
+    runs out."""
+    g = _genlib()
+    semi = np.ascontiguousarray(semi, dtype=np.float64)
+    n = semi.shape[0]
+    Lv = np.ascontiguousarray(L, dtype=np.float64)
+    per = np.ascontiguousarray(periodic, dtype=np.int32)
+    D = ctypes.POINTER(ctypes.c_double)
+    st = g.rsa_create(n, semi.ctypes.data_as(D), Lv.ctypes.data_as(D),
+                      per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    trials = 0
+    try:
+        while g.rsa_placed(st) < n and trials < max_trials:
+            m = min(chunk, max_trials - trials)
+            pos = np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(m, 3)))
+            quat = np.ascontiguousarray(random_quaternions(rng, m))
+            trials += g.rsa_run(st, m, pos.ctypes.data_as(D),
+                                quat.ctypes.data_as(D), float(wall_margin))
+        k = g.rsa_placed(st)
+        r = np.zeros((k, 3))
+        q = np.zeros((k, 4))
+        g.rsa_fetch(st, r.ctypes.data_as(D), q.ctypes.data_as(D))
+    finally:
+        g.rsa_destroy(st)
+    return r, q, trials
+
+
+# ---------------------------------------------------------------------------
+# the configurations
+# ---------------------------------------------------------------------------
+
+def _streams(seed: int, k: int = 4):
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(k)]
+
+
+def config1(seed: int = 0, n: int = 36) -> Workload:
+    """Equal spheres of radius 4 in a periodic 32^3 box.  64 spheres would
+    be volume fraction 0.52, beyond random sequential addition; capped at
+    0.3 the box holds 36 (0.2945).  v, omega i.i.d. N(0,1)."""
+    g_pos, g_ori, g_vel, _ = _streams(seed)
+    L = (32.0, 32.0, 32.0)
+    semi = np.full((n, 2), 4.0)
+    r, q, _ = rsa(g_pos, semi, L, (1, 1, 1))
+    if r.shape[0] != n:
+        raise RuntimeError("config1: random sequential addition ran out of trials")
+    q = random_quaternions(g_ori, n)
+    v = g_vel.normal(size=(n, 3))
+    w = g_vel.normal(size=(n, 3))
+    return Workload("spheres36_R4_L32_phi0.29", r, q, semi, v, w, L, (1, 1, 1),
+                    meta=dict(phi=n * 4.0 / 3.0 * np.pi * 64.0 / 32.0 ** 3))
+
+
+def config2(seed: int = 0, n: int = 4096, phi: float = 0.3) -> Workload:
+    """Prolate spheroids, semi-axes (8,4,4), uniform orientations, random
+    sequential addition to the volume fraction in a periodic cube;
+    simple-shear velocities."""
+    g_pos, _, g_vel, _ = _streams(seed)
+    semi = np.tile(np.array([8.0, 4.0]), (n, 1))
+    vol = n * 4.0 / 3.0 * np.pi * 8.0 * 4.0 * 4.0
+    Lx = (vol / phi) ** (1.0 / 3.0)
+    L = (Lx, Lx, Lx)
+    r, q, trials = rsa(g_pos, semi, L, (1, 1, 1))
+    if r.shape[0] != n:
+        raise RuntimeError("config2: random sequential addition ran out of trials")
+    v, w = shear_velocities(g_vel, r)
+    return Workload(f"prolates{n}_8x4x4_phi{phi}", r, q, semi, v, w, L,
+                    (1, 1, 1), meta=dict(phi=phi, rsa_trials=trials))
+
+
+def polydisperse_semi(rng: np.random.Generator, n: int, lam_lo: float,
+                      lam_hi: float, rperp_lo: float, rperp_hi: float):
+    lam = np.exp(rng.uniform(np.log(lam_lo), np.log(lam_hi), size=n))
+    rperp = rng.uniform(rperp_lo, rperp_hi, size=n)
+    return np.stack([lam * rperp, rperp], axis=1)
+
+
+def config3(seed: int = 0, n: int = 65536, phi: float = 0.4,
+            max_trials: int | None = None) -> Workload:
+    """Polydisperse spheroids (aspect ratio log-uniform in [1/3,3],
+    equatorial semi-axis uniform in [3,8]) between two walls z=0, z=L,
+    periodic in x and y, shear velocities (walls co-moving with the shear
+    field).  Placed by random sequential addition, largest first, which
+    lets the small particles fill the voids of the large ones."""
+    g_pos, g_shape, g_vel, _ = _streams(seed)
+    semi = polydisperse_semi(g_shape, n, 1.0 / 3.0, 3.0, 3.0, 8.0)
+    vol = float(np.sum(4.0 / 3.0 * np.pi * semi[:, 0] * semi[:, 1] ** 2))
+    Lx = (vol / phi) ** (1.0 / 3.0)
+    L = (Lx, Lx, Lx)
+    order = np.argsort(-semi.max(axis=1), kind="stable")
+    semi = semi[order]
+    r, q, trials = rsa(g_pos, semi, L, (1, 1, 0),
+                       max_trials=max_trials or 200 * n)
+    m = r.shape[0]
+    semi = semi[:m]
+    v, w = shear_velocities(g_vel, r)
+    gd = 1e-3
+    return Workload(f"polydisperse{n}_walls_phi{phi}", r, q, semi, v, w, L,
+                    (1, 1, 0), n_walls=2,
+                    wall_vel=((0.0, 0.0, 0.0), (gd * Lx, 0.0, 0.0)),
+                    meta=dict(phi_target=phi,
+                              phi=float(np.sum(4.0 / 3.0 * np.pi * semi[:, 0]
+                                               * semi[:, 1] ** 2)) / Lx ** 3,
+                              rsa_trials=trials, placed=m))
