@@ -1,0 +1,180 @@
+/*
+ * lub.h -- C ABI of the MI355X (gfx950) lubrication-correction library.
+ *
+ * The operation is the contact-based lubrication correction for spheres
+ * and spheroids of Janoschek, Harting & Toschi (arXiv:1308.6482), Sec. III:
+ * for every pair of particles whose centre distance is below the pruning
+ * bound of Sec. III.A, and for every particle near one of two planar walls,
+ *   1. the points of closest approach y_i*, y_j* and the signed gap h
+ *      (Sec. III.A; negative h = small overlap),
+ *   2. the local surface expansion at those points: principal directions
+ *      and radii, cubic coefficients (Eqs. lub:curvature-directions,
+ *      lub:curvature-radii, lub:surface-i, lub:surface-j, Sec. III.B),
+ *   3. the singular resistance matrix K (Appendix, Eqs. app:first-element
+ *      .. app:last-element), its cut-off correction (Eq.
+ *      lub:resistance-correction) and the contact model (Eqs. lub:frep,
+ *      lub:model),
+ *   4. the rigid-body transfer to per-particle force and torque (last
+ *      equations of Sec. III.B),
+ * summed per particle.
+ *
+ * Conventions
+ *   - Arrays are row-major float64 in DEVICE memory (HBM), e.g. the
+ *     data_ptr() of contiguous torch.cuda tensors; n may be 0.
+ *   - r[n][3]     particle centres (any value; periodic axes are wrapped
+ *                 by minimum image, wall axis z must lie in [0, L_z])
+ *   - q[n][4]     unit quaternions (w, x, y, z); x_world = Q(q) x_body; the
+ *                 body z axis is the symmetry axis (Eq. lub:spheroid)
+ *   - semi[n][2]  semi-axes (R_par along the symmetry axis, R_perp)
+ *   - v[n][3], w[n][3]  translational and angular velocities
+ *   - f[n][3], t[n][3]  OUTPUT force and torque (about the centre) on each
+ *                 particle; overwritten, not accumulated.
+ *   - Pairs are oriented (i, j) with i < j in input order; i is the first
+ *     surface (the gap vector points from i to j).  In a particle-wall pair
+ *     the particle is the first surface.  Walls are the planes z = 0
+ *     (side 0) and z = L_z (side 1).
+ *   - stream: a hipStream_t (NULL = the default stream).  All work is
+ *     enqueued on it; inputs must stay valid and unmodified until the
+ *     stream has passed the call.
+ *
+ * Ownership: the caller owns every array it passes.  The handle owns its
+ * device workspace (grown on demand) and keeps no caller pointer after the
+ * call returns.  A handle is not thread-safe; distinct handles are
+ * independent.
+ *
+ * Errors: every entry point returns LUB_OK (0) or a negative LUB_E* code;
+ * lub_strerror() names it.  Overlapping pairs, pairs that fall back or do
+ * not converge are not errors: they are counted in lub_stats_t.
+ */
+#ifndef LUB_H
+#define LUB_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LUB_OK 0
+#define LUB_EINVAL -1     /* bad argument or input value (NaN, |q|!=1, semi<=0, ...) */
+#define LUB_EDOMAIN -2    /* box too small for an unambiguous minimum image, */
+                          /* or a particle beyond a wall by more than its size */
+#define LUB_ECAPACITY -3  /* a particle has more candidates than max_neighbors */
+#define LUB_ENOMEM -4     /* device allocation failed */
+#define LUB_EDEVICE -5    /* HIP runtime error */
+
+#define LUB_FP64 0        /* every step in double precision */
+#define LUB_MIXED 1       /* FP64 closest-point solve, gap and ln h / 1/h terms; */
+                          /* FP32 geometry, resistance and transfer */
+
+#define LUB_SEED_PLAIN 0  /* Newton started from the line of centres */
+#define LUB_SEED_MLP 1    /* Newton started from the learned predictor */
+
+/* Physical parameters (Sec. III.B-C). */
+typedef struct {
+  double mu;       /* dynamic viscosity */
+  double delta_n;  /* cut-off of K33 (normal) */
+  double delta_t;  /* cut-off of all elements except K33 and K44,K45,K55 */
+  double delta_r;  /* cut-off of K44, K45, K54, K55 (rotation) */
+  double h_c;      /* clipping gap (Eq. lub:model); 0 disables clipping */
+  double eps_c;    /* Hookean contact stiffness (Eq. lub:frep) */
+} lub_params_t;
+
+/* Simulation box. */
+typedef struct {
+  double L[3];             /* box lengths */
+  int32_t periodic[3];     /* 1: periodic (minimum image), 0: bounded */
+  int32_t n_walls;         /* 0, or 2: planar walls z = 0 and z = L[2] (needs periodic[2] = 0) */
+  double wall_vel[2][3];   /* translational velocity of each wall */
+} lub_domain_t;
+
+/* Library options. */
+typedef struct {
+  int32_t device;          /* HIP device ordinal */
+  int32_t precision;       /* LUB_FP64 or LUB_MIXED */
+  int32_t seed_mode;       /* LUB_SEED_PLAIN or LUB_SEED_MLP */
+  int32_t newton_max_iter; /* iteration limit of the closest-point solve (<=0: 50) */
+  double rmax_bound;       /* upper bound of max(R_par, R_perp) over all particles; */
+                           /* sizes the cell grid.  A larger particle is LUB_EINVAL */
+  int32_t sync;            /* 1: lub_compute waits for the stream and reports input, */
+                           /* domain and capacity errors (and regrows and reruns on */
+                           /* capacity); 0: fully asynchronous, errors are reported */
+                           /* by the next lub_get_stats() */
+  int32_t timing;          /* 1: record HIP events around each pipeline stage on */
+                           /* the call's stream; totals appear in lub_stats_t */
+  int64_t max_neighbors;   /* neighbour-list entries per particle (candidate pairs */
+                           /* it takes part in), rounded up to a multiple of 64, at */
+                           /* most 512; <= 0: start at 64 and, with sync = 1, grow */
+                           /* on demand.  More candidates than that: LUB_ECAPACITY */
+} lub_opts_t;
+
+/* Per-call statistics of the last lub_compute. */
+typedef struct {
+  int64_t n;                /* particles */
+  int64_t candidates;       /* particle pairs passing the centre test */
+  int64_t wall_candidates;  /* particle-wall pairs passing the wall test */
+  int64_t evaluated;        /* pairs whose closest points were solved */
+  int64_t active;           /* pairs with a non-zero correction (incl. wall pairs) */
+  int64_t overlaps;         /* active pairs with h <= 0 */
+  int64_t unresolved;       /* h <= 0 with h_c = 0: skipped */
+  int64_t unconverged;      /* closest-point solve failed: skipped */
+  int64_t fallbacks;        /* learned seed rejected, plain seed used */
+  int64_t newton_iters;     /* total Newton iterations */
+  int32_t newton_max;       /* largest per-pair iteration count */
+  int32_t error;            /* LUB_OK or the error found by the last call */
+  int64_t iter_hist[32];    /* pairs per iteration count (last bin: >= 31) */
+  /* with opts.timing: device time summed over the timed calls since the */
+  /* handle was created or lub_reset_timers(), per stage: 0 staging and cell */
+  /* list, 1 neighbour lists and evaluation slots, 2 pair kernel, */
+  /* 3 per-particle reduction */
+  int64_t timed_calls;
+  double stage_ms[4];
+} lub_stats_t;
+
+typedef struct lub_ctx* lub_handle_t;
+
+/* Create a handle on opts->device; copies the parameters. */
+int lub_create(lub_handle_t* out, const lub_domain_t* domain,
+               const lub_params_t* params, const lub_opts_t* opts);
+
+/* Change parameters or domain between calls (no reallocation unless the
+ * cell grid grows). */
+int lub_set_params(lub_handle_t h, const lub_params_t* params);
+int lub_set_domain(lub_handle_t h, const lub_domain_t* domain);
+
+/* The correction: per-particle force f and torque t (device arrays, see
+ * the conventions above). */
+int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
+                const double* semi, const double* v, const double* w,
+                double* f, double* t, void* stream);
+
+/* Statistics of the last call (waits for the handle's last stream). */
+int lub_get_stats(lub_handle_t h, lub_stats_t* out);
+
+/* Zero the accumulated stage times (waits for the handle's last stream). */
+int lub_reset_timers(lub_handle_t h);
+
+/* Candidate lists of the last call, in input indices, written to HOST
+ * memory: particle pairs ij[k] = (i, j), i < j, sorted by (i, j); wall
+ * pairs wall[k] = (i, side) sorted.  *n_pairs / *n_wall receive the counts;
+ * LUB_ECAPACITY if a capacity is too small (counts still set). */
+int lub_get_pairs(lub_handle_t h, int64_t cap, int32_t* ij, int64_t* n_pairs,
+                  int64_t wcap, int32_t* wall, int64_t* n_wall);
+
+/* Per-pair results of the last call for every evaluated pair, HOST memory,
+ * in no particular order: ij[k] = (i, j) with j = -1 / -2 for the walls
+ * z = 0 / z = L; h[k] signed gap; F[k] force on i; Ti[k] torque on i about
+ * its centre; Tj[k] torque on j about its centre (force on j = -F);
+ * status[k]: 0 active, 1 inactive (h beyond the cut-offs), 2 unresolved
+ * overlap, 3 unconverged; iters[k] Newton iterations. */
+int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
+                         double* F, double* Ti, double* Tj, int32_t* status,
+                         int32_t* iters, int64_t* n_out);
+
+void lub_destroy(lub_handle_t h);
+const char* lub_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

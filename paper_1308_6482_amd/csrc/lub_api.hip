@@ -1,0 +1,532 @@
+// lub_api.hip -- the C ABI declared in include/lub.h: handle, device
+// workspace, the launch sequence of one evaluation, statistics and the
+// diagnostic read-backs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lub_internal.h"
+
+using namespace lub;
+
+struct lub_ctx {
+  int device = 0;
+  lub_params_t prm{};
+  lub_domain_t dom{};
+  lub_opts_t opt{};
+  hipStream_t last_stream = nullptr;
+  CallDesc last{};
+  bool have_last = false;
+
+  // workspace
+  int64_t cap_n = 0, cap_cells = 0, cap_entries = 0, cap_work = 0, cap_bs = 0;
+  int32_t cur_nbr = 64;            // neighbour-segment stride in use
+  int32_t* cell_id = nullptr;      // [n] by input index
+  int32_t* cell_count = nullptr;   // [ncell]
+  int32_t* cell_fill = nullptr;    // [ncell]
+  int32_t* cell_start = nullptr;   // [ncell + 1]
+  int32_t* sorted = nullptr;       // [n] cell order -> input index
+  int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
+  int32_t* deg = nullptr;          // [n] entries per segment
+  int32_t* block_sums = nullptr;   // scan scratch
+  int32_t* wall_slot = nullptr;    // [2n]
+  PRec* rec = nullptr;             // [n]
+  KRec* kin = nullptr;             // [n]
+  int32_t* nbr = nullptr;          // [n * cur_nbr] partner (cell order)
+  int32_t* slot = nullptr;         // [n * cur_nbr] evaluation slot, -1, -2
+  int32_t* work_s = nullptr;       // [work]
+  int32_t* work_t = nullptr;       // [work]
+  void* out = nullptr;             // [work] PairOut<double> (or float)
+  double* out_h = nullptr;         // [work]
+  int8_t* out_status = nullptr;    // [work]
+  uint8_t* out_iters = nullptr;    // [work]
+  Counters* cnt = nullptr;         // device
+  Counters* host_cnt = nullptr;    // pinned
+
+  // stage timing: five events per timed call, resolved lazily
+  std::vector<hipEvent_t> free_events;
+  std::vector<std::vector<hipEvent_t>> pending;
+  int64_t timed_calls = 0;
+  double stage_ms[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+constexpr int32_t kMaxNbr = 512;  // largest neighbour segment (8 entries per lane)
+
+int hip_err(hipError_t e) {
+  if (e == hipSuccess) return LUB_OK;
+  if (e == hipErrorOutOfMemory) return LUB_ENOMEM;
+  return LUB_EDEVICE;
+}
+
+#define HIP_TRY(x)                        \
+  do {                                    \
+    int _rc = hip_err(x);                 \
+    if (_rc != LUB_OK) return _rc;        \
+  } while (0)
+
+template <typename T>
+int grow(T** p, int64_t* cap, int64_t need) {
+  if (*p && *cap >= need) return LUB_OK;
+  if (*p) HIP_TRY(hipFree(*p));
+  *p = nullptr;
+  int64_t n = std::max<int64_t>(need, 1);
+  HIP_TRY(hipMalloc((void**)p, sizeof(T) * (size_t)n));
+  *cap = n;
+  return LUB_OK;
+}
+
+double max_cutoff(const lub_params_t& p) {
+  return std::max(p.delta_n, std::max(p.delta_t, p.delta_r));
+}
+
+int check_params(const lub_params_t* p) {
+  if (!p) return LUB_EINVAL;
+  if (!(p->mu >= 0.0) || !(p->delta_n > 0.0) || !(p->delta_t > 0.0) ||
+      !(p->delta_r > 0.0) || !(p->h_c >= 0.0) || !(p->eps_c >= 0.0))
+    return LUB_EINVAL;
+  return LUB_OK;
+}
+
+int check_domain(const lub_domain_t* d) {
+  if (!d) return LUB_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(d->L[k] > 0.0) || !std::isfinite(d->L[k])) return LUB_EINVAL;
+  if (d->n_walls != 0 && d->n_walls != 2) return LUB_EINVAL;
+  if (d->n_walls == 2 && d->periodic[2]) return LUB_EINVAL;
+  return LUB_OK;
+}
+
+// buffers sized by particle count
+int ensure_particles(lub_ctx* c, int64_t n) {
+  if (c->cap_n >= n && c->cell_id) return LUB_OK;
+  int64_t need = std::max<int64_t>(n, 1);
+  int64_t cap = 0;
+#define G(p) { int64_t tmp = 0; int rc = grow(&c->p, &tmp, need); if (rc) return rc; }
+  G(cell_id) G(sorted) G(cell_sorted) G(deg) G(rec) G(kin)
+#undef G
+  {
+    int64_t tmp = 0;
+    int rc = grow(&c->wall_slot, &tmp, 2 * need);
+    if (rc) return rc;
+  }
+  (void)cap;
+  c->cap_n = need;
+  return LUB_OK;
+}
+
+int ensure_cells(lub_ctx* c, int64_t ncell) {
+  if (c->cap_cells >= ncell && c->cell_count) return LUB_OK;
+  int64_t tmp = 0;
+  int rc;
+  if ((rc = grow(&c->cell_count, &tmp, ncell))) return rc;
+  if ((rc = grow(&c->cell_fill, &tmp, ncell))) return rc;
+  if ((rc = grow(&c->cell_start, &tmp, ncell + 1))) return rc;
+  c->cap_cells = ncell;
+  return LUB_OK;
+}
+
+// neighbour segments of stride max_nbr for n particles, and the evaluation
+// slots: at most half the entries (each pair appears in both segments) plus
+// two wall pairs per particle
+int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
+  int64_t entries = std::max<int64_t>(n, 1) * max_nbr;
+  int64_t work = entries / 2 + 2 * n + 64;
+  int rc;
+  if (c->cap_entries < entries || !c->nbr) {
+    int64_t tmp = 0;
+    if ((rc = grow(&c->nbr, &tmp, entries))) return rc;
+    if ((rc = grow(&c->slot, &tmp, entries))) return rc;
+    c->cap_entries = entries;
+  }
+  if (c->cap_work < work || !c->work_s) {
+    int64_t tmp = 0;
+    if ((rc = grow(&c->work_s, &tmp, work))) return rc;
+    if ((rc = grow(&c->work_t, &tmp, work))) return rc;
+    if ((rc = grow((PairOut<double>**)&c->out, &tmp, work))) return rc;
+    if ((rc = grow(&c->out_h, &tmp, work))) return rc;
+    if ((rc = grow(&c->out_status, &tmp, work))) return rc;
+    if ((rc = grow(&c->out_iters, &tmp, work))) return rc;
+    c->cap_work = work;
+  }
+  return LUB_OK;
+}
+
+int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
+  std::memset(d, 0, sizeof(*d));
+  d->n = (int32_t)n;
+  d->dmax = max_cutoff(c->prm);
+  double edge = 2.0 * c->opt.rmax_bound + d->dmax;
+  int64_t ncell = 1;
+  for (int k = 0; k < 3; ++k) {
+    d->L[k] = c->dom.L[k];
+    d->periodic[k] = c->dom.periodic[k];
+    // minimum image must be unambiguous for the largest pair bound
+    if (d->periodic[k] && d->L[k] < 2.0 * edge) return LUB_EDOMAIN;
+    int64_t nc = (int64_t)std::floor(d->L[k] / edge);
+    nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
+    d->nc[k] = (int32_t)nc;
+    d->cell[k] = d->L[k] / (double)nc;
+    ncell *= nc;
+  }
+  (void)ncell;
+  d->n_walls = c->dom.n_walls;
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 3; ++k) d->wall_vel[s][k] = c->dom.wall_vel[s][k];
+  d->rmax_bound = c->opt.rmax_bound;
+  d->mu = c->prm.mu;
+  d->delta_n = c->prm.delta_n;
+  d->delta_t = c->prm.delta_t;
+  d->delta_r = c->prm.delta_r;
+  d->h_c = c->prm.h_c;
+  d->eps_c = c->prm.eps_c;
+  d->max_iter = c->opt.newton_max_iter > 0 ? c->opt.newton_max_iter : 50;
+  d->max_nbr = c->cur_nbr;
+  d->precision = c->opt.precision;
+  return LUB_OK;
+}
+
+hipEvent_t take_event(lub_ctx* c) {
+  if (!c->free_events.empty()) {
+    hipEvent_t e = c->free_events.back();
+    c->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// resolve the events of finished timed calls into the stage totals
+int resolve_timing(lub_ctx* c) {
+  for (auto& ev : c->pending) {
+    HIP_TRY(hipEventSynchronize(ev[4]));
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      c->stage_ms[k] += ms;
+    }
+    c->timed_calls++;
+    for (hipEvent_t e : ev) c->free_events.push_back(e);
+  }
+  c->pending.clear();
+  return LUB_OK;
+}
+
+int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
+        const double* semi, const double* v, const double* w, double* f,
+        double* t, hipStream_t s) {
+  CallDesc d = d0;
+  d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
+  d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
+  int ncell = d.nc[0] * d.nc[1] * d.nc[2];
+  std::vector<hipEvent_t> ev;
+  const bool timing = c->opt.timing && d.n > 0;
+  if (timing) {
+    // bound the backlog of unresolved calls
+    if (c->pending.size() >= 4096) {
+      int rc = resolve_timing(c);
+      if (rc) return rc;
+    }
+    for (int k = 0; k < 5; ++k) {
+      hipEvent_t e = take_event(c);
+      if (!e) return LUB_EDEVICE;
+      ev.push_back(e);
+    }
+  }
+  auto mark = [&](int k) {
+    if (timing) hipEventRecord(ev[k], s);
+  };
+  mark(0);
+  launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  if (d.n > 0) {
+    launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
+    launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
+    launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->sorted, s);
+    launch_cell_sort(ncell, c->cell_start, c->sorted, s);
+    launch_build_records(d, c->sorted, c->cell_id, r, q, semi, v, w, c->rec,
+                         c->kin, c->cell_sorted, s);
+    mark(1);
+    launch_neighbors_wave(d, c->rec, c->sorted, c->cell_sorted, c->cell_start,
+                          c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
+                          c->work_t, c->cnt, s);
+    mark(2);
+    launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h,
+                 c->out_status, c->out_iters, c->cnt, s);
+    mark(3);
+    launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
+                  c->cnt, f, t, s);
+    mark(4);
+    if (timing) c->pending.push_back(ev);
+  }
+  HIP_TRY(hipGetLastError());
+  c->last = d;
+  c->have_last = true;
+  c->last_stream = s;
+  return LUB_OK;
+}
+
+int fetch_counters(lub_ctx* c) {
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(c->host_cnt, c->cnt, sizeof(Counters),
+                         hipMemcpyDeviceToHost, c->last_stream));
+  HIP_TRY(hipStreamSynchronize(c->last_stream));
+  return LUB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lub_create(lub_handle_t* out, const lub_domain_t* domain,
+               const lub_params_t* params, const lub_opts_t* opts) {
+  if (!out || !opts) return LUB_EINVAL;
+  *out = nullptr;
+  int rc;
+  if ((rc = check_params(params))) return rc;
+  if ((rc = check_domain(domain))) return rc;
+  if (!(opts->rmax_bound > 0.0)) return LUB_EINVAL;
+  if (opts->precision != LUB_FP64 && opts->precision != LUB_MIXED) return LUB_EINVAL;
+  if (opts->seed_mode != LUB_SEED_PLAIN) return LUB_EINVAL;
+  lub_ctx* c = new (std::nothrow) lub_ctx();
+  if (!c) return LUB_ENOMEM;
+  c->device = opts->device;
+  if (opts->max_neighbors > kMaxNbr) {
+    delete c;
+    return LUB_EINVAL;
+  }
+  c->cur_nbr = opts->max_neighbors > 0
+                   ? (int32_t)((opts->max_neighbors + 63) / 64 * 64)
+                   : 64;
+  c->prm = *params;
+  c->dom = *domain;
+  c->opt = *opts;
+  if (hipSetDevice(c->device) != hipSuccess) {
+    delete c;
+    return LUB_EDEVICE;
+  }
+  if (hipMalloc((void**)&c->cnt, sizeof(Counters)) != hipSuccess ||
+      hipHostMalloc((void**)&c->host_cnt, sizeof(Counters), 0) != hipSuccess) {
+    lub_destroy(c);
+    return LUB_ENOMEM;
+  }
+  std::memset(c->host_cnt, 0, sizeof(Counters));
+  *out = c;
+  return LUB_OK;
+}
+
+int lub_set_params(lub_handle_t h, const lub_params_t* params) {
+  if (!h) return LUB_EINVAL;
+  int rc = check_params(params);
+  if (rc) return rc;
+  h->prm = *params;
+  return LUB_OK;
+}
+
+int lub_set_domain(lub_handle_t h, const lub_domain_t* domain) {
+  if (!h) return LUB_EINVAL;
+  int rc = check_domain(domain);
+  if (rc) return rc;
+  h->dom = *domain;
+  return LUB_OK;
+}
+
+int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
+                const double* semi, const double* v, const double* w,
+                double* f, double* t, void* stream) {
+  if (!h || n < 0 || n > (int64_t)1 << 30) return LUB_EINVAL;
+  if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  CallDesc d;
+  int rc = build_desc(h, n, &d);
+  if (rc) return rc;
+  int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+  if ((rc = ensure_particles(h, n))) return rc;
+  if ((rc = ensure_cells(h, ncell))) return rc;
+  // scan scratch: one block sum per 8192 elements of the longer scan
+  if ((rc = grow(&h->block_sums, &h->cap_bs, std::max<int64_t>(ncell, n) / 1024 + 64)))
+    return rc;
+  if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
+  if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
+  if (!h->opt.sync) return LUB_OK;
+  if ((rc = fetch_counters(h))) return rc;
+  // automatic limit: widen the segments and evaluate again
+  while (h->host_cnt->error == LUB_ECAPACITY && h->opt.max_neighbors <= 0 &&
+         h->cur_nbr < kMaxNbr) {
+    h->cur_nbr = std::min(kMaxNbr, 2 * h->cur_nbr);
+    if ((rc = build_desc(h, n, &d))) return rc;
+    if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
+    if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
+    if ((rc = fetch_counters(h))) return rc;
+  }
+  return h->host_cnt->error;
+}
+
+int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
+  if (!h || !out) return LUB_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  if (!h->have_last) return LUB_OK;
+  int rc = fetch_counters(h);
+  if (rc) return rc;
+  const Counters& c = *h->host_cnt;
+  out->n = h->last.n;
+  out->candidates = c.candidates;
+  out->wall_candidates = c.wall_candidates;
+  out->evaluated = c.work;
+  out->active = c.active;
+  out->overlaps = c.overlaps;
+  out->unresolved = c.unresolved;
+  out->unconverged = c.unconverged;
+  out->fallbacks = c.fallbacks;
+  out->newton_iters = c.newton_iters;
+  out->newton_max = c.newton_max;
+  out->error = c.error;
+  for (int k = 0; k < 32; ++k) out->iter_hist[k] = c.iter_hist[k];
+  if ((rc = resolve_timing(h))) return rc;
+  out->timed_calls = h->timed_calls;
+  for (int k = 0; k < 4; ++k) out->stage_ms[k] = h->stage_ms[k];
+  return LUB_OK;
+}
+
+int lub_reset_timers(lub_handle_t h) {
+  if (!h) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  int rc = resolve_timing(h);
+  if (rc) return rc;
+  h->timed_calls = 0;
+  for (int k = 0; k < 4; ++k) h->stage_ms[k] = 0.0;
+  return LUB_OK;
+}
+
+int lub_get_pairs(lub_handle_t h, int64_t cap, int32_t* ij, int64_t* n_pairs,
+                  int64_t wcap, int32_t* wall, int64_t* n_wall) {
+  if (!h || !n_pairs || !n_wall) return LUB_EINVAL;
+  *n_pairs = 0;
+  *n_wall = 0;
+  if (!h->have_last || h->last.n == 0) return LUB_OK;
+  int rc = fetch_counters(h);
+  if (rc) return rc;
+  if (h->host_cnt->error) return h->host_cnt->error;
+  const int n = h->last.n;
+  const size_t stride = (size_t)h->last.max_nbr;
+  std::vector<int32_t> deg(n), sorted(n), wall_slot(2 * n);
+  HIP_TRY(hipMemcpy(deg.data(), h->deg, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sorted.data(), h->sorted, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  std::vector<int32_t> nbr(stride * n);
+  HIP_TRY(hipMemcpy(nbr.data(), h->nbr, sizeof(int32_t) * stride * n, hipMemcpyDeviceToHost));
+  std::vector<std::pair<int32_t, int32_t>> pairs;
+  for (int s = 0; s < n; ++s)
+    for (int k = 0; k < deg[s]; ++k) {
+      int a = sorted[s], b = sorted[nbr[stride * s + k]];
+      if (a < b) pairs.emplace_back(a, b);
+    }
+  std::sort(pairs.begin(), pairs.end());
+  *n_pairs = (int64_t)pairs.size();
+  std::vector<std::pair<int32_t, int32_t>> walls;
+  if (h->last.n_walls) {
+    HIP_TRY(hipMemcpy(wall_slot.data(), h->wall_slot, sizeof(int32_t) * 2 * n,
+                      hipMemcpyDeviceToHost));
+    for (int s = 0; s < n; ++s)
+      for (int side = 0; side < 2; ++side)
+        if (wall_slot[2 * s + side] != -1) walls.emplace_back(sorted[s], side);
+    std::sort(walls.begin(), walls.end());
+  }
+  *n_wall = (int64_t)walls.size();
+  if ((int64_t)pairs.size() > cap || (int64_t)walls.size() > wcap) return LUB_ECAPACITY;
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    ij[2 * k] = pairs[k].first;
+    ij[2 * k + 1] = pairs[k].second;
+  }
+  for (size_t k = 0; k < walls.size(); ++k) {
+    wall[2 * k] = walls[k].first;
+    wall[2 * k + 1] = walls[k].second;
+  }
+  return LUB_OK;
+}
+
+int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
+                         double* F, double* Ti, double* Tj, int32_t* status,
+                         int32_t* iters, int64_t* n_out) {
+  if (!h || !n_out) return LUB_EINVAL;
+  *n_out = 0;
+  if (!h->have_last || h->last.n == 0) return LUB_OK;
+  int rc = fetch_counters(h);
+  if (rc) return rc;
+  if (h->host_cnt->error) return h->host_cnt->error;
+  const int n = h->last.n;
+  const int m = h->host_cnt->work;
+  *n_out = m;
+  if (m > cap) return LUB_ECAPACITY;
+  if (m == 0) return LUB_OK;
+  std::vector<int32_t> sorted(n), ws(m), wt(m);
+  std::vector<double> hh(m);
+  std::vector<int8_t> st(m);
+  std::vector<uint8_t> it(m);
+  HIP_TRY(hipMemcpy(sorted.data(), h->sorted, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(ws.data(), h->work_s, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(wt.data(), h->work_t, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hh.data(), h->out_h, sizeof(double) * m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(st.data(), h->out_status, m, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(it.data(), h->out_iters, m, hipMemcpyDeviceToHost));
+  const bool mixed = h->last.precision == LUB_MIXED;
+  std::vector<double> od(9 * (size_t)m);
+  if (mixed) {
+    std::vector<float> of(9 * (size_t)m);
+    HIP_TRY(hipMemcpy(of.data(), h->out, sizeof(float) * 9 * m, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < of.size(); ++k) od[k] = of[k];
+  } else {
+    HIP_TRY(hipMemcpy(od.data(), h->out, sizeof(double) * 9 * m, hipMemcpyDeviceToHost));
+  }
+  for (int k = 0; k < m; ++k) {
+    if (ij) {
+      ij[2 * k] = sorted[ws[k]];
+      ij[2 * k + 1] = wt[k] >= 0 ? sorted[wt[k]] : wt[k];
+    }
+    if (hgap) hgap[k] = hh[k];
+    for (int c = 0; c < 3; ++c) {
+      if (F) F[3 * k + c] = od[9 * k + c];
+      if (Ti) Ti[3 * k + c] = od[9 * k + 3 + c];
+      if (Tj) Tj[3 * k + c] = od[9 * k + 6 + c];
+    }
+    if (status) status[k] = st[k];
+    if (iters) iters[k] = it[k];
+  }
+  return LUB_OK;
+}
+
+void lub_destroy(lub_handle_t h) {
+  if (!h) return;
+  hipSetDevice(h->device);
+  void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
+                  h->sorted, h->cell_sorted, h->deg, h->block_sums,
+                  h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
+                  h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
+                  h->cnt};
+  for (void* p : bufs)
+    if (p) hipFree(p);
+  if (h->host_cnt) hipHostFree(h->host_cnt);
+  for (auto& ev : h->pending)
+    for (hipEvent_t e : ev) h->free_events.push_back(e);
+  for (hipEvent_t e : h->free_events) hipEventDestroy(e);
+  delete h;
+}
+
+const char* lub_strerror(int code) {
+  switch (code) {
+    case LUB_OK: return "ok";
+    case LUB_EINVAL: return "invalid argument or input value";
+    case LUB_EDOMAIN: return "domain too small for an unambiguous minimum image, or particle beyond a wall";
+    case LUB_ECAPACITY: return "neighbour-list capacity exceeded";
+    case LUB_ENOMEM: return "device allocation failed";
+    case LUB_EDEVICE: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// lub_gather.hip -- per-particle sums of the pair forces and torques
+// (gfx950).  Sec. III.B: particle i receives f_i = F and t_i = T + (y_i -
+// r_i) x F from every pair, particle j the opposite force and -T + ... about
+// its own centre.
+//
+// No atomics: one wavefront per particle, lanes over the entries of its
+// neighbour segment (both directions of each of its pairs).  A pair's result
+// sits in the slot of the entry owned by its smaller-index particle; the
+// other particle finds that entry by binary search in its partner's sorted
+// segment.  The wave then reduces the six components with a fixed butterfly
+// in FP64, so the sums are bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "lub_internal.h"
+
+namespace lub {
+
+namespace {
+
+constexpr int kWaves = 4;
+
+__device__ __forceinline__ int find_entry(const int32_t* __restrict__ seg, int n,
+                                          int key) {
+  int lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    int v = seg[mid];
+    if (v == key) return mid;
+    if (v < key)
+      lo = mid + 1;
+    else
+      hi = mid - 1;
+  }
+  return -1;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64 * kWaves) k_gather(
+    CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ slot,
+    const int32_t* __restrict__ wall_slot, const PairOut<R>* __restrict__ out,
+    const Counters* cnt, double* __restrict__ f, double* __restrict__ t) {
+  const int lane = threadIdx.x & 63;
+  const int s = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (s >= d.n) return;  // whole wavefront
+  const size_t stride = (size_t)d.max_nbr;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  if (cnt->error == 0) {
+    const int ns = deg[s];
+    for (int k = lane; k < ns; k += 64) {
+      const size_t e = (size_t)s * stride + k;
+      const int sl = slot[e];
+      if (sl >= 0) {
+        const PairOut<R>& o = out[sl];
+        for (int c = 0; c < 3; ++c) {
+          acc[c] += (double)o.F[c];
+          acc[3 + c] += (double)o.Ti[c];
+        }
+      } else if (sl == -2) {
+        const int p = nbr[e];
+        const int kk = find_entry(nbr + (size_t)p * stride, deg[p], s);
+        const int sp = kk >= 0 ? slot[(size_t)p * stride + kk] : -1;
+        if (sp >= 0) {
+          const PairOut<R>& o = out[sp];
+          for (int c = 0; c < 3; ++c) {
+            acc[c] -= (double)o.F[c];
+            acc[3 + c] += (double)o.Tj[c];
+          }
+        }
+      }
+    }
+    if (d.n_walls && lane >= 62) {
+      const int ws = wall_slot[2 * s + (lane - 62)];
+      if (ws >= 0) {
+        const PairOut<R>& o = out[ws];
+        for (int c = 0; c < 3; ++c) {
+          acc[c] += (double)o.F[c];
+          acc[3 + c] += (double)o.Ti[c];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1)
+    for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
+  if (lane == 0) {
+    const int p = orig[s];
+    for (int c = 0; c < 3; ++c) {
+      f[3 * p + c] = acc[c];
+      t[3 * p + c] = acc[3 + c];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
+                   const int32_t* nbr, const int32_t* slot,
+                   const int32_t* wall_slot, const void* out,
+                   const Counters* cnt, double* f, double* t, hipStream_t s) {
+  if (d.n == 0) return;
+  dim3 grid((d.n + kWaves - 1) / kWaves);
+  if (d.precision == LUB_MIXED)
+    hipLaunchKernelGGL(k_gather<float>, grid, dim3(64 * kWaves), 0, s, d, orig,
+                       deg, nbr, slot, wall_slot, (const PairOut<float>*)out,
+                       cnt, f, t);
+  else
+    hipLaunchKernelGGL(k_gather<double>, grid, dim3(64 * kWaves), 0, s, d, orig,
+                       deg, nbr, slot, wall_slot, (const PairOut<double>*)out,
+                       cnt, f, t);
+}
+
+}  // namespace lub

@@ -1,0 +1,594 @@
+// lub_neighbors.hip -- staging, cell list and neighbour lists (gfx950).
+//
+// Candidate pairs follow the pruning of Sec. III.A of the paper: a pair is a
+// candidate when its minimum-image centre distance is below
+// R_max,i + R_max,j + (largest cut-off).  That test is evaluated in IEEE
+// double with FP contraction switched off so that it is reproducible bit for
+// bit.  A second, exact reject (a lower bound of the gap from the support
+// functions along the line of centres) removes candidates that can never be
+// lubrication-active before the closest-point solve.
+//
+// Layout: particles are binned into a uniform grid (cell edge >= 2 R_max +
+// largest cut-off) with a counting sort; every per-particle record is stored
+// in cell order so that neighbour loads of a wavefront hit few cache lines.
+// The neighbour list holds both directions of every pair, one fixed-stride
+// segment per particle (cell-order indices), each segment sorted by partner
+// index; the pair (i, j) is evaluated once, from the entry whose owner has
+// the smaller input index.
+#include <hip/hip_runtime.h>
+
+#include "lub_internal.h"
+
+namespace lub {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int cell_coord(double x, double L, int periodic,
+                                          double edge, int nc) {
+  if (periodic) x = x - L * floor(x / L);
+  int c = (int)floor(x / edge);
+  c = c < 0 ? 0 : c;
+  c = c >= nc ? nc - 1 : c;
+  return c;
+}
+
+__device__ __forceinline__ void set_error(Counters* cnt, int code) {
+  atomicCAS(&cnt->error, 0, code);
+}
+
+// Exact centre test: minimum-image squared distance below the squared
+// pruning bound, evaluated in a fixed order without contraction.
+__device__ __forceinline__ bool centre_test(const double* ri, const double* rj,
+                                            double rmi, double rmj,
+                                            const CallDesc& d) {
+#pragma clang fp contract(off)
+  double dx = rj[0] - ri[0];
+  double dy = rj[1] - ri[1];
+  double dz = rj[2] - ri[2];
+  if (d.periodic[0]) dx = dx - d.L[0] * rint(dx / d.L[0]);
+  if (d.periodic[1]) dy = dy - d.L[1] * rint(dy / d.L[1]);
+  if (d.periodic[2]) dz = dz - d.L[2] * rint(dz / d.L[2]);
+  double d2 = dx * dx + dy * dy;
+  d2 = d2 + dz * dz;
+  double sb = (rmi + rmj) + d.dmax;
+  return d2 < sb * sb;
+}
+
+// Inclusive scan of one int per thread across a block of up to 1024 threads.
+__device__ int block_inclusive_scan(int x, int* lds, int* total) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63 || threadIdx.x == blockDim.x - 1) lds[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    int v = lane < nw ? lds[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(v, o, 64);
+      if (lane >= o) v += y;
+    }
+    if (lane < nw) lds[lane] = v;
+  }
+  __syncthreads();
+  int res = x + (wid > 0 ? lds[wid - 1] : 0);
+  *total = lds[nw - 1];
+  __syncthreads();
+  return res;
+}
+
+__global__ void k_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
+                        int ncell) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncell) {
+    cell_count[i] = 0;
+    cell_fill[i] = 0;
+  }
+  if (i < (int)(sizeof(Counters) / sizeof(int32_t)))
+    reinterpret_cast<int32_t*>(c)[i] = 0;
+}
+
+// validate one particle's input, bin it
+__global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
+                            const double* __restrict__ q,
+                            const double* __restrict__ semi,
+                            int32_t* __restrict__ cell_id,
+                            int32_t* __restrict__ cell_count, Counters* cnt) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
+  double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
+  double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
+  double a = semi[2 * p], b = semi[2 * p + 1];
+  bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qw) &&
+            isfinite(qx) && isfinite(qy) && isfinite(qz) && a > 0.0 && b > 0.0 &&
+            isfinite(a) && isfinite(b);
+  double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  ok = ok && fabs(qn - 1.0) <= 1e-6 && fmax(a, b) <= d.rmax_bound;
+  if (!ok) set_error(cnt, LUB_EINVAL);
+  double rm = fmax(a, b);
+  if (d.n_walls && (z < -rm || z > d.L[2] + rm)) set_error(cnt, LUB_EDOMAIN);
+  int cx = cell_coord(x, d.L[0], d.periodic[0], d.cell[0], d.nc[0]);
+  int cy = cell_coord(y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
+  int cz = cell_coord(z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
+  if (!ok) cx = cy = cz = 0;
+  int c = (cz * d.nc[1] + cy) * d.nc[0] + cx;
+  cell_id[p] = c;
+  atomicAdd(&cell_count[c], 1);
+}
+
+// exclusive scan, tile level; single-tile case writes the total directly
+__global__ void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                            int n, int32_t* __restrict__ block_sums,
+                            int64_t* total) {
+  __shared__ int lds[16];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int idx = base + k;
+    v[k] = idx < n ? in[idx] : 0;
+    s += v[k];
+  }
+  int tot;
+  int incl = block_inclusive_scan(s, lds, &tot);
+  int run = incl - s;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int idx = base + k;
+    if (idx < n) out[idx] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) {
+    block_sums[blockIdx.x] = tot;
+    if (gridDim.x == 1) {
+      out[n] = tot;
+      if (total) *total = tot;
+    }
+  }
+}
+
+__global__ void k_scan_top(int32_t* block_sums, int nb, int32_t* out, int n,
+                           int64_t* total) {
+  __shared__ int lds[16];
+  const int base = threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < nb ? block_sums[base + k] : 0;
+    s += v[k];
+  }
+  int tot;
+  int incl = block_inclusive_scan(s, lds, &tot);
+  int run = incl - s;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < nb) block_sums[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) {
+    out[n] = tot;
+    if (total) *total = tot;
+  }
+}
+
+__global__ void k_scan_add(int32_t* out, int n, const int32_t* block_sums) {
+  int add = block_sums[blockIdx.x];
+  const int base = blockIdx.x * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += blockDim.x) {
+    int idx = base + k;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+__global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
+                               const int32_t* __restrict__ cell_start,
+                               int32_t* __restrict__ cell_fill,
+                               int32_t* __restrict__ sorted) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
+  int c = cell_id[p];
+  int pos = cell_start[c] + atomicAdd(&cell_fill[c], 1);
+  sorted[pos] = p;
+}
+
+// the atomic scatter leaves each cell in arbitrary order: sort it by input
+// index so that every later step is deterministic
+__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ cell_start,
+                            int32_t* __restrict__ sorted) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  int b = cell_start[c], e = cell_start[c + 1];
+  for (int i = b + 1; i < e; ++i) {
+    int key = sorted[i];
+    int j = i - 1;
+    while (j >= b && sorted[j] > key) {
+      sorted[j + 1] = sorted[j];
+      --j;
+    }
+    sorted[j + 1] = key;
+  }
+}
+
+// Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
+// with a the symmetry axis (third column of the rotation of q).
+__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ sorted,
+                                const int32_t* __restrict__ cell_id,
+                                const double* __restrict__ r,
+                                const double* __restrict__ q,
+                                const double* __restrict__ semi,
+                                const double* __restrict__ v,
+                                const double* __restrict__ w, PRec* __restrict__ rec,
+                                KRec* __restrict__ kin,
+                                int32_t* __restrict__ cell_sorted) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n) return;
+  int p = sorted[s];
+  double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
+  double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= inv;
+  qx *= inv;
+  qy *= inv;
+  qz *= inv;
+  double ax = 2.0 * (qx * qz + qw * qy);
+  double ay = 2.0 * (qy * qz - qw * qx);
+  double az = 1.0 - 2.0 * (qx * qx + qy * qy);
+  double Rpa = semi[2 * p], Rpe = semi[2 * p + 1];
+  double p2 = Rpe * Rpe, dd = Rpa * Rpa - p2;
+  PRec o;
+  o.r[0] = r[3 * p];
+  o.r[1] = r[3 * p + 1];
+  o.r[2] = r[3 * p + 2];
+  o.M[0] = p2 + dd * ax * ax;
+  o.M[1] = dd * ax * ay;
+  o.M[2] = dd * ax * az;
+  o.M[3] = p2 + dd * ay * ay;
+  o.M[4] = dd * ay * az;
+  o.M[5] = p2 + dd * az * az;
+  o.ax[0] = ax;
+  o.ax[1] = ay;
+  o.ax[2] = az;
+  o.Rpar = Rpa;
+  o.Rperp = Rpe;
+  o.Rmax = fmax(Rpa, Rpe);
+  o.pad = 0.0;
+  rec[s] = o;
+  KRec k;
+  for (int c = 0; c < 3; ++c) {
+    k.v[c] = v[3 * p + c];
+    k.w[c] = w[3 * p + c];
+  }
+  k.pad[0] = k.pad[1] = 0.0;
+  kin[s] = k;
+  cell_sorted[s] = cell_id[p];
+}
+
+// neighbour offsets along one axis: distinct cells only (a periodic axis
+// with fewer than three cells would otherwise visit a cell twice)
+__device__ __forceinline__ int axis_offsets(int c, int nc, int periodic,
+                                            int out[3]) {
+  int k = 0;
+  if (periodic) {
+    if (nc >= 3) {
+      out[k++] = (c + nc - 1) % nc;
+      out[k++] = c;
+      out[k++] = (c + 1) % nc;
+    } else if (nc == 2) {
+      out[k++] = 0;
+      out[k++] = 1;
+    } else {
+      out[k++] = 0;
+    }
+  } else {
+    if (c > 0) out[k++] = c - 1;
+    out[k++] = c;
+    if (c + 1 < nc) out[k++] = c + 1;
+  }
+  return k;
+}
+
+__device__ __forceinline__ double support(const double* M, double nx, double ny,
+                                          double nz) {
+  double mx = M[0] * nx + M[1] * ny + M[2] * nz;
+  double my = M[1] * nx + M[3] * ny + M[4] * nz;
+  double mz = M[2] * nx + M[4] * ny + M[5] * nz;
+  return sqrt(nx * mx + ny * my + nz * mz);
+}
+
+// One wavefront per particle: candidate test over the 27 neighbour cells
+// (lanes over the flattened cell members), in-wave compaction with a ballot,
+// rank sort of the segment by partner index, the support-function reject
+// for the entries this particle owns (smaller input index), slot
+// assignment (one atomic per block) and the wall candidates.  Segments
+// have a fixed stride of d.max_nbr entries.
+constexpr int kWavesPerBlock = 4;
+
+__device__ __forceinline__ int wave_prefix(unsigned long long mask, int lane) {
+  return __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(64 * kWavesPerBlock)
+k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
+                 const int32_t* __restrict__ orig,
+                 const int32_t* __restrict__ cell_sorted,
+                 const int32_t* __restrict__ cell_start,
+                 int32_t* __restrict__ deg, int32_t* __restrict__ nbr,
+                 int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
+                 int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
+                 Counters* cnt) {
+  extern __shared__ int32_t lds_keys[];  // kWavesPerBlock * max_nbr
+  __shared__ int s_keep[kWavesPerBlock];
+  __shared__ int s_upper[kWavesPerBlock];
+  __shared__ int s_wallc[kWavesPerBlock];
+  __shared__ int s_base[kWavesPerBlock];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int s = blockIdx.x * kWavesPerBlock + wv;
+  const int maxn = d.max_nbr;
+  int32_t* keys = lds_keys + wv * maxn;
+  const bool live = s < d.n;
+
+  int count = 0;
+  int nkeep = 0, nupper = 0, nwallc = 0;
+  // entries held by this lane after the sort: entry lane + 64 k
+  constexpr int kMaxPerLane = 8;  // max_nbr <= 512
+  int my_key[kMaxPerLane];
+  int my_keep[kMaxPerLane];
+  int wall_keep[2] = {0, 0};
+  if (live) {
+    const double ri[3] = {rec[s].r[0], rec[s].r[1], rec[s].r[2]};
+    const double rmi = rec[s].Rmax;
+    const int c = cell_sorted[s];
+    const int cx = c % d.nc[0];
+    const int cy = (c / d.nc[0]) % d.nc[1];
+    const int cz = c / (d.nc[0] * d.nc[1]);
+    int ox[3], oy[3], oz[3];
+    const int nx = axis_offsets(cx, d.nc[0], d.periodic[0], ox);
+    const int ny = axis_offsets(cy, d.nc[1], d.periodic[1], oy);
+    const int nz = axis_offsets(cz, d.nc[2], d.periodic[2], oz);
+    const int ncells = nx * ny * nz;
+    // lane k < ncells owns neighbour cell k: its member range and prefix
+    int cs = 0, cn = 0;
+    if (lane < ncells) {
+      int a = lane / (nx * ny), rem = lane % (nx * ny);
+      int b = rem / nx, e = rem % nx;
+      int cc = (oz[a] * d.nc[1] + oy[b]) * d.nc[0] + ox[e];
+      cs = cell_start[cc];
+      cn = cell_start[cc + 1] - cs;
+    }
+    int incl = cn;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      int y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, 31, 64);
+    const int excl = incl - cn;
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      bool acc = false;
+      int t = -1;
+      // the neighbour cell holding flattened index idx: binary search over the
+      // lanes' exclusive prefixes, every lane taking part in the shuffles
+      int lo = 0, hi = ncells - 1;
+      for (int step = 0; step < 5; ++step) {
+        int mid = (lo + hi + 1) >> 1;
+        int em = __shfl(excl, mid, 64);
+        bool up = lo < hi && em <= idx;
+        bool down = lo < hi && !(em <= idx);
+        lo = up ? mid : lo;
+        hi = down ? mid - 1 : hi;
+      }
+      const int start = __shfl(cs, lo, 64);
+      const int ex = __shfl(excl, lo, 64);
+      if (idx < total) {
+        t = start + (idx - ex);
+        acc = t != s && centre_test(ri, rec[t].r, rmi, rec[t].Rmax, d);
+      }
+      unsigned long long m = __ballot(acc);
+      if (acc) {
+        int pos = count + wave_prefix(m, lane);
+        if (pos < maxn) keys[pos] = t;
+      }
+      count += __popcll(m);
+    }
+  }
+  __syncthreads();
+  bool overflow = live && count > maxn;
+  if (overflow && lane == 0) set_error(cnt, LUB_ECAPACITY);
+  const int nent = (live && !overflow) ? count : 0;
+  // rank sort: keys are distinct partner indices
+  const int me = live ? orig[s] : 0;
+  const double* Mi = live ? rec[s].M : nullptr;
+  double rs[3] = {0, 0, 0};
+  if (live) {
+    rs[0] = rec[s].r[0];
+    rs[1] = rec[s].r[1];
+    rs[2] = rec[s].r[2];
+  }
+  for (int k = 0; k < kMaxPerLane; ++k) {
+    my_key[k] = -1;
+    my_keep[k] = 0;
+    const int e = lane + 64 * k;
+    if (e >= nent) continue;
+    const int key = keys[e];
+    int rank = 0;
+    for (int m2 = 0; m2 < nent; ++m2) rank += keys[m2] < key;
+    nbr[(size_t)s * maxn + rank] = key;
+    my_key[k] = key;
+    // owned entries (smaller input index) are evaluated unless the support
+    // functions along the line of centres already bound the gap above every
+    // cut-off
+    if (orig[key] > me) {
+      ++nupper;
+      double dx = rec[key].r[0] - rs[0], dy = rec[key].r[1] - rs[1],
+             dz = rec[key].r[2] - rs[2];
+      if (d.periodic[0]) dx -= d.L[0] * rint(dx / d.L[0]);
+      if (d.periodic[1]) dy -= d.L[1] * rint(dy / d.L[1]);
+      if (d.periodic[2]) dz -= d.L[2] * rint(dz / d.L[2]);
+      double dn = sqrt(dx * dx + dy * dy + dz * dz);
+      bool keep = true;
+      if (dn > 0.0) {
+        double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+        double g = dn - support(Mi, ux, uy, uz) - support(rec[key].M, ux, uy, uz);
+        keep = g < d.dmax;
+      }
+      my_keep[k] = keep ? 1 : 0;
+      slot[(size_t)s * maxn + rank] = -1;
+      if (keep) {
+        my_keep[k] = 1 + rank;  // remember the rank for the slot write
+        ++nkeep;
+      }
+    } else {
+      slot[(size_t)s * maxn + rank] = -2;
+    }
+  }
+  if (live && d.n_walls && lane < 2) {
+    const int side = lane;
+    double dist = side == 0 ? rs[2] : d.L[2] - rs[2];
+    bool cand = (dist - rec[s].Rmax) < d.dmax;
+    bool keep = cand && (dist - sqrt(Mi[5])) < d.dmax;
+    nwallc += cand;
+    wall_keep[0] = keep;
+    nkeep += keep;
+    // -3: candidate beyond every cut-off, -1: no candidate
+    wall_slot[2 * s + side] = keep ? 0 : (cand ? -3 : -1);
+  }
+  if (live) deg[s] = nent;
+  // wave totals -> block total -> one atomic per block
+  int wkeep = nkeep, wup = nupper, wwall = nwallc;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    wkeep += __shfl_xor(wkeep, o, 64);
+    wup += __shfl_xor(wup, o, 64);
+    wwall += __shfl_xor(wwall, o, 64);
+  }
+  if (lane == 0) {
+    s_keep[wv] = wkeep;
+    s_upper[wv] = wup;
+    s_wallc[wv] = wwall;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0, up = 0, wc = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) {
+      s_base[k] = tot;
+      tot += s_keep[k];
+      up += s_upper[k];
+      wc += s_wallc[k];
+    }
+    int b = tot ? atomicAdd(&cnt->work, tot) : 0;
+    if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
+    for (int k = 0; k < kWavesPerBlock; ++k) s_base[k] += b;
+    if (up) atomicAdd((unsigned long long*)&cnt->candidates, (unsigned long long)up);
+    if (wc) atomicAdd((unsigned long long*)&cnt->wall_candidates, (unsigned long long)wc);
+    s_keep[0] = b + tot <= d.cap_work;
+  }
+  __syncthreads();
+  const bool fits = s_keep[0] != 0;
+  // slots in lane order: exclusive prefix of nkeep across the wave
+  int incl2 = nkeep;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(incl2, o, 64);
+    if (lane >= o) incl2 += y;
+  }
+  if (!live || !fits) return;
+  int next = s_base[wv] + incl2 - nkeep;
+  for (int k = 0; k < kMaxPerLane; ++k) {
+    if (my_keep[k] <= 0) continue;
+    const int rank = my_keep[k] - 1;
+    slot[(size_t)s * maxn + rank] = next;
+    work_s[next] = s;
+    work_t[next] = my_key[k];
+    ++next;
+  }
+  if (d.n_walls && lane < 2 && wall_keep[0]) {
+    wall_slot[2 * s + lane] = next;
+    work_s[next] = s;
+    work_t[next] = -1 - lane;
+    ++next;
+  }
+}
+
+}  // namespace
+
+void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
+                  int ncell, hipStream_t s) {
+  int n = ncell > 128 ? ncell : 128;
+  hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, c,
+                     cell_count, cell_fill, ncell);
+}
+
+void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
+                      const double* semi, int32_t* cell_id, int32_t* cell_count,
+                      Counters* cnt, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_stage_bin, dim3((d.n + 255) / 256), dim3(256), 0, s, d,
+                     r, q, semi, cell_id, cell_count, cnt);
+}
+
+void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
+                 int64_t* total, hipStream_t s) {
+  int nb = (n + kScanTile - 1) / kScanTile;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_scan_tile, dim3(nb), dim3(kScanThreads), 0, s, in, out,
+                     n, block_sums, total);
+  if (nb > 1) {
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s,
+                       block_sums, nb, out, n, total);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, out, n,
+                       block_sums);
+  }
+}
+
+void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
+                         const int32_t* cell_start, int32_t* cell_fill,
+                         int32_t* sorted, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_cell_scatter, dim3((d.n + 255) / 256), dim3(256), 0, s,
+                     d, cell_id, cell_start, cell_fill, sorted);
+}
+
+void launch_cell_sort(int ncell, const int32_t* cell_start, int32_t* sorted,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + 255) / 256), dim3(256), 0, s,
+                     ncell, cell_start, sorted);
+}
+
+void launch_build_records(const CallDesc& d, const int32_t* sorted,
+                          const int32_t* cell_id, const double* r,
+                          const double* q, const double* semi, const double* v,
+                          const double* w, PRec* rec, KRec* kin,
+                          int32_t* cell_sorted, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
+                     d, sorted, cell_id, r, q, semi, v, w, rec, kin,
+                     cell_sorted);
+}
+
+void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
+                           const int32_t* orig, const int32_t* cell_sorted,
+                           const int32_t* cell_start, int32_t* deg,
+                           int32_t* nbr, int32_t* slot, int32_t* wall_slot,
+                           int32_t* work_s, int32_t* work_t, Counters* cnt,
+                           hipStream_t s) {
+  if (d.n == 0) return;
+  dim3 grid((d.n + kWavesPerBlock - 1) / kWavesPerBlock);
+  size_t lds = sizeof(int32_t) * kWavesPerBlock * (size_t)d.max_nbr;
+  hipLaunchKernelGGL(k_neighbors_wave, grid, dim3(64 * kWavesPerBlock), lds, s,
+                     d, rec, orig, cell_sorted, cell_start, deg, nbr, slot,
+                     wall_slot, work_s, work_t, cnt);
+}
+
+}  // namespace lub

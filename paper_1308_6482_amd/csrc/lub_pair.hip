@@ -1,0 +1,529 @@
+// lub_pair.hip -- per-pair closest points, local geometry, resistance and
+// transfer (gfx950).  One lane per pair.
+//
+// Closest points (Sec. III.A).  The paper's fixed point -- outward normals
+// antiparallel and along the line joining the tangent points -- is, with
+// the tangent points written as support points y_i = r_i + M_i n / h_i(n),
+// y_j = r_j - M_j n / h_j(n) (h_k(n) = sqrt(n.M_k n)), the stationary point
+// of g(n) = n.d - h_i(n) - h_j(n) on the unit sphere; g there is the signed
+// gap (negative for a small overlap).  It is found by Newton's method in the
+// tangent plane of n (two unknowns), started on the line of centres, in
+// FP64.  The Riemannian Hessian is shifted to stay negative definite far
+// from the solution.  This replaces the paper's Lin-Han tangent-sphere
+// iteration (linear convergence, ~40 iterations for aspect ratio 1/3) by a
+// quadratically convergent one that needs no pole-safe parametrisation.
+//
+// Local geometry (Sec. III.B).  For a spheroid the outward normal at
+// parametric latitude p satisfies tan(angle to the equator) =
+// (R_par/R_perp) tan p, so (cos p, sin p) follows from the normal's axial
+// component alone, and the principal direction x1 = d y / d p is the
+// projection of the symmetry axis onto the tangent plane.  Radii S1, S2
+// and the cubic coefficients Gamma_0, Gamma_2 follow Eq. lub:curvature-radii
+// and the Gamma formulas of Sec. III.B; phi, lambda, chi, beta, k and kappa
+// follow the Appendix.
+//
+// Resistance (Appendix, Eqs. app:first-element .. app:last-element), with
+// the cut-off correction of Eq. lub:resistance-correction at the clipped gap
+// max(h, h_c) and the Hookean contact of Eqs. lub:frep / lub:model; transfer
+// to the particle centres as at the end of Sec. III.B.
+//
+// Precision.  R = double: every step in FP64.  R = float: the Newton solve,
+// the gap, the frame vectors, relative surface velocities and the
+// ln(h/Delta), 1/h - 1/Delta factors stay in FP64; curvatures, K and the
+// transfer run in FP32.
+#include <hip/hip_runtime.h>
+
+#include "lub_internal.h"
+
+namespace lub {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__host__ __device__ __forceinline__ void symv(const double* M, const double x[3],
+                                     double y[3]) {
+  y[0] = M[0] * x[0] + M[1] * x[1] + M[2] * x[2];
+  y[1] = M[1] * x[0] + M[3] * x[1] + M[4] * x[2];
+  y[2] = M[2] * x[0] + M[4] * x[1] + M[5] * x[2];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T dot3(const T a[3], const T b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// any unit vector orthogonal to the unit vector n
+__host__ __device__ __forceinline__ void perp(const double n[3], double t[3]) {
+  double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
+  if (ax <= ay && ax <= az) {
+    t[0] = 0.0;
+    t[1] = n[2];
+    t[2] = -n[1];
+  } else if (ay <= az) {
+    t[0] = -n[2];
+    t[1] = 0.0;
+    t[2] = n[0];
+  } else {
+    t[0] = n[1];
+    t[1] = -n[0];
+    t[2] = 0.0;
+  }
+  double inv = 1.0 / sqrt(dot3(t, t));
+  t[0] *= inv;
+  t[1] *= inv;
+  t[2] *= inv;
+}
+
+struct Solve {
+  double n[3];   // unit gap direction i -> j
+  double ai[3];  // y_i - r_i
+  double bj[3];  // r_j - y_j
+  double h;
+  int iters;
+  bool ok;
+};
+
+// Newton iteration for the stationary point of g(n) on the unit sphere
+__host__ __device__ __forceinline__ Solve closest_points(const double d[3],
+                                                const double* Mi,
+                                                const double* Mj, int maxit) {
+  Solve o;
+  double dn = sqrt(dot3(d, d));
+  double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+  double prev = 1.0;
+  o.ok = false;
+  int it = 0;
+  double hi = 0, hj = 0, ai[3], bj[3];
+  for (;; ++it) {
+    double a[3], b[3];
+    symv(Mi, n, a);
+    symv(Mj, n, b);
+    hi = sqrt(dot3(n, a));
+    hj = sqrt(dot3(n, b));
+    double ih = 1.0 / hi, jh = 1.0 / hj;
+    for (int k = 0; k < 3; ++k) {
+      ai[k] = a[k] * ih;
+      bj[k] = b[k] * jh;
+    }
+    double g[3] = {d[0] - ai[0] - bj[0], d[1] - ai[1] - bj[1],
+                   d[2] - ai[2] - bj[2]};
+    double t1[3], t2[3];
+    perp(n, t1);
+    cross3(n, t1, t2);
+    double r1 = dot3(g, t1), r2 = dot3(g, t2);
+    double tol = 1e-14 * (hi + hj);
+    if (prev < 1e-8 || r1 * r1 + r2 * r2 <= tol * tol) {
+      o.ok = true;
+      break;
+    }
+    if (it >= maxit) break;
+    double gn = dot3(g, n);
+    double u1[3], u2[3], w1[3], w2[3];
+    symv(Mi, t1, u1);
+    symv(Mi, t2, u2);
+    symv(Mj, t1, w1);
+    symv(Mj, t2, w2);
+    double at1 = dot3(ai, t1), at2 = dot3(ai, t2);
+    double bt1 = dot3(bj, t1), bt2 = dot3(bj, t2);
+    double H11 = -(dot3(t1, u1) - at1 * at1) * ih - (dot3(t1, w1) - bt1 * bt1) * jh - gn;
+    double H12 = -(dot3(t1, u2) - at1 * at2) * ih - (dot3(t1, w2) - bt1 * bt2) * jh;
+    double H22 = -(dot3(t2, u2) - at2 * at2) * ih - (dot3(t2, w2) - bt2 * bt2) * jh - gn;
+    // keep the (maximisation) Hessian negative definite
+    double mid = 0.5 * (H11 + H22), dif = 0.5 * (H11 - H22);
+    double lmax = mid + sqrt(dif * dif + H12 * H12);
+    double floor_ = 1e-3 * (hi + hj);
+    if (lmax > -floor_) {
+      H11 -= lmax + floor_;
+      H22 -= lmax + floor_;
+    }
+    double det = H11 * H22 - H12 * H12;
+    double s1 = -(H22 * r1 - H12 * r2) / det;
+    double s2 = -(H11 * r2 - H12 * r1) / det;
+    double len = sqrt(s1 * s1 + s2 * s2);
+    if (len > 0.5) {
+      s1 *= 0.5 / len;
+      s2 *= 0.5 / len;
+      len = 0.5;
+    }
+    // Armijo backtracking on g along the (ascent) direction; skipped in the
+    // quadratic basin where the full step is always taken
+    double alpha = 1.0;
+    if (len > 1e-3) {
+      const double g0 = gn;  // g(n) = n.d - h_i - h_j
+      const double slope = r1 * s1 + r2 * s2;
+      for (int ls = 0; ls < 30; ++ls) {
+        double m[3];
+        for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
+        double inv = 1.0 / sqrt(dot3(m, m));
+        for (int k = 0; k < 3; ++k) m[k] *= inv;
+        double a2[3], b2[3];
+        symv(Mi, m, a2);
+        symv(Mj, m, b2);
+        double gt = dot3(m, d) - sqrt(dot3(m, a2)) - sqrt(dot3(m, b2));
+        if (gt >= g0 + 1e-4 * alpha * slope) break;
+        alpha *= 0.5;
+      }
+    }
+    prev = alpha * len;
+    double m[3];
+    for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
+    double inv = 1.0 / sqrt(dot3(m, m));
+    for (int k = 0; k < 3; ++k) n[k] = m[k] * inv;
+  }
+  for (int k = 0; k < 3; ++k) {
+    o.n[k] = n[k];
+    o.ai[k] = ai[k];
+    o.bj[k] = bj[k];
+  }
+  o.h = dot3(n, d) - hi - hj;
+  o.iters = it;
+  return o;
+}
+
+// (cos p, sin p) of the spheroid surface point whose outward unit normal is
+// n, from the cosine c = n.ax of the angle between normal and symmetry axis,
+// plus x1 = d y / d p: the axis projected onto the tangent plane
+__host__ __device__ __forceinline__ void latitude(const double n[3],
+                                                  const double ax[3], double Rpa,
+                                                  double Rpe, double* cp,
+                                                  double* sp, double e1[3]) {
+  const double c = dot3(n, ax);
+  double x[3];
+  cross3(n, ax, x);
+  double rho = sqrt(dot3(x, x));
+  double a = Rpe * rho, b = Rpa * c;
+  double nr = sqrt(a * a + b * b);
+  *cp = a / nr;
+  *sp = b / nr;
+  double t[3] = {ax[0] - c * n[0], ax[1] - c * n[1], ax[2] - c * n[2]};
+  double tl = sqrt(dot3(t, t));
+  if (tl > 1e-12) {
+    for (int k = 0; k < 3; ++k) e1[k] = t[k] / tl;
+  } else {
+    perp(n, e1);  // pole: S1 = S2 and Gamma = 0, any tangent will do
+  }
+}
+
+// principal radii and the two non-zero cubic coefficients of a spheroid
+template <typename R>
+__host__ __device__ __forceinline__ void radii(R Rpa, R Rpe, R cp, R sp, R* S1, R* S2,
+                                      R* G0, R* G2) {
+  R s1sq = Rpe * Rpe * sp * sp + Rpa * Rpa * cp * cp;
+  R s1 = sqrt(s1sq);
+  *S1 = s1sq * s1 / (Rpa * Rpe);
+  *S2 = Rpe * s1 / Rpa;
+  R num = (Rpa * Rpa - Rpe * Rpe) * Rpa * sp * cp;
+  R s4 = s1sq * s1sq;
+  *G0 = num * Rpe / (R(2) * s4 * s1sq);
+  *G2 = num / (R(2) * Rpe * s4);
+}
+
+// cubic coefficients a (given in axes rotated by +alpha) in unrotated axes
+template <typename R>
+__host__ __device__ __forceinline__ void rotate_cubic(R c, R s, const R a[4], R m[4]) {
+  R c2 = c * c, s2 = s * s;
+  m[0] = a[0] * c2 * c - a[1] * s * c2 + a[2] * s2 * c - a[3] * s2 * s;
+  m[1] = R(3) * a[0] * s * c2 + a[1] * (c2 * c - R(2) * s2 * c) +
+         a[2] * (s2 * s - R(2) * s * c2) + R(3) * a[3] * s2 * c;
+  m[2] = R(3) * a[0] * c * s2 + a[1] * (R(2) * c2 * s - s2 * s) +
+         a[2] * (c2 * c - R(2) * c * s2) - R(3) * a[3] * c2 * s;
+  m[3] = a[0] * s2 * s + a[1] * c * s2 + a[2] * c2 * s + a[3] * c2 * c;
+}
+
+// The 16 singular coefficients: K = C ln h (C33 / h for the normal one).
+// Index order 11 12 13 14 15 22 23 24 25 33 34 35 36 44 45 55.
+template <typename R>
+__host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p,
+                                         R iS2p, R G0p, R G2p, R cph, R sph,
+                                         R C[16]) {
+  const R pi = R(kPi);
+  // quadratic gap matrix and its eigen-decomposition: a few flops, in FP64
+  // (errors in chi propagate into every coupling term)
+  double m11 = 0.5 / (double)S1 + 0.5 * ((double)cph * cph * iS1p + (double)sph * sph * iS2p);
+  double m22 = 0.5 / (double)S2 + 0.5 * ((double)sph * sph * iS1p + (double)cph * cph * iS2p);
+  double m12 = 0.5 * (double)sph * cph * ((double)iS1p - iS2p);
+  double half = 0.5 * (m11 - m22);
+  double rad = sqrt(half * half + m12 * m12);
+  double dl1 = 0.5 * (m11 + m22) + rad;
+  double dl2 = (m11 * m22 - m12 * m12) / dl1;
+  // chi: eigenvector of l1 is (cos chi, -sin chi)
+  double dc = 1.0, ds = 0.0;
+  if (rad > 0.0) {
+    double c2x = half / rad, s2x = -m12 / rad;
+    if (c2x >= 0.0) {
+      dc = sqrt(0.5 * (1.0 + c2x));
+      ds = s2x / (2.0 * dc);
+    } else {
+      ds = sqrt(0.5 * (1.0 - c2x));
+      ds = s2x < 0.0 ? -ds : ds;
+      dc = s2x / (2.0 * ds);
+    }
+  }
+  const R l1 = R(dl1), l2 = R(dl2), c = R(dc), s = R(ds);
+  // beta = m(phi, Gamma'), k = Gamma + beta, kappa = m(chi, k) rescaled
+  R gp[4] = {G0p, R(0), G2p, R(0)}, beta[4];
+  rotate_cubic(cph, sph, gp, beta);
+  R kk[4] = {G0 + beta[0], beta[1], G2 + beta[2], beta[3]};
+  R mk[4];
+  rotate_cubic(c, s, kk, mk);
+  R q1 = sqrt(l1), q2 = sqrt(l2);
+  R k0 = mk[0] / (q1 * q1 * q1), k1 = mk[1] / (q1 * q1 * q2);
+  R k2 = mk[2] / (q1 * q2 * q2), k3 = mk[3] / (q2 * q2 * q2);
+
+  R sl = q1 * q2, lsum = l1 + l2;
+  R A = R(3) * l1 + R(2) * l2, B = R(2) * l1 + R(3) * l2;
+  R p1 = R(1) / (A * l1), p2 = R(1) / (B * l2);
+  R cc = c * c, ss = s * s, sc = s * c;
+  R isl = R(1) / sl;
+  R u1 = R(1) - l1 * S1, u2 = R(1) - l2 * S1;
+  R w1 = R(1) - l1 * S2, w2 = R(1) - l2 * S2;
+  R iS1 = R(1) / S1, iS2 = R(1) / S2;
+  // translation-translation and translation-rotation (curvature only)
+  C[0] = -pi * isl * iS1 * iS1 * (R(3) * cc * u1 * u1 * p1 + R(3) * ss * u2 * u2 * p2 + S1 * S1);
+  C[1] = R(3) * pi * isl * iS1 * iS2 * sc * (u1 * w1 * p1 - u2 * w2 * p2);
+  C[3] = R(3) * pi * isl * iS1 * sc * (u1 * p1 - u2 * p2);
+  C[4] = R(3) * pi * isl * iS1 * (cc * u1 * p1 + ss * u2 * p2);
+  C[5] = -pi * isl * iS2 * iS2 * (R(3) * ss * w1 * w1 * p1 + R(3) * cc * w2 * w2 * p2 + S2 * S2);
+  C[7] = -R(3) * pi * isl * iS2 * (ss * w1 * p1 + cc * w2 * p2);
+  C[8] = R(3) * pi * isl * iS2 * sc * (w2 * p2 - w1 * p1);
+  // normal
+  R f3 = R(3) * pi * isl / lsum;
+  C[9] = f3;
+  // cubic couplings
+  R Qa = (R(7) * l1 + R(2) * l2) * k0 + (l1 + R(2) * l2) * k2;
+  R Qb = (R(2) * l1 + l2) * k1 + (R(2) * l1 + R(7) * l2) * k3;
+  R Pa = R(3) * k0 * l1 + k2 * l2;
+  R Pb = k1 * l1 + R(3) * k3 * l2;
+  R ra = Qa / (q1 * A), rb = Qb / (q2 * B);
+  C[10] = R(0.75) * f3 * (rb * c - ra * s);
+  C[11] = -R(0.75) * f3 * (ra * c + rb * s);
+  R g0 = cc / l1 + ss / l2, g2 = ss / l1 + cc / l2, gx = sc * (R(1) / l2 - R(1) / l1);
+  R t13 = (R(2) * q1 * Pa - R(1.5) * iS1 * Qa / q1) * c / A +
+          (R(2) * q2 * Pb - R(1.5) * iS1 * Qb / q2) * s / B + R(3) * G0 * g0 + G2 * g2;
+  R t23 = (-R(2) * q1 * Pa + R(1.5) * iS2 * Qa / q1) * s / A +
+          (R(2) * q2 * Pb - R(1.5) * iS2 * Qb / q2) * c / B + R(2) * G2 * gx;
+  C[2] = -R(0.5) * f3 * t13;
+  C[6] = -R(0.5) * f3 * t23;
+  C[12] = -R(0.5) * f3 * sc * (iS1 - iS2) * (R(1) / l1 - R(1) / l2);
+  // rotation-rotation
+  C[13] = -R(3) * pi * isl * (ss * p1 + cc * p2);
+  C[14] = R(3) * pi * isl * sc * (p2 - p1);
+  C[15] = -R(3) * pi * isl * (cc * p1 + ss * p2);
+}
+
+template <typename R>
+__host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
+                          const PRec* B, const KRec* KB, int side,
+                          PairOut<R>& out, double& hout, int& status,
+                          int& iters) {
+  for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
+  Solve sv;
+  if (B) {
+    double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
+    for (int k = 0; k < 3; ++k)
+      if (cd.periodic[k]) d[k] -= cd.L[k] * rint(d[k] / cd.L[k]);
+    sv = closest_points(d, A.M, B->M, cd.max_iter);
+  } else {
+    // wall: the particle's support point towards the plane
+    double nz = side == 0 ? -1.0 : 1.0;
+    double hs = sqrt(A.M[5]);
+    sv.n[0] = 0.0;
+    sv.n[1] = 0.0;
+    sv.n[2] = nz;
+    sv.ai[0] = A.M[2] * nz / hs;
+    sv.ai[1] = A.M[4] * nz / hs;
+    sv.ai[2] = A.M[5] * nz / hs;
+    sv.bj[0] = sv.bj[1] = sv.bj[2] = 0.0;
+    sv.h = (side == 0 ? A.r[2] : cd.L[2] - A.r[2]) - hs;
+    sv.iters = 0;
+    sv.ok = true;
+  }
+  iters = sv.iters;
+  hout = sv.h;
+  if (!sv.ok) {
+    status = 3;
+    return;
+  }
+  const double h = sv.h;
+  const double heff = h > cd.h_c ? h : cd.h_c;
+  if (heff >= cd.dmax && h > cd.h_c) {
+    status = 1;
+    return;
+  }
+  if (!(heff > 0.0)) {
+    status = 2;
+    return;
+  }
+  status = 0;
+  const double* n = sv.n;
+
+  // frame of surface i and latitude of both closest points (FP64)
+  double cpi, spi, e1[3], e2[3];
+  latitude(n, A.ax, A.Rpar, A.Rperp, &cpi, &spi, e1);
+  cross3(n, e1, e2);
+  double S1, S2, G0, G2, iS1p = 0.0, iS2p = 0.0, G0p = 0.0, G2p = 0.0;
+  double cph = 1.0, sph = 0.0;
+  radii<double>(A.Rpar, A.Rperp, cpi, spi, &S1, &S2, &G0, &G2);
+  if (B) {
+    // surface j: outward normal -n; its x1' lies in the same tangent plane
+    double cpj, spj, e1p[3];
+    const double nj[3] = {-n[0], -n[1], -n[2]};
+    latitude(nj, B->ax, B->Rpar, B->Rperp, &cpj, &spj, e1p);
+    double S1p, S2p;
+    radii<double>(B->Rpar, B->Rperp, cpj, spj, &S1p, &S2p, &G0p, &G2p);
+    iS1p = 1.0 / S1p;
+    iS2p = 1.0 / S2p;
+    cph = dot3(e1p, e1);
+    sph = dot3(e1p, e2);
+  }
+  R C[16];
+  k_coeffs<R>(R(S1), R(S2), R(G0), R(G2), R(iS1p), R(iS2p), R(G0p), R(G2p),
+              R(cph), R(sph), C);
+
+  // cut-off factors (FP64), Eq. lub:resistance-correction
+  double Lt = heff < cd.delta_t ? log(heff) - log(cd.delta_t) : 0.0;
+  double Lr = heff < cd.delta_r ? log(heff) - log(cd.delta_r) : 0.0;
+  double Ln = heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
+
+  // relative surface velocities in the local frame (FP64)
+  double Vi[3], Vj[3], wr[3], tmp[3];
+  cross3(KA.w, sv.ai, tmp);
+  for (int k = 0; k < 3; ++k) Vi[k] = KA.v[k] + tmp[k];
+  if (B) {
+    double yj[3] = {-sv.bj[0], -sv.bj[1], -sv.bj[2]};
+    cross3(KB->w, yj, tmp);
+    for (int k = 0; k < 3; ++k) {
+      Vj[k] = KB->v[k] + tmp[k];
+      wr[k] = KB->w[k] - KA.w[k];
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      Vj[k] = cd.wall_vel[side][k];
+      wr[k] = -KA.w[k];
+    }
+  }
+  double dv[3] = {Vj[0] - Vi[0], Vj[1] - Vi[1], Vj[2] - Vi[2]};
+  R U[6] = {R(dot3(e1, dv)), R(dot3(e2, dv)), R(dot3(n, dv)),
+            R(dot3(e1, wr)), R(dot3(e2, wr)), R(dot3(n, wr))};
+  R lt = R(Lt), lr = R(Lr), ln_ = R(Ln), mu = R(cd.mu);
+  R Fb[6];
+  Fb[0] = mu * lt * (C[0] * U[0] + C[1] * U[1] + C[2] * U[2] + C[3] * U[3] + C[4] * U[4]);
+  Fb[1] = mu * lt * (C[1] * U[0] + C[5] * U[1] + C[6] * U[2] + C[7] * U[3] + C[8] * U[4]);
+  Fb[2] = mu * (lt * (C[2] * U[0] + C[6] * U[1] + C[10] * U[3] + C[11] * U[4] + C[12] * U[5]) +
+                ln_ * C[9] * U[2]);
+  Fb[3] = mu * (lt * (C[3] * U[0] + C[7] * U[1] + C[10] * U[2]) + lr * (C[13] * U[3] + C[14] * U[4]));
+  Fb[4] = mu * (lt * (C[4] * U[0] + C[8] * U[1] + C[11] * U[2]) + lr * (C[14] * U[3] + C[15] * U[4]));
+  Fb[5] = mu * lt * C[12] * U[2];
+  if (h <= cd.h_c) {
+    double Fr = h > 0.0 ? cd.eps_c * (cd.h_c - h) : cd.eps_c * cd.h_c;
+    Fb[2] -= R(Fr);
+  }
+  // back to the world frame; torques about the centres
+  R E1[3] = {R(e1[0]), R(e1[1]), R(e1[2])};
+  R E2[3] = {R(e2[0]), R(e2[1]), R(e2[2])};
+  R E3[3] = {R(n[0]), R(n[1]), R(n[2])};
+  R F[3], T[3];
+  for (int k = 0; k < 3; ++k) {
+    F[k] = Fb[0] * E1[k] + Fb[1] * E2[k] + Fb[2] * E3[k];
+    T[k] = Fb[3] * E1[k] + Fb[4] * E2[k] + Fb[5] * E3[k];
+  }
+  R ai[3] = {R(sv.ai[0]), R(sv.ai[1]), R(sv.ai[2])};
+  R bj[3] = {R(sv.bj[0]), R(sv.bj[1]), R(sv.bj[2])};
+  R xa[3], xb[3];
+  cross3(ai, F, xa);
+  cross3(bj, F, xb);
+  for (int k = 0; k < 3; ++k) {
+    out.F[k] = F[k];
+    out.Ti[k] = T[k] + xa[k];
+    out.Tj[k] = B ? -T[k] + xb[k] : R(0);
+  }
+}
+
+constexpr int kPairBlock = 64;
+
+template <typename R>
+__global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
+                                              const PRec* __restrict__ rec,
+                                              const KRec* __restrict__ kin,
+                                              const int32_t* __restrict__ work_s,
+                                              const int32_t* __restrict__ work_t,
+                                              PairOut<R>* __restrict__ out,
+                                              double* __restrict__ out_h,
+                                              int8_t* __restrict__ out_status,
+                                              uint8_t* __restrict__ out_iters,
+                                              Counters* cnt) {
+  __shared__ unsigned long long s_hist[32];
+  __shared__ unsigned long long s_stat[6];
+  __shared__ int s_max;
+  // the grid is sized for the capacity; blocks past the device-side work
+  // count leave at once
+  const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
+  if (blockIdx.x * blockDim.x >= nwork) return;
+  if (threadIdx.x < 32) s_hist[threadIdx.x] = 0;
+  if (threadIdx.x < 6) s_stat[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_max = 0;
+  __syncthreads();
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nwork;
+       w += gridDim.x * blockDim.x) {
+    int s = work_s[w], t = work_t[w];
+    PairOut<R> o;
+    double h;
+    int status, iters;
+    if (t >= 0)
+      eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters);
+    else
+      eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
+                   iters);
+    out[w] = o;
+    out_h[w] = h;
+    out_status[w] = (int8_t)status;
+    out_iters[w] = (uint8_t)(iters > 255 ? 255 : iters);
+    atomicAdd(&s_hist[iters < 31 ? iters : 31], 1ull);
+    atomicAdd(&s_stat[0], (unsigned long long)iters);
+    if (status == 0) atomicAdd(&s_stat[1], 1ull);
+    if (status == 0 && h <= 0.0) atomicAdd(&s_stat[2], 1ull);
+    if (status == 2) atomicAdd(&s_stat[3], 1ull);
+    if (status == 3) atomicAdd(&s_stat[4], 1ull);
+    atomicMax(&s_max, iters);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && s_hist[threadIdx.x])
+    atomicAdd((unsigned long long*)&cnt->iter_hist[threadIdx.x], s_hist[threadIdx.x]);
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&cnt->newton_iters, s_stat[0]);
+    atomicAdd((unsigned long long*)&cnt->active, s_stat[1]);
+    atomicAdd((unsigned long long*)&cnt->overlaps, s_stat[2]);
+    atomicAdd((unsigned long long*)&cnt->unresolved, s_stat[3]);
+    atomicAdd((unsigned long long*)&cnt->unconverged, s_stat[4]);
+    atomicMax(&cnt->newton_max, s_max);
+  }
+}
+
+}  // namespace
+
+void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
+                  const int32_t* work_s, const int32_t* work_t, void* out,
+                  double* out_h, int8_t* out_status, uint8_t* out_iters,
+                  Counters* cnt, hipStream_t s) {
+  int blocks = (d.cap_work + kPairBlock - 1) / kPairBlock;
+  if (blocks > 16384) blocks = 16384;  // grid-stride beyond 1M pairs
+  if (blocks < 1) blocks = 1;
+  if (d.precision == LUB_MIXED)
+    hipLaunchKernelGGL(k_pairs<float>, dim3(blocks), dim3(kPairBlock), 0, s, d,
+                       rec, kin, work_s, work_t, (PairOut<float>*)out, out_h,
+                       out_status, out_iters, cnt);
+  else
+    hipLaunchKernelGGL(k_pairs<double>, dim3(blocks), dim3(kPairBlock), 0, s, d,
+                       rec, kin, work_s, work_t, (PairOut<double>*)out, out_h,
+                       out_status, out_iters, cnt);
+}
+
+}  // namespace lub

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of the gfx950 lubrication library (include/lub.h).
+
+Argument marshalling only: every step of the correction runs in the HIP
+kernels of ``_lib/liblub.so``.  PyTorch provides device memory and streams.
+There is no CPU fallback: if the library is missing or no GPU is present,
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblub.so")
+
+LUB_OK, LUB_EINVAL, LUB_EDOMAIN, LUB_ECAPACITY, LUB_ENOMEM, LUB_EDEVICE = 0, -1, -2, -3, -4, -5
+LUB_FP64, LUB_MIXED = 0, 1
+LUB_SEED_PLAIN, LUB_SEED_MLP = 0, 1
+
+EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
+           "lub_get_stats", "lub_reset_timers", "lub_get_pairs",
+           "lub_get_pair_results", "lub_destroy", "lub_strerror"]
+
+
+class lub_params_t(C.Structure):
+    _fields_ = [("mu", C.c_double), ("delta_n", C.c_double),
+                ("delta_t", C.c_double), ("delta_r", C.c_double),
+                ("h_c", C.c_double), ("eps_c", C.c_double)]
+
+
+class lub_domain_t(C.Structure):
+    _fields_ = [("L", C.c_double * 3), ("periodic", C.c_int32 * 3),
+                ("n_walls", C.c_int32), ("wall_vel", (C.c_double * 3) * 2)]
+
+
+class lub_opts_t(C.Structure):
+    _fields_ = [("device", C.c_int32), ("precision", C.c_int32),
+                ("seed_mode", C.c_int32), ("newton_max_iter", C.c_int32),
+                ("rmax_bound", C.c_double), ("sync", C.c_int32),
+                ("timing", C.c_int32), ("max_neighbors", C.c_int64)]
+
+
+class lub_stats_t(C.Structure):
+    _fields_ = [("n", C.c_int64), ("candidates", C.c_int64),
+                ("wall_candidates", C.c_int64), ("evaluated", C.c_int64),
+                ("active", C.c_int64), ("overlaps", C.c_int64),
+                ("unresolved", C.c_int64), ("unconverged", C.c_int64),
+                ("fallbacks", C.c_int64), ("newton_iters", C.c_int64),
+                ("newton_max", C.c_int32), ("error", C.c_int32),
+                ("iter_hist", C.c_int64 * 32), ("timed_calls", C.c_int64),
+                ("stage_ms", C.c_double * 4)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("iter_hist", "stage_ms")}
+        d["iter_hist"] = list(self.iter_hist)
+        d["stage_ms"] = list(self.stage_ms)
+        return d
+
+
+_lib = None
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+
+
+class LubError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {lib().lub_strerror(code).decode()} ({code})")
+
+
+def lib():
+    """Load liblub.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        L.lub_create.argtypes = [C.POINTER(_P), C.POINTER(lub_domain_t),
+                                 C.POINTER(lub_params_t), C.POINTER(lub_opts_t)]
+        L.lub_set_params.argtypes = [_P, C.POINTER(lub_params_t)]
+        L.lub_set_domain.argtypes = [_P, C.POINTER(lub_domain_t)]
+        L.lub_compute.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.lub_get_stats.argtypes = [_P, C.POINTER(lub_stats_t)]
+        L.lub_reset_timers.argtypes = [_P]
+        L.lub_get_pairs.argtypes = [_P, C.c_int64, _I32, _I64, C.c_int64, _I32, _I64]
+        L.lub_get_pair_results.argtypes = [_P, C.c_int64, _I32, _D, _D, _D, _D,
+                                           _I32, _I32, _I64]
+        L.lub_destroy.argtypes = [_P]
+        L.lub_destroy.restype = None
+        L.lub_strerror.argtypes = [C.c_int]
+        L.lub_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != LUB_OK:
+        raise LubError(rc, where)
+
+
+def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0) -> lub_params_t:
+    return lub_params_t(mu, delta_n, delta_t, delta_r, h_c, eps_c)
+
+
+def make_domain(L, periodic=(1, 1, 1), n_walls=0,
+                wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))) -> lub_domain_t:
+    d = lub_domain_t()
+    for k in range(3):
+        d.L[k] = float(L[k])
+        d.periodic[k] = int(periodic[k])
+    d.n_walls = int(n_walls)
+    for s in range(2):
+        for k in range(3):
+            d.wall_vel[s][k] = float(wall_vel[s][k])
+    return d
+
+
+def make_opts(rmax_bound, precision=LUB_FP64, device=0, seed_mode=LUB_SEED_PLAIN,
+              newton_max_iter=0, sync=1, max_neighbors=0, timing=0) -> lub_opts_t:
+    return lub_opts_t(device, precision, seed_mode, newton_max_iter,
+                      float(rmax_bound), sync, timing, max_neighbors)
+
+
+# --- the C entry points, same names ------------------------------------------
+
+def lub_create(domain: lub_domain_t, params: lub_params_t, opts: lub_opts_t):
+    h = _P()
+    _check(lib().lub_create(C.byref(h), C.byref(domain), C.byref(params),
+                            C.byref(opts)), "lub_create")
+    return h
+
+
+def lub_set_params(h, params: lub_params_t):
+    _check(lib().lub_set_params(h, C.byref(params)), "lub_set_params")
+
+
+def lub_set_domain(h, domain: lub_domain_t):
+    _check(lib().lub_set_domain(h, C.byref(domain)), "lub_set_domain")
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("lub_compute takes torch.cuda tensors")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("lub_compute takes contiguous float64 tensors")
+    return t.data_ptr()
+
+
+def lub_compute(h, r, q, semi, v, w, f, t, stream=None, check=True) -> int:
+    """r, q, semi, v, w, f, t: contiguous float64 torch.cuda tensors of shape
+    (n,3), (n,4), (n,2), (n,3), (n,3), (n,3), (n,3).  f and t are written."""
+    import torch
+    n = r.shape[0]
+    for a, cols in ((r, 3), (q, 4), (semi, 2), (v, 3), (w, 3), (f, 3), (t, 3)):
+        if a.shape != (n, cols):
+            raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},{cols})")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    ptrs = [_ptr(x) if n > 0 else 0 for x in (r, q, semi, v, w, f, t)]
+    rc = lib().lub_compute(h, n, *ptrs, stream)
+    if check:
+        _check(rc, "lub_compute")
+    return rc
+
+
+def lub_get_stats(h) -> dict:
+    st = lub_stats_t()
+    _check(lib().lub_get_stats(h, C.byref(st)), "lub_get_stats")
+    return st.as_dict()
+
+
+def lub_reset_timers(h):
+    _check(lib().lub_reset_timers(h), "lub_reset_timers")
+
+
+def lub_get_pairs(h):
+    """(pairs (P,2) int32 sorted, wall pairs (W,2) int32 (particle, side))."""
+    L = lib()
+    npairs, nwall = C.c_int64(), C.c_int64()
+    rc = L.lub_get_pairs(h, 0, None, C.byref(npairs), 0, None, C.byref(nwall))
+    if rc not in (LUB_OK, LUB_ECAPACITY):
+        _check(rc, "lub_get_pairs")
+    ij = np.zeros((max(npairs.value, 1), 2), dtype=np.int32)
+    wall = np.zeros((max(nwall.value, 1), 2), dtype=np.int32)
+    _check(L.lub_get_pairs(h, npairs.value, ij.ctypes.data_as(_I32), C.byref(npairs),
+                           nwall.value, wall.ctypes.data_as(_I32), C.byref(nwall)),
+           "lub_get_pairs")
+    return ij[:npairs.value], wall[:nwall.value]
+
+
+def lub_get_pair_results(h) -> dict:
+    L = lib()
+    m = C.c_int64()
+    rc = L.lub_get_pair_results(h, 0, None, None, None, None, None, None, None,
+                                C.byref(m))
+    if rc not in (LUB_OK, LUB_ECAPACITY):
+        _check(rc, "lub_get_pair_results")
+    k = m.value
+    ij = np.zeros((max(k, 1), 2), dtype=np.int32)
+    hg = np.zeros(max(k, 1))
+    F = np.zeros((max(k, 1), 3))
+    Ti = np.zeros((max(k, 1), 3))
+    Tj = np.zeros((max(k, 1), 3))
+    st = np.zeros(max(k, 1), dtype=np.int32)
+    it = np.zeros(max(k, 1), dtype=np.int32)
+    _check(L.lub_get_pair_results(h, k, ij.ctypes.data_as(_I32), hg.ctypes.data_as(_D),
+                                  F.ctypes.data_as(_D), Ti.ctypes.data_as(_D),
+                                  Tj.ctypes.data_as(_D), st.ctypes.data_as(_I32),
+                                  it.ctypes.data_as(_I32), C.byref(m)),
+           "lub_get_pair_results")
+    return dict(ij=ij[:k], h=hg[:k], F=F[:k], Ti=Ti[:k], Tj=Tj[:k], status=st[:k],
+                iters=it[:k])
+
+
+def lub_destroy(h):
+    lib().lub_destroy(h)
+
+
+def lub_strerror(code: int) -> str:
+    return lib().lub_strerror(code).decode()
+
+
+# --- convenience ---------------------------------------------------------------
+
+class Lub:
+    """Owns one handle; ``compute`` takes and returns torch.cuda tensors."""
+
+    def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
+                 wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
+                 sync=1, newton_max_iter=0, max_neighbors=0, timing=0):
+        self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel),
+                            make_params(**params),
+                            make_opts(rmax_bound, precision, device,
+                                      newton_max_iter=newton_max_iter, sync=sync,
+                                      max_neighbors=max_neighbors, timing=timing))
+
+    def compute(self, r, q, semi, v, w, f=None, t=None, stream=None, check=True):
+        import torch
+        n = r.shape[0]
+        if f is None:
+            f = torch.empty((n, 3), dtype=torch.float64, device=r.device)
+        if t is None:
+            t = torch.empty((n, 3), dtype=torch.float64, device=r.device)
+        lub_compute(self.h, r, q, semi, v, w, f, t, stream, check)
+        return f, t
+
+    def stats(self):
+        return lub_get_stats(self.h)
+
+    def reset_timers(self):
+        lub_reset_timers(self.h)
+
+    def pairs(self):
+        return lub_get_pairs(self.h)
+
+    def pair_results(self):
+        return lub_get_pair_results(self.h)
+
+    def close(self):
+        if self.h:
+            lub_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @classmethod
+    def for_workload(cls, wl, precision=LUB_FP64, **kw):
+        return cls(wl.L, wl.periodic, wl.params, float(wl.semi.max()),
+                   n_walls=wl.n_walls, wall_vel=wl.wall_vel, precision=precision,
+                   **kw)
+
+
+def to_device(wl, device="cuda:0"):
+    """The workload's arrays as contiguous float64 tensors on the GPU."""
+    import torch
+    return [torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(device)
+            for a in (wl.r, wl.q, wl.semi, wl.v, wl.w)]
