@@ -171,6 +171,60 @@ int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
                          double* F, double* Ti, double* Tj, int32_t* status,
                          int32_t* iters, int64_t* n_out);
 
+/* ---- learned Newton seed ------------------------------------------------
+ * A 10-128-128-128-4 network with SiLU after the hidden layers predicts the
+ * closest-approach parameters (p, q of Eq. lub:spheroid on each particle)
+ * of a pair from 10 features in canonical pair frames (the relative centre,
+ * the relative orientation as a unit quaternion, three shape ratios).  With
+ * opts.seed_mode = LUB_SEED_MLP, lub_compute starts the closest-point Newton
+ * iteration from the normal these parameters imply; the iteration always
+ * runs to convergence from there, and a pair whose seeded iteration does not
+ * converge is solved again from the line of centres (counted in
+ * lub_stats_t.fallbacks), so the results do not depend on the network.
+ * Evaluation and training use BF16 MFMA with FP32 accumulation; the master
+ * weights and the Adam moments are FP32.
+ *
+ * Parameters: LUB_MLP_PARAMS floats, W1 (10 x 128, input-major), b1 (128),
+ * W2 (128 x 128), b2, W3 (128 x 128), b3, W4 (128 x 4), b4 (4).
+ * Features X: m x 10 float; outputs Y: m x 4 float (p_i, q_i, p_j, q_j);
+ * targets T: m x 6 float, the closest points in the canonical frames of i
+ * and of j, in units of R_perp of particle i.  Loss: mean over the samples
+ * of the squared distance between the surface points of the predicted
+ * parameters and the targets. */
+#define LUB_MLP_PARAMS 34948
+
+typedef struct {
+  int32_t epochs;    /* passes over the training set */
+  int32_t batch;     /* samples per step, a multiple of 64 (<= 0: 2048) */
+  float lr;          /* Adam step size */
+  float beta1;       /* Adam moments (<= 0: 0.9, 0.999, 1e-8) */
+  float beta2;
+  float eps;
+  float lr_decay;    /* step size factor per epoch (<= 0: 1) */
+  int32_t reserved;
+} lub_train_cfg_t;
+
+/* Copy the FP32 parameters in (host array of n = LUB_MLP_PARAMS floats);
+ * resets the Adam moments. */
+int lub_mlp_set_weights(lub_handle_t h, const float* theta, int64_t n);
+/* Copy the FP32 parameters out (host array). */
+int lub_mlp_get_weights(lub_handle_t h, float* theta, int64_t n);
+/* Uniform initialisation with bound sqrt(6 / fan_in), zero biases, from a
+ * seed; resets the Adam moments. */
+int lub_mlp_init(lub_handle_t h, uint64_t seed);
+/* Y = network(X) for m samples (device arrays). */
+int lub_mlp_forward(lub_handle_t h, int64_t m, const float* X, float* Y,
+                    void* stream);
+/* Loss and gradient of the parameters over m samples (m a multiple of 64;
+ * X, T device arrays; loss and grad host: 1 and LUB_MLP_PARAMS floats). */
+int lub_mlp_grad(lub_handle_t h, int64_t m, const float* X, const float* T,
+                 float* loss, float* grad, void* stream);
+/* Adam training over m samples (device arrays), in order, whole batches
+ * only (the samples are i.i.d. draws); the mean loss of every epoch is
+ * written to epoch_loss (host, cfg->epochs floats, may be NULL). */
+int lub_mlp_train(lub_handle_t h, int64_t m, const float* X, const float* T,
+                  const lub_train_cfg_t* cfg, float* epoch_loss, void* stream);
+
 void lub_destroy(lub_handle_t h);
 const char* lub_strerror(int code);
 

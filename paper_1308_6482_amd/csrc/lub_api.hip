@@ -47,6 +47,24 @@ struct lub_ctx {
   Counters* cnt = nullptr;         // device
   Counters* host_cnt = nullptr;    // pinned
 
+  // learned seed: FP32 master weights, Adam moments, gradient, packed BF16
+  // operands, training scratch and the per-slot features / outputs
+  float* th = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  float* grad = nullptr;
+  __bf16* wt = nullptr;
+  __bf16* wb = nullptr;
+  float* dloss = nullptr;          // device loss accumulator(s)
+  float* loss_parts = nullptr;
+  int64_t cap_batch = 0;
+  __bf16* aT = nullptr;
+  __bf16* dT = nullptr;
+  int64_t cap_seed = 0;
+  float* seedX = nullptr;
+  float* seedY = nullptr;
+  int adam_step = 0;
+
   // stage timing: five events per timed call, resolved lazily
   std::vector<hipEvent_t> free_events;
   std::vector<std::vector<hipEvent_t>> pending;
@@ -256,8 +274,14 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
                           c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                           c->work_t, c->cnt, s);
     mark(2);
-    launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h,
-                 c->out_status, c->out_iters, c->cnt, s);
+    const float* seeds = nullptr;
+    if (c->opt.seed_mode == LUB_SEED_MLP) {
+      launch_seed_features(d, c->rec, c->work_s, c->work_t, c->seedX, c->cnt, s);
+      mlp_forward_slots(c->cnt, d.cap_work, c->seedX, c->seedY, c->wt, c->th, s);
+      seeds = c->seedY;
+    }
+    launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
+                 c->out_h, c->out_status, c->out_iters, c->cnt, s);
     mark(3);
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
                   c->cnt, f, t, s);
@@ -279,6 +303,52 @@ int fetch_counters(lub_ctx* c) {
   return LUB_OK;
 }
 
+int mlp_upload(lub_ctx* c, const std::vector<float>& th) {
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpy(c->th, th.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(c->m1, 0, sizeof(float) * kNParams));
+  HIP_TRY(hipMemset(c->m2, 0, sizeof(float) * kNParams));
+  c->adam_step = 0;
+  mlp_pack(c->th, c->wt, c->wb, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return LUB_OK;
+}
+
+int mlp_init_host(lub_ctx* c, uint64_t seed) {
+  // uniform in [-sqrt(6/fan_in), sqrt(6/fan_in)], zero biases
+  std::vector<float> th(kNParams, 0.0f);
+  uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+  auto next = [&x]() {  // splitmix64
+    x += 0x9E3779B97F4A7C15ull;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  const int fan[4] = {10, 128, 128, 128}, outn[4] = {128, 128, 128, 4};
+  const int off[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+  for (int l = 0; l < 4; ++l) {
+    const float lim = std::sqrt(6.0f / (float)fan[l]);
+    for (int k = 0; k < fan[l] * outn[l]; ++k) {
+      double u = (double)(next() >> 11) * (1.0 / 9007199254740992.0);
+      th[off[l] + k] = (float)((2.0 * u - 1.0) * lim);
+    }
+  }
+  return mlp_upload(c, th);
+}
+
+int ensure_batch(lub_ctx* c, int64_t B) {
+  if (c->cap_batch >= B && c->aT) return LUB_OK;
+  int64_t tmp = 0;
+  int rc;
+  if ((rc = grow(&c->aT, &tmp, 416 * B))) return rc;
+  if ((rc = grow(&c->dT, &tmp, 400 * B))) return rc;
+  if ((rc = grow(&c->loss_parts, &tmp, B / 64 + 1))) return rc;
+  c->cap_batch = B;
+  return LUB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,7 +362,8 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   if ((rc = check_domain(domain))) return rc;
   if (!(opts->rmax_bound > 0.0)) return LUB_EINVAL;
   if (opts->precision != LUB_FP64 && opts->precision != LUB_MIXED) return LUB_EINVAL;
-  if (opts->seed_mode != LUB_SEED_PLAIN) return LUB_EINVAL;
+  if (opts->seed_mode != LUB_SEED_PLAIN && opts->seed_mode != LUB_SEED_MLP)
+    return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
   c->device = opts->device;
@@ -316,6 +387,22 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_ENOMEM;
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
+  {
+    int64_t tmp = 0;
+    int rc2 = LUB_OK;
+    if (!rc2) rc2 = grow(&c->th, &tmp, kNParams);
+    if (!rc2) rc2 = grow(&c->m1, &tmp, kNParams);
+    if (!rc2) rc2 = grow(&c->m2, &tmp, kNParams);
+    if (!rc2) rc2 = grow(&c->grad, &tmp, kNParams);
+    if (!rc2) rc2 = grow(&c->wt, &tmp, kWtTotal);
+    if (!rc2) rc2 = grow(&c->wb, &tmp, kWbTotal);
+    if (!rc2) rc2 = grow(&c->dloss, &tmp, 64);
+    if (!rc2) rc2 = mlp_init_host(c, 0);
+    if (rc2) {
+      lub_destroy(c);
+      return rc2;
+    }
+  }
   *out = c;
   return LUB_OK;
 }
@@ -353,6 +440,12 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   if ((rc = grow(&h->block_sums, &h->cap_bs, std::max<int64_t>(ncell, n) / 1024 + 64)))
     return rc;
   if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
+  if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
+    int64_t tmp = 0;
+    if ((rc = grow(&h->seedX, &tmp, 10 * h->cap_work))) return rc;
+    if ((rc = grow(&h->seedY, &tmp, 4 * h->cap_work))) return rc;
+    h->cap_seed = h->cap_work;
+  }
   if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
   if (!h->opt.sync) return LUB_OK;
   if ((rc = fetch_counters(h))) return rc;
@@ -362,6 +455,12 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
     h->cur_nbr = std::min(kMaxNbr, 2 * h->cur_nbr);
     if ((rc = build_desc(h, n, &d))) return rc;
     if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
+    if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
+      int64_t tmp = 0;
+      if ((rc = grow(&h->seedX, &tmp, 10 * h->cap_work))) return rc;
+      if ((rc = grow(&h->seedY, &tmp, 4 * h->cap_work))) return rc;
+      h->cap_seed = h->cap_work;
+    }
     if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
     if ((rc = fetch_counters(h))) return rc;
   }
@@ -500,6 +599,93 @@ int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
   return LUB_OK;
 }
 
+int lub_mlp_set_weights(lub_handle_t h, const float* theta, int64_t n) {
+  if (!h || !theta || n != kNParams) return LUB_EINVAL;
+  std::vector<float> th(theta, theta + kNParams);
+  for (float v : th)
+    if (!std::isfinite(v)) return LUB_EINVAL;
+  return mlp_upload(h, th);
+}
+
+int lub_mlp_get_weights(lub_handle_t h, float* theta, int64_t n) {
+  if (!h || !theta || n != kNParams) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(theta, h->th, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+  return LUB_OK;
+}
+
+int lub_mlp_init(lub_handle_t h, uint64_t seed) {
+  if (!h) return LUB_EINVAL;
+  return mlp_init_host(h, seed);
+}
+
+int lub_mlp_forward(lub_handle_t h, int64_t m, const float* X, float* Y, void* stream) {
+  if (!h || m < 0 || (m > 0 && (!X || !Y))) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  mlp_forward(m, X, Y, h->wt, h->th, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return LUB_OK;
+}
+
+int lub_mlp_grad(lub_handle_t h, int64_t m, const float* X, const float* T,
+                 float* loss, float* grad, void* stream) {
+  if (!h || m <= 0 || m % 64 || m > (1 << 24) || !X || !T || !loss || !grad)
+    return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_batch(h, m);
+  if (rc) return rc;
+  HIP_TRY(hipMemsetAsync(h->dloss, 0, sizeof(float), s));
+  rc = mlp_train_step(m, 0, (int)m, X, T, h->wt, h->wb, h->th, h->aT, h->dT, h->grad,
+                      h->m1, h->m2, h->loss_parts, 0.f, 0.9f, 0.999f, 1e-8f, 1, h->dloss,
+                      false, s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(grad, h->grad, sizeof(float) * kNParams, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(loss, h->dloss, sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return LUB_OK;
+}
+
+int lub_mlp_train(lub_handle_t h, int64_t m, const float* X, const float* T,
+                  const lub_train_cfg_t* cfg, float* epoch_loss, void* stream) {
+  if (!h || !cfg || m <= 0 || !X || !T || cfg->epochs < 0 || cfg->epochs > 64)
+    return LUB_EINVAL;
+  const int B = cfg->batch > 0 ? cfg->batch : 2048;
+  if (B % 64 || B > (1 << 20) || m < B || !(cfg->lr > 0.f)) return LUB_EINVAL;
+  const float b1 = cfg->beta1 > 0.f ? cfg->beta1 : 0.9f;
+  const float b2 = cfg->beta2 > 0.f ? cfg->beta2 : 0.999f;
+  const float ep = cfg->eps > 0.f ? cfg->eps : 1e-8f;
+  const float decay = cfg->lr_decay > 0.f ? cfg->lr_decay : 1.f;
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  int rc = ensure_batch(h, B);
+  if (rc) return rc;
+  HIP_TRY(hipMemsetAsync(h->dloss, 0, sizeof(float) * 64, s));
+  const int64_t steps = m / B;
+  float lr = cfg->lr;
+  for (int e = 0; e < cfg->epochs; ++e) {
+    for (int64_t k = 0; k < steps; ++k) {
+      h->adam_step += 1;
+      rc = mlp_train_step(m, k * B, B, X, T, h->wt, h->wb, h->th, h->aT, h->dT, h->grad,
+                          h->m1, h->m2, h->loss_parts, lr, b1, b2, ep, h->adam_step,
+                          h->dloss + e, true, s);
+      if (rc) return rc;
+    }
+    lr *= decay;
+  }
+  if (epoch_loss && cfg->epochs > 0) {
+    std::vector<float> tot(cfg->epochs);
+    HIP_TRY(hipMemcpyAsync(tot.data(), h->dloss, sizeof(float) * cfg->epochs,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int e = 0; e < cfg->epochs; ++e) epoch_loss[e] = tot[e] / (float)steps;
+  } else {
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return LUB_OK;
+}
+
 void lub_destroy(lub_handle_t h) {
   if (!h) return;
   hipSetDevice(h->device);
@@ -507,7 +693,8 @@ void lub_destroy(lub_handle_t h) {
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
-                  h->cnt};
+                  h->cnt, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
+                  h->loss_parts, h->aT, h->dT, h->seedX, h->seedY};
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);

@@ -71,6 +71,17 @@ struct PairOut {
   R F[3], Ti[3], Tj[3];
 };
 
+// ---- learned seed network: flat FP32 parameter layout ---------------------
+// W1 (10 x 128, input-major), b1, W2 (128 x 128), b2, W3 (128 x 128), b3,
+// W4 (128 x 4), b4
+constexpr int kOffW1 = 0, kOffB1 = 1280, kOffW2 = 1408, kOffB2 = 17792;
+constexpr int kOffW3 = 17920, kOffB3 = 34304, kOffW4 = 34432, kOffB4 = 34944;
+constexpr int kNParams = 34948;
+// packed BF16 copies: forward (output-major, padded) and backward
+constexpr int kWt1 = 128 * 32, kWt2 = 128 * 128;
+constexpr int kWtTotal = kWt1 + 2 * kWt2 + 16 * 128;
+constexpr int kWbTotal = 2 * kWt2 + 128 * 32;
+
 // ---- launch wrappers (lub_neighbors.hip) --------------------------------
 void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
                   int ncell, hipStream_t s);
@@ -97,10 +108,31 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
                            hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
+// seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the
+// line-of-centres start
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
-                  const int32_t* work_s, const int32_t* work_t, void* out,
-                  double* out_h, int8_t* out_status, uint8_t* out_iters,
+                  const int32_t* work_s, const int32_t* work_t, const float* seedY,
+                  void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   Counters* cnt, hipStream_t s);
+
+// seed features of every particle-particle evaluation slot (m x 10, FP32)
+void launch_seed_features(const CallDesc& d, const PRec* rec,
+                          const int32_t* work_s, const int32_t* work_t,
+                          float* X, Counters* cnt, hipStream_t s);
+
+// ---- learned seed network (lub_mlp.hip) -----------------------------------
+void mlp_pack(const float* th, __bf16* wt, __bf16* wb, hipStream_t s);
+void mlp_forward(int64_t m, const float* X, float* Y, const __bf16* wt,
+                 const float* th, hipStream_t s);
+int mlp_train_step(int64_t m, int64_t off, int B, const float* X, const float* T,
+                   const __bf16* wt, const __bf16* wb, float* th, __bf16* aT,
+                   __bf16* dT, float* grad, float* m1, float* m2, float* loss_parts,
+                   float lr, float beta1, float beta2, float eps, int step,
+                   float* loss_out, bool update, hipStream_t s);
+// network output for the evaluation slots of the last lub_compute: the
+// forward pass over the seed features, sized by the device work count
+void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
+                       const __bf16* wt, const float* th, hipStream_t s);
 
 // ---- per-particle reduction (lub_gather.hip) ------------------------------
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,

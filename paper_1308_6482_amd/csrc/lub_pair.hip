@@ -82,6 +82,85 @@ __host__ __device__ __forceinline__ void perp(const double n[3], double t[3]) {
   t[2] *= inv;
 }
 
+// Canonical pair frame of a spheroid with unit symmetry axis ax seen from
+// its partner at offset d: rows x, y, z; z = +-ax towards the partner,
+// x = the part of d normal to z (any normal if d lies on the axis).
+__host__ __device__ __forceinline__ void canonical_frame(const double ax[3],
+                                                        const double d[3],
+                                                        double F[3][3]) {
+  const double sg = dot3(ax, d) < 0.0 ? -1.0 : 1.0;
+  double z[3] = {sg * ax[0], sg * ax[1], sg * ax[2]};
+  const double dz = dot3(d, z);
+  double x[3] = {d[0] - dz * z[0], d[1] - dz * z[1], d[2] - dz * z[2]};
+  const double nx = sqrt(dot3(x, x));
+  if (nx <= 1e-12 * fmax(sqrt(dot3(d, d)), 1e-300)) {
+    perp(z, x);
+  } else {
+    for (int k = 0; k < 3; ++k) x[k] /= nx;
+  }
+  double y[3];
+  cross3(z, x, y);
+  for (int k = 0; k < 3; ++k) {
+    F[0][k] = x[k];
+    F[1][k] = y[k];
+    F[2][k] = z[k];
+  }
+}
+
+// the ten seed features: d in frame i / R_perp,i; the rotation from frame i
+// to frame j as a unit quaternion (w >= 0); three shape ratios
+__host__ __device__ __forceinline__ void seed_features(const double d[3],
+                                                      const PRec& A,
+                                                      const PRec& B, float X[10]) {
+  double Fi[3][3], Fj[3][3], md[3] = {-d[0], -d[1], -d[2]};
+  canonical_frame(A.ax, d, Fi);
+  canonical_frame(B.ax, md, Fj);
+  const double rp = A.Rperp;
+  for (int a = 0; a < 3; ++a) X[a] = (float)(dot3(Fi[a], d) / rp);
+  double R[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) R[a][b] = dot3(Fi[a], Fj[b]);
+  const double tr = R[0][0] + R[1][1] + R[2][2];
+  double q[4];
+  q[0] = sqrt(fmax(0.0, 1.0 + tr)) / 2.0;
+  q[1] = copysign(sqrt(fmax(0.0, 1.0 + R[0][0] - R[1][1] - R[2][2])) / 2.0, R[2][1] - R[1][2]);
+  q[2] = copysign(sqrt(fmax(0.0, 1.0 - R[0][0] + R[1][1] - R[2][2])) / 2.0, R[0][2] - R[2][0]);
+  q[3] = copysign(sqrt(fmax(0.0, 1.0 - R[0][0] - R[1][1] + R[2][2])) / 2.0, R[1][0] - R[0][1]);
+  const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int a = 0; a < 4; ++a) X[3 + a] = (float)(q[a] / qn);
+  X[7] = (float)(A.Rpar / rp);
+  X[8] = (float)(B.Rpar / rp);
+  X[9] = (float)(B.Rperp / rp);
+}
+
+// seed normal from predicted surface parameters (p, q) of both particles:
+// the outward normal of i at its point and minus that of j, averaged
+__host__ __device__ __forceinline__ bool seed_normal(const double d[3], const PRec& A,
+                                                    const PRec& B, const float Y[4],
+                                                    double n0[3]) {
+  double Fi[3][3], Fj[3][3], md[3] = {-d[0], -d[1], -d[2]};
+  canonical_frame(A.ax, d, Fi);
+  canonical_frame(B.ax, md, Fj);
+  double ni[3] = {0, 0, 0}, nj[3] = {0, 0, 0};
+  const double nbi[3] = {cos((double)Y[0]) * cos((double)Y[1]) / A.Rperp,
+                         cos((double)Y[0]) * sin((double)Y[1]) / A.Rperp,
+                         sin((double)Y[0]) / A.Rpar};
+  const double nbj[3] = {cos((double)Y[2]) * cos((double)Y[3]) / B.Rperp,
+                         cos((double)Y[2]) * sin((double)Y[3]) / B.Rperp,
+                         sin((double)Y[2]) / B.Rpar};
+  const double li = sqrt(dot3(nbi, nbi)), lj = sqrt(dot3(nbj, nbj));
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      ni[k] += Fi[a][k] * nbi[a] / li;
+      nj[k] += Fj[a][k] * nbj[a] / lj;
+    }
+  double m[3] = {ni[0] - nj[0], ni[1] - nj[1], ni[2] - nj[2]};
+  const double mn = sqrt(dot3(m, m));
+  if (!(mn > 1e-6) || !(dot3(m, d) > 0.0)) return false;
+  for (int k = 0; k < 3; ++k) n0[k] = m[k] / mn;
+  return true;
+}
+
 struct Solve {
   double n[3];   // unit gap direction i -> j
   double ai[3];  // y_i - r_i
@@ -91,13 +170,20 @@ struct Solve {
   bool ok;
 };
 
-// Newton iteration for the stationary point of g(n) on the unit sphere
+// Newton iteration for the stationary point of g(n) on the unit sphere,
+// started from n0 (unit) or, when n0 is null, from the line of centres
 __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
                                                 const double* Mi,
-                                                const double* Mj, int maxit) {
+                                                const double* Mj, int maxit,
+                                                const double* n0 = nullptr) {
   Solve o;
   double dn = sqrt(dot3(d, d));
   double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+  if (n0) {
+    n[0] = n0[0];
+    n[1] = n0[1];
+    n[2] = n0[2];
+  }
   double prev = 1.0;
   o.ok = false;
   int it = 0;
@@ -323,14 +409,29 @@ template <typename R>
 __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
                           const PRec* B, const KRec* KB, int side,
                           PairOut<R>& out, double& hout, int& status,
-                          int& iters) {
+                          int& iters, const float* seedY = nullptr,
+                          int* fell_back = nullptr) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
   Solve sv;
   if (B) {
     double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
     for (int k = 0; k < 3; ++k)
       if (cd.periodic[k]) d[k] -= cd.L[k] * rint(d[k] / cd.L[k]);
-    sv = closest_points(d, A.M, B->M, cd.max_iter);
+    double n0[3];
+    if (seedY && seed_normal(d, A, *B, seedY, n0)) {
+      // learned start; the plain start judges it: if the seeded iteration
+      // does not converge, start again from the line of centres
+      sv = closest_points(d, A.M, B->M, cd.max_iter, n0);
+      if (!sv.ok) {
+        const int used = sv.iters;
+        sv = closest_points(d, A.M, B->M, cd.max_iter);
+        sv.iters += used;
+        if (fell_back) *fell_back = 1;
+      }
+    } else {
+      sv = closest_points(d, A.M, B->M, cd.max_iter);
+      if (seedY && fell_back) *fell_back = 1;
+    }
   } else {
     // wall: the particle's support point towards the plane
     double nz = side == 0 ? -1.0 : 1.0;
@@ -455,6 +556,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               const KRec* __restrict__ kin,
                                               const int32_t* __restrict__ work_s,
                                               const int32_t* __restrict__ work_t,
+                                              const float* __restrict__ seedY,
                                               PairOut<R>* __restrict__ out,
                                               double* __restrict__ out_h,
                                               int8_t* __restrict__ out_status,
@@ -476,10 +578,14 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     int s = work_s[w], t = work_t[w];
     PairOut<R> o;
     double h;
-    int status, iters;
-    if (t >= 0)
-      eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters);
-    else
+    int status, iters, fb = 0;
+    if (t >= 0) {
+      float y[4];
+      if (seedY)
+        for (int k = 0; k < 4; ++k) y[k] = seedY[4 * (int64_t)w + k];
+      eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+                   seedY ? y : nullptr, &fb);
+    } else
       eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
                    iters);
     out[w] = o;
@@ -492,6 +598,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     if (status == 0 && h <= 0.0) atomicAdd(&s_stat[2], 1ull);
     if (status == 2) atomicAdd(&s_stat[3], 1ull);
     if (status == 3) atomicAdd(&s_stat[4], 1ull);
+    if (fb) atomicAdd(&s_stat[5], 1ull);
     atomicMax(&s_max, iters);
   }
   __syncthreads();
@@ -503,26 +610,59 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     atomicAdd((unsigned long long*)&cnt->overlaps, s_stat[2]);
     atomicAdd((unsigned long long*)&cnt->unresolved, s_stat[3]);
     atomicAdd((unsigned long long*)&cnt->unconverged, s_stat[4]);
+    if (s_stat[5]) atomicAdd((unsigned long long*)&cnt->fallbacks, s_stat[5]);
     atomicMax(&cnt->newton_max, s_max);
+  }
+}
+
+// seed features of the particle-particle slots
+__global__ void k_seed_features(CallDesc cd, const PRec* __restrict__ rec,
+                                const int32_t* __restrict__ work_s,
+                                const int32_t* __restrict__ work_t,
+                                float* __restrict__ X, const Counters* cnt) {
+  const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nwork;
+       w += gridDim.x * blockDim.x) {
+    const int s = work_s[w], t = work_t[w];
+    float x[10] = {0, 0, 0, 1, 0, 0, 0, 1, 1, 1};
+    if (t >= 0) {
+      const PRec& A = rec[s];
+      const PRec& B = rec[t];
+      double d[3] = {B.r[0] - A.r[0], B.r[1] - A.r[1], B.r[2] - A.r[2]};
+      for (int k = 0; k < 3; ++k)
+        if (cd.periodic[k]) d[k] -= cd.L[k] * rint(d[k] / cd.L[k]);
+      seed_features(d, A, B, x);
+    }
+    for (int k = 0; k < 10; ++k) X[10 * (int64_t)w + k] = x[k];
   }
 }
 
 }  // namespace
 
+void launch_seed_features(const CallDesc& d, const PRec* rec,
+                          const int32_t* work_s, const int32_t* work_t,
+                          float* X, Counters* cnt, hipStream_t s) {
+  int blocks = (d.cap_work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_seed_features, dim3(blocks), dim3(256), 0, s, d, rec,
+                     work_s, work_t, X, cnt);
+}
+
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
-                  const int32_t* work_s, const int32_t* work_t, void* out,
-                  double* out_h, int8_t* out_status, uint8_t* out_iters,
+                  const int32_t* work_s, const int32_t* work_t, const float* seedY,
+                  void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   Counters* cnt, hipStream_t s) {
   int blocks = (d.cap_work + kPairBlock - 1) / kPairBlock;
   if (blocks > 16384) blocks = 16384;  // grid-stride beyond 1M pairs
   if (blocks < 1) blocks = 1;
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_pairs<float>, dim3(blocks), dim3(kPairBlock), 0, s, d,
-                       rec, kin, work_s, work_t, (PairOut<float>*)out, out_h,
+                       rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
                        out_status, out_iters, cnt);
   else
     hipLaunchKernelGGL(k_pairs<double>, dim3(blocks), dim3(kPairBlock), 0, s, d,
-                       rec, kin, work_s, work_t, (PairOut<double>*)out, out_h,
+                       rec, kin, work_s, work_t, seedY, (PairOut<double>*)out, out_h,
                        out_status, out_iters, cnt);
 }
 

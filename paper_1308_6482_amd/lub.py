@@ -21,7 +21,10 @@ LUB_SEED_PLAIN, LUB_SEED_MLP = 0, 1
 
 EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_stats", "lub_reset_timers", "lub_get_pairs",
-           "lub_get_pair_results", "lub_destroy", "lub_strerror"]
+           "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
+           "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
+           "lub_destroy", "lub_strerror"]
+LUB_MLP_PARAMS = 34948
 
 
 class lub_params_t(C.Structure):
@@ -60,6 +63,12 @@ class lub_stats_t(C.Structure):
         return d
 
 
+class lub_train_cfg_t(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("lr_decay", C.c_float), ("reserved", C.c_int32)]
+
+
 _lib = None
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
@@ -92,6 +101,14 @@ def lib():
         L.lub_get_pairs.argtypes = [_P, C.c_int64, _I32, _I64, C.c_int64, _I32, _I64]
         L.lub_get_pair_results.argtypes = [_P, C.c_int64, _I32, _D, _D, _D, _D,
                                            _I32, _I32, _I64]
+        _F = C.POINTER(C.c_float)
+        L.lub_mlp_set_weights.argtypes = [_P, _F, C.c_int64]
+        L.lub_mlp_get_weights.argtypes = [_P, _F, C.c_int64]
+        L.lub_mlp_init.argtypes = [_P, C.c_uint64]
+        L.lub_mlp_forward.argtypes = [_P, C.c_int64, _P, _P, _P]
+        L.lub_mlp_grad.argtypes = [_P, C.c_int64, _P, _P, _F, _F, _P]
+        L.lub_mlp_train.argtypes = [_P, C.c_int64, _P, _P, C.POINTER(lub_train_cfg_t),
+                                    _F, _P]
         L.lub_destroy.argtypes = [_P]
         L.lub_destroy.restype = None
         L.lub_strerror.argtypes = [C.c_int]
@@ -220,6 +237,64 @@ def lub_get_pair_results(h) -> dict:
                 iters=it[:k])
 
 
+def _fptr(t, cols):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+            or not t.is_contiguous() or t.dim() != 2 or t.shape[1] != cols:
+        raise TypeError(f"expected a contiguous float32 cuda tensor (m,{cols})")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+
+def lub_mlp_set_weights(h, theta):
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    _check(lib().lub_mlp_set_weights(h, th.ctypes.data_as(C.POINTER(C.c_float)),
+                                     th.size), "lub_mlp_set_weights")
+
+
+def lub_mlp_get_weights(h):
+    th = np.zeros(LUB_MLP_PARAMS, dtype=np.float32)
+    _check(lib().lub_mlp_get_weights(h, th.ctypes.data_as(C.POINTER(C.c_float)),
+                                     th.size), "lub_mlp_get_weights")
+    return th
+
+
+def lub_mlp_init(h, seed=0):
+    _check(lib().lub_mlp_init(h, int(seed)), "lub_mlp_init")
+
+
+def lub_mlp_forward(h, X, Y, stream=None):
+    """Y (m,4) = network(X (m,10)); float32 cuda tensors."""
+    m = X.shape[0]
+    _check(lib().lub_mlp_forward(h, m, _fptr(X, 10), _fptr(Y, 4), _stream(stream)),
+           "lub_mlp_forward")
+
+
+def lub_mlp_grad(h, X, T, stream=None):
+    m = X.shape[0]
+    loss = np.zeros(1, dtype=np.float32)
+    g = np.zeros(LUB_MLP_PARAMS, dtype=np.float32)
+    Fp = C.POINTER(C.c_float)
+    _check(lib().lub_mlp_grad(h, m, _fptr(X, 10), _fptr(T, 6), loss.ctypes.data_as(Fp),
+                              g.ctypes.data_as(Fp), _stream(stream)), "lub_mlp_grad")
+    return float(loss[0]), g
+
+
+def lub_mlp_train(h, X, T, epochs=4, batch=2048, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, lr_decay=1.0, stream=None):
+    m = X.shape[0]
+    cfg = lub_train_cfg_t(epochs, batch, lr, beta1, beta2, eps, lr_decay, 0)
+    out = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(lib().lub_mlp_train(h, m, _fptr(X, 10), _fptr(T, 6), C.byref(cfg),
+                               out.ctypes.data_as(C.POINTER(C.c_float)), _stream(stream)),
+           "lub_mlp_train")
+    return out[:epochs]
+
+
 def lub_destroy(h):
     lib().lub_destroy(h)
 
@@ -235,10 +310,11 @@ class Lub:
 
     def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
-                 sync=1, newton_max_iter=0, max_neighbors=0, timing=0):
+                 sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
+                 seed_mode=LUB_SEED_PLAIN):
         self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel),
                             make_params(**params),
-                            make_opts(rmax_bound, precision, device,
+                            make_opts(rmax_bound, precision, device, seed_mode=seed_mode,
                                       newton_max_iter=newton_max_iter, sync=sync,
                                       max_neighbors=max_neighbors, timing=timing))
 

@@ -1,0 +1,168 @@
+"""GPU tests of the learned Newton seed through the C ABI.
+
+* The BF16 MFMA forward pass against the FP64 reference network on the same
+  (BF16-representable) weights: normwise relative difference <= 2e-2.
+* The BF16 MFMA gradient against the FP64 reference gradient (oracle): per
+  layer, normwise relative difference <= 5e-2.
+* Training on constructed pairs lowers the loss by a large factor, and the
+  trained network predicts held-out closest points far better than the
+  line of centres.
+* lub_compute with the learned seed gives the plain path's results (same
+  converged closest points) with fewer Newton iterations.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1308_6482_amd import lub as L  # noqa: E402
+from paper_1308_6482_amd import seed_data as S  # noqa: E402
+from paper_1308_6482_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+def bf16_round(x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32)).to(torch.bfloat16).float().numpy()
+
+
+def handle(**kw):
+    return L.Lub((100.0, 100.0, 100.0), (1, 1, 1),
+                 dict(mu=1 / 6, delta_n=0.67, delta_t=0.5, delta_r=0.25), 10.0, **kw)
+
+
+def cuda(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def test_forward_matches_reference():
+    from oracle import mlp_ref as M
+    print("[gpu] mlp forward", flush=True)
+    lb = handle()
+    theta = bf16_round(M.init(seed=4) * 0.8)
+    # biases are FP32 on the GPU
+    L.lub_mlp_set_weights(lb.h, theta)
+    P = S.sample_pairs(seed=11, m=1000)
+    X = bf16_round(P["X"])
+    Y = torch.zeros((1000, 4), dtype=torch.float32, device="cuda")
+    L.lub_mlp_forward(lb.h, cuda(X), Y)
+    torch.cuda.synchronize()
+    Yr, _ = M.forward(theta.astype(np.float64), X.astype(np.float64))
+    err = np.linalg.norm(Y.cpu().numpy() - Yr) / np.linalg.norm(Yr)
+    print(f"forward normwise rel diff {err:.3e}")
+    assert err < 2e-2
+    lb.close()
+
+
+def test_gradient_matches_reference():
+    from oracle import mlp_ref as M
+    print("[gpu] mlp gradient", flush=True)
+    lb = handle()
+    theta = bf16_round(M.init(seed=5) * 0.8)
+    L.lub_mlp_set_weights(lb.h, theta)
+    P = S.sample_pairs(seed=12, m=1024)
+    X = bf16_round(P["X"])
+    T = P["T"]
+    loss, g = L.lub_mlp_grad(lb.h, cuda(X), cuda(T))
+    Lr, gr = M.grad(theta.astype(np.float64), X.astype(np.float64), T.astype(np.float64))
+    print(f"loss gpu {loss:.6f} ref {Lr:.6f}")
+    assert abs(loss - Lr) < 2e-2 * Lr
+    o = 0
+    for name, (a, b) in zip(["W1", "W2", "W3", "W4"], M.SIZES):
+        for part, size in (("W", a * b), ("b", b)):
+            sl = slice(o, o + size)
+            e = np.linalg.norm(g[sl] - gr[sl]) / np.linalg.norm(gr[sl])
+            print(f"{part}{name[1]} grad normwise rel diff {e:.3e}")
+            assert e < 5e-2, (name, part, e)
+            o += size
+    lb.close()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    print("[gpu] mlp training", flush=True)
+    lb = handle()
+    L.lub_mlp_init(lb.h, 1)
+    P = S.sample_pairs(seed=1, m=1 << 17)
+    X, T = cuda(P["X"]), cuda(P["T"])
+    losses = L.lub_mlp_train(lb.h, X, T, epochs=12, batch=2048, lr=2e-3, lr_decay=0.8)
+    torch.cuda.synchronize()
+    theta = L.lub_mlp_get_weights(lb.h)
+    lb.close()
+    return theta, losses
+
+
+def test_training_reduces_loss(trained):
+    theta, losses = trained
+    print("epoch losses", losses)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.1 * losses[0]
+    # held-out pairs: surface-point error of the prediction vs the line of centres
+    from oracle import mlp_ref as M
+    P = S.sample_pairs(seed=2, m=4096)
+    lb = handle()
+    L.lub_mlp_set_weights(lb.h, theta)
+    Y = torch.zeros((4096, 4), dtype=torch.float32, device="cuda")
+    L.lub_mlp_forward(lb.h, cuda(P["X"]), Y)
+    torch.cuda.synchronize()
+    Yn = Y.cpu().numpy().astype(np.float64)
+    X, T = P["X"].astype(np.float64), P["T"].astype(np.float64)
+    held = M.loss_and_dy(Yn, X, T)[0]
+    # the line-of-centres guess: the support-free intersection of the centre
+    # line with each surface, expressed as (p, q)
+    d_i = X[:, 0:3]
+    Yc = np.zeros_like(Yn)
+    for part, dvec, (rpa, rpe) in ((0, d_i, (X[:, 7], np.ones(4096))),
+                                   (1, None, (X[:, 8], X[:, 9]))):
+        if part == 0:
+            u = dvec / np.linalg.norm(dvec, axis=1, keepdims=True)
+        else:
+            # centre line seen from j: the canonical x axis is the component
+            # of -d normal to its axis, z is towards i
+            u = None
+        if u is not None:
+            t = 1.0 / np.sqrt(u[:, 0] ** 2 / rpe ** 2 + u[:, 1] ** 2 / rpe ** 2
+                              + u[:, 2] ** 2 / rpa ** 2)
+            y = u * t[:, None]
+            Yc[:, 0] = np.arcsin(np.clip(y[:, 2] / rpa, -1, 1))
+            Yc[:, 1] = np.arctan2(y[:, 1], y[:, 0])
+    plain_i = np.mean(np.sum((M.surface(Yc[:, 0], Yc[:, 1], X[:, 7], np.ones(4096))
+                              - T[:, 0:3]) ** 2, axis=1))
+    pred_i = np.mean(np.sum((M.surface(Yn[:, 0], Yn[:, 1], X[:, 7], np.ones(4096))
+                             - T[:, 0:3]) ** 2, axis=1))
+    print(f"held-out loss {held:.4e}; particle-i surface error: network {pred_i:.4e} "
+          f"line of centres {plain_i:.4e}")
+    assert pred_i < 0.2 * plain_i
+    lb.close()
+
+
+def test_seeded_compute_equals_plain(trained):
+    theta, _ = trained
+    wl = W.config2()
+    r, q, semi, v, w = L.to_device(wl)
+    out = {}
+    for mode in (L.LUB_SEED_PLAIN, L.LUB_SEED_MLP):
+        print(f"[gpu] config2 seed_mode={mode}", flush=True)
+        lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, seed_mode=mode)
+        if mode == L.LUB_SEED_MLP:
+            L.lub_mlp_set_weights(lb.h, theta)
+        f, t = lb.compute(r, q, semi, v, w)
+        torch.cuda.synchronize()
+        out[mode] = (f.cpu().numpy(), t.cpu().numpy(), lb.stats())
+        lb.close()
+    (fp, tp, sp), (fm, tm, sm) = out[L.LUB_SEED_PLAIN], out[L.LUB_SEED_MLP]
+    print("plain iters", sp["newton_iters"], "max", sp["newton_max"],
+          "| mlp iters", sm["newton_iters"], "max", sm["newton_max"], "fallbacks",
+          sm["fallbacks"])
+    assert sm["active"] == sp["active"] and sm["unconverged"] == 0
+    scale_f = np.abs(fp).max()
+    scale_t = np.abs(tp).max()
+    assert np.abs(fm - fp).max() <= 1e-9 * scale_f
+    assert np.abs(tm - tp).max() <= 1e-9 * scale_t
+    assert sm["newton_iters"] < sp["newton_iters"]
