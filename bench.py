@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy after the timed region "
                          "(reference for the HBM traffic counters)")
+    ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
+                    help="Newton start: line of centres, learned network, or time both "
+                         "(the JSON value is the plain form unless --seed mlp)")
+    ap.add_argument("--train-pairs", type=int, default=1 << 21)
+    ap.add_argument("--train-epochs", type=int, default=6)
     return ap.parse_args()
 
 
@@ -112,19 +117,42 @@ def cpu_baseline(wl, seconds, gpu_pairs):
              max_rel_err_torque=float(eT.max()))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    import numpy as np  # noqa: F401
-    import torch
-    from paper_1308_6482_amd import lub as L
+def train_seed(L, torch, n_train, epochs):
+    """Train the seed network on the GPU with the library's own kernels on
+    constructed pairs shaped like the polydisperse suspension; returns the
+    weights and a report (losses, held-out loss, wall time)."""
+    import numpy as np
+    from paper_1308_6482_amd import seed_data as S
+    t0 = time.perf_counter()
+    P = S.sample_pairs(seed=1, m=n_train)
+    H = S.sample_pairs(seed=2, m=1 << 18)
+    t_gen = time.perf_counter() - t0
+    lb = L.Lub((100.0, 100.0, 100.0), (1, 1, 1),
+               dict(mu=1 / 6, delta_n=0.67, delta_t=0.5, delta_r=0.25), 10.0)
+    L.lub_mlp_init(lb.h, 1)
+    X = torch.as_tensor(P["X"]).cuda()
+    T = torch.as_tensor(P["T"]).cuda()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    losses = L.lub_mlp_train(lb.h, X, T, epochs=epochs, batch=4096, lr=2e-3, lr_decay=0.7)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    Xh = torch.as_tensor(H["X"]).cuda()
+    Th = torch.as_tensor(H["T"]).cuda()
+    held, _ = L.lub_mlp_grad(lb.h, Xh, Th)
+    theta = L.lub_mlp_get_weights(lb.h)
+    lb.close()
+    return theta, dict(train_pairs=n_train, heldout_pairs=1 << 18, epochs=epochs,
+                       epoch_loss=[float(x) for x in losses], heldout_loss=float(held),
+                       generate_s=t_gen, train_s=t_train)
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wl = workload(args.workload)
-    prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
-    lb = L.Lub.for_workload(wl, precision=prec, sync=0, timing=1)
+
+def measure(L, torch, wl, prec, args, theta=None):
+    """Time `args.steps` evaluations; returns (stats, ms_per_step)."""
+    mode = L.LUB_SEED_MLP if theta is not None else L.LUB_SEED_PLAIN
+    lb = L.Lub.for_workload(wl, precision=prec, sync=0, timing=1, seed_mode=mode)
+    if theta is not None:
+        L.lub_mlp_set_weights(lb.h, theta)
     r, q, semi, v, w = L.to_device(wl)
     f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
@@ -145,53 +173,100 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = lb.stats()
+    lb.close()
     if st["error"] or st["unconverged"]:
         raise RuntimeError(f"invalid run: error={st['error']} unconverged={st['unconverged']}")
+    return st, (t1 - t0) * 1e3 / args.steps, (f, t)
+
+
+def summary(st, ms, args):
+    active = st["active"]
+    pair_ms = st["stage_ms"][2] / max(st["timed_calls"], 1)
+    flops = (FLOPS_EVAL * st["evaluated"] + FLOPS_ITER * st["newton_iters"]
+             + FLOPS_POST[args.precision] * active)
+    return dict(value=active / (ms * 1e-3), ms_per_step=ms,
+                newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
+                newton_max=st["newton_max"], fallbacks=st["fallbacks"],
+                pair_kernel_ms=pair_ms, flops_per_launch=flops,
+                achieved_tflops=flops / (pair_ms * 1e-3) / 1e12,
+                stage_ms={k: v_ / max(st["timed_calls"], 1) for k, v_ in zip(
+                    ["cells", "neighbours", "pairs", "reduction"], st["stage_ms"])})
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np  # noqa: F401
+    import torch
+    from paper_1308_6482_amd import lub as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = workload(args.workload)
+    prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
+    forms = {}
+    mlp_report = None
+    theta = None
+    if args.seed in ("mlp", "both"):
+        theta, mlp_report = train_seed(L, torch, args.train_pairs, args.train_epochs)
+    if args.seed in ("plain", "both"):
+        st, ms, out_plain = measure(L, torch, wl, prec, args)
+        forms["plain"] = (st, ms)
+    if args.seed in ("mlp", "both"):
+        st, ms, out_mlp = measure(L, torch, wl, prec, args, theta)
+        forms["mlp"] = (st, ms)
+        if "plain" in forms:
+            # equal accuracy: the same converged closest points
+            fp, tp = out_plain
+            fm, tm = out_mlp
+            mlp_report["max_rel_diff_vs_plain"] = float(max(
+                (fm - fp).abs().max() / fp.abs().max(), (tm - tp).abs().max() / tp.abs().max()))
+    head = "mlp" if args.seed == "mlp" else "plain"
+    st, ms = forms[head]
     if args.calibrate_copy:
         x = torch.empty(512 * 2 ** 20, dtype=torch.uint8, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
-    ms = (t1 - t0) * 1e3 / args.steps
+    sm = summary(st, ms, args)
     active = st["active"]
-    value = active / (ms * 1e-3)
-    pair_ms = st["stage_ms"][2] / max(st["timed_calls"], 1)
-    flops = (FLOPS_EVAL * st["evaluated"] + FLOPS_ITER * st["newton_iters"]
-             + FLOPS_POST[args.precision] * active)
-    achieved = flops / (pair_ms * 1e-3) / 1e12
     res = dict(
         metric="lubrication-corrected pairs/sec on 1 GPU at rel err <=1e-5 vs FP64 oracle",
-        value=value, unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        value=sm["value"], unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f64+f32" if args.precision == "mixed" else "f64",
         data="synthetic (seeded random sequential addition, simple-shear velocities)",
         config=dict(workload=wl.name, n_particles=wl.n, box=list(wl.L),
                     periodic=list(wl.periodic), walls=wl.n_walls, seed=0,
-                    precision=args.precision, cutoffs=[wl.params["delta_n"], wl.params["delta_t"],
-                                                       wl.params["delta_r"]],
+                    precision=args.precision, newton_seed=head,
+                    cutoffs=[wl.params["delta_n"], wl.params["delta_t"], wl.params["delta_r"]],
                     h_c=wl.params["h_c"], eps_c=wl.params["eps_c"], mu=wl.params["mu"],
                     parallelism="single GPU"),
         pairs=dict(candidates=st["candidates"], wall_candidates=st["wall_candidates"],
                    evaluated=st["evaluated"], active=active, overlaps=st["overlaps"],
-                   newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
-                   newton_max=st["newton_max"]),
-        stage_ms={k: v_ / max(st["timed_calls"], 1) for k, v_ in zip(
-            ["cells", "neighbours", "pairs", "reduction"], st["stage_ms"])},
-        roofline=dict(bound="alu", kernel="k_pairs", achieved=achieved,
-                      peak=PEAK_ALU_TFLOPS, unit="TFLOP/s", frac=achieved / PEAK_ALU_TFLOPS,
-                      flops_per_launch=flops, launch_ms=pair_ms,
+                   newton_iters_mean=sm["newton_iters_mean"], newton_max=st["newton_max"]),
+        stage_ms=sm["stage_ms"],
+        roofline=dict(bound="alu", kernel="k_pairs", achieved=sm["achieved_tflops"],
+                      peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
+                      frac=sm["achieved_tflops"] / PEAK_ALU_TFLOPS,
+                      flops_per_launch=sm["flops_per_launch"], launch_ms=sm["pair_kernel_ms"],
                       traffic=pair_kernel_traffic(args.precision)),
+        seed_forms={k: {kk: vv for kk, vv in summary(v_[0], v_[1], args).items()
+                        if kk != "stage_ms"} for k, v_ in forms.items()},
     )
+    if mlp_report:
+        res["mlp_seed"] = mlp_report
     if args.cpu_seconds > 0:
         lb2 = L.Lub.for_workload(wl, precision=prec)
+        r, q, semi, v, w = L.to_device(wl)
         lb2.compute(r, q, semi, v, w)
         pr = lb2.pair_results()
         lb2.close()
         cb, acc = cpu_baseline(wl, args.cpu_seconds, pr)
         res["cpu_baseline"] = cb
         res["accuracy"] = acc
-    lb.close()
     print(json.dumps(res), flush=True)
 
 

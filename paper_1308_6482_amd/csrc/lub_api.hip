@@ -88,6 +88,18 @@ int hip_err(hipError_t e) {
     if (_rc != LUB_OK) return _rc;        \
   } while (0)
 
+// Replace *p by a fresh allocation of `need` elements (contents dropped).
+// Every buffer of a group that outgrew its capacity goes through this on
+// its own: a capacity shared between buffers would let a later one keep its
+// old, smaller allocation.
+template <typename T>
+int realloc_buf(T** p, int64_t need) {
+  if (*p) HIP_TRY(hipFree(*p));
+  *p = nullptr;
+  HIP_TRY(hipMalloc((void**)p, sizeof(T) * (size_t)std::max<int64_t>(need, 1)));
+  return LUB_OK;
+}
+
 template <typename T>
 int grow(T** p, int64_t* cap, int64_t need) {
   if (*p && *cap >= need) return LUB_OK;
@@ -124,27 +136,24 @@ int check_domain(const lub_domain_t* d) {
 int ensure_particles(lub_ctx* c, int64_t n) {
   if (c->cap_n >= n && c->cell_id) return LUB_OK;
   int64_t need = std::max<int64_t>(n, 1);
-  int64_t cap = 0;
-#define G(p) { int64_t tmp = 0; int rc = grow(&c->p, &tmp, need); if (rc) return rc; }
-  G(cell_id) G(sorted) G(cell_sorted) G(deg) G(rec) G(kin)
-#undef G
-  {
-    int64_t tmp = 0;
-    int rc = grow(&c->wall_slot, &tmp, 2 * need);
-    if (rc) return rc;
-  }
-  (void)cap;
+  int rc;
+  c->cap_n = 0;
+  if ((rc = realloc_buf(&c->cell_id, need)) || (rc = realloc_buf(&c->sorted, need)) ||
+      (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
+      (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->kin, need)) ||
+      (rc = realloc_buf(&c->wall_slot, 2 * need)))
+    return rc;
   c->cap_n = need;
   return LUB_OK;
 }
 
 int ensure_cells(lub_ctx* c, int64_t ncell) {
   if (c->cap_cells >= ncell && c->cell_count) return LUB_OK;
-  int64_t tmp = 0;
   int rc;
-  if ((rc = grow(&c->cell_count, &tmp, ncell))) return rc;
-  if ((rc = grow(&c->cell_fill, &tmp, ncell))) return rc;
-  if ((rc = grow(&c->cell_start, &tmp, ncell + 1))) return rc;
+  c->cap_cells = 0;
+  if ((rc = realloc_buf(&c->cell_count, ncell)) || (rc = realloc_buf(&c->cell_fill, ncell)) ||
+      (rc = realloc_buf(&c->cell_start, ncell + 1)))
+    return rc;
   c->cap_cells = ncell;
   return LUB_OK;
 }
@@ -157,19 +166,18 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
   int64_t work = entries / 2 + 2 * n + 64;
   int rc;
   if (c->cap_entries < entries || !c->nbr) {
-    int64_t tmp = 0;
-    if ((rc = grow(&c->nbr, &tmp, entries))) return rc;
-    if ((rc = grow(&c->slot, &tmp, entries))) return rc;
+    c->cap_entries = 0;
+    if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)))
+      return rc;
     c->cap_entries = entries;
   }
   if (c->cap_work < work || !c->work_s) {
-    int64_t tmp = 0;
-    if ((rc = grow(&c->work_s, &tmp, work))) return rc;
-    if ((rc = grow(&c->work_t, &tmp, work))) return rc;
-    if ((rc = grow((PairOut<double>**)&c->out, &tmp, work))) return rc;
-    if ((rc = grow(&c->out_h, &tmp, work))) return rc;
-    if ((rc = grow(&c->out_status, &tmp, work))) return rc;
-    if ((rc = grow(&c->out_iters, &tmp, work))) return rc;
+    c->cap_work = 0;
+    if ((rc = realloc_buf(&c->work_s, work)) || (rc = realloc_buf(&c->work_t, work)) ||
+        (rc = realloc_buf((PairOut<double>**)&c->out, work)) ||
+        (rc = realloc_buf(&c->out_h, work)) || (rc = realloc_buf(&c->out_status, work)) ||
+        (rc = realloc_buf(&c->out_iters, work)))
+      return rc;
     c->cap_work = work;
   }
   return LUB_OK;
@@ -261,14 +269,21 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
     if (timing) hipEventRecord(ev[k], s);
   };
   mark(0);
-  launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  if (d.n > 0 && cells_small_fits(d)) {
+    launch_cells_small(d, r, q, semi, v, w, c->cell_id, c->cell_start, c->sorted,
+                       c->rec, c->kin, c->cell_sorted, c->cnt, s);
+  } else {
+    launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  }
   if (d.n > 0) {
-    launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
-    launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
-    launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->sorted, s);
-    launch_cell_sort(ncell, c->cell_start, c->sorted, s);
-    launch_build_records(d, c->sorted, c->cell_id, r, q, semi, v, w, c->rec,
-                         c->kin, c->cell_sorted, s);
+    if (!cells_small_fits(d)) {
+      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
+      launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
+      launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->sorted, s);
+      launch_cell_sort(ncell, c->cell_start, c->sorted, s);
+      launch_build_records(d, c->sorted, c->cell_id, r, q, semi, v, w, c->rec,
+                           c->kin, c->cell_sorted, s);
+    }
     mark(1);
     launch_neighbors_wave(d, c->rec, c->sorted, c->cell_sorted, c->cell_start,
                           c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
@@ -340,12 +355,23 @@ int mlp_init_host(lub_ctx* c, uint64_t seed) {
 
 int ensure_batch(lub_ctx* c, int64_t B) {
   if (c->cap_batch >= B && c->aT) return LUB_OK;
-  int64_t tmp = 0;
   int rc;
-  if ((rc = grow(&c->aT, &tmp, 416 * B))) return rc;
-  if ((rc = grow(&c->dT, &tmp, 400 * B))) return rc;
-  if ((rc = grow(&c->loss_parts, &tmp, B / 64 + 1))) return rc;
+  c->cap_batch = 0;
+  if ((rc = realloc_buf(&c->aT, 416 * B)) || (rc = realloc_buf(&c->dT, 400 * B)) ||
+      (rc = realloc_buf(&c->loss_parts, B / 64 + 1)))
+    return rc;
   c->cap_batch = B;
+  return LUB_OK;
+}
+
+// seed features and outputs, one row per evaluation slot
+int ensure_seed(lub_ctx* c) {
+  int rc;
+  c->cap_seed = 0;
+  if ((rc = realloc_buf(&c->seedX, 10 * c->cap_work)) ||
+      (rc = realloc_buf(&c->seedY, 4 * c->cap_work)))
+    return rc;
+  c->cap_seed = c->cap_work;
   return LUB_OK;
 }
 
@@ -388,15 +414,14 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
   {
-    int64_t tmp = 0;
     int rc2 = LUB_OK;
-    if (!rc2) rc2 = grow(&c->th, &tmp, kNParams);
-    if (!rc2) rc2 = grow(&c->m1, &tmp, kNParams);
-    if (!rc2) rc2 = grow(&c->m2, &tmp, kNParams);
-    if (!rc2) rc2 = grow(&c->grad, &tmp, kNParams);
-    if (!rc2) rc2 = grow(&c->wt, &tmp, kWtTotal);
-    if (!rc2) rc2 = grow(&c->wb, &tmp, kWbTotal);
-    if (!rc2) rc2 = grow(&c->dloss, &tmp, 64);
+    if (!rc2) rc2 = realloc_buf(&c->th, kNParams);
+    if (!rc2) rc2 = realloc_buf(&c->m1, kNParams);
+    if (!rc2) rc2 = realloc_buf(&c->m2, kNParams);
+    if (!rc2) rc2 = realloc_buf(&c->grad, kNParams);
+    if (!rc2) rc2 = realloc_buf(&c->wt, kWtTotal);
+    if (!rc2) rc2 = realloc_buf(&c->wb, kWbTotal);
+    if (!rc2) rc2 = realloc_buf(&c->dloss, 64);
     if (!rc2) rc2 = mlp_init_host(c, 0);
     if (rc2) {
       lub_destroy(c);
@@ -441,10 +466,7 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
     return rc;
   if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
   if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
-    int64_t tmp = 0;
-    if ((rc = grow(&h->seedX, &tmp, 10 * h->cap_work))) return rc;
-    if ((rc = grow(&h->seedY, &tmp, 4 * h->cap_work))) return rc;
-    h->cap_seed = h->cap_work;
+    if ((rc = ensure_seed(h))) return rc;
   }
   if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
   if (!h->opt.sync) return LUB_OK;
@@ -456,10 +478,7 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
     if ((rc = build_desc(h, n, &d))) return rc;
     if ((rc = ensure_entries(h, n, h->cur_nbr))) return rc;
     if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
-      int64_t tmp = 0;
-      if ((rc = grow(&h->seedX, &tmp, 10 * h->cap_work))) return rc;
-      if ((rc = grow(&h->seedY, &tmp, 4 * h->cap_work))) return rc;
-      h->cap_seed = h->cap_work;
+      if ((rc = ensure_seed(h))) return rc;
     }
     if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
     if ((rc = fetch_counters(h))) return rc;

@@ -100,6 +100,13 @@ void launch_build_records(const CallDesc& d, const int32_t* sorted,
                           const double* q, const double* semi, const double* v,
                           const double* w, PRec* rec, KRec* kin,
                           int32_t* cell_sorted, hipStream_t s);
+// the whole cell build in one workgroup, when n and the grid are small enough
+bool cells_small_fits(const CallDesc& d);
+void launch_cells_small(const CallDesc& d, const double* r, const double* q,
+                        const double* semi, const double* v, const double* w,
+                        int32_t* cell_id, int32_t* cell_start, int32_t* sorted,
+                        PRec* rec, KRec* kin, int32_t* cell_sorted, Counters* cnt,
+                        hipStream_t s);
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,

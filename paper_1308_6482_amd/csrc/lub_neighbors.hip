@@ -97,14 +97,10 @@ __global__ void k_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
     reinterpret_cast<int32_t*>(c)[i] = 0;
 }
 
-// validate one particle's input, bin it
-__global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
+// validate one particle's input (EINVAL, EDOMAIN) and return its cell
+__device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
                             const double* __restrict__ q,
-                            const double* __restrict__ semi,
-                            int32_t* __restrict__ cell_id,
-                            int32_t* __restrict__ cell_count, Counters* cnt) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n) return;
+                            const double* __restrict__ semi, int p, Counters* cnt) {
   double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
   double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
   double a = semi[2 * p], b = semi[2 * p + 1];
@@ -120,7 +116,17 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
   int cy = cell_coord(y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
   int cz = cell_coord(z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
   if (!ok) cx = cy = cz = 0;
-  int c = (cz * d.nc[1] + cy) * d.nc[0] + cx;
+  return (cz * d.nc[1] + cy) * d.nc[0] + cx;
+}
+
+__global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
+                            const double* __restrict__ q,
+                            const double* __restrict__ semi,
+                            int32_t* __restrict__ cell_id,
+                            int32_t* __restrict__ cell_count, Counters* cnt) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
+  int c = validate_bin(d, r, q, semi, p, cnt);
   cell_id[p] = c;
   atomicAdd(&cell_count[c], 1);
 }
@@ -222,18 +228,12 @@ __global__ void k_cell_sort(int ncell, const int32_t* __restrict__ cell_start,
 
 // Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
 // with a the symmetry axis (third column of the rotation of q).
-__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ sorted,
-                                const int32_t* __restrict__ cell_id,
-                                const double* __restrict__ r,
-                                const double* __restrict__ q,
-                                const double* __restrict__ semi,
-                                const double* __restrict__ v,
-                                const double* __restrict__ w, PRec* __restrict__ rec,
-                                KRec* __restrict__ kin,
-                                int32_t* __restrict__ cell_sorted) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= d.n) return;
-  int p = sorted[s];
+__device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
+                            const double* __restrict__ r, const double* __restrict__ q,
+                            const double* __restrict__ semi,
+                            const double* __restrict__ v, const double* __restrict__ w,
+                            PRec* __restrict__ rec, KRec* __restrict__ kin,
+                            int32_t* __restrict__ cell_sorted) {
   double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
   double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= inv;
@@ -273,6 +273,20 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ sorted,
   cell_sorted[s] = cell_id[p];
 }
 
+__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ sorted,
+                                const int32_t* __restrict__ cell_id,
+                                const double* __restrict__ r,
+                                const double* __restrict__ q,
+                                const double* __restrict__ semi,
+                                const double* __restrict__ v,
+                                const double* __restrict__ w, PRec* __restrict__ rec,
+                                KRec* __restrict__ kin,
+                                int32_t* __restrict__ cell_sorted) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n) return;
+  make_record(s, sorted[s], cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
+}
+
 // neighbour offsets along one axis: distinct cells only (a periodic axis
 // with fewer than three cells would otherwise visit a cell twice)
 __device__ __forceinline__ int axis_offsets(int c, int nc, int periodic,
@@ -303,6 +317,84 @@ __device__ __forceinline__ double support(const double* M, double nx, double ny,
   double my = M[1] * nx + M[3] * ny + M[4] * nz;
   double mz = M[2] * nx + M[4] * ny + M[5] * nz;
   return sqrt(nx * mx + ny * my + nz * mz);
+}
+
+// Whole cell build in one workgroup for systems whose grid fits in LDS:
+// counter reset, validation and binning, counts, exclusive scan, scatter,
+// per-cell sort by input index and the cell-order records.  Replaces six
+// launches by one for small and medium systems.
+constexpr int kSmallThreads = 1024;
+
+__global__ void __launch_bounds__(kSmallThreads)
+k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
+              const double* __restrict__ semi, const double* __restrict__ v,
+              const double* __restrict__ w, int32_t* __restrict__ cell_id,
+              int32_t* __restrict__ cell_start, int32_t* __restrict__ sorted,
+              PRec* __restrict__ rec, KRec* __restrict__ kin,
+              int32_t* __restrict__ cell_sorted, Counters* cnt) {
+  extern __shared__ int32_t lds_cells[];  // counts / cursors [ncell], starts [ncell + 1]
+  __shared__ int lds_scan[16];
+  const int ncell = d.nc[0] * d.nc[1] * d.nc[2];
+  int32_t* cnt_l = lds_cells;
+  int32_t* start_l = lds_cells + ncell;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < (int)(sizeof(Counters) / sizeof(int32_t)); i += kSmallThreads)
+    reinterpret_cast<int32_t*>(cnt)[i] = 0;
+  for (int c = tid; c < ncell; c += kSmallThreads) cnt_l[c] = 0;
+  __syncthreads();
+  for (int p = tid; p < d.n; p += kSmallThreads) {
+    int c = validate_bin(d, r, q, semi, p, cnt);
+    cell_id[p] = c;
+    atomicAdd(&cnt_l[c], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the counts, `per` consecutive cells per thread
+  const int per = (ncell + kSmallThreads - 1) / kSmallThreads;
+  int run = 0;
+  for (int k = 0; k < per; ++k) {
+    int c = tid * per + k;
+    run += c < ncell ? cnt_l[c] : 0;
+  }
+  int tot;
+  int incl = block_inclusive_scan(run, lds_scan, &tot);
+  int acc = incl - run;
+  for (int k = 0; k < per; ++k) {
+    int c = tid * per + k;
+    if (c < ncell) {
+      start_l[c] = acc;
+      cell_start[c] = acc;
+      acc += cnt_l[c];
+    }
+  }
+  if (tid == 0) {
+    start_l[ncell] = tot;
+    cell_start[ncell] = tot;
+  }
+  __syncthreads();
+  for (int c = tid; c < ncell; c += kSmallThreads) cnt_l[c] = 0;
+  __syncthreads();
+  for (int p = tid; p < d.n; p += kSmallThreads) {
+    int c = cell_id[p];
+    sorted[start_l[c] + atomicAdd(&cnt_l[c], 1)] = p;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int c = tid; c < ncell; c += kSmallThreads) {
+    int b = start_l[c], e = start_l[c + 1];
+    for (int i = b + 1; i < e; ++i) {
+      int key = sorted[i];
+      int j = i - 1;
+      while (j >= b && sorted[j] > key) {
+        sorted[j + 1] = sorted[j];
+        --j;
+      }
+      sorted[j + 1] = key;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int s = tid; s < d.n; s += kSmallThreads)
+    make_record(s, sorted[s], cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
 }
 
 // One wavefront per particle: candidate test over the 27 neighbour cells
@@ -575,6 +667,22 @@ void launch_build_records(const CallDesc& d, const int32_t* sorted,
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
                      d, sorted, cell_id, r, q, semi, v, w, rec, kin,
                      cell_sorted);
+}
+
+bool cells_small_fits(const CallDesc& d) {
+  const int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+  return d.n <= (1 << 15) && ncell <= 8000;  // LDS: 2 ncell + 1 ints < 64 KiB
+}
+
+void launch_cells_small(const CallDesc& d, const double* r, const double* q,
+                        const double* semi, const double* v, const double* w,
+                        int32_t* cell_id, int32_t* cell_start, int32_t* sorted,
+                        PRec* rec, KRec* kin, int32_t* cell_sorted, Counters* cnt,
+                        hipStream_t s) {
+  const int ncell = d.nc[0] * d.nc[1] * d.nc[2];
+  size_t lds = sizeof(int32_t) * (2 * (size_t)ncell + 1);
+  hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), lds, s, d, r, q, semi,
+                     v, w, cell_id, cell_start, sorted, rec, kin, cell_sorted, cnt);
 }
 
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec,

@@ -55,7 +55,9 @@ def canonical_frame(axis, d):
     x = d - np.sum(d * z, axis=1)[:, None] * z
     nx = np.linalg.norm(x, axis=1)
     small = nx <= 1e-12 * np.maximum(np.linalg.norm(d, axis=1), 1e-300)
-    x = np.where(small[:, None], _perp(z), x / np.where(small, 1.0, nx)[:, None])
+    x /= np.where(small, 1.0, nx)[:, None]
+    if small.any():
+        x[small] = _perp(z[small])
     y = np.cross(z, x)
     return np.stack([x, y, z], axis=1)
 
@@ -80,8 +82,8 @@ def features(d, axis_i, semi_i, axis_j, semi_j):
     Fi = canonical_frame(axis_i, d)
     Fj = canonical_frame(axis_j, -d)
     rp = semi_i[:, 1]
-    dl = np.einsum("mij,mj->mi", Fi, d) / rp[:, None]
-    Rrel = np.einsum("mik,mjk->mij", Fi, Fj)   # columns: frame-j axes in frame i
+    dl = np.sum(Fi * d[:, None, :], axis=2) / rp[:, None]
+    Rrel = np.matmul(Fi, np.transpose(Fj, (0, 2, 1)))  # columns: frame-j axes in frame i
     q = matrix_to_quat(Rrel)
     X = np.concatenate([dl, q, np.stack([semi_i[:, 0] / rp, semi_j[:, 0] / rp,
                                          semi_j[:, 1] / rp], axis=1)], axis=1)
@@ -98,17 +100,23 @@ def surface_point(p, q, semi):
 def support_offsets(M, n):
     """M n / sqrt(n.M n) for each row: the point of the body (centre at 0)
     whose outward normal is n."""
-    Mn = np.einsum("mij,mj->mi", M, n)
+    Mn = np.sum(M * n[:, None, :], axis=2)
     return Mn / np.sqrt(np.sum(n * Mn, axis=1))[:, None]
 
 
-def sample_pairs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0),
-                 gap=(1e-4, 1.0)):
-    """m constructed pairs: dict with orientations q_i, q_j, semi-axes,
-    centre offset d, gap h, closest points (relative to each centre), the
-    features X (m,10) and targets T (m,6)."""
-    g_shape, g_ori, g_dir, g_gap = [np.random.default_rng(s) for s in
-                                    np.random.SeedSequence(seed).spawn(4)]
+def _support_offsets_axis(axis, semi, n):
+    """The point of a spheroid (centre at 0, symmetry axis `axis`) whose
+    outward normal is the unit n: M n / sqrt(n.M n) with M = R_perp^2 I +
+    (R_par^2 - R_perp^2) a a^T."""
+    p2 = semi[:, 1] ** 2
+    dd = semi[:, 0] ** 2 - p2
+    an = np.sum(axis * n, axis=1)
+    Mn = p2[:, None] * n + (dd * an)[:, None] * axis
+    return Mn / np.sqrt(p2 + dd * an * an)[:, None]
+
+
+def _sample_chunk(ss, m, lam, rperp, gap):
+    g_shape, g_ori, g_dir, g_gap = [np.random.default_rng(s) for s in ss.spawn(4)]
     semi_i = W.polydisperse_semi(g_shape, m, lam[0], lam[1], rperp[0], rperp[1])
     semi_j = W.polydisperse_semi(g_shape, m, lam[0], lam[1], rperp[0], rperp[1])
     q_i = W.random_quaternions(g_ori, m)
@@ -116,20 +124,36 @@ def sample_pairs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0),
     n = _unit(g_dir.normal(size=(m, 3)))
     a = np.minimum(semi_i.min(axis=1), semi_j.min(axis=1))
     h = a * np.exp(g_gap.uniform(np.log(gap[0]), np.log(gap[1]), size=m))
-    Mi = W.shape_matrices(q_i, semi_i)
-    Mj = W.shape_matrices(q_j, semi_j)
-    yi = support_offsets(Mi, n)          # y_i - r_i
-    yj = -support_offsets(Mj, n)         # y_j - r_j
+    axis_i = W.symmetry_axes(q_i)
+    axis_j = W.symmetry_axes(q_j)
+    yi = _support_offsets_axis(axis_i, semi_i, n)     # y_i - r_i
+    yj = _support_offsets_axis(axis_j, semi_j, -n)    # y_j - r_j
     d = yi + h[:, None] * n - yj
-    axis_i = W.quat_matrix(q_i)[:, :, 2]
-    axis_j = W.quat_matrix(q_j)[:, :, 2]
     X, Fi, Fj = features(d, axis_i, semi_i, axis_j, semi_j)
     rp = semi_i[:, 1][:, None]
-    T = np.concatenate([np.einsum("mij,mj->mi", Fi, yi) / rp,
-                        np.einsum("mij,mj->mi", Fj, yj) / rp], axis=1)
+    T = np.concatenate([np.sum(Fi * yi[:, None, :], axis=2) / rp,
+                        np.sum(Fj * yj[:, None, :], axis=2) / rp], axis=1)
     return dict(q_i=q_i, q_j=q_j, semi_i=semi_i, semi_j=semi_j, d=d, n=n, h=h,
                 yi=yi, yj=yj, X=X.astype(np.float32), T=T.astype(np.float32),
                 axis_i=axis_i, axis_j=axis_j)
+
+
+def sample_pairs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0),
+                 gap=(1e-4, 1.0), chunk: int = 1 << 17, threads: int = 8):
+    """m constructed pairs: dict with orientations q_i, q_j, semi-axes,
+    centre offset d, gap h, closest points (relative to each centre), the
+    features X (m,10) and targets T (m,6).  Generated in chunks with their
+    own child seeds (the result does not depend on the thread count)."""
+    nch = max(1, (m + chunk - 1) // chunk)
+    seqs = np.random.SeedSequence(seed).spawn(nch)
+    sizes = [min(chunk, m - k * chunk) for k in range(nch)]
+    if nch == 1:
+        return _sample_chunk(seqs[0], m, lam, rperp, gap)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(lambda k: _sample_chunk(seqs[k], sizes[k], lam, rperp, gap),
+                            range(nch)))
+    return {key: np.concatenate([p[key] for p in parts]) for key in parts[0]}
 
 
 def seed_normal(Y, semi_i, semi_j, Fi, Fj):

@@ -77,24 +77,28 @@ def random_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
 def quat_matrix(q: np.ndarray) -> np.ndarray:
     """Rotation matrices (n,3,3) of unit quaternions (w,x,y,z)."""
     w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
-    R = np.empty((q.shape[0], 3, 3))
-    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
-    R[:, 0, 1] = 2 * (x * y - w * z)
-    R[:, 0, 2] = 2 * (x * z + w * y)
-    R[:, 1, 0] = 2 * (x * y + w * z)
-    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
-    R[:, 1, 2] = 2 * (y * z - w * x)
-    R[:, 2, 0] = 2 * (x * z - w * y)
-    R[:, 2, 1] = 2 * (y * z + w * x)
-    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
-    return R
+    return np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                     2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                     2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+                    axis=1).reshape(-1, 3, 3)
+
+
+def symmetry_axes(q: np.ndarray) -> np.ndarray:
+    """Body z axes (n,3) in the world frame of unit quaternions."""
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    return np.stack([2 * (x * z + w * y), 2 * (y * z - w * x), 1 - 2 * (x * x + y * y)],
+                    axis=1)
 
 
 def shape_matrices(q: np.ndarray, semi: np.ndarray) -> np.ndarray:
-    """Q diag(R_perp^2, R_perp^2, R_par^2) Q^T for each particle."""
-    R = quat_matrix(q)
-    d2 = np.stack([semi[:, 1] ** 2, semi[:, 1] ** 2, semi[:, 0] ** 2], axis=1)
-    return np.einsum("nik,nk,njk->nij", R, d2, R)
+    """Q diag(R_perp^2, R_perp^2, R_par^2) Q^T = R_perp^2 I + (R_par^2 -
+    R_perp^2) a a^T for each particle (a: symmetry axis)."""
+    a = symmetry_axes(q)
+    p2 = semi[:, 1] ** 2
+    dd = semi[:, 0] ** 2 - p2
+    M = dd[:, None, None] * a[:, :, None] * a[:, None, :]
+    M[:, [0, 1, 2], [0, 1, 2]] += p2[:, None]
+    return M
 
 
 def shear_velocities(rng: np.random.Generator, r: np.ndarray,

@@ -184,6 +184,25 @@ def test_walls_polydisperse(ref):
     assert ef.max() < 1e-9 and et.max() < 1e-9
 
 
+@pytest.mark.timeout(600)
+def test_config3_full(ref):
+    """65,536 polydisperse spheroids between walls at the full size: more
+    particles than the single-workgroup cell build takes, so the multi-kernel
+    build runs; every pair and particle against the oracle."""
+    wl = W.config3()
+    assert wl.n > 1 << 15
+    g = run_gpu(wl, L.LUB_MIXED)
+    o = run_oracle(ref, wl)
+    check_pairs(g, o)
+    eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+    gate = act & (ha >= 1e-3)
+    print(f"pairs evaluated={len(act)} active={act.sum()} max eF={eF[gate].max():.3e} "
+          f"eT={eT[gate].max():.3e}")
+    assert eF[gate].max() < 1e-5 and eT[gate].max() < 1e-5
+    ef, et = particle_errors(g, o, ref, wl)
+    assert ef.max() < 1e-5 and et.max() < 1e-5, (ef.max(), et.max())
+
+
 def small(name, r, q, semi, v, w, L_=(60.0, 60.0, 60.0), periodic=(1, 1, 1),
           n_walls=0, **params):
     p = dict(mu=1.0 / 6.0, delta_n=0.67, delta_t=0.5, delta_r=0.25, h_c=0.0, eps_c=0.0)
