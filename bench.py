@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
                     help="Newton start: line of centres, learned network, or time both "
                          "(the JSON value is the plain form unless --seed mlp)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: read two rocprofv3 --pmc runs of this script with "
+                         "--calibrate-copy (FETCH_SIZE, then WRITE_SIZE), scale each by the "
+                         "copy kernel's reading and write profiles/pair_kernel_traffic.json")
     ap.add_argument("--train-pairs", type=int, default=1 << 21)
     ap.add_argument("--train-epochs", type=int, default=6)
     return ap.parse_args()
@@ -68,17 +72,91 @@ def workload(name):
     return W.config3()
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+COPY_BYTES = 512 * 2 ** 20
+
+
+def pair_kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lub_pair.hip", "lub_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1308_6482_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def pair_kernel_traffic(precision):
     """HBM bytes per launch of the pair kernel from the committed counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1308_6482_amd", "csrc", "lub_pair.hip"), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    rec = json.load(open(TRAFFIC_JSON))
+    if rec.get("source_sha256") != pair_kernel_source_hash():
         return None
     return rec.get(precision, {}).get("bytes_per_launch")
+
+
+def _counter_means(directory, counter):
+    """Mean value of `counter` per dispatch, number of dispatches and largest
+    value, by kernel name, over every counter_collection.csv under
+    `directory`."""
+    import csv
+    import glob
+    tot, num, big = {}, {}, {}
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {directory}")
+    for fn in files:
+        for row in csv.DictReader(open(fn)):
+            if row["Counter_Name"] != counter:
+                continue
+            k = row["Kernel_Name"]
+            v = float(row["Counter_Value"])
+            tot[k] = tot.get(k, 0.0) + v
+            num[k] = num.get(k, 0) + 1
+            big[k] = max(big.get(k, 0.0), v)
+    return {k: (tot[k] / num[k], num[k], big[k]) for k in tot}
+
+
+def traffic_summary(fetch_dir, write_dir, precision):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the pair kernel, each
+    scaled by bytes / reading of the calibration copy (512 MiB read and
+    written by one kernel); writes the JSON the bench line reads."""
+    fe = _counter_means(fetch_dir, "FETCH_SIZE")
+    wr = _counter_means(write_dir, "WRITE_SIZE")
+
+    def copy_kernel(tab):
+        # the calibration dispatch is the largest one of the copy kernel
+        for k in tab:
+            if "copyBuffer" in k:
+                return k
+        big = [k for k in tab if "elementwise" in k]
+        return max(big, key=lambda k: tab[k][2]) if big else None
+
+    kf, kw = copy_kernel(fe), copy_kernel(wr)
+    if kf is None or kw is None:
+        raise SystemExit("no calibration copy kernel in the counter runs")
+    f_fetch = COPY_BYTES / (fe[kf][2] * 1024.0)
+    f_write = COPY_BYTES / (wr[kw][2] * 1024.0)
+    kern = [k for k in fe if "k_pairs" in k]
+    if len(kern) != 1:
+        raise SystemExit(f"expected one pair kernel, found {kern}")
+    kp = kern[0]
+    fetch_b = fe[kp][0] * 1024.0 * f_fetch
+    write_b = wr[kp][0] * 1024.0 * f_write
+    rec = json.load(open(TRAFFIC_JSON)) if os.path.exists(TRAFFIC_JSON) else {}
+    if rec.get("source_sha256") != pair_kernel_source_hash():
+        rec = {}
+    rec["source_sha256"] = pair_kernel_source_hash()
+    rec[precision] = dict(kernel=kp, dispatches=fe[kp][1], fetch_kib=fe[kp][0],
+                          write_kib=wr[kp][0], copy_kernel=kf, copy_fetch_kib=fe[kf][2],
+                          copy_write_kib=wr[kw][2], scale_fetch=f_fetch, scale_write=f_write,
+                          bytes_per_launch=fetch_b + write_b)
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1, sort_keys=True)
+    others = {k: (fe[k][0] * 1024.0 * f_fetch, wr.get(k, (0.0, 0))[0] * 1024.0 * f_write)
+              for k in fe if k.startswith("lub::") or "k_" in k}
+    print(json.dumps(dict(pair_kernel=rec[precision],
+                          per_kernel_bytes={k: dict(fetch=a, write=b)
+                                            for k, (a, b) in others.items()}), indent=1))
 
 
 def cpu_baseline(wl, seconds, gpu_pairs):
@@ -195,6 +273,9 @@ def summary(st, ms, args):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.precision)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -225,10 +306,14 @@ def main():
     head = "mlp" if args.seed == "mlp" else "plain"
     st, ms = forms[head]
     if args.calibrate_copy:
-        x = torch.empty(512 * 2 ** 20, dtype=torch.uint8, device="cuda")
+        # a plain copy of known size (512 MiB read, 512 MiB written) as the
+        # reference reading of the traffic counters; a device-to-device copy
+        # and, in case the copy runs on a DMA engine, an elementwise kernel
+        x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
+            torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
     sm = summary(st, ms, args)
     active = st["active"]

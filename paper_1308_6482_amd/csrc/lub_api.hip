@@ -30,6 +30,9 @@ struct lub_ctx {
   int32_t* cell_fill = nullptr;    // [ncell]
   int32_t* cell_start = nullptr;   // [ncell + 1]
   int32_t* sorted = nullptr;       // [n] cell order -> input index
+  int32_t* scat = nullptr;         // [n] scatter output (cell ranges, any order)
+  int64_t* stat_nbr = nullptr;     // [neighbour blocks][kStatNbrWords]
+  int64_t* stat_pair = nullptr;    // [kMaxPairBlocks][kStatPairWords]
   int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
   int32_t* deg = nullptr;          // [n] entries per segment
   int32_t* block_sums = nullptr;   // scan scratch
@@ -44,7 +47,14 @@ struct lub_ctx {
   double* out_h = nullptr;         // [work]
   int8_t* out_status = nullptr;    // [work]
   uint8_t* out_iters = nullptr;    // [work]
-  Counters* cnt = nullptr;         // device
+  // Two sets of device counters, used by alternate calls: the last kernel
+  // of a call zeroes the other set, and the scatter and record kernels zero
+  // the cell counts and cursors, so a call needs no reset launch when the
+  // previous one ran to the end (`zeroed`).
+  Counters* cnt_buf = nullptr;     // device [2]
+  Counters* cnt = nullptr;         // the set of the current / last call
+  int cnt_idx = 0;
+  bool zeroed = false;
   Counters* host_cnt = nullptr;    // pinned
 
   // learned seed: FP32 master weights, Adam moments, gradient, packed BF16
@@ -141,6 +151,8 @@ int ensure_particles(lub_ctx* c, int64_t n) {
   if ((rc = realloc_buf(&c->cell_id, need)) || (rc = realloc_buf(&c->sorted, need)) ||
       (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
       (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->kin, need)) ||
+      (rc = realloc_buf(&c->scat, need)) ||
+      (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks((int)need))) ||
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
     return rc;
   c->cap_n = need;
@@ -151,6 +163,7 @@ int ensure_cells(lub_ctx* c, int64_t ncell) {
   if (c->cap_cells >= ncell && c->cell_count) return LUB_OK;
   int rc;
   c->cap_cells = 0;
+  c->zeroed = false;
   if ((rc = realloc_buf(&c->cell_count, ncell)) || (rc = realloc_buf(&c->cell_fill, ncell)) ||
       (rc = realloc_buf(&c->cell_start, ncell + 1)))
     return rc;
@@ -191,6 +204,7 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   int64_t ncell = 1;
   for (int k = 0; k < 3; ++k) {
     d->L[k] = c->dom.L[k];
+    d->invL[k] = 1.0 / c->dom.L[k];
     d->periodic[k] = c->dom.periodic[k];
     // minimum image must be unambiguous for the largest pair bound
     if (d->periodic[k] && d->L[k] < 2.0 * edge) return LUB_EDOMAIN;
@@ -269,25 +283,29 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
     if (timing) hipEventRecord(ev[k], s);
   };
   mark(0);
-  if (d.n > 0 && cells_small_fits(d)) {
-    launch_cells_small(d, r, q, semi, v, w, c->cell_id, c->cell_start, c->sorted,
-                       c->rec, c->kin, c->cell_sorted, c->cnt, s);
-  } else {
-    launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
-  }
+  // this call's counters: the set the previous call's last kernel zeroed
+  c->cnt_idx ^= 1;
+  c->cnt = c->cnt_buf + c->cnt_idx;
+  Counters* next_cnt = c->cnt_buf + (c->cnt_idx ^ 1);
+  const bool small = d.n > 0 && cells_small_fits(d);
+  if (!c->zeroed) launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  c->zeroed = false;
   if (d.n > 0) {
-    if (!cells_small_fits(d)) {
+    if (small) {
+      launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->kin,
+                         c->cell_sorted, c->cnt, s);
+    } else {
       launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
-      launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->sorted, s);
-      launch_cell_sort(ncell, c->cell_start, c->sorted, s);
-      launch_build_records(d, c->sorted, c->cell_id, r, q, semi, v, w, c->rec,
-                           c->kin, c->cell_sorted, s);
+      launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
+                          c->cell_count, ncell, s);
+      launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
+                           q, semi, v, w, c->sorted, c->rec, c->kin, c->cell_sorted, s);
     }
     mark(1);
     launch_neighbors_wave(d, c->rec, c->sorted, c->cell_sorted, c->cell_start,
                           c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
-                          c->work_t, c->cnt, s);
+                          c->work_t, c->stat_nbr, c->cnt, s);
     mark(2);
     const float* seeds = nullptr;
     if (c->opt.seed_mode == LUB_SEED_MLP) {
@@ -296,14 +314,15 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
       seeds = c->seedY;
     }
     launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
-                 c->out_h, c->out_status, c->out_iters, c->cnt, s);
+                 c->out_h, c->out_status, c->out_iters, c->stat_pair, c->cnt, s);
     mark(3);
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
-                  c->cnt, f, t, s);
+                  c->cnt, next_cnt, f, t, s);
     mark(4);
     if (timing) c->pending.push_back(ev);
   }
   HIP_TRY(hipGetLastError());
+  c->zeroed = d.n > 0;
   c->last = d;
   c->have_last = true;
   c->last_stream = s;
@@ -312,6 +331,9 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
 
 int fetch_counters(lub_ctx* c) {
   HIP_TRY(hipSetDevice(c->device));
+  // the statistics are kept as per-block rows: sum them now
+  if (c->have_last)
+    launch_stats_reduce(c->last, c->cnt, c->stat_pair, c->stat_nbr, c->last_stream);
   HIP_TRY(hipMemcpyAsync(c->host_cnt, c->cnt, sizeof(Counters),
                          hipMemcpyDeviceToHost, c->last_stream));
   HIP_TRY(hipStreamSynchronize(c->last_stream));
@@ -407,12 +429,17 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     delete c;
     return LUB_EDEVICE;
   }
-  if (hipMalloc((void**)&c->cnt, sizeof(Counters)) != hipSuccess ||
+  if (hipMalloc((void**)&c->cnt_buf, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&c->host_cnt, sizeof(Counters), 0) != hipSuccess) {
     lub_destroy(c);
     return LUB_ENOMEM;
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
+  c->cnt = c->cnt_buf;
+  if (hipMemset(c->cnt_buf, 0, 2 * sizeof(Counters)) != hipSuccess) {
+    lub_destroy(c);
+    return LUB_EDEVICE;
+  }
   {
     int rc2 = LUB_OK;
     if (!rc2) rc2 = realloc_buf(&c->th, kNParams);
@@ -422,6 +449,7 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     if (!rc2) rc2 = realloc_buf(&c->wt, kWtTotal);
     if (!rc2) rc2 = realloc_buf(&c->wb, kWbTotal);
     if (!rc2) rc2 = realloc_buf(&c->dloss, 64);
+    if (!rc2) rc2 = realloc_buf(&c->stat_pair, (int64_t)kStatPairWords * kMaxPairBlocks);
     if (!rc2) rc2 = mlp_init_host(c, 0);
     if (rc2) {
       lub_destroy(c);
@@ -712,7 +740,7 @@ void lub_destroy(lub_handle_t h) {
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
-                  h->cnt, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
+                  h->cnt_buf, h->scat, h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY};
   for (void* p : bufs)
     if (p) hipFree(p);

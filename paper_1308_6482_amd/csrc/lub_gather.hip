@@ -39,9 +39,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ slot,
     const int32_t* __restrict__ wall_slot, const PairOut<R>* __restrict__ out,
-    const Counters* cnt, double* __restrict__ f, double* __restrict__ t) {
+    const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
+    double* __restrict__ t) {
   const int lane = threadIdx.x & 63;
   const int s = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < (int)(sizeof(Counters) / sizeof(int32_t));
+         i += blockDim.x)
+      reinterpret_cast<int32_t*>(next_cnt)[i] = 0;
   if (s >= d.n) return;  // whole wavefront
   const size_t stride = (size_t)d.max_nbr;
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -97,17 +102,81 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, double* f, double* t, hipStream_t s) {
+                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
+                   hipStream_t s) {
   if (d.n == 0) return;
   dim3 grid((d.n + kWaves - 1) / kWaves);
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_gather<float>, grid, dim3(64 * kWaves), 0, s, d, orig,
                        deg, nbr, slot, wall_slot, (const PairOut<float>*)out,
-                       cnt, f, t);
+                       cnt, next_cnt, f, t);
   else
     hipLaunchKernelGGL(k_gather<double>, grid, dim3(64 * kWaves), 0, s, d, orig,
                        deg, nbr, slot, wall_slot, (const PairOut<double>*)out,
-                       cnt, f, t);
+                       cnt, next_cnt, f, t);
+}
+
+namespace {
+
+// One block per statistic: the sum (or, for the largest iteration count,
+// the maximum) of that word over the rows the last call's blocks wrote.
+constexpr int kReduceThreads = 256;
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_blocks,
+               const int64_t* __restrict__ stat_nbr, int nbr_rows, int cap_work) {
+  __shared__ int64_t part[kReduceThreads / 64];
+  const int word = blockIdx.x;
+  int rows, stride;
+  const int64_t* base;
+  if (word < kStatPairWords) {
+    const int nwork = cnt->error == 0 ? min(cnt->work, cap_work) : 0;
+    rows = min(pair_blocks, (nwork + 63) / 64);
+    base = stat_pair + word;
+    stride = kStatPairWords;
+  } else {
+    rows = nbr_rows;
+    base = stat_nbr + (word - kStatPairWords);
+    stride = kStatNbrWords;
+  }
+  const bool is_max = word == 6;
+  int64_t acc = 0;
+  for (int r = threadIdx.x; r < rows; r += kReduceThreads) {
+    const int64_t v = base[(int64_t)r * stride];
+    acc = is_max ? max(acc, v) : acc + v;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int64_t y = __shfl_xor(acc, o, 64);
+    acc = is_max ? max(acc, y) : acc + y;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < kReduceThreads / 64; ++k) acc = is_max ? max(acc, part[k]) : acc + part[k];
+  switch (word) {
+    case 0: cnt->newton_iters = acc; break;
+    case 1: cnt->active = acc; break;
+    case 2: cnt->overlaps = acc; break;
+    case 3: cnt->unresolved = acc; break;
+    case 4: cnt->unconverged = acc; break;
+    case 5: cnt->fallbacks = acc; break;
+    case 6: cnt->newton_max = (int32_t)acc; break;
+    case 7: break;
+    case kStatPairWords: cnt->candidates = acc; break;
+    case kStatPairWords + 1: cnt->wall_candidates = acc; break;
+    default: cnt->iter_hist[word - 8] = acc; break;
+  }
+}
+
+}  // namespace
+
+void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_pair,
+                         const int64_t* stat_nbr, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_stats_reduce, dim3(kStatPairWords + kStatNbrWords),
+                     dim3(kReduceThreads), 0, s, cnt, stat_pair, pair_grid(d), stat_nbr,
+                     nbr_blocks(d.n), d.cap_work);
 }
 
 }  // namespace lub

@@ -45,12 +45,23 @@ struct Counters {
   int64_t iter_hist[32];
 };
 
+// Per-block partial statistics, written with plain stores and summed only
+// when the host asks for the counters.
+//   pair kernel rows: [0] Newton iterations, [1] active, [2] overlaps,
+//   [3] unresolved, [4] unconverged, [5] fallbacks, [6] max iterations,
+//   [7] unused, [8..39] iteration histogram
+//   neighbour kernel rows: [0] candidate pairs, [1] wall candidates
+constexpr int kStatPairWords = 40;
+constexpr int kStatNbrWords = 2;
+constexpr int kMaxPairBlocks = 16384;  // larger slot counts: grid-stride loop
+
 // Constant description of one call.
 struct CallDesc {
   int32_t n;
   int32_t nc[3];         // cells per axis
   double cell[3];        // cell edge per axis
   double L[3];
+  double invL[3];       // 1 / L
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
@@ -90,29 +101,30 @@ void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       Counters* cnt, hipStream_t s);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
                  int64_t* total, hipStream_t s);
+// scatter into the cells' ranges (arbitrary order); zeroes cell_count
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* sorted, hipStream_t s);
-void launch_cell_sort(int ncell, const int32_t* cell_start, int32_t* sorted,
-                      hipStream_t s);
-void launch_build_records(const CallDesc& d, const int32_t* sorted,
-                          const int32_t* cell_id, const double* r,
+                         int32_t* unsorted, int32_t* cell_count, int ncell,
+                         hipStream_t s);
+// in-cell placement by input index and the records; zeroes cell_fill
+void launch_build_records(const CallDesc& d, const int32_t* unsorted,
+                          const int32_t* cell_id, const int32_t* cell_start,
+                          int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, PRec* rec, KRec* kin,
+                          const double* w, int32_t* sorted, PRec* rec, KRec* kin,
                           int32_t* cell_sorted, hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_id, int32_t* cell_start, int32_t* sorted,
-                        PRec* rec, KRec* kin, int32_t* cell_sorted, Counters* cnt,
-                        hipStream_t s);
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, KRec* kin,
+                        int32_t* cell_sorted, Counters* cnt, hipStream_t s);
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
-                           int32_t* work_s, int32_t* work_t, Counters* cnt,
-                           hipStream_t s);
+                           int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
+                           Counters* cnt, hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the
@@ -120,7 +132,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  Counters* cnt, hipStream_t s);
+                  int64_t* stat_pair, Counters* cnt, hipStream_t s);
 
 // seed features of every particle-particle evaluation slot (m x 10, FP32)
 void launch_seed_features(const CallDesc& d, const PRec* rec,
@@ -141,10 +153,33 @@ int mlp_train_step(int64_t m, int64_t off, int B, const float* X, const float* T
 void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
                        const __bf16* wt, const float* th, hipStream_t s);
 
-// ---- per-particle reduction (lub_gather.hip) ------------------------------
+// per-particle sums; also zeroes `next_cnt`, the counters of the next call
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, double* f, double* t, hipStream_t s);
+                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
+                   hipStream_t s);
+
+// grid of the pair kernel for a given slot capacity
+int pair_grid(const CallDesc& d);
+// neighbour-kernel blocks for n particles
+int nbr_blocks(int n);
+// sum the per-block partial statistics of the last call into `cnt`
+void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_pair,
+                         const int64_t* stat_nbr, hipStream_t s);
+
+#ifdef __HIPCC__
+// Minimum-image displacement along a periodic axis, dx - L rint(dx / L),
+// with the quotient taken as dx (1/L): the two round to different integers
+// only next to a half-integer, and there the division itself decides.
+// No contraction, so the result equals the plain expression bit for bit.
+__device__ __forceinline__ double min_image(double dx, double L, double invL) {
+#pragma clang fp contract(off)
+  const double x = dx * invL;
+  double k = rint(x);
+  if (fabs(fabs(x - k) - 0.5) < 1e-9) k = rint(dx / L);
+  return dx - L * k;
+}
+#endif
 
 }  // namespace lub

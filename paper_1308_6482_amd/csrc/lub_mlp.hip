@@ -341,59 +341,73 @@ struct DwLayer {
   int off;           // parameter offset of W (row-major in x out_real)
 };
 
+// One workgroup per 16 x 16 tile of dW: its kWaves wavefronts take
+// interleaved 32-sample slices of the batch, the partial tiles are summed in
+// LDS.  Tiles are numbered layer by layer.
 __global__ void __launch_bounds__(64 * kWaves) k_dw(int B, DwLayer l1, DwLayer l2, DwLayer l3,
                                                    DwLayer l4, float* __restrict__ grad) {
+  __shared__ f32x4 part[kWaves][64];
   const int lane = threadIdx.x & 63;
-  int t = blockIdx.x * kWaves + (threadIdx.x >> 6);
-  const DwLayer* L = nullptr;
-  DwLayer ls[4] = {l1, l2, l3, l4};
-  for (int k = 0; k < 4; ++k) {
-    int nt = ls[k].in_tiles * ls[k].out_tiles;
-    if (t < nt) {
-      L = &ls[k];
-      break;
-    }
-    t -= nt;
+  const int wv = threadIdx.x >> 6;
+  int t = blockIdx.x;
+  DwLayer L;
+  const int n1 = l1.in_tiles * l1.out_tiles, n2 = l2.in_tiles * l2.out_tiles,
+            n3 = l3.in_tiles * l3.out_tiles, n4 = l4.in_tiles * l4.out_tiles;
+  if (t < n1) {
+    L = l1;
+  } else if ((t -= n1) < n2) {
+    L = l2;
+  } else if ((t -= n2) < n3) {
+    L = l3;
+  } else if ((t -= n3) < n4) {
+    L = l4;
+  } else {
+    return;  // whole workgroup
   }
-  if (!L) return;
-  const int ti = t / L->out_tiles, to = t % L->out_tiles;
+  const int ti = t / L.out_tiles, to = t % L.out_tiles;
   const int r16 = lane % 16, g = lane / 16;
   f32x4 c = {0.f, 0.f, 0.f, 0.f};
-  const __bf16* ap = L->aT + (int64_t)(16 * ti + r16) * B + 8 * g;
-  const __bf16* dp = L->dT + (int64_t)(16 * to + r16) * B + 8 * g;
-  for (int k = 0; k < B; k += 32) c = mfma(ld8(ap + k), ld8(dp + k), c);
+  const __bf16* ap = L.aT + (int64_t)(16 * ti + r16) * B + 8 * g;
+  const __bf16* dp = L.dT + (int64_t)(16 * to + r16) * B + 8 * g;
+  for (int k = 32 * wv; k < B; k += 32 * kWaves) c = mfma(ld8(ap + k), ld8(dp + k), c);
+  part[wv][lane] = c;
+  __syncthreads();
+  if (wv != 0) return;
+  for (int w = 1; w < kWaves; ++w) {
+    const f32x4 o = part[w][lane];
+    for (int i = 0; i < 4; ++i) c[i] += o[i];
+  }
   const int o = 16 * to + r16;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int in = 16 * ti + 4 * g + i;
-    if (in < L->in_real && o < L->out_real) grad[L->off + in * L->out_real + o] = c[i];
+    if (in < L.in_real && o < L.out_real) grad[L.off + in * L.out_real + o] = c[i];
   }
 }
 
-// bias gradients: sum of the deltas over the batch (FP32)
-__global__ void k_db(int B, const __bf16* __restrict__ dT, float* __restrict__ grad) {
-  int u = blockIdx.x * blockDim.x + threadIdx.x;  // 0..387
-  const int64_t Bp = B;
-  const __bf16* row;
-  int dst;
-  if (u < 128) {
-    row = dT + (int64_t)u * Bp;                    // delta1
-    dst = kOffB1 + u;
-  } else if (u < 256) {
-    row = dT + (int64_t)(128 + u - 128) * Bp;      // delta2
-    dst = kOffB2 + u - 128;
-  } else if (u < 384) {
-    row = dT + (int64_t)(256 + u - 256) * Bp;      // delta3
-    dst = kOffB3 + u - 256;
-  } else if (u < 388) {
-    row = dT + (int64_t)(384 + u - 384) * Bp;      // delta4
-    dst = kOffB4 + u - 384;
-  } else {
-    return;
-  }
+// bias gradients: the sum of each delta row over the batch (FP32), one
+// wavefront per row with 16-byte loads
+constexpr int kBiasRows = 3 * 128 + 4;
+
+__global__ void __launch_bounds__(64 * kWaves) k_db(int B, const __bf16* __restrict__ dT,
+                                                   float* __restrict__ grad) {
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (u >= kBiasRows) return;  // whole wavefront
+  // rows of dT: delta1 [0,128), delta2 [128,256), delta3 [256,384), delta4 [384,388)
+  const int dst = u < 128 ? kOffB1 + u
+                : u < 256 ? kOffB2 + (u - 128)
+                : u < 384 ? kOffB3 + (u - 256)
+                          : kOffB4 + (u - 384);
+  const __bf16* row = dT + (int64_t)u * B;
   float s = 0.f;
-  for (int k = 0; k < B; ++k) s += (float)row[k];
-  grad[dst] = s;
+  for (int k = 8 * lane; k < B; k += 8 * 64) {
+    const bf16x8 v = ld8(row + k);
+    for (int i = 0; i < 8; ++i) s += (float)v[i];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) grad[dst] = s;
 }
 
 __global__ void k_adam(const float* __restrict__ grad, float* __restrict__ th,
@@ -464,9 +478,9 @@ int mlp_train_step(int64_t m, int64_t off, int B, const float* X, const float* T
   DwLayer l3{aT + 160 * Bp, dT + 256 * Bp, 128, 128, 8, 8, kOffW3};
   DwLayer l4{aT + 288 * Bp, dT + 384 * Bp, 128, 4, 8, 1, kOffW4};
   const int tiles = 8 + 64 + 64 + 8;
-  hipLaunchKernelGGL(k_dw, dim3((tiles + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, s, B,
-                     l1, l2, l3, l4, grad);
-  hipLaunchKernelGGL(k_db, dim3(2), dim3(256), 0, s, B, dT, grad);
+  hipLaunchKernelGGL(k_dw, dim3(tiles), dim3(64 * kWaves), 0, s, B, l1, l2, l3, l4, grad);
+  hipLaunchKernelGGL(k_db, dim3((kBiasRows + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, s,
+                     B, dT, grad);
   if (update) {
     float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, grad, th, m1,

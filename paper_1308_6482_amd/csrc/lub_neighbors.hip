@@ -49,9 +49,9 @@ __device__ __forceinline__ bool centre_test(const double* ri, const double* rj,
   double dx = rj[0] - ri[0];
   double dy = rj[1] - ri[1];
   double dz = rj[2] - ri[2];
-  if (d.periodic[0]) dx = dx - d.L[0] * rint(dx / d.L[0]);
-  if (d.periodic[1]) dy = dy - d.L[1] * rint(dy / d.L[1]);
-  if (d.periodic[2]) dz = dz - d.L[2] * rint(dz / d.L[2]);
+  if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
+  if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
+  if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
   double d2 = dx * dx + dy * dy;
   d2 = d2 + dz * dz;
   double sb = (rmi + rmj) + d.dmax;
@@ -197,33 +197,19 @@ __global__ void k_scan_add(int32_t* out, int n, const int32_t* block_sums) {
   }
 }
 
+// Particles into their cells' ranges in arbitrary order (atomic cursors).
+// The counts have been consumed by the scan: they are zeroed here for the
+// next call.
 __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
                                const int32_t* __restrict__ cell_start,
                                int32_t* __restrict__ cell_fill,
-                               int32_t* __restrict__ sorted) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n) return;
-  int c = cell_id[p];
-  int pos = cell_start[c] + atomicAdd(&cell_fill[c], 1);
-  sorted[pos] = p;
-}
-
-// the atomic scatter leaves each cell in arbitrary order: sort it by input
-// index so that every later step is deterministic
-__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ cell_start,
-                            int32_t* __restrict__ sorted) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  int b = cell_start[c], e = cell_start[c + 1];
-  for (int i = b + 1; i < e; ++i) {
-    int key = sorted[i];
-    int j = i - 1;
-    while (j >= b && sorted[j] > key) {
-      sorted[j + 1] = sorted[j];
-      --j;
-    }
-    sorted[j + 1] = key;
-  }
+                               int32_t* __restrict__ unsorted,
+                               int32_t* __restrict__ cell_count, int ncell) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
+  if (i >= d.n) return;
+  const int c = cell_id[i];
+  unsorted[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
 }
 
 // Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
@@ -273,18 +259,32 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
   cell_sorted[s] = cell_id[p];
 }
 
-__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ sorted,
+// Each cell's members in increasing input index (the position of a particle
+// is its cell's start plus the number of members with a smaller index), so
+// that every later step is deterministic, and their records.  The cursors
+// of the scatter are zeroed here for the next call.
+__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
                                 const int32_t* __restrict__ cell_id,
+                                const int32_t* __restrict__ cell_start,
+                                int32_t* __restrict__ cell_fill, int ncell,
                                 const double* __restrict__ r,
                                 const double* __restrict__ q,
                                 const double* __restrict__ semi,
                                 const double* __restrict__ v,
-                                const double* __restrict__ w, PRec* __restrict__ rec,
-                                KRec* __restrict__ kin,
+                                const double* __restrict__ w, int32_t* __restrict__ sorted,
+                                PRec* __restrict__ rec, KRec* __restrict__ kin,
                                 int32_t* __restrict__ cell_sorted) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= d.n) return;
-  make_record(s, sorted[s], cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
+  if (i >= d.n) return;
+  const int p = unsorted[i];
+  const int c = cell_id[p];
+  const int b = cell_start[c], e = cell_start[c + 1];
+  int rank = 0;
+  for (int k = b; k < e; ++k) rank += unsorted[k] < p;
+  const int s = b + rank;
+  sorted[s] = p;
+  make_record(s, p, cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
@@ -319,32 +319,35 @@ __device__ __forceinline__ double support(const double* M, double nx, double ny,
   return sqrt(nx * mx + ny * my + nz * mz);
 }
 
-// Whole cell build in one workgroup for systems whose grid fits in LDS:
-// counter reset, validation and binning, counts, exclusive scan, scatter,
-// per-cell sort by input index and the cell-order records.  Replaces six
-// launches by one for small and medium systems.
+// Whole cell build in one workgroup for small systems (all per-particle and
+// per-cell arrays in LDS): counter reset, validation and binning, counts,
+// exclusive scan, scatter, placement in increasing input index within each
+// cell and the cell-order records.  Replaces four to six launches.
 constexpr int kSmallThreads = 1024;
+constexpr int kSmallMaxN = 1024;
+constexpr int kSmallMaxCells = 4096;
 
 __global__ void __launch_bounds__(kSmallThreads)
 k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
               const double* __restrict__ semi, const double* __restrict__ v,
-              const double* __restrict__ w, int32_t* __restrict__ cell_id,
-              int32_t* __restrict__ cell_start, int32_t* __restrict__ sorted,
-              PRec* __restrict__ rec, KRec* __restrict__ kin,
-              int32_t* __restrict__ cell_sorted, Counters* cnt) {
-  extern __shared__ int32_t lds_cells[];  // counts / cursors [ncell], starts [ncell + 1]
+              const double* __restrict__ w, int32_t* __restrict__ cell_start,
+              int32_t* __restrict__ sorted, PRec* __restrict__ rec,
+              KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted, Counters* cnt) {
+  __shared__ int32_t cnt_l[kSmallMaxCells];        // counts, then cursors
+  __shared__ int32_t start_l[kSmallMaxCells + 1];
+  __shared__ int32_t cid_l[kSmallMaxN];            // cell of each input index
+  __shared__ int32_t scat_l[kSmallMaxN];           // scatter output
   __shared__ int lds_scan[16];
   const int ncell = d.nc[0] * d.nc[1] * d.nc[2];
-  int32_t* cnt_l = lds_cells;
-  int32_t* start_l = lds_cells + ncell;
   const int tid = threadIdx.x;
   for (int i = tid; i < (int)(sizeof(Counters) / sizeof(int32_t)); i += kSmallThreads)
     reinterpret_cast<int32_t*>(cnt)[i] = 0;
   for (int c = tid; c < ncell; c += kSmallThreads) cnt_l[c] = 0;
   __syncthreads();
-  for (int p = tid; p < d.n; p += kSmallThreads) {
-    int c = validate_bin(d, r, q, semi, p, cnt);
-    cell_id[p] = c;
+  const bool mine = tid < d.n;
+  if (mine) {
+    const int c = validate_bin(d, r, q, semi, tid, cnt);
+    cid_l[tid] = c;
     atomicAdd(&cnt_l[c], 1);
   }
   __syncthreads();
@@ -352,18 +355,19 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
   const int per = (ncell + kSmallThreads - 1) / kSmallThreads;
   int run = 0;
   for (int k = 0; k < per; ++k) {
-    int c = tid * per + k;
+    const int c = tid * per + k;
     run += c < ncell ? cnt_l[c] : 0;
   }
   int tot;
-  int incl = block_inclusive_scan(run, lds_scan, &tot);
+  const int incl = block_inclusive_scan(run, lds_scan, &tot);
   int acc = incl - run;
   for (int k = 0; k < per; ++k) {
-    int c = tid * per + k;
+    const int c = tid * per + k;
     if (c < ncell) {
       start_l[c] = acc;
       cell_start[c] = acc;
       acc += cnt_l[c];
+      cnt_l[c] = 0;
     }
   }
   if (tid == 0) {
@@ -371,30 +375,21 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
     cell_start[ncell] = tot;
   }
   __syncthreads();
-  for (int c = tid; c < ncell; c += kSmallThreads) cnt_l[c] = 0;
-  __syncthreads();
-  for (int p = tid; p < d.n; p += kSmallThreads) {
-    int c = cell_id[p];
-    sorted[start_l[c] + atomicAdd(&cnt_l[c], 1)] = p;
+  if (mine) {
+    const int c = cid_l[tid];
+    scat_l[start_l[c] + atomicAdd(&cnt_l[c], 1)] = tid;
   }
-  __threadfence_block();
   __syncthreads();
-  for (int c = tid; c < ncell; c += kSmallThreads) {
-    int b = start_l[c], e = start_l[c + 1];
-    for (int i = b + 1; i < e; ++i) {
-      int key = sorted[i];
-      int j = i - 1;
-      while (j >= b && sorted[j] > key) {
-        sorted[j + 1] = sorted[j];
-        --j;
-      }
-      sorted[j + 1] = key;
-    }
+  if (mine) {
+    const int p = scat_l[tid];
+    const int c = cid_l[p];
+    const int b = start_l[c], e = start_l[c + 1];
+    int rank = 0;
+    for (int k = b; k < e; ++k) rank += scat_l[k] < p;
+    const int s = b + rank;
+    sorted[s] = p;
+    make_record(s, p, cid_l, r, q, semi, v, w, rec, kin, cell_sorted);
   }
-  __threadfence_block();
-  __syncthreads();
-  for (int s = tid; s < d.n; s += kSmallThreads)
-    make_record(s, sorted[s], cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
 }
 
 // One wavefront per particle: candidate test over the 27 neighbour cells
@@ -417,7 +412,7 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
                  int32_t* __restrict__ deg, int32_t* __restrict__ nbr,
                  int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
                  int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
-                 Counters* cnt) {
+                 int64_t* __restrict__ stat_nbr, Counters* cnt) {
   extern __shared__ int32_t lds_keys[];  // kWavesPerBlock * max_nbr
   __shared__ int s_keep[kWavesPerBlock];
   __shared__ int s_upper[kWavesPerBlock];
@@ -525,13 +520,14 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
       ++nupper;
       double dx = rec[key].r[0] - rs[0], dy = rec[key].r[1] - rs[1],
              dz = rec[key].r[2] - rs[2];
-      if (d.periodic[0]) dx -= d.L[0] * rint(dx / d.L[0]);
-      if (d.periodic[1]) dy -= d.L[1] * rint(dy / d.L[1]);
-      if (d.periodic[2]) dz -= d.L[2] * rint(dz / d.L[2]);
+      if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
+      if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
+      if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
       double dn = sqrt(dx * dx + dy * dy + dz * dz);
       bool keep = true;
       if (dn > 0.0) {
-        double ux = dx / dn, uy = dy / dn, uz = dz / dn;
+        const double idn = 1.0 / dn;
+        double ux = dx * idn, uy = dy * idn, uz = dz * idn;
         double g = dn - support(Mi, ux, uy, uz) - support(rec[key].M, ux, uy, uz);
         keep = g < d.dmax;
       }
@@ -582,8 +578,8 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
     int b = tot ? atomicAdd(&cnt->work, tot) : 0;
     if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
     for (int k = 0; k < kWavesPerBlock; ++k) s_base[k] += b;
-    if (up) atomicAdd((unsigned long long*)&cnt->candidates, (unsigned long long)up);
-    if (wc) atomicAdd((unsigned long long*)&cnt->wall_candidates, (unsigned long long)wc);
+    stat_nbr[kStatNbrWords * blockIdx.x] = up;
+    stat_nbr[kStatNbrWords * blockIdx.x + 1] = wc;
     s_keep[0] = b + tot <= d.cap_work;
   }
   __syncthreads();
@@ -646,57 +642,52 @@ void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
 
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* sorted, hipStream_t s) {
+                         int32_t* unsorted, int32_t* cell_count, int ncell,
+                         hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_cell_scatter, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, cell_id, cell_start, cell_fill, sorted);
+                     d, cell_id, cell_start, cell_fill, unsorted, cell_count, ncell);
 }
 
-void launch_cell_sort(int ncell, const int32_t* cell_start, int32_t* sorted,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_cell_sort, dim3((ncell + 255) / 256), dim3(256), 0, s,
-                     ncell, cell_start, sorted);
-}
-
-void launch_build_records(const CallDesc& d, const int32_t* sorted,
-                          const int32_t* cell_id, const double* r,
+void launch_build_records(const CallDesc& d, const int32_t* unsorted,
+                          const int32_t* cell_id, const int32_t* cell_start,
+                          int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, PRec* rec, KRec* kin,
+                          const double* w, int32_t* sorted, PRec* rec, KRec* kin,
                           int32_t* cell_sorted, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, sorted, cell_id, r, q, semi, v, w, rec, kin,
-                     cell_sorted);
+                     d, unsorted, cell_id, cell_start, cell_fill, ncell, r, q, semi,
+                     v, w, sorted, rec, kin, cell_sorted);
 }
 
 bool cells_small_fits(const CallDesc& d) {
   const int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
-  return d.n <= (1 << 15) && ncell <= 8000;  // LDS: 2 ncell + 1 ints < 64 KiB
+  return d.n <= kSmallMaxN && ncell <= kSmallMaxCells;
 }
 
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_id, int32_t* cell_start, int32_t* sorted,
-                        PRec* rec, KRec* kin, int32_t* cell_sorted, Counters* cnt,
-                        hipStream_t s) {
-  const int ncell = d.nc[0] * d.nc[1] * d.nc[2];
-  size_t lds = sizeof(int32_t) * (2 * (size_t)ncell + 1);
-  hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), lds, s, d, r, q, semi,
-                     v, w, cell_id, cell_start, sorted, rec, kin, cell_sorted, cnt);
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, KRec* kin,
+                        int32_t* cell_sorted, Counters* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, d, r, q, semi,
+                     v, w, cell_start, sorted, rec, kin, cell_sorted, cnt);
 }
 
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
-                           int32_t* work_s, int32_t* work_t, Counters* cnt,
-                           hipStream_t s) {
+                           int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
+                           Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
-  dim3 grid((d.n + kWavesPerBlock - 1) / kWavesPerBlock);
+  dim3 grid(nbr_blocks(d.n));
   size_t lds = sizeof(int32_t) * kWavesPerBlock * (size_t)d.max_nbr;
   hipLaunchKernelGGL(k_neighbors_wave, grid, dim3(64 * kWavesPerBlock), lds, s,
                      d, rec, orig, cell_sorted, cell_start, deg, nbr, slot,
-                     wall_slot, work_s, work_t, cnt);
+                     wall_slot, work_s, work_t, stat_nbr, cnt);
 }
+
+int nbr_blocks(int n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
 
 }  // namespace lub

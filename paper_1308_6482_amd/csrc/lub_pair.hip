@@ -416,7 +416,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   if (B) {
     double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
     for (int k = 0; k < 3; ++k)
-      if (cd.periodic[k]) d[k] -= cd.L[k] * rint(d[k] / cd.L[k]);
+      if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
     double n0[3];
     if (seedY && seed_normal(d, A, *B, seedY, n0)) {
       // learned start; the plain start judges it: if the seeded iteration
@@ -561,58 +561,74 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               double* __restrict__ out_h,
                                               int8_t* __restrict__ out_status,
                                               uint8_t* __restrict__ out_iters,
-                                              Counters* cnt) {
-  __shared__ unsigned long long s_hist[32];
-  __shared__ unsigned long long s_stat[6];
-  __shared__ int s_max;
+                                              int64_t* __restrict__ stat_pair,
+                                              const Counters* cnt) {
+  // one wavefront per block: statistics are reduced in the wave (ballots,
+  // shuffles) and written as this block's row, without atomics
+  static_assert(kPairBlock == 64, "one wavefront per block");
+  const int lane = threadIdx.x;
   // the grid is sized for the capacity; blocks past the device-side work
-  // count leave at once
+  // count leave at once (their rows are not read)
   const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
   if (blockIdx.x * blockDim.x >= nwork) return;
-  if (threadIdx.x < 32) s_hist[threadIdx.x] = 0;
-  if (threadIdx.x < 6) s_stat[threadIdx.x] = 0;
-  if (threadIdx.x == 0) s_max = 0;
-  __syncthreads();
-  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nwork;
-       w += gridDim.x * blockDim.x) {
-    int s = work_s[w], t = work_t[w];
-    PairOut<R> o;
-    double h;
-    int status, iters, fb = 0;
-    if (t >= 0) {
-      float y[4];
-      if (seedY)
-        for (int k = 0; k < 4; ++k) y[k] = seedY[4 * (int64_t)w + k];
-      eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
-                   seedY ? y : nullptr, &fb);
-    } else
-      eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
-                   iters);
-    out[w] = o;
-    out_h[w] = h;
-    out_status[w] = (int8_t)status;
-    out_iters[w] = (uint8_t)(iters > 255 ? 255 : iters);
-    atomicAdd(&s_hist[iters < 31 ? iters : 31], 1ull);
-    atomicAdd(&s_stat[0], (unsigned long long)iters);
-    if (status == 0) atomicAdd(&s_stat[1], 1ull);
-    if (status == 0 && h <= 0.0) atomicAdd(&s_stat[2], 1ull);
-    if (status == 2) atomicAdd(&s_stat[3], 1ull);
-    if (status == 3) atomicAdd(&s_stat[4], 1ull);
-    if (fb) atomicAdd(&s_stat[5], 1ull);
-    atomicMax(&s_max, iters);
+  int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0;
+  int max_it = 0;
+  int64_t my_hist = 0;  // lane b < 32 holds histogram bucket b
+  for (int w0 = blockIdx.x * blockDim.x; w0 < nwork; w0 += gridDim.x * blockDim.x) {
+    const int w = w0 + lane;
+    const bool on = w < nwork;
+    int status = -1, iters = 0, fb = 0;
+    double h = 0.0;
+    if (on) {
+      int s = work_s[w], t = work_t[w];
+      PairOut<R> o;
+      if (t >= 0)
+        eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+                     seedY ? seedY + 4 * (int64_t)w : nullptr, &fb);
+      else
+        eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
+                     iters);
+      out[w] = o;
+      out_h[w] = h;
+      out_status[w] = (int8_t)status;
+      out_iters[w] = (uint8_t)(iters > 255 ? 255 : iters);
+    }
+    const int bucket = on ? (iters < 31 ? iters : 31) : -1;
+    n_iters += iters;
+    max_it = max(max_it, iters);
+    n_active += __popcll(__ballot(status == 0));
+    n_overlap += __popcll(__ballot(status == 0 && h <= 0.0));
+    n_unres += __popcll(__ballot(status == 2));
+    n_uncon += __popcll(__ballot(status == 3));
+    n_fb += __popcll(__ballot(fb != 0));
+    // histogram over the buckets present in this pass
+    int lo = on ? bucket : 32, hi = bucket;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o, 64));
+      hi = max(hi, __shfl_xor(hi, o, 64));
+    }
+    for (int b = lo; b <= hi; ++b) {
+      const int64_t c = __popcll(__ballot(bucket == b));
+      if (lane == b) my_hist += c;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < 32 && s_hist[threadIdx.x])
-    atomicAdd((unsigned long long*)&cnt->iter_hist[threadIdx.x], s_hist[threadIdx.x]);
-  if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long*)&cnt->newton_iters, s_stat[0]);
-    atomicAdd((unsigned long long*)&cnt->active, s_stat[1]);
-    atomicAdd((unsigned long long*)&cnt->overlaps, s_stat[2]);
-    atomicAdd((unsigned long long*)&cnt->unresolved, s_stat[3]);
-    atomicAdd((unsigned long long*)&cnt->unconverged, s_stat[4]);
-    if (s_stat[5]) atomicAdd((unsigned long long*)&cnt->fallbacks, s_stat[5]);
-    atomicMax(&cnt->newton_max, s_max);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    n_iters += __shfl_xor(n_iters, o, 64);
+    max_it = max(max_it, __shfl_xor(max_it, o, 64));
   }
+  int64_t* row = stat_pair + (int64_t)kStatPairWords * blockIdx.x;
+  const int64_t v = lane == 0 ? n_iters
+                  : lane == 1 ? n_active
+                  : lane == 2 ? n_overlap
+                  : lane == 3 ? n_unres
+                  : lane == 4 ? n_uncon
+                  : lane == 5 ? n_fb
+                  : lane == 6 ? (int64_t)max_it
+                              : 0;
+  if (lane < 8) row[lane] = v;
+  if (lane < 32) row[8 + lane] = my_hist;
 }
 
 // seed features of the particle-particle slots
@@ -630,7 +646,7 @@ __global__ void k_seed_features(CallDesc cd, const PRec* __restrict__ rec,
       const PRec& B = rec[t];
       double d[3] = {B.r[0] - A.r[0], B.r[1] - A.r[1], B.r[2] - A.r[2]};
       for (int k = 0; k < 3; ++k)
-        if (cd.periodic[k]) d[k] -= cd.L[k] * rint(d[k] / cd.L[k]);
+        if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
       seed_features(d, A, B, x);
     }
     for (int k = 0; k < 10; ++k) X[10 * (int64_t)w + k] = x[k];
@@ -649,21 +665,25 @@ void launch_seed_features(const CallDesc& d, const PRec* rec,
                      work_s, work_t, X, cnt);
 }
 
+int pair_grid(const CallDesc& d) {
+  int blocks = (d.cap_work + kPairBlock - 1) / kPairBlock;
+  if (blocks > kMaxPairBlocks) blocks = kMaxPairBlocks;  // grid-stride beyond
+  return blocks < 1 ? 1 : blocks;
+}
+
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  Counters* cnt, hipStream_t s) {
-  int blocks = (d.cap_work + kPairBlock - 1) / kPairBlock;
-  if (blocks > 16384) blocks = 16384;  // grid-stride beyond 1M pairs
-  if (blocks < 1) blocks = 1;
+                  int64_t* stat_pair, Counters* cnt, hipStream_t s) {
+  const int blocks = pair_grid(d);
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_pairs<float>, dim3(blocks), dim3(kPairBlock), 0, s, d,
                        rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
-                       out_status, out_iters, cnt);
+                       out_status, out_iters, stat_pair, cnt);
   else
     hipLaunchKernelGGL(k_pairs<double>, dim3(blocks), dim3(kPairBlock), 0, s, d,
                        rec, kin, work_s, work_t, seedY, (PairOut<double>*)out, out_h,
-                       out_status, out_iters, cnt);
+                       out_status, out_iters, stat_pair, cnt);
 }
 
 }  // namespace lub
