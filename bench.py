@@ -225,44 +225,65 @@ def train_seed(L, torch, n_train, epochs):
                        generate_s=t_gen, train_s=t_train)
 
 
+def _timed_loop(lb, torch, args, arrays, stream):
+    """W untimed steps, then exactly K timed steps bracketed by device
+    synchronisations; returns ms per step (wall clock)."""
+    r, q, semi, v, w, f, t = arrays
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+        torch.cuda.synchronize()
+        lb.reset_timers()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / args.steps
+
+
 def measure(L, torch, wl, prec, args, theta=None):
-    """Time `args.steps` evaluations; returns (stats, ms_per_step)."""
+    """Two timed loops of `args.steps` evaluations each on one stream: the
+    launch sequence replayed as a HIP graph (the headline), and eager
+    launches with HIP events around each stage (stage times, pair-kernel
+    duration).  Returns (stats of the event loop, ms per step with graphs,
+    ms per step eager, outputs)."""
     mode = L.LUB_SEED_MLP if theta is not None else L.LUB_SEED_PLAIN
-    lb = L.Lub.for_workload(wl, precision=prec, sync=0, timing=1, seed_mode=mode)
-    if theta is not None:
-        L.lub_mlp_set_weights(lb.h, theta)
     r, q, semi, v, w = L.to_device(wl)
     f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-    # first call synchronous: sizes the workspace and validates the inputs
-    lb.compute(r, q, semi, v, w, f, t)
-    st = lb.stats()
-    if st["error"]:
-        raise RuntimeError(f"lub_compute failed: {L.lub_strerror(st['error'])}")
-    for _ in range(args.warmup):
-        lb.compute(r, q, semi, v, w, f, t, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
-    lb.reset_timers()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        lb.compute(r, q, semi, v, w, f, t, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = lb.stats()
-    lb.close()
-    if st["error"] or st["unconverged"]:
-        raise RuntimeError(f"invalid run: error={st['error']} unconverged={st['unconverged']}")
-    return st, (t1 - t0) * 1e3 / args.steps, (f, t)
+    arrays = (r, q, semi, v, w, f, t)
+    stream = torch.cuda.Stream()
+    results = {}
+    for kind in ("graph", "eager"):
+        kw = dict(graph=1) if kind == "graph" else dict(timing=1)
+        lb = L.Lub.for_workload(wl, precision=prec, sync=0, seed_mode=mode, **kw)
+        if theta is not None:
+            L.lub_mlp_set_weights(lb.h, theta)
+        # first call: sizes the workspace; its statistics validate the inputs
+        with torch.cuda.stream(stream):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+        torch.cuda.synchronize()
+        st = lb.stats()
+        if st["error"]:
+            raise RuntimeError(f"lub_compute failed: {L.lub_strerror(st['error'])}")
+        ms = _timed_loop(lb, torch, args, arrays, stream)
+        st = lb.stats()
+        lb.close()
+        if st["error"] or st["unconverged"]:
+            raise RuntimeError(f"invalid run: error={st['error']} "
+                               f"unconverged={st['unconverged']}")
+        results[kind] = (st, ms)
+    return results["eager"][0], results["graph"][1], results["eager"][1], (f, t)
 
 
-def summary(st, ms, args):
+def summary(st, ms, args, ms_eager=None):
     active = st["active"]
     pair_ms = st["stage_ms"][2] / max(st["timed_calls"], 1)
     flops = (FLOPS_EVAL * st["evaluated"] + FLOPS_ITER * st["newton_iters"]
              + FLOPS_POST[args.precision] * active)
-    return dict(value=active / (ms * 1e-3), ms_per_step=ms,
+    return dict(value=active / (ms * 1e-3), ms_per_step=ms, ms_per_step_eager=ms_eager,
                 newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
                 newton_max=st["newton_max"], fallbacks=st["fallbacks"],
                 pair_kernel_ms=pair_ms, flops_per_launch=flops,
@@ -292,11 +313,11 @@ def main():
     if args.seed in ("mlp", "both"):
         theta, mlp_report = train_seed(L, torch, args.train_pairs, args.train_epochs)
     if args.seed in ("plain", "both"):
-        st, ms, out_plain = measure(L, torch, wl, prec, args)
-        forms["plain"] = (st, ms)
+        st, ms, ms_e, out_plain = measure(L, torch, wl, prec, args)
+        forms["plain"] = (st, ms, ms_e)
     if args.seed in ("mlp", "both"):
-        st, ms, out_mlp = measure(L, torch, wl, prec, args, theta)
-        forms["mlp"] = (st, ms)
+        st, ms, ms_e, out_mlp = measure(L, torch, wl, prec, args, theta)
+        forms["mlp"] = (st, ms, ms_e)
         if "plain" in forms:
             # equal accuracy: the same converged closest points
             fp, tp = out_plain
@@ -304,7 +325,7 @@ def main():
             mlp_report["max_rel_diff_vs_plain"] = float(max(
                 (fm - fp).abs().max() / fp.abs().max(), (tm - tp).abs().max() / tp.abs().max()))
     head = "mlp" if args.seed == "mlp" else "plain"
-    st, ms = forms[head]
+    st, ms, ms_e = forms[head]
     if args.calibrate_copy:
         # a plain copy of known size (512 MiB read, 512 MiB written) as the
         # reference reading of the traffic counters; a device-to-device copy
@@ -315,7 +336,7 @@ def main():
             y.copy_(x)
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
-    sm = summary(st, ms, args)
+    sm = summary(st, ms, args, ms_e)
     active = st["active"]
     res = dict(
         metric="lubrication-corrected pairs/sec on 1 GPU at rel err <=1e-5 vs FP64 oracle",
@@ -328,18 +349,18 @@ def main():
                     precision=args.precision, newton_seed=head,
                     cutoffs=[wl.params["delta_n"], wl.params["delta_t"], wl.params["delta_r"]],
                     h_c=wl.params["h_c"], eps_c=wl.params["eps_c"], mu=wl.params["mu"],
-                    parallelism="single GPU"),
+                    launch="HIP graph replay", parallelism="single GPU"),
         pairs=dict(candidates=st["candidates"], wall_candidates=st["wall_candidates"],
                    evaluated=st["evaluated"], active=active, overlaps=st["overlaps"],
                    newton_iters_mean=sm["newton_iters_mean"], newton_max=st["newton_max"]),
+        ms_per_step_eager=ms_e,
         stage_ms=sm["stage_ms"],
         roofline=dict(bound="alu", kernel="k_pairs", achieved=sm["achieved_tflops"],
                       peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
                       frac=sm["achieved_tflops"] / PEAK_ALU_TFLOPS,
                       flops_per_launch=sm["flops_per_launch"], launch_ms=sm["pair_kernel_ms"],
                       traffic=pair_kernel_traffic(args.precision)),
-        seed_forms={k: {kk: vv for kk, vv in summary(v_[0], v_[1], args).items()
-                        if kk != "stage_ms"} for k, v_ in forms.items()},
+        seed_forms={k: summary(v_[0], v_[1], args, v_[2]) for k, v_ in forms.items()},
     )
     if mlp_report:
         res["mlp_seed"] = mlp_report

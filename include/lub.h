@@ -106,6 +106,14 @@ typedef struct {
                            /* it takes part in), rounded up to a multiple of 64, at */
                            /* most 512; <= 0: start at 64 and, with sync = 1, grow */
                            /* on demand.  More candidates than that: LUB_ECAPACITY */
+  int32_t graph;           /* 1: replay the call's launch sequence as a HIP graph, */
+                           /* captured on first use for the given n, array pointers */
+                           /* and stream (two graphs, for alternate calls) and */
+                           /* captured again when any of them or the workspace */
+                           /* changes.  Needs a stream other than the null stream */
+                           /* and timing = 0 (else LUB_EINVAL).  The arrays are read */
+                           /* at replay time, so callers may update them in place */
+  int32_t reserved;        /* must be 0 */
 } lub_opts_t;
 
 /* Per-call statistics of the last lub_compute. */

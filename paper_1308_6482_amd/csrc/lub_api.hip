@@ -75,6 +75,18 @@ struct lub_ctx {
   float* seedY = nullptr;
   int adam_step = 0;
 
+  // graph mode: the launch sequence of a call, captured once per counter set
+  // (alternate calls use alternate sets) and replayed while the call's
+  // arguments and the workspace stay the same
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    int64_t n = -1;
+    const void* args[8] = {};
+    CallDesc d{};
+    std::vector<const void*> ws;
+  };
+  GraphSlot graphs[2];
+
   // stage timing: five events per timed call, resolved lazily
   std::vector<hipEvent_t> free_events;
   std::vector<std::vector<hipEvent_t>> pending;
@@ -258,12 +270,22 @@ int resolve_timing(lub_ctx* c) {
   return LUB_OK;
 }
 
+int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
+             const double* semi, const double* v, const double* w, double* f,
+             double* t, hipStream_t s);
+
 int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
         const double* semi, const double* v, const double* w, double* f,
         double* t, hipStream_t s) {
   CallDesc d = d0;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
+  return run_desc(c, d, r, q, semi, v, w, f, t, s);
+}
+
+int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
+             const double* semi, const double* v, const double* w, double* f,
+             double* t, hipStream_t s) {
   int ncell = d.nc[0] * d.nc[1] * d.nc[2];
   std::vector<hipEvent_t> ev;
   const bool timing = c->opt.timing && d.n > 0;
@@ -340,6 +362,78 @@ int fetch_counters(lub_ctx* c) {
   return LUB_OK;
 }
 
+// the device buffers a call's launch sequence uses
+std::vector<const void*> workspace_signature(const lub_ctx* c) {
+  return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
+          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->kin, c->nbr,
+          c->slot, c->work_s, c->work_t, c->out, c->out_h, c->out_status, c->out_iters,
+          c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th};
+}
+
+void drop_graphs(lub_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) {
+      hipStreamSynchronize((hipStream_t)g.args[7]);  // no replay in flight
+      hipGraphExecDestroy(g.exec);
+    }
+    g = lub_ctx::GraphSlot();
+  }
+}
+
+// One call as a graph replay.  The first call (and any call after a failure)
+// runs eagerly: it may need the reset launch, which a replay does not hold.
+int run_graph(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
+              const double* semi, const double* v, const double* w, double* f,
+              double* t, hipStream_t s) {
+  if (!c->zeroed || d0.n == 0) return run(c, d0, r, q, semi, v, w, f, t, s);
+  CallDesc d = d0;
+  d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
+  d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
+  const int par = c->cnt_idx ^ 1;  // the counter set this call uses
+  lub_ctx::GraphSlot& g = c->graphs[par];
+  const void* args[8] = {r, q, semi, v, w, f, t, s};
+  const std::vector<const void*> ws = workspace_signature(c);
+  const bool same = g.exec && g.n == d.n && std::memcmp(g.args, args, sizeof(args)) == 0 &&
+                    std::memcmp(&g.d, &d, sizeof(d)) == 0 && g.ws == ws;
+  if (!same) {
+    if (g.exec) {
+      HIP_TRY(hipStreamSynchronize((hipStream_t)g.args[7]));  // no replay in flight
+      HIP_TRY(hipGraphExecDestroy(g.exec));
+    }
+    g = lub_ctx::GraphSlot();
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int rc = run_desc(c, d, r, q, semi, v, w, f, t, s);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    // the capture only recorded the launches: restore the state a replay sets
+    c->zeroed = true;
+    if (rc || e != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      c->zeroed = false;
+      return rc ? rc : hip_err(e);
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g = lub_ctx::GraphSlot();
+      c->zeroed = false;
+      return hip_err(ei);
+    }
+    g.n = d.n;
+    std::memcpy(g.args, args, sizeof(args));
+    g.d = d;
+    g.ws = ws;
+  }
+  c->cnt_idx = par;
+  c->cnt = c->cnt_buf + par;
+  HIP_TRY(hipGraphLaunch(g.exec, s));
+  c->zeroed = true;
+  c->last = d;
+  c->have_last = true;
+  c->last_stream = s;
+  return LUB_OK;
+}
+
 int mlp_upload(lub_ctx* c, const std::vector<float>& th) {
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipMemcpy(c->th, th.data(), sizeof(float) * kNParams, hipMemcpyHostToDevice));
@@ -412,6 +506,9 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   if (opts->precision != LUB_FP64 && opts->precision != LUB_MIXED) return LUB_EINVAL;
   if (opts->seed_mode != LUB_SEED_PLAIN && opts->seed_mode != LUB_SEED_MLP)
     return LUB_EINVAL;
+  if ((opts->graph != 0 && opts->graph != 1) || (opts->graph && opts->timing) ||
+      opts->reserved != 0)
+    return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
   c->device = opts->device;
@@ -483,6 +580,7 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  if (h->opt.graph && s == nullptr) return LUB_EINVAL;  // no capture on the null stream
   CallDesc d;
   int rc = build_desc(h, n, &d);
   if (rc) return rc;
@@ -496,7 +594,9 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
     if ((rc = ensure_seed(h))) return rc;
   }
-  if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
+  if ((rc = h->opt.graph ? run_graph(h, d, r, q, semi, v, w, f, t, s)
+                         : run(h, d, r, q, semi, v, w, f, t, s)))
+    return rc;
   if (!h->opt.sync) return LUB_OK;
   if ((rc = fetch_counters(h))) return rc;
   // automatic limit: widen the segments and evaluate again
@@ -736,6 +836,7 @@ int lub_mlp_train(lub_handle_t h, int64_t m, const float* X, const float* T,
 void lub_destroy(lub_handle_t h) {
   if (!h) return;
   hipSetDevice(h->device);
+  drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,

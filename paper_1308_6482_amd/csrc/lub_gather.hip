@@ -17,7 +17,10 @@ namespace lub {
 
 namespace {
 
-constexpr int kWaves = 4;
+#ifndef LUB_GATHER_WAVES
+#define LUB_GATHER_WAVES 4
+#endif
+constexpr int kWaves = LUB_GATHER_WAVES;
 
 __device__ __forceinline__ int find_entry(const int32_t* __restrict__ seg, int n,
                                           int key) {

@@ -398,7 +398,10 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
 // for the entries this particle owns (smaller input index), slot
 // assignment (one atomic per block) and the wall candidates.  Segments
 // have a fixed stride of d.max_nbr entries.
-constexpr int kWavesPerBlock = 4;
+#ifndef LUB_NBR_WAVES
+#define LUB_NBR_WAVES 8
+#endif
+constexpr int kWavesPerBlock = LUB_NBR_WAVES;
 
 __device__ __forceinline__ int wave_prefix(unsigned long long mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));

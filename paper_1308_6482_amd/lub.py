@@ -42,7 +42,8 @@ class lub_opts_t(C.Structure):
     _fields_ = [("device", C.c_int32), ("precision", C.c_int32),
                 ("seed_mode", C.c_int32), ("newton_max_iter", C.c_int32),
                 ("rmax_bound", C.c_double), ("sync", C.c_int32),
-                ("timing", C.c_int32), ("max_neighbors", C.c_int64)]
+                ("timing", C.c_int32), ("max_neighbors", C.c_int64),
+                ("graph", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lub_stats_t(C.Structure):
@@ -140,9 +141,10 @@ def make_domain(L, periodic=(1, 1, 1), n_walls=0,
 
 
 def make_opts(rmax_bound, precision=LUB_FP64, device=0, seed_mode=LUB_SEED_PLAIN,
-              newton_max_iter=0, sync=1, max_neighbors=0, timing=0) -> lub_opts_t:
+              newton_max_iter=0, sync=1, max_neighbors=0, timing=0,
+              graph=0) -> lub_opts_t:
     return lub_opts_t(device, precision, seed_mode, newton_max_iter,
-                      float(rmax_bound), sync, timing, max_neighbors)
+                      float(rmax_bound), sync, timing, max_neighbors, graph, 0)
 
 
 # --- the C entry points, same names ------------------------------------------
@@ -181,6 +183,8 @@ def lub_compute(h, r, q, semi, v, w, f, t, stream=None, check=True) -> int:
             raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},{cols})")
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
     ptrs = [_ptr(x) if n > 0 else 0 for x in (r, q, semi, v, w, f, t)]
     rc = lib().lub_compute(h, n, *ptrs, stream)
     if check:
@@ -311,12 +315,13 @@ class Lub:
     def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
                  sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
-                 seed_mode=LUB_SEED_PLAIN):
+                 seed_mode=LUB_SEED_PLAIN, graph=0):
         self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel),
                             make_params(**params),
                             make_opts(rmax_bound, precision, device, seed_mode=seed_mode,
                                       newton_max_iter=newton_max_iter, sync=sync,
-                                      max_neighbors=max_neighbors, timing=timing))
+                                      max_neighbors=max_neighbors, timing=timing,
+                                      graph=graph))
 
     def compute(self, r, q, semi, v, w, f=None, t=None, stream=None, check=True):
         import torch
