@@ -71,6 +71,22 @@ extern "C" {
 #define LUB_SEED_MLP 1    /* Newton started from the learned predictor */
 
 /* Physical parameters (Sec. III.B-C). */
+/* Resistance law (the models the paper compares in Sec. IV):
+ *   LUB_MODEL_FULL    the contact-based correction of Sec. III, all sixteen
+ *                     singular elements of K (Appendix);
+ *   LUB_MODEL_NORMAL  the same with every non-normal element dropped (K33
+ *                     alone, "normal only" in the paper's tables);
+ *   LUB_MODEL_LADD    Ladd's normal law for spheres, Eq. methods:llub, with
+ *                     coefficient 6 pi mu (a b / (a + b))^2 (6 pi mu a^2 at a
+ *                     wall): force along the line of centres, no torque.
+ *                     Every particle must be a sphere (R_par == R_perp),
+ *                     else LUB_EINVAL.
+ * The reduced models act below delta_n only; all three clip the gap at h_c
+ * and add the contact force of Eq. lub:frep. */
+#define LUB_MODEL_FULL 0
+#define LUB_MODEL_NORMAL 1
+#define LUB_MODEL_LADD 2
+
 typedef struct {
   double mu;       /* dynamic viscosity */
   double delta_n;  /* cut-off of K33 (normal) */
@@ -78,6 +94,8 @@ typedef struct {
   double delta_r;  /* cut-off of K44, K45, K54, K55 (rotation) */
   double h_c;      /* clipping gap (Eq. lub:model); 0 disables clipping */
   double eps_c;    /* Hookean contact stiffness (Eq. lub:frep) */
+  int32_t model;   /* LUB_MODEL_* */
+  int32_t reserved;/* must be 0 */
 } lub_params_t;
 
 /* Simulation box. */

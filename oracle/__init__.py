@@ -34,10 +34,14 @@ def build(force: bool = True) -> str:
     return _SO
 
 
+MODEL_FULL, MODEL_NORMAL, MODEL_LADD = 0, 1, 2
+
+
 class Params(C.Structure):
     _fields_ = [("mu", C.c_double), ("delta_n", C.c_double),
                 ("delta_t", C.c_double), ("delta_r", C.c_double),
-                ("h_c", C.c_double), ("eps_c", C.c_double)]
+                ("h_c", C.c_double), ("eps_c", C.c_double),
+                ("model", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Domain(C.Structure):
@@ -137,8 +141,8 @@ def _p(a, t=_D):
 
 
 def make_params(mu=1.0 / 6.0, delta_n=2.0 / 3.0, delta_t=0.5, delta_r=0.25,
-                h_c=0.0, eps_c=0.0) -> Params:
-    return Params(mu, delta_n, delta_t, delta_r, h_c, eps_c)
+                h_c=0.0, eps_c=0.0, model=MODEL_FULL) -> Params:
+    return Params(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0)
 
 
 def make_domain(L=(1e9, 1e9, 1e9), periodic=(0, 0, 0), n_walls=0,

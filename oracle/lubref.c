@@ -552,6 +552,7 @@ static double cutoff(int r, int c, const ref_params* p) {
 }
 
 static double max_cutoff(const ref_params* p) {
+  if (p->model != REF_MODEL_FULL) return p->delta_n;  /* only the normal element */
   double m = p->delta_n;
   if (p->delta_t > m) m = p->delta_t;
   if (p->delta_r > m) m = p->delta_r;
@@ -642,11 +643,13 @@ static void resistance_and_transfer(const body* bi, const body* bj,
   o->schi = aux[3];
   for (int i = 0; i < 4; ++i) o->kappa[i] = aux[4 + i];
 
-  /* corrective matrix, Eq. lub:resistance-correction, gap clipped at h_c */
+  /* corrective matrix, Eq. lub:resistance-correction, gap clipped at h_c;
+   * the "normal only" model keeps K33 alone */
   for (int r = 0; r < 6; ++r)
     for (int c = 0; c < 6; ++c) {
       double D = cutoff(r, c, prm);
       if (!(heff < D)) continue;
+      if (prm->model == REF_MODEL_NORMAL && !(r == 2 && c == 2)) continue;
       if (r == 2 && c == 2)
         o->Kt[r][c] = o->C[r][c] * (1.0 / heff - 1.0 / D);
       else
@@ -710,11 +713,57 @@ int ref_closest_points(const double d[3], const double qi[4],
   return 0;
 }
 
+/* Ladd's normal law, Eq. methods:llub, for spheres of radii a and b (b = 0:
+ * a wall): force on i along the unit n from i to j,
+ *   mu 6 pi (a b / (a + b))^2 [n.(v_j - v_i)] (1/h - 1/Delta_n) n,
+ * which is 3 pi mu R^2 / 2 for equal spheres and 6 pi mu a^2 against a
+ * wall; the gap is clipped at h_c and the contact force of Eq. lub:frep
+ * added, as in the contact-based model.  No torque: the force passes
+ * through both centres. */
+static void ladd_eval(const double n[3], double h, double a, double b,
+                      const double vi[3], const double vj[3],
+                      const ref_params* prm, ref_pair_result* o) {
+  o->h = h;
+  memcpy(o->n, n, 3 * sizeof(double));
+  for (int k = 0; k < 3; ++k) {
+    o->yi[k] = a * n[k];
+    o->yj[k] = -b * n[k];
+  }
+  double heff = h > prm->h_c ? h : prm->h_c;
+  if (heff >= prm->delta_n) {
+    o->status = REFP_INACTIVE;
+    return;
+  }
+  if (!(heff > 0.0)) {
+    o->status = REFP_UNRESOLVED;
+    return;
+  }
+  o->status = REFP_ACTIVE;
+  double g = b > 0.0 ? a * b / (a + b) : a;
+  o->C[2][2] = 6.0 * PI * g * g;
+  o->Kt[2][2] = o->C[2][2] * (1.0 / heff - 1.0 / prm->delta_n);
+  double dv[3] = {vj[0] - vi[0], vj[1] - vi[1], vj[2] - vi[2]};
+  double fn = prm->mu * o->Kt[2][2] * dot3(n, dv);
+  if (h <= prm->h_c) fn -= h > 0.0 ? prm->eps_c * (prm->h_c - h) : prm->eps_c * prm->h_c;
+  o->Fbar[2] = fn;
+  for (int k = 0; k < 3; ++k) o->F[k] = fn * n[k];
+}
+
 int ref_pair_eval(const double d[3], const double qi[4], const double semii[2],
                   const double vi[3], const double wi[3], const double qj[4],
                   const double semij[2], const double vj[3], const double wj[3],
                   const ref_params* prm, ref_pair_result* out) {
   memset(out, 0, sizeof(*out));
+  if (prm->model == REF_MODEL_LADD) {
+    if (semii[0] != semii[1] || semij[0] != semij[1]) {
+      out->status = REFP_FAILED;  /* Ladd's law is for spheres */
+      return 0;
+    }
+    double dn = norm3(d);
+    double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+    ladd_eval(n, dn - semii[0] - semij[0], semii[0], semij[0], vi, vj, prm, out);
+    return 0;
+  }
   double zero[3] = {0, 0, 0};
   body bi, bj;
   body_init(&bi, zero, qi, semii);
@@ -735,10 +784,19 @@ int ref_wall_eval(const double ri[3], const double qi[4], const double semii[2],
                   const ref_domain* dom, const ref_params* prm,
                   ref_pair_result* out) {
   memset(out, 0, sizeof(*out));
+  double n[3] = {0.0, 0.0, side == 0 ? -1.0 : 1.0};
+  if (prm->model == REF_MODEL_LADD) {
+    if (semii[0] != semii[1]) {
+      out->status = REFP_FAILED;
+      return 0;
+    }
+    double dist = side == 0 ? ri[2] : dom->L[2] - ri[2];
+    ladd_eval(n, dist - semii[0], semii[0], 0.0, vi, dom->wall_vel[side], prm, out);
+    return 0;
+  }
   body bi;
   double zero[3] = {0, 0, 0};
   body_init(&bi, zero, qi, semii);
-  double n[3] = {0.0, 0.0, side == 0 ? -1.0 : 1.0};
   double off[3];
   double hs = support(&bi, n, off);
   out->h = side == 0 ? ri[2] - hs : dom->L[2] - ri[2] - hs;

@@ -55,6 +55,14 @@ extern "C" {
 #define REFP_UNRESOLVED 2  /* h <= 0 with h_c == 0: K~ undefined, skipped */
 #define REFP_FAILED 3      /* closest-point solve did not converge: skipped */
 
+/* Resistance laws the paper compares (Sec. IV, the viscosity and
+ * diffusion tables): the full contact-based model; the same with every
+ * non-normal element dropped ("normal only"); Ladd's normal law for
+ * spheres, Eq. methods:llub (force along the line of centres, no torque). */
+#define REF_MODEL_FULL 0
+#define REF_MODEL_NORMAL 1
+#define REF_MODEL_LADD 2
+
 typedef struct {
   double mu;       /* dynamic viscosity */
   double delta_n;  /* cut-off for K33 */
@@ -62,6 +70,8 @@ typedef struct {
   double delta_r;  /* cut-off for K44, K45, K54, K55 */
   double h_c;      /* clipping gap of Eq. lub:model */
   double eps_c;    /* Hookean stiffness of Eq. lub:frep */
+  int32_t model;   /* REF_MODEL_*; the reduced models are active below delta_n */
+  int32_t reserved;
 } ref_params;
 
 typedef struct {

@@ -38,6 +38,7 @@ struct lub_ctx {
   int32_t* block_sums = nullptr;   // scan scratch
   int32_t* wall_slot = nullptr;    // [2n]
   PRec* rec = nullptr;             // [n]
+  double4* pos = nullptr;          // [n] centre and largest semi-axis (centre test)
   KRec* kin = nullptr;             // [n]
   int32_t* nbr = nullptr;          // [n * cur_nbr] partner (cell order)
   int32_t* slot = nullptr;         // [n * cur_nbr] evaluation slot, -1, -2
@@ -133,7 +134,9 @@ int grow(T** p, int64_t* cap, int64_t need) {
   return LUB_OK;
 }
 
+// candidate and activity cut-off: the reduced models act below delta_n only
 double max_cutoff(const lub_params_t& p) {
+  if (p.model != LUB_MODEL_FULL) return p.delta_n;
   return std::max(p.delta_n, std::max(p.delta_t, p.delta_r));
 }
 
@@ -141,6 +144,8 @@ int check_params(const lub_params_t* p) {
   if (!p) return LUB_EINVAL;
   if (!(p->mu >= 0.0) || !(p->delta_n > 0.0) || !(p->delta_t > 0.0) ||
       !(p->delta_r > 0.0) || !(p->h_c >= 0.0) || !(p->eps_c >= 0.0))
+    return LUB_EINVAL;
+  if (p->model < LUB_MODEL_FULL || p->model > LUB_MODEL_LADD || p->reserved != 0)
     return LUB_EINVAL;
   return LUB_OK;
 }
@@ -163,6 +168,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
   if ((rc = realloc_buf(&c->cell_id, need)) || (rc = realloc_buf(&c->sorted, need)) ||
       (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
       (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->kin, need)) ||
+      (rc = realloc_buf(&c->pos, need)) ||
       (rc = realloc_buf(&c->scat, need)) ||
       (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks((int)need))) ||
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
@@ -213,20 +219,31 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->n = (int32_t)n;
   d->dmax = max_cutoff(c->prm);
   double edge = 2.0 * c->opt.rmax_bound + d->dmax;
-  int64_t ncell = 1;
   for (int k = 0; k < 3; ++k) {
     d->L[k] = c->dom.L[k];
     d->invL[k] = 1.0 / c->dom.L[k];
     d->periodic[k] = c->dom.periodic[k];
     // minimum image must be unambiguous for the largest pair bound
     if (d->periodic[k] && d->L[k] < 2.0 * edge) return LUB_EDOMAIN;
-    int64_t nc = (int64_t)std::floor(d->L[k] / edge);
-    nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
-    d->nc[k] = (int32_t)nc;
-    d->cell[k] = d->L[k] / (double)nc;
-    ncell *= nc;
   }
-  (void)ncell;
+  // Cells of 1/sub of the largest pair bound, sub = 3, 2 or 1: the finest
+  // grid with no more cells than particles (finer cells test fewer
+  // candidates, but every cell costs scan and zeroing work).  A particle
+  // searches up to `sub` cells on each side, fewer if it is small.  The
+  // relative margin, far above rounding, keeps binning by floor(x / cell)
+  // from putting a candidate more than `sub` cells away.
+  for (int sub = 3; sub >= 1; --sub) {
+    int64_t ncell = 1;
+    for (int k = 0; k < 3; ++k) {
+      int64_t nc = (int64_t)std::floor(d->L[k] / (edge / sub * (1.0 + 1e-9)));
+      nc = std::max<int64_t>(1, std::min<int64_t>(nc, 1024));
+      d->nc[k] = (int32_t)nc;
+      d->cell[k] = d->L[k] / (double)nc;
+      ncell *= nc;
+    }
+    d->reach_max = sub;
+    if (ncell <= std::max<int64_t>(n, 1)) break;
+  }
   d->n_walls = c->dom.n_walls;
   for (int s = 0; s < 2; ++s)
     for (int k = 0; k < 3; ++k) d->wall_vel[s][k] = c->dom.wall_vel[s][k];
@@ -240,6 +257,7 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->max_iter = c->opt.newton_max_iter > 0 ? c->opt.newton_max_iter : 50;
   d->max_nbr = c->cur_nbr;
   d->precision = c->opt.precision;
+  d->model = c->prm.model;
   return LUB_OK;
 }
 
@@ -314,18 +332,19 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   c->zeroed = false;
   if (d.n > 0) {
     if (small) {
-      launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->kin,
-                         c->cell_sorted, c->cnt, s);
+      launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->pos,
+                         c->kin, c->cell_sorted, c->cnt, s);
     } else {
       launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
                           c->cell_count, ncell, s);
       launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
-                           q, semi, v, w, c->sorted, c->rec, c->kin, c->cell_sorted, s);
+                           q, semi, v, w, c->sorted, c->rec, c->pos, c->kin, c->cell_sorted,
+                           s);
     }
     mark(1);
-    launch_neighbors_wave(d, c->rec, c->sorted, c->cell_sorted, c->cell_start,
+    launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                           c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                           c->work_t, c->stat_nbr, c->cnt, s);
     mark(2);
@@ -365,7 +384,8 @@ int fetch_counters(lub_ctx* c) {
 // the device buffers a call's launch sequence uses
 std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
-          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->kin, c->nbr,
+          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->pos, c->kin,
+          c->nbr,
           c->slot, c->work_s, c->work_t, c->out, c->out_h, c->out_status, c->out_iters,
           c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th};
 }
@@ -841,7 +861,7 @@ void lub_destroy(lub_handle_t h) {
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
-                  h->cnt_buf, h->scat, h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
+                  h->cnt_buf, h->scat, h->pos, h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY};
   for (void* p : bufs)
     if (p) hipFree(p);

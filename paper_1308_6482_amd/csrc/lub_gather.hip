@@ -3,11 +3,11 @@
 // r_i) x F from every pair, particle j the opposite force and -T + ... about
 // its own centre.
 //
-// No atomics: one wavefront per particle, lanes over the entries of its
+// No atomics: a group of 16 lanes per particle, lanes over the entries of its
 // neighbour segment (both directions of each of its pairs).  A pair's result
 // sits in the slot of the entry owned by its smaller-index particle; the
 // other particle finds that entry by binary search in its partner's sorted
-// segment.  The wave then reduces the six components with a fixed butterfly
+// segment.  The group then reduces the six components with a fixed butterfly
 // in FP64, so the sums are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
@@ -37,6 +37,11 @@ __device__ __forceinline__ int find_entry(const int32_t* __restrict__ seg, int n
   return -1;
 }
 
+// lanes per particle: the segments hold about ten entries in dense
+// suspensions, so a wavefront serves four particles
+constexpr int kGroup = 16;
+constexpr int kPerWave = 64 / kGroup;
+
 template <typename R>
 __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
@@ -45,17 +50,18 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
     const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
     double* __restrict__ t) {
   const int lane = threadIdx.x & 63;
-  const int s = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int g = lane % kGroup;  // lane within the particle's group
+  const int s = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kPerWave + lane / kGroup;
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < (int)(sizeof(Counters) / sizeof(int32_t));
          i += blockDim.x)
       reinterpret_cast<int32_t*>(next_cnt)[i] = 0;
-  if (s >= d.n) return;  // whole wavefront
+  const bool live = s < d.n;
   const size_t stride = (size_t)d.max_nbr;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (cnt->error == 0) {
+  if (live && cnt->error == 0) {
     const int ns = deg[s];
-    for (int k = lane; k < ns; k += 64) {
+    for (int k = g; k < ns; k += kGroup) {
       const size_t e = (size_t)s * stride + k;
       const int sl = slot[e];
       if (sl >= 0) {
@@ -77,8 +83,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
         }
       }
     }
-    if (d.n_walls && lane >= 62) {
-      const int ws = wall_slot[2 * s + (lane - 62)];
+    if (d.n_walls && g >= kGroup - 2) {
+      const int ws = wall_slot[2 * s + (g - (kGroup - 2))];
       if (ws >= 0) {
         const PairOut<R>& o = out[ws];
         for (int c = 0; c < 3; ++c) {
@@ -88,10 +94,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
       }
     }
   }
+  // fixed butterfly within each group of kGroup lanes
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1)
+  for (int o = kGroup / 2; o >= 1; o >>= 1)
     for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], o, 64);
-  if (lane == 0) {
+  if (live && g == 0) {
     const int p = orig[s];
     for (int c = 0; c < 3; ++c) {
       f[3 * p + c] = acc[c];
@@ -108,7 +115,8 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
                    hipStream_t s) {
   if (d.n == 0) return;
-  dim3 grid((d.n + kWaves - 1) / kWaves);
+  const int per_block = kWaves * kPerWave;
+  dim3 grid((d.n + per_block - 1) / per_block);
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_gather<float>, grid, dim3(64 * kWaves), 0, s, d, orig,
                        deg, nbr, slot, wall_slot, (const PairOut<float>*)out,

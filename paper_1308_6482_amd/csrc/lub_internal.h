@@ -62,6 +62,9 @@ struct CallDesc {
   double cell[3];        // cell edge per axis
   double L[3];
   double invL[3];       // 1 / L
+  int32_t reach_max;    // cells searched on each side at most (cells are at
+                        // least 1/reach_max of the largest pair bound)
+  int32_t model;        // LUB_MODEL_*
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
@@ -111,15 +114,15 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_id, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, KRec* kin,
-                          int32_t* cell_sorted, hipStream_t s);
+                          const double* w, int32_t* sorted, PRec* rec, double4* pos,
+                          KRec* kin, int32_t* cell_sorted, hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_start, int32_t* sorted, PRec* rec, KRec* kin,
-                        int32_t* cell_sorted, Counters* cnt, hipStream_t s);
-void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
+                        KRec* kin, int32_t* cell_sorted, Counters* cnt, hipStream_t s);
+void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,

@@ -24,8 +24,9 @@ namespace lub {
 namespace {
 
 constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanItems = 8;                             // per thread and chunk
+constexpr int kScanChunk = kScanThreads * kScanItems;     // staged through LDS
+constexpr int kScanTile = 8 * kScanChunk;                 // one block: 65536 cells
 
 __device__ __forceinline__ int cell_coord(double x, double L, int periodic,
                                           double edge, int nc) {
@@ -109,6 +110,7 @@ __device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
             isfinite(a) && isfinite(b);
   double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   ok = ok && fabs(qn - 1.0) <= 1e-6 && fmax(a, b) <= d.rmax_bound;
+  ok = ok && (d.model != LUB_MODEL_LADD || a == b);  // Ladd's law is for spheres
   if (!ok) set_error(cnt, LUB_EINVAL);
   double rm = fmax(a, b);
   if (d.n_walls && (z < -rm || z > d.L[2] + rm)) set_error(cnt, LUB_EDOMAIN);
@@ -131,29 +133,50 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
   atomicAdd(&cell_count[c], 1);
 }
 
-// exclusive scan, tile level; single-tile case writes the total directly
-__global__ void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                            int n, int32_t* __restrict__ block_sums,
-                            int64_t* total) {
+// Exclusive scan of in[0, n) into out[0, n) (the two may be the same
+// array) by one block of kScanThreads, chunk by chunk: coalesced loads into
+// LDS, kScanItems consecutive elements per thread, block scan, coalesced
+// stores.  Returns the total to every thread.
+__device__ int block_scan_range(const int32_t* in, int32_t* out, int n, int* chunk,
+                                int* lds_scan) {
+  int carry = 0;
+  for (int c0 = 0; c0 < n; c0 += kScanChunk) {
+    const int m = min(kScanChunk, n - c0);
+    for (int k = threadIdx.x; k < kScanChunk; k += kScanThreads)
+      chunk[k] = k < m ? in[c0 + k] : 0;
+    __syncthreads();
+    int v[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] = chunk[threadIdx.x * kScanItems + k];
+      sum += v[k];
+    }
+    int tot;
+    const int incl = block_inclusive_scan(sum, lds_scan, &tot);
+    int run = carry + incl - sum;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      chunk[threadIdx.x * kScanItems + k] = run;
+      run += v[k];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < m; k += kScanThreads) out[c0 + k] = chunk[k];
+    carry += tot;
+    __syncthreads();  // the next chunk reuses the LDS
+  }
+  return carry;
+}
+
+// exclusive scan, tile level; the single-tile case writes the total directly
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out, int n,
+            int32_t* __restrict__ block_sums, int64_t* total) {
+  __shared__ int chunk[kScanChunk];
   __shared__ int lds[16];
-  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int idx = base + k;
-    v[k] = idx < n ? in[idx] : 0;
-    s += v[k];
-  }
-  int tot;
-  int incl = block_inclusive_scan(s, lds, &tot);
-  int run = incl - s;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    int idx = base + k;
-    if (idx < n) out[idx] = run;
-    run += v[k];
-  }
+  const int base = blockIdx.x * kScanTile;
+  const int m = min(kScanTile, n - base);
+  const int tot = block_scan_range(in + base, out + base, m, chunk, lds);
   if (threadIdx.x == 0) {
     block_sums[blockIdx.x] = tot;
     if (gridDim.x == 1) {
@@ -163,25 +186,12 @@ __global__ void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict_
   }
 }
 
-__global__ void k_scan_top(int32_t* block_sums, int nb, int32_t* out, int n,
-                           int64_t* total) {
+// exclusive scan of the tile totals, in place
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_top(int32_t* block_sums, int nb, int32_t* out, int n, int64_t* total) {
+  __shared__ int chunk[kScanChunk];
   __shared__ int lds[16];
-  const int base = threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < nb ? block_sums[base + k] : 0;
-    s += v[k];
-  }
-  int tot;
-  int incl = block_inclusive_scan(s, lds, &tot);
-  int run = incl - s;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < nb) block_sums[base + k] = run;
-    run += v[k];
-  }
+  const int tot = block_scan_range(block_sums, block_sums, nb, chunk, lds);
   if (threadIdx.x == 0) {
     out[n] = tot;
     if (total) *total = tot;
@@ -218,8 +228,8 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
                             const double* __restrict__ r, const double* __restrict__ q,
                             const double* __restrict__ semi,
                             const double* __restrict__ v, const double* __restrict__ w,
-                            PRec* __restrict__ rec, KRec* __restrict__ kin,
-                            int32_t* __restrict__ cell_sorted) {
+                            PRec* __restrict__ rec, double4* __restrict__ pos,
+                            KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
   double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
   double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= inv;
@@ -249,6 +259,7 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
   o.Rmax = fmax(Rpa, Rpe);
   o.pad = 0.0;
   rec[s] = o;
+  pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
   KRec k;
   for (int c = 0; c < 3; ++c) {
     k.v[c] = v[3 * p + c];
@@ -272,8 +283,8 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 const double* __restrict__ semi,
                                 const double* __restrict__ v,
                                 const double* __restrict__ w, int32_t* __restrict__ sorted,
-                                PRec* __restrict__ rec, KRec* __restrict__ kin,
-                                int32_t* __restrict__ cell_sorted) {
+                                PRec* __restrict__ rec, double4* __restrict__ pos,
+                                KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
   if (i >= d.n) return;
@@ -284,31 +295,33 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
   for (int k = b; k < e; ++k) rank += unsorted[k] < p;
   const int s = b + rank;
   sorted[s] = p;
-  make_record(s, p, cell_id, r, q, semi, v, w, rec, kin, cell_sorted);
+  make_record(s, p, cell_id, r, q, semi, v, w, rec, pos, kin, cell_sorted);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
 // with fewer than three cells would otherwise visit a cell twice)
-__device__ __forceinline__ int axis_offsets(int c, int nc, int periodic,
-                                            int out[3]) {
-  int k = 0;
+// The cells along one axis within `reach` cells of cell c: first cell
+// (possibly negative or past the end on a periodic axis, to be wrapped) and
+// count.  A periodic axis shorter than the stencil is taken whole, once.
+__device__ __forceinline__ void axis_stencil(int c, int nc, int periodic, int reach,
+                                             int* first, int* count) {
   if (periodic) {
-    if (nc >= 3) {
-      out[k++] = (c + nc - 1) % nc;
-      out[k++] = c;
-      out[k++] = (c + 1) % nc;
-    } else if (nc == 2) {
-      out[k++] = 0;
-      out[k++] = 1;
+    if (2 * reach + 1 >= nc) {
+      *first = 0;
+      *count = nc;
     } else {
-      out[k++] = 0;
+      *first = c - reach;
+      *count = 2 * reach + 1;
     }
   } else {
-    if (c > 0) out[k++] = c - 1;
-    out[k++] = c;
-    if (c + 1 < nc) out[k++] = c + 1;
+    const int lo = max(0, c - reach), hi = min(nc - 1, c + reach);
+    *first = lo;
+    *count = hi - lo + 1;
   }
-  return k;
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int nc) {
+  return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
 __device__ __forceinline__ double support(const double* M, double nx, double ny,
@@ -332,7 +345,8 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
               const double* __restrict__ semi, const double* __restrict__ v,
               const double* __restrict__ w, int32_t* __restrict__ cell_start,
               int32_t* __restrict__ sorted, PRec* __restrict__ rec,
-              KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted, Counters* cnt) {
+              double4* __restrict__ pos, KRec* __restrict__ kin,
+              int32_t* __restrict__ cell_sorted, Counters* cnt) {
   __shared__ int32_t cnt_l[kSmallMaxCells];        // counts, then cursors
   __shared__ int32_t start_l[kSmallMaxCells + 1];
   __shared__ int32_t cid_l[kSmallMaxN];            // cell of each input index
@@ -388,7 +402,7 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
     for (int k = b; k < e; ++k) rank += scat_l[k] < p;
     const int s = b + rank;
     sorted[s] = p;
-    make_record(s, p, cid_l, r, q, semi, v, w, rec, kin, cell_sorted);
+    make_record(s, p, cid_l, r, q, semi, v, w, rec, pos, kin, cell_sorted);
   }
 }
 
@@ -402,13 +416,14 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
 #define LUB_NBR_WAVES 8
 #endif
 constexpr int kWavesPerBlock = LUB_NBR_WAVES;
+// at most 3 cells on each side (reach_max <= 3): 7 x 7 rows <= 64 lanes
 
 __device__ __forceinline__ int wave_prefix(unsigned long long mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
-k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
+k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
                  const int32_t* __restrict__ orig,
                  const int32_t* __restrict__ cell_sorted,
                  const int32_t* __restrict__ cell_start,
@@ -436,42 +451,65 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
   int my_keep[kMaxPerLane];
   int wall_keep[2] = {0, 0};
   if (live) {
-    const double ri[3] = {rec[s].r[0], rec[s].r[1], rec[s].r[2]};
-    const double rmi = rec[s].Rmax;
+    const double4 pi = pos[s];
+    const double ri[3] = {pi.x, pi.y, pi.z};
+    const double rmi = pi.w;
     const int c = cell_sorted[s];
     const int cx = c % d.nc[0];
     const int cy = (c / d.nc[0]) % d.nc[1];
     const int cz = c / (d.nc[0] * d.nc[1]);
-    int ox[3], oy[3], oz[3];
-    const int nx = axis_offsets(cx, d.nc[0], d.periodic[0], ox);
-    const int ny = axis_offsets(cy, d.nc[1], d.periodic[1], oy);
-    const int nz = axis_offsets(cz, d.nc[2], d.periodic[2], oz);
-    const int ncells = nx * ny * nz;
-    // lane k < ncells owns neighbour cell k: its member range and prefix
-    int cs = 0, cn = 0;
-    if (lane < ncells) {
-      int a = lane / (nx * ny), rem = lane % (nx * ny);
-      int b = rem / nx, e = rem % nx;
-      int cc = (oz[a] * d.nc[1] + oy[b]) * d.nc[0] + ox[e];
-      cs = cell_start[cc];
-      cn = cell_start[cc + 1] - cs;
+    // every partner lies within rho of this centre along each axis: at most
+    // `reach` cells away (cells are at least 1/reach_max of the largest rho)
+    const double rho = rmi + d.rmax_bound + d.dmax;
+    int reach[3], first[3], cnt3[3];
+    for (int k = 0; k < 3; ++k) reach[k] = min(d.reach_max, max(1, (int)ceil(rho / d.cell[k])));
+    axis_stencil(cx, d.nc[0], d.periodic[0], reach[0], &first[0], &cnt3[0]);
+    axis_stencil(cy, d.nc[1], d.periodic[1], reach[1], &first[1], &cnt3[1]);
+    axis_stencil(cz, d.nc[2], d.periodic[2], reach[2], &first[2], &cnt3[2]);
+    const int nrows = cnt3[1] * cnt3[2];
+    // lane u < nrows owns the row of cells (y, z) of the stencil: its cells
+    // along x are one contiguous range of cell-ordered particles, or two
+    // when the range wraps around a periodic axis
+    int s0 = 0, n0 = 0, s1 = 0, n1 = 0;
+    if (lane < nrows) {
+      const int ry = wrap_cell(first[1] + lane % cnt3[1], d.nc[1]);
+      const int rz = wrap_cell(first[2] + lane / cnt3[1], d.nc[2]);
+      const int rowbase = (rz * d.nc[1] + ry) * d.nc[0];
+      int a0 = first[0], a1 = first[0] + cnt3[0] - 1;  // cells a0..a1 along x
+      int b0 = 0, b1 = -1;                             // wrapped part
+      if (a0 < 0) {
+        b0 = a0 + d.nc[0];
+        b1 = d.nc[0] - 1;
+        a0 = 0;
+      } else if (a1 >= d.nc[0]) {
+        b0 = 0;
+        b1 = a1 - d.nc[0];
+        a1 = d.nc[0] - 1;
+      }
+      s0 = cell_start[rowbase + a0];
+      n0 = cell_start[rowbase + a1 + 1] - s0;
+      if (b1 >= b0) {
+        s1 = cell_start[rowbase + b0];
+        n1 = cell_start[rowbase + b1 + 1] - s1;
+      }
     }
+    const int cn = n0 + n1;
     int incl = cn;
 #pragma unroll
-    for (int o = 1; o < 32; o <<= 1) {
+    for (int o = 1; o < 64; o <<= 1) {
       int y = __shfl_up(incl, o, 64);
       if (lane >= o) incl += y;
     }
-    const int total = __shfl(incl, 31, 64);
+    const int total = __shfl(incl, 63, 64);
     const int excl = incl - cn;
     for (int base = 0; base < total; base += 64) {
       const int idx = base + lane;
       bool acc = false;
       int t = -1;
-      // the neighbour cell holding flattened index idx: binary search over the
-      // lanes' exclusive prefixes, every lane taking part in the shuffles
-      int lo = 0, hi = ncells - 1;
-      for (int step = 0; step < 5; ++step) {
+      // the row holding flattened index idx: binary search over the lanes'
+      // exclusive prefixes, every lane taking part in the shuffles
+      int lo = 0, hi = nrows - 1;
+      for (int step = 0; step < 6; ++step) {
         int mid = (lo + hi + 1) >> 1;
         int em = __shfl(excl, mid, 64);
         bool up = lo < hi && em <= idx;
@@ -479,16 +517,21 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec,
         lo = up ? mid : lo;
         hi = down ? mid - 1 : hi;
       }
-      const int start = __shfl(cs, lo, 64);
+      const int r0 = __shfl(s0, lo, 64);
+      const int rn0 = __shfl(n0, lo, 64);
+      const int r1 = __shfl(s1, lo, 64);
       const int ex = __shfl(excl, lo, 64);
       if (idx < total) {
-        t = start + (idx - ex);
-        acc = t != s && centre_test(ri, rec[t].r, rmi, rec[t].Rmax, d);
+        const int off = idx - ex;
+        t = off < rn0 ? r0 + off : r1 + (off - rn0);
+        const double4 pj = pos[t];
+        const double rj[3] = {pj.x, pj.y, pj.z};
+        acc = t != s && centre_test(ri, rj, rmi, pj.w, d);
       }
       unsigned long long m = __ballot(acc);
       if (acc) {
-        int pos = count + wave_prefix(m, lane);
-        if (pos < maxn) keys[pos] = t;
+        const int at = count + wave_prefix(m, lane);
+        if (at < maxn) keys[at] = t;
       }
       count += __popcll(m);
     }
@@ -656,12 +699,12 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_id, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, KRec* kin,
-                          int32_t* cell_sorted, hipStream_t s) {
+                          const double* w, int32_t* sorted, PRec* rec, double4* pos,
+                          KRec* kin, int32_t* cell_sorted, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
                      d, unsorted, cell_id, cell_start, cell_fill, ncell, r, q, semi,
-                     v, w, sorted, rec, kin, cell_sorted);
+                     v, w, sorted, rec, pos, kin, cell_sorted);
 }
 
 bool cells_small_fits(const CallDesc& d) {
@@ -671,13 +714,13 @@ bool cells_small_fits(const CallDesc& d) {
 
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_start, int32_t* sorted, PRec* rec, KRec* kin,
-                        int32_t* cell_sorted, Counters* cnt, hipStream_t s) {
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
+                        KRec* kin, int32_t* cell_sorted, Counters* cnt, hipStream_t s) {
   hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, d, r, q, semi,
-                     v, w, cell_start, sorted, rec, kin, cell_sorted, cnt);
+                     v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt);
 }
 
-void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
+void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
@@ -687,7 +730,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec,
   dim3 grid(nbr_blocks(d.n));
   size_t lds = sizeof(int32_t) * kWavesPerBlock * (size_t)d.max_nbr;
   hipLaunchKernelGGL(k_neighbors_wave, grid, dim3(64 * kWavesPerBlock), lds, s,
-                     d, rec, orig, cell_sorted, cell_start, deg, nbr, slot,
+                     d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
                      wall_slot, work_s, work_t, stat_nbr, cnt);
 }
 

@@ -405,6 +405,54 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
   C[15] = -R(3) * pi * isl * (cc * p1 + ss * p2);
 }
 
+// Ladd's normal law for spheres, Eq. methods:llub: the force on i along the
+// line of centres n (from i to j) is mu 6 pi (a b / (a + b))^2 times the
+// approach rate n.(v_j - v_i) times (1/h - 1/delta_n), with b -> infinity
+// (coefficient 6 pi mu a^2) for a wall; the gap is clipped at h_c and the
+// contact force added as in the contact-based model.  It passes through
+// both centres: no torque.
+template <typename R>
+__host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
+                                   const PRec* B, const KRec* KB, int side,
+                                   PairOut<R>& out, double& hout, int& status) {
+  const double a = A.Rperp;
+  double n[3], h, g;
+  const double* vj;
+  if (B) {
+    double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
+    for (int k = 0; k < 3; ++k)
+      if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
+    const double dn = sqrt(dot3(d, d));
+    for (int k = 0; k < 3; ++k) n[k] = d[k] / dn;
+    const double b = B->Rperp;
+    h = dn - a - b;
+    g = a * b / (a + b);
+    vj = KB->v;
+  } else {
+    n[0] = n[1] = 0.0;
+    n[2] = side == 0 ? -1.0 : 1.0;
+    h = (side == 0 ? A.r[2] : cd.L[2] - A.r[2]) - a;
+    g = a;
+    vj = cd.wall_vel[side];
+  }
+  hout = h;
+  const double heff = h > cd.h_c ? h : cd.h_c;
+  if (heff >= cd.delta_n && h > cd.h_c) {
+    status = 1;
+    return;
+  }
+  if (!(heff > 0.0)) {
+    status = 2;
+    return;
+  }
+  status = 0;
+  const double un = n[0] * (vj[0] - KA.v[0]) + n[1] * (vj[1] - KA.v[1]) +
+                    n[2] * (vj[2] - KA.v[2]);
+  double fn = cd.mu * 6.0 * kPi * g * g * (1.0 / heff - 1.0 / cd.delta_n) * un;
+  if (h <= cd.h_c) fn -= h > 0.0 ? cd.eps_c * (cd.h_c - h) : cd.eps_c * cd.h_c;
+  for (int k = 0; k < 3; ++k) out.F[k] = R(fn * n[k]);
+}
+
 template <typename R>
 __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
                           const PRec* B, const KRec* KB, int side,
@@ -412,6 +460,11 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
                           int& iters, const float* seedY = nullptr,
                           int* fell_back = nullptr) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
+  if (cd.model == LUB_MODEL_LADD) {
+    ladd_pair<R>(cd, A, KA, B, KB, side, out, hout, status);
+    iters = 0;
+    return;
+  }
   Solve sv;
   if (B) {
     double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
@@ -489,9 +542,11 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   k_coeffs<R>(R(S1), R(S2), R(G0), R(G2), R(iS1p), R(iS2p), R(G0p), R(G2p),
               R(cph), R(sph), C);
 
-  // cut-off factors (FP64), Eq. lub:resistance-correction
-  double Lt = heff < cd.delta_t ? log(heff) - log(cd.delta_t) : 0.0;
-  double Lr = heff < cd.delta_r ? log(heff) - log(cd.delta_r) : 0.0;
+  // cut-off factors (FP64), Eq. lub:resistance-correction; the "normal
+  // only" model drops every element but K33
+  const bool full = cd.model == LUB_MODEL_FULL;
+  double Lt = full && heff < cd.delta_t ? log(heff) - log(cd.delta_t) : 0.0;
+  double Lr = full && heff < cd.delta_r ? log(heff) - log(cd.delta_r) : 0.0;
   double Ln = heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
 
   // relative surface velocities in the local frame (FP64)

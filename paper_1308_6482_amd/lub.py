@@ -30,7 +30,8 @@ LUB_MLP_PARAMS = 34948
 class lub_params_t(C.Structure):
     _fields_ = [("mu", C.c_double), ("delta_n", C.c_double),
                 ("delta_t", C.c_double), ("delta_r", C.c_double),
-                ("h_c", C.c_double), ("eps_c", C.c_double)]
+                ("h_c", C.c_double), ("eps_c", C.c_double),
+                ("model", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lub_domain_t(C.Structure):
@@ -123,8 +124,12 @@ def _check(rc: int, where: str):
         raise LubError(rc, where)
 
 
-def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0) -> lub_params_t:
-    return lub_params_t(mu, delta_n, delta_t, delta_r, h_c, eps_c)
+LUB_MODEL_FULL, LUB_MODEL_NORMAL, LUB_MODEL_LADD = 0, 1, 2
+
+
+def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0,
+                model=LUB_MODEL_FULL) -> lub_params_t:
+    return lub_params_t(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0)
 
 
 def make_domain(L, periodic=(1, 1, 1), n_walls=0,

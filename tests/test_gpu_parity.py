@@ -293,3 +293,50 @@ def test_deterministic(cfg2):
     a = run_gpu(wl, L.LUB_MIXED)
     b = run_gpu(wl, L.LUB_MIXED)
     assert np.array_equal(a["f"], b["f"]) and np.array_equal(a["t"], b["t"])
+
+
+@pytest.mark.parametrize("model", [L.LUB_MODEL_NORMAL, L.LUB_MODEL_LADD])
+def test_reduced_models_spheres(ref, model):
+    """The paper's comparison models on 36 spheres (h_c = 0 and the
+    production clipping), both precisions, against the oracle's own
+    implementations of the same laws."""
+    for hc, ec in ((0.0, 0.0), (0.01, 100.0)):
+        wl = W.config1().with_params(h_c=hc, eps_c=ec, model=model)
+        o = run_oracle(ref, wl)
+        assert o["stats"]["active"] > 0
+        for prec, tol in ((L.LUB_FP64, 1e-9), (L.LUB_MIXED, 1e-5)):
+            g = run_gpu(wl, prec)
+            check_pairs(g, o)
+            assert g["stats"]["active"] == o["stats"]["active"]
+            ef, et = particle_errors(g, o)
+            print(f"model={model} hc={hc} prec={prec} f={ef.max():.3e} t={et.max():.3e}")
+            assert ef.max() < tol
+            if model == L.LUB_MODEL_LADD:
+                assert np.abs(g["t"]).max() == 0.0
+            else:
+                assert et.max() < tol or np.abs(g["t"]).max() < 1e-9 * np.abs(g["f"]).max()
+
+
+def test_normal_only_spheroids(ref, cfg2):
+    for wl, tol in ((cfg2.with_params(model=L.LUB_MODEL_NORMAL), 1e-5),
+                    (W.config3(n=3000).with_params(model=L.LUB_MODEL_NORMAL), 1e-5)):
+        g = run_gpu(wl, L.LUB_MIXED)
+        o = run_oracle(ref, wl)
+        check_pairs(g, o)
+        eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+        gate = act & (ha >= 1e-3)
+        print(f"{wl.name} normal-only active={act.sum()} eF={eF[gate].max():.3e} "
+              f"eT={eT[gate].max():.3e}")
+        assert eF[gate].max() < tol and eT[gate].max() < tol
+        ef, et = particle_errors(g, o, ref, wl)
+        assert ef.max() < tol and et.max() < tol
+
+
+def test_ladd_rejects_spheroids(cfg2):
+    wl = cfg2.with_params(model=L.LUB_MODEL_LADD)
+    lb = L.Lub.for_workload(wl)
+    r, q, semi, v, w = L.to_device(wl)
+    with pytest.raises(L.LubError) as e:
+        lb.compute(r, q, semi, v, w)
+    assert e.value.code == L.LUB_EINVAL
+    lb.close()
