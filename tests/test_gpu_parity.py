@@ -308,13 +308,13 @@ def test_reduced_models_spheres(ref, model):
             g = run_gpu(wl, prec)
             check_pairs(g, o)
             assert g["stats"]["active"] == o["stats"]["active"]
-            ef, et = particle_errors(g, o)
+            # the exact torques vanish (forces through the centres): their
+            # error is judged on the contribution scale, sum of a |F|
+            ef, et = particle_errors(g, o, ref, wl)
             print(f"model={model} hc={hc} prec={prec} f={ef.max():.3e} t={et.max():.3e}")
-            assert ef.max() < tol
+            assert ef.max() < tol and et.max() < tol
             if model == L.LUB_MODEL_LADD:
                 assert np.abs(g["t"]).max() == 0.0
-            else:
-                assert et.max() < tol or np.abs(g["t"]).max() < 1e-9 * np.abs(g["f"]).max()
 
 
 def test_normal_only_spheroids(ref, cfg2):
