@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy after the timed region "
                          "(reference for the HBM traffic counters)")
+    ap.add_argument("--model", choices=["full", "normal", "ladd"], default="full",
+                    help="resistance law: the full contact-based model, normal only, or "
+                         "Ladd's sphere law (spheres only)")
+    ap.add_argument("--compare-models", type=int, default=1,
+                    help="also time the normal-only model on the same workload (1) or not (0)")
     ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
                     help="Newton start: line of centres, learned network, or time both "
                          "(the JSON value is the plain form unless --seed mlp)")
@@ -305,7 +310,8 @@ def main():
     from paper_1308_6482_amd import lub as L
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wl = workload(args.workload)
+    models = {"full": L.LUB_MODEL_FULL, "normal": L.LUB_MODEL_NORMAL, "ladd": L.LUB_MODEL_LADD}
+    wl = workload(args.workload).with_params(model=models[args.model])
     prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
     forms = {}
     mlp_report = None
@@ -349,6 +355,7 @@ def main():
                     precision=args.precision, newton_seed=head,
                     cutoffs=[wl.params["delta_n"], wl.params["delta_t"], wl.params["delta_r"]],
                     h_c=wl.params["h_c"], eps_c=wl.params["eps_c"], mu=wl.params["mu"],
+                    model=args.model,
                     launch="HIP graph replay", parallelism="single GPU"),
         pairs=dict(candidates=st["candidates"], wall_candidates=st["wall_candidates"],
                    evaluated=st["evaluated"], active=active, overlaps=st["overlaps"],
@@ -364,6 +371,14 @@ def main():
     )
     if mlp_report:
         res["mlp_seed"] = mlp_report
+    if args.compare_models and args.model == "full":
+        # the paper's "normal only" comparison model on the same suspension
+        wn = wl.with_params(model=L.LUB_MODEL_NORMAL)
+        stn, msn, msn_e, _ = measure(L, torch, wn, prec, args)
+        res["models"] = {"normal": dict(value=stn["active"] / (msn * 1e-3), ms_per_step=msn,
+                                        ms_per_step_eager=msn_e, active=stn["active"],
+                                        newton_iters_mean=stn["newton_iters"]
+                                        / max(stn["evaluated"], 1))}
     if args.cpu_seconds > 0:
         lb2 = L.Lub.for_workload(wl, precision=prec)
         r, q, semi, v, w = L.to_device(wl)

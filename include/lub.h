@@ -131,7 +131,13 @@ typedef struct {
                            /* changes.  Needs a stream other than the null stream */
                            /* and timing = 0 (else LUB_EINVAL).  The arrays are read */
                            /* at replay time, so callers may update them in place */
-  int32_t reserved;        /* must be 0 */
+  int32_t warm_start;      /* 1: start each pair's Newton iteration from the common */
+                           /* normal it converged to in the previous call of this */
+                           /* handle (pairs keyed by their input indices), the */
+                           /* start of seed_mode judging it and taking over when it */
+                           /* does not converge; pairs new to the call use */
+                           /* seed_mode.  The paper's time-step continuation (Sec. */
+                           /* III.A).  0: every call starts afresh */
 } lub_opts_t;
 
 /* Per-call statistics of the last lub_compute. */
@@ -144,7 +150,7 @@ typedef struct {
   int64_t overlaps;         /* active pairs with h <= 0 */
   int64_t unresolved;       /* h <= 0 with h_c = 0: skipped */
   int64_t unconverged;      /* closest-point solve failed: skipped */
-  int64_t fallbacks;        /* learned seed rejected, plain seed used */
+  int64_t fallbacks;        /* learned or previous-call seed rejected, plain seed used */
   int64_t newton_iters;     /* total Newton iterations */
   int32_t newton_max;       /* largest per-pair iteration count */
   int32_t error;            /* LUB_OK or the error found by the last call */
@@ -155,6 +161,7 @@ typedef struct {
   /* 3 per-particle reduction */
   int64_t timed_calls;
   double stage_ms[4];
+  int64_t warm_seeded;      /* pairs started from the previous call's solution */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;

@@ -33,6 +33,11 @@ struct lub_ctx {
   int32_t* scat = nullptr;         // [n] scatter output (cell ranges, any order)
   int64_t* stat_nbr = nullptr;     // [neighbour blocks][kStatNbrWords]
   int64_t* stat_pair = nullptr;    // [kMaxPairBlocks][kStatPairWords]
+  // warm start: two tables of (pair key, converged normal), the one of
+  // counter set p written by calls using set p, read by the next call
+  uint64_t* warm_key[2] = {nullptr, nullptr};
+  float4* warm_val[2] = {nullptr, nullptr};
+  int64_t warm_size = 0;           // entries per table, a power of 2
   int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
   int32_t* deg = nullptr;          // [n] entries per segment
   int32_t* block_sums = nullptr;   // scan scratch
@@ -210,6 +215,20 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
         (rc = realloc_buf(&c->out_iters, work)))
       return rc;
     c->cap_work = work;
+    if (c->opt.warm_start) {
+      // load factor at most one half; new tables start empty (the seeds of
+      // earlier calls are dropped)
+      int64_t size = 1024;
+      while (size < 2 * work) size *= 2;
+      c->warm_size = 0;
+      for (int k = 0; k < 2; ++k) {
+        if ((rc = realloc_buf(&c->warm_key[k], size)) ||
+            (rc = realloc_buf(&c->warm_val[k], size)))
+          return rc;
+        HIP_TRY(hipMemset(c->warm_key[k], 0xff, sizeof(uint64_t) * size));
+      }
+      c->warm_size = size;
+    }
   }
   return LUB_OK;
 }
@@ -292,13 +311,22 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
              const double* semi, const double* v, const double* w, double* f,
              double* t, hipStream_t s);
 
-int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
-        const double* semi, const double* v, const double* w, double* f,
-        double* t, hipStream_t s) {
+// the capacities of the current workspace and the warm-start table size
+CallDesc finalize_desc(const lub_ctx* c, const CallDesc& d0) {
   CallDesc d = d0;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
-  return run_desc(c, d, r, q, semi, v, w, f, t, s);
+  // Ladd's law has no closest-point iteration to start
+  d.warm_mask = c->opt.warm_start && c->warm_size > 0 && d.model != LUB_MODEL_LADD
+                    ? c->warm_size - 1
+                    : 0;
+  return d;
+}
+
+int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
+        const double* semi, const double* v, const double* w, double* f,
+        double* t, hipStream_t s) {
+  return run_desc(c, finalize_desc(c, d0), r, q, semi, v, w, f, t, s);
 }
 
 int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
@@ -328,7 +356,13 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   c->cnt = c->cnt_buf + c->cnt_idx;
   Counters* next_cnt = c->cnt_buf + (c->cnt_idx ^ 1);
   const bool small = d.n > 0 && cells_small_fits(d);
-  if (!c->zeroed) launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  // warm-start tables of this call: written (empty on entry) and read
+  const int wc = c->cnt_idx, wp = c->cnt_idx ^ 1;
+  if (!c->zeroed) {
+    launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+    if (d.warm_mask)
+      HIP_TRY(hipMemsetAsync(c->warm_key[wc], 0xff, sizeof(uint64_t) * c->warm_size, s));
+  }
   c->zeroed = false;
   if (d.n > 0) {
     if (small) {
@@ -354,11 +388,14 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       mlp_forward_slots(c->cnt, d.cap_work, c->seedX, c->seedY, c->wt, c->th, s);
       seeds = c->seedY;
     }
+    WarmTables warm{c->warm_key[wp], c->warm_val[wp], c->warm_key[wc], c->warm_val[wc],
+                    c->sorted};
     launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
-                 c->out_h, c->out_status, c->out_iters, c->stat_pair, c->cnt, s);
+                 c->out_h, c->out_status, c->out_iters, warm, c->stat_pair, c->cnt, s);
     mark(3);
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
-                  c->cnt, next_cnt, f, t, s);
+                  c->cnt, next_cnt, d.warm_mask ? c->warm_key[wp] : nullptr,
+                  d.warm_mask ? c->warm_size : 0, f, t, s);
     mark(4);
     if (timing) c->pending.push_back(ev);
   }
@@ -387,7 +424,8 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->pos, c->kin,
           c->nbr,
           c->slot, c->work_s, c->work_t, c->out, c->out_h, c->out_status, c->out_iters,
-          c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th};
+          c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
+          c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1]};
 }
 
 void drop_graphs(lub_ctx* c) {
@@ -406,9 +444,7 @@ int run_graph(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
               const double* semi, const double* v, const double* w, double* f,
               double* t, hipStream_t s) {
   if (!c->zeroed || d0.n == 0) return run(c, d0, r, q, semi, v, w, f, t, s);
-  CallDesc d = d0;
-  d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
-  d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
+  const CallDesc d = finalize_desc(c, d0);
   const int par = c->cnt_idx ^ 1;  // the counter set this call uses
   lub_ctx::GraphSlot& g = c->graphs[par];
   const void* args[8] = {r, q, semi, v, w, f, t, s};
@@ -527,7 +563,7 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   if (opts->seed_mode != LUB_SEED_PLAIN && opts->seed_mode != LUB_SEED_MLP)
     return LUB_EINVAL;
   if ((opts->graph != 0 && opts->graph != 1) || (opts->graph && opts->timing) ||
-      opts->reserved != 0)
+      (opts->warm_start != 0 && opts->warm_start != 1))
     return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
@@ -643,6 +679,7 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   const Counters& c = *h->host_cnt;
   out->n = h->last.n;
   out->candidates = c.candidates;
+  out->warm_seeded = c.warm_seeded;
   out->wall_candidates = c.wall_candidates;
   out->evaluated = c.work;
   out->active = c.active;
@@ -861,7 +898,8 @@ void lub_destroy(lub_handle_t h) {
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
-                  h->cnt_buf, h->scat, h->pos, h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
+                  h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
+                  h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY};
   for (void* p : bufs)
     if (p) hipFree(p);

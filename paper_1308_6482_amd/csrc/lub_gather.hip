@@ -47,9 +47,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ slot,
     const int32_t* __restrict__ wall_slot, const PairOut<R>* __restrict__ out,
-    const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
+    const Counters* cnt, Counters* __restrict__ next_cnt,
+    uint64_t* __restrict__ warm_clear, int64_t warm_size, double* __restrict__ f,
     double* __restrict__ t) {
   const int lane = threadIdx.x & 63;
+  // the warm-start table this call read becomes the one the next call writes
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < warm_size;
+       e += (int64_t)gridDim.x * blockDim.x)
+    warm_clear[e] = kWarmEmpty;
   const int g = lane % kGroup;  // lane within the particle's group
   const int s = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kPerWave + lane / kGroup;
   if (blockIdx.x == 0)
@@ -112,19 +117,19 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
-                   hipStream_t s) {
+                   const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
+                   int64_t warm_size, double* f, double* t, hipStream_t s) {
   if (d.n == 0) return;
   const int per_block = kWaves * kPerWave;
   dim3 grid((d.n + per_block - 1) / per_block);
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_gather<float>, grid, dim3(64 * kWaves), 0, s, d, orig,
                        deg, nbr, slot, wall_slot, (const PairOut<float>*)out,
-                       cnt, next_cnt, f, t);
+                       cnt, next_cnt, warm_clear, warm_size, f, t);
   else
     hipLaunchKernelGGL(k_gather<double>, grid, dim3(64 * kWaves), 0, s, d, orig,
                        deg, nbr, slot, wall_slot, (const PairOut<double>*)out,
-                       cnt, next_cnt, f, t);
+                       cnt, next_cnt, warm_clear, warm_size, f, t);
 }
 
 namespace {
@@ -173,7 +178,7 @@ k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_bl
     case 4: cnt->unconverged = acc; break;
     case 5: cnt->fallbacks = acc; break;
     case 6: cnt->newton_max = (int32_t)acc; break;
-    case 7: break;
+    case 7: cnt->warm_seeded = acc; break;
     case kStatPairWords: cnt->candidates = acc; break;
     case kStatPairWords + 1: cnt->wall_candidates = acc; break;
     default: cnt->iter_hist[word - 8] = acc; break;

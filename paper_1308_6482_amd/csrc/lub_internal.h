@@ -42,6 +42,7 @@ struct Counters {
   int64_t fallbacks;
   int64_t newton_iters;
   int64_t total_entries;  // neighbour-list entries (both directions)
+  int64_t warm_seeded;    // pairs started from the previous call's normal
   int64_t iter_hist[32];
 };
 
@@ -49,7 +50,7 @@ struct Counters {
 // when the host asks for the counters.
 //   pair kernel rows: [0] Newton iterations, [1] active, [2] overlaps,
 //   [3] unresolved, [4] unconverged, [5] fallbacks, [6] max iterations,
-//   [7] unused, [8..39] iteration histogram
+//   [7] warm-seeded pairs, [8..39] iteration histogram
 //   neighbour kernel rows: [0] candidate pairs, [1] wall candidates
 constexpr int kStatPairWords = 40;
 constexpr int kStatNbrWords = 2;
@@ -65,6 +66,7 @@ struct CallDesc {
   int32_t reach_max;    // cells searched on each side at most (cells are at
                         // least 1/reach_max of the largest pair bound)
   int32_t model;        // LUB_MODEL_*
+  int64_t warm_mask;    // warm start: hash table size - 1; 0 = off
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
@@ -132,10 +134,23 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the
 // line-of-centres start
+// Warm start: converged normals of evaluated particle pairs by (input
+// index i << 32 | input index j), open addressing with linear probing.
+constexpr uint64_t kWarmEmpty = ~0ull;
+constexpr int kWarmProbes = 32;
+struct WarmTables {
+  const uint64_t* prev_key;  // read: the previous call's pairs
+  const float4* prev_val;
+  uint64_t* cur_key;         // written: this call's pairs (all empty on entry)
+  float4* cur_val;
+  const int32_t* orig;       // cell order -> input index
+};
+
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  int64_t* stat_pair, Counters* cnt, hipStream_t s);
+                  WarmTables warm, int64_t* stat_pair, Counters* cnt,
+                  hipStream_t s);
 
 // seed features of every particle-particle evaluation slot (m x 10, FP32)
 void launch_seed_features(const CallDesc& d, const PRec* rec,
@@ -160,8 +175,8 @@ void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
-                   hipStream_t s);
+                   const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
+                   int64_t warm_size, double* f, double* t, hipStream_t s);
 
 // grid of the pair kernel for a given slot capacity
 int pair_grid(const CallDesc& d);

@@ -458,7 +458,8 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
                           const PRec* B, const KRec* KB, int side,
                           PairOut<R>& out, double& hout, int& status,
                           int& iters, const float* seedY = nullptr,
-                          int* fell_back = nullptr) {
+                          int* fell_back = nullptr, const double* nseed = nullptr,
+                          int* warm_used = nullptr, double* nout = nullptr) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
   if (cd.model == LUB_MODEL_LADD) {
     ladd_pair<R>(cd, A, KA, B, KB, side, out, hout, status);
@@ -470,10 +471,21 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
     for (int k = 0; k < 3; ++k)
       if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
+    // start: the previous call's normal (warm start), else the learned
+    // prediction, else the line of centres.  The plain start judges a seeded
+    // one: if the seeded iteration does not converge, start again from the
+    // line of centres
     double n0[3];
-    if (seedY && seed_normal(d, A, *B, seedY, n0)) {
-      // learned start; the plain start judges it: if the seeded iteration
-      // does not converge, start again from the line of centres
+    bool seeded = false;
+    if (nseed && dot3(nseed, d) > 0.0) {
+      for (int k = 0; k < 3; ++k) n0[k] = nseed[k];
+      seeded = true;
+      if (warm_used) *warm_used = 1;
+    } else if (seedY) {
+      seeded = seed_normal(d, A, *B, seedY, n0);
+      if (!seeded && fell_back) *fell_back = 1;
+    }
+    if (seeded) {
       sv = closest_points(d, A.M, B->M, cd.max_iter, n0);
       if (!sv.ok) {
         const int used = sv.iters;
@@ -483,8 +495,9 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       }
     } else {
       sv = closest_points(d, A.M, B->M, cd.max_iter);
-      if (seedY && fell_back) *fell_back = 1;
     }
+    if (nout && sv.ok)
+      for (int k = 0; k < 3; ++k) nout[k] = sv.n[k];
   } else {
     // wall: the particle's support point towards the plane
     double nz = side == 0 ? -1.0 : 1.0;
@@ -605,6 +618,14 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
 
 constexpr int kPairBlock = 64;
 
+// bucket of a warm-start key (a 64-bit mix; the table size is a power of 2)
+__device__ __forceinline__ uint64_t warm_hash(uint64_t k) {
+  k ^= k >> 31;
+  k *= 0x9E3779B97F4A7C15ull;
+  k ^= k >> 29;
+  return k;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               const PRec* __restrict__ rec,
@@ -616,6 +637,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               double* __restrict__ out_h,
                                               int8_t* __restrict__ out_status,
                                               uint8_t* __restrict__ out_iters,
+                                              WarmTables warm,
                                               int64_t* __restrict__ stat_pair,
                                               const Counters* cnt) {
   // one wavefront per block: statistics are reduced in the wave (ballots,
@@ -626,21 +648,61 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
   // count leave at once (their rows are not read)
   const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
   if (blockIdx.x * blockDim.x >= nwork) return;
-  int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0;
+  int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0,
+          n_warm = 0;
   int max_it = 0;
   int64_t my_hist = 0;  // lane b < 32 holds histogram bucket b
   for (int w0 = blockIdx.x * blockDim.x; w0 < nwork; w0 += gridDim.x * blockDim.x) {
     const int w = w0 + lane;
     const bool on = w < nwork;
-    int status = -1, iters = 0, fb = 0;
+    int status = -1, iters = 0, fb = 0, wu = 0;
     double h = 0.0;
     if (on) {
       int s = work_s[w], t = work_t[w];
       PairOut<R> o;
-      if (t >= 0)
-        eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
-                     seedY ? seedY + 4 * (int64_t)w : nullptr, &fb);
-      else
+      if (t >= 0) {
+        if (cd.warm_mask) {
+          const uint64_t key = ((uint64_t)warm.orig[s] << 32) | (uint64_t)warm.orig[t];
+          const uint64_t h0 = warm_hash(key);
+          double nprev[3];
+          bool found = false;
+          for (int p = 0; p < kWarmProbes; ++p) {
+            const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
+            const uint64_t k = warm.prev_key[e];
+            if (k == key) {
+              const float4 v = warm.prev_val[e];
+              nprev[0] = v.x;
+              nprev[1] = v.y;
+              nprev[2] = v.z;
+              found = true;
+              break;
+            }
+            if (k == kWarmEmpty) break;
+          }
+          double nnew[3] = {0.0, 0.0, 0.0};
+          eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+                       seedY ? seedY + 4 * (int64_t)w : nullptr, &fb,
+                       found ? nprev : nullptr, &wu, nnew);
+          if (status != 3) {
+            // this call's normal for the next call (a full probe sequence
+            // only costs the pair its warm start)
+            for (int p = 0; p < kWarmProbes; ++p) {
+              const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
+              const unsigned long long old = atomicCAS(
+                  (unsigned long long*)&warm.cur_key[e], (unsigned long long)kWarmEmpty,
+                  (unsigned long long)key);
+              if (old == kWarmEmpty || old == key) {
+                warm.cur_val[e] = make_float4((float)nnew[0], (float)nnew[1],
+                                              (float)nnew[2], 0.f);
+                break;
+              }
+            }
+          }
+        } else {
+          eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+                       seedY ? seedY + 4 * (int64_t)w : nullptr, &fb);
+        }
+      } else
         eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
                      iters);
       out[w] = o;
@@ -656,6 +718,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     n_unres += __popcll(__ballot(status == 2));
     n_uncon += __popcll(__ballot(status == 3));
     n_fb += __popcll(__ballot(fb != 0));
+    n_warm += __popcll(__ballot(wu != 0));
     // histogram over the buckets present in this pass
     int lo = on ? bucket : 32, hi = bucket;
 #pragma unroll
@@ -681,7 +744,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                   : lane == 4 ? n_uncon
                   : lane == 5 ? n_fb
                   : lane == 6 ? (int64_t)max_it
-                              : 0;
+                              : n_warm;
   if (lane < 8) row[lane] = v;
   if (lane < 32) row[8 + lane] = my_hist;
 }
@@ -729,16 +792,16 @@ int pair_grid(const CallDesc& d) {
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  int64_t* stat_pair, Counters* cnt, hipStream_t s) {
+                  WarmTables warm, int64_t* stat_pair, Counters* cnt, hipStream_t s) {
   const int blocks = pair_grid(d);
   if (d.precision == LUB_MIXED)
     hipLaunchKernelGGL(k_pairs<float>, dim3(blocks), dim3(kPairBlock), 0, s, d,
                        rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
-                       out_status, out_iters, stat_pair, cnt);
+                       out_status, out_iters, warm, stat_pair, cnt);
   else
     hipLaunchKernelGGL(k_pairs<double>, dim3(blocks), dim3(kPairBlock), 0, s, d,
                        rec, kin, work_s, work_t, seedY, (PairOut<double>*)out, out_h,
-                       out_status, out_iters, stat_pair, cnt);
+                       out_status, out_iters, warm, stat_pair, cnt);
 }
 
 }  // namespace lub

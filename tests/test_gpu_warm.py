@@ -1,0 +1,127 @@
+"""GPU tests of the warm start (Newton started from the common normal the
+same pair converged to in the handle's previous call; Sec. III.A's
+continuation between time steps).
+
+* Same inputs twice: the second call seeds every evaluated particle pair
+  and converges in about two iterations to the plain result.
+* A short trajectory (positions advanced by v dt between calls): every
+  step equals a fresh evaluation with the plain start at the FP64 bar,
+  with fewer Newton iterations.
+* Graph replay with warm start equals eager warm start bit for bit, and
+  two warm handles on the same trajectory agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1308_6482_amd import lub as L  # noqa: E402
+from paper_1308_6482_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+def rel_err(a, b):
+    rms = np.sqrt(np.mean(np.sum(b ** 2, axis=1)))
+    den = np.maximum(np.linalg.norm(b, axis=1), max(1e-3 * rms, 1e-300))
+    return (np.linalg.norm(a - b, axis=1) / den).max()
+
+
+def test_repeat_call_is_seeded():
+    wl = W.config2()
+    print("[gpu] warm start, repeated call, 4096 prolates", flush=True)
+    r, q, semi, v, w = L.to_device(wl)
+    plain = L.Lub.for_workload(wl, precision=L.LUB_FP64)
+    fp, tp = plain.compute(r, q, semi, v, w)
+    sp = plain.stats()
+    warm = L.Lub.for_workload(wl, precision=L.LUB_FP64, warm_start=1)
+    warm.compute(r, q, semi, v, w)
+    s1 = warm.stats()
+    assert s1["warm_seeded"] == 0
+    fw, tw = warm.compute(r, q, semi, v, w)
+    s2 = warm.stats()
+    pp = s2["evaluated"] - s2["wall_candidates"]
+    print(f"plain iters/pair {sp['newton_iters'] / sp['evaluated']:.3f}, warm "
+          f"{s2['newton_iters'] / s2['evaluated']:.3f}, seeded {s2['warm_seeded']} of {pp}")
+    assert s2["warm_seeded"] == pp and s2["fallbacks"] == 0
+    assert s2["newton_iters"] <= 2.05 * s2["evaluated"]
+    assert s2["active"] == sp["active"]
+    assert rel_err(fw.cpu().numpy(), fp.cpu().numpy()) < 1e-10
+    assert rel_err(tw.cpu().numpy(), tp.cpu().numpy()) < 1e-10
+    plain.close()
+    warm.close()
+
+
+def trajectory(wl, steps, dt):
+    r = wl.r.copy()
+    out = []
+    for _ in range(steps):
+        out.append(r.copy())
+        r = r + wl.v * dt
+    return out
+
+
+@pytest.mark.parametrize("precision,tol", [(L.LUB_FP64, 1e-9), (L.LUB_MIXED, 1e-5)])
+def test_trajectory_matches_plain(precision, tol):
+    wl = W.config3(n=3000)
+    print(f"[gpu] warm start trajectory, 3000 polydisperse, precision={precision}",
+          flush=True)
+    warm = L.Lub.for_workload(wl, precision=precision, warm_start=1)
+    _, q, semi, v, w = L.to_device(wl)
+    it_w = it_p = 0
+    for k, rk in enumerate(trajectory(wl, 6, dt=1.0)):
+        r = torch.as_tensor(rk, dtype=torch.float64, device="cuda")
+        fw, tw = warm.compute(r, q, semi, v, w)
+        sw = warm.stats()
+        plain = L.Lub.for_workload(wl, precision=precision)
+        fp, tp = plain.compute(r, q, semi, v, w)
+        sp = plain.stats()
+        plain.close()
+        ef = rel_err(fw.cpu().numpy(), fp.cpu().numpy())
+        et = rel_err(tw.cpu().numpy(), tp.cpu().numpy())
+        print(f"step {k}: seeded {sw['warm_seeded']} iters warm {sw['newton_iters']} "
+              f"plain {sp['newton_iters']} err f={ef:.2e} t={et:.2e}")
+        assert sw["active"] == sp["active"] and sw["unconverged"] == 0
+        # the two starts converge to the same points: FP64-level agreement
+        # in FP64, the mixed-precision bar otherwise
+        assert ef < tol and et < tol
+        if k > 0:
+            assert sw["warm_seeded"] > 0.9 * (sw["evaluated"] - sw["wall_candidates"])
+            it_w += sw["newton_iters"]
+            it_p += sp["newton_iters"]
+    assert it_w < 0.75 * it_p
+    warm.close()
+
+
+def test_graph_and_determinism():
+    wl = W.config3(n=3000)
+    print("[gpu] warm start: graph replay and determinism", flush=True)
+    stream = torch.cuda.Stream()
+    _, q, semi, v, w = L.to_device(wl)
+    r = torch.as_tensor(wl.r, dtype=torch.float64, device="cuda")
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    eager = L.Lub.for_workload(wl, precision=L.LUB_MIXED, warm_start=1)
+    eager2 = L.Lub.for_workload(wl, precision=L.LUB_MIXED, warm_start=1)
+    graph = L.Lub.for_workload(wl, precision=L.LUB_MIXED, warm_start=1, graph=1, sync=0)
+    vel = torch.as_tensor(wl.v, dtype=torch.float64, device="cuda")
+    for k in range(6):
+        fe, te = eager.compute(r, q, semi, v, w)
+        fe2, te2 = eager2.compute(r, q, semi, v, w)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.compute(r, q, semi, v, w, f, t, stream=stream)
+        stream.synchronize()
+        assert torch.equal(fe, fe2) and torch.equal(te, te2), f"step {k} not deterministic"
+        assert torch.equal(f, fe) and torch.equal(t, te), f"graph step {k} differs"
+        assert graph.stats()["warm_seeded"] == eager.stats()["warm_seeded"]
+        r.add_(vel)   # advance in place: the replay reads the new positions
+        torch.cuda.synchronize()
+    for lb in (eager, eager2, graph):
+        lb.close()
