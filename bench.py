@@ -56,6 +56,9 @@ def parse():
                          "Ladd's sphere law (spheres only)")
     ap.add_argument("--compare-models", type=int, default=1,
                     help="also time the normal-only model on the same workload (1) or not (0)")
+    ap.add_argument("--trajectory-dt", type=float, default=0.1,
+                    help="warm-start leg: positions advanced by v dt between the K timed "
+                         "evaluations (0: skip the leg)")
     ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
                     help="Newton start: line of centres, learned network, or time both "
                          "(the JSON value is the plain form unless --seed mlp)")
@@ -283,6 +286,48 @@ def measure(L, torch, wl, prec, args, theta=None):
     return results["eager"][0], results["graph"][1], results["eager"][1], (f, t)
 
 
+def trajectory(L, torch, wl, prec, args, warm):
+    """K evaluations along a moving suspension (positions advanced in place
+    by v dt after each evaluation, graph replay), with or without the warm
+    start; returns a report of the last evaluation and the timing."""
+    import numpy as np
+    r0, q, semi, v, w = L.to_device(wl)
+    r = r0.clone()
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm))
+    iters = evaluated = seeded = 0
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            r.add_(v, alpha=args.trajectory_dt)
+        torch.cuda.synchronize()
+        st0 = lb.stats()
+        if st0["error"]:
+            raise RuntimeError(f"lub_compute failed: {L.lub_strerror(st0['error'])}")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            r.add_(v, alpha=args.trajectory_dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    st = lb.stats()
+    lb.close()
+    if st["error"] or st["unconverged"]:
+        raise RuntimeError(f"invalid run: error={st['error']} unconverged={st['unconverged']}")
+    ms = (t1 - t0) * 1e3 / args.steps
+    hist = np.array(st["iter_hist"], dtype=np.int64)
+    cdf = np.cumsum(hist) / max(hist.sum(), 1)
+    return dict(value=st["active"] / (ms * 1e-3), ms_per_step=ms, active=st["active"],
+                overlaps=st["overlaps"], evaluated=st["evaluated"],
+                warm_seeded=st["warm_seeded"], fallbacks=st["fallbacks"],
+                newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
+                newton_iters_p50=int(np.searchsorted(cdf, 0.5)),
+                newton_iters_p99=int(np.searchsorted(cdf, 0.99)),
+                newton_max=st["newton_max"])
+
+
 def summary(st, ms, args, ms_eager=None):
     active = st["active"]
     pair_ms = st["stage_ms"][2] / max(st["timed_calls"], 1)
@@ -371,6 +416,13 @@ def main():
     )
     if mlp_report:
         res["mlp_seed"] = mlp_report
+    if args.trajectory_dt > 0:
+        # the paper's continuation between time steps: the same moving
+        # suspension with and without the warm start (last evaluation's counts)
+        res["warm_start"] = dict(
+            dt=args.trajectory_dt,
+            warm=trajectory(L, torch, wl, prec, args, True),
+            plain=trajectory(L, torch, wl, prec, args, False))
     if args.compare_models and args.model == "full":
         # the paper's "normal only" comparison model on the same suspension
         wn = wl.with_params(model=L.LUB_MODEL_NORMAL)

@@ -121,11 +121,29 @@ def test_two_sphere_leading_terms(ref, a, b):
         assert np.allclose(o["Ti"], 0, atol=1e-12 * scale)
 
 
+def gcb_coefficients(a):
+    """The Goldman-Cox-Brenner leading coefficients for radius a, from the
+    cited fixture (literature normalisation: prefactor, fraction, power)."""
+    import os
+    from fractions import Fraction
+    path = os.path.join(os.path.dirname(__file__), "golden", "sphere_wall_gcb.txt")
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, pref, frac, power = line.split()
+        out[name] = {"6pi": 6.0, "8pi": 8.0}[pref] * np.pi * float(Fraction(frac)) \
+            * a ** int(power)
+    return out
+
+
 def test_sphere_wall_goldman_cox_brenner(ref):
     """The particle-wall pair of the oracle (wall as a surface with infinite
     radii) against the Goldman-Cox-Brenner leading terms."""
     rng = np.random.default_rng(5)
-    a, mu, delta = 3.0, 0.4, 0.5
+    a = 3.0
+    g = gcb_coefficients(a)
+    mu, delta = 0.4, 0.5
     z = np.zeros(3)
     P = ref.make_params(mu=mu, delta_n=delta, delta_t=delta, delta_r=delta)
     Ltop = 50.0
@@ -138,18 +156,18 @@ def test_sphere_wall_goldman_cox_brenner(ref):
             Lg = np.log(h / delta)
             o = ref.wall_eval(r, rand_quat(rng), [a, a], 0.8 * e3, z, side, dom, P)
             assert abs(o["h"] - h) < 1e-12 * Ltop
-            assert np.allclose(o["F"], -mu * 6 * np.pi * a * a * (1 / h - 1 / delta)
+            assert np.allclose(o["F"], -mu * g["K33_times_h"] * (1 / h - 1 / delta)
                                * 0.8 * e3, rtol=1e-9)
             e1 = np.array([1.0, 0, 0])
             o = ref.wall_eval(r, rand_quat(rng), [a, a], 0.8 * e1, z, side, dom, P)
-            assert np.allclose(o["F"], mu * 16 / 5 * np.pi * a * Lg * 0.8 * e1, rtol=1e-9)
-            assert np.allclose(o["Ti"], mu * 4 / 5 * np.pi * a * a * Lg * 0.8
+            assert np.allclose(o["F"], mu * g["tangential_ln"] * Lg * 0.8 * e1, rtol=1e-9)
+            assert np.allclose(o["Ti"], mu * g["coupling_ln"] * Lg * 0.8
                                * np.cross(e3, e1), rtol=1e-9, atol=1e-13)
             e2 = np.cross(e3, e1)
             o = ref.wall_eval(r, rand_quat(rng), [a, a], z, 0.5 * e2, side, dom, P)
-            assert np.allclose(o["F"], -mu * 4 / 5 * np.pi * a * a * Lg * 0.5
+            assert np.allclose(o["F"], -mu * g["coupling_ln"] * Lg * 0.5
                                * np.cross(e3, e2), rtol=1e-9)
-            assert np.allclose(o["Ti"], mu * 16 / 5 * np.pi * a ** 3 * Lg * 0.5 * e2,
+            assert np.allclose(o["Ti"], mu * g["rotation_ln"] * Lg * 0.5 * e2,
                                rtol=1e-9)
 
 
