@@ -320,6 +320,14 @@ __device__ __forceinline__ void axis_stencil(int c, int nc, int periodic, int re
   }
 }
 
+// Lower bound of the distance along one axis from a point at offset f from
+// the lower face of its cell to the cell `o` cells away, shrunk by a relative
+// margin far above rounding (the bound only prunes).
+__device__ __forceinline__ double axis_gap(int o, double f, double cell) {
+  const double g = o > 0 ? o * cell - f : (o < 0 ? f - (o + 1) * cell : 0.0);
+  return fmax(0.0, g * (1.0 - 1e-9) - 1e-9 * cell);
+}
+
 __device__ __forceinline__ int wrap_cell(int c, int nc) {
   return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
@@ -467,30 +475,60 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
     axis_stencil(cy, d.nc[1], d.periodic[1], reach[1], &first[1], &cnt3[1]);
     axis_stencil(cz, d.nc[2], d.periodic[2], reach[2], &first[2], &cnt3[2]);
     const int nrows = cnt3[1] * cnt3[2];
-    // lane u < nrows owns the row of cells (y, z) of the stencil: its cells
-    // along x are one contiguous range of cell-ordered particles, or two
-    // when the range wraps around a periodic axis
+    // this centre relative to the lower corner of its cell (the wrap of the
+    // binning on periodic axes)
+    double f3[3];
+    const int c3[3] = {cx, cy, cz};
+    for (int k = 0; k < 3; ++k) {
+      double x = ri[k];
+      if (d.periodic[k]) x = x - d.L[k] * floor(x / d.L[k]);
+      f3[k] = x - c3[k] * d.cell[k];
+    }
+    // an axis taken whole (periodic, shorter than the stencil) is not pruned
+    bool whole[3];
+    for (int k = 0; k < 3; ++k) whole[k] = d.periodic[k] && cnt3[k] == d.nc[k];
+    // lane u < nrows owns the row of cells (y, z) of the stencil.  Rows
+    // farther than rho from the centre hold no candidate; in the others the
+    // cells along x are cut to the chord of the sphere of radius rho.  What
+    // is left is one contiguous range of cell-ordered particles, or two when
+    // it wraps around a periodic axis
     int s0 = 0, n0 = 0, s1 = 0, n1 = 0;
     if (lane < nrows) {
-      const int ry = wrap_cell(first[1] + lane % cnt3[1], d.nc[1]);
-      const int rz = wrap_cell(first[2] + lane / cnt3[1], d.nc[2]);
-      const int rowbase = (rz * d.nc[1] + ry) * d.nc[0];
+      const int oy = first[1] + lane % cnt3[1] - cy;  // offsets from this cell
+      const int oz = first[2] + lane / cnt3[1] - cz;
+      const double gy = whole[1] ? 0.0 : axis_gap(oy, f3[1], d.cell[1]);
+      const double gz = whole[2] ? 0.0 : axis_gap(oz, f3[2], d.cell[2]);
+      const double rem = rho * rho - gy * gy - gz * gz;
       int a0 = first[0], a1 = first[0] + cnt3[0] - 1;  // cells a0..a1 along x
-      int b0 = 0, b1 = -1;                             // wrapped part
-      if (a0 < 0) {
-        b0 = a0 + d.nc[0];
-        b1 = d.nc[0] - 1;
-        a0 = 0;
-      } else if (a1 >= d.nc[0]) {
-        b0 = 0;
-        b1 = a1 - d.nc[0];
-        a1 = d.nc[0] - 1;
+      if (!whole[0]) {
+        const double wx = sqrt(fmax(rem, 0.0)) * (1.0 + 1e-9) + 1e-9 * d.cell[0];
+        a0 = max(a0, cx + (int)floor((f3[0] - wx) / d.cell[0]));
+        a1 = min(a1, cx + (int)floor((f3[0] + wx) / d.cell[0]));
       }
-      s0 = cell_start[rowbase + a0];
-      n0 = cell_start[rowbase + a1 + 1] - s0;
-      if (b1 >= b0) {
-        s1 = cell_start[rowbase + b0];
-        n1 = cell_start[rowbase + b1 + 1] - s1;
+      if (rem > 0.0 && a1 >= a0) {
+        const int ry = wrap_cell(cy + oy, d.nc[1]);
+        const int rz = wrap_cell(cz + oz, d.nc[2]);
+        const int rowbase = (rz * d.nc[1] + ry) * d.nc[0];
+        // the part inside [0, nc) and the part wrapped around (the range is
+        // shorter than the axis, so at most one side wraps)
+        const int nx = d.nc[0];
+        const int p0 = max(a0, 0), p1 = min(a1, nx - 1);
+        int b0 = 0, b1 = -1;
+        if (a0 < 0) {
+          b0 = a0 + nx;
+          b1 = min(a1, -1) + nx;
+        } else if (a1 >= nx) {
+          b0 = max(a0, nx) - nx;
+          b1 = a1 - nx;
+        }
+        if (p1 >= p0) {
+          s0 = cell_start[rowbase + p0];
+          n0 = cell_start[rowbase + p1 + 1] - s0;
+        }
+        if (b1 >= b0) {
+          s1 = cell_start[rowbase + b0];
+          n1 = cell_start[rowbase + b1 + 1] - s1;
+        }
       }
     }
     const int cn = n0 + n1;
