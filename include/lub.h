@@ -162,6 +162,8 @@ typedef struct {
   int64_t timed_calls;
   double stage_ms[4];
   int64_t warm_seeded;      /* pairs started from the previous call's solution */
+  int64_t max_degree;       /* most candidate partners of one particle (also when it */
+                            /* exceeded max_neighbors: the value to set) */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;

@@ -124,6 +124,9 @@ def lib():
                                          C.POINTER(Domain), C.POINTER(Params),
                                          C.c_int64, _I64, C.c_int, _D, _D,
                                          C.POINTER(Stats)]
+        L.ref_partners_subset.argtypes = [C.c_int64, _D, _D, C.POINTER(Domain),
+                                          C.POINTER(Params), C.c_int64, _I64,
+                                          C.c_int64, _I32, _I64]
         L.ref_eval_pairs.argtypes = [C.c_int64, _D, _D, _D, _D, _D,
                                      C.POINTER(Domain), C.POINTER(Params),
                                      C.c_int64, _I32, C.c_int, _D, _D, _D, _D,
@@ -253,6 +256,22 @@ def compute_subset(r, q, semi, v, w, domain: Domain, params: Params, idx,
     if rc != 0:
         raise ValueError(f"ref_compute_subset rejected its inputs (rc={rc})")
     return f, t, st.as_dict()
+
+
+def partners_subset(r, semi, domain: Domain, params: Params, idx, cap=512):
+    """Candidate partners of the particles idx (brute force): list of
+    sorted int arrays."""
+    r, semi = _d(r), _d(semi)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    m = idx.shape[0]
+    out = np.full((m, cap), -1, dtype=np.int32)
+    cnt = np.zeros(m, dtype=np.int64)
+    rc = lib().ref_partners_subset(r.shape[0], _p(r), _p(semi), C.byref(domain),
+                                   C.byref(params), m, _p(idx, _I64), cap,
+                                   _p(out, _I32), _p(cnt, _I64))
+    if rc != 0:
+        raise ValueError(f"ref_partners_subset failed (rc={rc})")
+    return [out[s, :cnt[s]].copy() for s in range(m)]
 
 
 def eval_pairs(r, q, semi, v, w, domain: Domain, params: Params, ij,

@@ -891,6 +891,33 @@ int ref_candidates(int64_t n, const double* r, const double* semi,
   return rc;
 }
 
+int ref_partners_subset(int64_t n, const double* r, const double* semi,
+                        const ref_domain* dom, const ref_params* prm, int64_t m,
+                        const int64_t* idx, int64_t cap, int32_t* partners,
+                        int64_t* counts) {
+  double dmax = max_cutoff(prm);
+  int rc = REF_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t s = 0; s < m; ++s) {
+    const int64_t k = idx[s];
+    int64_t c = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == k) continue;
+      if (!ref_centre_test(&r[3 * k], &r[3 * j], rmax_of(semi, k), rmax_of(semi, j),
+                           dmax, dom))
+        continue;
+      if (c < cap) partners[s * cap + c] = (int32_t)j;
+      ++c;
+    }
+    counts[s] = c;
+    if (c > cap) {
+#pragma omp critical
+      rc = REF_ECAPACITY;
+    }
+  }
+  return rc;
+}
+
 static void image_offset(const double* r, int64_t i, int64_t j,
                          const ref_domain* dom, double d[3]) {
   for (int k = 0; k < 3; ++k)

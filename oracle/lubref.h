@@ -174,6 +174,15 @@ int ref_compute(int64_t n, const double* r, const double* q,
 /* Per-particle force and torque for a subset of particles (brute-force
  * partner scan per sampled particle; same orientation and summation order
  * as ref_compute).  For large systems where the full oracle is too slow. */
+/* The candidate partners (the centre test of ref_candidates) of each of
+ * the m particles idx[s], in increasing index, into partners[s*cap ..]
+ * (brute force over all particles); counts[s] their number.
+ * REF_ECAPACITY if a particle has more than cap. */
+int ref_partners_subset(int64_t n, const double* r, const double* semi,
+                        const ref_domain* dom, const ref_params* prm, int64_t m,
+                        const int64_t* idx, int64_t cap, int32_t* partners,
+                        int64_t* counts);
+
 int ref_compute_subset(int64_t n, const double* r, const double* q,
                        const double* semi, const double* v, const double* w,
                        const ref_domain* dom, const ref_params* prm,

@@ -216,10 +216,12 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
       return rc;
     c->cap_work = work;
     if (c->opt.warm_start) {
-      // load factor at most one half; new tables start empty (the seeds of
-      // earlier calls are dropped)
+      // four entries per particle: dense suspensions evaluate one to two
+      // pairs per particle, so the load stays below one half (a fuller table
+      // only costs pairs their warm start).  New tables start empty: the
+      // seeds of earlier calls are dropped
       int64_t size = 1024;
-      while (size < 2 * work) size *= 2;
+      while (size < 4 * std::max<int64_t>(n, 1)) size *= 2;
       c->warm_size = 0;
       for (int k = 0; k < 2; ++k) {
         if ((rc = realloc_buf(&c->warm_key[k], size)) ||
@@ -680,6 +682,7 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   out->n = h->last.n;
   out->candidates = c.candidates;
   out->warm_seeded = c.warm_seeded;
+  out->max_degree = c.max_degree;
   out->wall_candidates = c.wall_candidates;
   out->evaluated = c.work;
   out->active = c.active;

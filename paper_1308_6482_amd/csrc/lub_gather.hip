@@ -155,7 +155,7 @@ k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_bl
     base = stat_nbr + (word - kStatPairWords);
     stride = kStatNbrWords;
   }
-  const bool is_max = word == 6;
+  const bool is_max = word == 6 || word == kStatPairWords + 2;
   int64_t acc = 0;
   for (int r = threadIdx.x; r < rows; r += kReduceThreads) {
     const int64_t v = base[(int64_t)r * stride];
@@ -181,6 +181,7 @@ k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_bl
     case 7: cnt->warm_seeded = acc; break;
     case kStatPairWords: cnt->candidates = acc; break;
     case kStatPairWords + 1: cnt->wall_candidates = acc; break;
+    case kStatPairWords + 2: cnt->max_degree = acc; break;
     default: cnt->iter_hist[word - 8] = acc; break;
   }
 }

@@ -43,6 +43,7 @@ struct Counters {
   int64_t newton_iters;
   int64_t total_entries;  // neighbour-list entries (both directions)
   int64_t warm_seeded;    // pairs started from the previous call's normal
+  int64_t max_degree;     // largest number of candidates of one particle
   int64_t iter_hist[32];
 };
 
@@ -51,9 +52,10 @@ struct Counters {
 //   pair kernel rows: [0] Newton iterations, [1] active, [2] overlaps,
 //   [3] unresolved, [4] unconverged, [5] fallbacks, [6] max iterations,
 //   [7] warm-seeded pairs, [8..39] iteration histogram
-//   neighbour kernel rows: [0] candidate pairs, [1] wall candidates
+//   neighbour kernel rows: [0] candidate pairs, [1] wall candidates,
+//   [2] largest number of candidates of one particle
 constexpr int kStatPairWords = 40;
-constexpr int kStatNbrWords = 2;
+constexpr int kStatNbrWords = 3;
 constexpr int kMaxPairBlocks = 16384;  // larger slot counts: grid-stride loop
 
 // Constant description of one call.

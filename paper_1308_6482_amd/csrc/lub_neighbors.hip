@@ -444,6 +444,7 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   __shared__ int s_upper[kWavesPerBlock];
   __shared__ int s_wallc[kWavesPerBlock];
   __shared__ int s_base[kWavesPerBlock];
+  __shared__ int s_deg[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int s = blockIdx.x * kWavesPerBlock + wv;
@@ -639,6 +640,7 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   if (live) deg[s] = nent;
   // wave totals -> block total -> one atomic per block
   int wkeep = nkeep, wup = nupper, wwall = nwallc;
+  const int wdeg = live ? count : 0;  // uniform in the wave
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     wkeep += __shfl_xor(wkeep, o, 64);
@@ -649,21 +651,24 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
     s_keep[wv] = wkeep;
     s_upper[wv] = wup;
     s_wallc[wv] = wwall;
+    s_deg[wv] = wdeg;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int tot = 0, up = 0, wc = 0;
+    int tot = 0, up = 0, wc = 0, dg = 0;
     for (int k = 0; k < kWavesPerBlock; ++k) {
       s_base[k] = tot;
       tot += s_keep[k];
       up += s_upper[k];
       wc += s_wallc[k];
+      dg = max(dg, s_deg[k]);
     }
     int b = tot ? atomicAdd(&cnt->work, tot) : 0;
     if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
     for (int k = 0; k < kWavesPerBlock; ++k) s_base[k] += b;
     stat_nbr[kStatNbrWords * blockIdx.x] = up;
     stat_nbr[kStatNbrWords * blockIdx.x + 1] = wc;
+    stat_nbr[kStatNbrWords * blockIdx.x + 2] = dg;
     s_keep[0] = b + tot <= d.cap_work;
   }
   __syncthreads();

@@ -55,7 +55,8 @@ class lub_stats_t(C.Structure):
                 ("fallbacks", C.c_int64), ("newton_iters", C.c_int64),
                 ("newton_max", C.c_int32), ("error", C.c_int32),
                 ("iter_hist", C.c_int64 * 32), ("timed_calls", C.c_int64),
-                ("stage_ms", C.c_double * 4), ("warm_seeded", C.c_int64)]
+                ("stage_ms", C.c_double * 4), ("warm_seeded", C.c_int64),
+                ("max_degree", C.c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_

@@ -293,3 +293,40 @@ def config3(seed: int = 0, n: int = 65536, phi: float = 0.4,
                               phi=float(np.sum(4.0 / 3.0 * np.pi * semi[:, 0]
                                                * semi[:, 1] ** 2)) / Lx ** 3,
                               rsa_trials=trials, placed=m))
+
+
+def config5(seed: int = 0, tiles: int = 8, n_tile: int = 16384, side: float = 2048.0,
+            phi: float = 0.4) -> Workload:
+    """Full-scale suspension: tiles x tiles x n_tile (default 1,048,576)
+    spheroids with aspect ratio log-uniform in [1/4, 4] and equatorial
+    semi-axis uniform in [4, 8], in a side x side x L box, periodic in x and
+    y, walls at z = 0 and z = L, shear velocities.
+
+    One periodic tile (side/tiles across, height from the volume fraction)
+    is filled by random sequential addition, largest first; the box is
+    tiles x tiles copies of it side by side, which overlap nowhere because
+    the tile is periodic in x and y.  Random sequential addition jams below
+    volume fraction 0.5 for these shapes, so the default is 0.4 (L = 850 at
+    the default sizes)."""
+    g_pos, g_shape, g_vel, _ = _streams(seed)
+    semi_t = polydisperse_semi(g_shape, n_tile, 0.25, 4.0, 4.0, 8.0)
+    order = np.argsort(-semi_t.max(axis=1), kind="stable")
+    semi_t = semi_t[order]
+    t = side / tiles
+    vol = float(np.sum(4.0 / 3.0 * np.pi * semi_t[:, 0] * semi_t[:, 1] ** 2))
+    Lz = vol / (phi * t * t)
+    r_t, q_t, trials = rsa(g_pos, semi_t, (t, t, Lz), (1, 1, 0), max_trials=400 * n_tile)
+    if r_t.shape[0] != n_tile:
+        raise RuntimeError("config5: random sequential addition ran out of trials")
+    shifts = np.array([(ix * t, iy * t, 0.0) for iy in range(tiles) for ix in range(tiles)])
+    r = (r_t[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    q = np.tile(q_t, (tiles * tiles, 1))
+    semi = np.tile(semi_t, (tiles * tiles, 1))
+    v, w = shear_velocities(g_vel, r)
+    gd = 1e-3
+    n = r.shape[0]
+    return Workload(f"fullscale{n}_walls_phi{phi}", r, q, semi, v, w, (side, side, Lz),
+                    (1, 1, 0), n_walls=2,
+                    wall_vel=((0.0, 0.0, 0.0), (gd * Lz, 0.0, 0.0)),
+                    meta=dict(phi=phi, tiles=tiles, n_tile=n_tile, tile=t,
+                              rsa_trials=trials))

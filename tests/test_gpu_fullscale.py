@@ -1,0 +1,89 @@
+"""GPU parity at full scale: 1,048,576 polydisperse spheroids (aspect ratio
+log-uniform in [1/4, 4], R_perp in [4, 8]) between walls, checked on a 1%
+sample of particles, the part of the system the oracle can evaluate one by
+one:
+
+* the candidate partners of every sampled particle, bit for bit (the
+  oracle's brute-force search over all particles);
+* every pair touching a sampled particle against the oracle's evaluation
+  of that pair (mixed-precision bar, h/a >= 1e-3);
+* the per-particle force and torque of the sampled particles against the
+  oracle's sums (contribution-scale bar).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1308_6482_amd import lub as L  # noqa: E402
+from paper_1308_6482_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+@pytest.mark.timeout(900)
+def test_fullscale_sampled(ref):
+    wl = W.config5()
+    print(f"[gpu] {wl.name} n={wl.n} box={wl.L}", flush=True)
+    lb = L.Lub.for_workload(wl, precision=L.LUB_MIXED)
+    f, t = lb.compute(*L.to_device(wl))
+    torch.cuda.synchronize()
+    st = lb.stats()
+    print(f"candidates={st['candidates']} evaluated={st['evaluated']} active={st['active']} "
+          f"max_degree={st['max_degree']}", flush=True)
+    gp, gw = lb.pairs()
+    res = lb.pair_results()
+    lb.close()
+    f, t = f.cpu().numpy(), t.cpu().numpy()
+    dom = ref.make_domain(**wl.domain())
+    P = ref.make_params(**wl.params)
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(wl.n, size=wl.n // 100, replace=False))
+    # candidate partners of the sample, bit for bit
+    parts = ref.partners_subset(wl.r, wl.semi, dom, P, idx)
+    keep = np.zeros(wl.n, dtype=bool)
+    keep[idx] = True
+    sel = keep[gp[:, 0]] | keep[gp[:, 1]]
+    gsub = gp[sel]
+    osub = sorted({(min(int(k), int(j)), max(int(k), int(j)))
+                   for k, pk in zip(idx, parts) for j in pk})
+    assert np.array_equal(gsub, np.array(osub, dtype=np.int32).reshape(-1, 2))
+    # every pair touching the sample
+    ij = res["ij"]
+    sel = keep[ij[:, 0]] | ((ij[:, 1] >= 0) & keep[np.maximum(ij[:, 1], 0)])
+    ij = ij[sel]
+    F, Ti, Tj, h, status = ref.eval_pairs(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, ij)
+    act = status == ref.REFP_ACTIVE
+    assert np.array_equal(res["status"][sel] == 0, act)
+    i, j = ij[:, 0], ij[:, 1]
+    a = wl.semi[i].min(axis=1)
+    a = np.where(j >= 0, np.minimum(a, wl.semi[np.maximum(j, 0)].min(axis=1)), a)
+    nF = np.linalg.norm(F, axis=1)
+    gate = act & (h / a >= 1e-3)
+    eF = np.linalg.norm(res["F"][sel] - F, axis=1)[gate] / nF[gate]
+    sT = np.maximum(np.linalg.norm(Ti, axis=1), a * nF)[gate]
+    eT = np.linalg.norm(res["Ti"][sel] - Ti, axis=1)[gate] / sT
+    print(f"sample pairs={len(ij)} active={act.sum()} max eF={eF.max():.3e} "
+          f"eT={eT.max():.3e}", flush=True)
+    assert eF.max() < 1e-5 and eT.max() < 1e-5
+    # per-particle sums of the sample
+    fo, to, _ = ref.compute_subset(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, idx)
+    sf = np.zeros(wl.n)
+    stq = np.zeros(wl.n)
+    np.add.at(sf, i, nF)
+    np.add.at(stq, i, np.maximum(np.linalg.norm(Ti, axis=1), a * nF))
+    m = j >= 0
+    np.add.at(sf, j[m], nF[m])
+    np.add.at(stq, j[m], np.maximum(np.linalg.norm(Tj[m], axis=1), a[m] * nF[m]))
+    ef = np.linalg.norm(f[idx] - fo, axis=1) / np.maximum(
+        np.maximum(np.linalg.norm(fo, axis=1), sf[idx]), 1e-300)
+    et = np.linalg.norm(t[idx] - to, axis=1) / np.maximum(
+        np.maximum(np.linalg.norm(to, axis=1), stq[idx]), 1e-300)
+    print(f"sample particles max f={ef.max():.3e} t={et.max():.3e}")
+    assert ef.max() < 1e-5 and et.max() < 1e-5

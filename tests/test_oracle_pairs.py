@@ -126,3 +126,17 @@ def test_config2_statistics(ref):
     assert h.min() > 0          # placement never overlaps
     active = np.sum(status == ref.REFP_ACTIVE)
     assert 0.5 * w.n < active < 4 * w.n
+
+
+def test_partners_subset_equals_pair_set(ref):
+    """The per-particle partner lists (used on samples of systems too large
+    for the full pair set) give back the full candidate set."""
+    from paper_1308_6482_amd import workloads as W
+    for wl in (W.config1(), W.config3(n=600)):
+        dom = ref.make_domain(**wl.domain())
+        P = ref.make_params(**wl.params)
+        ij, _ = ref.candidates(wl.r, wl.semi, dom, P)
+        parts = ref.partners_subset(wl.r, wl.semi, dom, P, np.arange(wl.n))
+        pairs = sorted({(min(k, int(j)), max(k, int(j))) for k in range(wl.n)
+                        for j in parts[k]})
+        assert np.array_equal(np.array(pairs, dtype=np.int32).reshape(-1, 2), ij)
