@@ -175,7 +175,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
       (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->kin, need)) ||
       (rc = realloc_buf(&c->pos, need)) ||
       (rc = realloc_buf(&c->scat, need)) ||
-      (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks((int)need))) ||
+      (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks_max((int)need))) ||
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
     return rc;
   c->cap_n = need;
@@ -279,6 +279,9 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->max_nbr = c->cur_nbr;
   d->precision = c->opt.precision;
   d->model = c->prm.model;
+  // two size classes with cells of their own: a particle searches the small
+  // ones within its own size + r_small + the cut-off only
+  d->r_small = 0.5 * c->opt.rmax_bound;
   return LUB_OK;
 }
 
@@ -334,7 +337,7 @@ int run(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
 int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
              const double* semi, const double* v, const double* w, double* f,
              double* t, hipStream_t s) {
-  int ncell = d.nc[0] * d.nc[1] * d.nc[2];
+  const int ncell = 2 * d.nc[0] * d.nc[1] * d.nc[2];  // bins: two size classes
   std::vector<hipEvent_t> ev;
   const bool timing = c->opt.timing && d.n > 0;
   if (timing) {
@@ -642,7 +645,7 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   CallDesc d;
   int rc = build_desc(h, n, &d);
   if (rc) return rc;
-  int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+  int64_t ncell = 2 * (int64_t)d.nc[0] * d.nc[1] * d.nc[2];  // bins: two size classes
   if ((rc = ensure_particles(h, n))) return rc;
   if ((rc = ensure_cells(h, ncell))) return rc;
   // scan scratch: one block sum per 8192 elements of the longer scan

@@ -193,7 +193,7 @@ void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_p
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_stats_reduce, dim3(kStatPairWords + kStatNbrWords),
                      dim3(kReduceThreads), 0, s, cnt, stat_pair, pair_grid(d), stat_nbr,
-                     nbr_blocks(d.n), d.cap_work);
+                     nbr_blocks(d), d.cap_work);
 }
 
 }  // namespace lub

@@ -68,6 +68,7 @@ struct CallDesc {
   int32_t reach_max;    // cells searched on each side at most (cells are at
                         // least 1/reach_max of the largest pair bound)
   int32_t model;        // LUB_MODEL_*
+  double r_small;       // size classes: R_max <= r_small is small (own cells)
   int64_t warm_mask;    // warm start: hash table size - 1; 0 = off
   int32_t periodic[3];
   int32_t n_walls;
@@ -182,8 +183,11 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
 
 // grid of the pair kernel for a given slot capacity
 int pair_grid(const CallDesc& d);
-// neighbour-kernel blocks for n particles
-int nbr_blocks(int n);
+// neighbour kernel: lanes per particle, blocks of a call, and the most
+// blocks n particles can need
+int nbr_group(const CallDesc& d);
+int nbr_blocks(const CallDesc& d);
+int nbr_blocks_max(int n);
 // sum the per-block partial statistics of the last call into `cnt`
 void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_pair,
                          const int64_t* stat_nbr, hipStream_t s);

@@ -26,7 +26,7 @@ namespace {
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 8;                             // per thread and chunk
 constexpr int kScanChunk = kScanThreads * kScanItems;     // staged through LDS
-constexpr int kScanTile = 8 * kScanChunk;                 // one block: 65536 cells
+constexpr int kScanTile = kScanChunk;                     // one block per tile
 
 __device__ __forceinline__ int cell_coord(double x, double L, int periodic,
                                           double edge, int nc) {
@@ -118,7 +118,9 @@ __device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
   int cy = cell_coord(y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
   int cz = cell_coord(z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
   if (!ok) cx = cy = cz = 0;
-  return (cz * d.nc[1] + cy) * d.nc[0] + cx;
+  // the large particles' cells follow the small particles' cells
+  const int big = rm > d.r_small ? d.nc[0] * d.nc[1] * d.nc[2] : 0;
+  return (cz * d.nc[1] + cy) * d.nc[0] + cx + big;
 }
 
 __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
@@ -360,7 +362,7 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
   __shared__ int32_t cid_l[kSmallMaxN];            // cell of each input index
   __shared__ int32_t scat_l[kSmallMaxN];           // scatter output
   __shared__ int lds_scan[16];
-  const int ncell = d.nc[0] * d.nc[1] * d.nc[2];
+  const int ncell = 2 * d.nc[0] * d.nc[1] * d.nc[2];  // bins: two size classes
   const int tid = threadIdx.x;
   for (int i = tid; i < (int)(sizeof(Counters) / sizeof(int32_t)); i += kSmallThreads)
     reinterpret_cast<int32_t*>(cnt)[i] = 0;
@@ -414,32 +416,35 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
   }
 }
 
-// One wavefront per particle: candidate test over the 27 neighbour cells
-// (lanes over the flattened cell members), in-wave compaction with a ballot,
-// rank sort of the segment by partner index, the support-function reject
-// for the entries this particle owns (smaller input index), slot
-// assignment (one atomic per block) and the wall candidates.  Segments
-// have a fixed stride of d.max_nbr entries.
+// A group of G lanes per particle (G = 64: one wavefront; G = 32 or 16: two
+// or four particles per wavefront): candidate test over the rows of its stencil
+// (lanes over the flattened row members, G rows at a time), compaction with
+// a ballot, rank sort of the segment by partner index, the support-function
+// reject for the entries this particle owns (smaller input index), slot
+// assignment (one atomic per block) and the wall candidates.  Segments have
+// a fixed stride of d.max_nbr entries, at most 8 G.
 #ifndef LUB_NBR_WAVES
 #define LUB_NBR_WAVES 8
 #endif
 constexpr int kWavesPerBlock = LUB_NBR_WAVES;
-// at most 3 cells on each side (reach_max <= 3): 7 x 7 rows <= 64 lanes
+constexpr int kMaxPerLane = 8;  // segment entries per lane after the sort
 
-__device__ __forceinline__ int wave_prefix(unsigned long long mask, int lane) {
+__device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
+template <int G>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
-k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
-                 const int32_t* __restrict__ orig,
-                 const int32_t* __restrict__ cell_sorted,
-                 const int32_t* __restrict__ cell_start,
-                 int32_t* __restrict__ deg, int32_t* __restrict__ nbr,
-                 int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
-                 int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
-                 int64_t* __restrict__ stat_nbr, Counters* cnt) {
-  extern __shared__ int32_t lds_keys[];  // kWavesPerBlock * max_nbr
+k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
+            const int32_t* __restrict__ orig, const int32_t* __restrict__ cell_sorted,
+            const int32_t* __restrict__ cell_start, int32_t* __restrict__ deg,
+            int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
+            int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
+            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt) {
+  constexpr int kPer = 64 / G;                 // particles per wavefront
+  constexpr int kSteps = G == 64 ? 6 : (G == 32 ? 5 : 4);  // log2 G
+  constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  extern __shared__ int32_t lds_keys[];        // kWavesPerBlock * kPer * max_nbr
   __shared__ int s_keep[kWavesPerBlock];
   __shared__ int s_upper[kWavesPerBlock];
   __shared__ int s_wallc[kWavesPerBlock];
@@ -447,35 +452,31 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   __shared__ int s_deg[kWavesPerBlock];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int s = blockIdx.x * kWavesPerBlock + wv;
+  const int grp = lane / G;                    // particle of the wavefront
+  const int gl = lane % G;                     // lane within its group
+  const int gbase = grp * G;
+  const int s = (blockIdx.x * kWavesPerBlock + wv) * kPer + grp;
   const int maxn = d.max_nbr;
-  int32_t* keys = lds_keys + wv * maxn;
+  int32_t* keys = lds_keys + (wv * kPer + grp) * maxn;
   const bool live = s < d.n;
 
   int count = 0;
   int nkeep = 0, nupper = 0, nwallc = 0;
-  // entries held by this lane after the sort: entry lane + 64 k
-  constexpr int kMaxPerLane = 8;  // max_nbr <= 512
+  // entries held by this lane after the sort: entry gl + G k
   int my_key[kMaxPerLane];
   int my_keep[kMaxPerLane];
-  int wall_keep[2] = {0, 0};
+  int wall_keep = 0;
   if (live) {
     const double4 pi = pos[s];
     const double ri[3] = {pi.x, pi.y, pi.z};
     const double rmi = pi.w;
-    const int c = cell_sorted[s];
+    // bins: the cells of the small particles (R_max <= r_small), then those
+    // of the large ones
+    const int ngeo = d.nc[0] * d.nc[1] * d.nc[2];
+    const int c = cell_sorted[s] % ngeo;
     const int cx = c % d.nc[0];
     const int cy = (c / d.nc[0]) % d.nc[1];
     const int cz = c / (d.nc[0] * d.nc[1]);
-    // every partner lies within rho of this centre along each axis: at most
-    // `reach` cells away (cells are at least 1/reach_max of the largest rho)
-    const double rho = rmi + d.rmax_bound + d.dmax;
-    int reach[3], first[3], cnt3[3];
-    for (int k = 0; k < 3; ++k) reach[k] = min(d.reach_max, max(1, (int)ceil(rho / d.cell[k])));
-    axis_stencil(cx, d.nc[0], d.periodic[0], reach[0], &first[0], &cnt3[0]);
-    axis_stencil(cy, d.nc[1], d.periodic[1], reach[1], &first[1], &cnt3[1]);
-    axis_stencil(cz, d.nc[2], d.periodic[2], reach[2], &first[2], &cnt3[2]);
-    const int nrows = cnt3[1] * cnt3[2];
     // this centre relative to the lower corner of its cell (the wrap of the
     // binning on periodic axes)
     double f3[3];
@@ -485,99 +486,118 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       if (d.periodic[k]) x = x - d.L[k] * floor(x / d.L[k]);
       f3[k] = x - c3[k] * d.cell[k];
     }
-    // an axis taken whole (periodic, shorter than the stencil) is not pruned
-    bool whole[3];
-    for (int k = 0; k < 3; ++k) whole[k] = d.periodic[k] && cnt3[k] == d.nc[k];
-    // lane u < nrows owns the row of cells (y, z) of the stencil.  Rows
-    // farther than rho from the centre hold no candidate; in the others the
-    // cells along x are cut to the chord of the sphere of radius rho.  What
-    // is left is one contiguous range of cell-ordered particles, or two when
-    // it wraps around a periodic axis
-    int s0 = 0, n0 = 0, s1 = 0, n1 = 0;
-    if (lane < nrows) {
-      const int oy = first[1] + lane % cnt3[1] - cy;  // offsets from this cell
-      const int oz = first[2] + lane / cnt3[1] - cz;
-      const double gy = whole[1] ? 0.0 : axis_gap(oy, f3[1], d.cell[1]);
-      const double gz = whole[2] ? 0.0 : axis_gap(oz, f3[2], d.cell[2]);
-      const double rem = rho * rho - gy * gy - gz * gz;
-      int a0 = first[0], a1 = first[0] + cnt3[0] - 1;  // cells a0..a1 along x
-      if (!whole[0]) {
-        const double wx = sqrt(fmax(rem, 0.0)) * (1.0 + 1e-9) + 1e-9 * d.cell[0];
-        a0 = max(a0, cx + (int)floor((f3[0] - wx) / d.cell[0]));
-        a1 = min(a1, cx + (int)floor((f3[0] + wx) / d.cell[0]));
-      }
-      if (rem > 0.0 && a1 >= a0) {
-        const int ry = wrap_cell(cy + oy, d.nc[1]);
-        const int rz = wrap_cell(cz + oz, d.nc[2]);
-        const int rowbase = (rz * d.nc[1] + ry) * d.nc[0];
-        // the part inside [0, nc) and the part wrapped around (the range is
-        // shorter than the axis, so at most one side wraps)
-        const int nx = d.nc[0];
-        const int p0 = max(a0, 0), p1 = min(a1, nx - 1);
-        int b0 = 0, b1 = -1;
-        if (a0 < 0) {
-          b0 = a0 + nx;
-          b1 = min(a1, -1) + nx;
-        } else if (a1 >= nx) {
-          b0 = max(a0, nx) - nx;
-          b1 = a1 - nx;
+    for (int cls = 0; cls < 2; ++cls) {
+      const int32_t* cs_cls = cell_start + cls * ngeo;
+      if (cs_cls[ngeo] == cs_cls[0]) continue;  // no particle of this class
+      // every partner of the class lies within rho of this centre along each
+      // axis: at most `reach` cells away (cells are at least 1/reach_max of
+      // the largest rho)
+      const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax;
+      int reach[3], first[3], cnt3[3];
+      for (int k = 0; k < 3; ++k)
+        reach[k] = min(d.reach_max, max(1, (int)ceil(rho / d.cell[k])));
+      axis_stencil(cx, d.nc[0], d.periodic[0], reach[0], &first[0], &cnt3[0]);
+      axis_stencil(cy, d.nc[1], d.periodic[1], reach[1], &first[1], &cnt3[1]);
+      axis_stencil(cz, d.nc[2], d.periodic[2], reach[2], &first[2], &cnt3[2]);
+      const int nrows = cnt3[1] * cnt3[2];
+      // an axis taken whole (periodic, shorter than the stencil) is not pruned
+      bool whole[3];
+      for (int k = 0; k < 3; ++k) whole[k] = d.periodic[k] && cnt3[k] == d.nc[k];
+      for (int row0 = 0; row0 < nrows; row0 += G) {
+        // lane gl owns row row0 + gl of the stencil (cells (y, z)).  Rows
+        // farther than rho from the centre hold no candidate; in the others
+        // the cells along x are cut to the chord of the sphere of radius
+        // rho.  What is left is one contiguous range of cell-ordered
+        // particles, or two when it wraps around a periodic axis
+        const int row = row0 + gl;
+        int s0 = 0, n0 = 0, s1 = 0, n1 = 0;
+        if (row < nrows) {
+          const int oy = first[1] + row % cnt3[1] - cy;  // offsets from this cell
+          const int oz = first[2] + row / cnt3[1] - cz;
+          const double gy = whole[1] ? 0.0 : axis_gap(oy, f3[1], d.cell[1]);
+          const double gz = whole[2] ? 0.0 : axis_gap(oz, f3[2], d.cell[2]);
+          const double rem = rho * rho - gy * gy - gz * gz;
+          int a0 = first[0], a1 = first[0] + cnt3[0] - 1;  // cells a0..a1 along x
+          if (!whole[0]) {
+            const double wx = sqrt(fmax(rem, 0.0)) * (1.0 + 1e-9) + 1e-9 * d.cell[0];
+            a0 = max(a0, cx + (int)floor((f3[0] - wx) / d.cell[0]));
+            a1 = min(a1, cx + (int)floor((f3[0] + wx) / d.cell[0]));
+          }
+          if (rem > 0.0 && a1 >= a0) {
+            const int ry = wrap_cell(cy + oy, d.nc[1]);
+            const int rz = wrap_cell(cz + oz, d.nc[2]);
+            const int rowbase = (rz * d.nc[1] + ry) * d.nc[0];
+            // the part inside [0, nc) and the part wrapped around (the range
+            // is shorter than the axis, so at most one side wraps)
+            const int nx = d.nc[0];
+            const int p0 = max(a0, 0), p1 = min(a1, nx - 1);
+            int b0 = 0, b1 = -1;
+            if (a0 < 0) {
+              b0 = a0 + nx;
+              b1 = min(a1, -1) + nx;
+            } else if (a1 >= nx) {
+              b0 = max(a0, nx) - nx;
+              b1 = a1 - nx;
+            }
+            if (p1 >= p0) {
+              s0 = cs_cls[rowbase + p0];
+              n0 = cs_cls[rowbase + p1 + 1] - s0;
+            }
+            if (b1 >= b0) {
+              s1 = cs_cls[rowbase + b0];
+              n1 = cs_cls[rowbase + b1 + 1] - s1;
+            }
+          }
         }
-        if (p1 >= p0) {
-          s0 = cell_start[rowbase + p0];
-          n0 = cell_start[rowbase + p1 + 1] - s0;
-        }
-        if (b1 >= b0) {
-          s1 = cell_start[rowbase + b0];
-          n1 = cell_start[rowbase + b1 + 1] - s1;
-        }
-      }
-    }
-    const int cn = n0 + n1;
-    int incl = cn;
+        const int cn = n0 + n1;
+        int incl = cn;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      int y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    const int total = __shfl(incl, 63, 64);
-    const int excl = incl - cn;
-    for (int base = 0; base < total; base += 64) {
-      const int idx = base + lane;
-      bool acc = false;
-      int t = -1;
-      // the row holding flattened index idx: binary search over the lanes'
-      // exclusive prefixes, every lane taking part in the shuffles
-      int lo = 0, hi = nrows - 1;
-      for (int step = 0; step < 6; ++step) {
-        int mid = (lo + hi + 1) >> 1;
-        int em = __shfl(excl, mid, 64);
-        bool up = lo < hi && em <= idx;
-        bool down = lo < hi && !(em <= idx);
-        lo = up ? mid : lo;
-        hi = down ? mid - 1 : hi;
+        for (int o = 1; o < G; o <<= 1) {
+          int y = __shfl_up(incl, o, G);
+          if (gl >= o) incl += y;
+        }
+        const int total = __shfl(incl, gbase + G - 1, 64);
+        const int excl = incl - cn;
+        const int nlanes = min(G, nrows - row0);
+        for (int base = 0; base < total; base += G) {
+          const int idx = base + gl;
+          bool acc = false;
+          int t = -1;
+          // the row holding flattened index idx: binary search over the
+          // group's exclusive prefixes, every lane of the group taking part
+          int lo = 0, hi = nlanes - 1;
+          for (int step = 0; step < kSteps; ++step) {
+            int mid = (lo + hi + 1) >> 1;
+            int em = __shfl(excl, gbase + mid, 64);
+            bool up = lo < hi && em <= idx;
+            bool down = lo < hi && !(em <= idx);
+            lo = up ? mid : lo;
+            hi = down ? mid - 1 : hi;
+          }
+          const int r0 = __shfl(s0, gbase + lo, 64);
+          const int rn0 = __shfl(n0, gbase + lo, 64);
+          const int r1 = __shfl(s1, gbase + lo, 64);
+          const int ex = __shfl(excl, gbase + lo, 64);
+          if (idx < total) {
+            const int off = idx - ex;
+            t = off < rn0 ? r0 + off : r1 + (off - rn0);
+            const double4 pj = pos[t];
+            const double rj[3] = {pj.x, pj.y, pj.z};
+            acc = t != s && centre_test(ri, rj, rmi, pj.w, d);
+          }
+          const unsigned long long m = (__ballot(acc) >> gbase) & kGroupMask;
+          if (acc) {
+            const int at = count + lane_prefix(m, gl);
+            if (at < maxn) keys[at] = t;
+          }
+          count += __popcll(m);
+        }
       }
-      const int r0 = __shfl(s0, lo, 64);
-      const int rn0 = __shfl(n0, lo, 64);
-      const int r1 = __shfl(s1, lo, 64);
-      const int ex = __shfl(excl, lo, 64);
-      if (idx < total) {
-        const int off = idx - ex;
-        t = off < rn0 ? r0 + off : r1 + (off - rn0);
-        const double4 pj = pos[t];
-        const double rj[3] = {pj.x, pj.y, pj.z};
-        acc = t != s && centre_test(ri, rj, rmi, pj.w, d);
-      }
-      unsigned long long m = __ballot(acc);
-      if (acc) {
-        const int at = count + wave_prefix(m, lane);
-        if (at < maxn) keys[at] = t;
-      }
-      count += __popcll(m);
     }
   }
   __syncthreads();
-  bool overflow = live && count > maxn;
-  if (overflow && lane == 0) set_error(cnt, LUB_ECAPACITY);
+  const bool overflow = live && count > maxn;
+  if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
   const int nent = (live && !overflow) ? count : 0;
   // rank sort: keys are distinct partner indices
   const int me = live ? orig[s] : 0;
@@ -591,7 +611,7 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   for (int k = 0; k < kMaxPerLane; ++k) {
     my_key[k] = -1;
     my_keep[k] = 0;
-    const int e = lane + 64 * k;
+    const int e = gl + G * k;
     if (e >= nent) continue;
     const int key = keys[e];
     int rank = 0;
@@ -616,7 +636,6 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
         double g = dn - support(Mi, ux, uy, uz) - support(rec[key].M, ux, uy, uz);
         keep = g < d.dmax;
       }
-      my_keep[k] = keep ? 1 : 0;
       slot[(size_t)s * maxn + rank] = -1;
       if (keep) {
         my_keep[k] = 1 + rank;  // remember the rank for the slot write
@@ -626,26 +645,27 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       slot[(size_t)s * maxn + rank] = -2;
     }
   }
-  if (live && d.n_walls && lane < 2) {
-    const int side = lane;
+  if (live && d.n_walls && gl < 2) {
+    const int side = gl;
     double dist = side == 0 ? rs[2] : d.L[2] - rs[2];
     bool cand = (dist - rec[s].Rmax) < d.dmax;
     bool keep = cand && (dist - sqrt(Mi[5])) < d.dmax;
     nwallc += cand;
-    wall_keep[0] = keep;
+    wall_keep = keep;
     nkeep += keep;
     // -3: candidate beyond every cut-off, -1: no candidate
     wall_slot[2 * s + side] = keep ? 0 : (cand ? -3 : -1);
   }
-  if (live) deg[s] = nent;
+  if (live && gl == 0) deg[s] = nent;
   // wave totals -> block total -> one atomic per block
   int wkeep = nkeep, wup = nupper, wwall = nwallc;
-  const int wdeg = live ? count : 0;  // uniform in the wave
+  int wdeg = live ? count : 0;  // uniform in each group
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     wkeep += __shfl_xor(wkeep, o, 64);
     wup += __shfl_xor(wup, o, 64);
     wwall += __shfl_xor(wwall, o, 64);
+    wdeg = max(wdeg, __shfl_xor(wdeg, o, 64));
   }
   if (lane == 0) {
     s_keep[wv] = wkeep;
@@ -690,10 +710,10 @@ k_neighbors_wave(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
     work_t[next] = my_key[k];
     ++next;
   }
-  if (d.n_walls && lane < 2 && wall_keep[0]) {
-    wall_slot[2 * s + lane] = next;
+  if (d.n_walls && gl < 2 && wall_keep) {
+    wall_slot[2 * s + gl] = next;
     work_s[next] = s;
-    work_t[next] = -1 - lane;
+    work_t[next] = -1 - gl;
     ++next;
   }
 }
@@ -751,8 +771,8 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
 }
 
 bool cells_small_fits(const CallDesc& d) {
-  const int64_t ncell = (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
-  return d.n <= kSmallMaxN && ncell <= kSmallMaxCells;
+  const int64_t nbins = 2 * (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+  return d.n <= kSmallMaxN && nbins <= kSmallMaxCells;
 }
 
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
@@ -770,13 +790,33 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
-  dim3 grid(nbr_blocks(d.n));
-  size_t lds = sizeof(int32_t) * kWavesPerBlock * (size_t)d.max_nbr;
-  hipLaunchKernelGGL(k_neighbors_wave, grid, dim3(64 * kWavesPerBlock), lds, s,
-                     d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
-                     wall_slot, work_s, work_t, stat_nbr, cnt);
+  dim3 grid(nbr_blocks(d));
+  size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
+  if (nbr_group(d) == 16)
+    hipLaunchKernelGGL(k_neighbors<16>, grid, dim3(64 * kWavesPerBlock), lds, s,
+                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
+                       wall_slot, work_s, work_t, stat_nbr, cnt);
+  else if (nbr_group(d) == 32)
+    hipLaunchKernelGGL(k_neighbors<32>, grid, dim3(64 * kWavesPerBlock), lds, s,
+                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
+                       wall_slot, work_s, work_t, stat_nbr, cnt);
+  else
+    hipLaunchKernelGGL(k_neighbors<64>, grid, dim3(64 * kWavesPerBlock), lds, s,
+                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
+                       wall_slot, work_s, work_t, stat_nbr, cnt);
 }
 
-int nbr_blocks(int n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
+// lanes per particle: the smallest group whose lanes hold the segment at 8
+// entries per lane
+int nbr_group(const CallDesc& d) {
+  return d.max_nbr <= 8 * 16 ? 16 : (d.max_nbr <= 8 * 32 ? 32 : 64);
+}
+
+int nbr_blocks(const CallDesc& d) {
+  const int per_block = kWavesPerBlock * 64 / nbr_group(d);
+  return (d.n + per_block - 1) / per_block;
+}
+
+int nbr_blocks_max(int n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
 
 }  // namespace lub

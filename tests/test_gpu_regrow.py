@@ -138,3 +138,24 @@ def test_handle_reuse_growing_n(ref, seed_mode):
         print(f"n={wl.n} max rel err f={ef:.3e} t={et:.3e}")
         assert ef < 1e-9 and et < 1e-9
     lb.close()
+
+
+@pytest.mark.parametrize("max_neighbors", [128, 192, 320])
+def test_neighbour_group_sizes(ref, max_neighbors):
+    """The neighbour kernel's lanes per particle follow the segment size
+    (16 up to 128 entries, 32 up to 256, a whole wavefront above): the same
+    system with each, against the oracle's pair set and forces."""
+    wl = W.config3(n=3000)
+    print(f"[gpu] polydisperse3000 max_neighbors={max_neighbors}", flush=True)
+    dom = ref.make_domain(**wl.domain())
+    P = ref.make_params(**wl.params)
+    fo, to, _ = ref.compute(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P)
+    ij, walls = ref.candidates(wl.r, wl.semi, dom, P)
+    lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, max_neighbors=max_neighbors)
+    f, t = lb.compute(*L.to_device(wl))
+    torch.cuda.synchronize()
+    gp, gw = lb.pairs()
+    lb.close()
+    assert np.array_equal(gp, ij) and np.array_equal(gw, walls)
+    assert rel_particle_error(f.cpu().numpy(), fo) < 1e-9
+    assert rel_particle_error(t.cpu().numpy(), to) < 1e-9
