@@ -81,11 +81,16 @@ extern "C" {
  *                     wall): force along the line of centres, no torque.
  *                     Every particle must be a sphere (R_par == R_perp),
  *                     else LUB_EINVAL.
- * The reduced models act below delta_n only; all three clip the gap at h_c
- * and add the contact force of Eq. lub:frep. */
+ *   LUB_MODEL_CONTACT no lubrication: the Hookean repulsion of Eq. lub:frep
+ *                     alone, acting for h <= h_c (needs h_c > 0).  The
+ *                     interaction of the growth stage of the packing
+ *                     generator (Sec. IV.A).
+ * The reduced models act below delta_n only; the first three clip the gap
+ * at h_c and add the contact force of Eq. lub:frep. */
 #define LUB_MODEL_FULL 0
 #define LUB_MODEL_NORMAL 1
 #define LUB_MODEL_LADD 2
+#define LUB_MODEL_CONTACT 3
 
 typedef struct {
   double mu;       /* dynamic viscosity */
@@ -104,6 +109,18 @@ typedef struct {
   int32_t periodic[3];     /* 1: periodic (minimum image), 0: bounded */
   int32_t n_walls;         /* 0, or 2: planar walls z = 0 and z = L[2] (needs periodic[2] = 0) */
   double wall_vel[2][3];   /* translational velocity of each wall */
+  /* Lees-Edwards images for a sheared periodic box (Sec. IV.A): with */
+  /* lees_edwards = 1 the image one box up in z of a particle at r with */
+  /* velocity v sits at r + (le_offset, 0, L_z) and moves with */
+  /* v + (le_velocity, 0, 0); for a shear rate g at time t, le_velocity = */
+  /* g L_z and le_offset = g L_z t (any value; taken modulo L_x).  Needs all */
+  /* three axes periodic and no walls (else LUB_EINVAL).  The nearest image */
+  /* is chosen in z first, then in x and y.  In graph mode a new offset */
+  /* captures the launch sequence again. */
+  int32_t lees_edwards;    /* 0 or 1 */
+  int32_t reserved;        /* must be 0 */
+  double le_offset;
+  double le_velocity;
 } lub_domain_t;
 
 /* Library options. */
@@ -111,7 +128,11 @@ typedef struct {
   int32_t device;          /* HIP device ordinal */
   int32_t precision;       /* LUB_FP64 or LUB_MIXED */
   int32_t seed_mode;       /* LUB_SEED_PLAIN or LUB_SEED_MLP */
-  int32_t newton_max_iter; /* iteration limit of the closest-point solve (<=0: 50) */
+  int32_t newton_max_iter; /* iteration limit of the closest-point solve (<=0: 50); */
+                           /* a pair whose Newton solve fails from every start */
+                           /* falls back to the tangent-sphere iteration of */
+                           /* Sec. III.A (N1 = 10 local, N2 = 1000 conservative) */
+                           /* and a polish of max(limit, 8) Newton iterations */
   double rmax_bound;       /* upper bound of max(R_par, R_perp) over all particles; */
                            /* sizes the cell grid.  A larger particle is LUB_EINVAL */
   int32_t sync;            /* 1: lub_compute waits for the stream and reports input, */
@@ -150,7 +171,9 @@ typedef struct {
   int64_t overlaps;         /* active pairs with h <= 0 */
   int64_t unresolved;       /* h <= 0 with h_c = 0: skipped */
   int64_t unconverged;      /* closest-point solve failed: skipped */
-  int64_t fallbacks;        /* learned or previous-call seed rejected, plain seed used */
+  int64_t fallbacks;        /* pairs whose first start failed: a learned or previous- */
+                            /* call seed rejected (plain start used), or the */
+                            /* tangent-sphere fallback taken */
   int64_t newton_iters;     /* total Newton iterations */
   int32_t newton_max;       /* largest per-pair iteration count */
   int32_t error;            /* LUB_OK or the error found by the last call */
@@ -164,6 +187,8 @@ typedef struct {
   int64_t warm_seeded;      /* pairs started from the previous call's solution */
   int64_t max_degree;       /* most candidate partners of one particle (also when it */
                             /* exceeded max_neighbors: the value to set) */
+  double pair_kernel_ms;    /* with opts.timing: the pair kernel's own execution */
+                            /* time (dispatch timestamps), summed like stage_ms */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;
@@ -182,6 +207,66 @@ int lub_set_domain(lub_handle_t h, const lub_domain_t* domain);
 int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
                 const double* semi, const double* v, const double* w,
                 double* f, double* t, void* stream);
+
+/* The handle's current domain (lub_integrate advances the Lees-Edwards
+ * offset). */
+int lub_get_domain(lub_handle_t h, lub_domain_t* out);
+
+/* Sub-stepped explicit particle update (Sec. II): the particle time step is
+ * decoupled from the fluid's and made a fraction of it (typically a tenth);
+ * the hydrodynamic force from the fluid stays fixed over the fluid step
+ * while the lubrication and contact forces are evaluated again at every
+ * sub-step.  One call runs step->n_sub sub-steps of length step->dt; each
+ * evaluates lub_compute on the current state and then, per particle (mass
+ * m = density 4/3 pi R_par R_perp^2, body inertia I_par = 2/5 m R_perp^2 about
+ * the axis and I_perp = 1/5 m (R_par^2 + R_perp^2) across it):
+ *   F = f_ext + f,  T = t_ext + t
+ *   v <- v + dt (F / m - damping v)
+ *   L = I(q) w;  L <- L + dt (T - damping L)
+ *   q <- rotation by the angle |I(q)^-1 L| dt about I(q)^-1 L, then q
+ *   r <- r + dt v;  w <- I(q)^-1 L with the new q
+ * (semi-implicit Euler, angular momentum in the world frame).  Periodic
+ * axes are wrapped into [0, L); with Lees-Edwards images the offset
+ * advances by le_velocity dt per sub-step and a particle leaving through
+ * z = L_z (z = 0) re-enters shifted by -offset (+offset) in x with its x
+ * velocity reduced (raised) by le_velocity.
+ * r, q, v, w: device arrays updated in place.  f_ext, t_ext: device arrays
+ * or NULL (zero).  f, t: device arrays receiving the last sub-step's
+ * lubrication force and torque.  Errors as lub_compute (the state is left
+ * after the last completed sub-step); LUB_EINVAL for dt <= 0, n_sub < 1,
+ * density <= 0, damping < 0 or reserved != 0. */
+typedef struct {
+  double dt;        /* sub-step length */
+  int32_t n_sub;    /* sub-steps per call */
+  int32_t reserved; /* must be 0 */
+  double density;   /* particle mass density */
+  double damping;   /* velocity damping rate (1/time); 0 for plain dynamics */
+} lub_step_t;
+
+int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
+                  double* v, double* w, const double* f_ext, const double* t_ext,
+                  double* f, double* t, const lub_step_t* step, void* stream);
+
+/* Growth stage of the packing generator (Sec. IV.A): particles placed
+ * without overlap at a reduced size grow linearly from scale0 to scale1
+ * times their semi-axes over n_steps sub-steps (scale1 slightly above 1
+ * leaves a minimum separation once the size is reset), free to move and
+ * turn, with the contact repulsion of Eq. lub:frep (stiffness eps_c, range
+ * h_c) as the only interaction and velocities damped at rate damping.  The
+ * handle's resistance law and clipping are set aside for the call (model
+ * LUB_MODEL_CONTACT with the given h_c, eps_c) and restored afterwards.
+ * r, q, v, w: device arrays updated in place; semi: the final semi-axes
+ * (not modified).  Needs opts.rmax_bound >= scale1 max(R_par, R_perp). */
+typedef struct {
+  int32_t n_steps;
+  int32_t reserved; /* must be 0 */
+  double scale0, scale1;
+  double dt, density, damping;
+  double h_c, eps_c;
+} lub_grow_t;
+
+int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
+             double* v, double* w, const lub_grow_t* cfg, void* stream);
 
 /* Statistics of the last call (waits for the handle's last stream). */
 int lub_get_stats(lub_handle_t h, lub_stats_t* out);

@@ -34,7 +34,7 @@ def build(force: bool = True) -> str:
     return _SO
 
 
-MODEL_FULL, MODEL_NORMAL, MODEL_LADD = 0, 1, 2
+MODEL_FULL, MODEL_NORMAL, MODEL_LADD, MODEL_CONTACT = 0, 1, 2, 3
 
 
 class Params(C.Structure):
@@ -46,7 +46,9 @@ class Params(C.Structure):
 
 class Domain(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("periodic", C.c_int32 * 3),
-                ("n_walls", C.c_int32), ("wall_vel", (C.c_double * 3) * 2)]
+                ("n_walls", C.c_int32), ("wall_vel", (C.c_double * 3) * 2),
+                ("lees_edwards", C.c_int32), ("reserved", C.c_int32),
+                ("le_offset", C.c_double), ("le_velocity", C.c_double)]
 
 
 class PairResult(C.Structure):
@@ -149,7 +151,9 @@ def make_params(mu=1.0 / 6.0, delta_n=2.0 / 3.0, delta_t=0.5, delta_r=0.25,
 
 
 def make_domain(L=(1e9, 1e9, 1e9), periodic=(0, 0, 0), n_walls=0,
-                wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))) -> Domain:
+                wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)), lees_edwards=None) -> Domain:
+    """lees_edwards: None, or (offset, velocity) of the image one box up in z
+    (Lees-Edwards images of a sheared periodic box)."""
     d = Domain()
     for k in range(3):
         d.L[k] = float(L[k])
@@ -158,6 +162,10 @@ def make_domain(L=(1e9, 1e9, 1e9), periodic=(0, 0, 0), n_walls=0,
     for s in range(2):
         for k in range(3):
             d.wall_vel[s][k] = float(wall_vel[s][k])
+    if lees_edwards is not None:
+        d.lees_edwards = 1
+        d.le_offset = float(lees_edwards[0])
+        d.le_velocity = float(lees_edwards[1])
     return d
 
 

@@ -552,6 +552,7 @@ static double cutoff(int r, int c, const ref_params* p) {
 }
 
 static double max_cutoff(const ref_params* p) {
+  if (p->model == REF_MODEL_CONTACT) return p->h_c;   /* the repulsion's range */
   if (p->model != REF_MODEL_FULL) return p->delta_n;  /* only the normal element */
   double m = p->delta_n;
   if (p->delta_t > m) m = p->delta_t;
@@ -575,7 +576,7 @@ static void resistance_and_transfer(const body* bi, const body* bj,
   memset(o->Kt, 0, sizeof(o->Kt));
   memset(o->C, 0, sizeof(o->C));
   memset(o->Fbar, 0, sizeof(o->Fbar));
-  if (heff >= hmax) {
+  if (heff >= hmax && h > prm->h_c) {
     o->status = REFP_INACTIVE;
     return;
   }
@@ -650,6 +651,7 @@ static void resistance_and_transfer(const body* bi, const body* bj,
       double D = cutoff(r, c, prm);
       if (!(heff < D)) continue;
       if (prm->model == REF_MODEL_NORMAL && !(r == 2 && c == 2)) continue;
+      if (prm->model == REF_MODEL_CONTACT) continue;
       if (r == 2 && c == 2)
         o->Kt[r][c] = o->C[r][c] * (1.0 / heff - 1.0 / D);
       else
@@ -820,11 +822,38 @@ static double min_image(double dx, double L, int periodic) {
   return dx;
 }
 
+/* Offset from i to the nearest image of j.  With Lees-Edwards images the
+ * z image is chosen first; taking m boxes down in z moves the image by
+ * -m le_offset in x (and its velocity by -m le_velocity), and x is then
+ * wrapped as usual.  The offset is used modulo L_x, in [0, L_x).  Returns m
+ * (0 without Lees-Edwards images). */
+static int pair_image(const double ri[3], const double rj[3], const ref_domain* dom,
+                      double d[3]) {
+  int m = 0;
+  double dx = rj[0] - ri[0];
+  double dz = rj[2] - ri[2];
+  if (dom->lees_edwards) {
+    double c = nearbyint(dz / dom->L[2]);
+    m = (int)c;
+    dz = dz - dom->L[2] * c;
+    double off = fmod(dom->le_offset, dom->L[0]);
+    if (off < 0.0) off = off + dom->L[0];
+    double shift = c * off;
+    dx = dx - shift;
+  } else {
+    dz = min_image(dz, dom->L[2], dom->periodic[2]);
+  }
+  d[0] = min_image(dx, dom->L[0], dom->periodic[0]);
+  d[1] = min_image(rj[1] - ri[1], dom->L[1], dom->periodic[1]);
+  d[2] = dz;
+  return m;
+}
+
 int ref_centre_test(const double ri[3], const double rj[3], double rmax_i,
                     double rmax_j, double dmax, const ref_domain* dom) {
-  double dx = min_image(rj[0] - ri[0], dom->L[0], dom->periodic[0]);
-  double dy = min_image(rj[1] - ri[1], dom->L[1], dom->periodic[1]);
-  double dz = min_image(rj[2] - ri[2], dom->L[2], dom->periodic[2]);
+  double d[3];
+  pair_image(ri, rj, dom, d);
+  double dx = d[0], dy = d[1], dz = d[2];
   double d2 = dx * dx + dy * dy + dz * dz;
   double s = (rmax_i + rmax_j) + dmax;
   return d2 < s * s;
@@ -918,11 +947,6 @@ int ref_partners_subset(int64_t n, const double* r, const double* semi,
   return rc;
 }
 
-static void image_offset(const double* r, int64_t i, int64_t j,
-                         const ref_domain* dom, double d[3]) {
-  for (int k = 0; k < 3; ++k)
-    d[k] = min_image(r[3 * j + k] - r[3 * i + k], dom->L[k], dom->periodic[k]);
-}
 
 static void eval_one(int64_t n, const double* r, const double* q,
                      const double* semi, const double* v, const double* w,
@@ -931,9 +955,11 @@ static void eval_one(int64_t n, const double* r, const double* q,
   (void)n;
   if (j >= 0) {
     double d[3];
-    image_offset(r, i, j, dom, d);
+    const int m = pair_image(&r[3 * i], &r[3 * j], dom, d);
+    /* velocity of the image of j that d points to */
+    double vj[3] = {v[3 * j] - m * dom->le_velocity, v[3 * j + 1], v[3 * j + 2]};
     ref_pair_eval(d, &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i], &q[4 * j],
-                  &semi[2 * j], &v[3 * j], &w[3 * j], prm, o);
+                  &semi[2 * j], vj, &w[3 * j], prm, o);
   } else {
     ref_wall_eval(&r[3 * i], &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i],
                   -j - 1, dom, prm, o);
@@ -959,6 +985,10 @@ static int valid_inputs(int64_t n, const double* r, const double* q,
                         const ref_domain* dom, const ref_params* prm) {
   if (n < 0 || !dom || !prm) return 0;
   if (n > 0 && (!r || !q || !semi || !v || !w)) return 0;
+  if (dom->lees_edwards &&
+      (!dom->periodic[0] || !dom->periodic[1] || !dom->periodic[2] || dom->n_walls ||
+       !isfinite(dom->le_offset) || !isfinite(dom->le_velocity)))
+    return 0;
   for (int64_t i = 0; i < n; ++i) {
     for (int k = 0; k < 3; ++k)
       if (!isfinite(r[3 * i + k]) || !isfinite(v[3 * i + k]) ||

@@ -62,6 +62,7 @@ extern "C" {
 #define REF_MODEL_FULL 0
 #define REF_MODEL_NORMAL 1
 #define REF_MODEL_LADD 2
+#define REF_MODEL_CONTACT 3 /* no lubrication: the repulsion of Eq. lub:frep alone */
 
 typedef struct {
   double mu;       /* dynamic viscosity */
@@ -79,6 +80,14 @@ typedef struct {
   int32_t periodic[3];
   int32_t n_walls;          /* 0 or 2 (planes z=0 and z=L[2]) */
   double wall_vel[2][3];    /* translational velocity of each wall */
+  /* Lees-Edwards images (sheared periodic box, Sec. IV.A): the image one box
+   * up in z of a particle at r with velocity v sits at r + (le_offset, 0, L_z)
+   * and moves with v + (le_velocity, 0, 0).  Needs all axes periodic and no
+   * walls. */
+  int32_t lees_edwards;
+  int32_t reserved;
+  double le_offset;
+  double le_velocity;
 } ref_domain;
 
 typedef struct {

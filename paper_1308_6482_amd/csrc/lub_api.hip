@@ -48,6 +48,7 @@ struct lub_ctx {
   int32_t* nbr = nullptr;          // [n * cur_nbr] partner (cell order)
   int32_t* slot = nullptr;         // [n * cur_nbr] evaluation slot, -1, -2
   int32_t* work_s = nullptr;       // [work]
+  int32_t* fail_list = nullptr;    // [work] slots left to the tangent-sphere pass
   int32_t* work_t = nullptr;       // [work]
   void* out = nullptr;             // [work] PairOut<double> (or float)
   double* out_h = nullptr;         // [work]
@@ -79,6 +80,11 @@ struct lub_ctx {
   int64_t cap_seed = 0;
   float* seedX = nullptr;
   float* seedY = nullptr;
+  // growth stage: scaled semi-axes and the forces of each sub-step
+  double* grow_semi = nullptr;
+  double* grow_f = nullptr;
+  double* grow_t = nullptr;
+  int64_t cap_grow = 0;
   int adam_step = 0;
 
   // graph mode: the launch sequence of a call, captured once per counter set
@@ -93,11 +99,13 @@ struct lub_ctx {
   };
   GraphSlot graphs[2];
 
-  // stage timing: five events per timed call, resolved lazily
+  // stage timing: five stage events and the pair kernel's own start and
+  // stop per timed call, resolved lazily
   std::vector<hipEvent_t> free_events;
   std::vector<std::vector<hipEvent_t>> pending;
   int64_t timed_calls = 0;
   double stage_ms[4] = {0, 0, 0, 0};
+  double pair_kernel_ms = 0.0;
 };
 
 namespace {
@@ -141,6 +149,7 @@ int grow(T** p, int64_t* cap, int64_t need) {
 
 // candidate and activity cut-off: the reduced models act below delta_n only
 double max_cutoff(const lub_params_t& p) {
+  if (p.model == LUB_MODEL_CONTACT) return p.h_c;
   if (p.model != LUB_MODEL_FULL) return p.delta_n;
   return std::max(p.delta_n, std::max(p.delta_t, p.delta_r));
 }
@@ -150,8 +159,9 @@ int check_params(const lub_params_t* p) {
   if (!(p->mu >= 0.0) || !(p->delta_n > 0.0) || !(p->delta_t > 0.0) ||
       !(p->delta_r > 0.0) || !(p->h_c >= 0.0) || !(p->eps_c >= 0.0))
     return LUB_EINVAL;
-  if (p->model < LUB_MODEL_FULL || p->model > LUB_MODEL_LADD || p->reserved != 0)
+  if (p->model < LUB_MODEL_FULL || p->model > LUB_MODEL_CONTACT || p->reserved != 0)
     return LUB_EINVAL;
+  if (p->model == LUB_MODEL_CONTACT && !(p->h_c > 0.0)) return LUB_EINVAL;
   return LUB_OK;
 }
 
@@ -161,6 +171,12 @@ int check_domain(const lub_domain_t* d) {
     if (!(d->L[k] > 0.0) || !std::isfinite(d->L[k])) return LUB_EINVAL;
   if (d->n_walls != 0 && d->n_walls != 2) return LUB_EINVAL;
   if (d->n_walls == 2 && d->periodic[2]) return LUB_EINVAL;
+  if (d->lees_edwards != 0 && d->lees_edwards != 1) return LUB_EINVAL;
+  if (d->reserved != 0) return LUB_EINVAL;
+  if (d->lees_edwards &&
+      (!d->periodic[0] || !d->periodic[1] || !d->periodic[2] || d->n_walls != 0 ||
+       !std::isfinite(d->le_offset) || !std::isfinite(d->le_velocity)))
+    return LUB_EINVAL;
   return LUB_OK;
 }
 
@@ -210,6 +226,7 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
   if (c->cap_work < work || !c->work_s) {
     c->cap_work = 0;
     if ((rc = realloc_buf(&c->work_s, work)) || (rc = realloc_buf(&c->work_t, work)) ||
+        (rc = realloc_buf(&c->fail_list, work)) ||
         (rc = realloc_buf((PairOut<double>**)&c->out, work)) ||
         (rc = realloc_buf(&c->out_h, work)) || (rc = realloc_buf(&c->out_status, work)) ||
         (rc = realloc_buf(&c->out_iters, work)))
@@ -268,6 +285,14 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->n_walls = c->dom.n_walls;
   for (int s = 0; s < 2; ++s)
     for (int k = 0; k < 3; ++k) d->wall_vel[s][k] = c->dom.wall_vel[s][k];
+  d->le = c->dom.lees_edwards;
+  if (d->le) {
+    // the offset modulo L_x, in [0, L_x)
+    double off = std::fmod(c->dom.le_offset, d->L[0]);
+    if (off < 0.0) off = off + d->L[0];
+    d->le_offset = off;
+    d->le_vel = c->dom.le_velocity;
+  }
   d->rmax_bound = c->opt.rmax_bound;
   d->mu = c->prm.mu;
   d->delta_n = c->prm.delta_n;
@@ -305,6 +330,9 @@ int resolve_timing(lub_ctx* c) {
       HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
       c->stage_ms[k] += ms;
     }
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[5], ev[6]));
+    c->pair_kernel_ms += ms;
     c->timed_calls++;
     for (hipEvent_t e : ev) c->free_events.push_back(e);
   }
@@ -346,7 +374,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       int rc = resolve_timing(c);
       if (rc) return rc;
     }
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 7; ++k) {
       hipEvent_t e = take_event(c);
       if (!e) return LUB_EDEVICE;
       ev.push_back(e);
@@ -396,7 +424,9 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     WarmTables warm{c->warm_key[wp], c->warm_val[wp], c->warm_key[wc], c->warm_val[wc],
                     c->sorted};
     launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
-                 c->out_h, c->out_status, c->out_iters, warm, c->stat_pair, c->cnt, s);
+                 c->out_h, c->out_status, c->out_iters, warm, c->fail_list, c->stat_pair,
+                 c->cnt, s,
+                 timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
     mark(3);
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
                   c->cnt, next_cnt, d.warm_mask ? c->warm_key[wp] : nullptr,
@@ -428,8 +458,8 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
           c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->pos, c->kin,
           c->nbr,
-          c->slot, c->work_s, c->work_t, c->out, c->out_h, c->out_status, c->out_iters,
-          c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
+          c->slot, c->work_s, c->work_t, c->fail_list, c->out, c->out_h, c->out_status,
+          c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
           c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1]};
 }
 
@@ -607,7 +637,8 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     if (!rc2) rc2 = realloc_buf(&c->wt, kWtTotal);
     if (!rc2) rc2 = realloc_buf(&c->wb, kWbTotal);
     if (!rc2) rc2 = realloc_buf(&c->dloss, 64);
-    if (!rc2) rc2 = realloc_buf(&c->stat_pair, (int64_t)kStatPairWords * kMaxPairBlocks);
+    if (!rc2) rc2 = realloc_buf(&c->stat_pair,
+                                   (int64_t)kStatPairWords * (kMaxPairBlocks + kTangentBlocks));
     if (!rc2) rc2 = mlp_init_host(c, 0);
     if (rc2) {
       lub_destroy(c);
@@ -675,6 +706,103 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   return h->host_cnt->error;
 }
 
+int lub_get_domain(lub_handle_t h, lub_domain_t* out) {
+  if (!h || !out) return LUB_EINVAL;
+  *out = h->dom;
+  return LUB_OK;
+}
+
+namespace {
+
+// One sub-step: the correction on the current state, then the particle
+// update; the Lees-Edwards offset advances by le_velocity dt first, so the
+// update re-enters particles with the offset of the new time.
+int substep(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
+            double* v, double* w, const double* f_ext, const double* t_ext, double* f,
+            double* t, double dt, double density, double damping, hipStream_t s) {
+  int rc = lub_compute(h, n, r, q, semi, v, w, f, t, s);
+  if (rc) return rc;
+  if (h->dom.lees_edwards) {
+    double off = std::fmod(h->dom.le_offset + h->dom.le_velocity * dt, h->dom.L[0]);
+    if (off < 0.0) off = off + h->dom.L[0];
+    h->dom.le_offset = off;
+  }
+  StepDesc sd{};
+  sd.n = (int32_t)n;
+  for (int k = 0; k < 3; ++k) {
+    sd.periodic[k] = h->dom.periodic[k];
+    sd.L[k] = h->dom.L[k];
+  }
+  sd.le = h->dom.lees_edwards;
+  sd.le_offset = h->dom.le_offset;
+  sd.le_vel = h->dom.le_velocity;
+  sd.dt = dt;
+  sd.density = density;
+  sd.damping = damping;
+  launch_integrate(sd, r, q, semi, v, w, f_ext, t_ext, f, t, s);
+  HIP_TRY(hipGetLastError());
+  return LUB_OK;
+}
+
+}  // namespace
+
+int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
+                  double* v, double* w, const double* f_ext, const double* t_ext,
+                  double* f, double* t, const lub_step_t* step, void* stream) {
+  if (!h || !step || n < 0 || n > (int64_t)1 << 30) return LUB_EINVAL;
+  if (!(step->dt > 0.0) || !std::isfinite(step->dt) || step->n_sub < 1 ||
+      step->reserved != 0 || !(step->density > 0.0) || !std::isfinite(step->density) ||
+      !(step->damping >= 0.0) || !std::isfinite(step->damping))
+    return LUB_EINVAL;
+  if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  for (int k = 0; k < step->n_sub; ++k) {
+    int rc = substep(h, n, r, q, semi, v, w, f_ext, t_ext, f, t, step->dt, step->density,
+                     step->damping, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return LUB_OK;
+}
+
+int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
+             double* v, double* w, const lub_grow_t* cfg, void* stream) {
+  if (!h || !cfg || n < 0 || n > (int64_t)1 << 30) return LUB_EINVAL;
+  if (cfg->n_steps < 1 || cfg->reserved != 0 || !(cfg->scale0 > 0.0) ||
+      !(cfg->scale1 >= cfg->scale0) || !std::isfinite(cfg->scale1) || !(cfg->dt > 0.0) ||
+      !std::isfinite(cfg->dt) || !(cfg->density > 0.0) || !std::isfinite(cfg->density) ||
+      !(cfg->damping >= 0.0) || !std::isfinite(cfg->damping) || !(cfg->h_c > 0.0) ||
+      !(cfg->eps_c >= 0.0) || !std::isfinite(cfg->eps_c))
+    return LUB_EINVAL;
+  if (n > 0 && (!r || !q || !semi || !v || !w)) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  if (h->cap_grow < n || !h->grow_semi) {
+    h->cap_grow = 0;
+    int rc;
+    if ((rc = realloc_buf(&h->grow_semi, 2 * n)) || (rc = realloc_buf(&h->grow_f, 3 * n)) ||
+        (rc = realloc_buf(&h->grow_t, 3 * n)))
+      return rc;
+    h->cap_grow = n;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // the contact repulsion alone for the call
+  const lub_params_t saved = h->prm;
+  h->prm.model = LUB_MODEL_CONTACT;
+  h->prm.h_c = cfg->h_c;
+  h->prm.eps_c = cfg->eps_c;
+  int rc = LUB_OK;
+  for (int k = 0; k < cfg->n_steps && rc == LUB_OK; ++k) {
+    const double sc =
+        cfg->scale0 + (cfg->scale1 - cfg->scale0) * (double)(k + 1) / (double)cfg->n_steps;
+    launch_scale((int)n, semi, sc, h->grow_semi, s);
+    rc = hip_err(hipGetLastError());
+    if (rc == LUB_OK)
+      rc = substep(h, n, r, q, h->grow_semi, v, w, nullptr, nullptr, h->grow_f, h->grow_t,
+                   cfg->dt, cfg->density, cfg->damping, s);
+  }
+  h->prm = saved;
+  return rc;
+}
+
 int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   if (!h || !out) return LUB_EINVAL;
   std::memset(out, 0, sizeof(*out));
@@ -700,6 +828,7 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   if ((rc = resolve_timing(h))) return rc;
   out->timed_calls = h->timed_calls;
   for (int k = 0; k < 4; ++k) out->stage_ms[k] = h->stage_ms[k];
+  out->pair_kernel_ms = h->pair_kernel_ms;
   return LUB_OK;
 }
 
@@ -710,6 +839,7 @@ int lub_reset_timers(lub_handle_t h) {
   if (rc) return rc;
   h->timed_calls = 0;
   for (int k = 0; k < 4; ++k) h->stage_ms[k] = 0.0;
+  h->pair_kernel_ms = 0.0;
   return LUB_OK;
 }
 
@@ -902,11 +1032,12 @@ void lub_destroy(lub_handle_t h) {
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
-                  h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s,
+                  h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
                   h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
                   h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
-                  h->loss_parts, h->aT, h->dT, h->seedX, h->seedY};
+                  h->loss_parts, h->aT, h->dT, h->seedX, h->seedY, h->grow_semi,
+                  h->grow_f, h->grow_t};
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);

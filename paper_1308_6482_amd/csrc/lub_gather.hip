@@ -161,6 +161,15 @@ k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_bl
     const int64_t v = base[(int64_t)r * stride];
     acc = is_max ? max(acc, v) : acc + v;
   }
+  if (word < kStatPairWords) {
+    // the rows of the tangent-sphere pass
+    const int nfail = cnt->error == 0 ? min(cnt->failed, cap_work) : 0;
+    const int trows = min(kTangentBlocks, (nfail + 63) / 64);
+    for (int r = threadIdx.x; r < trows; r += kReduceThreads) {
+      const int64_t v = base[(int64_t)(kMaxPairBlocks + r) * stride];
+      acc = is_max ? max(acc, v) : acc + v;
+    }
+  }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     const int64_t y = __shfl_xor(acc, o, 64);

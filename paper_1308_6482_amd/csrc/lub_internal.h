@@ -32,7 +32,7 @@ struct Counters {
   int32_t work;          // evaluated pair slots (particle + wall)
   int32_t error;         // LUB_E* found on the device
   int32_t newton_max;
-  int32_t pad0;
+  int32_t failed;        // slots whose Newton solve failed from every start
   int64_t candidates;
   int64_t wall_candidates;
   int64_t active;
@@ -49,7 +49,9 @@ struct Counters {
 
 // Per-block partial statistics, written with plain stores and summed only
 // when the host asks for the counters.
-//   pair kernel rows: [0] Newton iterations, [1] active, [2] overlaps,
+//   pair kernel rows (the main pass's blocks, then from row kMaxPairBlocks
+//   the tangent-sphere pass's blocks; a pair is counted by the pass that
+//   finished it): [0] Newton iterations, [1] active, [2] overlaps,
 //   [3] unresolved, [4] unconverged, [5] fallbacks, [6] max iterations,
 //   [7] warm-seeded pairs, [8..39] iteration histogram
 //   neighbour kernel rows: [0] candidate pairs, [1] wall candidates,
@@ -57,6 +59,7 @@ struct Counters {
 constexpr int kStatPairWords = 40;
 constexpr int kStatNbrWords = 3;
 constexpr int kMaxPairBlocks = 16384;  // larger slot counts: grid-stride loop
+constexpr int kTangentBlocks = 64;     // grid of the tangent-sphere pass
 
 // Constant description of one call.
 struct CallDesc {
@@ -73,6 +76,9 @@ struct CallDesc {
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
+  int32_t le;            // Lees-Edwards images (all axes periodic, no walls)
+  double le_offset;      // x offset of the image one box up, in [0, L_x)
+  double le_vel;         // x velocity of the image one box up
   double rmax_bound;
   double dmax;           // largest cut-off
   double mu, delta_n, delta_t, delta_r, h_c, eps_c;
@@ -152,8 +158,9 @@ struct WarmTables {
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  WarmTables warm, int64_t* stat_pair, Counters* cnt,
-                  hipStream_t s);
+                  WarmTables warm, int32_t* fail_list, int64_t* stat_pair,
+                  Counters* cnt, hipStream_t s, hipEvent_t ev_start = nullptr,
+                  hipEvent_t ev_stop = nullptr);
 
 // seed features of every particle-particle evaluation slot (m x 10, FP32)
 void launch_seed_features(const CallDesc& d, const PRec* rec,
@@ -181,6 +188,22 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
                    int64_t warm_size, double* f, double* t, hipStream_t s);
 
+// ---- integrator (lub_integrate.hip) ---------------------------------------
+struct StepDesc {
+  int32_t n;
+  int32_t periodic[3];
+  int32_t le;           // Lees-Edwards images
+  double L[3];
+  double le_offset;     // offset after this sub-step, in [0, L_x)
+  double le_vel;
+  double dt, density, damping;
+};
+void launch_integrate(const StepDesc& s, double* r, double* q, const double* semi,
+                      double* v, double* w, const double* f_ext, const double* t_ext,
+                      const double* f, const double* t, hipStream_t st);
+// out = scale * semi (n x 2)
+void launch_scale(int n, const double* semi, double scale, double* out, hipStream_t st);
+
 // grid of the pair kernel for a given slot capacity
 int pair_grid(const CallDesc& d);
 // neighbour kernel: lanes per particle, blocks of a call, and the most
@@ -197,12 +220,46 @@ void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_p
 // with the quotient taken as dx (1/L): the two round to different integers
 // only next to a half-integer, and there the division itself decides.
 // No contraction, so the result equals the plain expression bit for bit.
-__device__ __forceinline__ double min_image(double dx, double L, double invL) {
+__device__ __forceinline__ double image_count(double dx, double L, double invL) {
 #pragma clang fp contract(off)
   const double x = dx * invL;
   double k = rint(x);
   if (fabs(fabs(x - k) - 0.5) < 1e-9) k = rint(dx / L);
-  return dx - L * k;
+  return k;
+}
+
+__device__ __forceinline__ double min_image(double dx, double L, double invL) {
+#pragma clang fp contract(off)
+  return dx - L * image_count(dx, L, invL);
+}
+
+// Offset from centre ri to the nearest image of centre rj.  With
+// Lees-Edwards images the z image is taken first: m boxes down in z moves
+// the image by -m le_offset in x (and its velocity by -m le_velocity); x and
+// y are then wrapped as usual.  Returns m (0 without Lees-Edwards images).
+// Fixed order, no contraction: equal to the plain expressions bit for bit.
+__device__ __forceinline__ int pair_image(const CallDesc& d, const double* ri,
+                                          const double* rj, double* out) {
+#pragma clang fp contract(off)
+  double dx = rj[0] - ri[0];
+  double dy = rj[1] - ri[1];
+  double dz = rj[2] - ri[2];
+  int m = 0;
+  if (d.le) {
+    const double c = image_count(dz, d.L[2], d.invL[2]);
+    m = (int)c;
+    dz = dz - d.L[2] * c;
+    const double shift = c * d.le_offset;
+    dx = dx - shift;
+  } else if (d.periodic[2]) {
+    dz = min_image(dz, d.L[2], d.invL[2]);
+  }
+  if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
+  if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
+  out[0] = dx;
+  out[1] = dy;
+  out[2] = dz;
+  return m;
 }
 #endif
 

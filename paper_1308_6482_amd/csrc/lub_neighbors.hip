@@ -47,12 +47,9 @@ __device__ __forceinline__ bool centre_test(const double* ri, const double* rj,
                                             double rmi, double rmj,
                                             const CallDesc& d) {
 #pragma clang fp contract(off)
-  double dx = rj[0] - ri[0];
-  double dy = rj[1] - ri[1];
-  double dz = rj[2] - ri[2];
-  if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
-  if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
-  if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
+  double o[3];
+  pair_image(d, ri, rj, o);
+  const double dx = o[0], dy = o[1], dz = o[2];
   double d2 = dx * dx + dy * dy;
   d2 = d2 + dz * dz;
   double sb = (rmi + rmj) + d.dmax;
@@ -503,6 +500,15 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
       // an axis taken whole (periodic, shorter than the stencil) is not pruned
       bool whole[3];
       for (int k = 0; k < 3; ++k) whole[k] = d.periodic[k] && cnt3[k] == d.nc[k];
+      // Lees-Edwards images: a row reached across the z boundary holds
+      // partners whose nearest image is shifted by the offset in x, so its
+      // x window is moved by that offset.  With z taken whole a row's image
+      // is not known from the row: then x is taken whole too
+      if (d.le && whole[2]) {
+        whole[0] = true;
+        first[0] = 0;
+        cnt3[0] = d.nc[0];
+      }
       for (int row0 = 0; row0 < nrows; row0 += G) {
         // lane gl owns row row0 + gl of the stencil (cells (y, z)).  Rows
         // farther than rho from the centre hold no candidate; in the others
@@ -520,8 +526,21 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
           int a0 = first[0], a1 = first[0] + cnt3[0] - 1;  // cells a0..a1 along x
           if (!whole[0]) {
             const double wx = sqrt(fmax(rem, 0.0)) * (1.0 + 1e-9) + 1e-9 * d.cell[0];
-            a0 = max(a0, cx + (int)floor((f3[0] - wx) / d.cell[0]));
-            a1 = min(a1, cx + (int)floor((f3[0] + wx) / d.cell[0]));
+            int cxr = cx;
+            double fx = f3[0];
+            const int zr = cz + oz;
+            if (d.le && (zr < 0 || zr >= d.nc[2])) {
+              // partners across the top sit at x - offset, across the bottom
+              // at x + offset (stored coordinates of the nearest image)
+              double xs = fx + cx * d.cell[0] + (zr < 0 ? d.le_offset : -d.le_offset);
+              xs = xs - d.L[0] * floor(xs / d.L[0]);
+              cxr = min(d.nc[0] - 1, max(0, (int)floor(xs / d.cell[0])));
+              fx = xs - cxr * d.cell[0];
+              a0 = cxr - reach[0];
+              a1 = cxr + reach[0];
+            }
+            a0 = max(a0, cxr + (int)floor((fx - wx) / d.cell[0]));
+            a1 = min(a1, cxr + (int)floor((fx + wx) / d.cell[0]));
           }
           if (rem > 0.0 && a1 >= a0) {
             const int ry = wrap_cell(cy + oy, d.nc[1]);
@@ -623,11 +642,9 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     // cut-off
     if (orig[key] > me) {
       ++nupper;
-      double dx = rec[key].r[0] - rs[0], dy = rec[key].r[1] - rs[1],
-             dz = rec[key].r[2] - rs[2];
-      if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
-      if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
-      if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
+      double dv[3];
+      pair_image(d, rs, rec[key].r, dv);
+      const double dx = dv[0], dy = dv[1], dz = dv[2];
       double dn = sqrt(dx * dx + dy * dy + dz * dz);
       bool keep = true;
       if (dn > 0.0) {

@@ -31,6 +31,7 @@
 // the gap, the frame vectors, relative surface velocities and the
 // ln(h/Delta), 1/h - 1/Delta factors stay in FP64; curvatures, K and the
 // transfer run in FP32.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lub_internal.h"
@@ -313,6 +314,127 @@ __host__ __device__ __forceinline__ void radii(R Rpa, R Rpe, R cp, R sp, R* S1, 
 }
 
 // cubic coefficients a (given in axes rotated by +alpha) in unrotated axes
+// ---------------------------------------------------------------------------
+// Last resort: the tangent-sphere iteration of Sec. III.A (Lin and Han), on
+// the surfaces x^T A x = 1, A = (I - a a^T) / Rperp^2 + a a^T / Rpar^2.
+
+// quadratic form of a spheroid with unit axis a at x, and its bilinear form
+__host__ __device__ __forceinline__ double sph_q(const PRec& P, const double x[3]) {
+  const double ax = dot3(P.ax, x);
+  return (dot3(x, x) - ax * ax) / (P.Rperp * P.Rperp) + ax * ax / (P.Rpar * P.Rpar);
+}
+
+__host__ __device__ __forceinline__ double sph_b(const PRec& P, const double x[3],
+                                                 const double u[3]) {
+  const double ax = dot3(P.ax, x), au = dot3(P.ax, u);
+  return (dot3(x, u) - ax * au) / (P.Rperp * P.Rperp) + ax * au / (P.Rpar * P.Rpar);
+}
+
+// Where the ray x0 + t u (t > 0, u unit, x0 relative to the centre) leaves
+// the surface: the larger root of q(x0 + t u) = 1, also from a start
+// outside the body when the ray still crosses it.
+__host__ __device__ __forceinline__ bool ray_exit(const PRec& P, const double x0[3],
+                                                  const double u[3], double y[3]) {
+  const double qa = sph_q(P, u), qb = sph_b(P, x0, u), qc = sph_q(P, x0) - 1.0;
+  const double disc = qb * qb - qa * qc;
+  if (!(disc >= 0.0) || !(qa > 0.0)) return false;
+  const double t = (-qb + sqrt(disc)) / qa;
+  if (!(t > 0.0)) return false;
+  for (int k = 0; k < 3; ++k) y[k] = x0[k] + t * u[k];
+  return true;
+}
+
+// outward unit normal at the surface point y (relative to the centre)
+__host__ __device__ __forceinline__ void sph_normal(const PRec& P, const double y[3],
+                                                    double n[3]) {
+  const double ay = dot3(P.ax, y);
+  const double ip = 1.0 / (P.Rperp * P.Rperp), ia = 1.0 / (P.Rpar * P.Rpar);
+  for (int k = 0; k < 3; ++k) n[k] = (y[k] - ay * P.ax[k]) * ip + ay * P.ax[k] * ia;
+  const double ln = sqrt(dot3(n, n));
+  for (int k = 0; k < 3; ++k) n[k] /= ln;
+}
+
+// smaller principal radius of curvature at the surface point y (Eq.
+// lub:curvature-radii), or the conservative radius of Eq. lub:minimum-radius
+__host__ __device__ __forceinline__ double sph_radius(const PRec& P, const double y[3],
+                                                      bool local) {
+  if (!local) {
+    if (P.Rpar < P.Rperp) return P.Rpar * P.Rpar / P.Rperp;
+    if (P.Rpar > P.Rperp) return P.Rperp * P.Rperp / P.Rpar;
+    return P.Rpar;
+  }
+  const double ay = dot3(P.ax, y);
+  double sp = ay / P.Rpar;
+  double cp = sqrt(fmax(dot3(y, y) - ay * ay, 0.0)) / P.Rperp;
+  const double l = sqrt(sp * sp + cp * cp);
+  sp /= l;
+  cp /= l;
+  double S1, S2, G0, G2;
+  radii<double>(P.Rpar, P.Rperp, cp, sp, &S1, &S2, &G0, &G2);
+  return fmin(S1, S2);
+}
+
+// The two-fold strategy: up to n1 iterations with the local radii (accepted
+// only if the normals face the other centre and, for an overlap, each point
+// lies inside the other particle), else from the line of centres again with
+// the conservative radii for up to n2.  Returns the direction between the
+// final sphere centres (i -> j), the start of a Newton polish.
+__host__ __device__ bool tangent_spheres(const double d[3], const PRec& A, const PRec& B,
+                                         double nout[3]) {
+  constexpr int kN1 = 10, kN2 = 1000;
+  constexpr double kEps = 1e-6;
+  const double dn = sqrt(dot3(d, d));
+  if (!(dn > 0.0)) return false;
+  const double zero[3] = {0.0, 0.0, 0.0};
+  for (int phase = 0; phase < 2; ++phase) {
+    const bool local = phase == 0;
+    double u[3] = {d[0] / dn, d[1] / dn, d[2] / dn}, mu[3] = {-u[0], -u[1], -u[2]};
+    double yi[3], yj[3], ni[3], nj[3];  // yj relative to j's centre
+    if (!ray_exit(A, zero, u, yi) || !ray_exit(B, zero, mu, yj)) return false;
+    sph_normal(A, yi, ni);
+    sph_normal(B, yj, nj);
+    const int nmax = local ? kN1 : kN2;
+    for (int it = 0; it < nmax; ++it) {
+      const double si = sph_radius(A, yi, local), sj = sph_radius(B, yj, local);
+      double zi[3], zj[3], w[3];
+      for (int k = 0; k < 3; ++k) {
+        zi[k] = yi[k] - si * ni[k];           // relative to i's centre
+        zj[k] = yj[k] - sj * nj[k];           // relative to j's centre
+        w[k] = d[k] + zj[k] - zi[k];          // z_j - z_i
+      }
+      const double lw = sqrt(dot3(w, w));
+      if (!(lw > 0.0)) break;
+      for (int k = 0; k < 3; ++k) {
+        u[k] = w[k] / lw;
+        mu[k] = -u[k];
+      }
+      // converged: both normals along the line of the sphere centres
+      if (dot3(ni, u) > 1.0 - kEps && dot3(nj, mu) > 1.0 - kEps) {
+        bool ok = dot3(ni, d) > 0.0 && dot3(nj, d) < 0.0;
+        if (ok && lw < si + sj) {  // overlap: each point inside the other body
+          double yi_j[3], yj_i[3];
+          for (int k = 0; k < 3; ++k) {
+            yi_j[k] = yi[k] - d[k];
+            yj_i[k] = yj[k] + d[k];
+          }
+          ok = sph_q(B, yi_j) <= 1.0 && sph_q(A, yj_i) <= 1.0;
+        }
+        // the conservative phase's result is taken as it is: the Newton
+        // polish that follows judges it
+        if (!local || ok) {
+          for (int k = 0; k < 3; ++k) nout[k] = u[k];
+          return true;
+        }
+        break;  // the local radii gave no meaningful result: conservative phase
+      }
+      if (!ray_exit(A, zi, u, yi) || !ray_exit(B, zj, mu, yj)) break;
+      sph_normal(A, yi, ni);
+      sph_normal(B, yj, nj);
+    }
+  }
+  return false;
+}
+
 template <typename R>
 __host__ __device__ __forceinline__ void rotate_cubic(R c, R s, const R a[4], R m[4]) {
   R c2 = c * c, s2 = s * s;
@@ -416,24 +538,25 @@ __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec
                                    const PRec* B, const KRec* KB, int side,
                                    PairOut<R>& out, double& hout, int& status) {
   const double a = A.Rperp;
-  double n[3], h, g;
-  const double* vj;
+  double n[3], h, g, vj[3];  // vj: velocity of the partner (its image) or the wall
   if (B) {
-    double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
-    for (int k = 0; k < 3; ++k)
-      if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
+    double d[3];
+    const int m = pair_image(cd, A.r, B->r, d);
     const double dn = sqrt(dot3(d, d));
     for (int k = 0; k < 3; ++k) n[k] = d[k] / dn;
     const double b = B->Rperp;
     h = dn - a - b;
     g = a * b / (a + b);
-    vj = KB->v;
+    // velocity of the image of j that d points to
+    vj[0] = KB->v[0] - m * cd.le_vel;
+    vj[1] = KB->v[1];
+    vj[2] = KB->v[2];
   } else {
     n[0] = n[1] = 0.0;
     n[2] = side == 0 ? -1.0 : 1.0;
     h = (side == 0 ? A.r[2] : cd.L[2] - A.r[2]) - a;
     g = a;
-    vj = cd.wall_vel[side];
+    for (int k = 0; k < 3; ++k) vj[k] = cd.wall_vel[side][k];
   }
   hout = h;
   const double heff = h > cd.h_c ? h : cd.h_c;
@@ -453,7 +576,7 @@ __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec
   for (int k = 0; k < 3; ++k) out.F[k] = R(fn * n[k]);
 }
 
-template <typename R>
+template <typename R, bool kTangent>
 __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
                           const PRec* B, const KRec* KB, int side,
                           PairOut<R>& out, double& hout, int& status,
@@ -467,10 +590,10 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     return;
   }
   Solve sv;
+  int le_m = 0;  // Lees-Edwards image of j: its velocity differs by -le_m le_vel in x
   if (B) {
-    double d[3] = {B->r[0] - A.r[0], B->r[1] - A.r[1], B->r[2] - A.r[2]};
-    for (int k = 0; k < 3; ++k)
-      if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
+    double d[3];
+    le_m = pair_image(cd, A.r, B->r, d);
     // start: the previous call's normal (warm start), else the learned
     // prediction, else the line of centres.  The plain start judges a seeded
     // one: if the seeded iteration does not converge, start again from the
@@ -495,6 +618,21 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       }
     } else {
       sv = closest_points(d, A.M, B->M, cd.max_iter);
+    }
+    if (kTangent && !sv.ok) {
+      // last resort: the paper's tangent-sphere iteration, then a Newton
+      // polish from its normal (at least 8 iterations: its start is only
+      // within the iteration's tolerance)
+      double nl[3];
+      if (tangent_spheres(d, A, *B, nl)) {
+        const int used = sv.iters;
+        Solve sp = closest_points(d, A.M, B->M, cd.max_iter > 8 ? cd.max_iter : 8, nl);
+        sp.iters += used;
+        if (sp.ok) {
+          sv = sp;
+          if (fell_back) *fell_back = 1;
+        }
+      }
     }
     if (nout && sv.ok)
       for (int k = 0; k < 3; ++k) nout[k] = sv.n[k];
@@ -560,7 +698,9 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   const bool full = cd.model == LUB_MODEL_FULL;
   double Lt = full && heff < cd.delta_t ? log(heff) - log(cd.delta_t) : 0.0;
   double Lr = full && heff < cd.delta_r ? log(heff) - log(cd.delta_r) : 0.0;
-  double Ln = heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
+  // the contact-only law has no resistance: the repulsion below acts alone
+  const bool lub = cd.model != LUB_MODEL_CONTACT;
+  double Ln = lub && heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
 
   // relative surface velocities in the local frame (FP64)
   double Vi[3], Vj[3], wr[3], tmp[3];
@@ -573,6 +713,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       Vj[k] = KB->v[k] + tmp[k];
       wr[k] = KB->w[k] - KA.w[k];
     }
+    Vj[0] -= le_m * cd.le_vel;
   } else {
     for (int k = 0; k < 3; ++k) {
       Vj[k] = cd.wall_vel[side][k];
@@ -626,7 +767,12 @@ __device__ __forceinline__ uint64_t warm_hash(uint64_t k) {
   return k;
 }
 
-template <typename R>
+// kTangent = false: the main pass over all slots; a particle pair whose
+// Newton solve fails from every start is put on fail_list and left to the
+// second pass (kTangent = true, a small grid over that list), which adds the
+// tangent-sphere fallback.  The fallback's registers would otherwise lower
+// the occupancy of the main pass.
+template <typename R, bool kTangent>
 __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               const PRec* __restrict__ rec,
                                               const KRec* __restrict__ kin,
@@ -638,23 +784,26 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               int8_t* __restrict__ out_status,
                                               uint8_t* __restrict__ out_iters,
                                               WarmTables warm,
+                                              int32_t* __restrict__ fail_list,
                                               int64_t* __restrict__ stat_pair,
-                                              const Counters* cnt) {
+                                              Counters* cnt) {
   // one wavefront per block: statistics are reduced in the wave (ballots,
   // shuffles) and written as this block's row, without atomics
   static_assert(kPairBlock == 64, "one wavefront per block");
   const int lane = threadIdx.x;
   // the grid is sized for the capacity; blocks past the device-side work
   // count leave at once (their rows are not read)
-  const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
+  const int nwork = cnt->error != 0 ? 0
+                    : kTangent  ? min(cnt->failed, cd.cap_work)
+                                : min(cnt->work, cd.cap_work);
   if (blockIdx.x * blockDim.x >= nwork) return;
   int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0,
           n_warm = 0;
   int max_it = 0;
   int64_t my_hist = 0;  // lane b < 32 holds histogram bucket b
   for (int w0 = blockIdx.x * blockDim.x; w0 < nwork; w0 += gridDim.x * blockDim.x) {
-    const int w = w0 + lane;
-    const bool on = w < nwork;
+    const bool on = w0 + lane < nwork;
+    const int w = kTangent ? (on ? fail_list[w0 + lane] : 0) : w0 + lane;
     int status = -1, iters = 0, fb = 0, wu = 0;
     double h = 0.0;
     if (on) {
@@ -680,7 +829,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
             if (k == kWarmEmpty) break;
           }
           double nnew[3] = {0.0, 0.0, 0.0};
-          eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+          eval_pair<R, kTangent>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
                        seedY ? seedY + 4 * (int64_t)w : nullptr, &fb,
                        found ? nprev : nullptr, &wu, nnew);
           if (status != 3) {
@@ -699,18 +848,24 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
             }
           }
         } else {
-          eval_pair<R>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
+          eval_pair<R, kTangent>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
                        seedY ? seedY + 4 * (int64_t)w : nullptr, &fb);
         }
       } else
-        eval_pair<R>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
+        eval_pair<R, kTangent>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
                      iters);
       out[w] = o;
       out_h[w] = h;
       out_status[w] = (int8_t)status;
       out_iters[w] = (uint8_t)(iters > 255 ? 255 : iters);
+      if (!kTangent && status == 3 && t >= 0 && cd.model != LUB_MODEL_LADD) {
+        // deferred to the tangent-sphere pass, which counts it
+        fail_list[atomicAdd(&cnt->failed, 1)] = w;
+        status = -1;
+        iters = fb = wu = 0;
+      }
     }
-    const int bucket = on ? (iters < 31 ? iters : 31) : -1;
+    const int bucket = on && status >= 0 ? (iters < 31 ? iters : 31) : -1;
     n_iters += iters;
     max_it = max(max_it, iters);
     n_active += __popcll(__ballot(status == 0));
@@ -720,7 +875,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     n_fb += __popcll(__ballot(fb != 0));
     n_warm += __popcll(__ballot(wu != 0));
     // histogram over the buckets present in this pass
-    int lo = on ? bucket : 32, hi = bucket;
+    int lo = bucket >= 0 ? bucket : 32, hi = bucket;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
       lo = min(lo, __shfl_xor(lo, o, 64));
@@ -736,7 +891,8 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     n_iters += __shfl_xor(n_iters, o, 64);
     max_it = max(max_it, __shfl_xor(max_it, o, 64));
   }
-  int64_t* row = stat_pair + (int64_t)kStatPairWords * blockIdx.x;
+  int64_t* row = stat_pair + (int64_t)kStatPairWords *
+                                 (blockIdx.x + (kTangent ? kMaxPairBlocks : 0));
   const int64_t v = lane == 0 ? n_iters
                   : lane == 1 ? n_active
                   : lane == 2 ? n_overlap
@@ -762,9 +918,8 @@ __global__ void k_seed_features(CallDesc cd, const PRec* __restrict__ rec,
     if (t >= 0) {
       const PRec& A = rec[s];
       const PRec& B = rec[t];
-      double d[3] = {B.r[0] - A.r[0], B.r[1] - A.r[1], B.r[2] - A.r[2]};
-      for (int k = 0; k < 3; ++k)
-        if (cd.periodic[k]) d[k] = min_image(d[k], cd.L[k], cd.invL[k]);
+      double d[3];
+      pair_image(cd, A.r, B.r, d);
       seed_features(d, A, B, x);
     }
     for (int k = 0; k < 10; ++k) X[10 * (int64_t)w + k] = x[k];
@@ -792,16 +947,27 @@ int pair_grid(const CallDesc& d) {
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
-                  WarmTables warm, int64_t* stat_pair, Counters* cnt, hipStream_t s) {
+                  WarmTables warm, int32_t* fail_list, int64_t* stat_pair, Counters* cnt,
+                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int blocks = pair_grid(d);
-  if (d.precision == LUB_MIXED)
-    hipLaunchKernelGGL(k_pairs<float>, dim3(blocks), dim3(kPairBlock), 0, s, d,
-                       rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
-                       out_status, out_iters, warm, stat_pair, cnt);
-  else
-    hipLaunchKernelGGL(k_pairs<double>, dim3(blocks), dim3(kPairBlock), 0, s, d,
-                       rec, kin, work_s, work_t, seedY, (PairOut<double>*)out, out_h,
-                       out_status, out_iters, warm, stat_pair, cnt);
+  // the events (may be null) take the main pass's own start and end stamps
+  if (d.precision == LUB_MIXED) {
+    hipExtLaunchKernelGGL(k_pairs<float, false>, dim3(blocks), dim3(kPairBlock), 0, s,
+                          ev_start, ev_stop, 0, d, rec, kin, work_s, work_t, seedY,
+                          (PairOut<float>*)out, out_h, out_status, out_iters, warm,
+                          fail_list, stat_pair, cnt);
+    hipLaunchKernelGGL((k_pairs<float, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0, s,
+                       d, rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
+                       out_status, out_iters, warm, fail_list, stat_pair, cnt);
+  } else {
+    hipExtLaunchKernelGGL(k_pairs<double, false>, dim3(blocks), dim3(kPairBlock), 0, s,
+                          ev_start, ev_stop, 0, d, rec, kin, work_s, work_t, seedY,
+                          (PairOut<double>*)out, out_h, out_status, out_iters, warm,
+                          fail_list, stat_pair, cnt);
+    hipLaunchKernelGGL((k_pairs<double, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0,
+                       s, d, rec, kin, work_s, work_t, seedY, (PairOut<double>*)out,
+                       out_h, out_status, out_iters, warm, fail_list, stat_pair, cnt);
+  }
 }
 
 }  // namespace lub

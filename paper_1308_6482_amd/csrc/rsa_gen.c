@@ -28,6 +28,8 @@ typedef struct {
   double* M;          /* n_target x 9 (shape matrix Q D^2 Q^T) */
   const double* semi; /* n_target x 2, placement order */
   double rmax_glob;
+  int32_t le;         /* Lees-Edwards images: one box up in z is shifted by */
+  double le_offset;   /* le_offset in x */
 } rsa_state;
 
 static void quat_mat(const double* q, double R[9]) {
@@ -96,6 +98,30 @@ static int cell_of(const rsa_state* s, const double x[3], int c[3]) {
   return (c[2] * s->nc[1] + c[1]) * s->nc[0] + c[0];
 }
 
+/* does the trial at x (shape matrix Mi, semi-axes sem) overlap particle j's
+ * nearest image? */
+static int overlaps(const rsa_state* s, const double x[3], const double* Mi,
+                    const double* sem, int32_t j) {
+  double d[3];
+  for (int k = 0; k < 3; ++k) d[k] = s->r[3 * j + k] - x[k];
+  if (s->le) {
+    double m = nearbyint(d[2] / s->L[2]);
+    d[2] -= s->L[2] * m;
+    d[0] -= m * s->le_offset;
+  }
+  for (int k = 0; k < 3; ++k)
+    if (s->periodic[k] && !(s->le && k == 2)) d[k] -= s->L[k] * nearbyint(d[k] / s->L[k]);
+  double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double* sj = &s->semi[2 * j];
+  double rmi = sem[0] > sem[1] ? sem[0] : sem[1];
+  double rni = sem[0] < sem[1] ? sem[0] : sem[1];
+  double rmj = sj[0] > sj[1] ? sj[0] : sj[1];
+  double rnj = sj[0] < sj[1] ? sj[0] : sj[1];
+  if (dist >= rmi + rmj) return 0;
+  if (dist < rni + rnj) return 1;
+  return pw_overlap(Mi, &s->M[9 * j], d);
+}
+
 void* rsa_create(int64_t n_target, const double* semi, const double L[3],
                  const int32_t periodic[3]) {
   rsa_state* s = (rsa_state*)calloc(1, sizeof(rsa_state));
@@ -160,8 +186,6 @@ int64_t rsa_run(void* p, int64_t m, const double* pos, const double* quat,
           ok = 0;
       }
     if (!ok) continue;
-    double rmi = sem[0] > sem[1] ? sem[0] : sem[1];
-    double rni = sem[0] < sem[1] ? sem[0] : sem[1];
     int c[3];
     cell_of(s, x, c);
     int visited[27];
@@ -171,6 +195,21 @@ int64_t rsa_run(void* p, int64_t m, const double* pos, const double* quat,
         for (int dx = -1; dx <= 1 && ok; ++dx) {
           int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
           int skip = 0;
+          /* Lees-Edwards: rows across the z boundary are searched whole
+           * in x (from the dx = 0 pass) */
+          const int zwrap = s->le && (cc[2] < 0 || cc[2] >= s->nc[2]);
+          if (zwrap) {
+            if (dx != 0) continue;
+            int cy = ((cc[1] % s->nc[1]) + s->nc[1]) % s->nc[1];
+            int cz = ((cc[2] % s->nc[2]) + s->nc[2]) % s->nc[2];
+            if (cz == c[2]) continue; /* the own row is searched directly */
+            for (int ax = 0; ax < s->nc[0] && ok; ++ax) {
+              int id = (cz * s->nc[1] + cy) * s->nc[0] + ax;
+              for (int32_t j = s->head[id]; j >= 0 && ok; j = s->next[j])
+                if (overlaps(s, x, Mi, sem, j)) ok = 0;
+            }
+            continue;
+          }
           for (int k = 0; k < 3; ++k) {
             if (s->periodic[k])
               cc[k] = ((cc[k] % s->nc[k]) + s->nc[k]) % s->nc[k];
@@ -183,23 +222,8 @@ int64_t rsa_run(void* p, int64_t m, const double* pos, const double* quat,
             if (visited[v] == id) skip = 1;
           if (skip) continue;
           visited[nvis++] = id;
-          for (int32_t j = s->head[id]; j >= 0 && ok; j = s->next[j]) {
-            double d[3];
-            for (int k = 0; k < 3; ++k) {
-              d[k] = s->r[3 * j + k] - x[k];
-              if (s->periodic[k]) d[k] -= s->L[k] * nearbyint(d[k] / s->L[k]);
-            }
-            double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            const double* sj = &s->semi[2 * j];
-            double rmj = sj[0] > sj[1] ? sj[0] : sj[1];
-            double rnj = sj[0] < sj[1] ? sj[0] : sj[1];
-            if (dist >= rmi + rmj) continue;
-            if (dist < rni + rnj) {
-              ok = 0;
-              break;
-            }
-            if (pw_overlap(Mi, &s->M[9 * j], d)) ok = 0;
-          }
+          for (int32_t j = s->head[id]; j >= 0 && ok; j = s->next[j])
+            if (overlaps(s, x, Mi, sem, j)) ok = 0;
         }
     if (!ok) continue;
     memcpy(&s->r[3 * i], x, sizeof(x));
@@ -214,6 +238,14 @@ int64_t rsa_run(void* p, int64_t m, const double* pos, const double* quat,
 }
 
 int64_t rsa_placed(void* p) { return ((rsa_state*)p)->placed; }
+
+/* Lees-Edwards images for the overlap test (all axes periodic): the image
+ * one box up in z sits le_offset further in x. */
+void rsa_set_lees_edwards(void* p, double le_offset) {
+  rsa_state* s = (rsa_state*)p;
+  s->le = 1;
+  s->le_offset = le_offset;
+}
 
 void rsa_fetch(void* p, double* r, double* q) {
   rsa_state* s = (rsa_state*)p;

@@ -23,8 +23,21 @@ EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_stats", "lub_reset_timers", "lub_get_pairs",
            "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
            "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
+           "lub_get_domain", "lub_integrate", "lub_grow",
            "lub_destroy", "lub_strerror"]
 LUB_MLP_PARAMS = 34948
+
+
+class lub_step_t(C.Structure):
+    _fields_ = [("dt", C.c_double), ("n_sub", C.c_int32), ("reserved", C.c_int32),
+                ("density", C.c_double), ("damping", C.c_double)]
+
+
+class lub_grow_t(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("reserved", C.c_int32),
+                ("scale0", C.c_double), ("scale1", C.c_double), ("dt", C.c_double),
+                ("density", C.c_double), ("damping", C.c_double), ("h_c", C.c_double),
+                ("eps_c", C.c_double)]
 
 
 class lub_params_t(C.Structure):
@@ -36,7 +49,9 @@ class lub_params_t(C.Structure):
 
 class lub_domain_t(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("periodic", C.c_int32 * 3),
-                ("n_walls", C.c_int32), ("wall_vel", (C.c_double * 3) * 2)]
+                ("n_walls", C.c_int32), ("wall_vel", (C.c_double * 3) * 2),
+                ("lees_edwards", C.c_int32), ("reserved", C.c_int32),
+                ("le_offset", C.c_double), ("le_velocity", C.c_double)]
 
 
 class lub_opts_t(C.Structure):
@@ -56,7 +71,7 @@ class lub_stats_t(C.Structure):
                 ("newton_max", C.c_int32), ("error", C.c_int32),
                 ("iter_hist", C.c_int64 * 32), ("timed_calls", C.c_int64),
                 ("stage_ms", C.c_double * 4), ("warm_seeded", C.c_int64),
-                ("max_degree", C.c_int64)]
+                ("max_degree", C.c_int64), ("pair_kernel_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -112,6 +127,10 @@ def lib():
         L.lub_mlp_grad.argtypes = [_P, C.c_int64, _P, _P, _F, _F, _P]
         L.lub_mlp_train.argtypes = [_P, C.c_int64, _P, _P, C.POINTER(lub_train_cfg_t),
                                     _F, _P]
+        L.lub_get_domain.argtypes = [_P, C.POINTER(lub_domain_t)]
+        L.lub_integrate.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    C.POINTER(lub_step_t), _P]
+        L.lub_grow.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(lub_grow_t), _P]
         L.lub_destroy.argtypes = [_P]
         L.lub_destroy.restype = None
         L.lub_strerror.argtypes = [C.c_int]
@@ -125,7 +144,7 @@ def _check(rc: int, where: str):
         raise LubError(rc, where)
 
 
-LUB_MODEL_FULL, LUB_MODEL_NORMAL, LUB_MODEL_LADD = 0, 1, 2
+LUB_MODEL_FULL, LUB_MODEL_NORMAL, LUB_MODEL_LADD, LUB_MODEL_CONTACT = 0, 1, 2, 3
 
 
 def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0,
@@ -134,7 +153,9 @@ def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0,
 
 
 def make_domain(L, periodic=(1, 1, 1), n_walls=0,
-                wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))) -> lub_domain_t:
+                wall_vel=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
+                lees_edwards=None) -> lub_domain_t:
+    """lees_edwards: None, or (offset, velocity) of the image one box up in z."""
     d = lub_domain_t()
     for k in range(3):
         d.L[k] = float(L[k])
@@ -143,6 +164,10 @@ def make_domain(L, periodic=(1, 1, 1), n_walls=0,
     for s in range(2):
         for k in range(3):
             d.wall_vel[s][k] = float(wall_vel[s][k])
+    if lees_edwards is not None:
+        d.lees_edwards = 1
+        d.le_offset = float(lees_edwards[0])
+        d.le_velocity = float(lees_edwards[1])
     return d
 
 
@@ -196,6 +221,54 @@ def lub_compute(h, r, q, semi, v, w, f, t, stream=None, check=True) -> int:
     if check:
         _check(rc, "lub_compute")
     return rc
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return stream
+
+
+def _state_ptrs(n, r, q, semi, v, w):
+    for a, cols in ((r, 3), (q, 4), (semi, 2), (v, 3), (w, 3)):
+        if a.shape != (n, cols):
+            raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},{cols})")
+    return [_ptr(x) if n > 0 else 0 for x in (r, q, semi, v, w)]
+
+
+def lub_get_domain(h) -> lub_domain_t:
+    d = lub_domain_t()
+    _check(lib().lub_get_domain(h, C.byref(d)), "lub_get_domain")
+    return d
+
+
+def lub_integrate(h, r, q, semi, v, w, f, t, dt, n_sub, density=1.0, damping=0.0,
+                  f_ext=None, t_ext=None, stream=None):
+    """Sub-stepped update: r, q, v, w (float64 torch.cuda tensors) are
+    updated in place; f, t receive the last sub-step's correction."""
+    n = r.shape[0]
+    ptrs = _state_ptrs(n, r, q, semi, v, w)
+    for a in (f, t) + tuple(x for x in (f_ext, t_ext) if x is not None):
+        if a.shape != (n, 3):
+            raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},3)")
+    ext = [_ptr(x) if (x is not None and n > 0) else 0 for x in (f_ext, t_ext)]
+    out = [_ptr(x) if n > 0 else 0 for x in (f, t)]
+    st = lub_step_t(float(dt), int(n_sub), 0, float(density), float(damping))
+    _check(lib().lub_integrate(h, n, *ptrs, *ext, *out, C.byref(st), _stream_handle(stream)),
+           "lub_integrate")
+
+
+def lub_grow(h, r, q, semi, v, w, n_steps, scale0, scale1, dt, density=1.0, damping=0.0,
+             h_c=0.1, eps_c=100.0, stream=None):
+    """Growth stage of the packing generator: r, q, v, w updated in place."""
+    n = r.shape[0]
+    ptrs = _state_ptrs(n, r, q, semi, v, w)
+    cfg = lub_grow_t(int(n_steps), 0, float(scale0), float(scale1), float(dt),
+                     float(density), float(damping), float(h_c), float(eps_c))
+    _check(lib().lub_grow(h, n, *ptrs, C.byref(cfg), _stream_handle(stream)), "lub_grow")
 
 
 def lub_get_stats(h) -> dict:
@@ -321,8 +394,10 @@ class Lub:
     def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
                  sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
-                 seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0):
-        self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel),
+                 seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0, lees_edwards=None):
+        self.domain_args = dict(L=L, periodic=periodic, n_walls=n_walls, wall_vel=wall_vel,
+                                lees_edwards=lees_edwards)
+        self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel, lees_edwards),
                             make_params(**params),
                             make_opts(rmax_bound, precision, device, seed_mode=seed_mode,
                                       newton_max_iter=newton_max_iter, sync=sync,
@@ -341,6 +416,32 @@ class Lub:
 
     def stats(self):
         return lub_get_stats(self.h)
+
+    def integrate(self, r, q, semi, v, w, dt, n_sub, density=1.0, damping=0.0,
+                  f_ext=None, t_ext=None, f=None, t=None, stream=None):
+        import torch
+        n = r.shape[0]
+        if f is None:
+            f = torch.empty((n, 3), dtype=torch.float64, device=r.device)
+        if t is None:
+            t = torch.empty((n, 3), dtype=torch.float64, device=r.device)
+        lub_integrate(self.h, r, q, semi, v, w, f, t, dt, n_sub, density, damping,
+                      f_ext, t_ext, stream)
+        d = lub_get_domain(self.h)
+        if d.lees_edwards:
+            self.domain_args["lees_edwards"] = (d.le_offset, d.le_velocity)
+        return f, t
+
+    def grow(self, r, q, semi, v, w, **kw):
+        lub_grow(self.h, r, q, semi, v, w, **kw)
+        d = lub_get_domain(self.h)
+        if d.lees_edwards:
+            self.domain_args["lees_edwards"] = (d.le_offset, d.le_velocity)
+
+    def set_domain(self, **kw):
+        """Replace domain fields (e.g. lees_edwards=(offset, velocity))."""
+        self.domain_args.update(kw)
+        lub_set_domain(self.h, make_domain(**self.domain_args))
 
     def reset_timers(self):
         lub_reset_timers(self.h)
@@ -364,6 +465,7 @@ class Lub:
 
     @classmethod
     def for_workload(cls, wl, precision=LUB_FP64, **kw):
+        kw.setdefault("lees_edwards", wl.lees_edwards)
         return cls(wl.L, wl.periodic, wl.params, float(wl.semi.max()),
                    n_walls=wl.n_walls, wall_vel=wl.wall_vel, precision=precision,
                    **kw)

@@ -45,6 +45,8 @@ class Workload:
         mu=MU, delta_n=DELTA_N, delta_t=DELTA_T, delta_r=DELTA_R, h_c=H_C,
         eps_c=EPS_C))
     meta: dict = field(default_factory=dict)
+    # Lees-Edwards images: (offset, velocity) of the image one box up in z
+    lees_edwards: tuple = None
 
     @property
     def n(self) -> int:
@@ -52,14 +54,14 @@ class Workload:
 
     def domain(self) -> dict:
         return dict(L=self.L, periodic=self.periodic, n_walls=self.n_walls,
-                    wall_vel=self.wall_vel)
+                    wall_vel=self.wall_vel, lees_edwards=self.lees_edwards)
 
     def with_params(self, **kw) -> "Workload":
         p = dict(self.params)
         p.update(kw)
         return Workload(self.name, self.r, self.q, self.semi, self.v, self.w,
                         self.L, self.periodic, self.n_walls, self.wall_vel, p,
-                        dict(self.meta))
+                        dict(self.meta), self.lees_edwards)
 
 
 # ---------------------------------------------------------------------------
@@ -177,6 +179,8 @@ def _genlib():
                               ctypes.c_double]
         g.rsa_placed.restype = ctypes.c_int64
         g.rsa_placed.argtypes = [ctypes.c_void_p]
+        g.rsa_set_lees_edwards.restype = None
+        g.rsa_set_lees_edwards.argtypes = [ctypes.c_void_p, ctypes.c_double]
         g.rsa_fetch.argtypes = [ctypes.c_void_p, D, D]
         g.rsa_destroy.argtypes = [ctypes.c_void_p]
         _gen = g
@@ -185,13 +189,14 @@ def _genlib():
 
 def rsa(rng: np.random.Generator, semi: np.ndarray, L, periodic,
         max_trials: int = 10_000_000, wall_margin: float = 0.0,
-        chunk: int = 65536):
+        chunk: int = 65536, le_offset: float | None = None):
     """Random sequential addition: place the particles with the given
     semi-axes one after the other at uniform random positions and
     orientations, rejecting every trial that overlaps an accepted particle
     (Perram-Wertheim test) or crosses a wall on a non-periodic axis.
     Returns (r, q, trials); fewer particles than requested if max_trials
-    runs out."""
+    runs out.  le_offset: overlap test with Lees-Edwards images (the image
+    one box up in z shifted by le_offset in x)."""
     g = _genlib()
     semi = np.ascontiguousarray(semi, dtype=np.float64)
     n = semi.shape[0]
@@ -200,6 +205,8 @@ def rsa(rng: np.random.Generator, semi: np.ndarray, L, periodic,
     D = ctypes.POINTER(ctypes.c_double)
     st = g.rsa_create(n, semi.ctypes.data_as(D), Lv.ctypes.data_as(D),
                       per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if le_offset is not None:
+        g.rsa_set_lees_edwards(st, float(le_offset))
     trials = 0
     try:
         while g.rsa_placed(st) < n and trials < max_trials:
@@ -257,6 +264,36 @@ def config2(seed: int = 0, n: int = 4096, phi: float = 0.3) -> Workload:
     v, w = shear_velocities(g_vel, r)
     return Workload(f"prolates{n}_8x4x4_phi{phi}", r, q, semi, v, w, L,
                     (1, 1, 1), meta=dict(phi=phi, rsa_trials=trials))
+
+
+def sheared(seed: int = 0, n: int = 4096, phi: float = 0.3, offset_frac: float = 0.37,
+            polydisperse: bool = False) -> Workload:
+    """A periodic cube under simple shear with Lees-Edwards images (the
+    paper's sheared periodic systems, Sec. IV.A): the image one box up in z
+    is offset by offset_frac L in x (accumulated strain) and moves with
+    gamma_dot L in x.  Prolates (8,4,4), or with polydisperse=True aspect
+    ratios log-uniform in [1/3, 3] and R_perp in [3, 8]; placed by random
+    sequential addition with the same images; velocities follow the shear
+    field plus noise."""
+    g_pos, g_shape, g_vel, _ = _streams(seed + 7)
+    if polydisperse:
+        semi = polydisperse_semi(g_shape, n, 1.0 / 3.0, 3.0, 3.0, 8.0)
+        semi = semi[np.argsort(-semi.max(axis=1), kind="stable")]
+    else:
+        semi = np.tile(np.array([8.0, 4.0]), (n, 1))
+    vol = float(np.sum(4.0 / 3.0 * np.pi * semi[:, 0] * semi[:, 1] ** 2))
+    Lx = (vol / phi) ** (1.0 / 3.0)
+    L = (Lx, Lx, Lx)
+    off = offset_frac * Lx
+    r, q, trials = rsa(g_pos, semi, L, (1, 1, 1), le_offset=off)
+    if r.shape[0] != n:
+        raise RuntimeError("sheared: random sequential addition ran out of trials")
+    v, w = shear_velocities(g_vel, r)
+    gd = 1e-3
+    kind = "polydisperse" if polydisperse else "prolates"
+    return Workload(f"sheared_{kind}{n}_phi{phi}_le{offset_frac}", r, q, semi, v, w, L,
+                    (1, 1, 1), meta=dict(phi=phi, rsa_trials=trials),
+                    lees_edwards=(off, gd * Lx))
 
 
 def polydisperse_semi(rng: np.random.Generator, n: int, lam_lo: float,

@@ -340,3 +340,92 @@ def test_ladd_rejects_spheroids(cfg2):
         lb.compute(r, q, semi, v, w)
     assert e.value.code == L.LUB_EINVAL
     lb.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(L.LUB_FP64, 1e-9), (L.LUB_MIXED, 1e-5)])
+def test_tangent_sphere_fallback(ref, cfg2, precision, tol):
+    """Newton capped at 3 iterations fails from the line of centres for most
+    pairs; they go through the tangent-sphere iteration (Sec. III.A, both
+    phases) and a Newton polish from its normal in the second pass of the
+    pair stage, and must still meet the bars against the oracle."""
+    wl = cfg2
+    g = run_gpu(wl, precision, newton_max_iter=3)
+    o = run_oracle(ref, wl)
+    check_pairs(g, o)
+    st = g["stats"]
+    pp = st["evaluated"] - st["wall_candidates"]
+    print(f"fallbacks {st['fallbacks']} of {pp} particle pairs, unconverged "
+          f"{st['unconverged']}, iterations/pair {st['newton_iters'] / max(pp, 1):.2f}")
+    assert st["error"] == 0 and st["unconverged"] == 0
+    assert st["fallbacks"] > 0.3 * pp
+    # each slot is counted once, by the pass that finished it
+    assert sum(st["iter_hist"]) == st["evaluated"]
+    # the failed attempts plus the polish: more than the cap
+    assert st["newton_max"] > 3
+    assert st["active"] == o["stats"]["active"]
+    eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+    gate = act & (ha >= 1e-3)
+    assert eF[gate].max() < tol and eT[gate].max() < tol, (eF[gate].max(), eT[gate].max())
+    ef, et = particle_errors(g, o, ref, wl)
+    assert ef.max() < tol and et.max() < tol
+
+
+@pytest.mark.parametrize("kind,n,precision,tol", [
+    ("prolates", 4096, L.LUB_MIXED, 1e-5), ("prolates", 4096, L.LUB_FP64, 1e-9),
+    ("polydisperse", 6000, L.LUB_MIXED, 1e-5), ("prolates", 60, L.LUB_FP64, 1e-9)])
+def test_lees_edwards(ref, kind, n, precision, tol):
+    """Sheared periodic cube with Lees-Edwards images (offset 0.37 L): pair
+    lists bit-exact, pairs and particle sums at the bars.  n = 60 makes the
+    grid three cells or fewer per axis (z and x searched whole)."""
+    wl = W.sheared(n=n, polydisperse=kind == "polydisperse")
+    g = run_gpu(wl, precision)
+    o = run_oracle(ref, wl)
+    check_pairs(g, o)
+    st = g["stats"]
+    assert st["error"] == 0 and st["unconverged"] == 0
+    assert st["active"] == o["stats"]["active"] > 0
+    # pairs across the sheared boundary are present
+    ij = o["pairs"]
+    dz = wl.r[ij[:, 1], 2] - wl.r[ij[:, 0], 2]
+    assert np.sum(np.abs(dz) > wl.L[2] / 2) > (0 if n < 100 else 20)
+    eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+    gate = act & (ha >= 1e-3)
+    print(f"pairs active={act.sum()} max eF={eF[gate].max():.3e} eT={eT[gate].max():.3e}")
+    assert eF[gate].max() < tol and eT[gate].max() < tol
+    ef, et = particle_errors(g, o, ref, wl)
+    assert ef.max() < tol and et.max() < tol
+
+
+def test_lees_edwards_zero_offset_is_periodic(cfg2):
+    """Offset and image velocity 0: the plain periodic result, bit for bit."""
+    wl = cfg2
+    a = run_gpu(wl, L.LUB_MIXED)
+    wl0 = W.Workload(wl.name, wl.r, wl.q, wl.semi, wl.v, wl.w, wl.L, wl.periodic,
+                     params=wl.params, lees_edwards=(0.0, 0.0))
+    b = run_gpu(wl0, L.LUB_MIXED)
+    assert np.array_equal(a["f"], b["f"]) and np.array_equal(a["t"], b["t"])
+
+
+def test_lees_edwards_offset_update_graph():
+    """A new offset between calls (set_domain): graph replay recaptures and
+    equals eager evaluation bit for bit."""
+    wl = W.sheared(n=4096)
+    print("[gpu] Lees-Edwards offset updates, graph vs eager", flush=True)
+    r, q, semi, v, w = L.to_device(wl)
+    stream = torch.cuda.Stream()
+    eager = L.Lub.for_workload(wl, precision=L.LUB_MIXED)
+    graph = L.Lub.for_workload(wl, precision=L.LUB_MIXED, graph=1, sync=0)
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    off, U = wl.lees_edwards
+    for k, o in enumerate((off, off + 1.5, off + 1.5, off - 40.0)):
+        for lb in (eager, graph):
+            lb.set_domain(lees_edwards=(o, U))
+        fe, te = eager.compute(r, q, semi, v, w)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.compute(r, q, semi, v, w, f, t, stream=stream)
+        stream.synchronize()
+        assert torch.equal(f, fe) and torch.equal(t, te), f"step {k}"
+    eager.close()
+    graph.close()
