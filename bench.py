@@ -68,6 +68,9 @@ def parse():
                     help="no GPU work: read two rocprofv3 --pmc runs of this script with "
                          "--calibrate-copy (FETCH_SIZE, then WRITE_SIZE), scale each by the "
                          "copy kernel's reading and write profiles/pair_kernel_traffic.json")
+    ap.add_argument("--dynamics", type=int, default=1,
+                    help="also time the sheared box with Lees-Edwards images, the "
+                         "sub-stepped integrator and the growth stage (1) or not (0)")
     ap.add_argument("--train-pairs", type=int, default=1 << 21)
     ap.add_argument("--train-epochs", type=int, default=6)
     return ap.parse_args()
@@ -148,9 +151,10 @@ def traffic_summary(fetch_dir, write_dir, precision):
         raise SystemExit("no calibration copy kernel in the counter runs")
     f_fetch = COPY_BYTES / (fe[kf][2] * 1024.0)
     f_write = COPY_BYTES / (wr[kw][2] * 1024.0)
-    kern = [k for k in fe if "k_pairs" in k]
+    # the main pass of the pair stage (the tangent-sphere pass is k_pairs<R, true>)
+    kern = [k for k in fe if "k_pairs" in k and "true>" not in k]
     if len(kern) != 1:
-        raise SystemExit(f"expected one pair kernel, found {kern}")
+        raise SystemExit(f"expected one main pair kernel, found {kern}")
     kp = kern[0]
     fetch_b = fe[kp][0] * 1024.0 * f_fetch
     write_b = wr[kp][0] * 1024.0 * f_write
@@ -376,6 +380,62 @@ def trajectory(L, torch, wl, prec, args, warm):
                 newton_max=st["newton_max"])
 
 
+def dynamics(L, torch, args):
+    """Lees-Edwards evaluation (graph replay), sub-stepped integration and
+    the growth stage on a sheared periodic cube of 4096 prolates."""
+    import numpy as np
+    from paper_1308_6482_amd import workloads as W
+    prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
+    wl = W.sheared(n=4096)
+    args = argparse.Namespace(**vars(args))
+    args.max_neighbors = neighbour_capacity(L, torch, wl, prec)
+    st, ms, ms_e, _ = measure(L, torch, wl, prec, args)
+    out = dict(workload=wl.name, lees_edwards=dict(
+        value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
+        ms_per_step_eager=ms_e, active=st["active"]))
+    # integrator: sub-steps of 0.1 with the correction evaluated each time
+    r, q, semi, v, w = L.to_device(wl)
+    lb = L.Lub.for_workload(wl, precision=prec, sync=0, max_neighbors=args.max_neighbors)
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    nsub = max(args.steps // 4, 1)
+    lb.integrate(r, q, semi, v, w, 0.1, 5, f=f, t=t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.integrate(r, q, semi, v, w, 0.1, nsub, f=f, t=t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sti = lb.stats()
+    lb.close()
+    if sti["error"]:
+        raise RuntimeError(f"lub_integrate failed: {L.lub_strerror(sti['error'])}")
+    out["integrator"] = dict(substeps=nsub, dt=0.1, ms_per_substep=(t1 - t0) * 1e3 / nsub,
+                             active_last=sti["active"])
+    # growth stage: 4096 polydisperse spheroids from 30 % size to volume
+    # fraction 0.45, 1200 steps
+    rng = np.random.default_rng(7)
+    n = 4096
+    sm = W.polydisperse_semi(rng, n, 0.5, 2.0, 3.0, 5.0)
+    vol = float(np.sum(4.0 / 3.0 * np.pi * sm[:, 0] * sm[:, 1] ** 2))
+    Lx = (vol / 0.45) ** (1.0 / 3.0)
+    r0, q0, _ = W.rsa(rng, sm * 0.3, (Lx, Lx, Lx), (1, 1, 1))
+    params = dict(mu=1.0 / 6.0, delta_n=0.67, delta_t=0.5, delta_r=0.25, h_c=0.01,
+                  eps_c=100.0)
+    lb = L.Lub((Lx, Lx, Lx), (1, 1, 1), params, 1.05 * float(sm.max()), precision=prec)
+    dev = [torch.as_tensor(x, dtype=torch.float64, device="cuda")
+           for x in (r0, q0, sm, np.zeros_like(r0), np.zeros_like(r0))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lb.grow(*dev, n_steps=1200, scale0=0.3, scale1=1.05, dt=0.2, density=1.0, damping=1.0,
+            h_c=0.3, eps_c=1000.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lb.close()
+    out["growth"] = dict(n=n, phi=0.45, steps=1200, seconds=t1 - t0,
+                         ms_per_step=(t1 - t0) * 1e3 / 1200)
+    return out
+
+
 def summary(st, ms, args, ms_eager=None):
     active = st["active"]
     # the pair kernel's own duration, from events stamped by its dispatch
@@ -459,7 +519,7 @@ def main():
                    newton_iters_mean=sm["newton_iters_mean"], newton_max=st["newton_max"]),
         ms_per_step_eager=ms_e,
         stage_ms=sm["stage_ms"],
-        roofline=dict(bound="alu", kernel="k_pairs", achieved=sm["achieved_tflops"],
+        roofline=dict(bound="alu", kernel="k_pairs (main pass)", achieved=sm["achieved_tflops"],
                       peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
                       frac=sm["achieved_tflops"] / PEAK_ALU_TFLOPS,
                       flops_per_launch=sm["flops_per_launch"], launch_ms=sm["pair_kernel_ms"],
@@ -483,6 +543,8 @@ def main():
                                         ms_per_step_eager=msn_e, active=stn["active"],
                                         newton_iters_mean=stn["newton_iters"]
                                         / max(stn["evaluated"], 1))}
+    if args.dynamics:
+        res["dynamics"] = dynamics(L, torch, args)
     if args.cpu_seconds > 0:
         lb2 = L.Lub.for_workload(wl, precision=prec)
         r, q, semi, v, w = L.to_device(wl)
