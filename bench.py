@@ -436,6 +436,26 @@ def dynamics(L, torch, args):
     return out
 
 
+def link_laws(L, torch, args):
+    """The link-wise laws (Ding and Aidun; Clausen's averaged normal) on
+    2347 spheres of radius 4 in a periodic 128^3 lattice (volume fraction
+    0.3), graph replay; FP64."""
+    from paper_1308_6482_amd import workloads as W
+    wl0 = W.lattice_box()
+    out = dict(workload=wl0.name)
+    for name, model in (("link", L.LUB_MODEL_LINK), ("link_navg", L.LUB_MODEL_LINK_NAVG)):
+        wl = wl0.with_params(model=model, h_c=0.0, eps_c=0.0)
+        a2 = argparse.Namespace(**vars(args))
+        a2.max_neighbors = neighbour_capacity(L, torch, wl, L.LUB_FP64)
+        st, ms, ms_e, _ = measure(L, torch, wl, L.LUB_FP64, a2)
+        out[name] = dict(value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
+                         ms_per_step_eager=ms_e, active=st["active"],
+                         evaluated=st["evaluated"], links=st["newton_iters"],
+                         links_per_s=st["newton_iters"] / (ms * 1e-3),
+                         pair_stage_ms=st["stage_ms"][2] / max(st["timed_calls"], 1))
+    return out
+
+
 def summary(st, ms, args, ms_eager=None):
     active = st["active"]
     # the pair kernel's own duration, from events stamped by its dispatch
@@ -545,6 +565,7 @@ def main():
                                         / max(stn["evaluated"], 1))}
     if args.dynamics:
         res["dynamics"] = dynamics(L, torch, args)
+        res["link_laws"] = link_laws(L, torch, args)
     if args.cpu_seconds > 0:
         lb2 = L.Lub.for_workload(wl, precision=prec)
         r, q, semi, v, w = L.to_device(wl)

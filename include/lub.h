@@ -85,12 +85,35 @@ extern "C" {
  *                     alone, acting for h <= h_c (needs h_c > 0).  The
  *                     interaction of the growth stage of the packing
  *                     generator (Sec. IV.A).
+ *   LUB_MODEL_LINK    the link-wise law of Ding and Aidun (Sec. II.D, Eq.
+ *                     methods:dlub) on the lattice of integer points: every
+ *                     D3Q19 link from a site of j (or a fluid site halfway
+ *                     along two links from a site of j) to a site of i with
+ *                     link gap h* < |c| adds
+ *                     -3 q_bar mu / (2 |c|^2 lambda*) e (e.(V_i - V_j))
+ *                     (1/h_eff^2 - 1/|c|^2) on i at the crossing point of
+ *                     its surface (minus that on j), e the link direction
+ *                     from j to i, lambda* the mean of the two surfaces'
+ *                     mean curvatures at the crossings, h_eff = max(h*, h_c),
+ *                     plus the link-wise repulsion of Eq. lub:frep (h_c,
+ *                     eps_c are then the link-wise h_c*, eps_c*).
+ *   LUB_MODEL_LINK_NAVG the same with velocity difference, gap and force
+ *                     projected on the average normal of the two surfaces
+ *                     (Clausen's variant, Sec. II.D).
+ *                     The link-wise laws run in FP64 whatever the precision,
+ *                     need integer lengths on the periodic axes (lattice
+ *                     images) and accept neither walls nor Lees-Edwards
+ *                     images (LUB_EINVAL); lub_get_pair_results reports the
+ *                     number of contributing links in iters[], the smallest
+ *                     link gap in h.
  * The reduced models act below delta_n only; the first three clip the gap
  * at h_c and add the contact force of Eq. lub:frep. */
 #define LUB_MODEL_FULL 0
 #define LUB_MODEL_NORMAL 1
 #define LUB_MODEL_LADD 2
 #define LUB_MODEL_CONTACT 3
+#define LUB_MODEL_LINK 4
+#define LUB_MODEL_LINK_NAVG 5
 
 typedef struct {
   double mu;       /* dynamic viscosity */
@@ -101,6 +124,8 @@ typedef struct {
   double eps_c;    /* Hookean contact stiffness (Eq. lub:frep) */
   int32_t model;   /* LUB_MODEL_* */
   int32_t reserved;/* must be 0 */
+  double q_bar;    /* empirical weight of the link-wise laws (Ding and Aidun: */
+                   /* 0.6); must be > 0 for them, ignored by the others */
 } lub_params_t;
 
 /* Simulation box. */

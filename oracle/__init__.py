@@ -35,13 +35,15 @@ def build(force: bool = True) -> str:
 
 
 MODEL_FULL, MODEL_NORMAL, MODEL_LADD, MODEL_CONTACT = 0, 1, 2, 3
+MODEL_LINK, MODEL_LINK_NAVG = 4, 5
 
 
 class Params(C.Structure):
     _fields_ = [("mu", C.c_double), ("delta_n", C.c_double),
                 ("delta_t", C.c_double), ("delta_r", C.c_double),
                 ("h_c", C.c_double), ("eps_c", C.c_double),
-                ("model", C.c_int32), ("reserved", C.c_int32)]
+                ("model", C.c_int32), ("reserved", C.c_int32),
+                ("q_bar", C.c_double)]
 
 
 class Domain(C.Structure):
@@ -66,7 +68,7 @@ class PairResult(C.Structure):
                 ("kappa", C.c_double * 4), ("C", (C.c_double * 6) * 6),
                 ("Kt", (C.c_double * 6) * 6), ("Fbar", C.c_double * 6),
                 ("F", C.c_double * 3), ("Ti", C.c_double * 3),
-                ("Tj", C.c_double * 3)]
+                ("Tj", C.c_double * 3), ("links", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -132,7 +134,8 @@ def lib():
         L.ref_eval_pairs.argtypes = [C.c_int64, _D, _D, _D, _D, _D,
                                      C.POINTER(Domain), C.POINTER(Params),
                                      C.c_int64, _I32, C.c_int, _D, _D, _D, _D,
-                                     _I32]
+                                     _I32, _I32]
+        L.ref_link_eval.argtypes = [_D] * 10 + [C.POINTER(Params), C.POINTER(PairResult)]
         _lib = L
     return _lib
 
@@ -146,8 +149,8 @@ def _p(a, t=_D):
 
 
 def make_params(mu=1.0 / 6.0, delta_n=2.0 / 3.0, delta_t=0.5, delta_r=0.25,
-                h_c=0.0, eps_c=0.0, model=MODEL_FULL) -> Params:
-    return Params(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0)
+                h_c=0.0, eps_c=0.0, model=MODEL_FULL, q_bar=0.6) -> Params:
+    return Params(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0, float(q_bar))
 
 
 def make_domain(L=(1e9, 1e9, 1e9), periodic=(0, 0, 0), n_walls=0,
@@ -180,6 +183,14 @@ def pair_eval(d, qi, semii, vi, wi, qj, semij, vj, wj, params: Params) -> dict:
     o = PairResult()
     a = [_d(x) for x in (d, qi, semii, vi, wi, qj, semij, vj, wj)]
     lib().ref_pair_eval(*[_p(x) for x in a], C.byref(params), C.byref(o))
+    return o.as_dict()
+
+
+def link_eval(ri, d, qi, semii, vi, wi, qj, semij, vj, wj, params: Params) -> dict:
+    """Link-wise laws for one pair: ri absolute centre of i, d offset of j."""
+    o = PairResult()
+    a = [_d(x) for x in (ri, d, qi, semii, vi, wi, qj, semij, vj, wj)]
+    lib().ref_link_eval(*[_p(x) for x in a], C.byref(params), C.byref(o))
     return o.as_dict()
 
 
@@ -283,9 +294,10 @@ def partners_subset(r, semi, domain: Domain, params: Params, idx, cap=512):
 
 
 def eval_pairs(r, q, semi, v, w, domain: Domain, params: Params, ij,
-               nthreads=0):
+               nthreads=0, with_links=False):
     """Per-pair (F, Ti, Tj, h, status) for an explicit pair list; j<0 means
-    a wall (-1: z=0, -2: z=L)."""
+    a wall (-1: z=0, -2: z=L).  with_links: also the number of contributing
+    links of each pair (link-wise laws)."""
     r, q, semi, v, w = (_d(x) for x in (r, q, semi, v, w))
     ij = np.ascontiguousarray(ij, dtype=np.int32)
     m = ij.shape[0]
@@ -294,8 +306,11 @@ def eval_pairs(r, q, semi, v, w, domain: Domain, params: Params, ij,
     Tj = np.zeros((m, 3))
     h = np.zeros(m)
     status = np.zeros(m, dtype=np.int32)
+    links = np.zeros(m, dtype=np.int32)
     lib().ref_eval_pairs(r.shape[0], _p(r), _p(q), _p(semi), _p(v), _p(w),
                          C.byref(domain), C.byref(params), m, _p(ij, _I32),
                          int(nthreads), _p(F), _p(Ti), _p(Tj), _p(h),
-                         _p(status, _I32))
+                         _p(status, _I32), _p(links, _I32))
+    if with_links:
+        return F, Ti, Tj, h, status, links
     return F, Ti, Tj, h, status

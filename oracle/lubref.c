@@ -553,6 +553,8 @@ static double cutoff(int r, int c, const ref_params* p) {
 
 static double max_cutoff(const ref_params* p) {
   if (p->model == REF_MODEL_CONTACT) return p->h_c;   /* the repulsion's range */
+  /* link-wise: a site of i within two links (2 sqrt 2) of a site of j */
+  if (p->model == REF_MODEL_LINK || p->model == REF_MODEL_LINK_NAVG) return 2.0 * sqrt(2.0);
   if (p->model != REF_MODEL_FULL) return p->delta_n;  /* only the normal element */
   double m = p->delta_n;
   if (p->delta_t > m) m = p->delta_t;
@@ -778,6 +780,147 @@ int ref_pair_eval(const double d[3], const double qi[4], const double semii[2],
   return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* link-wise law (Sec. II.D, Eq. methods:dlub)                         */
+/* ------------------------------------------------------------------ */
+
+/* the 18 non-zero velocities of the D3Q19 lattice */
+static const int kD3Q19[18][3] = {
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1},
+    {1, 0, -1}, {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+/* a lattice site belongs to a particle when it lies inside or on its
+ * surface */
+static int site_in(const body* b, const double x[3]) { return body_implicit(b, x) <= 0.0; }
+
+/* parameters s_lo <= s_hi where the line x - s u (u unit) crosses the
+ * surface: roots of A s^2 - 2 B s + C = 0 with q(x - s u) = 1 + that */
+static int line_roots(const body* b, const double x[3], const double u[3], double* s_lo,
+                      double* s_hi) {
+  double xb[3], ub[3];
+  to_body(b, x, xb);
+  mattvec3(b->Q, u, ub);
+  double A = 0.0, B = 0.0, C = -1.0;
+  for (int k = 0; k < 3; ++k) {
+    double inv = 1.0 / (b->D[k] * b->D[k]);
+    A += ub[k] * ub[k] * inv;
+    B += xb[k] * ub[k] * inv;
+    C += xb[k] * xb[k] * inv;
+  }
+  double disc = B * B - A * C;
+  if (!(disc >= 0.0) || !(A > 0.0)) return 1;
+  double sq = sqrt(disc);
+  *s_lo = (B - sq) / A;
+  *s_hi = (B + sq) / A;
+  return 0;
+}
+
+/* mean curvature (1/S1 + 1/S2) / 2 at the surface point y (Eq.
+ * lub:curvature-radii) */
+static double mean_curvature(const body* b, const double y[3]) {
+  double yb[3], sp, cp, sq, cq, S1, S2, G0, G2;
+  to_body(b, y, yb);
+  surface_params(b, yb, &sp, &cp, &sq, &cq);
+  surface_coeffs(b, sp, cp, &S1, &S2, &G0, &G2);
+  return 0.5 * (1.0 / S1 + 1.0 / S2);
+}
+
+/* Every lattice link that ends on a site of i and starts on a site of j,
+ * or on a fluid site halfway along two links from a site of j, each
+ * undirected link once.  Its gap h* runs from where the link leaves the
+ * surface of i to where it enters the surface of j; links with h* < |c_r|
+ * carry the force of Eq. methods:dlub on i (minus it on j), at the
+ * crossing points, with lambda* the mean of the two surfaces' mean
+ * curvatures there, the gap clipped at h_c and the link-wise repulsion of
+ * Eq. lub:frep below h_c.  Averaged-normal variant: velocity difference,
+ * gap and force along the normalised difference of the two outward
+ * normals (pointing from j to i). */
+int ref_link_eval(const double ri[3], const double d[3], const double qi[4],
+                  const double semii[2], const double vi[3], const double wi[3],
+                  const double qj[4], const double semij[2], const double vj[3],
+                  const double wj[3], const ref_params* prm, ref_pair_result* out) {
+  memset(out, 0, sizeof(*out));
+  double rj[3] = {ri[0] + d[0], ri[1] + d[1], ri[2] + d[2]};
+  body bi, bj;
+  body_init(&bi, ri, qi, semii);
+  body_init(&bj, rj, qj, semij);
+  const int navg = prm->model == REF_MODEL_LINK_NAVG;
+  int lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    double e = sqrt(bi.M[4 * k]);
+    lo[k] = (int)floor(ri[k] - e);
+    hi[k] = (int)ceil(ri[k] + e);
+  }
+  double hmin = INFINITY;
+  int links = 0;
+  for (int z = lo[2]; z <= hi[2]; ++z)
+    for (int y = lo[1]; y <= hi[1]; ++y)
+      for (int x = lo[0]; x <= hi[0]; ++x) {
+        double xb[3] = {(double)x, (double)y, (double)z};
+        if (!site_in(&bi, xb) || site_in(&bj, xb)) continue;
+        for (int r = 0; r < 18; ++r) {
+          const int* c = kD3Q19[r];
+          double cl = sqrt((double)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
+          double x1[3] = {xb[0] - c[0], xb[1] - c[1], xb[2] - c[2]};
+          if (site_in(&bi, x1)) continue;
+          if (!site_in(&bj, x1)) {
+            /* a fluid site: the pair of links from a site of j */
+            double x2[3] = {xb[0] - 2 * c[0], xb[1] - 2 * c[1], xb[2] - 2 * c[2]};
+            if (!site_in(&bj, x2) || site_in(&bi, x2)) continue;
+          }
+          double u[3] = {c[0] / cl, c[1] / cl, c[2] / cl}; /* from j's side to i */
+          double a0, a1, b0, b1;
+          if (line_roots(&bi, xb, u, &a0, &a1) || line_roots(&bj, xb, u, &b0, &b1)) continue;
+          double hs = b0 - a1;
+          if (!(hs < cl)) continue;
+          ++links;
+          if (hs < hmin) hmin = hs;
+          double pi[3], pj[3], Vi[3], Vj[3], tmp[3], ai[3], aj[3];
+          for (int k = 0; k < 3; ++k) {
+            pi[k] = xb[k] - a1 * u[k];
+            pj[k] = xb[k] - b0 * u[k];
+            ai[k] = pi[k] - ri[k];
+            aj[k] = pj[k] - rj[k];
+          }
+          cross3(wi, ai, tmp);
+          for (int k = 0; k < 3; ++k) Vi[k] = vi[k] + tmp[k];
+          cross3(wj, aj, tmp);
+          for (int k = 0; k < 3; ++k) Vj[k] = vj[k] + tmp[k];
+          double lam = 0.5 * (mean_curvature(&bi, pi) + mean_curvature(&bj, pj));
+          double dir[3], gap;
+          if (navg) {
+            double ni[3], nj[3];
+            body_normal(&bi, pi, ni);
+            body_normal(&bj, pj, nj);
+            for (int k = 0; k < 3; ++k) dir[k] = nj[k] - ni[k];
+            scale3(dir, 1.0 / norm3(dir));
+            gap = hs * dot3(u, dir);
+          } else {
+            memcpy(dir, u, sizeof(dir));
+            gap = hs;
+          }
+          double heff = gap > prm->h_c ? gap : prm->h_c;
+          double dvn = dot3(dir, Vi) - dot3(dir, Vj);
+          double f = 0.0;
+          if (heff > 0.0)
+            f = -3.0 * prm->q_bar * prm->mu / (2.0 * cl * cl * lam) * dvn *
+                (1.0 / (heff * heff) - 1.0 / (cl * cl));
+          if (gap <= prm->h_c) f += gap > 0.0 ? prm->eps_c * (prm->h_c - gap) : prm->eps_c * prm->h_c;
+          double Fl[3] = {f * dir[0], f * dir[1], f * dir[2]};
+          for (int k = 0; k < 3; ++k) out->F[k] += Fl[k];
+          cross3(ai, Fl, tmp);
+          for (int k = 0; k < 3; ++k) out->Ti[k] += tmp[k];
+          cross3(aj, Fl, tmp);
+          for (int k = 0; k < 3; ++k) out->Tj[k] -= tmp[k];
+        }
+      }
+  out->links = links;
+  out->h = links ? hmin : 0.0;
+  out->status = links ? REFP_ACTIVE : REFP_INACTIVE;
+  return 0;
+}
+
 /* particle-wall: the wall is the second surface with infinite radii
  * (Appendix, wall remark); closest point on the particle is its support
  * point towards the wall */
@@ -958,8 +1101,12 @@ static void eval_one(int64_t n, const double* r, const double* q,
     const int m = pair_image(&r[3 * i], &r[3 * j], dom, d);
     /* velocity of the image of j that d points to */
     double vj[3] = {v[3 * j] - m * dom->le_velocity, v[3 * j + 1], v[3 * j + 2]};
-    ref_pair_eval(d, &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i], &q[4 * j],
-                  &semi[2 * j], vj, &w[3 * j], prm, o);
+    if (prm->model == REF_MODEL_LINK || prm->model == REF_MODEL_LINK_NAVG)
+      ref_link_eval(&r[3 * i], d, &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i], &q[4 * j],
+                    &semi[2 * j], vj, &w[3 * j], prm, o);
+    else
+      ref_pair_eval(d, &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i], &q[4 * j],
+                    &semi[2 * j], vj, &w[3 * j], prm, o);
   } else {
     ref_wall_eval(&r[3 * i], &q[4 * i], &semi[2 * i], &v[3 * i], &w[3 * i],
                   -j - 1, dom, prm, o);
@@ -989,6 +1136,12 @@ static int valid_inputs(int64_t n, const double* r, const double* q,
       (!dom->periodic[0] || !dom->periodic[1] || !dom->periodic[2] || dom->n_walls ||
        !isfinite(dom->le_offset) || !isfinite(dom->le_velocity)))
     return 0;
+  if (prm->model == REF_MODEL_LINK || prm->model == REF_MODEL_LINK_NAVG) {
+    /* lattice images of the sites: integer periodic lengths, no walls */
+    if (dom->n_walls || dom->lees_edwards || !(prm->q_bar > 0.0)) return 0;
+    for (int k = 0; k < 3; ++k)
+      if (dom->periodic[k] && dom->L[k] != floor(dom->L[k])) return 0;
+  }
   for (int64_t i = 0; i < n; ++i) {
     for (int k = 0; k < 3; ++k)
       if (!isfinite(r[3 * i + k]) || !isfinite(v[3 * i + k]) ||
@@ -1149,7 +1302,7 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
                    const double* semi, const double* v, const double* w,
                    const ref_domain* dom, const ref_params* prm, int64_t np,
                    const int32_t* ij, int nthreads, double* F, double* Ti,
-                   double* Tj, double* h, int32_t* status) {
+                   double* Tj, double* h, int32_t* status, int32_t* links) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -1164,6 +1317,7 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
     }
     h[p] = o.h;
     status[p] = o.status;
+    if (links) links[p] = o.links;
   }
   return REF_OK;
 }

@@ -63,6 +63,8 @@ extern "C" {
 #define REF_MODEL_NORMAL 1
 #define REF_MODEL_LADD 2
 #define REF_MODEL_CONTACT 3 /* no lubrication: the repulsion of Eq. lub:frep alone */
+#define REF_MODEL_LINK 4    /* link-wise law of Ding and Aidun, Eq. methods:dlub */
+#define REF_MODEL_LINK_NAVG 5 /* the same projected on the average normal (Clausen) */
 
 typedef struct {
   double mu;       /* dynamic viscosity */
@@ -73,6 +75,7 @@ typedef struct {
   double eps_c;    /* Hookean stiffness of Eq. lub:frep */
   int32_t model;   /* REF_MODEL_*; the reduced models are active below delta_n */
   int32_t reserved;
+  double q_bar;    /* empirical weight of the link-wise law (0.6) */
 } ref_params;
 
 typedef struct {
@@ -113,6 +116,8 @@ typedef struct {
   double F[3];         /* force on i, world frame (force on j = -F) */
   double Ti[3];        /* torque on i about r_i */
   double Tj[3];        /* torque on j about r_j */
+  int32_t links;       /* link-wise laws: contributing links (h* < |c_r|) */
+  int32_t pad_;
 } ref_pair_result;
 
 typedef struct {
@@ -153,6 +158,15 @@ int ref_pair_eval(const double d[3], const double qi[4], const double semii[2],
                   const double vi[3], const double wi[3], const double qj[4],
                   const double semij[2], const double vj[3], const double wj[3],
                   const ref_params* prm, ref_pair_result* out);
+
+/* Link-wise laws (REF_MODEL_LINK, REF_MODEL_LINK_NAVG) for one particle
+ * pair: ri is i's absolute centre (the lattice sites are the integer
+ * points), d the offset of j's image.  out->h is the smallest link gap,
+ * out->links the number of contributing links. */
+int ref_link_eval(const double ri[3], const double d[3], const double qi[4],
+                  const double semii[2], const double vi[3], const double wi[3],
+                  const double qj[4], const double semij[2], const double vj[3],
+                  const double wj[3], const ref_params* prm, ref_pair_result* out);
 
 /* Same for a particle and a wall (side 0: z=0, side 1: z=L). */
 int ref_wall_eval(const double ri[3], const double qi[4], const double semii[2],
@@ -206,7 +220,7 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
                    const ref_domain* dom, const ref_params* prm,
                    int64_t np, const int32_t* ij, int nthreads,
                    double* F, double* Ti, double* Tj, double* h,
-                   int32_t* status);
+                   int32_t* status, int32_t* links);
 
 #ifdef __cplusplus
 }

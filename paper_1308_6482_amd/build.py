@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblub.so")
 SOURCES = ["lub_api.hip", "lub_neighbors.hip", "lub_pair.hip", "lub_gather.hip",
-           "lub_mlp.hip", "lub_integrate.hip"]
+           "lub_mlp.hip", "lub_integrate.hip", "lub_link.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

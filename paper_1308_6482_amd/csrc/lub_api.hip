@@ -49,6 +49,7 @@ struct lub_ctx {
   int32_t* slot = nullptr;         // [n * cur_nbr] evaluation slot, -1, -2
   int32_t* work_s = nullptr;       // [work]
   int32_t* fail_list = nullptr;    // [work] slots left to the tangent-sphere pass
+  int32_t* out_links = nullptr;    // [work] link-wise laws: contributing links
   int32_t* work_t = nullptr;       // [work]
   void* out = nullptr;             // [work] PairOut<double> (or float)
   double* out_h = nullptr;         // [work]
@@ -147,9 +148,13 @@ int grow(T** p, int64_t* cap, int64_t need) {
   return LUB_OK;
 }
 
+bool is_link(int model) { return model == LUB_MODEL_LINK || model == LUB_MODEL_LINK_NAVG; }
+
 // candidate and activity cut-off: the reduced models act below delta_n only
 double max_cutoff(const lub_params_t& p) {
   if (p.model == LUB_MODEL_CONTACT) return p.h_c;
+  // link-wise: a site of i within two links (2 sqrt 2) of a site of j
+  if (is_link(p.model)) return 2.0 * std::sqrt(2.0);
   if (p.model != LUB_MODEL_FULL) return p.delta_n;
   return std::max(p.delta_n, std::max(p.delta_t, p.delta_r));
 }
@@ -159,9 +164,10 @@ int check_params(const lub_params_t* p) {
   if (!(p->mu >= 0.0) || !(p->delta_n > 0.0) || !(p->delta_t > 0.0) ||
       !(p->delta_r > 0.0) || !(p->h_c >= 0.0) || !(p->eps_c >= 0.0))
     return LUB_EINVAL;
-  if (p->model < LUB_MODEL_FULL || p->model > LUB_MODEL_CONTACT || p->reserved != 0)
+  if (p->model < LUB_MODEL_FULL || p->model > LUB_MODEL_LINK_NAVG || p->reserved != 0)
     return LUB_EINVAL;
   if (p->model == LUB_MODEL_CONTACT && !(p->h_c > 0.0)) return LUB_EINVAL;
+  if (is_link(p->model) && !(p->q_bar > 0.0 && std::isfinite(p->q_bar))) return LUB_EINVAL;
   return LUB_OK;
 }
 
@@ -226,7 +232,7 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
   if (c->cap_work < work || !c->work_s) {
     c->cap_work = 0;
     if ((rc = realloc_buf(&c->work_s, work)) || (rc = realloc_buf(&c->work_t, work)) ||
-        (rc = realloc_buf(&c->fail_list, work)) ||
+        (rc = realloc_buf(&c->fail_list, work)) || (rc = realloc_buf(&c->out_links, work)) ||
         (rc = realloc_buf((PairOut<double>**)&c->out, work)) ||
         (rc = realloc_buf(&c->out_h, work)) || (rc = realloc_buf(&c->out_status, work)) ||
         (rc = realloc_buf(&c->out_iters, work)))
@@ -304,6 +310,14 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->max_nbr = c->cur_nbr;
   d->precision = c->opt.precision;
   d->model = c->prm.model;
+  d->q_bar = c->prm.q_bar;
+  if (is_link(d->model)) {
+    // FP64 outputs; lattice images need integer periodic lengths
+    d->precision = LUB_FP64;
+    if (c->dom.n_walls || c->dom.lees_edwards) return LUB_EINVAL;
+    for (int k = 0; k < 3; ++k)
+      if (c->dom.periodic[k] && c->dom.L[k] != std::floor(c->dom.L[k])) return LUB_EINVAL;
+  }
   // two size classes with cells of their own: a particle searches the small
   // ones within its own size + r_small + the cut-off only
   d->r_small = 0.5 * c->opt.rmax_bound;
@@ -350,7 +364,8 @@ CallDesc finalize_desc(const lub_ctx* c, const CallDesc& d0) {
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
   // Ladd's law has no closest-point iteration to start
-  d.warm_mask = c->opt.warm_start && c->warm_size > 0 && d.model != LUB_MODEL_LADD
+  d.warm_mask = c->opt.warm_start && c->warm_size > 0 && d.model != LUB_MODEL_LADD &&
+                        !is_link(d.model)
                     ? c->warm_size - 1
                     : 0;
   return d;
@@ -416,17 +431,26 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                           c->work_t, c->stat_nbr, c->cnt, s);
     mark(2);
     const float* seeds = nullptr;
-    if (c->opt.seed_mode == LUB_SEED_MLP) {
+    if (c->opt.seed_mode == LUB_SEED_MLP && !is_link(d.model)) {
       launch_seed_features(d, c->rec, c->work_s, c->work_t, c->seedX, c->cnt, s);
       mlp_forward_slots(c->cnt, d.cap_work, c->seedX, c->seedY, c->wt, c->th, s);
       seeds = c->seedY;
     }
     WarmTables warm{c->warm_key[wp], c->warm_val[wp], c->warm_key[wc], c->warm_val[wc],
                     c->sorted};
-    launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
-                 c->out_h, c->out_status, c->out_iters, warm, c->fail_list, c->stat_pair,
-                 c->cnt, s,
-                 timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
+    if (is_link(d.model)) {
+      launch_links(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h, c->out_status,
+                   c->out_links, c->stat_pair, c->cnt, s);
+      if (timing) {  // no separate kernel stamps: the stage time
+        hipEventRecord(ev[5], s);
+        hipEventRecord(ev[6], s);
+      }
+    } else {
+      launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
+                   c->out_h, c->out_status, c->out_iters, warm, c->fail_list, c->stat_pair,
+                   c->cnt, s,
+                   timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
+    }
     mark(3);
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
                   c->cnt, next_cnt, d.warm_mask ? c->warm_key[wp] : nullptr,
@@ -458,7 +482,8 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
           c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->pos, c->kin,
           c->nbr,
-          c->slot, c->work_s, c->work_t, c->fail_list, c->out, c->out_h, c->out_status,
+          c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
+          c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
           c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1]};
 }
@@ -906,13 +931,19 @@ int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
   std::vector<int32_t> sorted(n), ws(m), wt(m);
   std::vector<double> hh(m);
   std::vector<int8_t> st(m);
-  std::vector<uint8_t> it(m);
+  std::vector<int32_t> it(m);
   HIP_TRY(hipMemcpy(sorted.data(), h->sorted, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(ws.data(), h->work_s, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(wt.data(), h->work_t, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(hh.data(), h->out_h, sizeof(double) * m, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(st.data(), h->out_status, m, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(it.data(), h->out_iters, m, hipMemcpyDeviceToHost));
+  if (is_link(h->last.model)) {
+    HIP_TRY(hipMemcpy(it.data(), h->out_links, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<uint8_t> it8(m);
+    HIP_TRY(hipMemcpy(it8.data(), h->out_iters, m, hipMemcpyDeviceToHost));
+    for (int k = 0; k < m; ++k) it[k] = it8[k];
+  }
   const bool mixed = h->last.precision == LUB_MIXED;
   std::vector<double> od(9 * (size_t)m);
   if (mixed) {
@@ -1033,6 +1064,7 @@ void lub_destroy(lub_handle_t h) {
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
                   h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
+                  h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
                   h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
                   h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,

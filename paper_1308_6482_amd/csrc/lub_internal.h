@@ -82,6 +82,7 @@ struct CallDesc {
   double rmax_bound;
   double dmax;           // largest cut-off
   double mu, delta_n, delta_t, delta_r, h_c, eps_c;
+  double q_bar;          // weight of the link-wise laws
   int32_t max_iter;
   int32_t max_nbr;       // neighbour-segment stride (entries per particle)
   int32_t cap_entries;
@@ -187,6 +188,12 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
                    int64_t warm_size, double* f, double* t, hipStream_t s);
+
+// ---- link-wise laws (lub_link.hip) ------------------------------------------
+int link_grid(const CallDesc& d);
+void launch_links(const CallDesc& d, const PRec* rec, const KRec* kin, const int32_t* work_s,
+                  const int32_t* work_t, void* out, double* out_h, int8_t* out_status,
+                  int32_t* out_links, int64_t* stat_pair, Counters* cnt, hipStream_t s);
 
 // ---- integrator (lub_integrate.hip) ---------------------------------------
 struct StepDesc {

@@ -44,7 +44,7 @@ class lub_params_t(C.Structure):
     _fields_ = [("mu", C.c_double), ("delta_n", C.c_double),
                 ("delta_t", C.c_double), ("delta_r", C.c_double),
                 ("h_c", C.c_double), ("eps_c", C.c_double),
-                ("model", C.c_int32), ("reserved", C.c_int32)]
+                ("model", C.c_int32), ("reserved", C.c_int32), ("q_bar", C.c_double)]
 
 
 class lub_domain_t(C.Structure):
@@ -145,11 +145,13 @@ def _check(rc: int, where: str):
 
 
 LUB_MODEL_FULL, LUB_MODEL_NORMAL, LUB_MODEL_LADD, LUB_MODEL_CONTACT = 0, 1, 2, 3
+LUB_MODEL_LINK, LUB_MODEL_LINK_NAVG = 4, 5
 
 
 def make_params(mu, delta_n, delta_t, delta_r, h_c=0.0, eps_c=0.0,
-                model=LUB_MODEL_FULL) -> lub_params_t:
-    return lub_params_t(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0)
+                model=LUB_MODEL_FULL, q_bar=0.6) -> lub_params_t:
+    return lub_params_t(mu, delta_n, delta_t, delta_r, h_c, eps_c, int(model), 0,
+                        float(q_bar))
 
 
 def make_domain(L, periodic=(1, 1, 1), n_walls=0,

@@ -296,6 +296,24 @@ def sheared(seed: int = 0, n: int = 4096, phi: float = 0.3, offset_frac: float =
                     lees_edwards=(off, gd * Lx))
 
 
+def lattice_box(seed: int = 0, n: int = 2347, L: int = 128, semi=(4.0, 4.0)) -> Workload:
+    """Particles on the lattice of a periodic cube of integer edge L (the
+    link-wise laws need lattice images): the paper's many-particle
+    benchmarks use spheres of radius 4 in 128^3 (n = 2347 is volume fraction
+    0.3).  semi = (R_par, R_perp) of every particle; random sequential
+    addition; simple-shear velocities."""
+    g_pos, _, g_vel, _ = _streams(seed + 11)
+    sm = np.tile(np.array(semi, dtype=np.float64), (n, 1))
+    Lb = (float(L), float(L), float(L))
+    r, q, trials = rsa(g_pos, sm, Lb, (1, 1, 1))
+    if r.shape[0] != n:
+        raise RuntimeError("lattice_box: random sequential addition ran out of trials")
+    v, w = shear_velocities(g_vel, r)
+    phi = n * 4.0 / 3.0 * np.pi * semi[0] * semi[1] ** 2 / float(L) ** 3
+    return Workload(f"lattice{n}_L{L}_{semi[0]:g}x{semi[1]:g}_phi{phi:.2f}", r, q, sm, v, w, Lb,
+                    (1, 1, 1), meta=dict(phi=phi, rsa_trials=trials))
+
+
 def polydisperse_semi(rng: np.random.Generator, n: int, lam_lo: float,
                       lam_hi: float, rperp_lo: float, rperp_hi: float):
     lam = np.exp(rng.uniform(np.log(lam_lo), np.log(lam_hi), size=n))
