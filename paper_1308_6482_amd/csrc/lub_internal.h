@@ -59,7 +59,7 @@ struct Counters {
 constexpr int kStatPairWords = 40;
 constexpr int kStatNbrWords = 3;
 constexpr int kMaxPairBlocks = 16384;  // larger slot counts: grid-stride loop
-constexpr int kTangentBlocks = 64;     // grid of the tangent-sphere pass
+constexpr int kTangentBlocks = 8;      // grid of the tangent-sphere pass
 
 // Constant description of one call.
 struct CallDesc {

@@ -18,10 +18,12 @@
 // The force acts on i at its crossing point and the opposite force on j at
 // its crossing point.
 //
-// One wavefront per pair: its lanes share the sites of the box where sites
-// of i can be linked to sites of j (the bounding box of i cut to that of j
-// widened by three lattice units, more than the two-link reach 2 sqrt 2);
-// per-lane sums are combined by a fixed butterfly.  FP64 throughout.
+// One wavefront per pair over the box where sites of i can be linked to
+// sites of j (the bounding box of i cut to that of j widened by three
+// lattice units, more than the two-link reach 2 sqrt 2), 64 sites at a time:
+// each lane tests a site, the sites of i within the reach of j are
+// compacted, and their (site, direction) items are spread over the lanes.
+// Per-lane sums are combined by a fixed butterfly.  FP64 throughout.
 #include <hip/hip_runtime.h>
 
 #include "lub_internal.h"
@@ -111,6 +113,7 @@ __global__ void __launch_bounds__(64 * kLinkWaves)
             int64_t* __restrict__ stat_pair, const Counters* cnt) {
 #pragma clang fp contract(off)
   __shared__ int64_t s_stat[kLinkWaves][4];
+  __shared__ int32_t s_list[kLinkWaves][64];   // per wavefront: the kept sites
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
   if (blockIdx.x * kLinkSlots >= nwork) return;
@@ -141,13 +144,37 @@ __global__ void __launch_bounds__(64 * kLinkWaves)
           n3[k] = max(0, h0 - l0 + 1);
         }
         const int nsites = n3[0] * n3[1] * n3[2];
-        for (int idx = lane; idx < nsites; idx += 64) {
-          const int x = lo[0] + idx % n3[0];
-          const int y = lo[1] + (idx / n3[0]) % n3[1];
-          const int z = lo[2] + idx / (n3[0] * n3[1]);
-          const double xb[3] = {(double)x, (double)y, (double)z};
-          if (!site_in(A, ri, xb) || site_in(B, rj, xb)) continue;
-          for (int r = 0; r < 18; ++r) {
+        // a site farther than the two-link reach 2 sqrt 2 from j carries no
+        // link: the body scaled by s = sqrt(q_j) lies at least
+        // (s - 1) min(R_par, R_perp) outside it
+        const double reach = (2.0 * sqrt(2.0)) * (1.0 + 1e-9) + 1e-9;
+        const double rminB = fmin(B.Rpar, B.Rperp);
+        for (int base = 0; base < nsites; base += 64) {
+          // phase 1: each lane tests one site; the sites of i within the
+          // two-link reach of j are compacted into the wavefront's list
+          const int idx = base + lane;
+          bool keep = false;
+          if (idx < nsites) {
+            const double xb[3] = {(double)(lo[0] + idx % n3[0]),
+                                  (double)(lo[1] + (idx / n3[0]) % n3[1]),
+                                  (double)(lo[2] + idx / (n3[0] * n3[1]))};
+            if (site_in(A, ri, xb)) {
+              const double yj[3] = {xb[0] - rj[0], xb[1] - rj[1], xb[2] - rj[2]};
+              const double qj = quad_form(B, yj);
+              keep = qj > 1.0 && !((sqrt(qj) - 1.0) * rminB > reach);
+            }
+          }
+          const unsigned long long m = __ballot(keep);
+          if (keep) s_list[wv][__popcll(m & ((1ull << lane) - 1ull))] = idx;
+          __builtin_amdgcn_wave_barrier();
+          const int nk = __popcll(m);
+          // phase 2: the (site, direction) items spread over the lanes
+          for (int it = lane; it < 18 * nk; it += 64) {
+            const int sidx = s_list[wv][it / 18];
+            const int r = it % 18;
+            const double xb[3] = {(double)(lo[0] + sidx % n3[0]),
+                                  (double)(lo[1] + (sidx / n3[0]) % n3[1]),
+                                  (double)(lo[2] + sidx / (n3[0] * n3[1]))};
             const int c[3] = {kD3Q19[r][0], kD3Q19[r][1], kD3Q19[r][2]};
             const double cl = sqrt((double)(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]));
             const double x1[3] = {xb[0] - c[0], xb[1] - c[1], xb[2] - c[2]};
@@ -201,6 +228,7 @@ __global__ void __launch_bounds__(64 * kLinkWaves)
             cross3d(aj, Fl, tmp);
             for (int k = 0; k < 3; ++k) acc[6 + k] -= tmp[k];
           }
+          __builtin_amdgcn_wave_barrier();
         }
       }
       // fixed butterfly over the wavefront
