@@ -10,7 +10,7 @@ Default workload: 4096 prolate spheroids (semi-axes 8,4,4) at volume
 fraction 0.3 in a periodic cube, simple-shear velocities, seed 0, mixed
 precision.  One step = one lub_compute call on that suspension.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -477,7 +477,7 @@ def main():
         traffic_summary(*args.traffic_summary, args.precision)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np  # noqa: F401
     import torch

@@ -17,8 +17,8 @@
  *   - closest points: the Lin-Han tangent-sphere iteration with the paper's
  *     two-fold radius strategy (Sec. III.A, Eqs. lub:minimum-radius and
  *     lub:convergence), then a Newton polish of the same fixed point to
- *     round-off (reading Q1 in the design notes), then a duality
- *     certificate for separated pairs;
+ *     round-off (the paper's tolerance on cos theta leaves the angle at
+ *     about 1e-3), then a duality certificate for separated pairs;
  *   - local geometry: Eq. lub:spheroid parametrisation, principal
  *     directions and radii (Eqs. lub:curvature-directions,
  *     lub:curvature-radii), cubic coefficients Gamma_0, Gamma_2 (Sec. III.B);
@@ -27,7 +27,20 @@
  *     kappa as defined there, the corrective matrix of Eq.
  *     lub:resistance-correction and the contact model of Eqs. lub:frep and
  *     lub:model;
- *   - rigid-body transfer of Sec. III.B (last equations of the section).
+ *   - rigid-body transfer of Sec. III.B (last equations of the section);
+ *   - the comparison laws: normal only (K33 alone), Ladd's sphere law
+ *     (Eq. methods:llub), the contact repulsion alone (growth stage of
+ *     Sec. IV.A), and the link-wise laws of Sec. II.D (Eq. methods:dlub,
+ *     Ding-Aidun and the averaged-normal variant) over the D3Q19 links
+ *     between the lattice sites of the two particles;
+ *   - Lees-Edwards images of a sheared periodic box (Sec. IV.A).
+ *
+ * Parity unpinned (no check independent of this code fixes them): the
+ * absolute signs of K13/K23 and K34/K35 beyond the swap, relabel and
+ * surface-fit consistency the tests verify; the Lin-Han iteration count
+ * (a band around the paper's "almost 40" for aspect ratio 1/3); lambda* of
+ * the link-wise law for non-spherical particles (the mean of the two
+ * surfaces' mean curvatures; spheres are pinned in closed form).
  *
  * Conventions (the paper leaves them implicit):
  *   q = (w,x,y,z) unit quaternion, x_world = Q(q) x_body, body z axis =

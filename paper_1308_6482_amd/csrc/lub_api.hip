@@ -21,6 +21,11 @@ struct lub_ctx {
   hipStream_t last_stream = nullptr;
   CallDesc last{};
   bool have_last = false;
+  // a second stream (default priority) for the partner-slot codes, forked
+  // from the call's stream after the neighbour lists and joined before the
+  // gather
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // workspace
   int64_t cap_n = 0, cap_cells = 0, cap_entries = 0, cap_work = 0, cap_bs = 0;
@@ -311,6 +316,8 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->precision = c->opt.precision;
   d->model = c->prm.model;
   d->q_bar = c->prm.q_bar;
+  d->ln_delta_t = std::log(c->prm.delta_t);
+  d->ln_delta_r = std::log(c->prm.delta_r);
   if (is_link(d->model)) {
     // FP64 outputs; lattice images need integer periodic lengths
     d->precision = LUB_FP64;
@@ -363,6 +370,10 @@ CallDesc finalize_desc(const lub_ctx* c, const CallDesc& d0) {
   CallDesc d = d0;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
+  // from about a quarter million particles the partner codes, written
+  // beside the pair kernel, save the gather its searches; below, the fork
+  // and join cost more than they save
+  d.partner_codes = d.n >= (1 << 18);
   // Ladd's law has no closest-point iteration to start
   d.warm_mask = c->opt.warm_start && c->warm_size > 0 && d.model != LUB_MODEL_LADD &&
                         !is_link(d.model)
@@ -430,6 +441,13 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                           c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                           c->work_t, c->stat_nbr, c->cnt, s);
     mark(2);
+    // the partner-slot codes beside the pair kernel
+    if (d.partner_codes) {
+      HIP_TRY(hipEventRecord(c->ev_fork, s));
+      HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      launch_partner_slots(d, c->work_s, c->work_t, c->deg, c->nbr, c->slot, c->cnt, c->side);
+      HIP_TRY(hipEventRecord(c->ev_join, c->side));
+    }
     const float* seeds = nullptr;
     if (c->opt.seed_mode == LUB_SEED_MLP && !is_link(d.model)) {
       launch_seed_features(d, c->rec, c->work_s, c->work_t, c->seedX, c->cnt, s);
@@ -452,6 +470,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                    timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
     }
     mark(3);
+    if (d.partner_codes) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
                   c->cnt, next_cnt, d.warm_mask ? c->warm_key[wp] : nullptr,
                   d.warm_mask ? c->warm_size : 0, f, t, s);
@@ -648,6 +667,12 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_ENOMEM;
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    lub_destroy(c);
+    return LUB_EDEVICE;
+  }
   c->cnt = c->cnt_buf;
   if (hipMemset(c->cnt_buf, 0, 2 * sizeof(Counters)) != hipSuccess) {
     lub_destroy(c);
@@ -1073,6 +1098,12 @@ void lub_destroy(lub_handle_t h) {
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);
+  if (h->side) {
+    hipStreamSynchronize(h->side);
+    hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
   for (auto& ev : h->pending)
     for (hipEvent_t e : ev) h->free_events.push_back(e);
   for (hipEvent_t e : h->free_events) hipEventDestroy(e);

@@ -42,6 +42,28 @@ __device__ __forceinline__ int find_entry(const int32_t* __restrict__ seg, int n
 constexpr int kGroup = 16;
 constexpr int kPerWave = 64 / kGroup;
 
+// For every evaluated particle pair (slot w, owner s, partner t): the
+// position of s in t's sorted segment, where the entry's code becomes
+// -3 - w, so that the gather reads the partner's result without a search.
+// Entries of pairs the owner did not evaluate keep -2.  Runs beside the
+// pair kernel (it reads only the neighbour kernel's output).
+__global__ void k_partner_slots(CallDesc d, const int32_t* __restrict__ work_s,
+                                const int32_t* __restrict__ work_t,
+                                const int32_t* __restrict__ deg,
+                                const int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
+                                const Counters* cnt) {
+  const int nwork = cnt->error == 0 ? min(cnt->work, d.cap_work) : 0;
+  const size_t stride = (size_t)d.max_nbr;
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nwork;
+       w += gridDim.x * blockDim.x) {
+    const int t = work_t[w];
+    if (t < 0) continue;  // wall slot
+    const int s = work_s[w];
+    const int kk = find_entry(nbr + (size_t)t * stride, deg[t], s);
+    if (kk >= 0) slot[(size_t)t * stride + kk] = -3 - w;
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
@@ -75,10 +97,15 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
           acc[c] += (double)o.F[c];
           acc[3 + c] += (double)o.Ti[c];
         }
-      } else if (sl == -2) {
-        const int p = nbr[e];
-        const int kk = find_entry(nbr + (size_t)p * stride, deg[p], s);
-        const int sp = kk >= 0 ? slot[(size_t)p * stride + kk] : -1;
+      } else if (sl <= -3 || (sl == -2 && !d.partner_codes)) {
+        // the partner owns the pair: its slot code (k_partner_slots), or
+        // found in the partner's sorted segment
+        int sp = -3 - sl;
+        if (sl == -2) {
+          const int p = nbr[e];
+          const int kk = find_entry(nbr + (size_t)p * stride, deg[p], s);
+          sp = kk >= 0 ? slot[(size_t)p * stride + kk] : -1;
+        }
         if (sp >= 0) {
           const PairOut<R>& o = out[sp];
           for (int c = 0; c < 3; ++c) {
@@ -113,6 +140,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
 }
 
 }  // namespace
+
+void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_t* work_t,
+                          const int32_t* deg, const int32_t* nbr, int32_t* slot,
+                          const Counters* cnt, hipStream_t s) {
+  int blocks = (d.cap_work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_partner_slots, dim3(blocks), dim3(256), 0, s, d, work_s, work_t, deg,
+                     nbr, slot, cnt);
+}
 
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,

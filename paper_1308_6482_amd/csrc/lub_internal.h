@@ -83,11 +83,15 @@ struct CallDesc {
   double dmax;           // largest cut-off
   double mu, delta_n, delta_t, delta_r, h_c, eps_c;
   double q_bar;          // weight of the link-wise laws
+  double ln_delta_t, ln_delta_r;  // log of the cut-offs (host-evaluated once)
   int32_t max_iter;
   int32_t max_nbr;       // neighbour-segment stride (entries per particle)
   int32_t cap_entries;
   int32_t cap_work;
   int32_t precision;
+  int32_t partner_codes;  // the partner's slot code is written into every
+                          // non-owned entry of an evaluated pair (large
+                          // systems); else the gather searches for it
 };
 
 // Pair output record: force on i, torque on i and torque on j about the
@@ -183,6 +187,10 @@ void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
                        const __bf16* wt, const float* th, hipStream_t s);
 
 // per-particle sums; also zeroes `next_cnt`, the counters of the next call
+// the partner's slot code in every non-owned entry of an evaluated pair
+void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_t* work_t,
+                          const int32_t* deg, const int32_t* nbr, int32_t* slot,
+                          const Counters* cnt, hipStream_t s);
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,

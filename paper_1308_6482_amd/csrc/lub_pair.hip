@@ -696,8 +696,9 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   // cut-off factors (FP64), Eq. lub:resistance-correction; the "normal
   // only" model drops every element but K33
   const bool full = cd.model == LUB_MODEL_FULL;
-  double Lt = full && heff < cd.delta_t ? log(heff) - log(cd.delta_t) : 0.0;
-  double Lr = full && heff < cd.delta_r ? log(heff) - log(cd.delta_r) : 0.0;
+  const double lh = full && heff < fmax(cd.delta_t, cd.delta_r) ? log(heff) : 0.0;
+  double Lt = full && heff < cd.delta_t ? lh - cd.ln_delta_t : 0.0;
+  double Lr = full && heff < cd.delta_r ? lh - cd.ln_delta_r : 0.0;
   // the contact-only law has no resistance: the repulsion below acts alone
   const bool lub = cd.model != LUB_MODEL_CONTACT;
   double Ln = lub && heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded inputs.
 
-Bars (written here, derived in the design notes):
+Bars:
   * candidate pair lists: bit-exact (same FP64 centre test);
   * LUB_FP64: per-pair force and torque within 1e-9 relative, per-particle
     sums within 1e-9 of max(|ref|, 1e-3 rms) -- the two sides use different
