@@ -61,6 +61,10 @@ def parse():
                     help="warm-start leg: positions advanced by v dt between the K timed "
                          "evaluations (0: skip the leg; default 1 for the full-scale "
                          "system, 0.1 otherwise)")
+    ap.add_argument("--skin", type=float, nargs="*", default=None,
+                    help="trajectory leg: also time reused neighbour lists with these skins "
+                         "(default 2 for the full-scale system, 1 otherwise; none given: "
+                         "skip)")
     ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
                     help="Newton start: line of centres, learned network, or time both "
                          "(the JSON value is the plain form unless --seed mlp)")
@@ -336,19 +340,23 @@ def measure(L, torch, wl, prec, args, theta=None):
     return results["eager"][0], results["graph"][1], results["eager"][1], (f, t)
 
 
-def trajectory(L, torch, wl, prec, args, warm):
+def trajectory(L, torch, wl, prec, args, warm, skin=0.0):
     """K evaluations along a moving suspension (positions advanced in place
     by v dt after each evaluation, graph replay), with or without the warm
-    start; returns a report of the last evaluation and the timing."""
+    start, or (skin > 0, eager and synchronous) with reused neighbour lists;
+    returns a report of the last evaluation and the timing."""
     import numpy as np
     r0, q, semi, v, w = L.to_device(wl)
     r = r0.clone()
     f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
-    lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm),
-                            max_neighbors=args.max_neighbors)
-    iters = evaluated = seeded = 0
+    if skin > 0.0:
+        # the superset needs wider segments: automatic capacity
+        lb = L.Lub.for_workload(wl, precision=prec, sync=0, skin=skin)
+    else:
+        lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm),
+                                max_neighbors=args.max_neighbors)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
@@ -370,6 +378,10 @@ def trajectory(L, torch, wl, prec, args, warm):
     ms = (t1 - t0) * 1e3 / args.steps
     hist = np.array(st["iter_hist"], dtype=np.int64)
     cdf = np.cumsum(hist) / max(hist.sum(), 1)
+    extra = {}
+    if skin > 0.0:
+        extra = dict(skin=skin, list_searches=st["list_builds"] - st0["list_builds"],
+                     calls=args.steps)
     return dict(value=st["active"] / (ms * 1e-3), ms_per_step=ms, active=st["active"],
                 overlaps=st["overlaps"], evaluated=st["evaluated"],
                 unconverged=st["unconverged"], unresolved=st["unresolved"],
@@ -377,7 +389,7 @@ def trajectory(L, torch, wl, prec, args, warm):
                 newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
                 newton_iters_p50=int(np.searchsorted(cdf, 0.5)),
                 newton_iters_p99=int(np.searchsorted(cdf, 0.99)),
-                newton_max=st["newton_max"])
+                newton_max=st["newton_max"], **extra)
 
 
 def dynamics(L, torch, args):
@@ -555,6 +567,12 @@ def main():
             dt=args.trajectory_dt,
             warm=trajectory(L, torch, wl, prec, args, True),
             plain=trajectory(L, torch, wl, prec, args, False))
+        skins = args.skin
+        if skins is None:
+            skins = [2.0] if args.workload == "fullscale1M" else [1.0]
+        for sk in skins:
+            res["warm_start"][f"reused_lists_skin{sk:g}"] = trajectory(L, torch, wl, prec,
+                                                                      args, False, sk)
     if args.compare_models and args.model == "full":
         # the paper's "normal only" comparison model on the same suspension
         wn = wl.with_params(model=L.LUB_MODEL_NORMAL)

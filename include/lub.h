@@ -184,6 +184,20 @@ typedef struct {
                            /* does not converge; pairs new to the call use */
                            /* seed_mode.  The paper's time-step continuation (Sec. */
                            /* III.A).  0: every call starts afresh */
+  int32_t reserved;        /* must be 0 */
+  double skin;             /* > 0: reuse the neighbour lists across calls.  A build */
+                           /* keeps every pair within the pruning bound + skin; a */
+                           /* call reuses the lists while every particle moved (minimum */
+                           /* image) plus grew in max(R_par, R_perp) by at most */
+                           /* skin / 2 since the build, re-applying the exact centre */
+                           /* test to the kept pairs, and builds again otherwise (or */
+                           /* when n, the parameters or the domain changed).  The */
+                           /* pair lists equal those of a fresh search.  Every call */
+                           /* then waits for its stream (the decision is taken on */
+                           /* the host).  Needs graph = 0 and no Lees-Edwards images */
+                           /* (else LUB_EINVAL); periodic lengths must hold twice */
+                           /* 2 rmax_bound + cut-off + skin (else LUB_EDOMAIN). */
+                           /* 0: search every call */
 } lub_opts_t;
 
 /* Per-call statistics of the last lub_compute. */
@@ -214,6 +228,8 @@ typedef struct {
                             /* exceeded max_neighbors: the value to set) */
   double pair_kernel_ms;    /* with opts.timing: the pair kernel's own execution */
                             /* time (dispatch timestamps), summed like stage_ms */
+  int64_t list_builds;      /* neighbour-list searches since the handle was created */
+                            /* (one per call unless opts.skin > 0) */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;

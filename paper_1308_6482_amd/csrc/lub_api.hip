@@ -26,6 +26,18 @@ struct lub_ctx {
   // gather
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // reused neighbour lists (opts.skin > 0): the superset segments of the
+  // last build in its cell order, the positions and sizes at the build, the
+  // displacement measure and the bookkeeping of the build
+  int32_t* sup_nbr = nullptr;
+  int32_t* sup_deg = nullptr;
+  double4* ref_pos = nullptr;
+  unsigned long long* disp_word = nullptr;
+  unsigned long long* host_disp = nullptr;
+  bool lists_valid = false;
+  int64_t build_n = -1;
+  int32_t build_stride = 0;
+  int64_t list_builds = 0;
 
   // workspace
   int64_t cap_n = 0, cap_cells = 0, cap_entries = 0, cap_work = 0, cap_bs = 0;
@@ -205,6 +217,10 @@ int ensure_particles(lub_ctx* c, int64_t n) {
       (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks_max((int)need))) ||
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
     return rc;
+  if (c->opt.skin > 0.0 &&
+      ((rc = realloc_buf(&c->sup_deg, need)) || (rc = realloc_buf(&c->ref_pos, need))))
+    return rc;
+  c->lists_valid = false;
   c->cap_n = need;
   return LUB_OK;
 }
@@ -232,6 +248,8 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
     c->cap_entries = 0;
     if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)))
       return rc;
+    if (c->opt.skin > 0.0 && (rc = realloc_buf(&c->sup_nbr, entries))) return rc;
+    c->lists_valid = false;
     c->cap_entries = entries;
   }
   if (c->cap_work < work || !c->work_s) {
@@ -267,7 +285,11 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   std::memset(d, 0, sizeof(*d));
   d->n = (int32_t)n;
   d->dmax = max_cutoff(c->prm);
-  double edge = 2.0 * c->opt.rmax_bound + d->dmax;
+  d->skin = c->opt.skin;
+  if (d->skin > 0.0 && c->dom.lees_edwards) return LUB_EINVAL;
+  // cells sized for the widest search: the pair bound plus the skin of
+  // reused lists
+  double edge = 2.0 * c->opt.rmax_bound + d->dmax + d->skin;
   for (int k = 0; k < 3; ++k) {
     d->L[k] = c->dom.L[k];
     d->invL[k] = 1.0 / c->dom.L[k];
@@ -423,7 +445,25 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       HIP_TRY(hipMemsetAsync(c->warm_key[wc], 0xff, sizeof(uint64_t) * c->warm_size, s));
   }
   c->zeroed = false;
-  if (d.n > 0) {
+  // reused neighbour lists: build again unless every particle stayed within
+  // half the skin of its place (and size) at the last build
+  bool rebuild = true;
+  if (d.n > 0 && d.skin > 0.0) {
+    rebuild = !c->lists_valid || c->build_n != d.n || c->build_stride != d.max_nbr;
+    if (!rebuild) {
+      HIP_TRY(hipMemsetAsync(c->disp_word, 0, sizeof(unsigned long long), s));
+      launch_disp(d, c->sorted, r, q, semi, c->ref_pos, c->disp_word, s);
+      HIP_TRY(hipMemcpyAsync(c->host_disp, c->disp_word, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double m;
+      std::memcpy(&m, c->host_disp, sizeof(m));
+      rebuild = !(2.0 * m <= d.skin * (1.0 - 1e-12));
+    }
+  }
+  if (d.n > 0 && !rebuild) {
+    launch_refresh(d, c->sorted, r, q, semi, v, w, c->rec, c->pos, c->kin, s);
+  } else if (d.n > 0) {
     if (small) {
       launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->pos,
                          c->kin, c->cell_sorted, c->cnt, s);
@@ -436,10 +476,31 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                            q, semi, v, w, c->sorted, c->rec, c->pos, c->kin, c->cell_sorted,
                            s);
     }
+  }
+  if (d.n > 0) {
     mark(1);
-    launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
-                          c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
-                          c->work_t, c->stat_nbr, c->cnt, s);
+    if (d.skin > 0.0) {
+      // superset of the build (its cell order), then the exact filter
+      if (rebuild) {
+        launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+                              c->sup_deg, c->sup_nbr, c->slot, c->wall_slot, c->work_s,
+                              c->work_t, c->stat_nbr, c->cnt, s, 1);
+        HIP_TRY(hipMemcpyAsync(c->ref_pos, c->pos, sizeof(double4) * d.n,
+                               hipMemcpyDeviceToDevice, s));
+        c->lists_valid = true;
+        c->build_n = d.n;
+        c->build_stride = d.max_nbr;
+        c->list_builds++;
+      }
+      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+                            c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
+                            c->stat_nbr, c->cnt, s, 2, c->sup_nbr, c->sup_deg);
+    } else {
+      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+                            c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
+                            c->work_t, c->stat_nbr, c->cnt, s);
+      c->list_builds++;
+    }
     mark(2);
     // the partner-slot codes beside the pair kernel
     if (d.partner_codes) {
@@ -644,6 +705,9 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   if ((opts->graph != 0 && opts->graph != 1) || (opts->graph && opts->timing) ||
       (opts->warm_start != 0 && opts->warm_start != 1))
     return LUB_EINVAL;
+  if (opts->reserved != 0 || !(opts->skin >= 0.0) || !std::isfinite(opts->skin) ||
+      (opts->skin > 0.0 && opts->graph))
+    return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
   c->device = opts->device;
@@ -667,6 +731,12 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_ENOMEM;
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
+  if (c->opt.skin > 0.0 &&
+      (hipMalloc((void**)&c->disp_word, sizeof(unsigned long long)) != hipSuccess ||
+       hipHostMalloc((void**)&c->host_disp, sizeof(unsigned long long), 0) != hipSuccess)) {
+    lub_destroy(c);
+    return LUB_ENOMEM;
+  }
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
@@ -704,6 +774,7 @@ int lub_set_params(lub_handle_t h, const lub_params_t* params) {
   int rc = check_params(params);
   if (rc) return rc;
   h->prm = *params;
+  h->lists_valid = false;
   return LUB_OK;
 }
 
@@ -712,6 +783,7 @@ int lub_set_domain(lub_handle_t h, const lub_domain_t* domain) {
   int rc = check_domain(domain);
   if (rc) return rc;
   h->dom = *domain;
+  h->lists_valid = false;
   return LUB_OK;
 }
 
@@ -737,10 +809,17 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
     if ((rc = ensure_seed(h))) return rc;
   }
   if ((rc = h->opt.graph ? run_graph(h, d, r, q, semi, v, w, f, t, s)
-                         : run(h, d, r, q, semi, v, w, f, t, s)))
+                         : run(h, d, r, q, semi, v, w, f, t, s))) {
+    h->lists_valid = false;
     return rc;
-  if (!h->opt.sync) return LUB_OK;
-  if ((rc = fetch_counters(h))) return rc;
+  }
+  // reused lists: every call is synchronous (the next call's decision needs
+  // this one's lists to be valid)
+  if (!h->opt.sync && !(h->opt.skin > 0.0)) return LUB_OK;
+  if ((rc = fetch_counters(h))) {
+    h->lists_valid = false;
+    return rc;
+  }
   // automatic limit: widen the segments and evaluate again
   while (h->host_cnt->error == LUB_ECAPACITY && h->opt.max_neighbors <= 0 &&
          h->cur_nbr < kMaxNbr) {
@@ -750,9 +829,12 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
     if (h->opt.seed_mode == LUB_SEED_MLP && h->cap_seed < h->cap_work) {
       if ((rc = ensure_seed(h))) return rc;
     }
-    if ((rc = run(h, d, r, q, semi, v, w, f, t, s))) return rc;
-    if ((rc = fetch_counters(h))) return rc;
+    if ((rc = run(h, d, r, q, semi, v, w, f, t, s)) || (rc = fetch_counters(h))) {
+      h->lists_valid = false;
+      return rc;
+    }
   }
+  if (h->host_cnt->error) h->lists_valid = false;
   return h->host_cnt->error;
 }
 
@@ -836,6 +918,8 @@ int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi
   hipStream_t s = (hipStream_t)stream;
   // the contact repulsion alone for the call
   const lub_params_t saved = h->prm;
+  // reused neighbour lists were built for the other law's cut-off
+  h->lists_valid = false;
   h->prm.model = LUB_MODEL_CONTACT;
   h->prm.h_c = cfg->h_c;
   h->prm.eps_c = cfg->eps_c;
@@ -850,6 +934,7 @@ int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi
                    cfg->dt, cfg->density, cfg->damping, s);
   }
   h->prm = saved;
+  h->lists_valid = false;
   return rc;
 }
 
@@ -879,6 +964,7 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   out->timed_calls = h->timed_calls;
   for (int k = 0; k < 4; ++k) out->stage_ms[k] = h->stage_ms[k];
   out->pair_kernel_ms = h->pair_kernel_ms;
+  out->list_builds = h->list_builds;
   return LUB_OK;
 }
 
@@ -1098,6 +1184,9 @@ void lub_destroy(lub_handle_t h) {
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);
+  if (h->host_disp) hipHostFree(h->host_disp);
+  for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->disp_word})
+    if (p) hipFree(p);
   if (h->side) {
     hipStreamSynchronize(h->side);
     hipStreamDestroy(h->side);

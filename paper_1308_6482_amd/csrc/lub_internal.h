@@ -76,6 +76,7 @@ struct CallDesc {
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
+  double skin;           // reused neighbour lists: superset margin (0: off)
   int32_t le;            // Lees-Edwards images (all axes periodic, no walls)
   double le_offset;      // x offset of the image one box up, in [0, L_x)
   double le_vel;         // x velocity of the image one box up
@@ -143,7 +144,17 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
-                           Counters* cnt, hipStream_t s);
+                           Counters* cnt, hipStream_t s, int mode = 0,
+                           const int32_t* sup_nbr = nullptr,
+                           const int32_t* sup_deg = nullptr);
+// reused neighbour lists: displacement measure since the build, and the
+// records of the current inputs in the build's cell order
+void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
+                 const double* semi, const double4* ref, unsigned long long* word,
+                 hipStream_t s);
+void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
+                    const double* semi, const double* v, const double* w, PRec* rec,
+                    double4* pos, KRec* kin, hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the

@@ -43,16 +43,18 @@ __device__ __forceinline__ void set_error(Counters* cnt, int code) {
 
 // Exact centre test: minimum-image squared distance below the squared
 // pruning bound, evaluated in a fixed order without contraction.
+// `extra` widens the bound (the skin of a reused list); with extra = 0 the
+// bound is (rmi + rmj) + dmax exactly.
 __device__ __forceinline__ bool centre_test(const double* ri, const double* rj,
                                             double rmi, double rmj,
-                                            const CallDesc& d) {
+                                            const CallDesc& d, double extra) {
 #pragma clang fp contract(off)
   double o[3];
   pair_image(d, ri, rj, o);
   const double dx = o[0], dy = o[1], dz = o[2];
   double d2 = dx * dx + dy * dy;
   d2 = d2 + dz * dz;
-  double sb = (rmi + rmj) + d.dmax;
+  double sb = (rmi + rmj) + (d.dmax + extra);
   return d2 < sb * sb;
 }
 
@@ -266,7 +268,7 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
   }
   k.pad[0] = k.pad[1] = 0.0;
   kin[s] = k;
-  cell_sorted[s] = cell_id[p];
+  if (cell_sorted) cell_sorted[s] = cell_id[p];
 }
 
 // Each cell's members in increasing input index (the position of a particle
@@ -430,14 +432,19 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
   return __popcll(mask & ((1ull << lane) - 1ull));
 }
 
-template <int G>
+// kMode 0: the full search.  kMode 1: the superset of a reused list (bound
+// widened by the skin; writes only the sorted segments into nbr, deg).
+// kMode 2: the reused superset sup_nbr / sup_deg filtered by the exact centre
+// test on the current positions, then as the full search.
+template <int G, int kMode>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
 k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
             const int32_t* __restrict__ orig, const int32_t* __restrict__ cell_sorted,
             const int32_t* __restrict__ cell_start, int32_t* __restrict__ deg,
             int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
             int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
-            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt) {
+            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
+            const int32_t* __restrict__ sup_nbr, const int32_t* __restrict__ sup_deg) {
   constexpr int kPer = 64 / G;                 // particles per wavefront
   constexpr int kSteps = G == 64 ? 6 : (G == 32 ? 5 : 4);  // log2 G
   constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
@@ -463,7 +470,32 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   int my_key[kMaxPerLane];
   int my_keep[kMaxPerLane];
   int wall_keep = 0;
-  if (live) {
+  const double extra = kMode == 1 ? d.skin : 0.0;
+  if (live && kMode == 2) {
+    // the superset of the last build (sorted), filtered in order
+    const double4 pi = pos[s];
+    const double ri[3] = {pi.x, pi.y, pi.z};
+    const int ns = sup_deg[s];
+    const int32_t* seg = sup_nbr + (size_t)s * maxn;
+    for (int base = 0; base < ns; base += G) {
+      const int e = base + gl;
+      bool acc = false;
+      int t = -1;
+      if (e < ns) {
+        t = seg[e];
+        const double4 pj = pos[t];
+        const double rj[3] = {pj.x, pj.y, pj.z};
+        acc = centre_test(ri, rj, pi.w, pj.w, d, 0.0);
+      }
+      const unsigned long long m = (__ballot(acc) >> gbase) & kGroupMask;
+      if (acc) {
+        const int at = count + lane_prefix(m, gl);
+        if (at < maxn) keys[at] = t;
+      }
+      count += __popcll(m);
+    }
+  }
+  if (live && kMode != 2) {
     const double4 pi = pos[s];
     const double ri[3] = {pi.x, pi.y, pi.z};
     const double rmi = pi.w;
@@ -489,7 +521,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
       // every partner of the class lies within rho of this centre along each
       // axis: at most `reach` cells away (cells are at least 1/reach_max of
       // the largest rho)
-      const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax;
+      const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax + extra;
       int reach[3], first[3], cnt3[3];
       for (int k = 0; k < 3; ++k)
         reach[k] = min(d.reach_max, max(1, (int)ceil(rho / d.cell[k])));
@@ -602,7 +634,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
             t = off < rn0 ? r0 + off : r1 + (off - rn0);
             const double4 pj = pos[t];
             const double rj[3] = {pj.x, pj.y, pj.z};
-            acc = t != s && centre_test(ri, rj, rmi, pj.w, d);
+            acc = t != s && centre_test(ri, rj, rmi, pj.w, d, extra);
           }
           const unsigned long long m = (__ballot(acc) >> gbase) & kGroupMask;
           if (acc) {
@@ -637,6 +669,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     for (int m2 = 0; m2 < nent; ++m2) rank += keys[m2] < key;
     nbr[(size_t)s * maxn + rank] = key;
     my_key[k] = key;
+    if (kMode == 1) continue;  // the superset: segments only
     // owned entries (smaller input index) are evaluated unless the support
     // functions along the line of centres already bound the gap above every
     // cut-off
@@ -661,6 +694,10 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     } else {
       slot[(size_t)s * maxn + rank] = -2;
     }
+  }
+  if (kMode == 1) {
+    if (live && gl == 0) deg[s] = nent;
+    return;
   }
   if (live && d.n_walls && gl < 2) {
     const int side = gl;
@@ -800,27 +837,111 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                      v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt);
 }
 
+template <int G>
+void launch_nbr_mode(int mode, dim3 grid, size_t lds, hipStream_t s, const CallDesc& d,
+                     const PRec* rec, const double4* pos, const int32_t* orig,
+                     const int32_t* cell_sorted, const int32_t* cell_start, int32_t* deg,
+                     int32_t* nbr, int32_t* slot, int32_t* wall_slot, int32_t* work_s,
+                     int32_t* work_t, int64_t* stat_nbr, Counters* cnt,
+                     const int32_t* sup_nbr, const int32_t* sup_deg) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_neighbors<G, 0>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
+                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_neighbors<G, 1>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
+                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+  else
+    hipLaunchKernelGGL((k_neighbors<G, 2>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
+                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+}
+
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
-                           Counters* cnt, hipStream_t s) {
+                           Counters* cnt, hipStream_t s, int mode, const int32_t* sup_nbr,
+                           const int32_t* sup_deg) {
   if (d.n == 0) return;
   dim3 grid(nbr_blocks(d));
   size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
   if (nbr_group(d) == 16)
-    hipLaunchKernelGGL(k_neighbors<16>, grid, dim3(64 * kWavesPerBlock), lds, s,
-                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
-                       wall_slot, work_s, work_t, stat_nbr, cnt);
+    launch_nbr_mode<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
   else if (nbr_group(d) == 32)
-    hipLaunchKernelGGL(k_neighbors<32>, grid, dim3(64 * kWavesPerBlock), lds, s,
-                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
-                       wall_slot, work_s, work_t, stat_nbr, cnt);
+    launch_nbr_mode<32>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
   else
-    hipLaunchKernelGGL(k_neighbors<64>, grid, dim3(64 * kWavesPerBlock), lds, s,
-                       d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
-                       wall_slot, work_s, work_t, stat_nbr, cnt);
+    launch_nbr_mode<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+}
+
+namespace {
+
+// Reused neighbour lists: the largest of |displacement since the build|
+// (minimum image) + growth of R_max since the build over all particles, as
+// the bit pattern of a non-negative double (ordered like the value) in
+// *word, which starts at zero.  A non-finite input counts as infinite.
+__global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
+                       const double* __restrict__ r, const double* __restrict__ q,
+                       const double* __restrict__ semi,
+                       const double4* __restrict__ ref, unsigned long long* word) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
+  if (s < d.n) {
+    const int p = sorted[s];
+    const double4 o = ref[s];
+    double dx = r[3 * p] - o.x, dy = r[3 * p + 1] - o.y, dz = r[3 * p + 2] - o.z;
+    if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
+    if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
+    if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
+    const double a = semi[2 * p], b = semi[2 * p + 1];
+    const double grow = fmax(a, b) - o.w;
+    m = sqrt(dx * dx + dy * dy + dz * dz) + (grow > 0.0 ? grow : 0.0);
+    // inputs the build would reject: build again (and report them)
+    const double qn = sqrt(q[4 * p] * q[4 * p] + q[4 * p + 1] * q[4 * p + 1] +
+                           q[4 * p + 2] * q[4 * p + 2] + q[4 * p + 3] * q[4 * p + 3]);
+    const bool ok = isfinite(m) && isfinite(grow) && fabs(qn - 1.0) <= 1e-6 && a > 0.0 &&
+                    b > 0.0 && fmax(a, b) <= d.rmax_bound &&
+                    (d.model != LUB_MODEL_LADD || a == b);
+    if (!ok) m = INFINITY;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0)
+    atomicMax(word, (unsigned long long)__double_as_longlong(m));
+}
+
+// records of the current inputs in the cell order of the last build
+__global__ void k_refresh(CallDesc d, const int32_t* __restrict__ sorted,
+                          const double* __restrict__ r, const double* __restrict__ q,
+                          const double* __restrict__ semi, const double* __restrict__ v,
+                          const double* __restrict__ w, PRec* __restrict__ rec,
+                          double4* __restrict__ pos, KRec* __restrict__ kin) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n) return;
+  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
+}
+
+}  // namespace
+
+void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
+                 const double* semi, const double4* ref, unsigned long long* word,
+                 hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_disp, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q, semi,
+                     ref, word);
+}
+
+void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
+                    const double* semi, const double* v, const double* w, PRec* rec,
+                    double4* pos, KRec* kin, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_refresh, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q,
+                     semi, v, w, rec, pos, kin);
 }
 
 // lanes per particle: the smallest group whose lanes hold the segment at 8

@@ -59,7 +59,8 @@ class lub_opts_t(C.Structure):
                 ("seed_mode", C.c_int32), ("newton_max_iter", C.c_int32),
                 ("rmax_bound", C.c_double), ("sync", C.c_int32),
                 ("timing", C.c_int32), ("max_neighbors", C.c_int64),
-                ("graph", C.c_int32), ("warm_start", C.c_int32)]
+                ("graph", C.c_int32), ("warm_start", C.c_int32),
+                ("reserved", C.c_int32), ("skin", C.c_double)]
 
 
 class lub_stats_t(C.Structure):
@@ -71,7 +72,8 @@ class lub_stats_t(C.Structure):
                 ("newton_max", C.c_int32), ("error", C.c_int32),
                 ("iter_hist", C.c_int64 * 32), ("timed_calls", C.c_int64),
                 ("stage_ms", C.c_double * 4), ("warm_seeded", C.c_int64),
-                ("max_degree", C.c_int64), ("pair_kernel_ms", C.c_double)]
+                ("max_degree", C.c_int64), ("pair_kernel_ms", C.c_double),
+                ("list_builds", C.c_int64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_
@@ -175,9 +177,10 @@ def make_domain(L, periodic=(1, 1, 1), n_walls=0,
 
 def make_opts(rmax_bound, precision=LUB_FP64, device=0, seed_mode=LUB_SEED_PLAIN,
               newton_max_iter=0, sync=1, max_neighbors=0, timing=0,
-              graph=0, warm_start=0) -> lub_opts_t:
+              graph=0, warm_start=0, skin=0.0) -> lub_opts_t:
     return lub_opts_t(device, precision, seed_mode, newton_max_iter,
-                      float(rmax_bound), sync, timing, max_neighbors, graph, warm_start)
+                      float(rmax_bound), sync, timing, max_neighbors, graph, warm_start, 0,
+                      float(skin))
 
 
 # --- the C entry points, same names ------------------------------------------
@@ -396,7 +399,8 @@ class Lub:
     def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
                  sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
-                 seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0, lees_edwards=None):
+                 seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0, lees_edwards=None,
+                 skin=0.0):
         self.domain_args = dict(L=L, periodic=periodic, n_walls=n_walls, wall_vel=wall_vel,
                                 lees_edwards=lees_edwards)
         self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel, lees_edwards),
@@ -404,7 +408,7 @@ class Lub:
                             make_opts(rmax_bound, precision, device, seed_mode=seed_mode,
                                       newton_max_iter=newton_max_iter, sync=sync,
                                       max_neighbors=max_neighbors, timing=timing,
-                                      graph=graph, warm_start=warm_start))
+                                      graph=graph, warm_start=warm_start, skin=skin))
 
     def compute(self, r, q, semi, v, w, f=None, t=None, stream=None, check=True):
         import torch

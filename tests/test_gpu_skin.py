@@ -1,0 +1,140 @@
+"""GPU tests of reused neighbour lists (opts.skin > 0): along a moving
+suspension the lists are searched again only when some particle moved (plus
+grew) by more than half the skin since the last search; in between, the
+superset of that search is filtered by the exact centre test.
+
+* Every step of a trajectory equals a fresh search (skin = 0) on the same
+  positions: candidate pair lists bit for bit, per-particle sums to
+  rounding (the two orders of summation differ), at both precisions; some
+  steps reuse the lists and some search again.
+* A particle that grows beyond half the skin forces a search.
+* Against the FP64 oracle after reuse steps, at the FP64 bar.
+* Argument errors: negative skin, skin with graph mode, skin with
+  Lees-Edwards images.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_1308_6482_amd import lub as L  # noqa: E402
+from paper_1308_6482_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.lib()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def close(a, b, tol):
+    scale = max(np.abs(b).max(), 1e-300)
+    return np.abs(a - b).max() <= tol * scale
+
+
+@pytest.mark.parametrize("name,precision", [("config3", L.LUB_MIXED), ("config2", L.LUB_FP64)])
+def test_trajectory_equals_fresh_search(name, precision):
+    wl = W.config3(n=6000) if name == "config3" else W.config2()
+    print(f"[gpu] reused lists along a trajectory: {wl.name}, precision={precision}", flush=True)
+    rng = np.random.default_rng(51)
+    vel = rng.normal(scale=0.15, size=(wl.n, 3))
+    if wl.n_walls:
+        vel[:, 2] *= 0.1
+    skin_lb = L.Lub.for_workload(wl, precision=precision, skin=1.0)
+    q, semi, v, w = (dev(x) for x in (wl.q, wl.semi, wl.v, wl.w))
+    r = wl.r.copy()
+    builds = []
+    for k in range(8):
+        rd = dev(r)
+        fs, ts = skin_lb.compute(rd, q, semi, v, w)
+        ss = skin_lb.stats()
+        ps = skin_lb.pairs()
+        fresh = L.Lub.for_workload(wl, precision=precision)
+        ff, tf = fresh.compute(rd, q, semi, v, w)
+        sf = fresh.stats()
+        pf = fresh.pairs()
+        fresh.close()
+        builds.append(ss["list_builds"])
+        assert ss["error"] == 0
+        assert np.array_equal(ps[0], pf[0]) and np.array_equal(ps[1], pf[1]), f"step {k}"
+        assert ss["active"] == sf["active"] and ss["evaluated"] == sf["evaluated"]
+        fs, ts, ff, tf = (x.cpu().numpy() for x in (fs, ts, ff, tf))
+        assert close(fs, ff, 1e-12) and close(ts, tf, 1e-12), f"step {k}"
+        r = r + 0.3 * vel
+        if wl.n_walls:
+            r[:, 2] = np.clip(r[:, 2], 0.0, wl.L[2])
+    skin_lb.close()
+    print(f"list searches after each step: {builds}")
+    # the first call searches (twice if the superset needed wider segments);
+    # later ones reuse until the skin is used up
+    assert builds[0] in (1, 2)
+    assert builds[-1] > builds[0] and builds[-1] - builds[0] < len(builds) - 1
+
+
+def test_growth_forces_search():
+    wl = W.config2()
+    print("[gpu] reused lists: growing particles", flush=True)
+    lb = L.Lub(wl.L, wl.periodic, wl.params, 1.1 * float(wl.semi.max()), skin=1.0)
+    r, q, semi, v, w = L.to_device(wl)
+    lb.compute(r, q, semi, v, w)
+    b0 = lb.stats()["list_builds"]   # 2 if the first search widened the segments
+    lb.compute(r, q, semi, v, w)
+    assert lb.stats()["list_builds"] == b0
+    semi2 = semi * 1.02   # 0.16 on R = 8: within half the skin
+    lb.compute(r, q, semi2, v, w)
+    assert lb.stats()["list_builds"] == b0
+    semi3 = semi * 1.07   # 0.56 > 0.5
+    f3, t3 = lb.compute(r, q, semi3, v, w)
+    assert lb.stats()["list_builds"] == b0 + 1
+    fresh = L.Lub(wl.L, wl.periodic, wl.params, 1.1 * float(wl.semi.max()))
+    ff, tf = fresh.compute(r, q, semi3, v, w)
+    assert np.array_equal(lb.pairs()[0], fresh.pairs()[0])
+    assert close(f3.cpu().numpy(), ff.cpu().numpy(), 1e-12)
+    lb.close()
+    fresh.close()
+
+
+def test_reuse_against_oracle(ref):
+    wl = W.config3(n=3000)
+    print("[gpu] reused lists against the oracle", flush=True)
+    rng = np.random.default_rng(52)
+    vel = rng.normal(scale=0.05, size=(wl.n, 3))
+    vel[:, 2] = 0.0
+    lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, skin=2.0)
+    q, semi, v, w = (dev(x) for x in (wl.q, wl.semi, wl.v, wl.w))
+    r = wl.r.copy()
+    for k in range(3):
+        f, t = lb.compute(dev(r), q, semi, v, w)
+        if k == 0:
+            b0 = lb.stats()["list_builds"]
+        r = r + 1.0 * vel
+    assert lb.stats()["list_builds"] == b0   # the later calls reused the lists
+    r = r - 1.0 * vel
+    dom = O.make_domain(**wl.domain())
+    P = O.make_params(**wl.params)
+    fo, to, so = ref.compute(r, wl.q, wl.semi, wl.v, wl.w, dom, P)
+    f, t = f.cpu().numpy(), t.cpu().numpy()
+    rms = np.sqrt(np.mean(np.sum(fo ** 2, axis=1)))
+    den = np.maximum(np.linalg.norm(fo, axis=1), 1e-3 * rms)
+    assert (np.linalg.norm(f - fo, axis=1) / den).max() < 1e-9
+    lb.close()
+
+
+def test_skin_errors():
+    wl = W.config2(n=500)
+    with pytest.raises(L.LubError):
+        L.Lub.for_workload(wl, skin=-1.0)
+    with pytest.raises(L.LubError):
+        L.Lub.for_workload(wl, skin=1.0, graph=1, sync=0)
+    wls = W.sheared(n=300)
+    lb = L.Lub.for_workload(wls, skin=1.0)
+    with pytest.raises(L.LubError):
+        lb.compute(*L.to_device(wls))
+    lb.close()
