@@ -275,11 +275,12 @@ def train_seed(L, torch, n_train, epochs):
                        generate_s=t_gen, train_s=t_train)
 
 
-def neighbour_capacity(L, torch, wl, prec):
+def neighbour_capacity(L, torch, wl, prec, skin=0.0):
     """One synchronous evaluation (the library widens its neighbour segments
-    on demand) gives the largest candidate count; the timed handles, which
-    run asynchronously, get that with headroom for moving particles."""
-    lb = L.Lub.for_workload(wl, precision=prec, sync=1)
+    on demand) gives the largest candidate count (of the superset, with a
+    skin); the timed handles, which run asynchronously, get that with
+    headroom for moving particles."""
+    lb = L.Lub.for_workload(wl, precision=prec, sync=1, skin=skin)
     lb.compute(*L.to_device(wl))
     deg = lb.stats()["max_degree"]
     lb.close()
@@ -343,7 +344,7 @@ def measure(L, torch, wl, prec, args, theta=None):
 def trajectory(L, torch, wl, prec, args, warm, skin=0.0):
     """K evaluations along a moving suspension (positions advanced in place
     by v dt after each evaluation, graph replay), with or without the warm
-    start, or (skin > 0, eager and synchronous) with reused neighbour lists;
+    start, or (skin > 0) with reused neighbour lists;
     returns a report of the last evaluation and the timing."""
     import numpy as np
     r0, q, semi, v, w = L.to_device(wl)
@@ -351,12 +352,12 @@ def trajectory(L, torch, wl, prec, args, warm, skin=0.0):
     f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
     stream = torch.cuda.Stream()
+    cap = args.max_neighbors
     if skin > 0.0:
-        # the superset needs wider segments: automatic capacity
-        lb = L.Lub.for_workload(wl, precision=prec, sync=0, skin=skin)
-    else:
-        lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm),
-                                max_neighbors=args.max_neighbors)
+        # the superset needs wider segments
+        cap = neighbour_capacity(L, torch, wl, prec, skin)
+    lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm),
+                            max_neighbors=cap, skin=skin)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)

@@ -185,17 +185,19 @@ typedef struct {
                            /* seed_mode.  The paper's time-step continuation (Sec. */
                            /* III.A).  0: every call starts afresh */
   int32_t reserved;        /* must be 0 */
-  double skin;             /* > 0: reuse the neighbour lists across calls.  A build */
+  double skin;             /* > 0: reuse the neighbour lists across calls.  A search */
                            /* keeps every pair within the pruning bound + skin; a */
                            /* call reuses the lists while every particle moved (minimum */
                            /* image) plus grew in max(R_par, R_perp) by at most */
-                           /* skin / 2 since the build, re-applying the exact centre */
-                           /* test to the kept pairs, and builds again otherwise (or */
-                           /* when n, the parameters or the domain changed).  The */
-                           /* pair lists equal those of a fresh search.  Every call */
-                           /* then waits for its stream (the decision is taken on */
-                           /* the host).  Needs graph = 0 and no Lees-Edwards images */
-                           /* (else LUB_EINVAL); periodic lengths must hold twice */
+                           /* skin / 2 since the search, re-applying the exact centre */
+                           /* test to the kept pairs, and searches again otherwise (or */
+                           /* when n, the parameters or the domain changed, or a call */
+                           /* failed).  The device takes the decision: calls stay */
+                           /* asynchronous and may be captured (graph = 1).  The pair */
+                           /* lists equal those of a fresh search.  The superset needs */
+                           /* wider segments (max_neighbors, or the automatic growth */
+                           /* with sync = 1).  No Lees-Edwards images (else */
+                           /* LUB_EINVAL); periodic lengths must hold twice */
                            /* 2 rmax_bound + cut-off + skin (else LUB_EDOMAIN). */
                            /* 0: search every call */
 } lub_opts_t;
@@ -225,11 +227,13 @@ typedef struct {
   double stage_ms[4];
   int64_t warm_seeded;      /* pairs started from the previous call's solution */
   int64_t max_degree;       /* most candidate partners of one particle (also when it */
-                            /* exceeded max_neighbors: the value to set) */
+                            /* exceeded max_neighbors: the value to set); with a */
+                            /* skin, of the superset */
   double pair_kernel_ms;    /* with opts.timing: the pair kernel's own execution */
                             /* time (dispatch timestamps), summed like stage_ms */
   int64_t list_builds;      /* neighbour-list searches since the handle was created */
-                            /* (one per call unless opts.skin > 0) */
+                            /* (one per call unless opts.skin > 0; with a skin, a */
+                            /* search whose superset overflowed counts too) */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;

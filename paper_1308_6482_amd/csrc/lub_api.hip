@@ -27,17 +27,17 @@ struct lub_ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // reused neighbour lists (opts.skin > 0): the superset segments of the
-  // last build in its cell order, the positions and sizes at the build, the
-  // displacement measure and the bookkeeping of the build
+  // last search in its cell order, the positions and sizes at the search,
+  // the device-side state (epoch of the lists, searches), and the host's
+  // epoch: any change that makes the lists unusable starts a new one
   int32_t* sup_nbr = nullptr;
   int32_t* sup_deg = nullptr;
   double4* ref_pos = nullptr;
-  unsigned long long* disp_word = nullptr;
-  unsigned long long* host_disp = nullptr;
-  bool lists_valid = false;
-  int64_t build_n = -1;
-  int32_t build_stride = 0;
-  int64_t list_builds = 0;
+  ListState* list_state = nullptr;
+  int32_t list_epoch = 0;
+  int64_t epoch_n = -1;
+  int32_t epoch_stride = 0;
+  int64_t list_builds = 0;  // searches without reuse (counted on the host)
 
   // workspace
   int64_t cap_n = 0, cap_cells = 0, cap_entries = 0, cap_work = 0, cap_bs = 0;
@@ -220,7 +220,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
   if (c->opt.skin > 0.0 &&
       ((rc = realloc_buf(&c->sup_deg, need)) || (rc = realloc_buf(&c->ref_pos, need))))
     return rc;
-  c->lists_valid = false;
+  c->list_epoch++;
   c->cap_n = need;
   return LUB_OK;
 }
@@ -249,7 +249,7 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
     if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)))
       return rc;
     if (c->opt.skin > 0.0 && (rc = realloc_buf(&c->sup_nbr, entries))) return rc;
-    c->lists_valid = false;
+    c->list_epoch++;
     c->cap_entries = entries;
   }
   if (c->cap_work < work || !c->work_s) {
@@ -387,9 +387,17 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
              const double* semi, const double* v, const double* w, double* f,
              double* t, hipStream_t s);
 
-// the capacities of the current workspace and the warm-start table size
-CallDesc finalize_desc(const lub_ctx* c, const CallDesc& d0) {
+// the capacities of the current workspace, the warm-start table size and
+// the epoch of reusable neighbour lists (a new one when n or the segment
+// stride changed)
+CallDesc finalize_desc(lub_ctx* c, const CallDesc& d0) {
   CallDesc d = d0;
+  if (d.skin > 0.0 && (c->epoch_n != d.n || c->epoch_stride != d.max_nbr)) {
+    c->list_epoch++;
+    c->epoch_n = d.n;
+    c->epoch_stride = d.max_nbr;
+  }
+  d.list_epoch = c->list_epoch;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
   // from about a quarter million particles the partner codes, written
@@ -445,53 +453,38 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       HIP_TRY(hipMemsetAsync(c->warm_key[wc], 0xff, sizeof(uint64_t) * c->warm_size, s));
   }
   c->zeroed = false;
-  // reused neighbour lists: build again unless every particle stayed within
-  // half the skin of its place (and size) at the last build
-  bool rebuild = true;
-  if (d.n > 0 && d.skin > 0.0) {
-    rebuild = !c->lists_valid || c->build_n != d.n || c->build_stride != d.max_nbr;
-    if (!rebuild) {
-      HIP_TRY(hipMemsetAsync(c->disp_word, 0, sizeof(unsigned long long), s));
-      launch_disp(d, c->sorted, r, q, semi, c->ref_pos, c->disp_word, s);
-      HIP_TRY(hipMemcpyAsync(c->host_disp, c->disp_word, sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      double m;
-      std::memcpy(&m, c->host_disp, sizeof(m));
-      rebuild = !(2.0 * m <= d.skin * (1.0 - 1e-12));
-    }
+  // reused neighbour lists: the device decides whether this call searches
+  // (every particle within half the skin of its place and size at the last
+  // search: no); the cell build runs only if it does, the record refresh
+  // only if it does not
+  const bool reuse = d.n > 0 && d.skin > 0.0;
+  const Counters* gate = reuse ? c->cnt : nullptr;
+  if (reuse) {
+    launch_disp(d, c->sorted, r, q, semi, c->ref_pos, c->list_state, c->cnt, s);
+    launch_refresh(d, c->sorted, r, q, semi, v, w, c->rec, c->pos, c->kin, c->cnt, s);
   }
-  if (d.n > 0 && !rebuild) {
-    launch_refresh(d, c->sorted, r, q, semi, v, w, c->rec, c->pos, c->kin, s);
-  } else if (d.n > 0) {
+  if (d.n > 0) {
     if (small) {
       launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->pos,
-                         c->kin, c->cell_sorted, c->cnt, s);
+                         c->kin, c->cell_sorted, c->cnt, gate, s);
     } else {
-      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, s);
+      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
-                          c->cell_count, ncell, s);
+                          c->cell_count, ncell, gate, s);
       launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
                            q, semi, v, w, c->sorted, c->rec, c->pos, c->kin, c->cell_sorted,
-                           s);
+                           gate, s);
     }
   }
   if (d.n > 0) {
     mark(1);
-    if (d.skin > 0.0) {
-      // superset of the build (its cell order), then the exact filter
-      if (rebuild) {
-        launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
-                              c->sup_deg, c->sup_nbr, c->slot, c->wall_slot, c->work_s,
-                              c->work_t, c->stat_nbr, c->cnt, s, 1);
-        HIP_TRY(hipMemcpyAsync(c->ref_pos, c->pos, sizeof(double4) * d.n,
-                               hipMemcpyDeviceToDevice, s));
-        c->lists_valid = true;
-        c->build_n = d.n;
-        c->build_stride = d.max_nbr;
-        c->list_builds++;
-      }
+    if (reuse) {
+      // the superset (searched in calls that search), then the exact filter
+      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+                            c->sup_deg, c->sup_nbr, c->slot, c->wall_slot, c->work_s,
+                            c->work_t, c->stat_nbr, c->cnt, s, 1, nullptr, nullptr,
+                            c->ref_pos, c->list_state);
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
                             c->stat_nbr, c->cnt, s, 2, c->sup_nbr, c->sup_deg);
@@ -565,7 +558,8 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
           c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
-          c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1]};
+          c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
+          c->sup_deg, c->ref_pos, c->list_state};
 }
 
 void drop_graphs(lub_ctx* c) {
@@ -705,8 +699,7 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   if ((opts->graph != 0 && opts->graph != 1) || (opts->graph && opts->timing) ||
       (opts->warm_start != 0 && opts->warm_start != 1))
     return LUB_EINVAL;
-  if (opts->reserved != 0 || !(opts->skin >= 0.0) || !std::isfinite(opts->skin) ||
-      (opts->skin > 0.0 && opts->graph))
+  if (opts->reserved != 0 || !(opts->skin >= 0.0) || !std::isfinite(opts->skin))
     return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
@@ -731,11 +724,18 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_ENOMEM;
   }
   std::memset(c->host_cnt, 0, sizeof(Counters));
-  if (c->opt.skin > 0.0 &&
-      (hipMalloc((void**)&c->disp_word, sizeof(unsigned long long)) != hipSuccess ||
-       hipHostMalloc((void**)&c->host_disp, sizeof(unsigned long long), 0) != hipSuccess)) {
-    lub_destroy(c);
-    return LUB_ENOMEM;
+  if (c->opt.skin > 0.0) {
+    // no lists yet (epoch -1), no searches
+    const ListState none{-1, 0, 0};
+    if (hipMalloc((void**)&c->list_state, sizeof(ListState)) != hipSuccess) {
+      lub_destroy(c);
+      return LUB_ENOMEM;
+    }
+    if (hipMemcpy(c->list_state, &none, sizeof(ListState), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      lub_destroy(c);
+      return LUB_EDEVICE;
+    }
   }
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -774,7 +774,7 @@ int lub_set_params(lub_handle_t h, const lub_params_t* params) {
   int rc = check_params(params);
   if (rc) return rc;
   h->prm = *params;
-  h->lists_valid = false;
+  h->list_epoch++;
   return LUB_OK;
 }
 
@@ -783,7 +783,7 @@ int lub_set_domain(lub_handle_t h, const lub_domain_t* domain) {
   int rc = check_domain(domain);
   if (rc) return rc;
   h->dom = *domain;
-  h->lists_valid = false;
+  h->list_epoch++;
   return LUB_OK;
 }
 
@@ -810,14 +810,12 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   }
   if ((rc = h->opt.graph ? run_graph(h, d, r, q, semi, v, w, f, t, s)
                          : run(h, d, r, q, semi, v, w, f, t, s))) {
-    h->lists_valid = false;
+    h->list_epoch++;
     return rc;
   }
-  // reused lists: every call is synchronous (the next call's decision needs
-  // this one's lists to be valid)
-  if (!h->opt.sync && !(h->opt.skin > 0.0)) return LUB_OK;
+  if (!h->opt.sync) return LUB_OK;
   if ((rc = fetch_counters(h))) {
-    h->lists_valid = false;
+    h->list_epoch++;
     return rc;
   }
   // automatic limit: widen the segments and evaluate again
@@ -830,11 +828,11 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
       if ((rc = ensure_seed(h))) return rc;
     }
     if ((rc = run(h, d, r, q, semi, v, w, f, t, s)) || (rc = fetch_counters(h))) {
-      h->lists_valid = false;
+      h->list_epoch++;
       return rc;
     }
   }
-  if (h->host_cnt->error) h->lists_valid = false;
+  if (h->host_cnt->error) h->list_epoch++;
   return h->host_cnt->error;
 }
 
@@ -919,7 +917,7 @@ int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi
   // the contact repulsion alone for the call
   const lub_params_t saved = h->prm;
   // reused neighbour lists were built for the other law's cut-off
-  h->lists_valid = false;
+  h->list_epoch++;
   h->prm.model = LUB_MODEL_CONTACT;
   h->prm.h_c = cfg->h_c;
   h->prm.eps_c = cfg->eps_c;
@@ -934,7 +932,7 @@ int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi
                    cfg->dt, cfg->density, cfg->damping, s);
   }
   h->prm = saved;
-  h->lists_valid = false;
+  h->list_epoch++;
   return rc;
 }
 
@@ -965,6 +963,13 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   for (int k = 0; k < 4; ++k) out->stage_ms[k] = h->stage_ms[k];
   out->pair_kernel_ms = h->pair_kernel_ms;
   out->list_builds = h->list_builds;
+  if (h->list_state) {
+    // searches decided on the device
+    ListState st{};
+    if (h->have_last) HIP_TRY(hipStreamSynchronize(h->last_stream));
+    HIP_TRY(hipMemcpy(&st, h->list_state, sizeof(ListState), hipMemcpyDeviceToHost));
+    out->list_builds = st.builds;
+  }
   return LUB_OK;
 }
 
@@ -1184,8 +1189,7 @@ void lub_destroy(lub_handle_t h) {
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);
-  if (h->host_disp) hipHostFree(h->host_disp);
-  for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->disp_word})
+  for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->list_state})
     if (p) hipFree(p);
   if (h->side) {
     hipStreamSynchronize(h->side);

@@ -45,6 +45,19 @@ struct Counters {
   int64_t warm_seeded;    // pairs started from the previous call's normal
   int64_t max_degree;     // largest number of candidates of one particle
   int64_t iter_hist[32];
+  // reused neighbour lists: the largest displacement plus growth since the
+  // last search (bits of a non-negative double) and this call's decision
+  unsigned long long disp_bits;
+  int32_t rebuild;
+  int32_t pad_list;
+};
+
+// Reused neighbour lists, kept on the device across calls: the epoch of the
+// lists in the superset buffers (-1: none) and the number of searches.
+struct ListState {
+  int32_t epoch;
+  int32_t pad;
+  int64_t builds;
 };
 
 // Per-block partial statistics, written with plain stores and summed only
@@ -77,6 +90,8 @@ struct CallDesc {
   int32_t n_walls;
   double wall_vel[2][3];
   double skin;           // reused neighbour lists: superset margin (0: off)
+  int32_t list_epoch;    // lists searched under another epoch are not reused
+  int32_t pad_epoch;
   int32_t le;            // Lees-Edwards images (all axes periodic, no walls)
   double le_offset;      // x offset of the image one box up, in [0, L_x)
   double le_vel;         // x velocity of the image one box up
@@ -116,29 +131,33 @@ constexpr int kWbTotal = 2 * kWt2 + 128 * 32;
 // ---- launch wrappers (lub_neighbors.hip) --------------------------------
 void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
                   int ncell, hipStream_t s);
+// The cell-build launchers take `gate`: null, or this call's counters, whose
+// `rebuild` flag (set on the device) turns the kernels into no-ops when the
+// neighbour lists are reused.
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, hipStream_t s);
+                      Counters* cnt, const Counters* gate, hipStream_t s);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
                  int64_t* total, hipStream_t s);
 // scatter into the cells' ranges (arbitrary order); zeroes cell_count
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
                          int32_t* unsorted, int32_t* cell_count, int ncell,
-                         hipStream_t s);
+                         const Counters* gate, hipStream_t s);
 // in-cell placement by input index and the records; zeroes cell_fill
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_id, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
                           const double* w, int32_t* sorted, PRec* rec, double4* pos,
-                          KRec* kin, int32_t* cell_sorted, hipStream_t s);
+                          KRec* kin, int32_t* cell_sorted, const Counters* gate, hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
                         int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
-                        KRec* kin, int32_t* cell_sorted, Counters* cnt, hipStream_t s);
+                        KRec* kin, int32_t* cell_sorted, Counters* cnt, const Counters* gate,
+                        hipStream_t s);
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
                            const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
@@ -146,15 +165,19 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode = 0,
                            const int32_t* sup_nbr = nullptr,
-                           const int32_t* sup_deg = nullptr);
-// reused neighbour lists: displacement measure since the build, and the
-// records of the current inputs in the build's cell order
+                           const int32_t* sup_deg = nullptr, double4* ref_pos = nullptr,
+                           ListState* state = nullptr);
+// reused neighbour lists: the displacement plus growth since the search
+// (skipped unless the lists are of this epoch), then the decision (a
+// search if the lists are of another epoch or the measure exceeds half the
+// skin), and the records of the current inputs in the search's cell order
+// (a no-op when searching)
 void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                 const double* semi, const double4* ref, unsigned long long* word,
+                 const double* semi, const double4* ref, ListState* state, Counters* cnt,
                  hipStream_t s);
 void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
                     const double* semi, const double* v, const double* w, PRec* rec,
-                    double4* pos, KRec* kin, hipStream_t s);
+                    double4* pos, KRec* kin, const Counters* cnt, hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the

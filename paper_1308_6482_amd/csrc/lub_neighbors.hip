@@ -97,10 +97,11 @@ __global__ void k_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
     reinterpret_cast<int32_t*>(c)[i] = 0;
 }
 
-// validate one particle's input (EINVAL, EDOMAIN) and return its cell
-__device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
-                            const double* __restrict__ q,
-                            const double* __restrict__ semi, int p, Counters* cnt) {
+// checks of one particle's input: bit 0 an invalid value (EINVAL), bit 1 a
+// centre beyond a wall by more than the particle's size (EDOMAIN)
+__device__ __forceinline__ int input_faults(const CallDesc& d, const double* __restrict__ r,
+                                            const double* __restrict__ q,
+                                            const double* __restrict__ semi, int p) {
   double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
   double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
   double a = semi[2 * p], b = semi[2 * p + 1];
@@ -110,9 +111,21 @@ __device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
   double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   ok = ok && fabs(qn - 1.0) <= 1e-6 && fmax(a, b) <= d.rmax_bound;
   ok = ok && (d.model != LUB_MODEL_LADD || a == b);  // Ladd's law is for spheres
-  if (!ok) set_error(cnt, LUB_EINVAL);
   double rm = fmax(a, b);
-  if (d.n_walls && (z < -rm || z > d.L[2] + rm)) set_error(cnt, LUB_EDOMAIN);
+  const bool wall = d.n_walls && (z < -rm || z > d.L[2] + rm);
+  return (ok ? 0 : 1) | (wall ? 2 : 0);
+}
+
+// validate one particle's input (EINVAL, EDOMAIN) and return its cell
+__device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
+                            const double* __restrict__ q,
+                            const double* __restrict__ semi, int p, Counters* cnt) {
+  double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
+  const int faults = input_faults(d, r, q, semi, p);
+  const bool ok = !(faults & 1);
+  if (!ok) set_error(cnt, LUB_EINVAL);
+  double rm = fmax(semi[2 * p], semi[2 * p + 1]);
+  if (faults & 2) set_error(cnt, LUB_EDOMAIN);
   int cx = cell_coord(x, d.L[0], d.periodic[0], d.cell[0], d.nc[0]);
   int cy = cell_coord(y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
   int cz = cell_coord(z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
@@ -126,7 +139,9 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
                             const double* __restrict__ q,
                             const double* __restrict__ semi,
                             int32_t* __restrict__ cell_id,
-                            int32_t* __restrict__ cell_count, Counters* cnt) {
+                            int32_t* __restrict__ cell_count, Counters* cnt,
+                            const Counters* gate) {
+  if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
   int c = validate_bin(d, r, q, semi, p, cnt);
@@ -215,7 +230,9 @@ __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
                                const int32_t* __restrict__ cell_start,
                                int32_t* __restrict__ cell_fill,
                                int32_t* __restrict__ unsorted,
-                               int32_t* __restrict__ cell_count, int ncell) {
+                               int32_t* __restrict__ cell_count, int ncell,
+                               const Counters* gate) {
+  if (gate && !gate->rebuild) return;  // reused lists: the counts stayed zero
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
   if (i >= d.n) return;
@@ -285,7 +302,9 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 const double* __restrict__ v,
                                 const double* __restrict__ w, int32_t* __restrict__ sorted,
                                 PRec* __restrict__ rec, double4* __restrict__ pos,
-                                KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
+                                KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted,
+                                const Counters* gate) {
+  if (gate && !gate->rebuild) return;  // reused lists: the cursors stayed zero
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
   if (i >= d.n) return;
@@ -355,7 +374,8 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
               const double* __restrict__ w, int32_t* __restrict__ cell_start,
               int32_t* __restrict__ sorted, PRec* __restrict__ rec,
               double4* __restrict__ pos, KRec* __restrict__ kin,
-              int32_t* __restrict__ cell_sorted, Counters* cnt) {
+              int32_t* __restrict__ cell_sorted, Counters* cnt, const Counters* gate) {
+  if (gate && !gate->rebuild) return;  // reused lists (uniform: one block)
   __shared__ int32_t cnt_l[kSmallMaxCells];        // counts, then cursors
   __shared__ int32_t start_l[kSmallMaxCells + 1];
   __shared__ int32_t cid_l[kSmallMaxN];            // cell of each input index
@@ -433,7 +453,10 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
 }
 
 // kMode 0: the full search.  kMode 1: the superset of a reused list (bound
-// widened by the skin; writes only the sorted segments into nbr, deg).
+// widened by the skin), only in calls that search: writes the sorted
+// segments into nbr, their lengths into deg (minus the count when a segment
+// overflows) and the positions and sizes of the search into ref_pos; an
+// overflow or an earlier input error discards the lists (state epoch -1).
 // kMode 2: the reused superset sup_nbr / sup_deg filtered by the exact centre
 // test on the current positions, then as the full search.
 template <int G, int kMode>
@@ -444,7 +467,9 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
             int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
             int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
             int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
-            const int32_t* __restrict__ sup_nbr, const int32_t* __restrict__ sup_deg) {
+            const int32_t* __restrict__ sup_nbr, const int32_t* __restrict__ sup_deg,
+            double4* __restrict__ ref_pos, ListState* state) {
+  if (kMode == 1 && !cnt->rebuild) return;  // the lists are reused
   constexpr int kPer = 64 / G;                 // particles per wavefront
   constexpr int kSteps = G == 64 ? 6 : (G == 32 ? 5 : 4);  // log2 G
   constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
@@ -471,11 +496,14 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   int my_keep[kMaxPerLane];
   int wall_keep = 0;
   const double extra = kMode == 1 ? d.skin : 0.0;
+  int sup_need = 0;  // mode 2: the superset's length (its need if it overflowed)
   if (live && kMode == 2) {
     // the superset of the last build (sorted), filtered in order
     const double4 pi = pos[s];
     const double ri[3] = {pi.x, pi.y, pi.z};
-    const int ns = sup_deg[s];
+    const int ns_raw = sup_deg[s];
+    const int ns = ns_raw > 0 ? ns_raw : 0;
+    sup_need = ns_raw >= 0 ? ns_raw : -ns_raw;
     const int32_t* seg = sup_nbr + (size_t)s * maxn;
     for (int base = 0; base < ns; base += G) {
       const int e = base + gl;
@@ -696,7 +724,12 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     }
   }
   if (kMode == 1) {
-    if (live && gl == 0) deg[s] = nent;
+    if (live && gl == 0) {
+      deg[s] = overflow ? -count : nent;
+      ref_pos[s] = pos[s];
+      if (overflow) state->epoch = -1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt->error) state->epoch = -1;
     return;
   }
   if (live && d.n_walls && gl < 2) {
@@ -713,7 +746,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   if (live && gl == 0) deg[s] = nent;
   // wave totals -> block total -> one atomic per block
   int wkeep = nkeep, wup = nupper, wwall = nwallc;
-  int wdeg = live ? count : 0;  // uniform in each group
+  int wdeg = live ? max(count, sup_need) : 0;  // uniform in each group
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     wkeep += __shfl_xor(wkeep, o, 64);
@@ -783,10 +816,10 @@ void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
 
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, hipStream_t s) {
+                      Counters* cnt, const Counters* gate, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_stage_bin, dim3((d.n + 255) / 256), dim3(256), 0, s, d,
-                     r, q, semi, cell_id, cell_count, cnt);
+                     r, q, semi, cell_id, cell_count, cnt, gate);
 }
 
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
@@ -806,10 +839,10 @@ void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
                          int32_t* unsorted, int32_t* cell_count, int ncell,
-                         hipStream_t s) {
+                         const Counters* gate, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_cell_scatter, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, cell_id, cell_start, cell_fill, unsorted, cell_count, ncell);
+                     d, cell_id, cell_start, cell_fill, unsorted, cell_count, ncell, gate);
 }
 
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
@@ -817,11 +850,12 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
                           const double* w, int32_t* sorted, PRec* rec, double4* pos,
-                          KRec* kin, int32_t* cell_sorted, hipStream_t s) {
+                          KRec* kin, int32_t* cell_sorted, const Counters* gate,
+                          hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
                      d, unsorted, cell_id, cell_start, cell_fill, ncell, r, q, semi,
-                     v, w, sorted, rec, pos, kin, cell_sorted);
+                     v, w, sorted, rec, pos, kin, cell_sorted, gate);
 }
 
 bool cells_small_fits(const CallDesc& d) {
@@ -832,9 +866,10 @@ bool cells_small_fits(const CallDesc& d) {
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
                         int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
-                        KRec* kin, int32_t* cell_sorted, Counters* cnt, hipStream_t s) {
+                        KRec* kin, int32_t* cell_sorted, Counters* cnt, const Counters* gate,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, d, r, q, semi,
-                     v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt);
+                     v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt, gate);
 }
 
 template <int G>
@@ -843,19 +878,20 @@ void launch_nbr_mode(int mode, dim3 grid, size_t lds, hipStream_t s, const CallD
                      const int32_t* cell_sorted, const int32_t* cell_start, int32_t* deg,
                      int32_t* nbr, int32_t* slot, int32_t* wall_slot, int32_t* work_s,
                      int32_t* work_t, int64_t* stat_nbr, Counters* cnt,
-                     const int32_t* sup_nbr, const int32_t* sup_deg) {
+                     const int32_t* sup_nbr, const int32_t* sup_deg, double4* ref_pos,
+                     ListState* state) {
   if (mode == 0)
     hipLaunchKernelGGL((k_neighbors<G, 0>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
   else if (mode == 1)
     hipLaunchKernelGGL((k_neighbors<G, 1>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
   else
     hipLaunchKernelGGL((k_neighbors<G, 2>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
 }
 
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
@@ -864,31 +900,36 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode, const int32_t* sup_nbr,
-                           const int32_t* sup_deg) {
+                           const int32_t* sup_deg, double4* ref_pos, ListState* state) {
   if (d.n == 0) return;
   dim3 grid(nbr_blocks(d));
   size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
   if (nbr_group(d) == 16)
     launch_nbr_mode<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
   else if (nbr_group(d) == 32)
     launch_nbr_mode<32>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
   else
     launch_nbr_mode<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
 }
 
 namespace {
 
-// Reused neighbour lists: the largest of |displacement since the build|
-// (minimum image) + growth of R_max since the build over all particles, as
+// Reused neighbour lists: the largest of |displacement since the search|
+// (minimum image) + growth of R_max since the search over all particles, as
 // the bit pattern of a non-negative double (ordered like the value) in
-// *word, which starts at zero.  A non-finite input counts as infinite.
+// cnt->disp_bits, which starts at zero.  An input that the search would
+// reject counts as infinite, so that the search runs and reports it.  Lists
+// of another epoch (or none) are not measured: `sorted` may not hold this
+// call's particles.
 __global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
                        const double* __restrict__ r, const double* __restrict__ q,
                        const double* __restrict__ semi,
-                       const double4* __restrict__ ref, unsigned long long* word) {
+                       const double4* __restrict__ ref, const ListState* state,
+                       Counters* cnt) {
+  if (state->epoch != d.list_epoch) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   double m = 0.0;
   if (s < d.n) {
@@ -898,29 +939,42 @@ __global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
     if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
     if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
     if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
-    const double a = semi[2 * p], b = semi[2 * p + 1];
-    const double grow = fmax(a, b) - o.w;
+    const double grow = fmax(semi[2 * p], semi[2 * p + 1]) - o.w;
     m = sqrt(dx * dx + dy * dy + dz * dz) + (grow > 0.0 ? grow : 0.0);
-    // inputs the build would reject: build again (and report them)
-    const double qn = sqrt(q[4 * p] * q[4 * p] + q[4 * p + 1] * q[4 * p + 1] +
-                           q[4 * p + 2] * q[4 * p + 2] + q[4 * p + 3] * q[4 * p + 3]);
-    const bool ok = isfinite(m) && isfinite(grow) && fabs(qn - 1.0) <= 1e-6 && a > 0.0 &&
-                    b > 0.0 && fmax(a, b) <= d.rmax_bound &&
-                    (d.model != LUB_MODEL_LADD || a == b);
-    if (!ok) m = INFINITY;
+    if (!isfinite(m) || input_faults(d, r, q, semi, p) != 0) m = INFINITY;
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0 && m > 0.0)
-    atomicMax(word, (unsigned long long)__double_as_longlong(m));
+    atomicMax(&cnt->disp_bits, (unsigned long long)__double_as_longlong(m));
 }
 
-// records of the current inputs in the cell order of the last build
+// The call's decision: search when the lists are of another epoch or some
+// particle moved plus grew by more than half the skin (the margin keeps a
+// rounding of the measure from deciding).  Every pair within the bound now
+// was then within the bound + skin at the search: the distance changed by
+// at most the two displacements and the bound grew by at most the two
+// growths.
+__global__ void k_decide(CallDesc d, ListState* state, Counters* cnt) {
+  if (threadIdx.x != 0) return;
+  const double m = __longlong_as_double((long long)cnt->disp_bits);
+  const bool search = state->epoch != d.list_epoch || !(2.0 * m <= d.skin * (1.0 - 1e-12));
+  cnt->rebuild = search ? 1 : 0;
+  if (search) {
+    state->epoch = d.list_epoch;
+    state->builds += 1;
+  }
+}
+
+// records of the current inputs in the cell order of the last search (calls
+// that reuse the lists only)
 __global__ void k_refresh(CallDesc d, const int32_t* __restrict__ sorted,
                           const double* __restrict__ r, const double* __restrict__ q,
                           const double* __restrict__ semi, const double* __restrict__ v,
                           const double* __restrict__ w, PRec* __restrict__ rec,
-                          double4* __restrict__ pos, KRec* __restrict__ kin) {
+                          double4* __restrict__ pos, KRec* __restrict__ kin,
+                          const Counters* cnt) {
+  if (cnt->rebuild) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.n) return;
   make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
@@ -929,19 +983,20 @@ __global__ void k_refresh(CallDesc d, const int32_t* __restrict__ sorted,
 }  // namespace
 
 void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                 const double* semi, const double4* ref, unsigned long long* word,
+                 const double* semi, const double4* ref, ListState* state, Counters* cnt,
                  hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_disp, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q, semi,
-                     ref, word);
+                     ref, state, cnt);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, d, state, cnt);
 }
 
 void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
                     const double* semi, const double* v, const double* w, PRec* rec,
-                    double4* pos, KRec* kin, hipStream_t s) {
+                    double4* pos, KRec* kin, const Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_refresh, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q,
-                     semi, v, w, rec, pos, kin);
+                     semi, v, w, rec, pos, kin, cnt);
 }
 
 // lanes per particle: the smallest group whose lanes hold the segment at 8

@@ -9,8 +9,11 @@ superset of that search is filtered by the exact centre test.
   steps reuse the lists and some search again.
 * A particle that grows beyond half the skin forces a search.
 * Against the FP64 oracle after reuse steps, at the FP64 bar.
-* Argument errors: negative skin, skin with graph mode, skin with
-  Lees-Edwards images.
+* Graph replay, asynchronous: the device decides, every replay equals a
+  fresh search.
+* A superset that overflows fixed segments fails every call (no silent
+  reuse of a truncated list), and a later handle with room succeeds.
+* Argument errors: negative skin, skin with Lees-Edwards images.
 """
 import numpy as np
 import pytest
@@ -127,12 +130,82 @@ def test_reuse_against_oracle(ref):
     lb.close()
 
 
+def superset_degree(wl, skin):
+    """Largest superset length: one synchronous call with automatic growth."""
+    lb = L.Lub.for_workload(wl, skin=skin)
+    lb.compute(*L.to_device(wl))
+    deg = lb.stats()["max_degree"]
+    lb.close()
+    return deg
+
+
+def test_graph_replay_trajectory():
+    wl = W.config2()
+    print("[gpu] reused lists under graph replay", flush=True)
+    cap = min(512, 64 * -(-int(1.5 * superset_degree(wl, 1.0) + 1) // 64))
+    rng = np.random.default_rng(53)
+    vel = rng.normal(scale=0.1, size=(wl.n, 3))
+    lb = L.Lub.for_workload(wl, precision=L.LUB_MIXED, skin=1.0, graph=1, sync=0,
+                            max_neighbors=cap)
+    r0, q, semi, v, w = L.to_device(wl)
+    r = r0.clone()
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    vd = dev(vel)
+    checked = 0
+    stream = torch.cuda.Stream()   # graph replay needs a stream of its own
+    for k in range(12):
+        with torch.cuda.stream(stream):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+        if k % 3 == 2:   # compare some replays with a fresh search on the same positions
+            torch.cuda.synchronize()
+            st = lb.stats()
+            assert st["error"] == 0
+            fresh = L.Lub.for_workload(wl, precision=L.LUB_MIXED)
+            ff, tf = fresh.compute(r, q, semi, v, w)
+            assert np.array_equal(lb.pairs()[0], fresh.pairs()[0]), f"step {k}"
+            assert close(f.cpu().numpy(), ff.cpu().numpy(), 1e-12), f"step {k}"
+            assert close(t.cpu().numpy(), tf.cpu().numpy(), 1e-12), f"step {k}"
+            fresh.close()
+            checked += 1
+        with torch.cuda.stream(stream):
+            r.add_(vd, alpha=0.4)
+    torch.cuda.synchronize()
+    builds = lb.stats()["list_builds"]
+    lb.close()
+    print(f"{builds} searches in 12 calls")
+    assert checked == 4 and 1 < builds < 12
+
+
+def test_overflowing_superset_fails_every_call():
+    wl = W.config2()
+    print("[gpu] reused lists: superset beyond fixed segments", flush=True)
+    exact = L.Lub.for_workload(wl)
+    exact.compute(*L.to_device(wl))
+    need = exact.stats()["max_degree"]
+    exact.close()
+    skin = next(s for s in (12.0, 16.0, 20.0) if superset_degree(wl, s) > 64)
+    assert need <= 64
+    lb = L.Lub.for_workload(wl, skin=skin, max_neighbors=64)
+    arrays = L.to_device(wl)
+    for _ in range(2):
+        with pytest.raises(L.LubError):
+            lb.compute(*arrays)
+    lb.close()
+    lb = L.Lub.for_workload(wl, skin=skin, max_neighbors=512)
+    f, t = lb.compute(*arrays)
+    fresh = L.Lub.for_workload(wl)
+    ff, tf = fresh.compute(*arrays)
+    assert np.array_equal(lb.pairs()[0], fresh.pairs()[0])
+    assert close(f.cpu().numpy(), ff.cpu().numpy(), 1e-12)
+    lb.close()
+    fresh.close()
+
+
 def test_skin_errors():
     wl = W.config2(n=500)
     with pytest.raises(L.LubError):
         L.Lub.for_workload(wl, skin=-1.0)
-    with pytest.raises(L.LubError):
-        L.Lub.for_workload(wl, skin=1.0, graph=1, sync=0)
     wls = W.sheared(n=300)
     lb = L.Lub.for_workload(wls, skin=1.0)
     with pytest.raises(L.LubError):
