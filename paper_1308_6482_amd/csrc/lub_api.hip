@@ -33,6 +33,8 @@ struct lub_ctx {
   int32_t* sup_nbr = nullptr;
   int32_t* sup_deg = nullptr;
   double4* ref_pos = nullptr;
+  int32_t* inv = nullptr;
+  double* disp_blk = nullptr;
   ListState* list_state = nullptr;
   int32_t list_epoch = 0;
   int64_t epoch_n = -1;
@@ -218,7 +220,8 @@ int ensure_particles(lub_ctx* c, int64_t n) {
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
     return rc;
   if (c->opt.skin > 0.0 &&
-      ((rc = realloc_buf(&c->sup_deg, need)) || (rc = realloc_buf(&c->ref_pos, need))))
+      ((rc = realloc_buf(&c->sup_deg, need)) || (rc = realloc_buf(&c->ref_pos, need)) ||
+       (rc = realloc_buf(&c->inv, need)) || (rc = realloc_buf(&c->disp_blk, (need + 255) / 256))))
     return rc;
   c->list_epoch++;
   c->cap_n = need;
@@ -459,9 +462,10 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   // only if it does not
   const bool reuse = d.n > 0 && d.skin > 0.0;
   const Counters* gate = reuse ? c->cnt : nullptr;
+  const ListBufs lists{c->sup_nbr, c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state};
   if (reuse) {
-    launch_disp(d, c->sorted, r, q, semi, c->ref_pos, c->list_state, c->cnt, s);
-    launch_refresh(d, c->sorted, r, q, semi, v, w, c->rec, c->pos, c->kin, c->cnt, s);
+    launch_disp(d, r, q, semi, lists, c->cnt, s);
+    launch_refresh(d, r, q, semi, v, w, lists, c->rec, c->pos, c->kin, c->cnt, s);
   }
   if (d.n > 0) {
     if (small) {
@@ -483,11 +487,10 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       // the superset (searched in calls that search), then the exact filter
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->sup_deg, c->sup_nbr, c->slot, c->wall_slot, c->work_s,
-                            c->work_t, c->stat_nbr, c->cnt, s, 1, nullptr, nullptr,
-                            c->ref_pos, c->list_state);
+                            c->work_t, c->stat_nbr, c->cnt, s, 1, &lists);
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
-                            c->stat_nbr, c->cnt, s, 2, c->sup_nbr, c->sup_deg);
+                            c->stat_nbr, c->cnt, s, 2, &lists);
     } else {
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
@@ -559,7 +562,7 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
           c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
-          c->sup_deg, c->ref_pos, c->list_state};
+          c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state};
 }
 
 void drop_graphs(lub_ctx* c) {
@@ -1189,7 +1192,8 @@ void lub_destroy(lub_handle_t h) {
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);
-  for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->list_state})
+  for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->inv,
+                  (void*)h->disp_blk, (void*)h->list_state})
     if (p) hipFree(p);
   if (h->side) {
     hipStreamSynchronize(h->side);

@@ -45,9 +45,7 @@ struct Counters {
   int64_t warm_seeded;    // pairs started from the previous call's normal
   int64_t max_degree;     // largest number of candidates of one particle
   int64_t iter_hist[32];
-  // reused neighbour lists: the largest displacement plus growth since the
-  // last search (bits of a non-negative double) and this call's decision
-  unsigned long long disp_bits;
+  // reused neighbour lists: this call's decision (1: search)
   int32_t rebuild;
   int32_t pad_list;
 };
@@ -58,6 +56,19 @@ struct ListState {
   int32_t epoch;
   int32_t pad;
   int64_t builds;
+};
+
+// The buffers of reused neighbour lists: the superset segments and their
+// lengths (cell order of the search), each particle's position and R_max at
+// the search and its place in the search's cell order (input order), one
+// displacement maximum per block of the measuring kernel, and the state.
+struct ListBufs {
+  int32_t* sup_nbr;
+  int32_t* sup_deg;
+  double4* ref_pos;
+  int32_t* inv;
+  double* disp_blk;
+  ListState* state;
 };
 
 // Per-block partial statistics, written with plain stores and summed only
@@ -164,19 +175,16 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode = 0,
-                           const int32_t* sup_nbr = nullptr,
-                           const int32_t* sup_deg = nullptr, double4* ref_pos = nullptr,
-                           ListState* state = nullptr);
+                           const ListBufs* lists = nullptr);
 // reused neighbour lists: the displacement plus growth since the search
 // (skipped unless the lists are of this epoch), then the decision (a
 // search if the lists are of another epoch or the measure exceeds half the
 // skin), and the records of the current inputs in the search's cell order
 // (a no-op when searching)
-void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                 const double* semi, const double4* ref, ListState* state, Counters* cnt,
-                 hipStream_t s);
-void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                    const double* semi, const double* v, const double* w, PRec* rec,
+void launch_disp(const CallDesc& d, const double* r, const double* q, const double* semi,
+                 const ListBufs& lists, Counters* cnt, hipStream_t s);
+void launch_refresh(const CallDesc& d, const double* r, const double* q, const double* semi,
+                    const double* v, const double* w, const ListBufs& lists, PRec* rec,
                     double4* pos, KRec* kin, const Counters* cnt, hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------

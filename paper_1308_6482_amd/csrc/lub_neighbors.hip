@@ -455,10 +455,11 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
 // kMode 0: the full search.  kMode 1: the superset of a reused list (bound
 // widened by the skin), only in calls that search: writes the sorted
 // segments into nbr, their lengths into deg (minus the count when a segment
-// overflows) and the positions and sizes of the search into ref_pos; an
-// overflow or an earlier input error discards the lists (state epoch -1).
-// kMode 2: the reused superset sup_nbr / sup_deg filtered by the exact centre
-// test on the current positions, then as the full search.
+// overflows), and per input index the position and size at the search
+// (lb.ref_pos) and the place in its cell order (lb.inv); an overflow or an
+// earlier input error discards the lists (state epoch -1).  kMode 2: the
+// reused superset lb.sup_nbr / lb.sup_deg filtered by the exact centre test
+// on the current positions, then as the full search.
 template <int G, int kMode>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
 k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
@@ -467,8 +468,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
             int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
             int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
             int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
-            const int32_t* __restrict__ sup_nbr, const int32_t* __restrict__ sup_deg,
-            double4* __restrict__ ref_pos, ListState* state) {
+            ListBufs lb) {
   if (kMode == 1 && !cnt->rebuild) return;  // the lists are reused
   constexpr int kPer = 64 / G;                 // particles per wavefront
   constexpr int kSteps = G == 64 ? 6 : (G == 32 ? 5 : 4);  // log2 G
@@ -501,10 +501,10 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     // the superset of the last build (sorted), filtered in order
     const double4 pi = pos[s];
     const double ri[3] = {pi.x, pi.y, pi.z};
-    const int ns_raw = sup_deg[s];
+    const int ns_raw = lb.sup_deg[s];
     const int ns = ns_raw > 0 ? ns_raw : 0;
     sup_need = ns_raw >= 0 ? ns_raw : -ns_raw;
-    const int32_t* seg = sup_nbr + (size_t)s * maxn;
+    const int32_t* seg = lb.sup_nbr + (size_t)s * maxn;
     for (int base = 0; base < ns; base += G) {
       const int e = base + gl;
       bool acc = false;
@@ -678,7 +678,8 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   const bool overflow = live && count > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
   const int nent = (live && !overflow) ? count : 0;
-  // rank sort: keys are distinct partner indices
+  // rank sort: keys are distinct partner indices (mode 2 keeps the order of
+  // the sorted superset: the rank is the position)
   const int me = live ? orig[s] : 0;
   const double* Mi = live ? rec[s].M : nullptr;
   double rs[3] = {0, 0, 0};
@@ -694,7 +695,10 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     if (e >= nent) continue;
     const int key = keys[e];
     int rank = 0;
-    for (int m2 = 0; m2 < nent; ++m2) rank += keys[m2] < key;
+    if (kMode == 2)
+      rank = e;
+    else
+      for (int m2 = 0; m2 < nent; ++m2) rank += keys[m2] < key;
     nbr[(size_t)s * maxn + rank] = key;
     my_key[k] = key;
     if (kMode == 1) continue;  // the superset: segments only
@@ -726,10 +730,11 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   if (kMode == 1) {
     if (live && gl == 0) {
       deg[s] = overflow ? -count : nent;
-      ref_pos[s] = pos[s];
-      if (overflow) state->epoch = -1;
+      lb.ref_pos[me] = pos[s];
+      lb.inv[me] = s;
+      if (overflow) lb.state->epoch = -1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt->error) state->epoch = -1;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt->error) lb.state->epoch = -1;
     return;
   }
   if (live && d.n_walls && gl < 2) {
@@ -877,21 +882,19 @@ void launch_nbr_mode(int mode, dim3 grid, size_t lds, hipStream_t s, const CallD
                      const PRec* rec, const double4* pos, const int32_t* orig,
                      const int32_t* cell_sorted, const int32_t* cell_start, int32_t* deg,
                      int32_t* nbr, int32_t* slot, int32_t* wall_slot, int32_t* work_s,
-                     int32_t* work_t, int64_t* stat_nbr, Counters* cnt,
-                     const int32_t* sup_nbr, const int32_t* sup_deg, double4* ref_pos,
-                     ListState* state) {
+                     int32_t* work_t, int64_t* stat_nbr, Counters* cnt, const ListBufs& lb) {
   if (mode == 0)
     hipLaunchKernelGGL((k_neighbors<G, 0>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                       work_t, stat_nbr, cnt, lb);
   else if (mode == 1)
     hipLaunchKernelGGL((k_neighbors<G, 1>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                       work_t, stat_nbr, cnt, lb);
   else
     hipLaunchKernelGGL((k_neighbors<G, 2>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
                        pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                       work_t, stat_nbr, cnt, lb);
 }
 
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
@@ -899,42 +902,40 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
-                           Counters* cnt, hipStream_t s, int mode, const int32_t* sup_nbr,
-                           const int32_t* sup_deg, double4* ref_pos, ListState* state) {
+                           Counters* cnt, hipStream_t s, int mode, const ListBufs* lists) {
+  const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
   dim3 grid(nbr_blocks(d));
   size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
   if (nbr_group(d) == 16)
     launch_nbr_mode<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
   else if (nbr_group(d) == 32)
     launch_nbr_mode<32>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
   else
     launch_nbr_mode<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
-                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, sup_nbr, sup_deg, ref_pos, state);
+                        nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
 }
 
 namespace {
 
+constexpr int kDispThreads = 256;
+
 // Reused neighbour lists: the largest of |displacement since the search|
-// (minimum image) + growth of R_max since the search over all particles, as
-// the bit pattern of a non-negative double (ordered like the value) in
-// cnt->disp_bits, which starts at zero.  An input that the search would
-// reject counts as infinite, so that the search runs and reports it.  Lists
-// of another epoch (or none) are not measured: `sorted` may not hold this
-// call's particles.
-__global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
-                       const double* __restrict__ r, const double* __restrict__ q,
-                       const double* __restrict__ semi,
-                       const double4* __restrict__ ref, const ListState* state,
-                       Counters* cnt) {
-  if (state->epoch != d.list_epoch) return;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// (minimum image) + growth of R_max since the search, per block of
+// particles in input order, into lb.disp_blk.  An input that the search
+// would reject counts as infinite, so that the search runs and reports it.
+// Lists of another epoch (or none) are not measured.
+__global__ void __launch_bounds__(kDispThreads)
+k_disp(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
+       const double* __restrict__ semi, ListBufs lb) {
+  __shared__ double s_max[kDispThreads / 64];
+  if (lb.state->epoch != d.list_epoch) return;
+  const int p = blockIdx.x * kDispThreads + threadIdx.x;
   double m = 0.0;
-  if (s < d.n) {
-    const int p = sorted[s];
-    const double4 o = ref[s];
+  if (p < d.n) {
+    const double4 o = lb.ref_pos[p];
     double dx = r[3 * p] - o.x, dy = r[3 * p + 1] - o.y, dz = r[3 * p + 2] - o.z;
     if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
     if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
@@ -945,8 +946,13 @@ __global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0 && m > 0.0)
-    atomicMax(&cnt->disp_bits, (unsigned long long)__double_as_longlong(m));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = s_max[0];
+    for (int k = 1; k < kDispThreads / 64; ++k) b = fmax(b, s_max[k]);
+    lb.disp_blk[blockIdx.x] = b;
+  }
 }
 
 // The call's decision: search when the lists are of another epoch or some
@@ -954,53 +960,63 @@ __global__ void k_disp(CallDesc d, const int32_t* __restrict__ sorted,
 // rounding of the measure from deciding).  Every pair within the bound now
 // was then within the bound + skin at the search: the distance changed by
 // at most the two displacements and the bound grew by at most the two
-// growths.
-__global__ void k_decide(CallDesc d, ListState* state, Counters* cnt) {
+// growths.  One block.
+__global__ void __launch_bounds__(kDispThreads)
+k_decide(CallDesc d, ListBufs lb, Counters* cnt) {
+  __shared__ double s_max[kDispThreads / 64];
+  const bool same = lb.state->epoch == d.list_epoch;
+  double m = 0.0;
+  if (same) {
+    const int nb = (d.n + kDispThreads - 1) / kDispThreads;
+    for (int k = threadIdx.x; k < nb; k += kDispThreads) m = fmax(m, lb.disp_blk[k]);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  const double m = __longlong_as_double((long long)cnt->disp_bits);
-  const bool search = state->epoch != d.list_epoch || !(2.0 * m <= d.skin * (1.0 - 1e-12));
+  for (int k = 1; k < kDispThreads / 64; ++k) m = fmax(m, s_max[k]);
+  const bool search = !same || !(2.0 * m <= d.skin * (1.0 - 1e-12));
   cnt->rebuild = search ? 1 : 0;
   if (search) {
-    state->epoch = d.list_epoch;
-    state->builds += 1;
+    lb.state->epoch = d.list_epoch;
+    lb.state->builds += 1;
   }
 }
 
 // records of the current inputs in the cell order of the last search (calls
-// that reuse the lists only)
-__global__ void k_refresh(CallDesc d, const int32_t* __restrict__ sorted,
-                          const double* __restrict__ r, const double* __restrict__ q,
-                          const double* __restrict__ semi, const double* __restrict__ v,
-                          const double* __restrict__ w, PRec* __restrict__ rec,
-                          double4* __restrict__ pos, KRec* __restrict__ kin,
-                          const Counters* cnt) {
+// that reuse the lists only): read in input order, written to their places
+__global__ void k_refresh(CallDesc d, const double* __restrict__ r,
+                          const double* __restrict__ q, const double* __restrict__ semi,
+                          const double* __restrict__ v, const double* __restrict__ w,
+                          ListBufs lb, PRec* __restrict__ rec, double4* __restrict__ pos,
+                          KRec* __restrict__ kin, const Counters* cnt) {
   if (cnt->rebuild) return;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= d.n) return;
-  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
+  make_record(lb.inv[p], p, nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
 }
 
 }  // namespace
 
-void launch_disp(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                 const double* semi, const double4* ref, ListState* state, Counters* cnt,
-                 hipStream_t s) {
+void launch_disp(const CallDesc& d, const double* r, const double* q, const double* semi,
+                 const ListBufs& lists, Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
-  hipLaunchKernelGGL(k_disp, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q, semi,
-                     ref, state, cnt);
-  hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, d, state, cnt);
+  hipLaunchKernelGGL(k_disp, dim3((d.n + kDispThreads - 1) / kDispThreads), dim3(kDispThreads),
+                     0, s, d, r, q, semi, lists);
+  hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDispThreads), 0, s, d, lists, cnt);
 }
 
-void launch_refresh(const CallDesc& d, const int32_t* sorted, const double* r, const double* q,
-                    const double* semi, const double* v, const double* w, PRec* rec,
+void launch_refresh(const CallDesc& d, const double* r, const double* q, const double* semi,
+                    const double* v, const double* w, const ListBufs& lists, PRec* rec,
                     double4* pos, KRec* kin, const Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
-  hipLaunchKernelGGL(k_refresh, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted, r, q,
-                     semi, v, w, rec, pos, kin, cnt);
+  hipLaunchKernelGGL(k_refresh, dim3((d.n + 255) / 256), dim3(256), 0, s, d, r, q, semi, v, w,
+                     lists, rec, pos, kin, cnt);
 }
 
 // lanes per particle: the smallest group whose lanes hold the segment at 8
-// entries per lane
+// entries per lane (more lanes for small systems measured slower)
 int nbr_group(const CallDesc& d) {
   return d.max_nbr <= 8 * 16 ? 16 : (d.max_nbr <= 8 * 32 ? 32 : 64);
 }
