@@ -187,17 +187,18 @@ typedef struct {
   int32_t reserved;        /* must be 0 */
   double skin;             /* > 0: reuse the neighbour lists across calls.  A search */
                            /* keeps every pair within the pruning bound + skin; a */
-                           /* call reuses the lists while every particle moved (minimum */
-                           /* image) plus grew in max(R_par, R_perp) by at most */
-                           /* skin / 2 since the search, re-applying the exact centre */
-                           /* test to the kept pairs, and searches again otherwise (or */
-                           /* when n, the parameters or the domain changed, or a call */
+                           /* call reuses the lists while 2 (largest displacement, */
+                           /* nearest image, + growth of max(R_par, R_perp)) + the */
+                           /* change of the Lees-Edwards offset since the search stays */
+                           /* within the skin, re-applying the exact centre test to */
+                           /* the kept pairs, and searches again otherwise (or when */
+                           /* n, the parameters or the domain other than the */
+                           /* Lees-Edwards offset and velocity changed, or a call */
                            /* failed).  The device takes the decision: calls stay */
                            /* asynchronous and may be captured (graph = 1).  The pair */
                            /* lists equal those of a fresh search.  The superset needs */
                            /* wider segments (max_neighbors, or the automatic growth */
-                           /* with sync = 1).  No Lees-Edwards images (else */
-                           /* LUB_EINVAL); periodic lengths must hold twice */
+                           /* with sync = 1).  Periodic lengths must hold twice */
                            /* 2 rmax_bound + cut-off + skin (else LUB_EDOMAIN). */
                            /* 0: search every call */
 } lub_opts_t;

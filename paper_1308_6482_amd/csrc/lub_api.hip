@@ -289,7 +289,6 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->n = (int32_t)n;
   d->dmax = max_cutoff(c->prm);
   d->skin = c->opt.skin;
-  if (d->skin > 0.0 && c->dom.lees_edwards) return LUB_EINVAL;
   // cells sized for the widest search: the pair bound plus the skin of
   // reused lists
   double edge = 2.0 * c->opt.rmax_bound + d->dmax + d->skin;
@@ -729,7 +728,7 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
   std::memset(c->host_cnt, 0, sizeof(Counters));
   if (c->opt.skin > 0.0) {
     // no lists yet (epoch -1), no searches
-    const ListState none{-1, 0, 0};
+    const ListState none{-1, 0, 0, 0.0};
     if (hipMalloc((void**)&c->list_state, sizeof(ListState)) != hipSuccess) {
       lub_destroy(c);
       return LUB_ENOMEM;
@@ -785,8 +784,13 @@ int lub_set_domain(lub_handle_t h, const lub_domain_t* domain) {
   if (!h) return LUB_EINVAL;
   int rc = check_domain(domain);
   if (rc) return rc;
+  // a new Lees-Edwards offset or velocity keeps reused lists (the offset's
+  // change enters the decision); any other change discards them
+  lub_domain_t a = h->dom, b = *domain;
+  a.le_offset = b.le_offset = 0.0;
+  a.le_velocity = b.le_velocity = 0.0;
+  if (std::memcmp(&a, &b, sizeof(a)) != 0) h->list_epoch++;
   h->dom = *domain;
-  h->list_epoch++;
   return LUB_OK;
 }
 

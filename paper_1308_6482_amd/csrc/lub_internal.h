@@ -56,6 +56,7 @@ struct ListState {
   int32_t epoch;
   int32_t pad;
   int64_t builds;
+  double le_offset;  // Lees-Edwards offset at the search
 };
 
 // The buffers of reused neighbour lists: the superset segments and their

@@ -923,8 +923,9 @@ namespace {
 constexpr int kDispThreads = 256;
 
 // Reused neighbour lists: the largest of |displacement since the search|
-// (minimum image) + growth of R_max since the search, per block of
-// particles in input order, into lb.disp_blk.  An input that the search
+// (the nearest image of the current centre seen from the centre at the
+// search, with the current Lees-Edwards offset) + growth of R_max since the
+// search, per block of particles in input order, into lb.disp_blk.  An input that the search
 // would reject counts as infinite, so that the search runs and reports it.
 // Lists of another epoch (or none) are not measured.
 __global__ void __launch_bounds__(kDispThreads)
@@ -936,12 +937,12 @@ k_disp(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
   double m = 0.0;
   if (p < d.n) {
     const double4 o = lb.ref_pos[p];
-    double dx = r[3 * p] - o.x, dy = r[3 * p + 1] - o.y, dz = r[3 * p + 2] - o.z;
-    if (d.periodic[0]) dx = min_image(dx, d.L[0], d.invL[0]);
-    if (d.periodic[1]) dy = min_image(dy, d.L[1], d.invL[1]);
-    if (d.periodic[2]) dz = min_image(dz, d.L[2], d.invL[2]);
+    const double r0[3] = {o.x, o.y, o.z};
+    const double r1[3] = {r[3 * p], r[3 * p + 1], r[3 * p + 2]};
+    double u[3];
+    pair_image(d, r0, r1, u);
     const double grow = fmax(semi[2 * p], semi[2 * p + 1]) - o.w;
-    m = sqrt(dx * dx + dy * dy + dz * dz) + (grow > 0.0 ? grow : 0.0);
+    m = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + (grow > 0.0 ? grow : 0.0);
     if (!isfinite(m) || input_faults(d, r, q, semi, p) != 0) m = INFINITY;
   }
 #pragma unroll
@@ -955,11 +956,15 @@ k_disp(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
   }
 }
 
-// The call's decision: search when the lists are of another epoch or some
-// particle moved plus grew by more than half the skin (the margin keeps a
-// rounding of the measure from deciding).  Every pair within the bound now
-// was then within the bound + skin at the search: the distance changed by
-// at most the two displacements and the bound grew by at most the two
+// The call's decision: search when the lists are of another epoch or when
+// 2 (largest displacement + growth) + |change of the Lees-Edwards offset
+// since the search| exceeds the skin (the margin keeps a rounding of the
+// measure from deciding).  Every pair within the bound now was then within
+// the bound + skin at the search: writing each centre as its centre at the
+// search plus its displacement plus a lattice vector of the current images,
+// the pair's image vector differs from one at the search by the two
+// displacements and at most one box's change of offset (the images in
+// question are the nearest in z), and the bound grew by at most the two
 // growths.  One block.
 __global__ void __launch_bounds__(kDispThreads)
 k_decide(CallDesc d, ListBufs lb, Counters* cnt) {
@@ -976,11 +981,15 @@ k_decide(CallDesc d, ListBufs lb, Counters* cnt) {
   __syncthreads();
   if (threadIdx.x != 0) return;
   for (int k = 1; k < kDispThreads / 64; ++k) m = fmax(m, s_max[k]);
-  const bool search = !same || !(2.0 * m <= d.skin * (1.0 - 1e-12));
+  double shear = 0.0;
+  if (d.le && same)
+    shear = fabs(min_image(d.le_offset - lb.state->le_offset, d.L[0], d.invL[0]));
+  const bool search = !same || !(2.0 * m + shear <= d.skin * (1.0 - 1e-12));
   cnt->rebuild = search ? 1 : 0;
   if (search) {
     lb.state->epoch = d.list_epoch;
     lb.state->builds += 1;
+    lb.state->le_offset = d.le_offset;
   }
 }
 

@@ -13,7 +13,10 @@ superset of that search is filtered by the exact centre test.
   fresh search.
 * A superset that overflows fixed segments fails every call (no silent
   reuse of a truncated list), and a later handle with room succeeds.
-* Argument errors: negative skin, skin with Lees-Edwards images.
+* Lees-Edwards images: along a sheared trajectory with an advancing offset
+  every call equals a fresh search; the integrator with reused lists gives
+  the trajectory of the integrator without them (to rounding).
+* Argument errors: negative skin.
 """
 import numpy as np
 import pytest
@@ -202,12 +205,73 @@ def test_overflowing_superset_fails_every_call():
     fresh.close()
 
 
+def le_wrap(r, L, off):
+    """Centres back into the box; leaving through the top (bottom) moves a
+    centre by -off (+off) in x, the image convention of the domain."""
+    r = r.copy()
+    up = r[:, 2] >= L[2]
+    down = r[:, 2] < 0.0
+    r[up, 2] -= L[2]
+    r[up, 0] -= off
+    r[down, 2] += L[2]
+    r[down, 0] += off
+    r[:, 0] = np.mod(r[:, 0], L[0])
+    r[:, 1] = np.mod(r[:, 1], L[1])
+    return r
+
+
+def test_lees_edwards_trajectory():
+    wl = W.sheared()
+    off, U = wl.lees_edwards
+    print(f"[gpu] reused lists with Lees-Edwards images: {wl.name}", flush=True)
+    rng = np.random.default_rng(54)
+    vel = wl.v + rng.normal(scale=0.05, size=(wl.n, 3))
+    dt = 2.0
+    lb = L.Lub.for_workload(wl, precision=L.LUB_MIXED, skin=2.0)
+    q, semi, v, w = (dev(x) for x in (wl.q, wl.semi, wl.v, wl.w))
+    r = wl.r.copy()
+    builds = []
+    for k in range(10):
+        rd = dev(r)
+        fs, ts = lb.compute(rd, q, semi, v, w)
+        builds.append(lb.stats()["list_builds"])
+        fresh = L.Lub.for_workload(wl, precision=L.LUB_MIXED, lees_edwards=(off, U))
+        ff, tf = fresh.compute(rd, q, semi, v, w)
+        assert np.array_equal(lb.pairs()[0], fresh.pairs()[0]), f"step {k}"
+        assert lb.stats()["active"] == fresh.stats()["active"]
+        assert close(fs.cpu().numpy(), ff.cpu().numpy(), 1e-12), f"step {k}"
+        assert close(ts.cpu().numpy(), tf.cpu().numpy(), 1e-12), f"step {k}"
+        fresh.close()
+        off = float(np.mod(off + U * dt, wl.L[0]))
+        lb.set_domain(lees_edwards=(off, U))   # keeps the lists
+        r = le_wrap(r + dt * vel, wl.L, off)
+    lb.close()
+    print(f"list searches after each step: {builds}")
+    assert builds[-1] > builds[0] and builds[-1] - builds[0] < len(builds) - 1
+
+
+def test_integrator_with_reused_lists():
+    wl = W.sheared(n=2000)
+    print("[gpu] lub_integrate with and without reused lists", flush=True)
+    rng = np.random.default_rng(55)
+    v0 = wl.v + rng.normal(scale=0.01, size=(wl.n, 3))
+    out = []
+    for skin in (0.0, 1.0):
+        lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, skin=skin)
+        r, q, semi, v, w = (dev(x) for x in (wl.r, wl.q, wl.semi, v0, wl.w))
+        lb.integrate(r, q, semi, v, w, 0.1, 6)
+        torch.cuda.synchronize()
+        st = lb.stats()
+        assert st["error"] == 0
+        out.append(([x.cpu().numpy() for x in (r, q, v, w)], st["list_builds"]))
+        lb.close()
+    (a, _), (b, builds) = out
+    assert builds < 6
+    for x, y in zip(a, b):
+        assert close(y, x, 1e-10)
+
+
 def test_skin_errors():
     wl = W.config2(n=500)
     with pytest.raises(L.LubError):
         L.Lub.for_workload(wl, skin=-1.0)
-    wls = W.sheared(n=300)
-    lb = L.Lub.for_workload(wls, skin=1.0)
-    with pytest.raises(L.LubError):
-        lb.compute(*L.to_device(wls))
-    lb.close()
