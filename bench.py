@@ -63,7 +63,7 @@ def parse():
                          "system, 0.1 otherwise)")
     ap.add_argument("--skin", type=float, nargs="*", default=None,
                     help="trajectory leg: also time reused neighbour lists with these skins "
-                         "(default 2 for the full-scale system, 1 otherwise; none given: "
+                         "(default 4 for the full-scale system, 1 otherwise; none given: "
                          "skip)")
     ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
                     help="Newton start: line of centres, learned network, or time both "
@@ -406,24 +406,30 @@ def dynamics(L, torch, args):
     out = dict(workload=wl.name, lees_edwards=dict(
         value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
         ms_per_step_eager=ms_e, active=st["active"]))
-    # integrator: sub-steps of 0.1 with the correction evaluated each time
-    r, q, semi, v, w = L.to_device(wl)
-    lb = L.Lub.for_workload(wl, precision=prec, sync=0, max_neighbors=args.max_neighbors)
-    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
-    t = torch.empty_like(f)
+    # integrator: sub-steps of 0.1 with the correction evaluated each time,
+    # searching every sub-step or reusing the neighbour lists (skin 1)
     nsub = max(args.steps // 4, 1)
-    lb.integrate(r, q, semi, v, w, 0.1, 5, f=f, t=t)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lb.integrate(r, q, semi, v, w, 0.1, nsub, f=f, t=t)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sti = lb.stats()
-    lb.close()
-    if sti["error"]:
-        raise RuntimeError(f"lub_integrate failed: {L.lub_strerror(sti['error'])}")
-    out["integrator"] = dict(substeps=nsub, dt=0.1, ms_per_substep=(t1 - t0) * 1e3 / nsub,
-                             active_last=sti["active"])
+    for key, skin in (("integrator", 0.0), ("integrator_reused_lists", 1.0)):
+        r, q, semi, v, w = L.to_device(wl)
+        cap = args.max_neighbors if skin == 0.0 else neighbour_capacity(L, torch, wl, prec, skin)
+        lb = L.Lub.for_workload(wl, precision=prec, sync=0, max_neighbors=cap, skin=skin)
+        f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+        t = torch.empty_like(f)
+        lb.integrate(r, q, semi, v, w, 0.1, 5, f=f, t=t)
+        torch.cuda.synchronize()
+        b0 = lb.stats()["list_builds"]
+        t0 = time.perf_counter()
+        lb.integrate(r, q, semi, v, w, 0.1, nsub, f=f, t=t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sti = lb.stats()
+        lb.close()
+        if sti["error"]:
+            raise RuntimeError(f"lub_integrate failed: {L.lub_strerror(sti['error'])}")
+        out[key] = dict(substeps=nsub, dt=0.1, ms_per_substep=(t1 - t0) * 1e3 / nsub,
+                        active_last=sti["active"])
+        if skin > 0.0:
+            out[key].update(skin=skin, list_searches=sti["list_builds"] - b0)
     # growth stage: 4096 polydisperse spheroids from 30 % size to volume
     # fraction 0.45, 1200 steps
     rng = np.random.default_rng(7)
@@ -570,7 +576,7 @@ def main():
             plain=trajectory(L, torch, wl, prec, args, False))
         skins = args.skin
         if skins is None:
-            skins = [2.0] if args.workload == "fullscale1M" else [1.0]
+            skins = [4.0] if args.workload == "fullscale1M" else [1.0]
         for sk in skins:
             res["warm_start"][f"reused_lists_skin{sk:g}"] = trajectory(L, torch, wl, prec,
                                                                       args, False, sk)

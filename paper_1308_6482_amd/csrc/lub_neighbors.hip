@@ -15,6 +15,11 @@
 // segment per particle (cell-order indices), each segment sorted by partner
 // index; the pair (i, j) is evaluated once, from the entry whose owner has
 // the smaller input index.
+//
+// Reused lists (a skin): a search keeps every pair within the bound + skin;
+// later calls measure how far the particles moved and grew since, decide on
+// the device whether to search again, and otherwise refresh the records in
+// the old cell order and filter the kept pairs with the exact centre test.
 #include <hip/hip_runtime.h>
 
 #include "lub_internal.h"
@@ -97,38 +102,48 @@ __global__ void k_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
     reinterpret_cast<int32_t*>(c)[i] = 0;
 }
 
+// One particle's input, loaded at once.
+struct PIn {
+  double x, y, z, qw, qx, qy, qz, a, b;
+};
+
+__device__ __forceinline__ PIn load_input(const double* __restrict__ r,
+                                          const double* __restrict__ q,
+                                          const double* __restrict__ semi, int p) {
+  return PIn{r[3 * p],     r[3 * p + 1], r[3 * p + 2], q[4 * p],        q[4 * p + 1],
+             q[4 * p + 2], q[4 * p + 3], semi[2 * p],  semi[2 * p + 1]};
+}
+
 // checks of one particle's input: bit 0 an invalid value (EINVAL), bit 1 a
 // centre beyond a wall by more than the particle's size (EDOMAIN)
-__device__ __forceinline__ int input_faults(const CallDesc& d, const double* __restrict__ r,
-                                            const double* __restrict__ q,
-                                            const double* __restrict__ semi, int p) {
-  double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
-  double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
-  double a = semi[2 * p], b = semi[2 * p + 1];
-  bool ok = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qw) &&
-            isfinite(qx) && isfinite(qy) && isfinite(qz) && a > 0.0 && b > 0.0 &&
-            isfinite(a) && isfinite(b);
-  double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-  ok = ok && fabs(qn - 1.0) <= 1e-6 && fmax(a, b) <= d.rmax_bound;
-  ok = ok && (d.model != LUB_MODEL_LADD || a == b);  // Ladd's law is for spheres
-  double rm = fmax(a, b);
-  const bool wall = d.n_walls && (z < -rm || z > d.L[2] + rm);
+__device__ __forceinline__ int input_faults(const CallDesc& d, const PIn& u) {
+  bool ok = isfinite(u.x) && isfinite(u.y) && isfinite(u.z) && isfinite(u.qw) &&
+            isfinite(u.qx) && isfinite(u.qy) && isfinite(u.qz) && u.a > 0.0 && u.b > 0.0 &&
+            isfinite(u.a) && isfinite(u.b);
+  double qn = sqrt(u.qw * u.qw + u.qx * u.qx + u.qy * u.qy + u.qz * u.qz);
+  ok = ok && fabs(qn - 1.0) <= 1e-6 && fmax(u.a, u.b) <= d.rmax_bound;
+  ok = ok && (d.model != LUB_MODEL_LADD || u.a == u.b);  // Ladd's law is for spheres
+  double rm = fmax(u.a, u.b);
+  const bool wall = d.n_walls && (u.z < -rm || u.z > d.L[2] + rm);
   return (ok ? 0 : 1) | (wall ? 2 : 0);
 }
 
+__device__ __forceinline__ int input_faults(const CallDesc& d, const double* __restrict__ r,
+                                            const double* __restrict__ q,
+                                            const double* __restrict__ semi, int p) {
+  return input_faults(d, load_input(r, q, semi, p));
+}
+
 // validate one particle's input (EINVAL, EDOMAIN) and return its cell
-__device__ int validate_bin(const CallDesc& d, const double* __restrict__ r,
-                            const double* __restrict__ q,
-                            const double* __restrict__ semi, int p, Counters* cnt) {
-  double x = r[3 * p], y = r[3 * p + 1], z = r[3 * p + 2];
-  const int faults = input_faults(d, r, q, semi, p);
+__device__ int validate_bin(const CallDesc& d, const PIn& u, Counters* cnt) {
+  const int faults = input_faults(d, u);
   const bool ok = !(faults & 1);
   if (!ok) set_error(cnt, LUB_EINVAL);
-  double rm = fmax(semi[2 * p], semi[2 * p + 1]);
+  double rm = fmax(u.a, u.b);
   if (faults & 2) set_error(cnt, LUB_EDOMAIN);
-  int cx = cell_coord(x, d.L[0], d.periodic[0], d.cell[0], d.nc[0]);
-  int cy = cell_coord(y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
-  int cz = cell_coord(z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
+  int cx = cell_coord(u.x, d.L[0], d.periodic[0], d.cell[0], d.nc[0]);
+  int cy = cell_coord(u.y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
+  int cz = cell_coord(u.z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
   if (!ok) cx = cy = cz = 0;
   // the large particles' cells follow the small particles' cells
   const int big = rm > d.r_small ? d.nc[0] * d.nc[1] * d.nc[2] : 0;
@@ -144,7 +159,7 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
   if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
-  int c = validate_bin(d, r, q, semi, p, cnt);
+  int c = validate_bin(d, load_input(r, q, semi, p), cnt);
   cell_id[p] = c;
   atomicAdd(&cell_count[c], 1);
 }
@@ -361,12 +376,16 @@ __device__ __forceinline__ double support(const double* M, double nx, double ny,
 }
 
 // Whole cell build in one workgroup for small systems (all per-particle and
-// per-cell arrays in LDS): counter reset, validation and binning, counts,
-// exclusive scan, scatter, placement in increasing input index within each
-// cell and the cell-order records.  Replaces four to six launches.
+// per-cell arrays in LDS, 16-bit where the values fit): validation and
+// binning, counts, exclusive scan, scatter, placement in increasing input
+// index within each cell, and up to kSmallRecN particles the cell-order
+// records (beyond, k_records_sorted writes them with the whole chip).
+// Replaces four launches.  The counters were zeroed by the previous call.
 constexpr int kSmallThreads = 1024;
-constexpr int kSmallMaxN = 1024;
+constexpr int kSmallMaxN = 4096;
 constexpr int kSmallMaxCells = 4096;
+constexpr int kSmallRecN = 1024;
+constexpr int kSmallPer = kSmallMaxN / kSmallThreads;
 
 __global__ void __launch_bounds__(kSmallThreads)
 k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
@@ -377,21 +396,29 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
               int32_t* __restrict__ cell_sorted, Counters* cnt, const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists (uniform: one block)
   __shared__ int32_t cnt_l[kSmallMaxCells];        // counts, then cursors
-  __shared__ int32_t start_l[kSmallMaxCells + 1];
-  __shared__ int32_t cid_l[kSmallMaxN];            // cell of each input index
-  __shared__ int32_t scat_l[kSmallMaxN];           // scatter output
+  __shared__ int16_t start_l[kSmallMaxCells + 1];
+  __shared__ int16_t cid_l[kSmallMaxN];            // cell of each input index
+  __shared__ int16_t scat_l[kSmallMaxN];           // scatter output
   __shared__ int lds_scan[16];
   const int ncell = 2 * d.nc[0] * d.nc[1] * d.nc[2];  // bins: two size classes
   const int tid = threadIdx.x;
-  for (int i = tid; i < (int)(sizeof(Counters) / sizeof(int32_t)); i += kSmallThreads)
-    reinterpret_cast<int32_t*>(cnt)[i] = 0;
   for (int c = tid; c < ncell; c += kSmallThreads) cnt_l[c] = 0;
   __syncthreads();
-  const bool mine = tid < d.n;
-  if (mine) {
-    const int c = validate_bin(d, r, q, semi, tid, cnt);
-    cid_l[tid] = c;
-    atomicAdd(&cnt_l[c], 1);
+  // all loads first: one memory round trip for the thread's particles
+  PIn in[kSmallPer];
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int p = tid + k * kSmallThreads;
+    if (p < d.n) in[k] = load_input(r, q, semi, p);
+  }
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int p = tid + k * kSmallThreads;
+    if (p < d.n) {
+      const int c = validate_bin(d, in[k], cnt);
+      cid_l[p] = (int16_t)c;
+      atomicAdd(&cnt_l[c], 1);
+    }
   }
   __syncthreads();
   // exclusive scan of the counts, `per` consecutive cells per thread
@@ -407,32 +434,47 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
   for (int k = 0; k < per; ++k) {
     const int c = tid * per + k;
     if (c < ncell) {
-      start_l[c] = acc;
+      start_l[c] = (int16_t)acc;
       cell_start[c] = acc;
       acc += cnt_l[c];
       cnt_l[c] = 0;
     }
   }
   if (tid == 0) {
-    start_l[ncell] = tot;
+    start_l[ncell] = (int16_t)tot;
     cell_start[ncell] = tot;
   }
   __syncthreads();
-  if (mine) {
-    const int c = cid_l[tid];
-    scat_l[start_l[c] + atomicAdd(&cnt_l[c], 1)] = tid;
+  for (int p = tid; p < d.n; p += kSmallThreads) {
+    const int c = cid_l[p];
+    scat_l[start_l[c] + atomicAdd(&cnt_l[c], 1)] = (int16_t)p;
   }
   __syncthreads();
-  if (mine) {
-    const int p = scat_l[tid];
+  for (int i = tid; i < d.n; i += kSmallThreads) {
+    const int p = scat_l[i];
     const int c = cid_l[p];
     const int b = start_l[c], e = start_l[c + 1];
     int rank = 0;
     for (int k = b; k < e; ++k) rank += scat_l[k] < p;
     const int s = b + rank;
     sorted[s] = p;
-    make_record(s, p, cid_l, r, q, semi, v, w, rec, pos, kin, cell_sorted);
+    cell_sorted[s] = c;
+    if (d.n <= kSmallRecN) make_record(s, p, nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
   }
+}
+
+// the cell-order records of a small system's larger part: particle sorted[s]
+// into place s
+__global__ void k_records_sorted(CallDesc d, const int32_t* __restrict__ sorted,
+                                 const double* __restrict__ r, const double* __restrict__ q,
+                                 const double* __restrict__ semi,
+                                 const double* __restrict__ v, const double* __restrict__ w,
+                                 PRec* __restrict__ rec, double4* __restrict__ pos,
+                                 KRec* __restrict__ kin, const Counters* gate) {
+  if (gate && !gate->rebuild) return;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= d.n) return;
+  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
 }
 
 // A group of G lanes per particle (G = 64: one wavefront; G = 32 or 16: two
@@ -875,6 +917,9 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, d, r, q, semi,
                      v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt, gate);
+  if (d.n > kSmallRecN)
+    hipLaunchKernelGGL(k_records_sorted, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted,
+                       r, q, semi, v, w, rec, pos, kin, gate);
 }
 
 template <int G>

@@ -394,7 +394,8 @@ def lub_strerror(code: int) -> str:
 # --- convenience ---------------------------------------------------------------
 
 class Lub:
-    """Owns one handle; ``compute`` takes and returns torch.cuda tensors."""
+    """Owns one handle; ``compute`` takes and returns torch.cuda tensors.
+    ``skin`` > 0 reuses the neighbour lists across calls (lub_opts_t.skin)."""
 
     def __init__(self, L, periodic, params: dict, rmax_bound, n_walls=0,
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,

@@ -45,9 +45,13 @@ def close(a, b, tol):
     return np.abs(a - b).max() <= tol * scale
 
 
-@pytest.mark.parametrize("name,precision", [("config3", L.LUB_MIXED), ("config2", L.LUB_FP64)])
+@pytest.mark.parametrize("name,precision", [("config3", L.LUB_MIXED), ("config2", L.LUB_FP64),
+                                            ("config2_800", L.LUB_MIXED)])
 def test_trajectory_equals_fresh_search(name, precision):
-    wl = W.config3(n=6000) if name == "config3" else W.config2()
+    # 6000 particles between walls; 4096 and 800 periodic (the one-workgroup
+    # cell build, with and without the separate record kernel)
+    wl = {"config3": lambda: W.config3(n=6000), "config2": W.config2,
+          "config2_800": lambda: W.config2(n=800)}[name]()
     print(f"[gpu] reused lists along a trajectory: {wl.name}, precision={precision}", flush=True)
     rng = np.random.default_rng(51)
     vel = rng.normal(scale=0.15, size=(wl.n, 3))
