@@ -580,6 +580,9 @@ def main():
         for sk in skins:
             res["warm_start"][f"reused_lists_skin{sk:g}"] = trajectory(L, torch, wl, prec,
                                                                       args, False, sk)
+            # with the warm start kept per superset entry
+            res["warm_start"][f"reused_lists_warm_skin{sk:g}"] = trajectory(
+                L, torch, wl, prec, args, True, sk)
     if args.compare_models and args.model == "full":
         # the paper's "normal only" comparison model on the same suspension
         wn = wl.with_params(model=L.LUB_MODEL_NORMAL)

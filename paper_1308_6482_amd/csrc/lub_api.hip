@@ -36,6 +36,10 @@ struct lub_ctx {
   int32_t* inv = nullptr;
   double* disp_blk = nullptr;
   ListState* list_state = nullptr;
+  // warm start with reused lists: per superset entry the last normal, per
+  // evaluation slot its superset entry
+  float4* sup_val = nullptr;
+  int32_t* work_sup = nullptr;
   int32_t list_epoch = 0;
   int64_t epoch_n = -1;
   int32_t epoch_stride = 0;
@@ -252,6 +256,12 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
     if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)))
       return rc;
     if (c->opt.skin > 0.0 && (rc = realloc_buf(&c->sup_nbr, entries))) return rc;
+    if (c->opt.skin > 0.0 && c->opt.warm_start) {
+      // no stored normal yet: tag -1 matches no search
+      if ((rc = realloc_buf(&c->sup_val, entries))) return rc;
+      HIP_TRY(hipMemset(c->sup_val, 0xff, sizeof(float4) * entries));
+      HIP_TRY(hipDeviceSynchronize());  // cleared before any stream uses it
+    }
     c->list_epoch++;
     c->cap_entries = entries;
   }
@@ -262,6 +272,8 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
         (rc = realloc_buf((PairOut<double>**)&c->out, work)) ||
         (rc = realloc_buf(&c->out_h, work)) || (rc = realloc_buf(&c->out_status, work)) ||
         (rc = realloc_buf(&c->out_iters, work)))
+      return rc;
+    if (c->opt.skin > 0.0 && c->opt.warm_start && (rc = realloc_buf(&c->work_sup, work)))
       return rc;
     c->cap_work = work;
     if (c->opt.warm_start) {
@@ -278,6 +290,7 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
           return rc;
         HIP_TRY(hipMemset(c->warm_key[k], 0xff, sizeof(uint64_t) * size));
       }
+      HIP_TRY(hipDeviceSynchronize());  // cleared before any stream uses them
       c->warm_size = size;
     }
   }
@@ -406,11 +419,13 @@ CallDesc finalize_desc(lub_ctx* c, const CallDesc& d0) {
   // beside the pair kernel, save the gather its searches; below, the fork
   // and join cost more than they save
   d.partner_codes = d.n >= (1 << 18);
-  // Ladd's law has no closest-point iteration to start
-  d.warm_mask = c->opt.warm_start && c->warm_size > 0 && d.model != LUB_MODEL_LADD &&
-                        !is_link(d.model)
-                    ? c->warm_size - 1
-                    : 0;
+  // Ladd's law has no closest-point iteration to start.  With reused lists
+  // the normals are kept per superset entry (no hashing), else in the hash
+  // tables
+  const bool warm = c->opt.warm_start && d.model != LUB_MODEL_LADD && !is_link(d.model);
+  d.warm_slots = warm && d.skin > 0.0 && c->sup_val && c->work_sup &&
+                 (int64_t)std::max<int64_t>(d.n, 1) * d.max_nbr <= INT32_MAX;
+  d.warm_mask = warm && !d.warm_slots && c->warm_size > 0 ? c->warm_size - 1 : 0;
   return d;
 }
 
@@ -461,7 +476,9 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   // only if it does not
   const bool reuse = d.n > 0 && d.skin > 0.0;
   const Counters* gate = reuse ? c->cnt : nullptr;
-  const ListBufs lists{c->sup_nbr, c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state};
+  const ListBufs lists{c->sup_nbr,    c->sup_deg,    c->ref_pos,
+                       c->inv,        c->disp_blk,   c->list_state,
+                       d.warm_slots ? c->work_sup : nullptr};
   if (reuse) {
     launch_disp(d, r, q, semi, lists, c->cnt, s);
     launch_refresh(d, r, q, semi, v, w, lists, c->rec, c->pos, c->kin, c->cnt, s);
@@ -511,7 +528,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       seeds = c->seedY;
     }
     WarmTables warm{c->warm_key[wp], c->warm_val[wp], c->warm_key[wc], c->warm_val[wc],
-                    c->sorted};
+                    c->sorted,       c->work_sup,     c->sup_val,      c->list_state};
     if (is_link(d.model)) {
       launch_links(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h, c->out_status,
                    c->out_links, c->stat_pair, c->cnt, s);
@@ -561,7 +578,7 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
           c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
-          c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state};
+          c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state, c->sup_val, c->work_sup};
 }
 
 void drop_graphs(lub_ctx* c) {
@@ -1197,7 +1214,8 @@ void lub_destroy(lub_handle_t h) {
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);
   for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->inv,
-                  (void*)h->disp_blk, (void*)h->list_state})
+                  (void*)h->disp_blk, (void*)h->list_state, (void*)h->sup_val,
+                  (void*)h->work_sup})
     if (p) hipFree(p);
   if (h->side) {
     hipStreamSynchronize(h->side);

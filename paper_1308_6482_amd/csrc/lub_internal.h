@@ -70,6 +70,7 @@ struct ListBufs {
   int32_t* inv;
   double* disp_blk;
   ListState* state;
+  int32_t* work_sup;  // per evaluation slot: its superset entry (warm start)
 };
 
 // Per-block partial statistics, written with plain stores and summed only
@@ -103,7 +104,7 @@ struct CallDesc {
   double wall_vel[2][3];
   double skin;           // reused neighbour lists: superset margin (0: off)
   int32_t list_epoch;    // lists searched under another epoch are not reused
-  int32_t pad_epoch;
+  int32_t warm_slots;    // warm start stored per superset entry (reused lists)
   int32_t le;            // Lees-Edwards images (all axes periodic, no walls)
   double le_offset;      // x offset of the image one box up, in [0, L_x)
   double le_vel;         // x velocity of the image one box up
@@ -201,6 +202,11 @@ struct WarmTables {
   uint64_t* cur_key;         // written: this call's pairs (all empty on entry)
   float4* cur_val;
   const int32_t* orig;       // cell order -> input index
+  // with reused lists (CallDesc::warm_slots): the last normal of each
+  // superset entry, tagged with the search that made the superset
+  const int32_t* slot_sup;   // evaluation slot -> superset entry
+  float4* sup_val;           // normal (x, y, z), tag in w (int bits)
+  const ListState* state;    // the current search count (the tag)
 };
 
 void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,

@@ -515,7 +515,9 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   constexpr int kPer = 64 / G;                 // particles per wavefront
   constexpr int kSteps = G == 64 ? 6 : (G == 32 ? 5 : 4);  // log2 G
   constexpr unsigned long long kGroupMask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-  extern __shared__ int32_t lds_keys[];        // kWavesPerBlock * kPer * max_nbr
+  // kWavesPerBlock * kPer * max_nbr partner keys; mode 2 with a warm start
+  // then as many superset positions
+  extern __shared__ int32_t lds_keys[];
   __shared__ int s_keep[kWavesPerBlock];
   __shared__ int s_upper[kWavesPerBlock];
   __shared__ int s_wallc[kWavesPerBlock];
@@ -529,6 +531,9 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   const int s = (blockIdx.x * kWavesPerBlock + wv) * kPer + grp;
   const int maxn = d.max_nbr;
   int32_t* keys = lds_keys + (wv * kPer + grp) * maxn;
+  // mode 2 with a warm start: the superset position of each kept key
+  int32_t* keys_e = keys + kWavesPerBlock * kPer * maxn;
+  const bool want_e = kMode == 2 && lb.work_sup != nullptr;
   const bool live = s < d.n;
 
   int count = 0;
@@ -560,7 +565,10 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
       const unsigned long long m = (__ballot(acc) >> gbase) & kGroupMask;
       if (acc) {
         const int at = count + lane_prefix(m, gl);
-        if (at < maxn) keys[at] = t;
+        if (at < maxn) {
+          keys[at] = t;
+          if (want_e) keys_e[at] = e;
+        }
       }
       count += __popcll(m);
     }
@@ -842,6 +850,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     slot[(size_t)s * maxn + rank] = next;
     work_s[next] = s;
     work_t[next] = my_key[k];
+    if (want_e) lb.work_sup[next] = s * maxn + keys_e[rank];
     ++next;
   }
   if (d.n_walls && gl < 2 && wall_keep) {
@@ -952,6 +961,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
   if (d.n == 0) return;
   dim3 grid(nbr_blocks(d));
   size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
+  if (mode == 2 && lists && lists->work_sup) lds *= 2;  // the superset positions too
   if (nbr_group(d) == 16)
     launch_nbr_mode<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);

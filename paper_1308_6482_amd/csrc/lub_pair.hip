@@ -172,19 +172,16 @@ struct Solve {
 };
 
 // Newton iteration for the stationary point of g(n) on the unit sphere,
-// started from n0 (unit) or, when n0 is null, from the line of centres
+// started from n0 (unit) when use_n0, else from the line of centres (the
+// start is selected by value: no pointer to a local escapes to memory)
 __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
                                                 const double* Mi,
                                                 const double* Mj, int maxit,
-                                                const double* n0 = nullptr) {
+                                                const double (&n0)[3], bool use_n0) {
   Solve o;
   double dn = sqrt(dot3(d, d));
   double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
-  if (n0) {
-    n[0] = n0[0];
-    n[1] = n0[1];
-    n[2] = n0[2];
-  }
+  for (int k = 0; k < 3; ++k) n[k] = use_n0 ? n0[k] : n[k];
   double prev = 1.0;
   o.ok = false;
   int it = 0;
@@ -576,13 +573,16 @@ __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec
   for (int k = 0; k < 3; ++k) out.F[k] = R(fn * n[k]);
 }
 
+// nseed (used when use_nseed): the previous call's normal; fell_back and
+// warm_used are set to 1 when the solve fell back to another start or
+// started from nseed; nout receives the converged normal.
 template <typename R, bool kTangent>
 __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
                           const PRec* B, const KRec* KB, int side,
                           PairOut<R>& out, double& hout, int& status,
-                          int& iters, const float* seedY = nullptr,
-                          int* fell_back = nullptr, const double* nseed = nullptr,
-                          int* warm_used = nullptr, double* nout = nullptr) {
+                          int& iters, const float* seedY, int& fell_back,
+                          const double (&nseed)[3], bool use_nseed, int& warm_used,
+                          double (&nout)[3]) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
   if (cd.model == LUB_MODEL_LADD) {
     ladd_pair<R>(cd, A, KA, B, KB, side, out, hout, status);
@@ -598,27 +598,29 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     // prediction, else the line of centres.  The plain start judges a seeded
     // one: if the seeded iteration does not converge, start again from the
     // line of centres
-    double n0[3];
+    double n0[3] = {0.0, 0.0, 0.0};
     bool seeded = false;
-    if (nseed && dot3(nseed, d) > 0.0) {
+    if (use_nseed && dot3(nseed, d) > 0.0) {
       for (int k = 0; k < 3; ++k) n0[k] = nseed[k];
       seeded = true;
-      if (warm_used) *warm_used = 1;
+      warm_used = 1;
     } else if (seedY) {
       seeded = seed_normal(d, A, *B, seedY, n0);
-      if (!seeded && fell_back) *fell_back = 1;
+      if (!seeded) fell_back = 1;
     }
-    if (seeded) {
-      sv = closest_points(d, A.M, B->M, cd.max_iter, n0);
-      if (!sv.ok) {
-        const int used = sv.iters;
-        sv = closest_points(d, A.M, B->M, cd.max_iter);
-        sv.iters += used;
-        if (fell_back) *fell_back = 1;
-      }
-    } else {
-      sv = closest_points(d, A.M, B->M, cd.max_iter);
+    // one call site of the solver (a second inlined copy only costs
+    // instruction cache): the seeded attempt, then the plain one if needed
+    bool from_seed = seeded;
+    int used = 0;
+#pragma clang loop unroll(disable)
+    for (;;) {
+      sv = closest_points(d, A.M, B->M, cd.max_iter, n0, from_seed);
+      if (sv.ok || !from_seed) break;
+      used = sv.iters;
+      from_seed = false;
+      fell_back = 1;
     }
+    sv.iters += used;
     if (kTangent && !sv.ok) {
       // last resort: the paper's tangent-sphere iteration, then a Newton
       // polish from its normal (at least 8 iterations: its start is only
@@ -626,15 +628,15 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       double nl[3];
       if (tangent_spheres(d, A, *B, nl)) {
         const int used = sv.iters;
-        Solve sp = closest_points(d, A.M, B->M, cd.max_iter > 8 ? cd.max_iter : 8, nl);
+        Solve sp = closest_points(d, A.M, B->M, cd.max_iter > 8 ? cd.max_iter : 8, nl, true);
         sp.iters += used;
         if (sp.ok) {
           sv = sp;
-          if (fell_back) *fell_back = 1;
+          fell_back = 1;
         }
       }
     }
-    if (nout && sv.ok)
+    if (sv.ok)
       for (int k = 0; k < 3; ++k) nout[k] = sv.n[k];
   } else {
     // wall: the particle's support point towards the plane
@@ -800,6 +802,9 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
   if (blockIdx.x * blockDim.x >= nwork) return;
   int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0,
           n_warm = 0;
+  // reused lists: normals stored per superset entry carry the number of the
+  // search that made the superset
+  const int tag = cd.warm_slots ? (int)warm.state->builds : 0;
   int max_it = 0;
   int64_t my_hist = 0;  // lane b < 32 holds histogram bucket b
   for (int w0 = blockIdx.x * blockDim.x; w0 < nwork; w0 += gridDim.x * blockDim.x) {
@@ -808,53 +813,68 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
     int status = -1, iters = 0, fb = 0, wu = 0;
     double h = 0.0;
     if (on) {
-      int s = work_s[w], t = work_t[w];
+      const int s = work_s[w], t = work_t[w];
+      const bool pp = t >= 0;  // a particle pair, else a wall pair
+      // warm start: the previous normal of the pair, kept per superset
+      // entry (reused lists) or in the hash tables.  One call site of the
+      // pair evaluation for every kind (inlined copies only cost
+      // instruction cache)
+      const bool warm_on = pp && (cd.warm_slots || cd.warm_mask != 0);
+      double nprev[3] = {0.0, 0.0, 0.0};
+      double nnew[3] = {0.0, 0.0, 0.0};
+      bool found = false;
+      int e_sup = 0;
+      uint64_t key = 0, h0 = 0;
+      if (warm_on && cd.warm_slots) {
+        // made under the current superset?
+        e_sup = warm.slot_sup[w];
+        const float4 v = warm.sup_val[e_sup];
+        found = __float_as_int(v.w) == tag;
+        nprev[0] = v.x;
+        nprev[1] = v.y;
+        nprev[2] = v.z;
+      } else if (warm_on) {
+        key = ((uint64_t)warm.orig[s] << 32) | (uint64_t)warm.orig[t];
+        h0 = warm_hash(key);
+        for (int p = 0; p < kWarmProbes; ++p) {
+          const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
+          const uint64_t k = warm.prev_key[e];
+          if (k == key) {
+            const float4 v = warm.prev_val[e];
+            nprev[0] = v.x;
+            nprev[1] = v.y;
+            nprev[2] = v.z;
+            found = true;
+            break;
+          }
+          if (k == kWarmEmpty) break;
+        }
+      }
       PairOut<R> o;
-      if (t >= 0) {
-        if (cd.warm_mask) {
-          const uint64_t key = ((uint64_t)warm.orig[s] << 32) | (uint64_t)warm.orig[t];
-          const uint64_t h0 = warm_hash(key);
-          double nprev[3];
-          bool found = false;
+      eval_pair<R, kTangent>(cd, rec[s], kin[s], pp ? &rec[t] : nullptr,
+                             pp ? &kin[t] : nullptr, pp ? 0 : -1 - t, o, h, status, iters,
+                             pp && seedY ? seedY + 4 * (int64_t)w : nullptr, fb, nprev,
+                             found, wu, nnew);
+      if (warm_on && status != 3) {
+        if (cd.warm_slots) {
+          warm.sup_val[e_sup] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
+                                            __int_as_float(tag));
+        } else {
+          // this call's normal for the next call (a full probe sequence
+          // only costs the pair its warm start)
           for (int p = 0; p < kWarmProbes; ++p) {
             const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
-            const uint64_t k = warm.prev_key[e];
-            if (k == key) {
-              const float4 v = warm.prev_val[e];
-              nprev[0] = v.x;
-              nprev[1] = v.y;
-              nprev[2] = v.z;
-              found = true;
+            const unsigned long long old = atomicCAS(
+                (unsigned long long*)&warm.cur_key[e], (unsigned long long)kWarmEmpty,
+                (unsigned long long)key);
+            if (old == kWarmEmpty || old == key) {
+              warm.cur_val[e] = make_float4((float)nnew[0], (float)nnew[1],
+                                            (float)nnew[2], 0.f);
               break;
             }
-            if (k == kWarmEmpty) break;
           }
-          double nnew[3] = {0.0, 0.0, 0.0};
-          eval_pair<R, kTangent>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
-                       seedY ? seedY + 4 * (int64_t)w : nullptr, &fb,
-                       found ? nprev : nullptr, &wu, nnew);
-          if (status != 3) {
-            // this call's normal for the next call (a full probe sequence
-            // only costs the pair its warm start)
-            for (int p = 0; p < kWarmProbes; ++p) {
-              const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
-              const unsigned long long old = atomicCAS(
-                  (unsigned long long*)&warm.cur_key[e], (unsigned long long)kWarmEmpty,
-                  (unsigned long long)key);
-              if (old == kWarmEmpty || old == key) {
-                warm.cur_val[e] = make_float4((float)nnew[0], (float)nnew[1],
-                                              (float)nnew[2], 0.f);
-                break;
-              }
-            }
-          }
-        } else {
-          eval_pair<R, kTangent>(cd, rec[s], kin[s], &rec[t], &kin[t], 0, o, h, status, iters,
-                       seedY ? seedY + 4 * (int64_t)w : nullptr, &fb);
         }
-      } else
-        eval_pair<R, kTangent>(cd, rec[s], kin[s], nullptr, nullptr, -1 - t, o, h, status,
-                     iters);
+      }
       out[w] = o;
       out_h[w] = h;
       out_status[w] = (int8_t)status;
