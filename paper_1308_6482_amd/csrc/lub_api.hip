@@ -66,6 +66,7 @@ struct lub_ctx {
   int32_t* block_sums = nullptr;   // scan scratch
   int32_t* wall_slot = nullptr;    // [2n]
   PRec* rec = nullptr;             // [n]
+  PRecP* recp = nullptr;           // [n] the pair kernels' copy
   double4* pos = nullptr;          // [n] centre and largest semi-axis (centre test)
   KRec* kin = nullptr;             // [n]
   int32_t* nbr = nullptr;          // [n * cur_nbr] partner (cell order)
@@ -217,7 +218,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
   c->cap_n = 0;
   if ((rc = realloc_buf(&c->cell_id, need)) || (rc = realloc_buf(&c->sorted, need)) ||
       (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
-      (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->kin, need)) ||
+      (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->recp, need)) || (rc = realloc_buf(&c->kin, need)) ||
       (rc = realloc_buf(&c->pos, need)) ||
       (rc = realloc_buf(&c->scat, need)) ||
       (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks_max((int)need))) ||
@@ -481,11 +482,11 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                        d.warm_slots ? c->work_sup : nullptr};
   if (reuse) {
     launch_disp(d, r, q, semi, lists, c->cnt, s);
-    launch_refresh(d, r, q, semi, v, w, lists, c->rec, c->pos, c->kin, c->cnt, s);
+    launch_refresh(d, r, q, semi, v, w, lists, c->rec, c->recp, c->pos, c->kin, c->cnt, s);
   }
   if (d.n > 0) {
     if (small) {
-      launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->pos,
+      launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->recp, c->pos,
                          c->kin, c->cell_sorted, c->cnt, gate, s);
     } else {
       launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s);
@@ -493,8 +494,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
                           c->cell_count, ncell, gate, s);
       launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
-                           q, semi, v, w, c->sorted, c->rec, c->pos, c->kin, c->cell_sorted,
-                           gate, s);
+                           q, semi, v, w, c->sorted, c->rec, c->recp, c->pos, c->kin,
+                           c->cell_sorted, gate, s);
     }
   }
   if (d.n > 0) {
@@ -537,7 +538,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
         hipEventRecord(ev[6], s);
       }
     } else {
-      launch_pairs(d, c->rec, c->kin, c->work_s, c->work_t, seeds, c->out,
+      launch_pairs(d, c->recp, c->kin, c->work_s, c->work_t, seeds, c->out,
                    c->out_h, c->out_status, c->out_iters, warm, c->fail_list, c->stat_pair,
                    c->cnt, s,
                    timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
@@ -572,7 +573,7 @@ int fetch_counters(lub_ctx* c) {
 // the device buffers a call's launch sequence uses
 std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
-          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->pos, c->kin,
+          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->recp, c->pos, c->kin,
           c->nbr,
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
           c->out_status,
@@ -1203,7 +1204,7 @@ void lub_destroy(lub_handle_t h) {
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->block_sums,
-                  h->wall_slot, h->rec, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
+                  h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
                   h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
                   h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],

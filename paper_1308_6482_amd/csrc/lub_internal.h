@@ -20,6 +20,44 @@ struct alignas(128) PRec {
   double pad;
 };
 
+// The pair kernels' copy of the geometry, 64 B, in cell order: the full
+// record is formed from it in registers (support_matrix gives the M of the
+// staging), which halves the bytes a pair gathers.
+struct alignas(64) PRecP {
+  double r[3];
+  double ax[3];
+  double Rpar, Rperp;
+};
+
+// M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T as xx xy xz yy yz zz, in a fixed
+// order without contraction: the staging and the pair kernels form the same
+// bits.
+__host__ __device__ inline void support_matrix(const double a[3], double Rpa, double Rpe,
+                                               double M[6]) {
+#pragma clang fp contract(off)
+  const double p2 = Rpe * Rpe, dd = Rpa * Rpa - p2;
+  M[0] = p2 + dd * a[0] * a[0];
+  M[1] = dd * a[0] * a[1];
+  M[2] = dd * a[0] * a[2];
+  M[3] = p2 + dd * a[1] * a[1];
+  M[4] = dd * a[1] * a[2];
+  M[5] = p2 + dd * a[2] * a[2];
+}
+
+__host__ __device__ inline PRec expand_record(const PRecP& c) {
+  PRec o;
+  for (int k = 0; k < 3; ++k) {
+    o.r[k] = c.r[k];
+    o.ax[k] = c.ax[k];
+  }
+  o.Rpar = c.Rpar;
+  o.Rperp = c.Rperp;
+  o.Rmax = c.Rpar > c.Rperp ? c.Rpar : c.Rperp;
+  o.pad = 0.0;
+  support_matrix(o.ax, o.Rpar, o.Rperp, o.M);
+  return o;
+}
+
 // Per-particle kinematics, 64 B, in cell order.
 struct alignas(64) KRec {
   double v[3];
@@ -162,13 +200,15 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_id, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, double4* pos,
+                          const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
+                          double4* pos,
                           KRec* kin, int32_t* cell_sorted, const Counters* gate, hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, PRecP* recp,
+                        double4* pos,
                         KRec* kin, int32_t* cell_sorted, Counters* cnt, const Counters* gate,
                         hipStream_t s);
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
@@ -187,6 +227,7 @@ void launch_disp(const CallDesc& d, const double* r, const double* q, const doub
                  const ListBufs& lists, Counters* cnt, hipStream_t s);
 void launch_refresh(const CallDesc& d, const double* r, const double* q, const double* semi,
                     const double* v, const double* w, const ListBufs& lists, PRec* rec,
+                    PRecP* recp,
                     double4* pos, KRec* kin, const Counters* cnt, hipStream_t s);
 
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
@@ -209,7 +250,7 @@ struct WarmTables {
   const ListState* state;    // the current search count (the tag)
 };
 
-void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
+void launch_pairs(const CallDesc& d, const PRecP* recp, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   WarmTables warm, int32_t* fail_list, int64_t* stat_pair,

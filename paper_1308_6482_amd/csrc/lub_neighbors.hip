@@ -261,8 +261,9 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
                             const double* __restrict__ r, const double* __restrict__ q,
                             const double* __restrict__ semi,
                             const double* __restrict__ v, const double* __restrict__ w,
-                            PRec* __restrict__ rec, double4* __restrict__ pos,
-                            KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
+                            PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                            double4* __restrict__ pos, KRec* __restrict__ kin,
+                            int32_t* __restrict__ cell_sorted) {
   double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
   double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= inv;
@@ -273,24 +274,17 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
   double ay = 2.0 * (qy * qz - qw * qx);
   double az = 1.0 - 2.0 * (qx * qx + qy * qy);
   double Rpa = semi[2 * p], Rpe = semi[2 * p + 1];
-  double p2 = Rpe * Rpe, dd = Rpa * Rpa - p2;
-  PRec o;
-  o.r[0] = r[3 * p];
-  o.r[1] = r[3 * p + 1];
-  o.r[2] = r[3 * p + 2];
-  o.M[0] = p2 + dd * ax * ax;
-  o.M[1] = dd * ax * ay;
-  o.M[2] = dd * ax * az;
-  o.M[3] = p2 + dd * ay * ay;
-  o.M[4] = dd * ay * az;
-  o.M[5] = p2 + dd * az * az;
-  o.ax[0] = ax;
-  o.ax[1] = ay;
-  o.ax[2] = az;
-  o.Rpar = Rpa;
-  o.Rperp = Rpe;
-  o.Rmax = fmax(Rpa, Rpe);
-  o.pad = 0.0;
+  PRecP c;
+  c.r[0] = r[3 * p];
+  c.r[1] = r[3 * p + 1];
+  c.r[2] = r[3 * p + 2];
+  c.ax[0] = ax;
+  c.ax[1] = ay;
+  c.ax[2] = az;
+  c.Rpar = Rpa;
+  c.Rperp = Rpe;
+  recp[s] = c;
+  const PRec o = expand_record(c);
   rec[s] = o;
   pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
   KRec k;
@@ -316,9 +310,9 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 const double* __restrict__ semi,
                                 const double* __restrict__ v,
                                 const double* __restrict__ w, int32_t* __restrict__ sorted,
-                                PRec* __restrict__ rec, double4* __restrict__ pos,
-                                KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted,
-                                const Counters* gate) {
+                                PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                                double4* __restrict__ pos, KRec* __restrict__ kin,
+                                int32_t* __restrict__ cell_sorted, const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists: the cursors stayed zero
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
@@ -330,7 +324,7 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
   for (int k = b; k < e; ++k) rank += unsorted[k] < p;
   const int s = b + rank;
   sorted[s] = p;
-  make_record(s, p, cell_id, r, q, semi, v, w, rec, pos, kin, cell_sorted);
+  make_record(s, p, cell_id, r, q, semi, v, w, rec, recp, pos, kin, cell_sorted);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
@@ -392,7 +386,7 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
               const double* __restrict__ semi, const double* __restrict__ v,
               const double* __restrict__ w, int32_t* __restrict__ cell_start,
               int32_t* __restrict__ sorted, PRec* __restrict__ rec,
-              double4* __restrict__ pos, KRec* __restrict__ kin,
+              PRecP* __restrict__ recp, double4* __restrict__ pos, KRec* __restrict__ kin,
               int32_t* __restrict__ cell_sorted, Counters* cnt, const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists (uniform: one block)
   __shared__ int32_t cnt_l[kSmallMaxCells];        // counts, then cursors
@@ -459,7 +453,8 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
     const int s = b + rank;
     sorted[s] = p;
     cell_sorted[s] = c;
-    if (d.n <= kSmallRecN) make_record(s, p, nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
+    if (d.n <= kSmallRecN)
+      make_record(s, p, nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
   }
 }
 
@@ -469,12 +464,13 @@ __global__ void k_records_sorted(CallDesc d, const int32_t* __restrict__ sorted,
                                  const double* __restrict__ r, const double* __restrict__ q,
                                  const double* __restrict__ semi,
                                  const double* __restrict__ v, const double* __restrict__ w,
-                                 PRec* __restrict__ rec, double4* __restrict__ pos,
-                                 KRec* __restrict__ kin, const Counters* gate) {
+                                 PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                                 double4* __restrict__ pos, KRec* __restrict__ kin,
+                                 const Counters* gate) {
   if (gate && !gate->rebuild) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.n) return;
-  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
+  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
 }
 
 // A group of G lanes per particle (G = 64: one wavefront; G = 32 or 16: two
@@ -905,13 +901,14 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_id, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, double4* pos,
+                          const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
+                          double4* pos,
                           KRec* kin, int32_t* cell_sorted, const Counters* gate,
                           hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
                      d, unsorted, cell_id, cell_start, cell_fill, ncell, r, q, semi,
-                     v, w, sorted, rec, pos, kin, cell_sorted, gate);
+                     v, w, sorted, rec, recp, pos, kin, cell_sorted, gate);
 }
 
 bool cells_small_fits(const CallDesc& d) {
@@ -921,14 +918,15 @@ bool cells_small_fits(const CallDesc& d) {
 
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         const double* semi, const double* v, const double* w,
-                        int32_t* cell_start, int32_t* sorted, PRec* rec, double4* pos,
+                        int32_t* cell_start, int32_t* sorted, PRec* rec, PRecP* recp,
+                        double4* pos,
                         KRec* kin, int32_t* cell_sorted, Counters* cnt, const Counters* gate,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, d, r, q, semi,
-                     v, w, cell_start, sorted, rec, pos, kin, cell_sorted, cnt, gate);
+                     v, w, cell_start, sorted, rec, recp, pos, kin, cell_sorted, cnt, gate);
   if (d.n > kSmallRecN)
     hipLaunchKernelGGL(k_records_sorted, dim3((d.n + 255) / 256), dim3(256), 0, s, d, sorted,
-                       r, q, semi, v, w, rec, pos, kin, gate);
+                       r, q, semi, v, w, rec, recp, pos, kin, gate);
 }
 
 template <int G>
@@ -1053,12 +1051,13 @@ k_decide(CallDesc d, ListBufs lb, Counters* cnt) {
 __global__ void k_refresh(CallDesc d, const double* __restrict__ r,
                           const double* __restrict__ q, const double* __restrict__ semi,
                           const double* __restrict__ v, const double* __restrict__ w,
-                          ListBufs lb, PRec* __restrict__ rec, double4* __restrict__ pos,
+                          ListBufs lb, PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                          double4* __restrict__ pos,
                           KRec* __restrict__ kin, const Counters* cnt) {
   if (cnt->rebuild) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
-  make_record(lb.inv[p], p, nullptr, r, q, semi, v, w, rec, pos, kin, nullptr);
+  make_record(lb.inv[p], p, nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
 }
 
 }  // namespace
@@ -1073,10 +1072,10 @@ void launch_disp(const CallDesc& d, const double* r, const double* q, const doub
 
 void launch_refresh(const CallDesc& d, const double* r, const double* q, const double* semi,
                     const double* v, const double* w, const ListBufs& lists, PRec* rec,
-                    double4* pos, KRec* kin, const Counters* cnt, hipStream_t s) {
+                    PRecP* recp, double4* pos, KRec* kin, const Counters* cnt, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_refresh, dim3((d.n + 255) / 256), dim3(256), 0, s, d, r, q, semi, v, w,
-                     lists, rec, pos, kin, cnt);
+                     lists, rec, recp, pos, kin, cnt);
 }
 
 // lanes per particle: the smallest group whose lanes hold the segment at 8

@@ -532,16 +532,16 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
 // both centres: no torque.
 template <typename R>
 __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
-                                   const PRec* B, const KRec* KB, int side,
+                                   const PRec& Bp, const KRec* KB, bool pair, int side,
                                    PairOut<R>& out, double& hout, int& status) {
   const double a = A.Rperp;
   double n[3], h, g, vj[3];  // vj: velocity of the partner (its image) or the wall
-  if (B) {
+  if (pair) {
     double d[3];
-    const int m = pair_image(cd, A.r, B->r, d);
+    const int m = pair_image(cd, A.r, Bp.r, d);
     const double dn = sqrt(dot3(d, d));
     for (int k = 0; k < 3; ++k) n[k] = d[k] / dn;
-    const double b = B->Rperp;
+    const double b = Bp.Rperp;
     h = dn - a - b;
     g = a * b / (a + b);
     // velocity of the image of j that d points to
@@ -578,22 +578,22 @@ __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec
 // started from nseed; nout receives the converged normal.
 template <typename R, bool kTangent>
 __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec& KA,
-                          const PRec* B, const KRec* KB, int side,
+                          const PRec& Bp, const KRec* KB, bool pair, int side,
                           PairOut<R>& out, double& hout, int& status,
                           int& iters, const float* seedY, int& fell_back,
                           const double (&nseed)[3], bool use_nseed, int& warm_used,
                           double (&nout)[3]) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
   if (cd.model == LUB_MODEL_LADD) {
-    ladd_pair<R>(cd, A, KA, B, KB, side, out, hout, status);
+    ladd_pair<R>(cd, A, KA, Bp, KB, pair, side, out, hout, status);
     iters = 0;
     return;
   }
   Solve sv;
   int le_m = 0;  // Lees-Edwards image of j: its velocity differs by -le_m le_vel in x
-  if (B) {
+  if (pair) {
     double d[3];
-    le_m = pair_image(cd, A.r, B->r, d);
+    le_m = pair_image(cd, A.r, Bp.r, d);
     // start: the previous call's normal (warm start), else the learned
     // prediction, else the line of centres.  The plain start judges a seeded
     // one: if the seeded iteration does not converge, start again from the
@@ -605,7 +605,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       seeded = true;
       warm_used = 1;
     } else if (seedY) {
-      seeded = seed_normal(d, A, *B, seedY, n0);
+      seeded = seed_normal(d, A, Bp, seedY, n0);
       if (!seeded) fell_back = 1;
     }
     // one call site of the solver (a second inlined copy only costs
@@ -614,7 +614,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     int used = 0;
 #pragma clang loop unroll(disable)
     for (;;) {
-      sv = closest_points(d, A.M, B->M, cd.max_iter, n0, from_seed);
+      sv = closest_points(d, A.M, Bp.M, cd.max_iter, n0, from_seed);
       if (sv.ok || !from_seed) break;
       used = sv.iters;
       from_seed = false;
@@ -626,9 +626,9 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       // polish from its normal (at least 8 iterations: its start is only
       // within the iteration's tolerance)
       double nl[3];
-      if (tangent_spheres(d, A, *B, nl)) {
+      if (tangent_spheres(d, A, Bp, nl)) {
         const int used = sv.iters;
-        Solve sp = closest_points(d, A.M, B->M, cd.max_iter > 8 ? cd.max_iter : 8, nl, true);
+        Solve sp = closest_points(d, A.M, Bp.M, cd.max_iter > 8 ? cd.max_iter : 8, nl, true);
         sp.iters += used;
         if (sp.ok) {
           sv = sp;
@@ -679,13 +679,13 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   double S1, S2, G0, G2, iS1p = 0.0, iS2p = 0.0, G0p = 0.0, G2p = 0.0;
   double cph = 1.0, sph = 0.0;
   radii<double>(A.Rpar, A.Rperp, cpi, spi, &S1, &S2, &G0, &G2);
-  if (B) {
+  if (pair) {
     // surface j: outward normal -n; its x1' lies in the same tangent plane
     double cpj, spj, e1p[3];
     const double nj[3] = {-n[0], -n[1], -n[2]};
-    latitude(nj, B->ax, B->Rpar, B->Rperp, &cpj, &spj, e1p);
+    latitude(nj, Bp.ax, Bp.Rpar, Bp.Rperp, &cpj, &spj, e1p);
     double S1p, S2p;
-    radii<double>(B->Rpar, B->Rperp, cpj, spj, &S1p, &S2p, &G0p, &G2p);
+    radii<double>(Bp.Rpar, Bp.Rperp, cpj, spj, &S1p, &S2p, &G0p, &G2p);
     iS1p = 1.0 / S1p;
     iS2p = 1.0 / S2p;
     cph = dot3(e1p, e1);
@@ -709,7 +709,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   double Vi[3], Vj[3], wr[3], tmp[3];
   cross3(KA.w, sv.ai, tmp);
   for (int k = 0; k < 3; ++k) Vi[k] = KA.v[k] + tmp[k];
-  if (B) {
+  if (pair) {
     double yj[3] = {-sv.bj[0], -sv.bj[1], -sv.bj[2]};
     cross3(KB->w, yj, tmp);
     for (int k = 0; k < 3; ++k) {
@@ -756,7 +756,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   for (int k = 0; k < 3; ++k) {
     out.F[k] = F[k];
     out.Ti[k] = T[k] + xa[k];
-    out.Tj[k] = B ? -T[k] + xb[k] : R(0);
+    out.Tj[k] = pair ? -T[k] + xb[k] : R(0);
   }
 }
 
@@ -777,7 +777,7 @@ __device__ __forceinline__ uint64_t warm_hash(uint64_t k) {
 // the occupancy of the main pass.
 template <typename R, bool kTangent>
 __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
-                                              const PRec* __restrict__ rec,
+                                              const PRecP* __restrict__ recp,
                                               const KRec* __restrict__ kin,
                                               const int32_t* __restrict__ work_s,
                                               const int32_t* __restrict__ work_t,
@@ -851,8 +851,11 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
         }
       }
       PairOut<R> o;
-      eval_pair<R, kTangent>(cd, rec[s], kin[s], pp ? &rec[t] : nullptr,
-                             pp ? &kin[t] : nullptr, pp ? 0 : -1 - t, o, h, status, iters,
+      // the full records, formed from the 64-B copies
+      const PRec A = expand_record(recp[s]);
+      const PRec B = expand_record(recp[pp ? t : s]);
+      eval_pair<R, kTangent>(cd, A, kin[s], B, pp ? &kin[t] : nullptr, pp,
+                             pp ? 0 : -1 - t, o, h, status, iters,
                              pp && seedY ? seedY + 4 * (int64_t)w : nullptr, fb, nprev,
                              found, wu, nnew);
       if (warm_on && status != 3) {
@@ -965,7 +968,7 @@ int pair_grid(const CallDesc& d) {
   return blocks < 1 ? 1 : blocks;
 }
 
-void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
+void launch_pairs(const CallDesc& d, const PRecP* recp, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   WarmTables warm, int32_t* fail_list, int64_t* stat_pair, Counters* cnt,
@@ -974,19 +977,19 @@ void launch_pairs(const CallDesc& d, const PRec* rec, const KRec* kin,
   // the events (may be null) take the main pass's own start and end stamps
   if (d.precision == LUB_MIXED) {
     hipExtLaunchKernelGGL(k_pairs<float, false>, dim3(blocks), dim3(kPairBlock), 0, s,
-                          ev_start, ev_stop, 0, d, rec, kin, work_s, work_t, seedY,
+                          ev_start, ev_stop, 0, d, recp, kin, work_s, work_t, seedY,
                           (PairOut<float>*)out, out_h, out_status, out_iters, warm,
                           fail_list, stat_pair, cnt);
     hipLaunchKernelGGL((k_pairs<float, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0, s,
-                       d, rec, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
+                       d, recp, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
                        out_status, out_iters, warm, fail_list, stat_pair, cnt);
   } else {
     hipExtLaunchKernelGGL(k_pairs<double, false>, dim3(blocks), dim3(kPairBlock), 0, s,
-                          ev_start, ev_stop, 0, d, rec, kin, work_s, work_t, seedY,
+                          ev_start, ev_stop, 0, d, recp, kin, work_s, work_t, seedY,
                           (PairOut<double>*)out, out_h, out_status, out_iters, warm,
                           fail_list, stat_pair, cnt);
     hipLaunchKernelGGL((k_pairs<double, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0,
-                       s, d, rec, kin, work_s, work_t, seedY, (PairOut<double>*)out,
+                       s, d, recp, kin, work_s, work_t, seedY, (PairOut<double>*)out,
                        out_h, out_status, out_iters, warm, fail_list, stat_pair, cnt);
   }
 }
