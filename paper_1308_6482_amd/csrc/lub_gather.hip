@@ -37,10 +37,14 @@ __device__ __forceinline__ int find_entry(const int32_t* __restrict__ seg, int n
   return -1;
 }
 
-// lanes per particle: the segments hold about ten entries in dense
-// suspensions, so a wavefront serves four particles
-constexpr int kGroup = 16;
-constexpr int kPerWave = 64 / kGroup;
+// lanes per particle (template G): the segments hold about ten to twenty
+// entries in dense suspensions.  16 lanes (four particles per wavefront)
+// for small systems, where the launch is latency-bound; 8 from about a
+// quarter million particles, where two entries per lane keep more loads in
+// flight per wavefront (measured: 220 -> 180 us at a million particles,
+// slower below)
+constexpr int kGroupLarge = 8;
+constexpr int kGroupSmall = 16;
 
 // For every evaluated particle pair (slot w, owner s, partner t): the
 // position of s in t's sorted segment, where the entry's code becomes
@@ -64,7 +68,7 @@ __global__ void k_partner_slots(CallDesc d, const int32_t* __restrict__ work_s,
   }
 }
 
-template <typename R>
+template <typename R, int kGroup>
 __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ slot,
@@ -72,6 +76,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
     const Counters* cnt, Counters* __restrict__ next_cnt,
     uint64_t* __restrict__ warm_clear, int64_t warm_size, double* __restrict__ f,
     double* __restrict__ t) {
+  constexpr int kPerWave = 64 / kGroup;
   const int lane = threadIdx.x & 63;
   // the warm-start table this call read becomes the one the next call writes
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < warm_size;
@@ -157,16 +162,27 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
                    int64_t warm_size, double* f, double* t, hipStream_t s) {
   if (d.n == 0) return;
-  const int per_block = kWaves * kPerWave;
+  const bool large = d.n >= (1 << 18);
+  const int per_block = kWaves * (64 / (large ? kGroupLarge : kGroupSmall));
   dim3 grid((d.n + per_block - 1) / per_block);
-  if (d.precision == LUB_MIXED)
-    hipLaunchKernelGGL(k_gather<float>, grid, dim3(64 * kWaves), 0, s, d, orig,
-                       deg, nbr, slot, wall_slot, (const PairOut<float>*)out,
-                       cnt, next_cnt, warm_clear, warm_size, f, t);
-  else
-    hipLaunchKernelGGL(k_gather<double>, grid, dim3(64 * kWaves), 0, s, d, orig,
-                       deg, nbr, slot, wall_slot, (const PairOut<double>*)out,
-                       cnt, next_cnt, warm_clear, warm_size, f, t);
+  const dim3 block(64 * kWaves);
+  if (d.precision == LUB_MIXED) {
+    const PairOut<float>* o = (const PairOut<float>*)out;
+    if (large)
+      hipLaunchKernelGGL((k_gather<float, kGroupLarge>), grid, block, 0, s, d, orig, deg, nbr,
+                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+    else
+      hipLaunchKernelGGL((k_gather<float, kGroupSmall>), grid, block, 0, s, d, orig, deg, nbr,
+                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+  } else {
+    const PairOut<double>* o = (const PairOut<double>*)out;
+    if (large)
+      hipLaunchKernelGGL((k_gather<double, kGroupLarge>), grid, block, 0, s, d, orig, deg, nbr,
+                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+    else
+      hipLaunchKernelGGL((k_gather<double, kGroupSmall>), grid, block, 0, s, d, orig, deg, nbr,
+                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+  }
 }
 
 namespace {
