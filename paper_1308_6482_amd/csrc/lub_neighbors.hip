@@ -33,10 +33,19 @@ constexpr int kScanItems = 8;                             // per thread and chun
 constexpr int kScanChunk = kScanThreads * kScanItems;     // staged through LDS
 constexpr int kScanTile = kScanChunk;                     // one block per tile
 
-__device__ __forceinline__ int cell_coord(double x, double L, int periodic,
-                                          double edge, int nc) {
-  if (periodic) x = x - L * floor(x / L);
-  int c = (int)floor(x / edge);
+// A coordinate wrapped into the box along a periodic axis.  The binning and
+// the neighbour search take the same expression, so that a centre's cell
+// and its place in that cell agree.
+__device__ __forceinline__ double wrap_coord(double x, double L, double invL) {
+  return x - L * floor(x * invL);
+}
+
+// Cell along one axis (inv_edge = 1 / cell edge; the grid's margin is far
+// above the rounding of the product).
+__device__ __forceinline__ int cell_coord(double x, double L, double invL, int periodic,
+                                          double inv_edge, int nc) {
+  if (periodic) x = wrap_coord(x, L, invL);
+  int c = (int)floor(x * inv_edge);
   c = c < 0 ? 0 : c;
   c = c >= nc ? nc - 1 : c;
   return c;
@@ -135,15 +144,17 @@ __device__ __forceinline__ int input_faults(const CallDesc& d, const double* __r
 }
 
 // validate one particle's input (EINVAL, EDOMAIN) and return its cell
-__device__ int validate_bin(const CallDesc& d, const PIn& u, Counters* cnt) {
+// (inv_cell: 1 / cell edge per axis)
+__device__ int validate_bin(const CallDesc& d, const PIn& u, const double inv_cell[3],
+                            Counters* cnt) {
   const int faults = input_faults(d, u);
   const bool ok = !(faults & 1);
   if (!ok) set_error(cnt, LUB_EINVAL);
   double rm = fmax(u.a, u.b);
   if (faults & 2) set_error(cnt, LUB_EDOMAIN);
-  int cx = cell_coord(u.x, d.L[0], d.periodic[0], d.cell[0], d.nc[0]);
-  int cy = cell_coord(u.y, d.L[1], d.periodic[1], d.cell[1], d.nc[1]);
-  int cz = cell_coord(u.z, d.L[2], d.periodic[2], d.cell[2], d.nc[2]);
+  int cx = cell_coord(u.x, d.L[0], d.invL[0], d.periodic[0], inv_cell[0], d.nc[0]);
+  int cy = cell_coord(u.y, d.L[1], d.invL[1], d.periodic[1], inv_cell[1], d.nc[1]);
+  int cz = cell_coord(u.z, d.L[2], d.invL[2], d.periodic[2], inv_cell[2], d.nc[2]);
   if (!ok) cx = cy = cz = 0;
   // the large particles' cells follow the small particles' cells
   const int big = rm > d.r_small ? d.nc[0] * d.nc[1] * d.nc[2] : 0;
@@ -159,7 +170,8 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
   if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
-  int c = validate_bin(d, load_input(r, q, semi, p), cnt);
+  const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
+  int c = validate_bin(d, load_input(r, q, semi, p), inv_cell, cnt);
   cell_id[p] = c;
   atomicAdd(&cell_count[c], 1);
 }
@@ -405,11 +417,12 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
     const int p = tid + k * kSmallThreads;
     if (p < d.n) in[k] = load_input(r, q, semi, p);
   }
+  const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k) {
     const int p = tid + k * kSmallThreads;
     if (p < d.n) {
-      const int c = validate_bin(d, in[k], cnt);
+      const int c = validate_bin(d, in[k], inv_cell, cnt);
       cid_l[p] = (int16_t)c;
       atomicAdd(&cnt_l[c], 1);
     }
@@ -586,7 +599,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     const int c3[3] = {cx, cy, cz};
     for (int k = 0; k < 3; ++k) {
       double x = ri[k];
-      if (d.periodic[k]) x = x - d.L[k] * floor(x / d.L[k]);
+      if (d.periodic[k]) x = wrap_coord(x, d.L[k], d.invL[k]);
       f3[k] = x - c3[k] * d.cell[k];
     }
     for (int cls = 0; cls < 2; ++cls) {
