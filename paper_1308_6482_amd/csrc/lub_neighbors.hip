@@ -602,6 +602,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
       if (d.periodic[k]) x = wrap_coord(x, d.L[k], d.invL[k]);
       f3[k] = x - c3[k] * d.cell[k];
     }
+    const double inv_cx = 1.0 / d.cell[0];
     for (int cls = 0; cls < 2; ++cls) {
       const int32_t* cs_cls = cell_start + cls * ngeo;
       if (cs_cls[ngeo] == cs_cls[0]) continue;  // no particle of this class
@@ -658,8 +659,10 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
               a0 = cxr - reach[0];
               a1 = cxr + reach[0];
             }
-            a0 = max(a0, cxr + (int)floor((fx - wx) / d.cell[0]));
-            a1 = min(a1, cxr + (int)floor((fx + wx) / d.cell[0]));
+            // (products with 1 / cell: the chord's margin is far above
+            // their rounding)
+            a0 = max(a0, cxr + (int)floor((fx - wx) * inv_cx));
+            a1 = min(a1, cxr + (int)floor((fx + wx) * inv_cx));
           }
           if (rem > 0.0 && a1 >= a0) {
             const int ry = wrap_cell(cy + oy, d.nc[1]);
