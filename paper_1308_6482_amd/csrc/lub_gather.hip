@@ -3,12 +3,14 @@
 // r_i) x F from every pair, particle j the opposite force and -T + ... about
 // its own centre.
 //
-// No atomics: a group of 16 lanes per particle, lanes over the entries of its
-// neighbour segment (both directions of each of its pairs).  A pair's result
-// sits in the slot of the entry owned by its smaller-index particle; the
-// other particle finds that entry by binary search in its partner's sorted
-// segment.  The group then reduces the six components with a fixed butterfly
-// in FP64, so the sums are bitwise reproducible run to run.
+// No atomics: a group of 16 (large systems: 8) lanes per particle, lanes
+// over the entries of its neighbour segment (both directions of each of its
+// pairs).  A pair's result sits in the slot of the entry owned by its
+// smaller-index particle; the other particle reads it through the slot code
+// written into its own entry beside the pair kernel (large systems) or finds
+// that entry by binary search in its partner's sorted segment.  The group
+// then reduces the six components with a fixed butterfly in FP64, so the
+// sums are bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
 
 #include "lub_internal.h"

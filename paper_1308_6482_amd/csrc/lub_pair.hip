@@ -27,6 +27,12 @@
 // max(h, h_c) and the Hookean contact of Eqs. lub:frep / lub:model; transfer
 // to the particle centres as at the end of Sec. III.B.
 //
+// Records.  The kernels gather a 64-B copy per particle (centre, axis, radii)
+// and form the support matrix M in registers with the staging's expression.
+// The previous call's normal (warm start) comes from hash tables keyed by the
+// input indices, or, with reused neighbour lists, from a slot per superset
+// entry tagged with the search that made the superset.
+//
 // Precision.  R = double: every step in FP64.  R = float: the Newton solve,
 // the gap, the frame vectors, relative surface velocities and the
 // ln(h/Delta), 1/h - 1/Delta factors stay in FP64; curvatures, K and the
