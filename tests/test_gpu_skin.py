@@ -279,3 +279,44 @@ def test_skin_errors():
     wl = W.config2(n=500)
     with pytest.raises(L.LubError):
         L.Lub.for_workload(wl, skin=-1.0)
+
+
+def test_reuse_across_changing_n():
+    # a handle with a skin, called with the first 1500 particles, all 4096,
+    # then 1500 again (same box): every call equals a fresh handle
+    wl = W.config2()
+    print("[gpu] reused lists: n changes between calls", flush=True)
+    lb = L.Lub.for_workload(wl, precision=L.LUB_MIXED, skin=1.0)
+    full = L.to_device(wl)
+    for n in (1500, wl.n, 1500, 1500):
+        arrays = [a[:n].contiguous() for a in full]
+        f, t = lb.compute(*arrays)
+        fresh = L.Lub.for_workload(wl, precision=L.LUB_MIXED)
+        ff, tf = fresh.compute(*arrays)
+        assert np.array_equal(lb.pairs()[0], fresh.pairs()[0]), f"n={n}"
+        assert close(f.cpu().numpy(), ff.cpu().numpy(), 1e-12), f"n={n}"
+        fresh.close()
+    assert lb.stats()["list_builds"] >= 3
+    lb.close()
+
+
+def test_reuse_still_validates_input():
+    # a call that would reuse the lists (nothing moved) still validates its
+    # input: a quaternion off the unit sphere forces a search, which reports
+    # it; the next good call equals a fresh handle
+    wl = W.config3(n=3000)
+    print("[gpu] reused lists: input errors are still reported", flush=True)
+    lb = L.Lub.for_workload(wl, skin=2.0)
+    r, q, semi, v, w = L.to_device(wl)
+    lb.compute(r, q, semi, v, w)
+    bad = q.clone()
+    bad[7] *= 1.1
+    with pytest.raises(L.LubError):
+        lb.compute(r, bad, semi, v, w)
+    f, t = lb.compute(r, q, semi, v, w)
+    fresh = L.Lub.for_workload(wl)
+    ff, tf = fresh.compute(r, q, semi, v, w)
+    assert np.array_equal(lb.pairs()[0], fresh.pairs()[0])
+    assert close(f.cpu().numpy(), ff.cpu().numpy(), 1e-12)
+    lb.close()
+    fresh.close()
