@@ -183,7 +183,10 @@ typedef struct {
                            /* start of seed_mode judging it and taking over when it */
                            /* does not converge; pairs new to the call use */
                            /* seed_mode.  The paper's time-step continuation (Sec. */
-                           /* III.A).  0: every call starts afresh */
+                           /* III.A).  With skin > 0 the normals are kept per entry */
+                           /* of the reused lists (16 B each; a call that searches */
+                           /* again starts its pairs from seed_mode).  0: every call */
+                           /* starts afresh */
   int32_t reserved;        /* must be 0 */
   double skin;             /* > 0: reuse the neighbour lists across calls.  A search */
                            /* keeps every pair within the pruning bound + skin; a */
