@@ -493,10 +493,12 @@ __global__ void k_records_sorted(CallDesc d, const int32_t* __restrict__ sorted,
 // reject for the entries this particle owns (smaller input index), slot
 // assignment (one atomic per block) and the wall candidates.  Segments have
 // a fixed stride of d.max_nbr entries, at most 8 G.
-#ifndef LUB_NBR_WAVES
-#define LUB_NBR_WAVES 8
-#endif
-constexpr int kWavesPerBlock = LUB_NBR_WAVES;
+// Wavefronts per block (template W): 8 below about a quarter million
+// particles, 4 above, where more, smaller blocks fit beside each other on a
+// CU (measured at a million particles: 2.19 -> 1.97 ms; 8 is faster below
+// and for the kernels of reused lists).
+constexpr int kWavesSmall = 8;
+constexpr int kWavesLarge = 4;
 constexpr int kMaxPerLane = 8;  // segment entries per lane after the sort
 
 __device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
@@ -511,7 +513,7 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask, int lane) {
 // earlier input error discards the lists (state epoch -1).  kMode 2: the
 // reused superset lb.sup_nbr / lb.sup_deg filtered by the exact centre test
 // on the current positions, then as the full search.
-template <int G, int kMode>
+template <int G, int kMode, int kWavesPerBlock>
 __global__ void __launch_bounds__(64 * kWavesPerBlock)
 k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
             const int32_t* __restrict__ orig, const int32_t* __restrict__ cell_sorted,
@@ -945,24 +947,42 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                        r, q, semi, v, w, rec, recp, pos, kin, gate);
 }
 
-template <int G>
+int nbr_waves(const CallDesc& d);  // wavefronts per block of the neighbour kernel
+
+template <int G, int W>
 void launch_nbr_mode(int mode, dim3 grid, size_t lds, hipStream_t s, const CallDesc& d,
                      const PRec* rec, const double4* pos, const int32_t* orig,
                      const int32_t* cell_sorted, const int32_t* cell_start, int32_t* deg,
                      int32_t* nbr, int32_t* slot, int32_t* wall_slot, int32_t* work_s,
                      int32_t* work_t, int64_t* stat_nbr, Counters* cnt, const ListBufs& lb) {
   if (mode == 0)
-    hipLaunchKernelGGL((k_neighbors<G, 0>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
-                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, lb);
+    hipLaunchKernelGGL((k_neighbors<G, 0, W>), grid, dim3(64 * W), lds, s, d, rec, pos, orig,
+                       cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                       stat_nbr, cnt, lb);
   else if (mode == 1)
-    hipLaunchKernelGGL((k_neighbors<G, 1>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
-                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, lb);
+    hipLaunchKernelGGL((k_neighbors<G, 1, W>), grid, dim3(64 * W), lds, s, d, rec, pos, orig,
+                       cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                       stat_nbr, cnt, lb);
   else
-    hipLaunchKernelGGL((k_neighbors<G, 2>), grid, dim3(64 * kWavesPerBlock), lds, s, d, rec,
-                       pos, orig, cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s,
-                       work_t, stat_nbr, cnt, lb);
+    hipLaunchKernelGGL((k_neighbors<G, 2, W>), grid, dim3(64 * W), lds, s, d, rec, pos, orig,
+                       cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                       stat_nbr, cnt, lb);
+}
+
+template <int G>
+void launch_nbr_waves(int mode, dim3 grid, size_t lds, hipStream_t s, const CallDesc& d,
+                      const PRec* rec, const double4* pos, const int32_t* orig,
+                      const int32_t* cell_sorted, const int32_t* cell_start, int32_t* deg,
+                      int32_t* nbr, int32_t* slot, int32_t* wall_slot, int32_t* work_s,
+                      int32_t* work_t, int64_t* stat_nbr, Counters* cnt, const ListBufs& lb) {
+  if (nbr_waves(d) == kWavesLarge)
+    launch_nbr_mode<G, kWavesLarge>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted,
+                                    cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                                    stat_nbr, cnt, lb);
+  else
+    launch_nbr_mode<G, kWavesSmall>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted,
+                                    cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                                    stat_nbr, cnt, lb);
 }
 
 void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
@@ -974,16 +994,16 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
   const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
   dim3 grid(nbr_blocks(d));
-  size_t lds = sizeof(int32_t) * 64 * kWavesPerBlock / nbr_group(d) * (size_t)d.max_nbr;
+  size_t lds = sizeof(int32_t) * 64 * nbr_waves(d) / nbr_group(d) * (size_t)d.max_nbr;
   if (mode == 2 && lists && lists->work_sup) lds *= 2;  // the superset positions too
   if (nbr_group(d) == 16)
-    launch_nbr_mode<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+    launch_nbr_waves<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
   else if (nbr_group(d) == 32)
-    launch_nbr_mode<32>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+    launch_nbr_waves<32>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
   else
-    launch_nbr_mode<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
+    launch_nbr_waves<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
 }
 
@@ -1100,11 +1120,17 @@ int nbr_group(const CallDesc& d) {
   return d.max_nbr <= 8 * 16 ? 16 : (d.max_nbr <= 8 * 32 ? 32 : 64);
 }
 
+// (the superset search and filter of reused lists measured faster with 8)
+int nbr_waves(const CallDesc& d) {
+  return d.n >= (1 << 18) && !(d.skin > 0.0) ? kWavesLarge : kWavesSmall;
+}
+
 int nbr_blocks(const CallDesc& d) {
-  const int per_block = kWavesPerBlock * 64 / nbr_group(d);
+  const int per_block = nbr_waves(d) * 64 / nbr_group(d);
   return (d.n + per_block - 1) / per_block;
 }
 
-int nbr_blocks_max(int n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
+// at least one particle per wavefront, at most kWavesLarge wavefronts
+int nbr_blocks_max(int n) { return (n + kWavesLarge - 1) / kWavesLarge; }
 
 }  // namespace lub
