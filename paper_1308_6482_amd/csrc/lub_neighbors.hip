@@ -493,10 +493,10 @@ __global__ void k_records_sorted(CallDesc d, const int32_t* __restrict__ sorted,
 // reject for the entries this particle owns (smaller input index), slot
 // assignment (one atomic per block) and the wall candidates.  Segments have
 // a fixed stride of d.max_nbr entries, at most 8 G.
-// Wavefronts per block (template W): 8 below about a quarter million
-// particles, 4 above, where more, smaller blocks fit beside each other on a
-// CU (measured at a million particles: 2.19 -> 1.97 ms; 8 is faster below
-// and for the kernels of reused lists).
+// Wavefronts per block (template W): 8 below 16,384 particles, 4 from
+// there, where more, smaller blocks fit beside each other on a CU
+// (measured: a million particles 2.19 -> 1.97 ms, 65,536 106 -> 101 us;
+// 8 is faster at 4096 and for the kernels of reused lists).
 constexpr int kWavesSmall = 8;
 constexpr int kWavesLarge = 4;
 constexpr int kMaxPerLane = 8;  // segment entries per lane after the sort
@@ -1122,7 +1122,7 @@ int nbr_group(const CallDesc& d) {
 
 // (the superset search and filter of reused lists measured faster with 8)
 int nbr_waves(const CallDesc& d) {
-  return d.n >= (1 << 18) && !(d.skin > 0.0) ? kWavesLarge : kWavesSmall;
+  return d.n >= (1 << 14) && !(d.skin > 0.0) ? kWavesLarge : kWavesSmall;
 }
 
 int nbr_blocks(const CallDesc& d) {
