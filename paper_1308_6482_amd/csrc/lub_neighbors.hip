@@ -267,16 +267,33 @@ __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
   unsorted[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
 }
 
+// One particle's inputs for its records, loaded at once.
+struct RecIn {
+  PIn u;
+  double v[3], w[3];
+};
+
+__device__ __forceinline__ RecIn load_record_input(const double* __restrict__ r,
+                                                   const double* __restrict__ q,
+                                                   const double* __restrict__ semi,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ w, int p) {
+  RecIn in;
+  in.u = load_input(r, q, semi, p);
+  for (int k = 0; k < 3; ++k) {
+    in.v[k] = v[3 * p + k];
+    in.w[k] = w[3 * p + k];
+  }
+  return in;
+}
+
 // Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
-// with a the symmetry axis (third column of the rotation of q).
-__device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
-                            const double* __restrict__ r, const double* __restrict__ q,
-                            const double* __restrict__ semi,
-                            const double* __restrict__ v, const double* __restrict__ w,
-                            PRec* __restrict__ rec, PRecP* __restrict__ recp,
-                            double4* __restrict__ pos, KRec* __restrict__ kin,
-                            int32_t* __restrict__ cell_sorted) {
-  double qw = q[4 * p], qx = q[4 * p + 1], qy = q[4 * p + 2], qz = q[4 * p + 3];
+// with a the symmetry axis (third column of the rotation of q).  `cell` is
+// written to cell_sorted when that is given.
+__device__ void make_record_from(int s, const RecIn& in, int cell, PRec* __restrict__ rec,
+                                 PRecP* __restrict__ recp, double4* __restrict__ pos,
+                                 KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
+  double qw = in.u.qw, qx = in.u.qx, qy = in.u.qy, qz = in.u.qz;
   double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= inv;
   qx *= inv;
@@ -285,28 +302,38 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
   double ax = 2.0 * (qx * qz + qw * qy);
   double ay = 2.0 * (qy * qz - qw * qx);
   double az = 1.0 - 2.0 * (qx * qx + qy * qy);
-  double Rpa = semi[2 * p], Rpe = semi[2 * p + 1];
   PRecP c;
-  c.r[0] = r[3 * p];
-  c.r[1] = r[3 * p + 1];
-  c.r[2] = r[3 * p + 2];
+  c.r[0] = in.u.x;
+  c.r[1] = in.u.y;
+  c.r[2] = in.u.z;
   c.ax[0] = ax;
   c.ax[1] = ay;
   c.ax[2] = az;
-  c.Rpar = Rpa;
-  c.Rperp = Rpe;
+  c.Rpar = in.u.a;
+  c.Rperp = in.u.b;
   recp[s] = c;
   const PRec o = expand_record(c);
   rec[s] = o;
   pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
   KRec k;
-  for (int c = 0; c < 3; ++c) {
-    k.v[c] = v[3 * p + c];
-    k.w[c] = w[3 * p + c];
+  for (int m = 0; m < 3; ++m) {
+    k.v[m] = in.v[m];
+    k.w[m] = in.w[m];
   }
   k.pad[0] = k.pad[1] = 0.0;
   kin[s] = k;
-  if (cell_sorted) cell_sorted[s] = cell_id[p];
+  if (cell_sorted) cell_sorted[s] = cell;
+}
+
+__device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
+                            const double* __restrict__ r, const double* __restrict__ q,
+                            const double* __restrict__ semi,
+                            const double* __restrict__ v, const double* __restrict__ w,
+                            PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                            double4* __restrict__ pos, KRec* __restrict__ kin,
+                            int32_t* __restrict__ cell_sorted) {
+  make_record_from(s, load_record_input(r, q, semi, v, w, p), cell_sorted ? cell_id[p] : 0,
+                   rec, recp, pos, kin, cell_sorted);
 }
 
 // Each cell's members in increasing input index (the position of a particle
@@ -330,13 +357,15 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
   if (i >= d.n) return;
   const int p = unsorted[i];
+  // the inputs are fetched while the rank within the cell is counted
+  const RecIn in = load_record_input(r, q, semi, v, w, p);
   const int c = cell_id[p];
   const int b = cell_start[c], e = cell_start[c + 1];
   int rank = 0;
   for (int k = b; k < e; ++k) rank += unsorted[k] < p;
   const int s = b + rank;
   sorted[s] = p;
-  make_record(s, p, cell_id, r, q, semi, v, w, rec, recp, pos, kin, cell_sorted);
+  make_record_from(s, in, c, rec, recp, pos, kin, cell_sorted);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
