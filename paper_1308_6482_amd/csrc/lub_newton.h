@@ -1,0 +1,197 @@
+// lub_newton.h -- closest points of two spheroids by Newton's method on the
+// common normal (Sec. III.A), shared by the pair kernels.  Host and device
+// code: a host build of this header checks the solver's branches on the CPU.
+//
+// The paper's fixed point -- outward normals antiparallel and along the line
+// joining the tangent points -- is, with the tangent points written as
+// support points y_i = r_i + M_i n / h_i(n), y_j = r_j - M_j n / h_j(n)
+// (h_k(n) = sqrt(n.M_k n)), the stationary point of
+// g(n) = n.d - h_i(n) - h_j(n) on the unit sphere; g there is the signed gap
+// (negative for a small overlap).  Newton's method in the tangent plane of n
+// (two unknowns), FP64, with the Hessian shifted to stay negative definite
+// far from the solution and Armijo backtracking.
+#pragma once
+
+#include <math.h>
+
+#ifndef __HIPCC__
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#endif
+
+// backtracking trials and sufficient-increase constant of the line search
+// (a host test build overrides them to force an exhausted search)
+#ifndef LUB_LINE_SEARCH_TRIALS
+#define LUB_LINE_SEARCH_TRIALS 30
+#endif
+#ifndef LUB_ARMIJO
+#define LUB_ARMIJO 1e-4
+#endif
+
+namespace lub {
+
+__host__ __device__ __forceinline__ void symv(const double* M, const double x[3],
+                                     double y[3]) {
+  y[0] = M[0] * x[0] + M[1] * x[1] + M[2] * x[2];
+  y[1] = M[1] * x[0] + M[3] * x[1] + M[4] * x[2];
+  y[2] = M[2] * x[0] + M[4] * x[1] + M[5] * x[2];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T dot3(const T a[3], const T b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// any unit vector orthogonal to the unit vector n
+__host__ __device__ __forceinline__ void perp(const double n[3], double t[3]) {
+  double ax = fabs(n[0]), ay = fabs(n[1]), az = fabs(n[2]);
+  if (ax <= ay && ax <= az) {
+    t[0] = 0.0;
+    t[1] = n[2];
+    t[2] = -n[1];
+  } else if (ay <= az) {
+    t[0] = -n[2];
+    t[1] = 0.0;
+    t[2] = n[0];
+  } else {
+    t[0] = n[1];
+    t[1] = -n[0];
+    t[2] = 0.0;
+  }
+  double inv = 1.0 / sqrt(dot3(t, t));
+  t[0] *= inv;
+  t[1] *= inv;
+  t[2] *= inv;
+}
+
+struct Solve {
+  double n[3];   // unit gap direction i -> j
+  double ai[3];  // y_i - r_i
+  double bj[3];  // r_j - y_j
+  double h;
+  int iters;
+  bool ok;
+};
+
+// Newton iteration for the stationary point of g(n) on the unit sphere,
+// started from n0 (unit) when use_n0, else from the line of centres (the
+// start is selected by value: no pointer to a local escapes to memory)
+__host__ __device__ __forceinline__ Solve closest_points(const double d[3],
+                                                const double* Mi,
+                                                const double* Mj, int maxit,
+                                                const double (&n0)[3], bool use_n0) {
+  Solve o;
+  double dn = sqrt(dot3(d, d));
+  double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+  for (int k = 0; k < 3; ++k) n[k] = use_n0 ? n0[k] : n[k];
+  double prev = 1.0;
+  bool last_full = false;
+  o.ok = false;
+  int it = 0;
+  double hi = 0, hj = 0, ai[3], bj[3];
+  for (;; ++it) {
+    double a[3], b[3];
+    symv(Mi, n, a);
+    symv(Mj, n, b);
+    hi = sqrt(dot3(n, a));
+    hj = sqrt(dot3(n, b));
+    double ih = 1.0 / hi, jh = 1.0 / hj;
+    for (int k = 0; k < 3; ++k) {
+      ai[k] = a[k] * ih;
+      bj[k] = b[k] * jh;
+    }
+    double g[3] = {d[0] - ai[0] - bj[0], d[1] - ai[1] - bj[1],
+                   d[2] - ai[2] - bj[2]};
+    double t1[3], t2[3];
+    perp(n, t1);
+    cross3(n, t1, t2);
+    double r1 = dot3(g, t1), r2 = dot3(g, t2);
+    double tol = 1e-14 * (hi + hj);
+    // converged: the tangential residual at round-off, or a full Newton step
+    // below 1e-8 (quadratic convergence leaves an error of its square); a
+    // step shortened by the line search says nothing about convergence
+    if ((prev < 1e-8 && last_full) || r1 * r1 + r2 * r2 <= tol * tol) {
+      o.ok = true;
+      break;
+    }
+    if (it >= maxit) break;
+    double gn = dot3(g, n);
+    double u1[3], u2[3], w1[3], w2[3];
+    symv(Mi, t1, u1);
+    symv(Mi, t2, u2);
+    symv(Mj, t1, w1);
+    symv(Mj, t2, w2);
+    double at1 = dot3(ai, t1), at2 = dot3(ai, t2);
+    double bt1 = dot3(bj, t1), bt2 = dot3(bj, t2);
+    double H11 = -(dot3(t1, u1) - at1 * at1) * ih - (dot3(t1, w1) - bt1 * bt1) * jh - gn;
+    double H12 = -(dot3(t1, u2) - at1 * at2) * ih - (dot3(t1, w2) - bt1 * bt2) * jh;
+    double H22 = -(dot3(t2, u2) - at2 * at2) * ih - (dot3(t2, w2) - bt2 * bt2) * jh - gn;
+    // keep the (maximisation) Hessian negative definite
+    double mid = 0.5 * (H11 + H22), dif = 0.5 * (H11 - H22);
+    double lmax = mid + sqrt(dif * dif + H12 * H12);
+    double floor_ = 1e-3 * (hi + hj);
+    if (lmax > -floor_) {
+      H11 -= lmax + floor_;
+      H22 -= lmax + floor_;
+    }
+    double det = H11 * H22 - H12 * H12;
+    double s1 = -(H22 * r1 - H12 * r2) / det;
+    double s2 = -(H11 * r2 - H12 * r1) / det;
+    double len = sqrt(s1 * s1 + s2 * s2);
+    if (len > 0.5) {
+      s1 *= 0.5 / len;
+      s2 *= 0.5 / len;
+      len = 0.5;
+    }
+    // Armijo backtracking on g along the (ascent) direction; skipped in the
+    // quadratic basin where the full step is always taken
+    double alpha = 1.0;
+    if (len > 1e-3) {
+      const double g0 = gn;  // g(n) = n.d - h_i - h_j
+      const double slope = r1 * s1 + r2 * s2;
+      bool ascent = false;
+      for (int ls = 0; ls < LUB_LINE_SEARCH_TRIALS; ++ls) {
+        double m[3];
+        for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
+        double inv = 1.0 / sqrt(dot3(m, m));
+        for (int k = 0; k < 3; ++k) m[k] *= inv;
+        double a2[3], b2[3];
+        symv(Mi, m, a2);
+        symv(Mj, m, b2);
+        double gt = dot3(m, d) - sqrt(dot3(m, a2)) - sqrt(dot3(m, b2));
+        if (gt >= g0 + LUB_ARMIJO * alpha * slope) {
+          ascent = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      // no ascent step along the direction: the solve fails (the caller
+      // starts again from another seed or takes the tangent-sphere pass)
+      if (!ascent) break;
+    }
+    prev = alpha * len;
+    last_full = alpha == 1.0;
+    double m[3];
+    for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
+    double inv = 1.0 / sqrt(dot3(m, m));
+    for (int k = 0; k < 3; ++k) n[k] = m[k] * inv;
+  }
+  for (int k = 0; k < 3; ++k) {
+    o.n[k] = n[k];
+    o.ai[k] = ai[k];
+    o.bj[k] = bj[k];
+  }
+  o.h = dot3(n, d) - hi - hj;
+  o.iters = it;
+  return o;
+}
+
+}  // namespace lub
