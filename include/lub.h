@@ -20,7 +20,8 @@
  *
  * Conventions
  *   - Arrays are row-major float64 in DEVICE memory (HBM), e.g. the
- *     data_ptr() of contiguous torch.cuda tensors; n may be 0.
+ *     data_ptr() of contiguous torch.cuda tensors (lub_compute takes host
+ *     arrays instead when lub_opts_t.host_pointers = 1); n may be 0.
  *   - r[n][3]     particle centres (any value; periodic axes are wrapped
  *                 by minimum image, wall axis z must lie in [0, L_z])
  *   - q[n][4]     unit quaternions (w, x, y, z); x_world = Q(q) x_body; the
@@ -84,7 +85,7 @@ extern "C" {
  *   LUB_MODEL_CONTACT no lubrication: the Hookean repulsion of Eq. lub:frep
  *                     alone, acting for h <= h_c (needs h_c > 0).  The
  *                     interaction of the growth stage of the packing
- *                     generator (Sec. IV.A).
+ *                     generator (Sec. IV.C).
  *   LUB_MODEL_LINK    the link-wise law of Ding and Aidun (Sec. II.D, Eq.
  *                     methods:dlub) on the lattice of integer points: every
  *                     D3Q19 link from a site of j (or a fluid site halfway
@@ -134,7 +135,7 @@ typedef struct {
   int32_t periodic[3];     /* 1: periodic (minimum image), 0: bounded */
   int32_t n_walls;         /* 0, or 2: planar walls z = 0 and z = L[2] (needs periodic[2] = 0) */
   double wall_vel[2][3];   /* translational velocity of each wall */
-  /* Lees-Edwards images for a sheared periodic box (Sec. IV.A): with */
+  /* Lees-Edwards images for a sheared periodic box (Sec. IV.C): with */
   /* lees_edwards = 1 the image one box up in z of a particle at r with */
   /* velocity v sits at r + (le_offset, 0, L_z) and moves with */
   /* v + (le_velocity, 0, 0); for a shear rate g at time t, le_velocity = */
@@ -204,6 +205,18 @@ typedef struct {
                            /* with sync = 1).  Periodic lengths must hold twice */
                            /* 2 rmax_bound + cut-off + skin (else LUB_EDOMAIN). */
                            /* 0: search every call */
+  double newton_tol;       /* convergence of the closest-point solve: tangential */
+                           /* residual of the common normal below newton_tol */
+                           /* (h_i(n) + h_j(n)), or a full Newton step below 1e-8 */
+                           /* (<= 0: 1e-14) */
+  int32_t host_pointers;   /* 1: the arrays of lub_compute are in HOST memory: the */
+                           /* call copies r, q, semi, v, w to device staging buffers */
+                           /* of the handle, evaluates, copies f and t back and */
+                           /* waits for the stream (the results are in f and t when */
+                           /* it returns).  Not with graph = 1; lub_integrate and */
+                           /* lub_grow keep taking device arrays (LUB_EINVAL).  0: */
+                           /* device arrays */
+  int32_t reserved2;       /* must be 0 */
 } lub_opts_t;
 
 /* Per-call statistics of the last lub_compute. */
@@ -296,7 +309,7 @@ int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double*
                   double* v, double* w, const double* f_ext, const double* t_ext,
                   double* f, double* t, const lub_step_t* step, void* stream);
 
-/* Growth stage of the packing generator (Sec. IV.A): particles placed
+/* Growth stage of the packing generator (Sec. IV.C): particles placed
  * without overlap at a reduced size grow linearly from scale0 to scale1
  * times their semi-axes over n_steps sub-steps (scale1 slightly above 1
  * leaves a minimum separation once the size is reset), free to move and
@@ -378,6 +391,16 @@ typedef struct {
 int lub_mlp_set_weights(lub_handle_t h, const float* theta, int64_t n);
 /* Copy the FP32 parameters out (host array). */
 int lub_mlp_get_weights(lub_handle_t h, float* theta, int64_t n);
+/* Training state for checkpoints: LUB_MLP_STATE floats, the parameters, the
+ * Adam first and second moments (LUB_MLP_PARAMS each, in that order) and the
+ * number of Adam steps taken (an integer below 2^24 held in a float).  A
+ * state saved and loaded into any handle continues training bit for bit as
+ * the saving handle would.  lub_mlp_save writes a host array (waits for the
+ * device); lub_mlp_load reads one (LUB_EINVAL on a wrong size, a non-finite
+ * value or a bad step count). */
+#define LUB_MLP_STATE (3 * LUB_MLP_PARAMS + 1)
+int lub_mlp_save(lub_handle_t h, float* state, int64_t n);
+int lub_mlp_load(lub_handle_t h, const float* state, int64_t n);
 /* Uniform initialisation with bound sqrt(6 / fan_in), zero biases, from a
  * seed; resets the Adam moments. */
 int lub_mlp_init(lub_handle_t h, uint64_t seed);

@@ -23,7 +23,7 @@ the offset advances by the image velocity times dt first, and a particle
 leaving through z = L_z (z = 0) re-enters at -offset (+offset) in x with its
 x velocity lowered (raised) by the image velocity.
 
-Sec. IV.A, growth stage: particles placed at a reduced linear size grow to
+Sec. IV.C, growth stage: particles placed at a reduced linear size grow to
 slightly beyond their final size, free to move and turn, with the Hookean
 repulsion of Eq. lub:frep as the only interaction and damped velocities.
 Here the scale rises linearly, s_k = s0 + (s1 - s0) (k + 1) / n_steps for

@@ -30,10 +30,10 @@
  *   - rigid-body transfer of Sec. III.B (last equations of the section);
  *   - the comparison laws: normal only (K33 alone), Ladd's sphere law
  *     (Eq. methods:llub), the contact repulsion alone (growth stage of
- *     Sec. IV.A), and the link-wise laws of Sec. II.D (Eq. methods:dlub,
+ *     Sec. IV.C), and the link-wise laws of Sec. II.D (Eq. methods:dlub,
  *     Ding-Aidun and the averaged-normal variant) over the D3Q19 links
  *     between the lattice sites of the two particles;
- *   - Lees-Edwards images of a sheared periodic box (Sec. IV.A).
+ *   - Lees-Edwards images of a sheared periodic box (Sec. IV.C).
  *
  * Parity unpinned (no check independent of this code fixes them): the
  * absolute signs of K13/K23 and K34/K35 beyond the swap, relabel and
@@ -96,7 +96,7 @@ typedef struct {
   int32_t periodic[3];
   int32_t n_walls;          /* 0 or 2 (planes z=0 and z=L[2]) */
   double wall_vel[2][3];    /* translational velocity of each wall */
-  /* Lees-Edwards images (sheared periodic box, Sec. IV.A): the image one box
+  /* Lees-Edwards images (sheared periodic box, Sec. IV.C): the image one box
    * up in z of a particle at r with velocity v sits at r + (le_offset, 0, L_z)
    * and moves with v + (le_velocity, 0, 0).  Needs all axes periodic and no
    * walls. */

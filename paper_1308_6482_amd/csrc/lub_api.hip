@@ -105,6 +105,11 @@ struct lub_ctx {
   int64_t cap_seed = 0;
   float* seedX = nullptr;
   float* seedY = nullptr;
+  // host-pointer mode: device copies of the inputs (15 n doubles: r, q,
+  // semi, v, w) and of the outputs (6 n: f, t)
+  double* stage_in = nullptr;
+  double* stage_out = nullptr;
+  int64_t cap_stage = 0;
   // growth stage: scaled semi-axes and the forces of each sub-step
   double* grow_semi = nullptr;
   double* grow_f = nullptr;
@@ -350,6 +355,7 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->h_c = c->prm.h_c;
   d->eps_c = c->prm.eps_c;
   d->max_iter = c->opt.newton_max_iter > 0 ? c->opt.newton_max_iter : 50;
+  d->newton_tol = c->opt.newton_tol > 0.0 ? c->opt.newton_tol : 1e-14;
   d->max_nbr = c->cur_nbr;
   d->precision = c->opt.precision;
   d->model = c->prm.model;
@@ -721,6 +727,10 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_EINVAL;
   if (opts->reserved != 0 || !(opts->skin >= 0.0) || !std::isfinite(opts->skin))
     return LUB_EINVAL;
+  if (!(opts->newton_tol < 1e-2) || opts->reserved2 != 0 ||
+      (opts->host_pointers != 0 && opts->host_pointers != 1) ||
+      (opts->host_pointers && opts->graph))
+    return LUB_EINVAL;
   lub_ctx* c = new (std::nothrow) lub_ctx();
   if (!c) return LUB_ENOMEM;
   c->device = opts->device;
@@ -812,6 +822,12 @@ int lub_set_domain(lub_handle_t h, const lub_domain_t* domain) {
   return LUB_OK;
 }
 
+namespace {
+int compute_device(lub_handle_t h, int64_t n, const double* r, const double* q,
+                   const double* semi, const double* v, const double* w, double* f,
+                   double* t, hipStream_t s);
+}  // namespace
+
 int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
                 const double* semi, const double* v, const double* w,
                 double* f, double* t, void* stream) {
@@ -819,6 +835,44 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
   HIP_TRY(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  if (!h->opt.host_pointers || n == 0)
+    return compute_device(h, n, r, q, semi, v, w, f, t, s);
+  // host arrays: through the handle's staging buffers
+  if (h->cap_stage < n || !h->stage_in) {
+    h->cap_stage = 0;
+    int rc;
+    if ((rc = realloc_buf(&h->stage_in, 15 * n)) || (rc = realloc_buf(&h->stage_out, 6 * n)))
+      return rc;
+    h->cap_stage = n;
+  }
+  double* dr = h->stage_in;
+  double* dq = dr + 3 * n;
+  double* ds = dq + 4 * n;
+  double* dv = ds + 2 * n;
+  double* dw = dv + 3 * n;
+  double* df = h->stage_out;
+  double* dt = df + 3 * n;
+  const size_t b = sizeof(double) * (size_t)n;
+  HIP_TRY(hipMemcpyAsync(dr, r, 3 * b, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dq, q, 4 * b, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ds, semi, 2 * b, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dv, v, 3 * b, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dw, w, 3 * b, hipMemcpyHostToDevice, s));
+  const int rc = compute_device(h, n, dr, dq, ds, dv, dw, df, dt, s);
+  if (rc) {
+    hipStreamSynchronize(s);
+    return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(f, df, 3 * b, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(t, dt, 3 * b, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return LUB_OK;
+}
+
+namespace {
+int compute_device(lub_handle_t h, int64_t n, const double* r, const double* q,
+                   const double* semi, const double* v, const double* w, double* f,
+                   double* t, hipStream_t s) {
   if (h->opt.graph && s == nullptr) return LUB_EINVAL;  // no capture on the null stream
   CallDesc d;
   int rc = build_desc(h, n, &d);
@@ -860,6 +914,8 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   if (h->host_cnt->error) h->list_epoch++;
   return h->host_cnt->error;
 }
+}  // namespace
+
 
 int lub_get_domain(lub_handle_t h, lub_domain_t* out) {
   if (!h || !out) return LUB_EINVAL;
@@ -910,6 +966,7 @@ int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double*
       !(step->damping >= 0.0) || !std::isfinite(step->damping))
     return LUB_EINVAL;
   if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
+  if (h->opt.host_pointers) return LUB_EINVAL;  // device arrays only
   HIP_TRY(hipSetDevice(h->device));
   for (int k = 0; k < step->n_sub; ++k) {
     int rc = substep(h, n, r, q, semi, v, w, f_ext, t_ext, f, t, step->dt, step->density,
@@ -929,6 +986,7 @@ int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi
       !(cfg->eps_c >= 0.0) || !std::isfinite(cfg->eps_c))
     return LUB_EINVAL;
   if (n > 0 && (!r || !q || !semi || !v || !w)) return LUB_EINVAL;
+  if (h->opt.host_pointers) return LUB_EINVAL;  // device arrays only
   HIP_TRY(hipSetDevice(h->device));
   if (h->cap_grow < n || !h->grow_semi) {
     h->cap_grow = 0;
@@ -1127,6 +1185,39 @@ int lub_mlp_get_weights(lub_handle_t h, float* theta, int64_t n) {
   return LUB_OK;
 }
 
+int lub_mlp_save(lub_handle_t h, float* state, int64_t n) {
+  if (!h || !state || n != 3 * (int64_t)kNParams + 1) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(state, h->th, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(state + kNParams, h->m1, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(state + 2 * kNParams, h->m2, sizeof(float) * kNParams,
+                    hipMemcpyDeviceToHost));
+  state[3 * kNParams] = (float)h->adam_step;
+  return LUB_OK;
+}
+
+int lub_mlp_load(lub_handle_t h, const float* state, int64_t n) {
+  if (!h || !state || n != 3 * (int64_t)kNParams + 1) return LUB_EINVAL;
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(state[k])) return LUB_EINVAL;
+  const float st = state[3 * kNParams];
+  if (!(st >= 0.f) || st > 16777216.f || st != std::floor(st)) return LUB_EINVAL;
+  for (int k = 0; k < kNParams; ++k)
+    if (state[2 * kNParams + k] < 0.f) return LUB_EINVAL;  // second moments
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(h->th, state, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->m1, state + kNParams, sizeof(float) * kNParams, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->m2, state + 2 * kNParams, sizeof(float) * kNParams,
+                    hipMemcpyHostToDevice));
+  h->adam_step = (int)st;
+  mlp_pack(h->th, h->wt, h->wb, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  return LUB_OK;
+}
+
 int lub_mlp_init(lub_handle_t h, uint64_t seed) {
   if (!h) return LUB_EINVAL;
   return mlp_init_host(h, seed);
@@ -1210,7 +1301,7 @@ void lub_destroy(lub_handle_t h) {
                   h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
                   h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY, h->grow_semi,
-                  h->grow_f, h->grow_t};
+                  h->grow_f, h->grow_t, h->stage_in, h->stage_out};
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);

@@ -1,7 +1,7 @@
 // Particle update of the sub-stepped integrator (Sec. II: the particle time
 // step is a fraction of the fluid's, with the lubrication forces evaluated
 // again at every sub-step) and the size ramp of the packing generator's
-// growth stage (Sec. IV.A).
+// growth stage (Sec. IV.C).
 //
 // One thread per particle, FP64 throughout.  The update is semi-implicit
 // Euler with the angular momentum carried in the world frame:

@@ -153,6 +153,7 @@ struct CallDesc {
   double ln_delta_t, ln_delta_r;  // log of the cut-offs (host-evaluated once)
   int32_t max_iter;
   int32_t max_nbr;       // neighbour-segment stride (entries per particle)
+  double newton_tol;     // relative tangential residual of the Newton solve
   int32_t cap_entries;
   int32_t cap_work;
   int32_t precision;

@@ -83,11 +83,13 @@ struct Solve {
 
 // Newton iteration for the stationary point of g(n) on the unit sphere,
 // started from n0 (unit) when use_n0, else from the line of centres (the
-// start is selected by value: no pointer to a local escapes to memory)
+// start is selected by value: no pointer to a local escapes to memory);
+// converged when the tangential residual is below rel_tol (h_i + h_j)
 __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
                                                 const double* Mi,
                                                 const double* Mj, int maxit,
-                                                const double (&n0)[3], bool use_n0) {
+                                                const double (&n0)[3], bool use_n0,
+                                                double rel_tol = 1e-14) {
   Solve o;
   double dn = sqrt(dot3(d, d));
   double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
@@ -114,7 +116,7 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     perp(n, t1);
     cross3(n, t1, t2);
     double r1 = dot3(g, t1), r2 = dot3(g, t2);
-    double tol = 1e-14 * (hi + hj);
+    double tol = rel_tol * (hi + hj);
     // converged: the tangential residual at round-off, or a full Newton step
     // below 1e-8 (quadratic convergence leaves an error of its square); a
     // step shortened by the line search says nothing about convergence

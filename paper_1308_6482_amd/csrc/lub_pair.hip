@@ -470,7 +470,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     int used = 0;
 #pragma clang loop unroll(disable)
     for (;;) {
-      sv = closest_points(d, A.M, Bp.M, cd.max_iter, n0, from_seed);
+      sv = closest_points(d, A.M, Bp.M, cd.max_iter, n0, from_seed, cd.newton_tol);
       if (sv.ok || !from_seed) break;
       used = sv.iters;
       from_seed = false;
@@ -484,7 +484,8 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
       double nl[3];
       if (tangent_spheres(d, A, Bp, nl)) {
         const int used = sv.iters;
-        Solve sp = closest_points(d, A.M, Bp.M, cd.max_iter > 8 ? cd.max_iter : 8, nl, true);
+        Solve sp = closest_points(d, A.M, Bp.M, cd.max_iter > 8 ? cd.max_iter : 8, nl, true,
+                                  cd.newton_tol);
         sp.iters += used;
         if (sp.ok) {
           sv = sp;

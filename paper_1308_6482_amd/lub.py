@@ -24,8 +24,10 @@ EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
            "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
            "lub_get_domain", "lub_integrate", "lub_grow",
+           "lub_mlp_save", "lub_mlp_load",
            "lub_destroy", "lub_strerror"]
 LUB_MLP_PARAMS = 34948
+LUB_MLP_STATE = 3 * LUB_MLP_PARAMS + 1
 
 
 class lub_step_t(C.Structure):
@@ -60,7 +62,9 @@ class lub_opts_t(C.Structure):
                 ("rmax_bound", C.c_double), ("sync", C.c_int32),
                 ("timing", C.c_int32), ("max_neighbors", C.c_int64),
                 ("graph", C.c_int32), ("warm_start", C.c_int32),
-                ("reserved", C.c_int32), ("skin", C.c_double)]
+                ("reserved", C.c_int32), ("skin", C.c_double),
+                ("newton_tol", C.c_double), ("host_pointers", C.c_int32),
+                ("reserved2", C.c_int32)]
 
 
 class lub_stats_t(C.Structure):
@@ -125,6 +129,8 @@ def lib():
         L.lub_mlp_set_weights.argtypes = [_P, _F, C.c_int64]
         L.lub_mlp_get_weights.argtypes = [_P, _F, C.c_int64]
         L.lub_mlp_init.argtypes = [_P, C.c_uint64]
+        L.lub_mlp_save.argtypes = [_P, _F, C.c_int64]
+        L.lub_mlp_load.argtypes = [_P, _F, C.c_int64]
         L.lub_mlp_forward.argtypes = [_P, C.c_int64, _P, _P, _P]
         L.lub_mlp_grad.argtypes = [_P, C.c_int64, _P, _P, _F, _F, _P]
         L.lub_mlp_train.argtypes = [_P, C.c_int64, _P, _P, C.POINTER(lub_train_cfg_t),
@@ -177,10 +183,11 @@ def make_domain(L, periodic=(1, 1, 1), n_walls=0,
 
 def make_opts(rmax_bound, precision=LUB_FP64, device=0, seed_mode=LUB_SEED_PLAIN,
               newton_max_iter=0, sync=1, max_neighbors=0, timing=0,
-              graph=0, warm_start=0, skin=0.0) -> lub_opts_t:
+              graph=0, warm_start=0, skin=0.0, newton_tol=0.0,
+              host_pointers=0) -> lub_opts_t:
     return lub_opts_t(device, precision, seed_mode, newton_max_iter,
                       float(rmax_bound), sync, timing, max_neighbors, graph, warm_start, 0,
-                      float(skin))
+                      float(skin), float(newton_tol), int(host_pointers), 0)
 
 
 # --- the C entry points, same names ------------------------------------------
@@ -226,6 +233,21 @@ def lub_compute(h, r, q, semi, v, w, f, t, stream=None, check=True) -> int:
     if check:
         _check(rc, "lub_compute")
     return rc
+
+
+def lub_compute_host(h, r, q, semi, v, w, stream=None):
+    """lub_compute on a handle created with host_pointers=1: numpy float64
+    arrays in, numpy (f, t) out (the call waits for the results)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (r, q, semi, v, w)]
+    n = arrs[0].shape[0]
+    for a, cols in zip(arrs, (3, 4, 2, 3, 3)):
+        if a.shape != (n, cols):
+            raise ValueError(f"bad shape {a.shape}, expected ({n},{cols})")
+    f = np.zeros((n, 3))
+    t = np.zeros((n, 3))
+    ptrs = [a.ctypes.data for a in arrs] + [f.ctypes.data, t.ctypes.data]
+    _check(lib().lub_compute(h, n, *ptrs, _stream_handle(stream)), "lub_compute")
+    return f, t
 
 
 def _stream_handle(stream):
@@ -351,6 +373,21 @@ def lub_mlp_get_weights(h):
     return th
 
 
+def lub_mlp_save(h):
+    """The training state (weights, Adam moments, step count) as a float32
+    array of LUB_MLP_STATE values."""
+    st = np.zeros(LUB_MLP_STATE, dtype=np.float32)
+    _check(lib().lub_mlp_save(h, st.ctypes.data_as(C.POINTER(C.c_float)), st.size),
+           "lub_mlp_save")
+    return st
+
+
+def lub_mlp_load(h, state):
+    st = np.ascontiguousarray(state, dtype=np.float32)
+    _check(lib().lub_mlp_load(h, st.ctypes.data_as(C.POINTER(C.c_float)), st.size),
+           "lub_mlp_load")
+
+
 def lub_mlp_init(h, seed=0):
     _check(lib().lub_mlp_init(h, int(seed)), "lub_mlp_init")
 
@@ -401,7 +438,7 @@ class Lub:
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
                  sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
                  seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0, lees_edwards=None,
-                 skin=0.0):
+                 skin=0.0, newton_tol=0.0, host_pointers=0):
         self.domain_args = dict(L=L, periodic=periodic, n_walls=n_walls, wall_vel=wall_vel,
                                 lees_edwards=lees_edwards)
         self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel, lees_edwards),
@@ -409,7 +446,8 @@ class Lub:
                             make_opts(rmax_bound, precision, device, seed_mode=seed_mode,
                                       newton_max_iter=newton_max_iter, sync=sync,
                                       max_neighbors=max_neighbors, timing=timing,
-                                      graph=graph, warm_start=warm_start, skin=skin))
+                                      graph=graph, warm_start=warm_start, skin=skin,
+                                      newton_tol=newton_tol, host_pointers=host_pointers))
 
     def compute(self, r, q, semi, v, w, f=None, t=None, stream=None, check=True):
         import torch

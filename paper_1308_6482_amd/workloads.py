@@ -269,7 +269,7 @@ def config2(seed: int = 0, n: int = 4096, phi: float = 0.3) -> Workload:
 def sheared(seed: int = 0, n: int = 4096, phi: float = 0.3, offset_frac: float = 0.37,
             polydisperse: bool = False) -> Workload:
     """A periodic cube under simple shear with Lees-Edwards images (the
-    paper's sheared periodic systems, Sec. IV.A): the image one box up in z
+    paper's sheared periodic systems, Sec. IV.C): the image one box up in z
     is offset by offset_frac L in x (accumulated strain) and moves with
     gamma_dot L in x.  Prolates (8,4,4), or with polydisperse=True aspect
     ratios log-uniform in [1/3, 3] and R_perp in [3, 8]; placed by random

@@ -1,5 +1,5 @@
 """GPU tests of the sub-stepped particle update (lub_integrate, Sec. II) and
-the growth stage of the packing generator (lub_grow, Sec. IV.A), through
+the growth stage of the packing generator (lub_grow, Sec. IV.C), through
 the C ABI, against the reference integrator over the FP64 oracle.
 
 Bars: the state after the sub-steps is compared with the reference; the

@@ -166,3 +166,65 @@ def test_seeded_compute_equals_plain(trained):
     assert np.abs(fm - fp).max() <= 1e-9 * scale_f
     assert np.abs(tm - tp).max() <= 1e-9 * scale_t
     assert sm["newton_iters"] < sp["newton_iters"]
+
+
+def test_seeded_compute_against_oracle(trained, ref):
+    """The trained-weight seeded evaluation against the FP64 oracle, pair by
+    pair (FP64 bar 1e-9), not only against the plain start."""
+    theta, _ = trained
+    wl = W.config2()
+    r, q, semi, v, w = L.to_device(wl)
+    print("[gpu] config2 seeded vs oracle", flush=True)
+    lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, seed_mode=L.LUB_SEED_MLP)
+    L.lub_mlp_set_weights(lb.h, theta)
+    lb.compute(r, q, semi, v, w)
+    torch.cuda.synchronize()
+    pr = lb.pair_results()
+    lb.close()
+    dom = ref.make_domain(**wl.domain())
+    P = ref.make_params(**wl.params)
+    F, Ti, Tj, h, status = ref.eval_pairs(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, pr["ij"])
+    act = status == 0
+    assert np.array_equal(pr["status"] == 0, act)
+    assert np.abs(pr["h"] - h).max() <= 1e-9 * wl.semi.max()
+    nF = np.linalg.norm(F[act], axis=1)
+    eF = np.linalg.norm(pr["F"][act] - F[act], axis=1) / nF
+    sT = np.maximum(np.linalg.norm(Ti[act], axis=1), 4.0 * nF)
+    eT = np.linalg.norm(pr["Ti"][act] - Ti[act], axis=1) / sT
+    print(f"seeded vs oracle: max rel err F {eF.max():.2e} Ti {eT.max():.2e}")
+    assert eF.max() <= 1e-9 and eT.max() <= 1e-9
+
+
+def test_checkpoint_roundtrip():
+    """save -> load -> identical training: a state saved mid-training and
+    loaded into a fresh handle continues bit for bit (weights and Adam
+    moments), and the restored network's outputs equal the original's."""
+    print("[gpu] mlp checkpoint", flush=True)
+    P = S.sample_pairs(seed=21, m=1 << 14)
+    X, T = cuda(P["X"]), cuda(P["T"])
+    a = handle()
+    L.lub_mlp_init(a.h, 3)
+    L.lub_mlp_train(a.h, X, T, epochs=2, batch=1024, lr=2e-3)
+    state = L.lub_mlp_save(a.h)
+    assert state.shape == (L.LUB_MLP_STATE,) and state[-1] == 2 * (1 << 14) // 1024
+    L.lub_mlp_train(a.h, X, T, epochs=2, batch=1024, lr=1e-3)
+    ref_state = L.lub_mlp_save(a.h)
+    b = handle()
+    L.lub_mlp_init(b.h, 99)
+    L.lub_mlp_load(b.h, state)
+    assert np.array_equal(L.lub_mlp_save(b.h), state)
+    L.lub_mlp_train(b.h, X, T, epochs=2, batch=1024, lr=1e-3)
+    got = L.lub_mlp_save(b.h)
+    assert np.array_equal(got, ref_state)
+    Ya = torch.zeros((4096, 4), dtype=torch.float32, device="cuda")
+    Yb = torch.zeros_like(Ya)
+    L.lub_mlp_forward(a.h, X[:4096].contiguous(), Ya)
+    L.lub_mlp_forward(b.h, X[:4096].contiguous(), Yb)
+    torch.cuda.synchronize()
+    assert torch.equal(Ya, Yb)
+    bad = state.copy()
+    bad[-1] = 0.5
+    with pytest.raises(L.LubError):
+        L.lub_mlp_load(b.h, bad)
+    a.close()
+    b.close()

@@ -7,6 +7,8 @@ continuation between time steps).
 * A short trajectory (positions advanced by v dt between calls): every
   step equals a fresh evaluation with the plain start at the FP64 bar,
   with fewer Newton iterations.
+* Every step of a warm-started trajectory against the FP64 oracle pair by
+  pair (and the reused candidate lists bit for bit).
 * Graph replay with warm start equals eager warm start bit for bit, and
   two warm handles on the same trajectory agree bit for bit.
 """
@@ -132,3 +134,41 @@ def test_graph_and_determinism():
         torch.cuda.synchronize()
     for lb in (eager, eager2, graph):
         lb.close()
+
+
+@pytest.mark.parametrize("skin", [0.0, 2.0])
+@pytest.mark.parametrize("precision", [L.LUB_FP64, L.LUB_MIXED])
+def test_trajectory_against_oracle(ref, precision, skin):
+    """Every step of a warm-started trajectory against the FP64 oracle
+    directly: the candidate lists bit for bit (also when reused across calls)
+    and every evaluated pair at the per-pair bar (FP64: 1e-9; mixed: 1e-5
+    for h/a >= 1e-3), as the parity tests check a single evaluation."""
+    from test_gpu_parity import per_pair_errors, run_oracle, check_pairs
+    wl0 = W.config3(n=3000)
+    print(f"[gpu] warm trajectory vs oracle, precision={precision}, skin={skin}", flush=True)
+    warm = L.Lub.for_workload(wl0, precision=precision, warm_start=1, skin=skin)
+    _, q, semi, v, w = L.to_device(wl0)
+    seeded = 0
+    for k, rk in enumerate(trajectory(wl0, 5, dt=1.0)):
+        wl = W.Workload(wl0.name, rk, wl0.q, wl0.semi, wl0.v, wl0.w, wl0.L, wl0.periodic,
+                        wl0.n_walls, wl0.wall_vel, dict(wl0.params))
+        r = torch.as_tensor(rk, dtype=torch.float64, device="cuda")
+        f, t = warm.compute(r, q, semi, v, w)
+        torch.cuda.synchronize()
+        g = dict(f=f.cpu().numpy(), t=t.cpu().numpy(), stats=warm.stats(),
+                 pairs=warm.pairs(), res=warm.pair_results())
+        o = run_oracle(ref, wl)
+        check_pairs(g, o)
+        assert g["stats"]["active"] == o["stats"]["active"]
+        assert g["stats"]["unconverged"] == 0
+        eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+        if precision == L.LUB_FP64:
+            bar, m = 1e-9, act
+        else:
+            bar, m = 1e-5, act & (ha >= 1e-3)
+        print(f"step {k}: seeded {g['stats']['warm_seeded']} active {act.sum()} "
+              f"max err F {eF[m].max():.2e} T {eT[m].max():.2e}")
+        assert eF[m].max() <= bar and eT[m].max() <= bar
+        seeded += g["stats"]["warm_seeded"]
+    assert seeded > 0
+    warm.close()

@@ -1,5 +1,5 @@
 """Pins of the reference integrator (sub-stepped update of Sec. II) and of
-the contact-only law used by the growth stage (Sec. IV.A).
+the contact-only law used by the growth stage (Sec. IV.C).
 
 * Constant force on a free particle: the semi-implicit Euler step has the
   closed form v_N = v_0 + N dt F/m, r_N = r_0 + N dt v_0 + dt^2 F/m N(N+1)/2,

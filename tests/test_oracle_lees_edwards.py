@@ -1,5 +1,5 @@
 """Pins of the oracle's Lees-Edwards images (sheared periodic box of the
-paper's suspension benchmarks, Sec. IV.A).
+paper's suspension benchmarks, Sec. IV.C).
 
 * Offset 0 and image velocity 0: the plain periodic box, bit for bit.
 * The offset acts modulo L_x (exactly representable shifts give identical
