@@ -136,6 +136,8 @@ def lib():
                                      C.c_int64, _I32, C.c_int, _D, _D, _D, _D,
                                      _I32, _I32]
         L.ref_link_eval.argtypes = [_D] * 10 + [C.POINTER(Params), C.POINTER(PairResult)]
+        L.ref_place_pairs.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, C.c_int, _D, _D,
+                                      _D, _D, _D, _I32, _I32]
         _lib = L
     return _lib
 
@@ -314,3 +316,21 @@ def eval_pairs(r, q, semi, v, w, domain: Domain, params: Params, ij,
     if with_links:
         return F, Ti, Tj, h, status, links
     return F, Ti, Tj, h, status
+
+
+def place_pairs(u, target, qi, semii, qj, semij, nthreads=0) -> dict:
+    """Pairs at a prescribed gap: for each row, the centre separation s along
+    the unit u at which the oracle gap equals target, and the oracle's
+    closest points there (dict of s, h, n, yi, yj, iters_lh, status)."""
+    u, target, qi, semii, qj, semij = (_d(x) for x in (u, target, qi, semii, qj, semij))
+    m = u.shape[0]
+    out = dict(s=np.zeros(m), h=np.zeros(m), n=np.zeros((m, 3)), yi=np.zeros((m, 3)),
+               yj=np.zeros((m, 3)), iters_lh=np.zeros(m, dtype=np.int32),
+               status=np.zeros(m, dtype=np.int32))
+    rc = lib().ref_place_pairs(m, _p(u), _p(target), _p(qi), _p(semii), _p(qj), _p(semij),
+                               int(nthreads), _p(out["s"]), _p(out["h"]), _p(out["n"]),
+                               _p(out["yi"]), _p(out["yj"]), _p(out["iters_lh"], _I32),
+                               _p(out["status"], _I32))
+    if rc != 0:
+        raise ValueError(f"ref_place_pairs failed (rc={rc})")
+    return out

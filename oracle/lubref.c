@@ -1321,3 +1321,49 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
   }
   return REF_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* pairs at a prescribed gap (learned-seed data)                       */
+/* ------------------------------------------------------------------ */
+
+int ref_place_pairs(int64_t m, const double* u, const double* target,
+                    const double* qi, const double* semii, const double* qj,
+                    const double* semij, int nthreads, double* s, double* h,
+                    double* n, double* yi, double* yj, int32_t* iters_lh,
+                    int32_t* status) {
+  if (m < 0) return REF_EINVAL;
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < m; ++k) {
+    const double* uk = u + 3 * k;
+    const double g = target[k];
+    const double rmi = semii[2 * k] > semii[2 * k + 1] ? semii[2 * k] : semii[2 * k + 1];
+    const double rmj = semij[2 * k] > semij[2 * k + 1] ? semij[2 * k] : semij[2 * k + 1];
+    double sk = rmi + rmj + g;  /* the gap here is >= g */
+    ref_pair_result o;
+    int st = 3;
+    for (int it = 0; it < 60; ++it) {
+      const double d[3] = {sk * uk[0], sk * uk[1], sk * uk[2]};
+      ref_closest_points(d, qi + 4 * k, semii + 2 * k, qj + 4 * k, semij + 2 * k, &o);
+      if (o.status != REFP_ACTIVE) break;
+      const double diff = o.h - g;
+      if (fabs(diff) <= 1e-12 * (1.0 + g)) {
+        st = 0;
+        break;
+      }
+      const double slope = dot3(o.n, uk);
+      if (!(slope > 1e-12)) break;
+      sk -= diff / slope;
+    }
+    s[k] = sk;
+    h[k] = o.h;
+    for (int a = 0; a < 3; ++a) {
+      n[3 * k + a] = o.n[a];
+      yi[3 * k + a] = o.yi[a];
+      yj[3 * k + a] = o.yj[a];
+    }
+    iters_lh[k] = o.iters_lh;
+    status[k] = st;
+  }
+  return 0;
+}

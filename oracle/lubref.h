@@ -235,6 +235,24 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
                    double* F, double* Ti, double* Tj, double* h,
                    int32_t* status, int32_t* links);
 
+/* Pairs at a prescribed gap along a prescribed direction (the learned
+ * seed's training and held-out pairs): for each of the m pairs, the centre
+ * separation s > 0 along the unit vector u[k] at which the gap of
+ * ref_closest_points equals target[k] > 0, and the closest points there.
+ * The gap along a ray, dist(s u, K_i - K_j), is convex and increasing in s
+ * outside the bodies with slope n.u (n the unit gap direction), so Newton's
+ * method started at the bounding-sphere distance R_max,i + R_max,j +
+ * target converges monotonically from above; it stops when the gap is
+ * within 1e-12 (1 + target) of the target.  Outputs per pair: s, the gap
+ * h, n, y_i - r_i, y_j - r_j (each 3), the Lin-Han iterations of the last
+ * solve, and a status (0 placed, 3 a solve failed or no convergence).
+ * OpenMP over the pairs (nthreads <= 0: the default). */
+int ref_place_pairs(int64_t m, const double* u, const double* target,
+                    const double* qi, const double* semii, const double* qj,
+                    const double* semij, int nthreads, double* s, double* h,
+                    double* n, double* yi, double* yj, int32_t* iters_lh,
+                    int32_t* status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -385,3 +385,24 @@ def config5(seed: int = 0, tiles: int = 8, n_tile: int = 16384, side: float = 20
                     wall_vel=((0.0, 0.0, 0.0), (gd * Lz, 0.0, 0.0)),
                     meta=dict(phi=phi, tiles=tiles, n_tile=n_tile, tile=t,
                               rsa_trials=trials))
+
+
+def config4_pair_inputs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0),
+                        gap=(1e-4, 1.0)) -> dict:
+    """Isolated pairs for the learned Newton seed: both shapes from the
+    polydisperse law of config3 (aspect ratio log-uniform in [1/3, 3],
+    R_perp uniform in [3, 8]), independent uniform orientations, the
+    direction u of the centre offset uniform on the sphere, and a target gap
+    g a with g log-uniform in [1e-4, 1] and a the smallest semi-axis of the
+    pair.  The centre separation along u that gives that gap is found on the
+    oracle's gap (test infrastructure); only the draws are made here."""
+    g_shape, g_ori, g_dir, g_gap = _streams(seed)
+    semi_i = polydisperse_semi(g_shape, m, lam[0], lam[1], rperp[0], rperp[1])
+    semi_j = polydisperse_semi(g_shape, m, lam[0], lam[1], rperp[0], rperp[1])
+    q_i = random_quaternions(g_ori, m)
+    q_j = random_quaternions(g_ori, m)
+    u = g_dir.normal(size=(m, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    a = np.minimum(semi_i.min(axis=1), semi_j.min(axis=1))
+    target = a * np.exp(g_gap.uniform(np.log(gap[0]), np.log(gap[1]), size=m))
+    return dict(q_i=q_i, q_j=q_j, semi_i=semi_i, semi_j=semi_j, u=u, target=target)
