@@ -2,15 +2,24 @@
 """Benchmark of the lubrication correction on one MI355X.
 
 Metric: lubrication-corrected pairs per second (pairs with a non-zero
-correction, particle-particle and particle-wall) for one full evaluation
-(staging, cell list, neighbour lists, closest points, geometry,
-resistance, transfer, per-particle sums) with inputs resident in HBM.
+correction, particle-particle and particle-wall) with the inputs resident
+in HBM.  A step is one full evaluation (staging, cell list, neighbour
+lists, closest points, geometry, resistance, transfer, per-particle sums)
+followed by the advance of the suspension by one time step.
 
-Default workload: 4096 prolate spheroids (semi-axes 8,4,4) at volume
-fraction 0.3 in a periodic cube, simple-shear velocities, seed 0, mixed
-precision.  One step = one lub_compute call on that suspension.
+Default workload (the full-scale configuration): 1,048,576 spheroids with
+aspect ratios log-uniform in [1/4, 4] and R_perp in [4, 8] at volume
+fraction 0.5 in a 2048 x 2048 x 680 box, periodic in x and y, walls at
+z = 0 and z = L, placed by the paper's growth method (Sec. IV.C) and moving
+in a simple shear field; mixed precision.  Between evaluations the
+positions advance by v dt and the orientations by the angular velocity
+(dt = 1).  The timed steps are steps W .. W+K-1 of that trajectory; the
+100-evaluation protocol (per-step counts, Newton iteration percentiles,
+accuracy against the FP64 oracle on a 1 % particle sample every 10th step)
+runs the same trajectory untimed.
 
-Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one
+GPU.
 """
 from __future__ import annotations
 
@@ -18,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -32,49 +42,50 @@ sys.path.insert(0, ROOT)
 #   per active pair, LUB_MIXED: 225 FP64 + 450 FP32 flops; LUB_FP64: 675 FP64
 FLOPS_EVAL = 100
 FLOPS_ITER = 306
-FLOPS_POST = {"mixed": 225 + 450, "fp64": 675}
+FLOPS_POST = {"mixed": (225, 450), "fp64": (675, 0)}
+# Neighbour search per candidate pair (both directions of the centre test and
+# the support-function reject of the owned entry): 55 FP64 flops
+FLOPS_CAND = 55
 # MI355X vector ALU peak, non-packed FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 # (the same for FP64 and unpacked FP32; packed FP32 is not used)
 PEAK_ALU_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+METRIC = "lubrication-corrected pairs/sec on 1 GPU at rel err <=1e-5 vs FP64 oracle"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--workload", choices=["prolates4096", "spheres36", "polydisperse65536",
-                                           "fullscale1M"],
-                    default="prolates4096")
+    ap.add_argument("--workload", choices=["fullscale1M", "prolates4096", "spheres36",
+                                           "polydisperse65536"], default="fullscale1M")
+    ap.add_argument("--dt", type=float, default=None,
+                    help="time step of the trajectory (default 1 for the full-scale "
+                         "system, 0.1 otherwise)")
+    ap.add_argument("--protocol-steps", type=int, default=100,
+                    help="evaluations of the untimed protocol pass (counts, iteration "
+                         "percentiles, accuracy every --snap-every steps)")
+    ap.add_argument("--snap-every", type=int, default=10)
+    ap.add_argument("--sample-frac", type=float, default=0.01,
+                    help="particle sample of the accuracy checks (full-scale system)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="budget of the CPU oracle baseline (0: skip)")
+                    help="budget of the CPU oracle baseline (0: skip the oracle leg)")
+    ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
+                    help="Newton start: line of centres, learned network, or both "
+                         "(the JSON value is the plain form unless --seed mlp)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also run the variants (warm start, reused lists, normal-only "
+                         "law), the 4096-prolate single-evaluation leg, the dynamics "
+                         "and the link-wise laws (1) or not (0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy after the timed region "
                          "(reference for the HBM traffic counters)")
-    ap.add_argument("--model", choices=["full", "normal", "ladd"], default="full",
-                    help="resistance law: the full contact-based model, normal only, or "
-                         "Ladd's sphere law (spheres only)")
-    ap.add_argument("--compare-models", type=int, default=1,
-                    help="also time the normal-only model on the same workload (1) or not (0)")
-    ap.add_argument("--trajectory-dt", type=float, default=None,
-                    help="warm-start leg: positions advanced by v dt between the K timed "
-                         "evaluations (0: skip the leg; default 1 for the full-scale "
-                         "system, 0.1 otherwise)")
-    ap.add_argument("--skin", type=float, nargs="*", default=None,
-                    help="trajectory leg: also time reused neighbour lists with these skins "
-                         "(default 4 for the full-scale system, 1 otherwise; none given: "
-                         "skip)")
-    ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
-                    help="Newton start: line of centres, learned network, or time both "
-                         "(the JSON value is the plain form unless --seed mlp)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU work: read two rocprofv3 --pmc runs of this script with "
                          "--calibrate-copy (FETCH_SIZE, then WRITE_SIZE), scale each by the "
-                         "copy kernel's reading and write profiles/pair_kernel_traffic.json")
-    ap.add_argument("--dynamics", type=int, default=1,
-                    help="also time the sheared box with Lees-Edwards images, the "
-                         "sub-stepped integrator and the growth stage (1) or not (0)")
+                         "copy kernel's reading and write profiles/kernel_traffic.json")
     ap.add_argument("--train-pairs", type=int, default=1 << 21)
     ap.add_argument("--train-epochs", type=int, default=6)
     return ap.parse_args()
@@ -91,26 +102,33 @@ def workload(name):
     return W.config3()
 
 
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+# ---------------------------------------------------------------------------
+# HBM traffic of the dominant kernels from two rocprofv3 --pmc runs
+# ---------------------------------------------------------------------------
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "kernel_traffic.json")
 COPY_BYTES = 512 * 2 ** 20
+TRAFFIC_SOURCES = {"k_pairs": ("lub_pair.hip", "lub_newton.h", "lub_internal.h"),
+                   "k_neighbors": ("lub_neighbors.hip", "lub_internal.h")}
 
 
-def pair_kernel_source_hash():
+def kernel_source_hash(kind):
     h = hashlib.sha256()
-    for f in ("lub_pair.hip", "lub_internal.h"):
+    for f in TRAFFIC_SOURCES[kind]:
         h.update(open(os.path.join(ROOT, "paper_1308_6482_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def pair_kernel_traffic(precision):
-    """HBM bytes per launch of the pair kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
+def kernel_traffic(kind, workload_name, precision):
+    """HBM bytes per launch of a kernel from the committed counter summary,
+    if it was taken on the current kernel source and workload."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
-    rec = json.load(open(TRAFFIC_JSON))
-    if rec.get("source_sha256") != pair_kernel_source_hash():
+    rec = json.load(open(TRAFFIC_JSON)).get(kind, {})
+    if rec.get("source_sha256") != kernel_source_hash(kind):
         return None
-    return rec.get(precision, {}).get("bytes_per_launch")
+    ent = rec.get(f"{workload_name}/{precision}")
+    return ent.get("bytes_per_launch") if ent else None
 
 
 def _counter_means(directory, counter):
@@ -135,15 +153,15 @@ def _counter_means(directory, counter):
     return {k: (tot[k] / num[k], num[k], big[k]) for k in tot}
 
 
-def traffic_summary(fetch_dir, write_dir, precision):
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the pair kernel, each
-    scaled by bytes / reading of the calibration copy (512 MiB read and
-    written by one kernel); writes the JSON the bench line reads."""
+def traffic_summary(fetch_dir, write_dir, workload_name, precision):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the main pair pass and
+    the neighbour search, each scaled by bytes / reading of the calibration
+    copy (512 MiB read and written by one kernel); writes the JSON the bench
+    line reads."""
     fe = _counter_means(fetch_dir, "FETCH_SIZE")
     wr = _counter_means(write_dir, "WRITE_SIZE")
 
     def copy_kernel(tab):
-        # the calibration dispatch is the largest one of the copy kernel
         for k in tab:
             if "copyBuffer" in k:
                 return k
@@ -155,101 +173,42 @@ def traffic_summary(fetch_dir, write_dir, precision):
         raise SystemExit("no calibration copy kernel in the counter runs")
     f_fetch = COPY_BYTES / (fe[kf][2] * 1024.0)
     f_write = COPY_BYTES / (wr[kw][2] * 1024.0)
-    # the main pass of the pair stage (the tangent-sphere pass is k_pairs<R, true>)
-    kern = [k for k in fe if "k_pairs" in k and "true>" not in k]
-    if len(kern) != 1:
-        raise SystemExit(f"expected one main pair kernel, found {kern}")
-    kp = kern[0]
-    fetch_b = fe[kp][0] * 1024.0 * f_fetch
-    write_b = wr[kp][0] * 1024.0 * f_write
     rec = json.load(open(TRAFFIC_JSON)) if os.path.exists(TRAFFIC_JSON) else {}
-    if rec.get("source_sha256") != pair_kernel_source_hash():
-        rec = {}
-    rec["source_sha256"] = pair_kernel_source_hash()
-    rec[precision] = dict(kernel=kp, dispatches=fe[kp][1], fetch_kib=fe[kp][0],
-                          write_kib=wr[kp][0], copy_kernel=kf, copy_fetch_kib=fe[kf][2],
-                          copy_write_kib=wr[kw][2], scale_fetch=f_fetch, scale_write=f_write,
-                          bytes_per_launch=fetch_b + write_b)
+    out = {}
+    for kind, pick in (("k_pairs", lambda k: "k_pairs" in k and "true>" not in k),
+                       ("k_neighbors", lambda k: "k_neighbors" in k)):
+        names = [k for k in fe if pick(k)]
+        if not names:
+            continue
+        # the most frequent instantiation (the probe before the timed region
+        # may use another lane-group size)
+        kp = max(names, key=lambda k: fe[k][1])
+        ent = dict(kernel=kp, dispatches=fe[kp][1], fetch_kib=fe[kp][0],
+                   write_kib=wr.get(kp, (0.0,))[0], copy_kernel=kf,
+                   copy_fetch_kib=fe[kf][2], copy_write_kib=wr[kw][2], scale_fetch=f_fetch,
+                   scale_write=f_write,
+                   bytes_per_launch=fe[kp][0] * 1024.0 * f_fetch
+                   + wr.get(kp, (0.0,))[0] * 1024.0 * f_write)
+        r = rec.get(kind, {})
+        if r.get("source_sha256") != kernel_source_hash(kind):
+            r = {}
+        r["source_sha256"] = kernel_source_hash(kind)
+        r[f"{workload_name}/{precision}"] = ent
+        rec[kind] = r
+        out[kind] = ent
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     json.dump(rec, open(TRAFFIC_JSON, "w"), indent=1, sort_keys=True)
-    others = {k: (fe[k][0] * 1024.0 * f_fetch, wr.get(k, (0.0, 0))[0] * 1024.0 * f_write)
-              for k in fe if k.startswith("lub::") or "k_" in k}
-    print(json.dumps(dict(pair_kernel=rec[precision],
-                          per_kernel_bytes={k: dict(fetch=a, write=b)
-                                            for k, (a, b) in others.items()}), indent=1))
+    print(json.dumps(out, indent=1))
 
 
-def cpu_baseline(wl, seconds, gpu_pairs):
-    """The FP64 oracle on the host cores over the same suspension, plus the
-    error of the GPU pair results against it.  Up to 200,000 particles:
-    whole evaluations repeated for about `seconds`.  Larger systems (whose
-    whole evaluation by the oracle's brute-force pair search would take far
-    longer): all pairs of a random sample of particles, sized to about
-    `seconds`, and the accuracy on the pairs touching a 1% sample."""
-    import numpy as np
-    import oracle
-    dom = oracle.make_domain(**wl.domain())
-    P = oracle.make_params(**wl.params)
-    if wl.n <= 200_000:
-        f, t, st = oracle.compute(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P)
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            f, t, st = oracle.compute(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= seconds:
-                break
-        value = st["active"] * reps / el
-        sample = (f"whole evaluations of the same {wl.n}-particle suspension, "
-                  f"{reps} repeats in {el:.1f} s")
-        ij = gpu_pairs["ij"]
-        res = gpu_pairs
-    else:
-        rng = np.random.default_rng(3)
-        m = 64
-        while True:
-            idx = np.sort(rng.choice(wl.n, size=m, replace=False))
-            t0 = time.perf_counter()
-            _, _, st = oracle.compute_subset(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, idx)
-            el = time.perf_counter() - t0
-            if el >= 0.3 * seconds or m >= 1 << 16:
-                break
-            m *= 4
-        # each active pair is counted once per sampled end, as the oracle
-        # evaluates it once per sampled end
-        value = st["active"] / el
-        sample = (f"all pairs of {m} random particles of the {wl.n}-particle suspension "
-                  f"(brute-force partner search included), {el:.1f} s")
-        # accuracy: the GPU pairs touching a 1% sample
-        keep = np.zeros(wl.n, dtype=bool)
-        keep[rng.choice(wl.n, size=wl.n // 100, replace=False)] = True
-        ij_all = gpu_pairs["ij"]
-        sel = keep[ij_all[:, 0]] | ((ij_all[:, 1] >= 0) & keep[np.maximum(ij_all[:, 1], 0)])
-        ij = ij_all[sel]
-        res = {k: gpu_pairs[k][sel] for k in ("F", "Ti", "Tj")}
-    # GPU accuracy on the checked pairs (force and torque, h/a >= 1e-3)
-    F, Ti, Tj, h, status = oracle.eval_pairs(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, ij)
-    i, j = ij[:, 0], ij[:, 1]
-    a = wl.semi[i].min(axis=1)
-    a = np.where(j >= 0, np.minimum(a, wl.semi[np.maximum(j, 0)].min(axis=1)), a)
-    act = (status == 0) & (h / a >= 1e-3)
-    nF = np.linalg.norm(F, axis=1)
-    eF = np.linalg.norm(res["F"] - F, axis=1)[act] / nF[act]
-    sT = np.maximum(np.linalg.norm(Ti, axis=1), a * nF)[act]
-    eT = np.linalg.norm(res["Ti"] - Ti, axis=1)[act] / sT
-    return dict(value=value, unit="pairs/s", cores=int(st["threads"]), kind="oracle",
-                sample=sample), \
-        dict(pairs_checked=int(act.sum()), max_rel_err_force=float(eF.max()),
-             max_rel_err_torque=float(eT.max()),
-             p99_rel_err_force=float(np.quantile(eF, 0.99)))
-
+# ---------------------------------------------------------------------------
+# learned seed
+# ---------------------------------------------------------------------------
 
 def train_seed(L, torch, n_train, epochs):
     """Train the seed network on the GPU with the library's own kernels on
     constructed pairs shaped like the polydisperse suspension; returns the
     weights and a report (losses, held-out loss, wall time)."""
-    import numpy as np
     from paper_1308_6482_amd import seed_data as S
     t0 = time.perf_counter()
     P = S.sample_pairs(seed=1, m=n_train)
@@ -275,6 +234,22 @@ def train_seed(L, torch, n_train, epochs):
                        generate_s=t_gen, train_s=t_train)
 
 
+# ---------------------------------------------------------------------------
+# the trajectory
+# ---------------------------------------------------------------------------
+
+def advance(r, q, v, w, dt):
+    """One time step of the suspension in place: r += v dt, and the
+    orientation q <- normalise(q + dt/2 (0, w) * q) (quaternion product)."""
+    import torch
+    r.add_(v, alpha=dt)
+    qw, qv = q[:, :1], q[:, 1:]
+    dqw = -(w * qv).sum(dim=1, keepdim=True)
+    dqv = qw * w + torch.cross(w, qv, dim=1)
+    q.add_(torch.cat([dqw, dqv], dim=1), alpha=0.5 * dt)
+    q.div_(q.norm(dim=1, keepdim=True))
+
+
 def neighbour_capacity(L, torch, wl, prec, skin=0.0):
     """One synchronous evaluation (the library widens its neighbour segments
     on demand) gives the largest candidate count (of the superset, with a
@@ -287,110 +262,375 @@ def neighbour_capacity(L, torch, wl, prec, skin=0.0):
     return min(512, 64 * -(-int(1.5 * deg + 1) // 64))
 
 
-def _timed_loop(lb, torch, args, arrays, stream):
-    """W untimed steps, then exactly K timed steps bracketed by device
-    synchronisations; returns ms per step (wall clock)."""
-    r, q, semi, v, w, f, t = arrays
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            lb.compute(r, q, semi, v, w, f, t, stream=stream)
-        torch.cuda.synchronize()
-        lb.reset_timers()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            lb.compute(r, q, semi, v, w, f, t, stream=stream)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    return (t1 - t0) * 1e3 / args.steps
-
-
-def measure(L, torch, wl, prec, args, theta=None):
-    """Two timed loops of `args.steps` evaluations each on one stream: the
-    launch sequence replayed as a HIP graph (the headline), and eager
-    launches with HIP events around each stage (stage times, pair-kernel
-    duration).  Returns (stats of the event loop, ms per step with graphs,
-    ms per step eager, outputs)."""
+def make_handle(L, wl, prec, cap, theta=None, **kw):
     mode = L.LUB_SEED_MLP if theta is not None else L.LUB_SEED_PLAIN
+    lb = L.Lub.for_workload(wl, precision=prec, seed_mode=mode, max_neighbors=cap, **kw)
+    if theta is not None:
+        L.lub_mlp_set_weights(lb.h, theta)
+    return lb
+
+
+def percentile_iters(hist, p):
+    import numpy as np
+    hist = np.asarray(hist, dtype=np.int64)
+    cdf = np.cumsum(hist) / max(hist.sum(), 1)
+    return int(np.searchsorted(cdf, p))
+
+
+def protocol_pass(L, torch, wl, prec, args, cap, theta=None, sample=None, **kw):
+    """The trajectory untimed, with the statistics of every step and, every
+    args.snap_every steps, a snapshot of the state and of the pairs touching
+    the particle sample (for the oracle checks)."""
+    import numpy as np
     r, q, semi, v, w = L.to_device(wl)
-    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
-    t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
-    arrays = (r, q, semi, v, w, f, t)
-    stream = torch.cuda.Stream()
-    results = {}
-    for kind in ("graph", "eager"):
-        kw = dict(graph=1) if kind == "graph" else dict(timing=1)
-        lb = L.Lub.for_workload(wl, precision=prec, sync=0, seed_mode=mode,
-                                max_neighbors=args.max_neighbors, **kw)
-        if theta is not None:
-            L.lub_mlp_set_weights(lb.h, theta)
-        # first call: sizes the workspace; its statistics validate the inputs
-        with torch.cuda.stream(stream):
-            lb.compute(r, q, semi, v, w, f, t, stream=stream)
-        torch.cuda.synchronize()
+    lb = make_handle(L, wl, prec, cap, theta, sync=0, **kw)
+    steps = []
+    snaps = []
+    hist = np.zeros(32, dtype=np.int64)
+    for k in range(args.protocol_steps):
+        lb.compute(r, q, semi, v, w)
         st = lb.stats()
         if st["error"]:
-            raise RuntimeError(f"lub_compute failed: {L.lub_strerror(st['error'])}")
-        ms = _timed_loop(lb, torch, args, arrays, stream)
-        st = lb.stats()
-        lb.close()
-        if st["error"] or st["unconverged"]:
-            raise RuntimeError(f"invalid run: error={st['error']} "
-                               f"unconverged={st['unconverged']}")
-        results[kind] = (st, ms)
-    return results["eager"][0], results["graph"][1], results["eager"][1], (f, t)
+            raise RuntimeError(f"lub_compute failed at step {k}: {L.lub_strerror(st['error'])}")
+        steps.append({key: st[key] for key in ("active", "evaluated", "candidates",
+                                                "wall_candidates", "overlaps", "unresolved",
+                                                "unconverged", "fallbacks", "newton_iters",
+                                                "newton_max", "warm_seeded", "list_builds")})
+        hist += np.asarray(st["iter_hist"], dtype=np.int64)
+        if sample is not None and args.snap_every > 0 and k % args.snap_every == 0:
+            pr = lb.pair_results()
+            ij = pr["ij"]
+            sel = sample[ij[:, 0]] | ((ij[:, 1] >= 0) & sample[np.maximum(ij[:, 1], 0)])
+            snaps.append(dict(step=k, r=r.cpu().numpy(), q=q.cpu().numpy(),
+                              pairs={key: pr[key][sel] for key in pr}))
+        advance(r, q, v, w, args.dt)
+    torch.cuda.synchronize()
+    lb.close()
+    act = np.array([s["active"] for s in steps], dtype=np.int64)
+    ev = np.array([s["evaluated"] for s in steps], dtype=np.int64)
+    it = np.array([s["newton_iters"] for s in steps], dtype=np.int64)
+    summary = dict(steps=args.protocol_steps, dt=args.dt,
+                   active_first=int(act[0]), active_last=int(act[-1]),
+                   active_mean=float(act.mean()), evaluated_mean=float(ev.mean()),
+                   candidates_mean=float(np.mean([s["candidates"] for s in steps])),
+                   overlaps_max=int(max(s["overlaps"] for s in steps)),
+                   unresolved_max=int(max(s["unresolved"] for s in steps)),
+                   unconverged_total=int(sum(s["unconverged"] for s in steps)),
+                   fallbacks_total=int(sum(s["fallbacks"] for s in steps)),
+                   warm_seeded_total=int(sum(s["warm_seeded"] for s in steps)),
+                   newton_iters_mean=float(it.sum() / max(ev.sum(), 1)),
+                   newton_iters_p50=percentile_iters(hist, 0.5),
+                   newton_iters_p99=percentile_iters(hist, 0.99),
+                   newton_max=int(max(s["newton_max"] for s in steps)),
+                   list_searches=int(steps[-1]["list_builds"] - steps[0]["list_builds"] + 1)
+                   if kw.get("skin", 0.0) > 0.0 else args.protocol_steps)
+    return summary, steps, snaps
 
 
-def trajectory(L, torch, wl, prec, args, warm, skin=0.0):
-    """K evaluations along a moving suspension (positions advanced in place
-    by v dt after each evaluation, graph replay), with or without the warm
-    start, or (skin > 0) with reused neighbour lists;
-    returns a report of the last evaluation and the timing."""
-    import numpy as np
-    r0, q, semi, v, w = L.to_device(wl)
-    r = r0.clone()
+def timed_pass(L, torch, wl, prec, args, cap, theta=None, **kw):
+    """W untimed steps, then exactly K timed steps of the trajectory (graph
+    replay), bracketed by device synchronisations; returns ms per step."""
+    r, q, semi, v, w = L.to_device(wl)
     f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
-    t = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
     stream = torch.cuda.Stream()
-    cap = args.max_neighbors
-    if skin > 0.0:
-        # the superset needs wider segments
-        cap = neighbour_capacity(L, torch, wl, prec, skin)
-    lb = L.Lub.for_workload(wl, precision=prec, sync=0, graph=1, warm_start=int(warm),
-                            max_neighbors=cap, skin=skin)
+    lb = make_handle(L, wl, prec, cap, theta, sync=0, graph=1, **kw)
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            r.add_(v, alpha=args.trajectory_dt)
+            advance(r, q, v, w, args.dt)
         torch.cuda.synchronize()
-        st0 = lb.stats()
-        if st0["error"]:
-            raise RuntimeError(f"lub_compute failed: {L.lub_strerror(st0['error'])}")
         t0 = time.perf_counter()
         for _ in range(args.steps):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            r.add_(v, alpha=args.trajectory_dt)
+            advance(r, q, v, w, args.dt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     st = lb.stats()
     lb.close()
     if st["error"]:
-        raise RuntimeError(f"invalid run: error={L.lub_strerror(st['error'])}")
-    ms = (t1 - t0) * 1e3 / args.steps
-    hist = np.array(st["iter_hist"], dtype=np.int64)
-    cdf = np.cumsum(hist) / max(hist.sum(), 1)
-    extra = {}
-    if skin > 0.0:
-        extra = dict(skin=skin, list_searches=st["list_builds"] - st0["list_builds"],
-                     calls=args.steps)
-    return dict(value=st["active"] / (ms * 1e-3), ms_per_step=ms, active=st["active"],
-                overlaps=st["overlaps"], evaluated=st["evaluated"],
-                unconverged=st["unconverged"], unresolved=st["unresolved"],
-                warm_seeded=st["warm_seeded"], fallbacks=st["fallbacks"],
+        raise RuntimeError(f"invalid timed run: {L.lub_strerror(st['error'])}")
+    return (t1 - t0) * 1e3 / args.steps
+
+
+def eager_pass(L, torch, wl, prec, args, cap, theta=None, **kw):
+    """The same K steps launched eagerly with HIP events around each stage
+    and the pair kernel's own dispatch stamps; returns per-step stage times
+    (ms) and the pair-kernel duration, averaged over the K steps."""
+    r, q, semi, v, w = L.to_device(wl)
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    stream = torch.cuda.Stream()
+    lb = make_handle(L, wl, prec, cap, theta, sync=0, timing=1, **kw)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            advance(r, q, v, w, args.dt)
+        torch.cuda.synchronize()
+        lb.reset_timers()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            advance(r, q, v, w, args.dt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    st = lb.stats()
+    lb.close()
+    n = max(st["timed_calls"], 1)
+    return dict(ms_per_step_eager=(t1 - t0) * 1e3 / args.steps,
+                stage_ms={k: v_ / n for k, v_ in zip(
+                    ["cells", "neighbours", "pairs", "reduction"], st["stage_ms"])},
+                pair_kernel_ms=st["pair_kernel_ms"] / n)
+
+
+def measure_form(L, torch, wl, prec, args, cap, theta=None, sample=None, **kw):
+    """Protocol pass, timed pass and eager pass of one form on the trajectory."""
+    summary, steps, snaps = protocol_pass(L, torch, wl, prec, args, cap, theta, sample, **kw)
+    ms = timed_pass(L, torch, wl, prec, args, cap, theta, **kw)
+    # the protocol pass ran the same trajectory: its counts of the timed
+    # steps W .. W+K-1 (the evaluation is deterministic)
+    window = steps[args.warmup:args.warmup + args.steps]
+    timed_active = sum(s_["active"] for s_ in window)
+    ev = eager_pass(L, torch, wl, prec, args, cap, theta, **kw)
+    out = dict(value=timed_active / (args.steps * ms * 1e-3), unit="pairs/s", ms_per_step=ms,
+               active_per_step_timed=timed_active / args.steps, protocol=summary, **ev)
+    return out, snaps, window
+
+
+def detail_snapshot(L, torch, wl, prec, cap, sample):
+    """One evaluation of the initial state with the per-pair intermediate
+    results recorded (closest points, gap direction, frame axis, the 16
+    corrective elements), restricted to the pairs touching the sample."""
+    import numpy as np
+    lb = make_handle(L, wl, prec, cap, None, sync=1, record_detail=1)
+    lb.compute(*L.to_device(wl))
+    pr = lb.pair_results()
+    dt = lb.pair_detail()
+    lb.close()
+    ij = pr["ij"]
+    sel = sample[ij[:, 0]] | ((ij[:, 1] >= 0) & sample[np.maximum(ij[:, 1], 0)])
+    out = {k: v[sel] for k, v in pr.items()}
+    out.update({k: v[sel] for k, v in dt.items()})
+    return out
+
+
+KIDX = [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (1, 1), (1, 2), (1, 3), (1, 4), (2, 2),
+        (2, 3), (2, 4), (2, 5), (3, 3), (3, 4), (4, 4)]
+
+
+def per_output_errors(wl, det, oracle, dom, P):
+    """Every output of the pair path against the oracle on the same pairs:
+    the gap, the closest points, the gap direction, each corrective element
+    (relative to the pair's largest element; pairs whose frame axis differs,
+    at a spheroid's pole, are left out of the elements), force and torque."""
+    import numpy as np
+    ij = det["ij"]
+    o = oracle.eval_pairs_detail(wl.r, wl.q, wl.semi, wl.v, wl.w, dom, P, ij)
+    i, j = ij[:, 0], ij[:, 1]
+    a = wl.semi[i].min(axis=1)
+    a = np.where(j >= 0, np.minimum(a, wl.semi[np.maximum(j, 0)].min(axis=1)), a)
+    act = o["status"] == 0
+    gate = act & (o["h"] / a >= 1e-3)
+    pp = act & (j >= 0)
+    Ko = np.stack([o["Kt"][:, r_, c_] for r_, c_ in KIDX], axis=1)
+    same = np.abs(np.sum(det["e1"] * o["e1"], axis=1) - 1.0) < 1e-9
+    km = gate & same
+    scale = np.maximum(np.abs(Ko).max(axis=1), 1e-300)
+    ek = (np.abs(det["Kt"] - Ko) / scale[:, None])[km]
+    nF = np.linalg.norm(o["F"], axis=1)
+    eF = np.linalg.norm(det["F"] - o["F"], axis=1)[gate] / nF[gate]
+    sT = np.maximum(np.linalg.norm(o["Ti"], axis=1), a * nF)[gate]
+    eT = np.linalg.norm(det["Ti"] - o["Ti"], axis=1)[gate] / sT
+    names = [f"K{r_ + 1}{c_ + 1}" for r_, c_ in KIDX]
+    return dict(
+        pairs=int(len(ij)), active=int(act.sum()), gated=int(gate.sum()),
+        frame_differs=int((act & ~same).sum()),
+        h_abs_over_a=float((np.abs(det["h"] - o["h"]) / a)[act].max()),
+        h_rel=float((np.abs(det["h"] - o["h"]) / np.abs(o["h"]))[gate].max()),
+        yi_over_a=float((np.linalg.norm(det["yi"] - o["yi"], axis=1) / a)[act].max()),
+        yj_over_a=float((np.linalg.norm(det["yj"] - o["yj"], axis=1) / a)[pp].max()),
+        n=float(np.linalg.norm(det["n"] - o["n"], axis=1)[act].max()),
+        K={nm: float(ek[:, k].max()) if ek.size else 0.0 for k, nm in enumerate(names)},
+        force=float(eF.max()), torque=float(eT.max()),
+        lin_han_iters_mean=float(o["iters_lh"][act & (j >= 0)].mean()))
+
+
+def roofline_entries(form, stats_k, args, wl_name):
+    """Achieved / peak of the pair kernel and the neighbour search on the
+    timed steps (counted work of the protocol's steps W..W+K-1 over the
+    launch durations measured with events in the eager pass)."""
+    post64, post32 = FLOPS_POST[args.precision]
+    ev = sum(s["evaluated"] for s in stats_k)
+    it = sum(s["newton_iters"] for s in stats_k)
+    act = sum(s["active"] for s in stats_k)
+    cand = sum(s["candidates"] for s in stats_k)
+    k = max(len(stats_k), 1)
+    flops_pair = (FLOPS_EVAL * ev + FLOPS_ITER * it + (post64 + post32) * act) / k
+    flops_nbr = FLOPS_CAND * cand / k
+    pair_ms = form["pair_kernel_ms"]
+    nbr_ms = form["stage_ms"]["neighbours"]
+    pair = dict(bound="alu", kernel="k_pairs (main pass)", unit="TFLOP/s",
+                achieved=flops_pair / (pair_ms * 1e-3) / 1e12, peak=PEAK_ALU_TFLOPS,
+                flops_per_launch=flops_pair, launch_ms=pair_ms,
+                fp64_flops_per_launch=(FLOPS_EVAL * ev + FLOPS_ITER * it + post64 * act) / k,
+                fp32_flops_per_launch=post32 * act / k,
+                traffic=kernel_traffic("k_pairs", wl_name, args.precision))
+    pair["frac"] = pair["achieved"] / PEAK_ALU_TFLOPS
+    pair["frac_fp64"] = pair["fp64_flops_per_launch"] / (pair_ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS
+    pair["frac_fp32"] = pair["fp32_flops_per_launch"] / (pair_ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS
+    nbr = dict(bound="alu", kernel="k_neighbors (neighbour-list stage)", unit="TFLOP/s",
+               achieved=flops_nbr / (nbr_ms * 1e-3) / 1e12, peak=PEAK_ALU_TFLOPS,
+               flops_per_launch=flops_nbr, launch_ms=nbr_ms,
+               traffic=kernel_traffic("k_neighbors", wl_name, args.precision))
+    nbr["frac"] = nbr["achieved"] / PEAK_ALU_TFLOPS
+    return pair, nbr
+
+
+# ---------------------------------------------------------------------------
+# the oracle leg: CPU baseline and accuracy (the only part that runs it)
+# ---------------------------------------------------------------------------
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def pair_errors(wl, r, q, pairs, ref, dom, P):
+    """Errors of GPU pair results against the oracle's evaluation of the same
+    pairs at the given state: force and torque (h/a >= 1e-3, per-pair
+    scales) and the gap."""
+    import numpy as np
+    ij = pairs["ij"]
+    F, Ti, Tj, h, status = ref.eval_pairs(r, q, wl.semi, wl.v, wl.w, dom, P, ij)
+    i, j = ij[:, 0], ij[:, 1]
+    a = wl.semi[i].min(axis=1)
+    a = np.where(j >= 0, np.minimum(a, wl.semi[np.maximum(j, 0)].min(axis=1)), a)
+    act = (status == 0) & (h / a >= 1e-3)
+    nF = np.linalg.norm(F, axis=1)
+    eF = np.linalg.norm(pairs["F"] - F, axis=1)[act] / nF[act]
+    sT = np.maximum(np.linalg.norm(Ti, axis=1), a * nF)[act]
+    eT = np.linalg.norm(pairs["Ti"] - Ti, axis=1)[act] / sT
+    jj = j >= 0
+    sTj = np.maximum(np.linalg.norm(Tj, axis=1), a * nF)[act & jj]
+    eTj = np.linalg.norm(pairs["Tj"] - Tj, axis=1)[act & jj] / sTj
+    eh = np.abs(pairs["h"] - h) / np.maximum(a, 1e-300)
+    same_status = bool(np.array_equal(pairs["status"] == 0, status == 0))
+    return dict(pairs=int(len(ij)), checked=int(act.sum()), status_equal=same_status,
+                max_rel_err_force=float(eF.max()) if eF.size else 0.0,
+                p99_rel_err_force=float(np.quantile(eF, 0.99)) if eF.size else 0.0,
+                max_rel_err_torque=float(max(eT.max() if eT.size else 0.0,
+                                             eTj.max() if eTj.size else 0.0)),
+                max_abs_err_gap_over_a=float(eh.max()) if eh.size else 0.0)
+
+
+def cpu_leg(wl, snaps_by_form, seconds, det=None):
+    """The FP64 oracle on the host cores: its pairs/s on the pairs the GPU
+    evaluated around the particle sample at the first step (1 thread and all
+    threads, median of 5 after a warm-up), and the accuracy of every
+    snapshot of every form against it."""
+    import numpy as np
+    import oracle
+    dom = oracle.make_domain(**wl.domain())
+    P = oracle.make_params(**wl.params)
+    first = snaps_by_form["plain"][0] if "plain" in snaps_by_form else \
+        next(iter(snaps_by_form.values()))[0]
+    ij = first["pairs"]["ij"]
+    # bounded sample: as many of those pairs as one thread evaluates in
+    # about seconds / 12 (6 runs of each thread count)
+    t0 = time.perf_counter()
+    oracle.eval_pairs(first["r"], first["q"], wl.semi, wl.v, wl.w, dom, P, ij[:2000],
+                      nthreads=1)
+    per_pair = (time.perf_counter() - t0) / min(len(ij), 2000)
+    m = int(min(len(ij), max(2000, seconds / 12.0 / max(per_pair, 1e-9))))
+    sub = ij[:m]
+
+    def timed(nthreads):
+        runs = []
+        for k in range(6):
+            t0 = time.perf_counter()
+            F, Ti, Tj, h, st = oracle.eval_pairs(first["r"], first["q"], wl.semi, wl.v, wl.w,
+                                                 dom, P, sub, nthreads=nthreads)
+            runs.append(time.perf_counter() - t0)
+        active = int(np.sum(st == 0))
+        med = float(np.median(runs[1:]))
+        return active / med, med, active
+
+    v1, med1, act = timed(1)
+    nthr = os.cpu_count() or 1
+    vn, medn, _ = timed(nthr)
+    _, _, st_all = oracle.compute_subset(first["r"], first["q"], wl.semi, wl.v, wl.w, dom, P,
+                                         np.arange(min(64, wl.n)), nthreads=nthr)
+    base = dict(value=vn, unit="pairs/s", cores=int(st_all["threads"]), kind="oracle",
+                sample=(f"{m} pairs touching a {len(first['pairs']['ij'])}-pair neighbourhood "
+                        f"of a particle sample at step 0 ({act} active), evaluated by the "
+                        f"oracle's per-pair path; median of 5 after 1 warm-up"),
+                value_1thread=v1, median_s_1thread=med1, median_s_all=medn,
+                cpu_model=cpu_model(), host_cpus=nthr)
+    acc = {}
+    for form, snaps in snaps_by_form.items():
+        per = [dict(step=s["step"], **pair_errors(wl, s["r"], s["q"], s["pairs"], oracle, dom, P))
+               for s in snaps]
+        acc[form] = dict(
+            snapshots=len(per), pairs_checked=int(sum(p["checked"] for p in per)),
+            max_rel_err_force=max(p["max_rel_err_force"] for p in per),
+            max_rel_err_torque=max(p["max_rel_err_torque"] for p in per),
+            p99_rel_err_force=max(p["p99_rel_err_force"] for p in per),
+            max_abs_err_gap_over_a=max(p["max_abs_err_gap_over_a"] for p in per),
+            status_equal=all(p["status_equal"] for p in per), per_snapshot=per)
+    if det is not None:
+        acc["per_output_step0"] = per_output_errors(wl, det, oracle, dom, P)
+        base["lin_han_iters_mean"] = acc["per_output_step0"]["lin_han_iters_mean"]
+    return base, acc
+
+
+# ---------------------------------------------------------------------------
+# secondary legs
+# ---------------------------------------------------------------------------
+
+def single_eval(L, torch, wl, prec, args, theta=None, **kw):
+    """K graph-replayed evaluations of the same input, and an eager loop with
+    stage events: ms per step, stage times, pair-kernel duration, counts."""
+    r, q, semi, v, w = L.to_device(wl)
+    f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
+    t = torch.empty_like(f)
+    stream = torch.cuda.Stream()
+    cap = neighbour_capacity(L, torch, wl, prec)
+    out = {}
+    for kind in ("graph", "eager"):
+        extra = dict(graph=1) if kind == "graph" else dict(timing=1)
+        lb = make_handle(L, wl, prec, cap, theta, sync=0, **extra, **kw)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            torch.cuda.synchronize()
+            lb.reset_timers()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                lb.compute(r, q, semi, v, w, f, t, stream=stream)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        st = lb.stats()
+        lb.close()
+        if st["error"] or st["unconverged"]:
+            raise RuntimeError(f"invalid run: error={st['error']} unconverged={st['unconverged']}")
+        out[kind] = (st, (t1 - t0) * 1e3 / args.steps)
+    st, ms = out["graph"]
+    ste, mse = out["eager"]
+    n = max(ste["timed_calls"], 1)
+    return dict(value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
+                ms_per_step_eager=mse, active=st["active"], evaluated=st["evaluated"],
+                candidates=st["candidates"],
                 newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
-                newton_iters_p50=int(np.searchsorted(cdf, 0.5)),
-                newton_iters_p99=int(np.searchsorted(cdf, 0.99)),
-                newton_max=st["newton_max"], **extra)
+                newton_max=st["newton_max"], fallbacks=st["fallbacks"],
+                pair_kernel_ms=ste["pair_kernel_ms"] / n,
+                stage_ms={k: v_ / n for k, v_ in zip(
+                    ["cells", "neighbours", "pairs", "reduction"], ste["stage_ms"])}), \
+        (f, t)
 
 
 def dynamics(L, torch, args):
@@ -400,18 +640,16 @@ def dynamics(L, torch, args):
     from paper_1308_6482_amd import workloads as W
     prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
     wl = W.sheared(n=4096)
-    args = argparse.Namespace(**vars(args))
-    args.max_neighbors = neighbour_capacity(L, torch, wl, prec)
-    st, ms, ms_e, _ = measure(L, torch, wl, prec, args)
-    out = dict(workload=wl.name, lees_edwards=dict(
-        value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
-        ms_per_step_eager=ms_e, active=st["active"]))
-    # integrator: sub-steps of 0.1 with the correction evaluated each time,
-    # searching every sub-step or reusing the neighbour lists (skin 1)
-    nsub = max(args.steps // 4, 1)
+    a2 = argparse.Namespace(**vars(args))
+    a2.steps, a2.warmup = 50, 5
+    le, _ = single_eval(L, torch, wl, prec, a2)
+    out = dict(workload=wl.name, lees_edwards=dict(value=le["value"], unit="pairs/s",
+                                                   ms_per_step=le["ms_per_step"],
+                                                   active=le["active"]))
+    nsub = 50
     for key, skin in (("integrator", 0.0), ("integrator_reused_lists", 1.0)):
         r, q, semi, v, w = L.to_device(wl)
-        cap = args.max_neighbors if skin == 0.0 else neighbour_capacity(L, torch, wl, prec, skin)
+        cap = neighbour_capacity(L, torch, wl, prec, skin)
         lb = L.Lub.for_workload(wl, precision=prec, sync=0, max_neighbors=cap, skin=skin)
         f = torch.empty((wl.n, 3), dtype=torch.float64, device="cuda")
         t = torch.empty_like(f)
@@ -430,8 +668,6 @@ def dynamics(L, torch, args):
                         active_last=sti["active"])
         if skin > 0.0:
             out[key].update(skin=skin, list_searches=sti["list_builds"] - b0)
-    # growth stage: 4096 polydisperse spheroids from 30 % size to volume
-    # fraction 0.45, 1200 steps
     rng = np.random.default_rng(7)
     n = 4096
     sm = W.polydisperse_semi(rng, n, 0.5, 2.0, 3.0, 5.0)
@@ -462,146 +698,136 @@ def link_laws(L, torch, args):
     from paper_1308_6482_amd import workloads as W
     wl0 = W.lattice_box()
     out = dict(workload=wl0.name)
+    a2 = argparse.Namespace(**vars(args))
+    a2.steps, a2.warmup = 20, 3
     for name, model in (("link", L.LUB_MODEL_LINK), ("link_navg", L.LUB_MODEL_LINK_NAVG)):
         wl = wl0.with_params(model=model, h_c=0.0, eps_c=0.0)
-        a2 = argparse.Namespace(**vars(args))
-        a2.max_neighbors = neighbour_capacity(L, torch, wl, L.LUB_FP64)
-        st, ms, ms_e, _ = measure(L, torch, wl, L.LUB_FP64, a2)
-        out[name] = dict(value=st["active"] / (ms * 1e-3), unit="pairs/s", ms_per_step=ms,
-                         ms_per_step_eager=ms_e, active=st["active"],
-                         evaluated=st["evaluated"], links=st["newton_iters"],
-                         links_per_s=st["newton_iters"] / (ms * 1e-3),
-                         pair_stage_ms=st["stage_ms"][2] / max(st["timed_calls"], 1))
+        s, _ = single_eval(L, torch, wl, L.LUB_FP64, a2)
+        out[name] = dict(value=s["value"], unit="pairs/s", ms_per_step=s["ms_per_step"],
+                         active=s["active"], evaluated=s["evaluated"],
+                         pair_stage_ms=s["stage_ms"]["pairs"])
     return out
 
 
-def summary(st, ms, args, ms_eager=None):
-    active = st["active"]
-    # the pair kernel's own duration, from events stamped by its dispatch
-    pair_ms = st["pair_kernel_ms"] / max(st["timed_calls"], 1)
-    flops = (FLOPS_EVAL * st["evaluated"] + FLOPS_ITER * st["newton_iters"]
-             + FLOPS_POST[args.precision] * active)
-    return dict(value=active / (ms * 1e-3), ms_per_step=ms, ms_per_step_eager=ms_eager,
-                newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
-                newton_max=st["newton_max"], fallbacks=st["fallbacks"],
-                pair_kernel_ms=pair_ms, flops_per_launch=flops,
-                achieved_tflops=flops / (pair_ms * 1e-3) / 1e12,
-                stage_ms={k: v_ / max(st["timed_calls"], 1) for k, v_ in zip(
-                    ["cells", "neighbours", "pairs", "reduction"], st["stage_ms"])})
-
+# ---------------------------------------------------------------------------
 
 def main():
     args = parse()
     if args.traffic_summary:
-        traffic_summary(*args.traffic_summary, args.precision)
+        wl_name = "fullscale1M" if args.workload == "fullscale1M" else args.workload
+        traffic_summary(*args.traffic_summary, wl_name, args.precision)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the build has no "
+                                   "multi-GPU path); run it with --gpus 1"}), flush=True)
         sys.exit(2)
-    import numpy as np  # noqa: F401
+    import numpy as np
     import torch
     from paper_1308_6482_amd import lub as L
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    models = {"full": L.LUB_MODEL_FULL, "normal": L.LUB_MODEL_NORMAL, "ladd": L.LUB_MODEL_LADD}
-    wl = workload(args.workload).with_params(model=models[args.model])
+    L.lib()
+    if args.dt is None:
+        args.dt = 1.0 if args.workload == "fullscale1M" else 0.1
+    args.protocol_steps = max(args.protocol_steps, args.warmup + args.steps)
     prec = L.LUB_MIXED if args.precision == "mixed" else L.LUB_FP64
-    args.max_neighbors = neighbour_capacity(L, torch, wl, prec)
-    if args.trajectory_dt is None:
-        args.trajectory_dt = 1.0 if args.workload == "fullscale1M" else 0.1
-    forms = {}
-    mlp_report = None
-    theta = None
+    t0 = time.perf_counter()
+    wl = workload(args.workload)
+    gen_s = time.perf_counter() - t0
+    cap = neighbour_capacity(L, torch, wl, prec)
+    sample = None
+    if args.cpu_seconds > 0:
+        rng = np.random.default_rng(3)
+        sample = np.zeros(wl.n, dtype=bool)
+        k = max(1, int(round(args.sample_frac * wl.n))) if wl.n > 20000 else wl.n
+        sample[rng.choice(wl.n, size=k, replace=False)] = True
+
+    theta, mlp_report = None, None
     if args.seed in ("mlp", "both"):
         theta, mlp_report = train_seed(L, torch, args.train_pairs, args.train_epochs)
+    forms, snaps, windows = {}, {}, {}
     if args.seed in ("plain", "both"):
-        st, ms, ms_e, out_plain = measure(L, torch, wl, prec, args)
-        forms["plain"] = (st, ms, ms_e)
+        forms["plain"], snaps["plain"], windows["plain"] = measure_form(
+            L, torch, wl, prec, args, cap, sample=sample)
     if args.seed in ("mlp", "both"):
-        st, ms, ms_e, out_mlp = measure(L, torch, wl, prec, args, theta)
-        forms["mlp"] = (st, ms, ms_e)
-        if "plain" in forms:
-            # equal accuracy: the same converged closest points
-            fp, tp = out_plain
-            fm, tm = out_mlp
-            mlp_report["max_rel_diff_vs_plain"] = float(max(
-                (fm - fp).abs().max() / fp.abs().max(), (tm - tp).abs().max() / tp.abs().max()))
+        forms["mlp"], snaps["mlp"], windows["mlp"] = measure_form(
+            L, torch, wl, prec, args, cap, theta, sample=sample)
     head = "mlp" if args.seed == "mlp" else "plain"
-    st, ms, ms_e = forms[head]
+    hf = forms[head]
+    pair_rl, nbr_rl = roofline_entries(hf, windows[head], args, args.workload)
+    dominant = nbr_rl if nbr_rl["launch_ms"] >= pair_rl["launch_ms"] else pair_rl
     if args.calibrate_copy:
         # a plain copy of known size (512 MiB read, 512 MiB written) as the
-        # reference reading of the traffic counters; a device-to-device copy
-        # and, in case the copy runs on a DMA engine, an elementwise kernel
+        # reference reading of the traffic counters
         x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
-    sm = summary(st, ms, args, ms_e)
-    active = st["active"]
+
     res = dict(
-        metric="lubrication-corrected pairs/sec on 1 GPU at rel err <=1e-5 vs FP64 oracle",
-        value=sm["value"], unit="pairs/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+        metric=METRIC, value=hf["value"], unit="pairs/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=hf["ms_per_step"], higher_is_better=True,
+        scaling="weak", vs_baseline=None,
         dtype="f64+f32" if args.precision == "mixed" else "f64",
-        data="synthetic (seeded random sequential addition, simple-shear velocities)",
+        data="synthetic (seeded; growth-method packing, simple-shear velocities)",
         config=dict(workload=wl.name, n_particles=wl.n, box=list(wl.L),
                     periodic=list(wl.periodic), walls=wl.n_walls, seed=0,
-                    precision=args.precision, newton_seed=head,
-                    cutoffs=[wl.params["delta_n"], wl.params["delta_t"], wl.params["delta_r"]],
+                    volume_fraction=wl.meta.get("phi"), precision=args.precision,
+                    newton_seed=head, dt=args.dt,
+                    cutoffs=[wl.params["delta_n"], wl.params["delta_t"],
+                             wl.params["delta_r"]],
                     h_c=wl.params["h_c"], eps_c=wl.params["eps_c"], mu=wl.params["mu"],
-                    model=args.model,
-                    launch="HIP graph replay", parallelism="single GPU"),
-        pairs=dict(candidates=st["candidates"], wall_candidates=st["wall_candidates"],
-                   evaluated=st["evaluated"], active=active, overlaps=st["overlaps"],
-                   newton_iters_mean=sm["newton_iters_mean"], newton_max=st["newton_max"]),
-        ms_per_step_eager=ms_e,
-        stage_ms=sm["stage_ms"],
-        roofline=dict(bound="alu", kernel="k_pairs (main pass)", achieved=sm["achieved_tflops"],
-                      peak=PEAK_ALU_TFLOPS, unit="TFLOP/s",
-                      frac=sm["achieved_tflops"] / PEAK_ALU_TFLOPS,
-                      flops_per_launch=sm["flops_per_launch"], launch_ms=sm["pair_kernel_ms"],
-                      traffic=pair_kernel_traffic(args.precision)),
-        seed_forms={k: summary(v_[0], v_[1], args, v_[2]) for k, v_ in forms.items()},
+                    launch="HIP graph replay", step="one evaluation + advance by dt",
+                    parallelism="single GPU"),
+        roofline=dict(dominant),
+        roofline_pair_kernel=pair_rl, roofline_neighbour_search=nbr_rl,
+        seed_forms=forms,
+        generation=dict(seconds=gen_s, **{k: v_ for k, v_ in wl.meta.items()
+                                          if k != "growth_stages"}),
     )
+    res["roofline"]["frac"] = dominant["frac"]
     if mlp_report:
         res["mlp_seed"] = mlp_report
-    if args.trajectory_dt > 0:
-        # the paper's continuation between time steps: the same moving
-        # suspension with and without the warm start (last evaluation's counts)
-        res["warm_start"] = dict(
-            dt=args.trajectory_dt,
-            warm=trajectory(L, torch, wl, prec, args, True),
-            plain=trajectory(L, torch, wl, prec, args, False))
-        skins = args.skin
-        if skins is None:
-            skins = [4.0] if args.workload == "fullscale1M" else [1.0]
-        for sk in skins:
-            res["warm_start"][f"reused_lists_skin{sk:g}"] = trajectory(L, torch, wl, prec,
-                                                                      args, False, sk)
-            # with the warm start kept per superset entry
-            res["warm_start"][f"reused_lists_warm_skin{sk:g}"] = trajectory(
-                L, torch, wl, prec, args, True, sk)
-    if args.compare_models and args.model == "full":
-        # the paper's "normal only" comparison model on the same suspension
+    print(f"main forms measured: {res['value']:.4g} pairs/s", file=sys.stderr, flush=True)
+
+    if args.extras:
+        var = {}
+        for name, kw in (("warm_start", dict(warm_start=1)),
+                         ("reused_lists_skin4", dict(skin=4.0)),
+                         ("reused_lists_warm_skin4", dict(skin=4.0, warm_start=1))):
+            a2 = argparse.Namespace(**vars(args))
+            a2.snap_every = 0
+            capk = cap if "skin" not in kw else neighbour_capacity(L, torch, wl, prec,
+                                                                  kw["skin"])
+            var[name], _, _ = measure_form(L, torch, wl, prec, a2, capk, **kw)
+        if theta is not None:
+            a2 = argparse.Namespace(**vars(args))
+            a2.snap_every = 0
+            var["warm_start_mlp_new_pairs"], _, _ = measure_form(L, torch, wl, prec, a2,
+                                                                 cap, theta, warm_start=1)
         wn = wl.with_params(model=L.LUB_MODEL_NORMAL)
-        stn, msn, msn_e, _ = measure(L, torch, wn, prec, args)
-        res["models"] = {"normal": dict(value=stn["active"] / (msn * 1e-3), ms_per_step=msn,
-                                        ms_per_step_eager=msn_e, active=stn["active"],
-                                        newton_iters_mean=stn["newton_iters"]
-                                        / max(stn["evaluated"], 1))}
-    if args.dynamics:
+        a2 = argparse.Namespace(**vars(args))
+        a2.snap_every = 0
+        var["normal_only_law"], _, _ = measure_form(L, torch, wn, prec, a2, cap)
+        res["variants"] = var
+        from paper_1308_6482_amd import workloads as W
+        w2 = W.config2()
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps, a2.warmup = 200, 20
+        sec = {}
+        sec["plain"], _ = single_eval(L, torch, w2, prec, a2)
+        if theta is not None:
+            sec["mlp"], _ = single_eval(L, torch, w2, prec, a2, theta)
+        res["prolates4096"] = dict(workload=w2.name, step="one evaluation of the same input",
+                                   forms=sec)
         res["dynamics"] = dynamics(L, torch, args)
         res["link_laws"] = link_laws(L, torch, args)
     if args.cpu_seconds > 0:
-        lb2 = L.Lub.for_workload(wl, precision=prec)
-        r, q, semi, v, w = L.to_device(wl)
-        lb2.compute(r, q, semi, v, w)
-        pr = lb2.pair_results()
-        lb2.close()
-        cb, acc = cpu_baseline(wl, args.cpu_seconds, pr)
-        res["cpu_baseline"] = cb
+        det = detail_snapshot(L, torch, wl, prec, cap, sample)
+        base, acc = cpu_leg(wl, snaps, args.cpu_seconds, det)
+        res["cpu_baseline"] = base
         res["accuracy"] = acc
     print(json.dumps(res), flush=True)
 

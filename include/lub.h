@@ -216,7 +216,11 @@ typedef struct {
                            /* it returns).  Not with graph = 1; lub_integrate and */
                            /* lub_grow keep taking device arrays (LUB_EINVAL).  0: */
                            /* device arrays */
-  int32_t reserved2;       /* must be 0 */
+  int32_t record_detail;   /* 1: the pair kernel also stores, per evaluated pair, the */
+                           /* closest points, the gap direction, the frame axis x1 */
+                           /* and the 16 corrective resistance elements, for */
+                           /* lub_get_pair_detail (validation: 224 B per evaluation */
+                           /* slot of device memory and the stores); 0: not */
 } lub_opts_t;
 
 /* Per-call statistics of the last lub_compute. */
@@ -352,6 +356,20 @@ int lub_get_pairs(lub_handle_t h, int64_t cap, int32_t* ij, int64_t* n_pairs,
 int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
                          double* F, double* Ti, double* Tj, int32_t* status,
                          int32_t* iters, int64_t* n_out);
+
+/* With opts.record_detail: per evaluated pair of the last call, in the order
+ * of lub_get_pair_results, HOST arrays (each may be NULL): n[k] the unit gap
+ * direction from i to j (3), yi[k] = y_i* - r_i and yj[k] = y_j* - r_j (3
+ * each; 0 for a wall), e1[k] the principal direction x1 of surface i at its
+ * closest point (3; Eq. lub:curvature-directions), Kt[k] the 16 corrective
+ * elements of Eq. lub:resistance-correction at the clipped gap, without the
+ * viscosity, in the order 11 12 13 14 15 22 23 24 25 33 34 35 36 44 45 55
+ * (0 unless the pair is active; the "normal only" law keeps 33 alone).  A
+ * pair whose solve failed reports zeros.  LUB_EINVAL without record_detail
+ * or for the link-wise laws; LUB_ECAPACITY if cap is too small (*n_out
+ * set). */
+int lub_get_pair_detail(lub_handle_t h, int64_t cap, double* n, double* yi, double* yj,
+                        double* e1, double* Kt, int64_t* n_out);
 
 /* ---- learned Newton seed ------------------------------------------------
  * A 10-128-128-128-4 network with SiLU after the hidden layers predicts the

@@ -136,6 +136,10 @@ def lib():
                                      C.c_int64, _I32, C.c_int, _D, _D, _D, _D,
                                      _I32, _I32]
         L.ref_link_eval.argtypes = [_D] * 10 + [C.POINTER(Params), C.POINTER(PairResult)]
+        L.ref_eval_pairs_detail.argtypes = [C.c_int64, _D, _D, _D, _D, _D,
+                                            C.POINTER(Domain), C.POINTER(Params),
+                                            C.c_int64, _I32, C.c_int, _D, _D, _D, _D,
+                                            _I32, _D, _D, _D, _D, _D, _I32, _I32]
         L.ref_place_pairs.argtypes = [C.c_int64, _D, _D, _D, _D, _D, _D, C.c_int, _D, _D,
                                       _D, _D, _D, _I32, _I32]
         _lib = L
@@ -334,3 +338,24 @@ def place_pairs(u, target, qi, semii, qj, semij, nthreads=0) -> dict:
     if rc != 0:
         raise ValueError(f"ref_place_pairs failed (rc={rc})")
     return out
+
+
+def eval_pairs_detail(r, q, semi, v, w, domain: Domain, params: Params, ij, nthreads=0):
+    """eval_pairs with the intermediate results of every pair: dict of F, Ti,
+    Tj, h, status, n, yi, yj, e1 (m,3), Kt (m,6,6, without the viscosity),
+    iters_lh, iters_polish."""
+    r, q, semi, v, w = (_d(x) for x in (r, q, semi, v, w))
+    ij = np.ascontiguousarray(ij, dtype=np.int32)
+    m = ij.shape[0]
+    o = {k: np.zeros((m, 3)) for k in ("F", "Ti", "Tj", "n", "yi", "yj", "e1")}
+    o["h"] = np.zeros(m)
+    o["Kt"] = np.zeros((m, 6, 6))
+    for k in ("status", "iters_lh", "iters_polish"):
+        o[k] = np.zeros(m, dtype=np.int32)
+    lib().ref_eval_pairs_detail(r.shape[0], _p(r), _p(q), _p(semi), _p(v), _p(w),
+                                C.byref(domain), C.byref(params), m, _p(ij, _I32),
+                                int(nthreads), _p(o["F"]), _p(o["Ti"]), _p(o["Tj"]),
+                                _p(o["h"]), _p(o["status"], _I32), _p(o["n"]), _p(o["yi"]),
+                                _p(o["yj"]), _p(o["e1"]), _p(o["Kt"]),
+                                _p(o["iters_lh"], _I32), _p(o["iters_polish"], _I32))
+    return o

@@ -1322,6 +1322,41 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
   return REF_OK;
 }
 
+int ref_eval_pairs_detail(int64_t n, const double* r, const double* q,
+                          const double* semi, const double* v, const double* w,
+                          const ref_domain* dom, const ref_params* prm,
+                          int64_t np, const int32_t* ij, int nthreads,
+                          double* F, double* Ti, double* Tj, double* h,
+                          int32_t* status, double* nrm, double* yi, double* yj,
+                          double* e1, double* Kt, int32_t* iters_lh,
+                          int32_t* iters_polish) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t p = 0; p < np; ++p) {
+    ref_pair_result o;
+    eval_one(n, r, q, semi, v, w, dom, prm, ij[2 * p], ij[2 * p + 1], &o);
+    for (int k = 0; k < 3; ++k) {
+      if (F) F[3 * p + k] = o.F[k];
+      if (Ti) Ti[3 * p + k] = o.Ti[k];
+      if (Tj) Tj[3 * p + k] = o.Tj[k];
+      if (nrm) nrm[3 * p + k] = o.n[k];
+      if (yi) yi[3 * p + k] = o.yi[k];
+      if (yj) yj[3 * p + k] = o.yj[k];
+      if (e1) e1[3 * p + k] = o.e[0][k];
+    }
+    if (Kt)
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b) Kt[36 * p + 6 * a + b] = o.Kt[a][b];
+    if (h) h[p] = o.h;
+    if (status) status[p] = o.status;
+    if (iters_lh) iters_lh[p] = o.iters_lh;
+    if (iters_polish) iters_polish[p] = o.iters_polish;
+  }
+  return REF_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* pairs at a prescribed gap (learned-seed data)                       */
 /* ------------------------------------------------------------------ */

@@ -235,6 +235,20 @@ int ref_eval_pairs(int64_t n, const double* r, const double* q,
                    double* F, double* Ti, double* Tj, double* h,
                    int32_t* status, int32_t* links);
 
+/* As ref_eval_pairs, with the intermediate results of every pair: the unit
+ * gap direction n, y_i - r_i, y_j - r_j (3 each), the frame axis e1 of
+ * surface i (3), the corrective matrix K~ at the clipped gap (36, row-major,
+ * without the viscosity), and the Lin-Han and polish iteration counts.  Any
+ * output pointer may be NULL. */
+int ref_eval_pairs_detail(int64_t n, const double* r, const double* q,
+                          const double* semi, const double* v, const double* w,
+                          const ref_domain* dom, const ref_params* prm,
+                          int64_t np, const int32_t* ij, int nthreads,
+                          double* F, double* Ti, double* Tj, double* h,
+                          int32_t* status, double* nrm, double* yi, double* yj,
+                          double* e1, double* Kt, int32_t* iters_lh,
+                          int32_t* iters_polish);
+
 /* Pairs at a prescribed gap along a prescribed direction (the learned
  * seed's training and held-out pairs): for each of the m pairs, the centre
  * separation s > 0 along the unit vector u[k] at which the gap of

@@ -107,6 +107,7 @@ struct lub_ctx {
   float* seedY = nullptr;
   // host-pointer mode: device copies of the inputs (15 n doubles: r, q,
   // semi, v, w) and of the outputs (6 n: f, t)
+  double* detail = nullptr;        // [work][kDetailWords] with opts.record_detail
   double* stage_in = nullptr;
   double* stage_out = nullptr;
   int64_t cap_stage = 0;
@@ -280,6 +281,8 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
         (rc = realloc_buf(&c->out_iters, work)))
       return rc;
     if (c->opt.skin > 0.0 && c->opt.warm_start && (rc = realloc_buf(&c->work_sup, work)))
+      return rc;
+    if (c->opt.record_detail && (rc = realloc_buf(&c->detail, work * (int64_t)kDetailWords)))
       return rc;
     c->cap_work = work;
     if (c->opt.warm_start) {
@@ -547,7 +550,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_pairs(d, c->recp, c->kin, c->work_s, c->work_t, seeds, c->out,
                    c->out_h, c->out_status, c->out_iters, warm, c->fail_list, c->stat_pair,
                    c->cnt, s,
-                   timing ? ev[5] : nullptr, timing ? ev[6] : nullptr);
+                   timing ? ev[5] : nullptr, timing ? ev[6] : nullptr, c->detail);
     }
     mark(3);
     if (d.partner_codes) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
@@ -585,7 +588,8 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
           c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
-          c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state, c->sup_val, c->work_sup};
+          c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state, c->sup_val, c->work_sup,
+          c->detail};
 }
 
 void drop_graphs(lub_ctx* c) {
@@ -727,7 +731,8 @@ int lub_create(lub_handle_t* out, const lub_domain_t* domain,
     return LUB_EINVAL;
   if (opts->reserved != 0 || !(opts->skin >= 0.0) || !std::isfinite(opts->skin))
     return LUB_EINVAL;
-  if (!(opts->newton_tol < 1e-2) || opts->reserved2 != 0 ||
+  if (!(opts->newton_tol < 1e-2) ||
+      (opts->record_detail != 0 && opts->record_detail != 1) ||
       (opts->host_pointers != 0 && opts->host_pointers != 1) ||
       (opts->host_pointers && opts->graph))
     return LUB_EINVAL;
@@ -1169,6 +1174,35 @@ int lub_get_pair_results(lub_handle_t h, int64_t cap, int32_t* ij, double* hgap,
   return LUB_OK;
 }
 
+int lub_get_pair_detail(lub_handle_t h, int64_t cap, double* n, double* yi, double* yj,
+                        double* e1, double* Kt, int64_t* n_out) {
+  if (!h || !n_out) return LUB_EINVAL;
+  *n_out = 0;
+  if (!h->opt.record_detail || is_link(h->last.model)) return LUB_EINVAL;
+  if (!h->have_last || h->last.n == 0) return LUB_OK;
+  int rc = fetch_counters(h);
+  if (rc) return rc;
+  if (h->host_cnt->error) return h->host_cnt->error;
+  const int m = h->host_cnt->work;
+  *n_out = m;
+  if (m > cap) return LUB_ECAPACITY;
+  if (m == 0) return LUB_OK;
+  std::vector<double> det((size_t)m * kDetailWords);
+  HIP_TRY(hipMemcpy(det.data(), h->detail, sizeof(double) * det.size(), hipMemcpyDeviceToHost));
+  for (int k = 0; k < m; ++k) {
+    const double* d = det.data() + (size_t)k * kDetailWords;
+    for (int c = 0; c < 3; ++c) {
+      if (n) n[3 * k + c] = d[c];
+      if (yi) yi[3 * k + c] = d[3 + c];
+      if (yj) yj[3 * k + c] = d[6 + c];
+      if (e1) e1[3 * k + c] = d[9 + c];
+    }
+    if (Kt)
+      for (int c = 0; c < 16; ++c) Kt[16 * k + c] = d[12 + c];
+  }
+  return LUB_OK;
+}
+
 int lub_mlp_set_weights(lub_handle_t h, const float* theta, int64_t n) {
   if (!h || !theta || n != kNParams) return LUB_EINVAL;
   std::vector<float> th(theta, theta + kNParams);
@@ -1301,7 +1335,7 @@ void lub_destroy(lub_handle_t h) {
                   h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
                   h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY, h->grow_semi,
-                  h->grow_f, h->grow_t, h->stage_in, h->stage_out};
+                  h->grow_f, h->grow_t, h->stage_in, h->stage_out, h->detail};
   for (void* p : bufs)
     if (p) hipFree(p);
   if (h->host_cnt) hipHostFree(h->host_cnt);

@@ -251,12 +251,17 @@ struct WarmTables {
   const ListState* state;    // the current search count (the tag)
 };
 
+// detail (may be null): kDetailWords doubles per evaluation slot, the
+// unit gap direction n, y_i - r_i, y_j - r_j, the frame axis x1 of surface i
+// and the 16 corrective elements K~ (order 11 12 13 14 15 22 23 24 25 33 34
+// 35 36 44 45 55, without the viscosity)
+constexpr int kDetailWords = 28;
 void launch_pairs(const CallDesc& d, const PRecP* recp, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   WarmTables warm, int32_t* fail_list, int64_t* stat_pair,
                   Counters* cnt, hipStream_t s, hipEvent_t ev_start = nullptr,
-                  hipEvent_t ev_stop = nullptr);
+                  hipEvent_t ev_stop = nullptr, double* detail = nullptr);
 
 // seed features of every particle-particle evaluation slot (m x 10, FP32)
 void launch_seed_features(const CallDesc& d, const PRec* rec,

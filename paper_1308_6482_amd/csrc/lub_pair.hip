@@ -438,8 +438,10 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
                           PairOut<R>& out, double& hout, int& status,
                           int& iters, const float* seedY, int& fell_back,
                           const double (&nseed)[3], bool use_nseed, int& warm_used,
-                          double (&nout)[3]) {
+                          double (&nout)[3], double* det) {
   for (int k = 0; k < 3; ++k) out.F[k] = out.Ti[k] = out.Tj[k] = R(0);
+  if (det)
+    for (int k = 0; k < kDetailWords; ++k) det[k] = 0.0;
   if (cd.model == LUB_MODEL_LADD) {
     ladd_pair<R>(cd, A, KA, Bp, KB, pair, side, out, hout, status);
     iters = 0;
@@ -516,6 +518,12 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     status = 3;
     return;
   }
+  if (det)
+    for (int k = 0; k < 3; ++k) {
+      det[k] = sv.n[k];
+      det[3 + k] = sv.ai[k];
+      det[6 + k] = -sv.bj[k];
+    }
   const double h = sv.h;
   const double heff = h > cd.h_c ? h : cd.h_c;
   if (heff >= cd.dmax && h > cd.h_c) {
@@ -561,6 +569,15 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   // the contact-only law has no resistance: the repulsion below acts alone
   const bool lub = cd.model != LUB_MODEL_CONTACT;
   double Ln = lub && heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
+  if (det) {
+    // the frame's x1 axis and the corrective elements K~ = C (ln h_eff - ln
+    // Delta) or C33 (1/h_eff - 1/Delta_n), as the transfer below uses them
+    for (int k = 0; k < 3; ++k) det[9 + k] = e1[k];
+    for (int k = 0; k < 16; ++k) {
+      const double fac = k == 9 ? Ln : (k >= 13 ? Lr : Lt);
+      det[12 + k] = (double)C[k] * fac;
+    }
+  }
 
   // relative surface velocities in the local frame (FP64)
   double Vi[3], Vj[3], wr[3], tmp[3];
@@ -646,7 +663,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                                               WarmTables warm,
                                               int32_t* __restrict__ fail_list,
                                               int64_t* __restrict__ stat_pair,
-                                              Counters* cnt) {
+                                              Counters* cnt, double* __restrict__ detail) {
   // one wavefront per block: statistics are reduced in the wave (ballots,
   // shuffles) and written as this block's row, without atomics
   static_assert(kPairBlock == 64, "one wavefront per block");
@@ -714,7 +731,8 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
       eval_pair<R, kTangent>(cd, A, kin[s], B, pp ? &kin[t] : nullptr, pp,
                              pp ? 0 : -1 - t, o, h, status, iters,
                              pp && seedY ? seedY + 4 * (int64_t)w : nullptr, fb, nprev,
-                             found, wu, nnew);
+                             found, wu, nnew,
+                             detail ? detail + (int64_t)kDetailWords * w : nullptr);
       if (warm_on && status != 3) {
         if (cd.warm_slots) {
           warm.sup_val[e_sup] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
@@ -829,25 +847,25 @@ void launch_pairs(const CallDesc& d, const PRecP* recp, const KRec* kin,
                   const int32_t* work_s, const int32_t* work_t, const float* seedY,
                   void* out, double* out_h, int8_t* out_status, uint8_t* out_iters,
                   WarmTables warm, int32_t* fail_list, int64_t* stat_pair, Counters* cnt,
-                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                  hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop, double* detail) {
   const int blocks = pair_grid(d);
   // the events (may be null) take the main pass's own start and end stamps
   if (d.precision == LUB_MIXED) {
     hipExtLaunchKernelGGL(k_pairs<float, false>, dim3(blocks), dim3(kPairBlock), 0, s,
                           ev_start, ev_stop, 0, d, recp, kin, work_s, work_t, seedY,
                           (PairOut<float>*)out, out_h, out_status, out_iters, warm,
-                          fail_list, stat_pair, cnt);
+                          fail_list, stat_pair, cnt, detail);
     hipLaunchKernelGGL((k_pairs<float, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0, s,
                        d, recp, kin, work_s, work_t, seedY, (PairOut<float>*)out, out_h,
-                       out_status, out_iters, warm, fail_list, stat_pair, cnt);
+                       out_status, out_iters, warm, fail_list, stat_pair, cnt, detail);
   } else {
     hipExtLaunchKernelGGL(k_pairs<double, false>, dim3(blocks), dim3(kPairBlock), 0, s,
                           ev_start, ev_stop, 0, d, recp, kin, work_s, work_t, seedY,
                           (PairOut<double>*)out, out_h, out_status, out_iters, warm,
-                          fail_list, stat_pair, cnt);
+                          fail_list, stat_pair, cnt, detail);
     hipLaunchKernelGGL((k_pairs<double, true>), dim3(kTangentBlocks), dim3(kPairBlock), 0,
                        s, d, recp, kin, work_s, work_t, seedY, (PairOut<double>*)out,
-                       out_h, out_status, out_iters, warm, fail_list, stat_pair, cnt);
+                       out_h, out_status, out_iters, warm, fail_list, stat_pair, cnt, detail);
   }
 }
 

@@ -24,7 +24,7 @@ EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
            "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
            "lub_get_domain", "lub_integrate", "lub_grow",
-           "lub_mlp_save", "lub_mlp_load",
+           "lub_mlp_save", "lub_mlp_load", "lub_get_pair_detail",
            "lub_destroy", "lub_strerror"]
 LUB_MLP_PARAMS = 34948
 LUB_MLP_STATE = 3 * LUB_MLP_PARAMS + 1
@@ -64,7 +64,7 @@ class lub_opts_t(C.Structure):
                 ("graph", C.c_int32), ("warm_start", C.c_int32),
                 ("reserved", C.c_int32), ("skin", C.c_double),
                 ("newton_tol", C.c_double), ("host_pointers", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("record_detail", C.c_int32)]
 
 
 class lub_stats_t(C.Structure):
@@ -126,6 +126,7 @@ def lib():
         L.lub_get_pair_results.argtypes = [_P, C.c_int64, _I32, _D, _D, _D, _D,
                                            _I32, _I32, _I64]
         _F = C.POINTER(C.c_float)
+        L.lub_get_pair_detail.argtypes = [_P, C.c_int64, _D, _D, _D, _D, _D, _I64]
         L.lub_mlp_set_weights.argtypes = [_P, _F, C.c_int64]
         L.lub_mlp_get_weights.argtypes = [_P, _F, C.c_int64]
         L.lub_mlp_init.argtypes = [_P, C.c_uint64]
@@ -184,10 +185,10 @@ def make_domain(L, periodic=(1, 1, 1), n_walls=0,
 def make_opts(rmax_bound, precision=LUB_FP64, device=0, seed_mode=LUB_SEED_PLAIN,
               newton_max_iter=0, sync=1, max_neighbors=0, timing=0,
               graph=0, warm_start=0, skin=0.0, newton_tol=0.0,
-              host_pointers=0) -> lub_opts_t:
+              host_pointers=0, record_detail=0) -> lub_opts_t:
     return lub_opts_t(device, precision, seed_mode, newton_max_iter,
                       float(rmax_bound), sync, timing, max_neighbors, graph, warm_start, 0,
-                      float(skin), float(newton_tol), int(host_pointers), 0)
+                      float(skin), float(newton_tol), int(host_pointers), int(record_detail))
 
 
 # --- the C entry points, same names ------------------------------------------
@@ -347,6 +348,23 @@ def lub_get_pair_results(h) -> dict:
                 iters=it[:k])
 
 
+def lub_get_pair_detail(h) -> dict:
+    """Per evaluated pair (order of lub_get_pair_results): n, yi, yj, e1
+    (m,3) and Kt (m,16); needs a handle created with record_detail=1."""
+    L = lib()
+    m = C.c_int64()
+    rc = L.lub_get_pair_detail(h, 0, None, None, None, None, None, C.byref(m))
+    if rc not in (LUB_OK, LUB_ECAPACITY):
+        _check(rc, "lub_get_pair_detail")
+    k = max(m.value, 1)
+    out = dict(n=np.zeros((k, 3)), yi=np.zeros((k, 3)), yj=np.zeros((k, 3)),
+               e1=np.zeros((k, 3)), Kt=np.zeros((k, 16)))
+    _check(L.lub_get_pair_detail(h, k, *[out[x].ctypes.data_as(_D)
+                                         for x in ("n", "yi", "yj", "e1", "Kt")], C.byref(m)),
+           "lub_get_pair_detail")
+    return {x: v[:m.value] for x, v in out.items()}
+
+
 def _fptr(t, cols):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
@@ -438,7 +456,7 @@ class Lub:
                  wall_vel=((0, 0, 0), (0, 0, 0)), precision=LUB_FP64, device=0,
                  sync=1, newton_max_iter=0, max_neighbors=0, timing=0,
                  seed_mode=LUB_SEED_PLAIN, graph=0, warm_start=0, lees_edwards=None,
-                 skin=0.0, newton_tol=0.0, host_pointers=0):
+                 skin=0.0, newton_tol=0.0, host_pointers=0, record_detail=0):
         self.domain_args = dict(L=L, periodic=periodic, n_walls=n_walls, wall_vel=wall_vel,
                                 lees_edwards=lees_edwards)
         self.h = lub_create(make_domain(L, periodic, n_walls, wall_vel, lees_edwards),
@@ -447,7 +465,8 @@ class Lub:
                                       newton_max_iter=newton_max_iter, sync=sync,
                                       max_neighbors=max_neighbors, timing=timing,
                                       graph=graph, warm_start=warm_start, skin=skin,
-                                      newton_tol=newton_tol, host_pointers=host_pointers))
+                                      newton_tol=newton_tol, host_pointers=host_pointers,
+                                      record_detail=record_detail))
 
     def compute(self, r, q, semi, v, w, f=None, t=None, stream=None, check=True):
         import torch
@@ -496,6 +515,9 @@ class Lub:
 
     def pair_results(self):
         return lub_get_pair_results(self.h)
+
+    def pair_detail(self):
+        return lub_get_pair_detail(self.h)
 
     def close(self):
         if self.h:

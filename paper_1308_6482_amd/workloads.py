@@ -350,41 +350,99 @@ def config3(seed: int = 0, n: int = 65536, phi: float = 0.4,
                               rsa_trials=trials, placed=m))
 
 
-def config5(seed: int = 0, tiles: int = 8, n_tile: int = 16384, side: float = 2048.0,
-            phi: float = 0.4) -> Workload:
-    """Full-scale suspension: tiles x tiles x n_tile (default 1,048,576)
-    spheroids with aspect ratio log-uniform in [1/4, 4] and equatorial
-    semi-axis uniform in [4, 8], in a side x side x L box, periodic in x and
-    y, walls at z = 0 and z = L, shear velocities.
+# Growth schedule of config5 (Sec. IV.C's packing generator, run on the GPU by
+# the library's growth stage, lub_grow): (scale0, scale1, steps, h_c, eps_ref)
+# per call; the contact stiffness is eps_ref scale0^3, so that accelerations
+# (force over a mass that scales with the volume) do not depend on the size.
+# Five ramps from 30 % to the final size with a contact range of 0.3, a ramp
+# to 103 % with a range of 0.05, a relaxation there, then the size is reset:
+# the overshoot leaves a minimum separation (min gap ~0.15 lattice units).
+CONFIG5_GROWTH = [(0.3, 0.45, 2000, 0.3, 1000.0), (0.45, 0.6, 2000, 0.3, 1000.0),
+                  (0.6, 0.75, 2000, 0.3, 1000.0), (0.75, 0.9, 2000, 0.3, 1000.0),
+                  (0.9, 1.0, 2000, 0.3, 1000.0), (1.0, 1.03, 2000, 0.05, 1000.0),
+                  (1.03, 1.03, 1000, 0.05, 1000.0)]
 
-    One periodic tile (side/tiles across, height from the volume fraction)
-    is filled by random sequential addition, largest first; the box is
-    tiles x tiles copies of it side by side, which overlap nowhere because
-    the tile is periodic in x and y.  Random sequential addition jams below
-    volume fraction 0.5 for these shapes, so the default is 0.4 (L = 850 at
-    the default sizes)."""
+
+def grow_suspension(r, q, semi, L, periodic, n_walls, stages, device="cuda:0",
+                    dt=0.2, damping=1.0):
+    """Growth stage of the packing generator on the GPU (the library's
+    lub_grow, contact repulsion only, damped velocities): particles placed at
+    scale stages[0][0] grow through the stages; returns the final (r, q)."""
+    import torch
+    from . import lub as L_
+    smax = max(max(s0, s1) for s0, s1, *_ in stages)
+    params = dict(mu=MU, delta_n=DELTA_N, delta_t=DELTA_T, delta_r=DELTA_R, h_c=H_C,
+                  eps_c=EPS_C)
+    lb = L_.Lub(L, periodic, params, smax * float(semi.max()), n_walls=n_walls,
+                device=int(str(device).split(":")[-1]) if ":" in str(device) else 0)
+    z = np.zeros_like(r)
+    dev = [torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).to(device)
+           for x in (r, q, semi, z, z)]
+    for s0, s1, steps, hc, eps in stages:
+        lb.grow(*dev, n_steps=steps, scale0=s0, scale1=s1, dt=dt, density=1.0,
+                damping=damping, h_c=hc, eps_c=eps * s0 ** 3)
+    torch.cuda.synchronize()
+    lb.close()
+    return dev[0].cpu().numpy(), dev[1].cpu().numpy()
+
+
+def _cache_dir():
+    return os.environ.get("LUB_WORKLOAD_CACHE",
+                          os.path.join(os.environ.get("TMPDIR", "/tmp"), "lub_workloads"))
+
+
+def config5(seed: int = 0, n: int = 1 << 20, side: float = 2048.0, phi: float = 0.5,
+            device: str = "cuda:0", stages=None, cache: bool = True) -> Workload:
+    """Full-scale suspension: n spheroids (default 1,048,576) with aspect
+    ratio log-uniform in [1/4, 4] and equatorial semi-axis uniform in [4, 8]
+    at volume fraction phi in a side x side x L box (L = 680 at the defaults),
+    periodic in x and y, walls at z = 0 and z = L, shear velocities (walls
+    co-moving with the shear field).
+
+    Placed with the paper's growth method (Sec. IV.C): random sequential
+    addition at 30 % of the linear size (volume fraction 0.0135), then the
+    growth stage on the GPU (lub_grow: contact repulsion only, damped
+    motion) to 103 % of the size and a reset to the true size.  Needs the
+    GPU; the result is cached in $LUB_WORKLOAD_CACHE (default
+    $TMPDIR/lub_workloads) keyed by the arguments and the library build."""
+    import hashlib
+    stages = stages or CONFIG5_GROWTH
     g_pos, g_shape, g_vel, _ = _streams(seed)
-    semi_t = polydisperse_semi(g_shape, n_tile, 0.25, 4.0, 4.0, 8.0)
-    order = np.argsort(-semi_t.max(axis=1), kind="stable")
-    semi_t = semi_t[order]
-    t = side / tiles
-    vol = float(np.sum(4.0 / 3.0 * np.pi * semi_t[:, 0] * semi_t[:, 1] ** 2))
-    Lz = vol / (phi * t * t)
-    r_t, q_t, trials = rsa(g_pos, semi_t, (t, t, Lz), (1, 1, 0), max_trials=400 * n_tile)
-    if r_t.shape[0] != n_tile:
-        raise RuntimeError("config5: random sequential addition ran out of trials")
-    shifts = np.array([(ix * t, iy * t, 0.0) for iy in range(tiles) for ix in range(tiles)])
-    r = (r_t[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
-    q = np.tile(q_t, (tiles * tiles, 1))
-    semi = np.tile(semi_t, (tiles * tiles, 1))
+    semi = polydisperse_semi(g_shape, n, 0.25, 4.0, 4.0, 8.0)
+    vol = float(np.sum(4.0 / 3.0 * np.pi * semi[:, 0] * semi[:, 1] ** 2))
+    Lz = vol / (phi * side * side)
+    L = (side, side, Lz)
+    key = hashlib.sha256(repr((seed, n, side, phi, stages)).encode())
+    from . import lub as L_
+    with open(L_.LIB_PATH, "rb") as fh:
+        key.update(fh.read())
+    path = os.path.join(_cache_dir(), f"config5_{key.hexdigest()[:24]}.npz")
+    meta = dict(phi=phi, growth_stages=[list(s) for s in stages])
+    if cache and os.path.exists(path):
+        z = np.load(path)
+        r, q = z["r"], z["q"]
+        meta.update(rsa_trials=int(z["trials"]), generate_s=0.0, cached=True)
+    else:
+        import time
+        t0 = time.perf_counter()
+        r0, q0, trials = rsa(g_pos, semi * stages[0][0], L, (1, 1, 0), max_trials=50 * n)
+        if r0.shape[0] != n:
+            raise RuntimeError("config5: random sequential addition ran out of trials")
+        t1 = time.perf_counter()
+        r, q = grow_suspension(r0, q0, semi, L, (1, 1, 0), 2, stages, device)
+        t2 = time.perf_counter()
+        meta.update(rsa_trials=trials, rsa_s=t1 - t0, grow_s=t2 - t1, generate_s=t2 - t0,
+                    cached=False)
+        if cache:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            tmp = path + f".tmp{os.getpid()}.npz"
+            np.savez(tmp, r=r, q=q, trials=trials)
+            os.replace(tmp, path)
     v, w = shear_velocities(g_vel, r)
     gd = 1e-3
-    n = r.shape[0]
-    return Workload(f"fullscale{n}_walls_phi{phi}", r, q, semi, v, w, (side, side, Lz),
+    return Workload(f"fullscale{n}_walls_phi{phi}_grown", r, q, semi, v, w, L,
                     (1, 1, 0), n_walls=2,
-                    wall_vel=((0.0, 0.0, 0.0), (gd * Lz, 0.0, 0.0)),
-                    meta=dict(phi=phi, tiles=tiles, n_tile=n_tile, tile=t,
-                              rsa_trials=trials))
+                    wall_vel=((0.0, 0.0, 0.0), (gd * Lz, 0.0, 0.0)), meta=meta)
 
 
 def config4_pair_inputs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0),

@@ -38,23 +38,56 @@ def test_traffic_summary_scaling(tmp_path, capsys):
     b.TRAFFIC_JSON = str(tmp_path / "traffic.json")
     pair = "void lub::k_pairs<float, false>(lub::CallDesc, ...)"
     tangent = "void lub::k_pairs<float, true>(lub::CallDesc, ...)"
+    nbr = "void lub::k_neighbors<32, 0, 4>(lub::CallDesc, ...)"
+    probe = "void lub::k_neighbors<16, 0, 4>(lub::CallDesc, ...)"
     copy = "__amd_rocclr_copyBuffer"
     # the copy reads 512 MiB: FETCH_SIZE shows half (scale 2), WRITE_SIZE all
     write_counters(tmp_path / "f", "FETCH_SIZE",
                    [(copy, 262144.0), (copy, 10.0), (pair, 100.0), (pair, 300.0),
-                    (tangent, 5.0)])
+                    (tangent, 5.0), (nbr, 1000.0), (nbr, 1000.0), (nbr, 1000.0),
+                    (probe, 7.0)])
     write_counters(tmp_path / "w", "WRITE_SIZE",
-                   [(copy, 524288.0), (pair, 50.0), (pair, 50.0), (tangent, 1.0)])
-    b.traffic_summary(str(tmp_path / "f"), str(tmp_path / "w"), "mixed")
+                   [(copy, 524288.0), (pair, 50.0), (pair, 50.0), (tangent, 1.0),
+                    (nbr, 20.0), (nbr, 20.0), (nbr, 20.0), (probe, 1.0)])
+    b.traffic_summary(str(tmp_path / "f"), str(tmp_path / "w"), "wl", "mixed")
     rec = json.load(open(b.TRAFFIC_JSON))
-    m = rec["mixed"]
+    m = rec["k_pairs"]["wl/mixed"]
     assert m["kernel"] == pair and m["dispatches"] == 2
     assert abs(m["scale_fetch"] - 2.0) < 1e-12 and abs(m["scale_write"] - 1.0) < 1e-12
     # mean fetch 200 KiB x 2 + mean write 50 KiB x 1
     assert abs(m["bytes_per_launch"] - (400.0 + 50.0) * 1024.0) < 1e-6
-    assert rec["source_sha256"] == b.pair_kernel_source_hash()
+    assert rec["k_pairs"]["source_sha256"] == b.kernel_source_hash("k_pairs")
+    # the most frequent instantiation of the neighbour search is taken
+    n = rec["k_neighbors"]["wl/mixed"]
+    assert n["kernel"] == nbr and abs(n["bytes_per_launch"] - 2020.0 * 1024.0) < 1e-6
     # the bench line takes it only while the kernel source is unchanged
-    assert b.pair_kernel_traffic("mixed") == m["bytes_per_launch"]
-    rec["source_sha256"] = "0" * 64
+    assert b.kernel_traffic("k_pairs", "wl", "mixed") == m["bytes_per_launch"]
+    assert b.kernel_traffic("k_pairs", "other", "mixed") is None
+    rec["k_pairs"]["source_sha256"] = "0" * 64
     json.dump(rec, open(b.TRAFFIC_JSON, "w"))
-    assert b.pair_kernel_traffic("mixed") is None
+    assert b.kernel_traffic("k_pairs", "wl", "mixed") is None
+
+
+def test_advance_quaternion_step():
+    """The trajectory's orientation update: q <- normalise(q + dt/2 (0,w) q)
+    turns the symmetry axis by w x axis dt to first order."""
+    import numpy as np
+    import torch
+    b = load_bench()
+    rng = np.random.default_rng(0)
+    q = rng.normal(size=(50, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w = rng.normal(scale=1e-3, size=(50, 3))
+    v = rng.normal(size=(50, 3))
+    r = rng.normal(size=(50, 3))
+    rt, qt = torch.tensor(r), torch.tensor(q)
+    b.advance(rt, qt, torch.tensor(v), torch.tensor(w), 0.5)
+    assert np.allclose(rt.numpy(), r + 0.5 * v)
+    assert np.allclose(np.linalg.norm(qt.numpy(), axis=1), 1.0)
+
+    def axis(qq):
+        w_, x, y, z = qq.T
+        return np.stack([2 * (x * z + w_ * y), 2 * (y * z - w_ * x), 1 - 2 * (x * x + y * y)], 1)
+    a0, a1 = axis(q), axis(qt.numpy())
+    # first order in |w| dt ~ 1e-3: the remainder is of order (|w| dt)^2
+    assert np.abs(a1 - a0 - 0.5 * np.cross(w, a0)).max() < 1e-5

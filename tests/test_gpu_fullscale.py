@@ -1,14 +1,17 @@
 """GPU parity at full scale: 1,048,576 polydisperse spheroids (aspect ratio
-log-uniform in [1/4, 4], R_perp in [4, 8]) between walls, checked on a 1%
-sample of particles, the part of the system the oracle can evaluate one by
-one:
+log-uniform in [1/4, 4], R_perp in [4, 8]) at volume fraction 0.5 between
+walls, placed by the growth method, checked on a 1% sample of particles,
+the part of the system the oracle can evaluate one by one:
 
 * the candidate partners of every sampled particle, bit for bit (the
   oracle's brute-force search over all particles);
 * every pair touching a sampled particle against the oracle's evaluation
   of that pair (mixed-precision bar, h/a >= 1e-3);
 * the per-particle force and torque of the sampled particles against the
-  oracle's sums (contribution-scale bar).
+  oracle's sums (contribution-scale bar);
+* a warm-started trajectory (positions and orientations advanced by one
+  time step between calls): the pairs touching the sample at its last step
+  against the oracle at that step.
 """
 import numpy as np
 import pytest
@@ -87,3 +90,50 @@ def test_fullscale_sampled(ref):
         np.maximum(np.linalg.norm(to, axis=1), stq[idx]), 1e-300)
     print(f"sample particles max f={ef.max():.3e} t={et.max():.3e}")
     assert ef.max() < 1e-5 and et.max() < 1e-5
+
+
+@pytest.mark.timeout(900)
+def test_fullscale_warm_trajectory_sampled(ref):
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                  "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    wl = W.config5()
+    print(f"[gpu] warm trajectory on {wl.name}", flush=True)
+    r, q, semi, v, w = L.to_device(wl)
+    lb = L.Lub.for_workload(wl, precision=L.LUB_MIXED, warm_start=1)
+    for k in range(3):
+        lb.compute(r, q, semi, v, w)
+        st = lb.stats()
+        if k < 2:
+            bench.advance(r, q, v, w, 1.0)
+    torch.cuda.synchronize()
+    assert st["warm_seeded"] > 0.8 * (st["evaluated"] - st["wall_candidates"])
+    res = lb.pair_results()
+    lb.close()
+    rk, qk = r.cpu().numpy(), q.cpu().numpy()
+    rng = np.random.default_rng(4)
+    keep = np.zeros(wl.n, dtype=bool)
+    keep[rng.choice(wl.n, size=wl.n // 100, replace=False)] = True
+    ij = res["ij"]
+    sel = keep[ij[:, 0]] | ((ij[:, 1] >= 0) & keep[np.maximum(ij[:, 1], 0)])
+    ij = ij[sel]
+    dom = ref.make_domain(**wl.domain())
+    P = ref.make_params(**wl.params)
+    F, Ti, Tj, h, status = ref.eval_pairs(rk, qk, wl.semi, wl.v, wl.w, dom, P, ij)
+    act = status == ref.REFP_ACTIVE
+    assert np.array_equal(res["status"][sel] == 0, act)
+    i, j = ij[:, 0], ij[:, 1]
+    a = wl.semi[i].min(axis=1)
+    a = np.where(j >= 0, np.minimum(a, wl.semi[np.maximum(j, 0)].min(axis=1)), a)
+    nF = np.linalg.norm(F, axis=1)
+    gate = act & (h / a >= 1e-3)
+    eF = np.linalg.norm(res["F"][sel] - F, axis=1)[gate] / nF[gate]
+    sT = np.maximum(np.linalg.norm(Ti, axis=1), a * nF)[gate]
+    eT = np.linalg.norm(res["Ti"][sel] - Ti, axis=1)[gate] / sT
+    print(f"warm step 2: seeded {st['warm_seeded']} sample pairs={len(ij)} "
+          f"max eF={eF.max():.3e} eT={eT.max():.3e}", flush=True)
+    assert eF.max() < 1e-5 and eT.max() < 1e-5
