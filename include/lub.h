@@ -263,6 +263,41 @@ typedef struct lub_ctx* lub_handle_t;
 int lub_create(lub_handle_t* out, const lub_domain_t* domain,
                const lub_params_t* params, const lub_opts_t* opts);
 
+/* ---- allocation-free evaluation -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * correction as lub_compute (same kernels, same results) without a handle:
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); its workspace is a fixed device array of LUB_STATIC_SCRATCH_BYTES
+ * inside the library, one per GPU, held until the process ends.
+ *
+ * domain, params: as for lub_create (link-wise laws excluded).  opts: device,
+ * precision, newton_max_iter, rmax_bound and max_neighbors (<= 0: 64; at
+ * most LUB_STATIC_MAX_NEIGHBORS) are used; seed_mode must be LUB_SEED_PLAIN
+ * and warm_start, graph, timing, skin and reserved 0 (sync is ignored), else
+ * LUB_EINVAL.  Arrays as for lub_compute (device memory, f and t
+ * overwritten); n <= LUB_STATIC_MAX_PARTICLES (else LUB_EINVAL).  A call
+ * whose workspace does not fit the array (a cell grid too fine for the box,
+ * more than 8 evaluated pairs per particle) returns LUB_ECAPACITY before any
+ * launch, or sets it on the device.
+ *
+ * stats: NULL, or a host struct that receives the call's statistics: the
+ * call then waits for the stream and returns the error found on the device
+ * (input errors, capacity); with NULL the call is fully asynchronous (and
+ * may be captured into a graph) and device-side errors are not reported.
+ * Every call on one GPU uses that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialised by the caller. */
+#define LUB_STATIC_MAX_PARTICLES 16384
+#define LUB_STATIC_MAX_NEIGHBORS 128
+#define LUB_STATIC_SCRATCH_BYTES (48u << 20)
+
+int lub_compute_static(const lub_domain_t* domain, const lub_params_t* params,
+                       const lub_opts_t* opts, int64_t n, const double* r,
+                       const double* q, const double* semi, const double* v,
+                       const double* w, double* f, double* t, void* stream,
+                       lub_stats_t* stats);
+
 /* Change parameters or domain between calls (no reallocation unless the
  * cell grid grows). */
 int lub_set_params(lub_handle_t h, const lub_params_t* params);

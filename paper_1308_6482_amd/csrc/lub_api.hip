@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -713,6 +714,53 @@ int ensure_seed(lub_ctx* c) {
 
 }  // namespace
 
+// ---- allocation-free evaluation (lub_compute_static) -----------------------
+// The workspace of one such call lives in this file-scope device array: each
+// GPU that runs the call holds its own copy until the process ends.  Host
+// code never uses the array's name as an address: its device address on each
+// device is looked up once (hipGetSymbolAddress, with that device current)
+// and kept per device.
+static __device__ __align__(256) unsigned char scratch[LUB_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return LUB_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return LUB_EDEVICE;
+    g_scratch_dev[device] = p;
+  }
+  *out = (unsigned char*)g_scratch_dev[device];
+  return LUB_OK;
+}
+
+// Bump allocator over the scratch array (256-B aligned pieces).
+struct Carve {
+  unsigned char* base;
+  size_t used = 0;
+  bool ok = true;
+  template <typename T>
+  T* take(int64_t count) {
+    const size_t bytes = (sizeof(T) * (size_t)std::max<int64_t>(count, 1) + 255) & ~(size_t)255;
+    if (used + bytes > (size_t)LUB_STATIC_SCRATCH_BYTES) {
+      ok = false;
+      return nullptr;
+    }
+    T* p = (T*)(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
 extern "C" {
 
 int lub_create(lub_handle_t* out, const lub_domain_t* domain,
@@ -921,6 +969,102 @@ int compute_device(lub_handle_t h, int64_t n, const double* r, const double* q,
 }
 }  // namespace
 
+
+int lub_compute_static(const lub_domain_t* domain, const lub_params_t* params,
+                       const lub_opts_t* opts, int64_t n, const double* r, const double* q,
+                       const double* semi, const double* v, const double* w, double* f,
+                       double* t, void* stream, lub_stats_t* stats) {
+  if (!opts || n < 0 || n > LUB_STATIC_MAX_PARTICLES) return LUB_EINVAL;
+  if (n > 0 && (!r || !q || !semi || !v || !w || !f || !t)) return LUB_EINVAL;
+  int rc;
+  if ((rc = check_params(params)) || (rc = check_domain(domain))) return rc;
+  if (is_link(params->model)) return LUB_EINVAL;
+  if (!(opts->rmax_bound > 0.0) || !std::isfinite(opts->rmax_bound)) return LUB_EINVAL;
+  if (opts->precision != LUB_FP64 && opts->precision != LUB_MIXED) return LUB_EINVAL;
+  if (opts->seed_mode != LUB_SEED_PLAIN || opts->warm_start || opts->graph || opts->timing ||
+      opts->skin != 0.0 || opts->reserved != 0 || opts->host_pointers || opts->record_detail)
+    return LUB_EINVAL;
+  if (opts->max_neighbors > LUB_STATIC_MAX_NEIGHBORS) return LUB_EINVAL;
+  HIP_TRY(hipSetDevice(opts->device));
+  unsigned char* base = nullptr;
+  if ((rc = scratch_address(opts->device, &base))) return rc;
+  // a handle on the stack whose workspace points into the scratch array
+  lub_ctx c;
+  c.device = opts->device;
+  c.prm = *params;
+  c.dom = *domain;
+  c.opt = *opts;
+  c.opt.sync = 0;
+  c.cur_nbr = opts->max_neighbors > 0 ? (int32_t)((opts->max_neighbors + 63) / 64 * 64) : 64;
+  CallDesc d;
+  if ((rc = build_desc(&c, n, &d))) return rc;
+  const int64_t ncell = 2 * (int64_t)d.nc[0] * d.nc[1] * d.nc[2];
+  if (ncell > 4 * LUB_STATIC_MAX_PARTICLES + 64) return LUB_ECAPACITY;
+  const int64_t np = std::max<int64_t>(n, 1);
+  const int64_t entries = np * c.cur_nbr;
+  const int64_t work = std::min<int64_t>(entries / 2 + 2 * np + 64, 8 * np + 64);
+  Carve cv{base};
+  c.cnt_buf = cv.take<Counters>(2);
+  c.cell_id = cv.take<int32_t>(np);
+  c.sorted = cv.take<int32_t>(np);
+  c.cell_sorted = cv.take<int32_t>(np);
+  c.deg = cv.take<int32_t>(np);
+  c.scat = cv.take<int32_t>(np);
+  c.wall_slot = cv.take<int32_t>(2 * np);
+  c.rec = cv.take<PRec>(np);
+  c.recp = cv.take<PRecP>(np);
+  c.kin = cv.take<KRec>(np);
+  c.pos = cv.take<double4>(np);
+  c.stat_nbr = cv.take<int64_t>((int64_t)kStatNbrWords * nbr_blocks_max((int)np));
+  c.stat_pair = cv.take<int64_t>((int64_t)kStatPairWords * (kMaxPairBlocks + kTangentBlocks));
+  c.cell_count = cv.take<int32_t>(ncell);
+  c.cell_fill = cv.take<int32_t>(ncell);
+  c.cell_start = cv.take<int32_t>(ncell + 1);
+  c.block_sums = cv.take<int32_t>(std::max<int64_t>(ncell, np) / 1024 + 64);
+  c.nbr = cv.take<int32_t>(entries);
+  c.slot = cv.take<int32_t>(entries);
+  c.work_s = cv.take<int32_t>(work);
+  c.work_t = cv.take<int32_t>(work);
+  c.fail_list = cv.take<int32_t>(work);
+  c.out_links = cv.take<int32_t>(work);
+  c.out = cv.take<PairOut<double>>(work);
+  c.out_h = cv.take<double>(work);
+  c.out_status = cv.take<int8_t>(work);
+  c.out_iters = cv.take<uint8_t>(work);
+  if (!cv.ok) return LUB_ECAPACITY;
+  c.cap_n = np;
+  c.cap_cells = ncell;
+  c.cap_entries = entries;
+  c.cap_work = work;
+  c.cnt = c.cnt_buf;
+  // the array keeps the last call's contents: the counters and the cell
+  // counts are cleared by the reset kernel that starts the call
+  c.zeroed = false;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = run(&c, d, r, q, semi, v, w, f, t, s))) return rc;
+  if (!stats) return LUB_OK;
+  // statistics: sum the per-block rows, copy them out, wait for the stream
+  std::memset(stats, 0, sizeof(*stats));
+  Counters host{};
+  launch_stats_reduce(c.last, c.cnt, c.stat_pair, c.stat_nbr, s);
+  HIP_TRY(hipMemcpyAsync(&host, c.cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  stats->n = n;
+  stats->candidates = host.candidates;
+  stats->wall_candidates = host.wall_candidates;
+  stats->evaluated = host.work;
+  stats->active = host.active;
+  stats->overlaps = host.overlaps;
+  stats->unresolved = host.unresolved;
+  stats->unconverged = host.unconverged;
+  stats->fallbacks = host.fallbacks;
+  stats->newton_iters = host.newton_iters;
+  stats->newton_max = host.newton_max;
+  stats->error = host.error;
+  stats->max_degree = host.max_degree;
+  for (int k = 0; k < 32; ++k) stats->iter_hist[k] = host.iter_hist[k];
+  return host.error;
+}
 
 int lub_get_domain(lub_handle_t h, lub_domain_t* out) {
   if (!h || !out) return LUB_EINVAL;

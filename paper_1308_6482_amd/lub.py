@@ -23,7 +23,7 @@ EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_stats", "lub_reset_timers", "lub_get_pairs",
            "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
            "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
-           "lub_get_domain", "lub_integrate", "lub_grow",
+           "lub_get_domain", "lub_integrate", "lub_grow", "lub_compute_static",
            "lub_mlp_save", "lub_mlp_load", "lub_get_pair_detail",
            "lub_destroy", "lub_strerror"]
 LUB_MLP_PARAMS = 34948
@@ -140,6 +140,9 @@ def lib():
         L.lub_integrate.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                     C.POINTER(lub_step_t), _P]
         L.lub_grow.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(lub_grow_t), _P]
+        L.lub_compute_static.argtypes = [C.POINTER(lub_domain_t), C.POINTER(lub_params_t),
+                                         C.POINTER(lub_opts_t), C.c_int64, _P, _P, _P, _P,
+                                         _P, _P, _P, _P, C.POINTER(lub_stats_t)]
         L.lub_destroy.argtypes = [_P]
         L.lub_destroy.restype = None
         L.lub_strerror.argtypes = [C.c_int]
@@ -234,6 +237,24 @@ def lub_compute(h, r, q, semi, v, w, f, t, stream=None, check=True) -> int:
     if check:
         _check(rc, "lub_compute")
     return rc
+
+
+def lub_compute_static(domain: lub_domain_t, params: lub_params_t, opts: lub_opts_t,
+                       r, q, semi, v, w, f, t, stream=None, stats=True):
+    """The allocation-free evaluation (no handle): same arrays as
+    lub_compute.  With stats=True the call waits and returns the statistics
+    dict (raising on a device-side error); with stats=False it returns None
+    without waiting."""
+    n = r.shape[0]
+    for a, cols in ((r, 3), (q, 4), (semi, 2), (v, 3), (w, 3), (f, 3), (t, 3)):
+        if a.shape != (n, cols):
+            raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},{cols})")
+    ptrs = [_ptr(x) if n > 0 else 0 for x in (r, q, semi, v, w, f, t)]
+    st = lub_stats_t() if stats else None
+    rc = lib().lub_compute_static(C.byref(domain), C.byref(params), C.byref(opts), n, *ptrs,
+                                  _stream_handle(stream), C.byref(st) if stats else None)
+    _check(rc, "lub_compute_static")
+    return st.as_dict() if stats else None
 
 
 def lub_compute_host(h, r, q, semi, v, w, stream=None):
