@@ -904,6 +904,356 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
   }
 }
 
+// The search without Lees-Edwards images, flattened through LDS (kMode 0:
+// the full search; kMode 1: the superset of reused lists, bound widened by
+// the skin).  G lanes share a particle.  Its stencil rows are visited in
+// increasing cell order (a periodic axis's window from its smallest wrapped
+// cell, the two x parts of a row in increasing order too), so that the
+// candidates, and with them the accepted partners, come out sorted by cell
+// order: no sort.  Per chunk of G rows each lane cuts its row to the chord
+// of the sphere of radius rho and appends the particle indices of that range
+// to the group's LDS buffer; the group then tests the buffer G entries at a
+// time with the exact centre test, one candidate per lane, and writes the
+// accepted ones straight into the segment.  Owned entries then get the
+// support-function reject and their evaluation slots (one atomic per block).
+constexpr int kFlatG = 16;
+constexpr int kFlatWaves = 4;
+constexpr int kFlatBuf = 256;  // candidate indices per group
+
+// Workgroups are dealt to the eight XCDs in turn.  Renumbered so that each
+// XCD takes runs of kXcdRun consecutive blocks (particles close in cell
+// order share most stencil rows, so their candidates stay in the L2 of the
+// XCD that tests them) and the runs go round the XCDs (the work per block
+// changes along the cell order: the large particles come last).  Blocks past
+// the last whole round keep their number.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 128;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int full = nb / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+  if (b >= full) return b;
+  const int x = b % kXcds, k = b / kXcds;
+  return ((k / kXcdRun) * kXcds + x) * kXcdRun + k % kXcdRun;
+}
+
+// Row range of a stencil row along one axis, in FP32 with margins far above
+// its rounding (a row or cell too many is harmless: the exact FP64 centre
+// test decides): the distance from the centre (f from its cell's lower
+// corner) to cells o away, under-estimated.
+__device__ __forceinline__ float axis_gap_f(int o, float f, float cell) {
+  const float g = o > 0 ? (float)o * cell - f : (o < 0 ? f - (float)(o + 1) * cell : 0.0f);
+  return fmaxf(0.0f, g * (1.0f - 1e-5f) - 1e-5f * cell);
+}
+
+// the visiting order of an axis window [first, first + count): the offset
+// into the window at which the wrapped cell index is smallest
+__device__ __forceinline__ int axis_rotation(int first, int count, int nc) {
+  if (first < 0) return -first;
+  if (first + count > nc) return nc - first;
+  return 0;
+}
+
+template <int kMode>
+__global__ void __launch_bounds__(64 * kFlatWaves)
+k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
+                 const int32_t* __restrict__ orig, const int32_t* __restrict__ cell_sorted,
+                 const int32_t* __restrict__ cell_start, int32_t* __restrict__ deg,
+                 int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
+                 int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
+                 int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
+                 ListBufs lb) {
+  if (kMode == 1 && !cnt->rebuild) return;  // the lists are reused
+  constexpr int G = kFlatG;
+  constexpr int kPer = 64 / G;
+  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
+  __shared__ int32_t s_cand[kFlatWaves * kPer][kFlatBuf];
+  __shared__ int s_keep[kFlatWaves], s_upper[kFlatWaves], s_wallc[kFlatWaves];
+  __shared__ int s_base[kFlatWaves], s_deg[kFlatWaves];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int grp = lane / G;
+  const int gl = lane % G;
+  const int gbase = grp * G;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int s = (blk * kFlatWaves + wv) * kPer + grp;
+  const bool live = s < d.n;
+  const int maxn = d.max_nbr;
+  int32_t* cand = s_cand[wv * kPer + grp];
+  int32_t* seg = nbr + (size_t)(live ? s : 0) * maxn;
+  const double extra = kMode == 1 ? d.skin : 0.0;
+  int count = 0;
+  if (live) {
+    const double4 pi = pos[s];
+    const double ri[3] = {pi.x, pi.y, pi.z};
+    const double rmi = pi.w;
+    const int ngeo = d.nc[0] * d.nc[1] * d.nc[2];
+    const int c = cell_sorted[s] % ngeo;
+    const int c3[3] = {c % d.nc[0], (c / d.nc[0]) % d.nc[1], c / (d.nc[0] * d.nc[1])};
+    double f3[3];
+    for (int k = 0; k < 3; ++k) {
+      double x = ri[k];
+      if (d.periodic[k]) x = wrap_coord(x, d.L[k], d.invL[k]);
+      f3[k] = x - c3[k] * d.cell[k];
+    }
+    // the chord cut in FP32 (see axis_gap_f)
+    const float fx = (float)f3[0], fy = (float)f3[1], fz = (float)f3[2];
+    const float cellx = (float)d.cell[0], celly = (float)d.cell[1], cellz = (float)d.cell[2];
+    const float inv_cx = 1.0f / cellx;
+    int nbuf = 0;  // entries in the buffer (uniform in the group)
+    // test the buffer's entries [0, m): accepted partners go to the segment
+    auto flush = [&](int m) {
+      for (int base = 0; base < m; base += G) {
+        const int e = base + gl;
+        bool acc = false;
+        int t = -1;
+        if (e < m) {
+          t = cand[e];
+          const double4 pj = pos[t];
+          const double rj[3] = {pj.x, pj.y, pj.z};
+          acc = t != s && centre_test(ri, rj, rmi, pj.w, d, extra);
+        }
+        const unsigned long long mk = (__ballot(acc) >> gbase) & kGroupMask;
+        if (acc) {
+          const int at = count + lane_prefix(mk, gl);
+          if (at < maxn) seg[at] = t;
+        }
+        count += __popcll(mk);
+      }
+    };
+    for (int cls = 0; cls < 2; ++cls) {
+      const int32_t* cs_cls = cell_start + cls * ngeo;
+      if (cs_cls[ngeo] == cs_cls[0]) continue;  // no particle of this class
+      const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax + extra;
+      int first[3], cnt3[3], rot[3];
+      bool whole[3];
+      for (int k = 0; k < 3; ++k) {
+        const int reach = min(d.reach_max, max(1, (int)ceil(rho / d.cell[k])));
+        axis_stencil(c3[k], d.nc[k], d.periodic[k], reach, &first[k], &cnt3[k]);
+        whole[k] = d.periodic[k] && cnt3[k] == d.nc[k];
+        rot[k] = axis_rotation(first[k], cnt3[k], d.nc[k]);
+      }
+      const float rhof = (float)rho * (1.0f + 1e-5f) + 1e-5f * cellx;
+      const int nrows = cnt3[1] * cnt3[2];
+      // lane gl's row (iy, iz) = row0 + gl, advanced by G rows per chunk
+      // without divisions
+      int iy = gl % cnt3[1], iz = gl / cnt3[1];
+      const int step_y = G % cnt3[1], step_z = G / cnt3[1];
+      for (int row0 = 0; row0 < nrows; row0 += G) {
+        // lane gl's row: its cell range along x cut to the chord, as one or
+        // two index ranges in increasing order
+        int lo0 = 0, n0 = 0, lo1 = 0, n1 = 0;
+        if (row0 + gl < nrows) {
+          int ry = iy + rot[1], rz = iz + rot[2];
+          ry = ry >= cnt3[1] ? ry - cnt3[1] : ry;
+          rz = rz >= cnt3[2] ? rz - cnt3[2] : rz;
+          const int uy = first[1] + ry, uz = first[2] + rz;  // unwrapped cells
+          const float gy = whole[1] ? 0.0f : axis_gap_f(uy - c3[1], fy, celly);
+          const float gz = whole[2] ? 0.0f : axis_gap_f(uz - c3[2], fz, cellz);
+          const float rem = rhof * rhof - gy * gy - gz * gz;
+          int a0 = first[0], a1 = first[0] + cnt3[0] - 1;
+          if (!whole[0]) {
+            const float wx = sqrtf(fmaxf(rem, 0.0f)) * (1.0f + 1e-5f) + 1e-5f * cellx;
+            a0 = max(a0, c3[0] + (int)floorf((fx - wx) * inv_cx));
+            a1 = min(a1, c3[0] + (int)floorf((fx + wx) * inv_cx));
+          }
+          if (rem > 0.0f && a1 >= a0) {
+            const int nx = d.nc[0];
+            const int rowbase = (wrap_cell(uz, d.nc[2]) * d.nc[1] + wrap_cell(uy, d.nc[1])) * nx;
+            // the part wrapped to the start (smaller cells) first, then the
+            // part inside [0, nx), then the part wrapped to the end
+            int b0 = 0, b1 = -1, e0 = 0, e1 = -1;
+            const int p0 = max(a0, 0), p1 = min(a1, nx - 1);
+            if (a1 >= nx) {
+              b0 = max(a0, nx) - nx;
+              b1 = a1 - nx;
+            }
+            if (a0 < 0) {
+              e0 = a0 + nx;
+              e1 = min(a1, -1) + nx;
+            }
+            if (b1 >= b0) {
+              lo0 = cs_cls[rowbase + b0];
+              n0 = cs_cls[rowbase + b1 + 1] - lo0;
+            }
+            if (p1 >= p0) {
+              const int l = cs_cls[rowbase + p0], h = cs_cls[rowbase + p1 + 1];
+              if (n0 == 0) {
+                lo0 = l;
+                n0 = h - l;
+              } else {
+                lo1 = l;
+                n1 = h - l;
+              }
+            }
+            if (e1 >= e0) {
+              lo1 = cs_cls[rowbase + e0];
+              n1 = cs_cls[rowbase + e1 + 1] - lo1;
+            }
+          }
+        }
+        iy += step_y;
+        iz += step_z;
+        if (iy >= cnt3[1]) {
+          iy -= cnt3[1];
+          ++iz;
+        }
+        const int cn = n0 + n1;
+        int incl = cn;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+          const int y = __shfl_up(incl, o, G);
+          if (gl >= o) incl += y;
+        }
+        const int total = __shfl(incl, gbase + G - 1, 64);
+        const int excl = incl - cn;
+        if (nbuf + total > kFlatBuf) {
+          flush(nbuf);
+          nbuf = 0;
+        }
+        if (total <= kFlatBuf) {
+          // append
+          int at = nbuf + excl;
+          for (int j = 0; j < n0; ++j) cand[at + j] = lo0 + j;
+          at += n0;
+          for (int j = 0; j < n1; ++j) cand[at + j] = lo1 + j;
+          nbuf += total;
+        } else {
+          // a chunk longer than the buffer goes through it in windows (the
+          // buffer was flushed above)
+          for (int win = 0; win < total; win += kFlatBuf) {
+            const int lim = min(total - win, kFlatBuf);
+            for (int j = 0; j < cn; ++j) {
+              const int q = excl + j - win;
+              if (q >= 0 && q < lim) cand[q] = j < n0 ? lo0 + j : lo1 + (j - n0);
+            }
+            flush(lim);
+          }
+        }
+      }
+    }
+    flush(nbuf);
+  }
+  const bool overflow = live && count > maxn;
+  if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
+  const int nent = (live && !overflow) ? count : 0;
+  const int me = live ? orig[s] : 0;
+  if (kMode == 1) {
+    if (live && gl == 0) {
+      deg[s] = overflow ? -count : nent;
+      lb.ref_pos[me] = pos[s];
+      lb.inv[me] = s;
+      if (overflow) lb.state->epoch = -1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt->error) lb.state->epoch = -1;
+    return;
+  }
+  // owned entries (smaller input index) are evaluated unless the support
+  // functions along the line of centres bound the gap above every cut-off;
+  // bit k of `kept`: entry gl + G k is kept
+  int nkeep = 0, nupper = 0, nwallc = 0, wall_keep = 0;
+  unsigned kept = 0u;
+  double rs[3] = {0, 0, 0};
+  const double* Mi = live ? rec[s].M : nullptr;
+  if (live) {
+    for (int k = 0; k < 3; ++k) rs[k] = rec[s].r[k];
+  }
+  int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
+  for (int k = 0, e = gl; e < nent; ++k, e += G) {
+    const int key = seg[e];
+    if (orig[key] > me) {
+      ++nupper;
+      const PRec& B = rec[key];
+      double dv[3];
+      pair_image(d, rs, B.r, dv);
+      const double dx = dv[0], dy = dv[1], dz = dv[2];
+      const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+      bool keep = true;
+      if (dn > 0.0) {
+        const double idn = 1.0 / dn;
+        const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
+        const double g = dn - support(Mi, ux, uy, uz) - support(B.M, ux, uy, uz);
+        keep = g < d.dmax;
+      }
+      sl[e] = -1;
+      if (keep) {
+        kept |= 1u << k;
+        ++nkeep;
+      }
+    } else {
+      sl[e] = -2;
+    }
+  }
+  if (live && d.n_walls && gl < 2) {
+    const int side = gl;
+    const double dist = side == 0 ? rs[2] : d.L[2] - rs[2];
+    const bool cand_w = (dist - rec[s].Rmax) < d.dmax;
+    const bool keep = cand_w && (dist - sqrt(Mi[5])) < d.dmax;
+    nwallc += cand_w;
+    wall_keep = keep;
+    nkeep += keep;
+    // -3: candidate beyond every cut-off, -1: no candidate
+    wall_slot[2 * s + side] = keep ? 0 : (cand_w ? -3 : -1);
+  }
+  if (live && gl == 0) deg[s] = nent;
+  // wave totals -> block total -> one atomic per block
+  int wkeep = nkeep, wup = nupper, wwall = nwallc;
+  int wdeg = live ? count : 0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    wkeep += __shfl_xor(wkeep, o, 64);
+    wup += __shfl_xor(wup, o, 64);
+    wwall += __shfl_xor(wwall, o, 64);
+    wdeg = max(wdeg, __shfl_xor(wdeg, o, 64));
+  }
+  if (lane == 0) {
+    s_keep[wv] = wkeep;
+    s_upper[wv] = wup;
+    s_wallc[wv] = wwall;
+    s_deg[wv] = wdeg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0, up = 0, wc = 0, dg = 0;
+    for (int k = 0; k < kFlatWaves; ++k) {
+      s_base[k] = tot;
+      tot += s_keep[k];
+      up += s_upper[k];
+      wc += s_wallc[k];
+      dg = max(dg, s_deg[k]);
+    }
+    const int b = tot ? atomicAdd(&cnt->work, tot) : 0;
+    if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
+    for (int k = 0; k < kFlatWaves; ++k) s_base[k] += b;
+    stat_nbr[kStatNbrWords * blk] = up;
+    stat_nbr[kStatNbrWords * blk + 1] = wc;
+    stat_nbr[kStatNbrWords * blk + 2] = dg;
+    s_keep[0] = b + tot <= d.cap_work;
+  }
+  __syncthreads();
+  const bool fits = s_keep[0] != 0;
+  // slots in lane order: exclusive prefix of nkeep across the wave
+  int incl2 = nkeep;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl2, o, 64);
+    if (lane >= o) incl2 += y;
+  }
+  if (!live || !fits) return;
+  int next = s_base[wv] + incl2 - nkeep;
+  for (int k = 0, e = gl; e < nent; ++k, e += G) {
+    if (!((kept >> k) & 1u)) continue;
+    sl[e] = next;
+    work_s[next] = s;
+    work_t[next] = seg[e];
+    ++next;
+  }
+  if (d.n_walls && gl < 2 && wall_keep) {
+    wall_slot[2 * s + gl] = next;
+    work_s[next] = s;
+    work_t[next] = -1 - gl;
+    ++next;
+  }
+}
+
 }  // namespace
 
 void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
@@ -977,6 +1327,9 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
 }
 
 int nbr_waves(const CallDesc& d);  // wavefronts per block of the neighbour kernel
+int nbr_blocks_group(const CallDesc& d);
+bool nbr_flat(const CallDesc& d);
+int nbr_blocks_flat(const CallDesc& d);
 
 template <int G, int W>
 void launch_nbr_mode(int mode, dim3 grid, size_t lds, hipStream_t s, const CallDesc& d,
@@ -1022,7 +1375,19 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            Counters* cnt, hipStream_t s, int mode, const ListBufs* lists) {
   const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
-  dim3 grid(nbr_blocks(d));
+  if (mode != 2 && nbr_flat(d)) {
+    const dim3 grid_f(nbr_blocks_flat(d)), block_f(64 * kFlatWaves);
+    if (mode == 0)
+      hipLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, d, rec, pos, orig,
+                         cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                         stat_nbr, cnt, lb);
+    else
+      hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, pos, orig,
+                         cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                         stat_nbr, cnt, lb);
+    return;
+  }
+  dim3 grid(nbr_blocks_group(d));
   size_t lds = sizeof(int32_t) * 64 * nbr_waves(d) / nbr_group(d) * (size_t)d.max_nbr;
   if (mode == 2 && lists && lists->work_sup) lds *= 2;  // the superset positions too
   if (nbr_group(d) == 16)
@@ -1154,9 +1519,27 @@ int nbr_waves(const CallDesc& d) {
   return d.n >= (1 << 14) && !(d.skin > 0.0) ? kWavesLarge : kWavesSmall;
 }
 
-int nbr_blocks(const CallDesc& d) {
+// blocks of the lane-group kernel (the filter of reused lists, Lees-Edwards
+// images)
+int nbr_blocks_group(const CallDesc& d) {
   const int per_block = nbr_waves(d) * 64 / nbr_group(d);
   return (d.n + per_block - 1) / per_block;
+}
+
+// blocks of the flattened search
+int nbr_blocks_flat(const CallDesc& d) {
+  constexpr int per_block = kFlatWaves * 64 / kFlatG;
+  return (d.n + per_block - 1) / per_block;
+}
+
+// the search and the superset of reused lists without Lees-Edwards images
+// go through the flattened kernel
+bool nbr_flat(const CallDesc& d) { return !d.le; }
+
+// blocks of the kernel that writes a call's statistics rows: the filter of
+// reused lists, the Lees-Edwards search, else the flattened search
+int nbr_blocks(const CallDesc& d) {
+  return d.skin > 0.0 || !nbr_flat(d) ? nbr_blocks_group(d) : nbr_blocks_flat(d);
 }
 
 // at least one particle per wavefront, at most kWavesLarge wavefronts
