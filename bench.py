@@ -86,6 +86,9 @@ def parse():
                     help="no GPU work: read two rocprofv3 --pmc runs of this script with "
                          "--calibrate-copy (FETCH_SIZE, then WRITE_SIZE), scale each by the "
                          "copy kernel's reading and write profiles/kernel_traffic.json")
+    ap.add_argument("--heldout-pairs", type=int, default=1 << 18,
+                    help="the learned seed's held-out pairs (oracle-labelled) evaluated "
+                         "with both starts (part of the oracle leg; 0: skip)")
     ap.add_argument("--train-pairs", type=int, default=1 << 21)
     ap.add_argument("--train-epochs", type=int, default=6)
     return ap.parse_args()
@@ -528,6 +531,54 @@ def pair_errors(wl, r, q, pairs, ref, dom, P):
                 max_abs_err_gap_over_a=float(eh.max()) if eh.size else 0.0)
 
 
+def heldout_leg(L, torch, theta, prec, m):
+    """The learned seed's held-out evaluation: m pairs placed by the oracle at
+    gaps log-uniform in [1e-4, 1] of the smallest semi-axis (labels: the
+    oracle's closest points), evaluated by the library as isolated pairs with
+    the plain and the learned start (cut-offs widened so that every pair is
+    solved): Newton iteration p50/p99, fallbacks, and |dh|/h, |dy*|/a
+    against the labels."""
+    import numpy as np
+    from oracle import seed_pairs as SP
+    from paper_1308_6482_amd import workloads as W
+    t0 = time.perf_counter()
+    P = SP.labelled_pairs(2, m)
+    t_label = time.perf_counter() - t0
+    ok = np.flatnonzero(P["status"] == 0)
+    wl = W.pair_lattice(P["q_i"][ok], P["semi_i"][ok], P["q_j"][ok], P["semi_j"][ok],
+                        P["d"][ok], name=f"heldout{m}")
+    wl = wl.with_params(delta_n=10.0, delta_t=10.0, delta_r=10.0)
+    a = np.minimum(P["semi_i"][ok].min(axis=1), P["semi_j"][ok].min(axis=1))
+    out = dict(pairs=int(m), placed=int(ok.size), label_s=t_label)
+    for form, th in (("plain", None), ("mlp", theta)):
+        if form == "mlp" and th is None:
+            continue
+        lb = make_handle(L, wl, prec, 64, th, sync=1, record_detail=1)
+        lb.compute(*L.to_device(wl))
+        st = lb.stats()
+        pr = lb.pair_results()
+        dt = lb.pair_detail()
+        lb.close()
+        k = pr["ij"][:, 0] // 2
+        it = pr["iters"]
+        hist = np.bincount(np.minimum(it, 31), minlength=32)
+        cdf = np.cumsum(hist) / max(hist.sum(), 1)
+        solved = pr["status"] != 3
+        dh = np.abs(pr["h"] - P["h"][ok][k]) / P["h"][ok][k]
+        dyi = np.linalg.norm(dt["yi"] - P["yi"][ok][k], axis=1) / a[k]
+        dyj = np.linalg.norm(dt["yj"] - P["yj"][ok][k], axis=1) / a[k]
+        out[form] = dict(evaluated=int(len(k)), unconverged=int(st["unconverged"]),
+                         fallbacks=int(st["fallbacks"]),
+                         fallback_rate=float(st["fallbacks"] / max(len(k), 1)),
+                         newton_iters_mean=float(it.mean()),
+                         newton_iters_p50=int(np.searchsorted(cdf, 0.5)),
+                         newton_iters_p99=int(np.searchsorted(cdf, 0.99)),
+                         newton_max=int(it.max()), iter_hist=[int(x) for x in hist],
+                         max_rel_err_h=float(dh[solved].max()),
+                         max_err_y_over_a=float(max(dyi[solved].max(), dyj[solved].max())))
+    return out
+
+
 def cpu_leg(wl, snaps_by_form, seconds, det=None):
     """The FP64 oracle on the host cores: its pairs/s on the pairs the GPU
     evaluated around the particle sample at the first step (1 thread and all
@@ -744,7 +795,17 @@ def main():
 
     theta, mlp_report = None, None
     if args.seed in ("mlp", "both"):
-        theta, mlp_report = train_seed(L, torch, args.train_pairs, args.train_epochs)
+        from paper_1308_6482_amd import train_seed as TS
+        theta, rec = TS.load_weights()
+        if theta is not None:
+            # trained on oracle-labelled pairs by train_seed.py (GPU); the
+            # bench times a short training run of the same kernels beside
+            _, speed = train_seed(L, torch, 1 << 18, 2)
+            mlp_report = dict(weights="paper_1308_6482_amd/data/seed_weights.npz", training=rec,
+                              training_speed_check=speed)
+        else:
+            theta, mlp_report = train_seed(L, torch, args.train_pairs, args.train_epochs)
+            mlp_report["weights"] = "trained here on constructed pairs (no committed weights)"
     forms, snaps, windows = {}, {}, {}
     if args.seed in ("plain", "both"):
         forms["plain"], snaps["plain"], windows["plain"] = measure_form(
@@ -827,6 +888,8 @@ def main():
     if args.cpu_seconds > 0:
         det = detail_snapshot(L, torch, wl, prec, cap, sample)
         base, acc = cpu_leg(wl, snaps, args.cpu_seconds, det)
+        if args.heldout_pairs > 0:
+            res["heldout"] = heldout_leg(L, torch, theta, prec, args.heldout_pairs)
         res["cpu_baseline"] = base
         res["accuracy"] = acc
     print(json.dumps(res), flush=True)

@@ -168,3 +168,18 @@ def seed_normal(Y, semi_i, semi_j, Fi, Fj):
     ni = normal(Y[:, 0], Y[:, 1], semi_i, Fi)
     nj = normal(Y[:, 2], Y[:, 3], semi_j, Fj)
     return _unit(ni - nj)
+
+
+def labelled_features(P) -> dict:
+    """Features X (m,10) and targets T (m,6) of pairs labelled elsewhere (the
+    oracle's closest points): P holds q_i, q_j, semi_i, semi_j, the centre
+    offset d (or u and the separation s) and the closest points yi, yj
+    relative to each centre."""
+    d = P["d"] if "d" in P else P["s"][:, None] * P["u"]
+    axis_i = W.symmetry_axes(P["q_i"])
+    axis_j = W.symmetry_axes(P["q_j"])
+    X, Fi, Fj = features(d, axis_i, P["semi_i"], axis_j, P["semi_j"])
+    rp = P["semi_i"][:, 1][:, None]
+    T = np.concatenate([np.sum(Fi * P["yi"][:, None, :], axis=2) / rp,
+                        np.sum(Fj * P["yj"][:, None, :], axis=2) / rp], axis=1)
+    return dict(X=X.astype(np.float32), T=T.astype(np.float32), d=d)

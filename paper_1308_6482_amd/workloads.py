@@ -464,3 +464,35 @@ def config4_pair_inputs(seed: int, m: int, lam=(1.0 / 3.0, 3.0), rperp=(3.0, 8.0
     a = np.minimum(semi_i.min(axis=1), semi_j.min(axis=1))
     target = a * np.exp(g_gap.uniform(np.log(gap[0]), np.log(gap[1]), size=m))
     return dict(q_i=q_i, q_j=q_j, semi_i=semi_i, semi_j=semi_j, u=u, target=target)
+
+
+def pair_lattice(q_i, semi_i, q_j, semi_j, d, spacing: float | None = None,
+                 name: str = "pairs") -> Workload:
+    """Isolated pairs as one system, so that the library evaluates them
+    with its ordinary call: pair k's particle i sits on site k of a cubic
+    lattice and its particle j at that site + d[k]; the spacing keeps every
+    particle of one pair beyond the pruning bound of every particle of
+    another.  Particle 2k is i, 2k + 1 is j of pair k; no walls, no periodic
+    axes; zero velocities; h_c = eps_c = 0."""
+    m = d.shape[0]
+    rmax = max(float(semi_i.max()), float(semi_j.max()))
+    reach = float(np.linalg.norm(d, axis=1).max()) + 2.0 * rmax
+    spacing = spacing or 2.0 * reach + 2.0
+    side = int(np.ceil(m ** (1.0 / 3.0)))
+    k = np.arange(m)
+    sites = spacing * (np.stack([k % side, (k // side) % side, k // (side * side)], 1) + 0.5)
+    r = np.empty((2 * m, 3))
+    r[0::2] = sites
+    r[1::2] = sites + d
+    q = np.empty((2 * m, 4))
+    q[0::2] = q_i
+    q[1::2] = q_j
+    semi = np.empty((2 * m, 2))
+    semi[0::2] = semi_i
+    semi[1::2] = semi_j
+    L = side * spacing + spacing
+    z = np.zeros((2 * m, 3))
+    return Workload(name, r, q, semi, z, z.copy(), (L, L, L), (0, 0, 0),
+                    params=dict(mu=MU, delta_n=DELTA_N, delta_t=DELTA_T, delta_r=DELTA_R,
+                                h_c=0.0, eps_c=0.0),
+                    meta=dict(pairs=m, spacing=spacing))

@@ -228,3 +228,42 @@ def test_checkpoint_roundtrip():
         L.lub_mlp_load(b.h, bad)
     a.close()
     b.close()
+
+
+def test_heldout_pairs_against_oracle_labels():
+    """Isolated oracle-labelled pairs (the learned seed's held-out recipe)
+    through the library's ordinary call (a lattice of pairs): the gap and the
+    closest points equal the oracle's labels at the FP64 bar, with the plain
+    and with the learned start (committed weights when present, else a
+    random network: the plain start then takes over)."""
+    from oracle import seed_pairs as SP
+    from paper_1308_6482_amd import train_seed as TS
+    print("[gpu] held-out pairs vs oracle labels", flush=True)
+    P = SP.labelled_pairs(2, 4096)
+    ok = P["status"] == 0
+    assert ok.all()
+    wl = W.pair_lattice(P["q_i"], P["semi_i"], P["q_j"], P["semi_j"], P["d"])
+    wl = wl.with_params(delta_n=10.0, delta_t=10.0, delta_r=10.0)
+    a = np.minimum(P["semi_i"].min(axis=1), P["semi_j"].min(axis=1))
+    theta, _ = TS.load_weights()
+    res = {}
+    for mode in (L.LUB_SEED_PLAIN, L.LUB_SEED_MLP):
+        lb = L.Lub.for_workload(wl, precision=L.LUB_FP64, seed_mode=mode, record_detail=1)
+        if mode == L.LUB_SEED_MLP and theta is not None:
+            L.lub_mlp_set_weights(lb.h, theta)
+        lb.compute(*L.to_device(wl))
+        torch.cuda.synchronize()
+        st, pr, dt = lb.stats(), lb.pair_results(), lb.pair_detail()
+        lb.close()
+        assert st["evaluated"] == 4096 and st["unconverged"] == 0
+        k = pr["ij"][:, 0] // 2
+        assert np.array_equal(pr["ij"][:, 1], pr["ij"][:, 0] + 1)
+        eh = np.abs(pr["h"] - P["h"][k]) / a[k]
+        ey = np.maximum(np.linalg.norm(dt["yi"] - P["yi"][k], axis=1),
+                        np.linalg.norm(dt["yj"] - P["yj"][k], axis=1)) / a[k]
+        print(f"mode {mode}: iterations {st['newton_iters'] / 4096:.2f} fallbacks "
+              f"{st['fallbacks']} max |dh|/a {eh.max():.1e} |dy|/a {ey.max():.1e}")
+        assert eh.max() <= 1e-9 and ey.max() <= 1e-9
+        res[mode] = st
+    if theta is not None:
+        assert res[L.LUB_SEED_MLP]["newton_iters"] < res[L.LUB_SEED_PLAIN]["newton_iters"]
