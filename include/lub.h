@@ -65,8 +65,9 @@ extern "C" {
 #define LUB_EDEVICE -5    /* HIP runtime error */
 
 #define LUB_FP64 0        /* every step in double precision */
-#define LUB_MIXED 1       /* FP64 closest-point solve, gap and ln h / 1/h terms; */
-                          /* FP32 geometry, resistance and transfer */
+#define LUB_MIXED 1       /* FP64 closest-point solve, gap, surface geometry and */
+                          /* ln h / 1/h terms; FP32 resistance coefficients, */
+                          /* 6x6 product and transfer */
 
 #define LUB_SEED_PLAIN 0  /* Newton started from the line of centres */
 #define LUB_SEED_MLP 1    /* Newton started from the learned predictor */

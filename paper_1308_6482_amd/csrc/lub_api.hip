@@ -64,6 +64,8 @@ struct lub_ctx {
   int64_t warm_size = 0;           // entries per table, a power of 2
   int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
   int32_t* deg = nullptr;          // [n] entries per segment
+  int32_t* bcount = nullptr;       // [2n + 2] forward search: backward entries, slot
+                                   // offsets, their int64 total
   int32_t* block_sums = nullptr;   // scan scratch
   int32_t* wall_slot = nullptr;    // [2n]
   PRec* rec = nullptr;             // [n]
@@ -225,6 +227,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
   c->cap_n = 0;
   if ((rc = realloc_buf(&c->cell_id, need)) || (rc = realloc_buf(&c->sorted, need)) ||
       (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
+      (rc = realloc_buf(&c->bcount, 2 * need + 2)) ||
       (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->recp, need)) || (rc = realloc_buf(&c->kin, need)) ||
       (rc = realloc_buf(&c->pos, need)) ||
       (rc = realloc_buf(&c->scat, need)) ||
@@ -499,7 +502,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->recp, c->pos,
                          c->kin, c->cell_sorted, c->cnt, gate, s);
     } else {
-      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s);
+      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s, c->bcount);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
                           c->cell_count, ncell, gate, s);
@@ -521,7 +524,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     } else {
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
-                            c->work_t, c->stat_nbr, c->cnt, s);
+                            c->work_t, c->stat_nbr, c->cnt, s, 0, nullptr, c->bcount,
+                            c->block_sums);
       c->list_builds++;
     }
     mark(2);
@@ -1472,7 +1476,7 @@ void lub_destroy(lub_handle_t h) {
   hipSetDevice(h->device);
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
-                  h->sorted, h->cell_sorted, h->deg, h->block_sums,
+                  h->sorted, h->cell_sorted, h->deg, h->bcount, h->block_sums,
                   h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
                   h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,

@@ -185,10 +185,12 @@ void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
                   int ncell, hipStream_t s);
 // The cell-build launchers take `gate`: null, or this call's counters, whose
 // `rebuild` flag (set on the device) turns the kernels into no-ops when the
-// neighbour lists are reused.
+// neighbour lists are reused.  The binning also zeroes `bcount` (2 n
+// entries) when given.
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, const Counters* gate, hipStream_t s);
+                      Counters* cnt, const Counters* gate, hipStream_t s,
+                      int32_t* bcount = nullptr);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
                  int64_t* total, hipStream_t s);
 // scatter into the cells' ranges (arbitrary order); zeroes cell_count
@@ -218,7 +220,11 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode = 0,
-                           const ListBufs* lists = nullptr);
+                           const ListBufs* lists = nullptr, int32_t* bcount = nullptr,
+                           int32_t* block_sums = nullptr);
+// (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,
+// and block_sums, scan scratch for n entries; given, the full search of
+// large systems runs as a forward search, a scan and a merge)
 // reused neighbour lists: the displacement plus growth since the search
 // (skipped unless the lists are of this epoch), then the decision (a
 // search if the lists are of another epoch or the measure exceeds half the

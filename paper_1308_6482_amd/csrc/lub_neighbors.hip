@@ -166,10 +166,14 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
                             const double* __restrict__ semi,
                             int32_t* __restrict__ cell_id,
                             int32_t* __restrict__ cell_count, Counters* cnt,
-                            const Counters* gate) {
+                            const Counters* gate, int32_t* __restrict__ bcount) {
   if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
+  if (bcount) {  // backward counts and kept pairs of the forward search
+    bcount[p] = 0;
+    bcount[d.n + p] = 0;
+  }
   const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
   int c = validate_bin(d, load_input(r, q, semi, p), inv_cell, cnt);
   cell_id[p] = c;
@@ -916,9 +920,26 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
 // time with the exact centre test, one candidate per lane, and writes the
 // accepted ones straight into the segment.  Owned entries then get the
 // support-function reject and their evaluation slots (one atomic per block).
+// kMode kFwd, the forward search of large systems: each pair is tested once,
+// by the particle that comes first in cell order (its own class's rows from
+// its own row on, the ranges cut to later indices, and the later class);
+// the particle is appended to each partner's segment through an atomic
+// count, and k_nbr_merge sorts those backward entries in front of the
+// forward ones.  Half the rows and half the centre tests of the full search.
 constexpr int kFlatG = 16;
 constexpr int kFlatWaves = 4;
 constexpr int kFlatBuf = 256;  // candidate indices per group
+constexpr int kFwd = 3;        // mode of the forward search (partners later in cell order)
+// the forward search and merge from this many particles, with segments of
+// at most kFwdMaxNbr entries (LDS of the merge: 2 x 16 x 4 B per entry)
+constexpr int kFwdMinN = 1 << 15;
+constexpr int kFwdMaxNbr = 256;
+// the forward search hands the merge each entry with two flags above the
+// partner index: this segment's particle evaluates the pair (smaller input
+// index), and the support-function bound lets the pair through
+constexpr int32_t kOwnBit = 1 << 29;
+constexpr int32_t kKeepBit = 1 << 30;
+constexpr int32_t kIndexMask = kOwnBit - 1;
 
 // Workgroups are dealt to the eight XCDs in turn.  Renumbered so that each
 // XCD takes runs of kXcdRun consecutive blocks (particles close in cell
@@ -952,6 +973,131 @@ __device__ __forceinline__ int axis_rotation(int first, int count, int nc) {
   return 0;
 }
 
+// The end of the full search: owned entries (smaller input index) are
+// evaluated unless the support functions along the line of centres bound
+// the gap above every cut-off; wall candidates; the block's statistics row
+// and one atomic per block for its evaluation slots, assigned in lane order.
+// keys: the particle's segment (nent entries); need: its length before an
+// overflow cut it.  Every thread of the block calls it.
+__device__ __forceinline__ void evaluation_slots(
+    const CallDesc& d, const PRec* __restrict__ rec, const int32_t* __restrict__ orig,
+    int blk, int s, bool live, int need, int nent, const int32_t* keys,
+    int32_t* __restrict__ deg, int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
+    int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
+    int64_t* __restrict__ stat_nbr, Counters* cnt, int* s_keep, int* s_upper, int* s_wallc,
+    int* s_base, int* s_deg) {
+  constexpr int G = kFlatG;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int gl = lane % G;
+  const int maxn = d.max_nbr;
+  const int me = live ? orig[s] : 0;
+  // bit k of `kept`: entry gl + G k is kept
+  int nkeep = 0, nupper = 0, nwallc = 0, wall_keep = 0;
+  unsigned kept = 0u;
+  double rs[3] = {0, 0, 0};
+  const double* Mi = live ? rec[s].M : nullptr;
+  if (live) {
+    for (int k = 0; k < 3; ++k) rs[k] = rec[s].r[k];
+  }
+  int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
+  for (int k = 0, e = gl; e < nent; ++k, e += G) {
+    const int key = keys[e];
+    if (orig[key] > me) {
+      ++nupper;
+      const PRec& B = rec[key];
+      double dv[3];
+      pair_image(d, rs, B.r, dv);
+      const double dx = dv[0], dy = dv[1], dz = dv[2];
+      const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+      bool keep = true;
+      if (dn > 0.0) {
+        const double idn = 1.0 / dn;
+        const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
+        const double g = dn - support(Mi, ux, uy, uz) - support(B.M, ux, uy, uz);
+        keep = g < d.dmax;
+      }
+      sl[e] = -1;
+      if (keep) {
+        kept |= 1u << k;
+        ++nkeep;
+      }
+    } else {
+      sl[e] = -2;
+    }
+  }
+  if (live && d.n_walls && gl < 2) {
+    const int side = gl;
+    const double dist = side == 0 ? rs[2] : d.L[2] - rs[2];
+    const bool cand_w = (dist - rec[s].Rmax) < d.dmax;
+    const bool keep = cand_w && (dist - sqrt(Mi[5])) < d.dmax;
+    nwallc += cand_w;
+    wall_keep = keep;
+    nkeep += keep;
+    // -3: candidate beyond every cut-off, -1: no candidate
+    wall_slot[2 * s + side] = keep ? 0 : (cand_w ? -3 : -1);
+  }
+  if (live && gl == 0) deg[s] = nent;
+  // wave totals -> block total -> one atomic per block
+  int wkeep = nkeep, wup = nupper, wwall = nwallc;
+  int wdeg = live ? need : 0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    wkeep += __shfl_xor(wkeep, o, 64);
+    wup += __shfl_xor(wup, o, 64);
+    wwall += __shfl_xor(wwall, o, 64);
+    wdeg = max(wdeg, __shfl_xor(wdeg, o, 64));
+  }
+  if (lane == 0) {
+    s_keep[wv] = wkeep;
+    s_upper[wv] = wup;
+    s_wallc[wv] = wwall;
+    s_deg[wv] = wdeg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0, up = 0, wc = 0, dg = 0;
+    for (int k = 0; k < kFlatWaves; ++k) {
+      s_base[k] = tot;
+      tot += s_keep[k];
+      up += s_upper[k];
+      wc += s_wallc[k];
+      dg = max(dg, s_deg[k]);
+    }
+    const int b = tot ? atomicAdd(&cnt->work, tot) : 0;
+    if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
+    for (int k = 0; k < kFlatWaves; ++k) s_base[k] += b;
+    stat_nbr[kStatNbrWords * blk] = up;
+    stat_nbr[kStatNbrWords * blk + 1] = wc;
+    stat_nbr[kStatNbrWords * blk + 2] = dg;
+    s_keep[0] = b + tot <= d.cap_work;
+  }
+  __syncthreads();
+  const bool fits = s_keep[0] != 0;
+  // slots in lane order: exclusive prefix of nkeep across the wave
+  int incl2 = nkeep;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl2, o, 64);
+    if (lane >= o) incl2 += y;
+  }
+  if (!live || !fits) return;
+  int next = s_base[wv] + incl2 - nkeep;
+  for (int k = 0, e = gl; e < nent; ++k, e += G) {
+    if (!((kept >> k) & 1u)) continue;
+    sl[e] = next;
+    work_s[next] = s;
+    work_t[next] = keys[e];
+    ++next;
+  }
+  if (d.n_walls && gl < 2 && wall_keep) {
+    wall_slot[2 * s + gl] = next;
+    work_s[next] = s;
+    work_t[next] = -1 - gl;
+    ++next;
+  }
+}
+
 template <int kMode>
 __global__ void __launch_bounds__(64 * kFlatWaves)
 k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
@@ -960,12 +1106,14 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
                  int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
                  int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
                  int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
-                 ListBufs lb) {
+                 ListBufs lb, int32_t* __restrict__ bcount) {
   if (kMode == 1 && !cnt->rebuild) return;  // the lists are reused
   constexpr int G = kFlatG;
   constexpr int kPer = 64 / G;
   constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
   __shared__ int32_t s_cand[kFlatWaves * kPer][kFlatBuf];
+  // the forward search keeps its accepted partners here (max_nbr per group)
+  extern __shared__ int32_t s_fwd[];
   __shared__ int s_keep[kFlatWaves], s_upper[kFlatWaves], s_wallc[kFlatWaves];
   __shared__ int s_base[kFlatWaves], s_deg[kFlatWaves];
   const int lane = threadIdx.x & 63;
@@ -978,7 +1126,8 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   const bool live = s < d.n;
   const int maxn = d.max_nbr;
   int32_t* cand = s_cand[wv * kPer + grp];
-  int32_t* seg = nbr + (size_t)(live ? s : 0) * maxn;
+  int32_t* seg = kMode == kFwd ? s_fwd + (size_t)(wv * kPer + grp) * maxn
+                               : nbr + (size_t)(live ? s : 0) * maxn;
   const double extra = kMode == 1 ? d.skin : 0.0;
   int count = 0;
   if (live) {
@@ -1019,7 +1168,10 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
         count += __popcll(mk);
       }
     };
-    for (int cls = 0; cls < 2; ++cls) {
+    // the forward search: partners later in cell order only (a class before
+    // this particle's holds none)
+    const int cls_s = s >= cell_start[ngeo] ? 1 : 0;
+    for (int cls = kMode == kFwd ? cls_s : 0; cls < 2; ++cls) {
       const int32_t* cs_cls = cell_start + cls * ngeo;
       if (cs_cls[ngeo] == cs_cls[0]) continue;  // no particle of this class
       const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax + extra;
@@ -1033,11 +1185,22 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       }
       const float rhof = (float)rho * (1.0f + 1e-5f) + 1e-5f * cellx;
       const int nrows = cnt3[1] * cnt3[2];
+      // the forward search in this particle's own class starts at its own
+      // row: the rows before it (in increasing cell order) hold smaller
+      // indices only, the rows after it larger ones, and in its own row
+      // the ranges are cut to indices above s
+      const bool own = kMode == kFwd && cls == cls_s;
+      int row_start = 0;
+      if (own) {
+        const int py = ((c3[1] - first[1] - rot[1]) % cnt3[1] + cnt3[1]) % cnt3[1];
+        const int pz = ((c3[2] - first[2] - rot[2]) % cnt3[2] + cnt3[2]) % cnt3[2];
+        row_start = pz * cnt3[1] + py;
+      }
       // lane gl's row (iy, iz) = row0 + gl, advanced by G rows per chunk
       // without divisions
-      int iy = gl % cnt3[1], iz = gl / cnt3[1];
+      int iy = (row_start + gl) % cnt3[1], iz = (row_start + gl) / cnt3[1];
       const int step_y = G % cnt3[1], step_z = G / cnt3[1];
-      for (int row0 = 0; row0 < nrows; row0 += G) {
+      for (int row0 = row_start; row0 < nrows; row0 += G) {
         // lane gl's row: its cell range along x cut to the chord, as one or
         // two index ranges in increasing order
         int lo0 = 0, n0 = 0, lo1 = 0, n1 = 0;
@@ -1090,6 +1253,14 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
             }
           }
         }
+        if (own) {
+          int h = lo0 + n0;
+          lo0 = max(lo0, s + 1);
+          n0 = max(0, h - lo0);
+          h = lo1 + n1;
+          lo1 = max(lo1, s + 1);
+          n1 = max(0, h - lo1);
+        }
         iy += step_y;
         iz += step_z;
         if (iy >= cnt3[1]) {
@@ -1135,8 +1306,70 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
   const bool overflow = live && count > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
   const int nent = (live && !overflow) ? count : 0;
-  const int me = live ? orig[s] : 0;
+  if (kMode == kFwd) {
+    // Each pair once: which side evaluates it (smaller input index) and the
+    // support-function bound along the line of centres, taken as the
+    // evaluating side would take it (same operands, same order).  The
+    // forward partners go to the slot segment (read by the merge) and this
+    // particle to each partner's segment at a place counted by bcount (the
+    // backward partners, in no particular order), both with the flags; the
+    // pairs each particle will evaluate, and its kept walls, are counted in
+    // kcnt (scanned into the merge's slot offsets).
+    if (live) {
+      int32_t* kcnt = bcount + d.n;
+      if (gl == 0) deg[s] = count;
+      const int nf = min(count, maxn);
+      const int me = orig[s];
+      const PRec& A = rec[s];
+      int32_t* srow = slot + (size_t)s * maxn;
+      int kept_own = 0;
+      for (int k = gl; k < nf; k += G) {
+        const int t = seg[k];
+        const int q = atomicAdd(&bcount[t], 1);
+        const bool own = me < orig[t];
+        const PRec& B = rec[t];
+        double dv[3];
+        if (own)
+          pair_image(d, A.r, B.r, dv);
+        else
+          pair_image(d, B.r, A.r, dv);
+        const double dx = dv[0], dy = dv[1], dz = dv[2];
+        const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+        bool keep = true;
+        if (dn > 0.0) {
+          const double idn = 1.0 / dn;
+          const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
+          const double* M1 = own ? A.M : B.M;
+          const double* M2 = own ? B.M : A.M;
+          const double g = dn - support(M1, ux, uy, uz) - support(M2, ux, uy, uz);
+          keep = g < d.dmax;
+        }
+        const int32_t fk = keep ? kKeepBit : 0;
+        srow[k] = t | (own ? kOwnBit : 0) | fk;
+        if (q < maxn) nbr[(size_t)t * maxn + q] = s | (own ? 0 : kOwnBit) | fk;
+        if (keep) {
+          if (own)
+            ++kept_own;
+          else
+            atomicAdd(&kcnt[t], 1);
+        }
+      }
+      if (d.n_walls && gl < 2) {
+        // -3: candidate beyond every cut-off, -1: no candidate, 0: kept
+        const double dist = gl == 0 ? A.r[2] : d.L[2] - A.r[2];
+        const bool cand_w = (dist - A.Rmax) < d.dmax;
+        const bool keep = cand_w && (dist - sqrt(A.M[5])) < d.dmax;
+        wall_slot[2 * s + gl] = keep ? 0 : (cand_w ? -3 : -1);
+        kept_own += keep;
+      }
+#pragma unroll
+      for (int o = G / 2; o >= 1; o >>= 1) kept_own += __shfl_xor(kept_own, o, G);
+      if (gl == 0 && kept_own) atomicAdd(&kcnt[s], kept_own);
+    }
+    return;
+  }
   if (kMode == 1) {
+    const int me = live ? orig[s] : 0;
     if (live && gl == 0) {
       deg[s] = overflow ? -count : nent;
       lb.ref_pos[me] = pos[s];
@@ -1146,111 +1379,144 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0 && cnt->error) lb.state->epoch = -1;
     return;
   }
-  // owned entries (smaller input index) are evaluated unless the support
-  // functions along the line of centres bound the gap above every cut-off;
-  // bit k of `kept`: entry gl + G k is kept
-  int nkeep = 0, nupper = 0, nwallc = 0, wall_keep = 0;
-  unsigned kept = 0u;
-  double rs[3] = {0, 0, 0};
-  const double* Mi = live ? rec[s].M : nullptr;
-  if (live) {
-    for (int k = 0; k < 3; ++k) rs[k] = rec[s].r[k];
-  }
+  evaluation_slots(d, rec, orig, blk, s, live, live ? count : 0, nent, seg, deg, slot,
+                   wall_slot, work_s, work_t, stat_nbr, cnt, s_keep, s_upper, s_wallc, s_base,
+                   s_deg);
+}
+
+// The merge of the forward search: each particle's segment is its backward
+// partners (smaller indices, written by the partners' forward searches in no
+// particular order; sorted here by rank) followed by its forward partners
+// (larger indices, already sorted).  Its evaluation slots are the range the
+// scan of kcnt gave it, in entry order, then its walls: no atomics, and the
+// slot order does not depend on the schedule.  LDS: two max_nbr buffers per
+// group.  bcount: [n] backward counts, [n] slot offsets, the int64 total.
+__global__ void __launch_bounds__(64 * kFlatWaves)
+k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict__ deg,
+            int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
+            int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
+            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt) {
+  constexpr int G = kFlatG;
+  constexpr int kPer = 64 / G;
+  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
+  extern __shared__ int4 s_merge[];  // int4: 16-B aligned rows
+  __shared__ int s_upper[kFlatWaves], s_wallc[kFlatWaves], s_deg[kFlatWaves];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int grp = lane / G;
+  const int gl = lane % G;
+  const int gbase = grp * G;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int s = (blk * kFlatWaves + wv) * kPer + grp;
+  const bool live = s < d.n;
+  const int maxn = d.max_nbr;
+  const int32_t* kbase = bcount + d.n;
+  const int64_t total = *reinterpret_cast<const int64_t*>(bcount + 2 * (size_t)d.n);
+  int32_t* tmp = reinterpret_cast<int32_t*>(s_merge) + (size_t)(wv * kPer + grp) * 2 * maxn;
+  int32_t* fin = tmp + maxn;
+  const int nb = live ? bcount[s] : 0;
+  const int nf = live ? deg[s] : 0;
+  const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
+  const bool overflow = live && need > maxn;
+  if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
+  const int nent = (live && !overflow) ? need : 0;
+  const int nbk = nent ? nb : 0, nfk = nent ? nf : 0;
+  int32_t* row = nbr + (size_t)(live ? s : 0) * maxn;
   int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
-  for (int k = 0, e = gl; e < nent; ++k, e += G) {
-    const int key = seg[e];
-    if (orig[key] > me) {
-      ++nupper;
-      const PRec& B = rec[key];
-      double dv[3];
-      pair_image(d, rs, B.r, dv);
-      const double dx = dv[0], dy = dv[1], dz = dv[2];
-      const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-      bool keep = true;
-      if (dn > 0.0) {
-        const double idn = 1.0 / dn;
-        const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
-        const double g = dn - support(Mi, ux, uy, uz) - support(B.M, ux, uy, uz);
-        keep = g < d.dmax;
+  for (int k = gl; k < nbk; k += G) tmp[k] = row[k];
+  for (int k = gl; k < nfk; k += G) fin[nbk + k] = sl[k];
+  __syncthreads();
+  for (int k = gl; k < nbk; k += G) {
+    const int raw = tmp[k];
+    const int key = raw & kIndexMask;
+    int rank = 0, m = 0;
+    for (; m + 4 <= nbk; m += 4) {
+      const int4 v = *reinterpret_cast<const int4*>(tmp + m);
+      rank += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
+              ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
+    }
+    for (; m < nbk; ++m) rank += (tmp[m] & kIndexMask) < key;
+    fin[rank] = raw;
+  }
+  __syncthreads();
+  int nupper = 0, nwallc = 0;
+  if (live) {
+    for (int k = gl; k < nent; k += G) row[k] = fin[k] & kIndexMask;
+    if (gl == 0) deg[s] = nent;
+    // slots [base, next) of this particle: kept owned entries in entry
+    // order, then its kept walls
+    const int base = kbase[s];
+    const int64_t next = s + 1 < d.n ? (int64_t)kbase[s + 1] : total;
+    int at = base;
+    for (int e0 = 0; e0 < nent; e0 += G) {
+      const int e = e0 + gl;
+      const int raw = e < nent ? fin[e] : 0;
+      const bool own = e < nent && (raw & kOwnBit);
+      const bool kp = own && (raw & kKeepBit);
+      const unsigned long long mk = (__ballot(kp) >> gbase) & kGroupMask;
+      if (e < nent) {
+        int code = own ? -1 : -2;
+        if (kp) {
+          code = at + lane_prefix(mk, gl);
+          if (code < d.cap_work) {
+            work_s[code] = s;
+            work_t[code] = raw & kIndexMask;
+          }
+        }
+        sl[e] = code;
       }
-      sl[e] = -1;
-      if (keep) {
-        kept |= 1u << k;
-        ++nkeep;
+      nupper += own;
+      at += __popcll(mk);
+    }
+    if (d.n_walls) {
+      const int w0 = wall_slot[2 * s], w1 = wall_slot[2 * s + 1];
+      if (gl == 0) nwallc = (w0 != -1) + (w1 != -1);
+      if (gl < 2 && (gl == 0 ? w0 : w1) == 0) {
+        const int code = at + (gl == 1 && w0 == 0 ? 1 : 0);
+        if (code < d.cap_work) {
+          work_s[code] = s;
+          work_t[code] = -1 - gl;
+        }
+        wall_slot[2 * s + gl] = code;
       }
-    } else {
-      sl[e] = -2;
+      at += (w0 == 0) + (w1 == 0);
+    }
+    // an overflowing segment leaves its range to harmless particle-wall
+    // slots (the call reports the overflow)
+    for (int64_t k = at + gl; k < next; k += G)
+      if (k < d.cap_work) {
+        work_s[k] = s;
+        work_t[k] = -1;
+      }
+    if (s == d.n - 1 && gl == 0) {
+      cnt->work = (int32_t)min<int64_t>(total, INT32_MAX);
+      if (total > d.cap_work) set_error(cnt, LUB_ECAPACITY);
     }
   }
-  if (live && d.n_walls && gl < 2) {
-    const int side = gl;
-    const double dist = side == 0 ? rs[2] : d.L[2] - rs[2];
-    const bool cand_w = (dist - rec[s].Rmax) < d.dmax;
-    const bool keep = cand_w && (dist - sqrt(Mi[5])) < d.dmax;
-    nwallc += cand_w;
-    wall_keep = keep;
-    nkeep += keep;
-    // -3: candidate beyond every cut-off, -1: no candidate
-    wall_slot[2 * s + side] = keep ? 0 : (cand_w ? -3 : -1);
-  }
-  if (live && gl == 0) deg[s] = nent;
-  // wave totals -> block total -> one atomic per block
-  int wkeep = nkeep, wup = nupper, wwall = nwallc;
-  int wdeg = live ? count : 0;
+  // the block's statistics row
+  int wup = nupper, wwall = nwallc, wdeg = live ? need : 0;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
-    wkeep += __shfl_xor(wkeep, o, 64);
     wup += __shfl_xor(wup, o, 64);
     wwall += __shfl_xor(wwall, o, 64);
     wdeg = max(wdeg, __shfl_xor(wdeg, o, 64));
   }
   if (lane == 0) {
-    s_keep[wv] = wkeep;
     s_upper[wv] = wup;
     s_wallc[wv] = wwall;
     s_deg[wv] = wdeg;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int tot = 0, up = 0, wc = 0, dg = 0;
+    int up = 0, wc = 0, dg = 0;
     for (int k = 0; k < kFlatWaves; ++k) {
-      s_base[k] = tot;
-      tot += s_keep[k];
       up += s_upper[k];
       wc += s_wallc[k];
       dg = max(dg, s_deg[k]);
     }
-    const int b = tot ? atomicAdd(&cnt->work, tot) : 0;
-    if (b + tot > d.cap_work) set_error(cnt, LUB_ECAPACITY);
-    for (int k = 0; k < kFlatWaves; ++k) s_base[k] += b;
     stat_nbr[kStatNbrWords * blk] = up;
     stat_nbr[kStatNbrWords * blk + 1] = wc;
     stat_nbr[kStatNbrWords * blk + 2] = dg;
-    s_keep[0] = b + tot <= d.cap_work;
-  }
-  __syncthreads();
-  const bool fits = s_keep[0] != 0;
-  // slots in lane order: exclusive prefix of nkeep across the wave
-  int incl2 = nkeep;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(incl2, o, 64);
-    if (lane >= o) incl2 += y;
-  }
-  if (!live || !fits) return;
-  int next = s_base[wv] + incl2 - nkeep;
-  for (int k = 0, e = gl; e < nent; ++k, e += G) {
-    if (!((kept >> k) & 1u)) continue;
-    sl[e] = next;
-    work_s[next] = s;
-    work_t[next] = seg[e];
-    ++next;
-  }
-  if (d.n_walls && gl < 2 && wall_keep) {
-    wall_slot[2 * s + gl] = next;
-    work_s[next] = s;
-    work_t[next] = -1 - gl;
-    ++next;
   }
 }
 
@@ -1265,10 +1531,10 @@ void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
 
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, const Counters* gate, hipStream_t s) {
+                      Counters* cnt, const Counters* gate, hipStream_t s, int32_t* bcount) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_stage_bin, dim3((d.n + 255) / 256), dim3(256), 0, s, d,
-                     r, q, semi, cell_id, cell_count, cnt, gate);
+                     r, q, semi, cell_id, cell_count, cnt, gate, bcount);
 }
 
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
@@ -1329,6 +1595,7 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
 int nbr_waves(const CallDesc& d);  // wavefronts per block of the neighbour kernel
 int nbr_blocks_group(const CallDesc& d);
 bool nbr_flat(const CallDesc& d);
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums);
 int nbr_blocks_flat(const CallDesc& d);
 
 template <int G, int W>
@@ -1372,19 +1639,31 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
-                           Counters* cnt, hipStream_t s, int mode, const ListBufs* lists) {
+                           Counters* cnt, hipStream_t s, int mode, const ListBufs* lists,
+                           int32_t* bcount, int32_t* block_sums) {
   const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
   if (mode != 2 && nbr_flat(d)) {
     const dim3 grid_f(nbr_blocks_flat(d)), block_f(64 * kFlatWaves);
-    if (mode == 0)
+    if (mode == 0 && nbr_forward(d, bcount, block_sums)) {
+      const size_t lds_f = sizeof(int32_t) * kFlatWaves * (64 / kFlatG) * (size_t)d.max_nbr;
+      hipLaunchKernelGGL(k_neighbors_flat<kFwd>, grid_f, block_f, lds_f, s, d, rec, pos, orig,
+                         cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
+                         stat_nbr, cnt, lb, bcount);
+      int32_t* kcnt = bcount + d.n;
+      launch_scan(kcnt, kcnt, d.n, block_sums,
+                  reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
+      hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, deg, nbr, slot,
+                         wall_slot, work_s, work_t, stat_nbr, cnt);
+    } else if (mode == 0) {
       hipLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, d, rec, pos, orig,
                          cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
-                         stat_nbr, cnt, lb);
-    else
+                         stat_nbr, cnt, lb, nullptr);
+    } else {
       hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, pos, orig,
                          cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
-                         stat_nbr, cnt, lb);
+                         stat_nbr, cnt, lb, nullptr);
+    }
     return;
   }
   dim3 grid(nbr_blocks_group(d));
@@ -1535,6 +1814,14 @@ int nbr_blocks_flat(const CallDesc& d) {
 // the search and the superset of reused lists without Lees-Edwards images
 // go through the flattened kernel
 bool nbr_flat(const CallDesc& d) { return !d.le; }
+
+// the full search of large systems as forward search + merge (needs the
+// backward counts, zeroed by the binning kernel)
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums) {
+  return bcount != nullptr && block_sums != nullptr && !d.le && d.n >= kFwdMinN &&
+         d.n <= kIndexMask &&
+         d.max_nbr <= kFwdMaxNbr;
+}
 
 // blocks of the kernel that writes a call's statistics rows: the filter of
 // reused lists, the Lees-Edwards search, else the flattened search
