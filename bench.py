@@ -883,6 +883,14 @@ def main():
             sec["mlp"], _ = single_eval(L, torch, w2, prec, a2, theta)
         res["prolates4096"] = dict(workload=w2.name, step="one evaluation of the same input",
                                    forms=sec)
+        w3 = W.config3()
+        a2.steps, a2.warmup = 100, 10
+        sec3 = {}
+        sec3["plain"], _ = single_eval(L, torch, w3, prec, a2)
+        if theta is not None:
+            sec3["mlp"], _ = single_eval(L, torch, w3, prec, a2, theta)
+        res["polydisperse65536"] = dict(workload=w3.name,
+                                        step="one evaluation of the same input", forms=sec3)
         res["dynamics"] = dynamics(L, torch, args)
         res["link_laws"] = link_laws(L, torch, args)
     if args.cpu_seconds > 0:

@@ -920,12 +920,14 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
 // time with the exact centre test, one candidate per lane, and writes the
 // accepted ones straight into the segment.  Owned entries then get the
 // support-function reject and their evaluation slots (one atomic per block).
-// kMode kFwd, the forward search of large systems: each pair is tested once,
-// by the particle that comes first in cell order (its own class's rows from
-// its own row on, the ranges cut to later indices, and the later class);
-// the particle is appended to each partner's segment through an atomic
-// count, and k_nbr_merge sorts those backward entries in front of the
-// forward ones.  Half the rows and half the centre tests of the full search.
+// kMode kFwd, the forward search of large systems: each pair is tested once:
+// a pair of one size class by the particle that comes first in cell order
+// (its own class's rows from its own row on, the ranges cut to later
+// indices), a small-large pair by the large particle (the small class
+// whole); the particle is appended to each partner's segment through an
+// atomic count, and k_nbr_merge merges those backward entries with the
+// forward ones.  About half the centre tests of the full search, and the
+// small particles (most of them) walk no rows of the sparse large class.
 constexpr int kFlatG = 16;
 constexpr int kFlatWaves = 4;
 constexpr int kFlatBuf = 256;  // candidate indices per group
@@ -1168,10 +1170,13 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
         count += __popcll(mk);
       }
     };
-    // the forward search: partners later in cell order only (a class before
-    // this particle's holds none)
+    // the forward search: a small particle searches its own class only,
+    // from its own row on; a large one the small class whole and its own
+    // class from its own row on (each small-large pair is found by the
+    // large particle: the small class is the dense one)
     const int cls_s = s >= cell_start[ngeo] ? 1 : 0;
-    for (int cls = kMode == kFwd ? cls_s : 0; cls < 2; ++cls) {
+    const int cls_end = kMode == kFwd && cls_s == 0 ? 1 : 2;
+    for (int cls = 0; cls < cls_end; ++cls) {
       const int32_t* cs_cls = cell_start + cls * ngeo;
       if (cs_cls[ngeo] == cs_cls[0]) continue;  // no particle of this class
       const double rho = rmi + (cls == 0 ? d.r_small : d.rmax_bound) + d.dmax + extra;
@@ -1323,24 +1328,32 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       const PRec& A = rec[s];
       int32_t* srow = slot + (size_t)s * maxn;
       int kept_own = 0;
+      double ra[3], ma[6];
+      for (int m = 0; m < 3; ++m) ra[m] = A.r[m];
+      for (int m = 0; m < 6; ++m) ma[m] = A.M[m];
       for (int k = gl; k < nf; k += G) {
         const int t = seg[k];
+        // the partner's data first, the atomic after it: its return is
+        // needed last (vector memory operations complete in order)
+        const int ot = orig[t];
+        double rb[3], mb[6];
+        for (int m = 0; m < 3; ++m) rb[m] = rec[t].r[m];
+        for (int m = 0; m < 6; ++m) mb[m] = rec[t].M[m];
         const int q = atomicAdd(&bcount[t], 1);
-        const bool own = me < orig[t];
-        const PRec& B = rec[t];
+        const bool own = me < ot;
         double dv[3];
         if (own)
-          pair_image(d, A.r, B.r, dv);
+          pair_image(d, ra, rb, dv);
         else
-          pair_image(d, B.r, A.r, dv);
+          pair_image(d, rb, ra, dv);
         const double dx = dv[0], dy = dv[1], dz = dv[2];
         const double dn = sqrt(dx * dx + dy * dy + dz * dz);
         bool keep = true;
         if (dn > 0.0) {
           const double idn = 1.0 / dn;
           const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
-          const double* M1 = own ? A.M : B.M;
-          const double* M2 = own ? B.M : A.M;
+          const double* M1 = own ? ma : mb;
+          const double* M2 = own ? mb : ma;
           const double g = dn - support(M1, ux, uy, uz) - support(M2, ux, uy, uz);
           keep = g < d.dmax;
         }
@@ -1356,9 +1369,9 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       }
       if (d.n_walls && gl < 2) {
         // -3: candidate beyond every cut-off, -1: no candidate, 0: kept
-        const double dist = gl == 0 ? A.r[2] : d.L[2] - A.r[2];
+        const double dist = gl == 0 ? ra[2] : d.L[2] - ra[2];
         const bool cand_w = (dist - A.Rmax) < d.dmax;
-        const bool keep = cand_w && (dist - sqrt(A.M[5])) < d.dmax;
+        const bool keep = cand_w && (dist - sqrt(ma[5])) < d.dmax;
         wall_slot[2 * s + gl] = keep ? 0 : (cand_w ? -3 : -1);
         kept_own += keep;
       }
@@ -1384,10 +1397,10 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
                    s_deg);
 }
 
-// The merge of the forward search: each particle's segment is its backward
-// partners (smaller indices, written by the partners' forward searches in no
-// particular order; sorted here by rank) followed by its forward partners
-// (larger indices, already sorted).  Its evaluation slots are the range the
+// The merge of the forward search: each particle's segment is the sorted
+// union of its backward partners (written by the partners' forward searches
+// in no particular order) and its forward partners (sorted by the walk).
+// Its evaluation slots are the range the
 // scan of kcnt gave it, in entry order, then its walls: no atomics, and the
 // slot order does not depend on the schedule.  LDS: two max_nbr buffers per
 // group.  bcount: [n] backward counts, [n] slot offsets, the int64 total.
@@ -1412,10 +1425,17 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
   const int maxn = d.max_nbr;
   const int32_t* kbase = bcount + d.n;
   const int64_t total = *reinterpret_cast<const int64_t*>(bcount + 2 * (size_t)d.n);
-  int32_t* tmp = reinterpret_cast<int32_t*>(s_merge) + (size_t)(wv * kPer + grp) * 2 * maxn;
-  int32_t* fin = tmp + maxn;
+  // stg: the backward entries (any order) then the forward ones (sorted);
+  // fin: the segment
+  int32_t* stg = reinterpret_cast<int32_t*>(s_merge) + (size_t)(wv * kPer + grp) * 2 * maxn;
+  int32_t* fin = stg + maxn;
+  // every per-particle word up front
   const int nb = live ? bcount[s] : 0;
   const int nf = live ? deg[s] : 0;
+  const int base = live ? kbase[s] : 0;
+  const int64_t next = live ? (s + 1 < d.n ? (int64_t)kbase[s + 1] : total) : 0;
+  const int w0 = live && d.n_walls ? wall_slot[2 * s] : -1;
+  const int w1 = live && d.n_walls ? wall_slot[2 * s + 1] : -1;
   const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
   const bool overflow = live && need > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
@@ -1423,20 +1443,36 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
   const int nbk = nent ? nb : 0, nfk = nent ? nf : 0;
   int32_t* row = nbr + (size_t)(live ? s : 0) * maxn;
   int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
-  for (int k = gl; k < nbk; k += G) tmp[k] = row[k];
-  for (int k = gl; k < nfk; k += G) fin[nbk + k] = sl[k];
+  for (int k = gl; k < nbk; k += G) stg[k] = row[k];
+  for (int k = gl; k < nfk; k += G) stg[nbk + k] = sl[k];
   __syncthreads();
-  for (int k = gl; k < nbk; k += G) {
-    const int raw = tmp[k];
+  // the place of each entry in the segment: the backward entries below it
+  // (counted over the unsorted ones) plus the forward entries below it (its
+  // own index in the forward list, else a binary search there)
+  for (int k = gl; k < nent; k += G) {
+    const int raw = stg[k];
     const int key = raw & kIndexMask;
-    int rank = 0, m = 0;
+    int below = 0, m = 0;
     for (; m + 4 <= nbk; m += 4) {
-      const int4 v = *reinterpret_cast<const int4*>(tmp + m);
-      rank += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
-              ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
+      const int4 v = *reinterpret_cast<const int4*>(stg + m);
+      below += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
+               ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
     }
-    for (; m < nbk; ++m) rank += (tmp[m] & kIndexMask) < key;
-    fin[rank] = raw;
+    for (; m < nbk; ++m) below += (stg[m] & kIndexMask) < key;
+    if (k >= nbk) {
+      below += k - nbk;
+    } else {
+      int lo = 0, hi = nfk;  // forward entries below key: [0, lo)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((stg[nbk + mid] & kIndexMask) < key)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      below += lo;
+    }
+    fin[below] = raw;
   }
   __syncthreads();
   int nupper = 0, nwallc = 0;
@@ -1445,8 +1481,6 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
     if (gl == 0) deg[s] = nent;
     // slots [base, next) of this particle: kept owned entries in entry
     // order, then its kept walls
-    const int base = kbase[s];
-    const int64_t next = s + 1 < d.n ? (int64_t)kbase[s + 1] : total;
     int at = base;
     for (int e0 = 0; e0 < nent; e0 += G) {
       const int e = e0 + gl;
@@ -1469,7 +1503,6 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
       at += __popcll(mk);
     }
     if (d.n_walls) {
-      const int w0 = wall_slot[2 * s], w1 = wall_slot[2 * s + 1];
       if (gl == 0) nwallc = (w0 != -1) + (w1 != -1);
       if (gl < 2 && (gl == 0 ? w0 : w1) == 0) {
         const int code = at + (gl == 1 && w0 == 0 ? 1 : 0);
