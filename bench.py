@@ -383,7 +383,8 @@ def eager_pass(L, torch, wl, prec, args, cap, theta=None, **kw):
     return dict(ms_per_step_eager=(t1 - t0) * 1e3 / args.steps,
                 stage_ms={k: v_ / n for k, v_ in zip(
                     ["cells", "neighbours", "pairs", "reduction"], st["stage_ms"])},
-                pair_kernel_ms=st["pair_kernel_ms"] / n)
+                pair_kernel_ms=st["pair_kernel_ms"] / n,
+                search_kernel_ms=st["search_kernel_ms"] / n)
 
 
 def measure_form(L, torch, wl, prec, args, cap, theta=None, sample=None, **kw):
@@ -471,7 +472,7 @@ def roofline_entries(form, stats_k, args, wl_name):
     flops_pair = (FLOPS_EVAL * ev + FLOPS_ITER * it + (post64 + post32) * act) / k
     flops_nbr = FLOPS_CAND * cand / k
     pair_ms = form["pair_kernel_ms"]
-    nbr_ms = form["stage_ms"]["neighbours"]
+    nbr_ms = form["search_kernel_ms"]
     pair = dict(bound="alu", kernel="k_pairs (main pass)", unit="TFLOP/s",
                 achieved=flops_pair / (pair_ms * 1e-3) / 1e12, peak=PEAK_ALU_TFLOPS,
                 flops_per_launch=flops_pair, launch_ms=pair_ms,
@@ -481,9 +482,10 @@ def roofline_entries(form, stats_k, args, wl_name):
     pair["frac"] = pair["achieved"] / PEAK_ALU_TFLOPS
     pair["frac_fp64"] = pair["fp64_flops_per_launch"] / (pair_ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS
     pair["frac_fp32"] = pair["fp32_flops_per_launch"] / (pair_ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS
-    nbr = dict(bound="alu", kernel="k_neighbors (neighbour-list stage)", unit="TFLOP/s",
+    nbr = dict(bound="alu", kernel="k_neighbors_flat (neighbour search walk)", unit="TFLOP/s",
                achieved=flops_nbr / (nbr_ms * 1e-3) / 1e12, peak=PEAK_ALU_TFLOPS,
                flops_per_launch=flops_nbr, launch_ms=nbr_ms,
+               stage_ms=form["stage_ms"]["neighbours"],
                traffic=kernel_traffic("k_neighbors", wl_name, args.precision))
     nbr["frac"] = nbr["achieved"] / PEAK_ALU_TFLOPS
     return pair, nbr
@@ -679,6 +681,7 @@ def single_eval(L, torch, wl, prec, args, theta=None, **kw):
                 newton_iters_mean=st["newton_iters"] / max(st["evaluated"], 1),
                 newton_max=st["newton_max"], fallbacks=st["fallbacks"],
                 pair_kernel_ms=ste["pair_kernel_ms"] / n,
+                search_kernel_ms=ste["search_kernel_ms"] / n,
                 stage_ms={k: v_ / n for k, v_ in zip(
                     ["cells", "neighbours", "pairs", "reduction"], ste["stage_ms"])}), \
         (f, t)

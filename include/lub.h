@@ -256,6 +256,10 @@ typedef struct {
   int64_t list_builds;      /* neighbour-list searches since the handle was created */
                             /* (one per call unless opts.skin > 0; with a skin, a */
                             /* search whose superset overflowed counts too) */
+  double search_kernel_ms;  /* with opts.timing: the neighbour search's own */
+                            /* execution time (dispatch timestamps; the forward walk */
+                            /* of large systems, the filter of reused lists), summed */
+                            /* like stage_ms */
 } lub_stats_t;
 
 typedef struct lub_ctx* lub_handle_t;

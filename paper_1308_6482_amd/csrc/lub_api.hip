@@ -140,6 +140,7 @@ struct lub_ctx {
   int64_t timed_calls = 0;
   double stage_ms[4] = {0, 0, 0, 0};
   double pair_kernel_ms = 0.0;
+  double search_kernel_ms = 0.0;
 };
 
 namespace {
@@ -405,6 +406,8 @@ int resolve_timing(lub_ctx* c) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[5], ev[6]));
     c->pair_kernel_ms += ms;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[7], ev[8]));
+    c->search_kernel_ms += ms;
     c->timed_calls++;
     for (hipEvent_t e : ev) c->free_events.push_back(e);
   }
@@ -461,7 +464,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       int rc = resolve_timing(c);
       if (rc) return rc;
     }
-    for (int k = 0; k < 7; ++k) {
+    // 0..4 stage marks, 5-6 the pair kernel, 7-8 the search kernel
+    for (int k = 0; k < 9; ++k) {
       hipEvent_t e = take_event(c);
       if (!e) return LUB_EDEVICE;
       ev.push_back(e);
@@ -520,12 +524,14 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                             c->work_t, c->stat_nbr, c->cnt, s, 1, &lists);
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
-                            c->stat_nbr, c->cnt, s, 2, &lists);
+                            c->stat_nbr, c->cnt, s, 2, &lists, nullptr, nullptr,
+                            timing ? ev[7] : nullptr, timing ? ev[8] : nullptr);
     } else {
       launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                             c->work_t, c->stat_nbr, c->cnt, s, 0, nullptr, c->bcount,
-                            c->block_sums);
+                            c->block_sums, timing ? ev[7] : nullptr,
+                            timing ? ev[8] : nullptr);
       c->list_builds++;
     }
     mark(2);
@@ -587,7 +593,8 @@ int fetch_counters(lub_ctx* c) {
 // the device buffers a call's launch sequence uses
 std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
-          c->cell_sorted, c->deg, c->block_sums, c->wall_slot, c->rec, c->recp, c->pos, c->kin,
+          c->cell_sorted, c->deg, c->bcount, c->block_sums, c->wall_slot, c->rec, c->recp,
+          c->pos, c->kin,
           c->nbr,
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
           c->out_status,
@@ -1198,6 +1205,7 @@ int lub_get_stats(lub_handle_t h, lub_stats_t* out) {
   out->timed_calls = h->timed_calls;
   for (int k = 0; k < 4; ++k) out->stage_ms[k] = h->stage_ms[k];
   out->pair_kernel_ms = h->pair_kernel_ms;
+  out->search_kernel_ms = h->search_kernel_ms;
   out->list_builds = h->list_builds;
   if (h->list_state) {
     // searches decided on the device
@@ -1217,6 +1225,7 @@ int lub_reset_timers(lub_handle_t h) {
   h->timed_calls = 0;
   for (int k = 0; k < 4; ++k) h->stage_ms[k] = 0.0;
   h->pair_kernel_ms = 0.0;
+  h->search_kernel_ms = 0.0;
   return LUB_OK;
 }
 

@@ -221,10 +221,13 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode = 0,
                            const ListBufs* lists = nullptr, int32_t* bcount = nullptr,
-                           int32_t* block_sums = nullptr);
+                           int32_t* block_sums = nullptr, hipEvent_t ev_start = nullptr,
+                           hipEvent_t ev_stop = nullptr);
 // (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,
 // and block_sums, scan scratch for n entries; given, the full search of
-// large systems runs as a forward search, a scan and a merge)
+// large systems runs as a forward search, a scan and a merge; the events,
+// when given, take the search kernel's own start and end stamps: the full
+// search, the forward walk or the filter of reused lists)
 // reused neighbour lists: the displacement plus growth since the search
 // (skipped unless the lists are of this epoch), then the decision (a
 // search if the lists are of another epoch or the measure exceeds half the

@@ -20,6 +20,7 @@
 // later calls measure how far the particles moved and grew since, decide on
 // the device whether to search again, and otherwise refresh the records in
 // the old cell order and filter the kept pairs with the exact centre test.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lub_internal.h"
@@ -967,6 +968,22 @@ __device__ __forceinline__ float axis_gap_f(int o, float f, float cell) {
   return fmaxf(0.0f, g * (1.0f - 1e-5f) - 1e-5f * cell);
 }
 
+// x / m and x % m for 0 <= x < 2^20 and m >= 1: a float estimate (off by at
+// most one) and one correction
+__device__ __forceinline__ int small_divmod(int x, int m, int* rem) {
+  int q = (int)((float)x * __builtin_amdgcn_rcpf((float)m));
+  int r = x - q * m;
+  if (r < 0) {
+    --q;
+    r += m;
+  } else if (r >= m) {
+    ++q;
+    r -= m;
+  }
+  *rem = r;
+  return q;
+}
+
 // the visiting order of an axis window [first, first + count): the offset
 // into the window at which the wrapped cell index is smallest
 __device__ __forceinline__ int axis_rotation(int first, int count, int nc) {
@@ -1195,16 +1212,21 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       // indices only, the rows after it larger ones, and in its own row
       // the ranges are cut to indices above s
       const bool own = kMode == kFwd && cls == cls_s;
-      int row_start = 0;
+      // (c3 - first and rot both lie in [0, cnt): their difference in
+      // (-cnt, cnt))
+      int py = 0, pz = 0;
       if (own) {
-        const int py = ((c3[1] - first[1] - rot[1]) % cnt3[1] + cnt3[1]) % cnt3[1];
-        const int pz = ((c3[2] - first[2] - rot[2]) % cnt3[2] + cnt3[2]) % cnt3[2];
-        row_start = pz * cnt3[1] + py;
+        py = c3[1] - first[1] - rot[1];
+        pz = c3[2] - first[2] - rot[2];
+        py += py < 0 ? cnt3[1] : 0;
+        pz += pz < 0 ? cnt3[2] : 0;
       }
+      const int row_start = pz * cnt3[1] + py;
       // lane gl's row (iy, iz) = row0 + gl, advanced by G rows per chunk
-      // without divisions
-      int iy = (row_start + gl) % cnt3[1], iz = (row_start + gl) / cnt3[1];
-      const int step_y = G % cnt3[1], step_z = G / cnt3[1];
+      int step_y, iy;
+      const int step_z = small_divmod(G, cnt3[1], &step_y);
+      const int iz0 = small_divmod(py + gl, cnt3[1], &iy);
+      int iz = pz + iz0;
       for (int row0 = row_start; row0 < nrows; row0 += G) {
         // lane gl's row: its cell range along x cut to the chord, as one or
         // two index ranges in increasing order
@@ -1673,25 +1695,26 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode, const ListBufs* lists,
-                           int32_t* bcount, int32_t* block_sums) {
+                           int32_t* bcount, int32_t* block_sums, hipEvent_t ev_start,
+                           hipEvent_t ev_stop) {
   const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
   if (mode != 2 && nbr_flat(d)) {
     const dim3 grid_f(nbr_blocks_flat(d)), block_f(64 * kFlatWaves);
     if (mode == 0 && nbr_forward(d, bcount, block_sums)) {
       const size_t lds_f = sizeof(int32_t) * kFlatWaves * (64 / kFlatG) * (size_t)d.max_nbr;
-      hipLaunchKernelGGL(k_neighbors_flat<kFwd>, grid_f, block_f, lds_f, s, d, rec, pos, orig,
-                         cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
-                         stat_nbr, cnt, lb, bcount);
+      hipExtLaunchKernelGGL(k_neighbors_flat<kFwd>, grid_f, block_f, lds_f, s, ev_start,
+                            ev_stop, 0, d, rec, pos, orig, cell_sorted, cell_start, deg, nbr,
+                            slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb, bcount);
       int32_t* kcnt = bcount + d.n;
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
       hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, deg, nbr, slot,
                          wall_slot, work_s, work_t, stat_nbr, cnt);
     } else if (mode == 0) {
-      hipLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, d, rec, pos, orig,
-                         cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
-                         stat_nbr, cnt, lb, nullptr);
+      hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
+                            d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
+                            wall_slot, work_s, work_t, stat_nbr, cnt, lb, nullptr);
     } else {
       hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, pos, orig,
                          cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
@@ -1702,6 +1725,8 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
   dim3 grid(nbr_blocks_group(d));
   size_t lds = sizeof(int32_t) * 64 * nbr_waves(d) / nbr_group(d) * (size_t)d.max_nbr;
   if (mode == 2 && lists && lists->work_sup) lds *= 2;  // the superset positions too
+  // (the lane-group kernels take stream-ordered stamps around their launch)
+  if (ev_start) hipEventRecord(ev_start, s);
   if (nbr_group(d) == 16)
     launch_nbr_waves<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
@@ -1711,6 +1736,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
   else
     launch_nbr_waves<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
+  if (ev_stop) hipEventRecord(ev_stop, s);
 }
 
 namespace {

@@ -77,7 +77,7 @@ class lub_stats_t(C.Structure):
                 ("iter_hist", C.c_int64 * 32), ("timed_calls", C.c_int64),
                 ("stage_ms", C.c_double * 4), ("warm_seeded", C.c_int64),
                 ("max_degree", C.c_int64), ("pair_kernel_ms", C.c_double),
-                ("list_builds", C.c_int64)]
+                ("list_builds", C.c_int64), ("search_kernel_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_
