@@ -510,24 +510,28 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
                           c->cell_count, ncell, gate, s);
+      // the 128-B records feed the lane-group search, the full search of
+      // small systems, the learned seed's features and the link-wise laws
+      const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums)) ||
+                            is_link(d.model) || c->opt.seed_mode == LUB_SEED_MLP;
       launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
-                           q, semi, v, w, c->sorted, c->rec, c->recp, c->pos, c->kin,
-                           c->cell_sorted, gate, s);
+                           q, semi, v, w, c->sorted, need_rec ? c->rec : nullptr, c->recp,
+                           c->pos, c->kin, c->cell_sorted, gate, s);
     }
   }
   if (d.n > 0) {
     mark(1);
     if (reuse) {
       // the superset (searched in calls that search), then the exact filter
-      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+      launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->sup_deg, c->sup_nbr, c->slot, c->wall_slot, c->work_s,
                             c->work_t, c->stat_nbr, c->cnt, s, 1, &lists);
-      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+      launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
                             c->stat_nbr, c->cnt, s, 2, &lists, nullptr, nullptr,
                             timing ? ev[7] : nullptr, timing ? ev[8] : nullptr);
     } else {
-      launch_neighbors_wave(d, c->rec, c->pos, c->sorted, c->cell_sorted, c->cell_start,
+      launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                             c->work_t, c->stat_nbr, c->cnt, s, 0, nullptr, c->bcount,
                             c->block_sums, timing ? ev[7] : nullptr,

@@ -214,8 +214,8 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
                         double4* pos,
                         KRec* kin, int32_t* cell_sorted, Counters* cnt, const Counters* gate,
                         hipStream_t s);
-void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
-                           const int32_t* orig, const int32_t* cell_sorted,
+void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp,
+                           const double4* pos, const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
@@ -223,6 +223,9 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                            const ListBufs* lists = nullptr, int32_t* bcount = nullptr,
                            int32_t* block_sums = nullptr, hipEvent_t ev_start = nullptr,
                            hipEvent_t ev_stop = nullptr);
+// whether the full search runs as forward search + merge (then the 128-B
+// records are not read by the search)
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums);
 // (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,
 // and block_sums, scan scratch for n entries; given, the full search of
 // large systems runs as a forward search, a scan and a merge; the events,

@@ -294,7 +294,8 @@ __device__ __forceinline__ RecIn load_record_input(const double* __restrict__ r,
 
 // Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
 // with a the symmetry axis (third column of the rotation of q).  `cell` is
-// written to cell_sorted when that is given.
+// written to cell_sorted when that is given; the 128-B record only when rec
+// is given (the forward search of large systems reads the 64-B copy).
 __device__ void make_record_from(int s, const RecIn& in, int cell, PRec* __restrict__ rec,
                                  PRecP* __restrict__ recp, double4* __restrict__ pos,
                                  KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
@@ -318,7 +319,7 @@ __device__ void make_record_from(int s, const RecIn& in, int cell, PRec* __restr
   c.Rperp = in.u.b;
   recp[s] = c;
   const PRec o = expand_record(c);
-  rec[s] = o;
+  if (rec) rec[s] = o;
   pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
   KRec k;
   for (int m = 0; m < 3; ++m) {
@@ -1119,7 +1120,8 @@ __device__ __forceinline__ void evaluation_slots(
 
 template <int kMode>
 __global__ void __launch_bounds__(64 * kFlatWaves)
-k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict__ pos,
+k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restrict__ recp,
+                 const double4* __restrict__ pos,
                  const int32_t* __restrict__ orig, const int32_t* __restrict__ cell_sorted,
                  const int32_t* __restrict__ cell_start, int32_t* __restrict__ deg,
                  int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
@@ -1347,21 +1349,23 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       if (gl == 0) deg[s] = count;
       const int nf = min(count, maxn);
       const int me = orig[s];
-      const PRec& A = rec[s];
+      // the 64-B geometry copies, M formed with the staging's expression
+      const PRecP A = recp[s];
       int32_t* srow = slot + (size_t)s * maxn;
       int kept_own = 0;
-      double ra[3], ma[6];
-      for (int m = 0; m < 3; ++m) ra[m] = A.r[m];
-      for (int m = 0; m < 6; ++m) ma[m] = A.M[m];
+      double ma[6];
+      support_matrix(A.ax, A.Rpar, A.Rperp, ma);
+      const double* ra = A.r;
       for (int k = gl; k < nf; k += G) {
         const int t = seg[k];
         // the partner's data first, the atomic after it: its return is
         // needed last (vector memory operations complete in order)
         const int ot = orig[t];
-        double rb[3], mb[6];
-        for (int m = 0; m < 3; ++m) rb[m] = rec[t].r[m];
-        for (int m = 0; m < 6; ++m) mb[m] = rec[t].M[m];
+        const PRecP B = recp[t];
         const int q = atomicAdd(&bcount[t], 1);
+        double mb[6];
+        support_matrix(B.ax, B.Rpar, B.Rperp, mb);
+        const double* rb = B.r;
         const bool own = me < ot;
         double dv[3];
         if (own)
@@ -1392,7 +1396,7 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const double4* __rest
       if (d.n_walls && gl < 2) {
         // -3: candidate beyond every cut-off, -1: no candidate, 0: kept
         const double dist = gl == 0 ? ra[2] : d.L[2] - ra[2];
-        const bool cand_w = (dist - A.Rmax) < d.dmax;
+        const bool cand_w = (dist - (A.Rpar > A.Rperp ? A.Rpar : A.Rperp)) < d.dmax;
         const bool keep = cand_w && (dist - sqrt(ma[5])) < d.dmax;
         wall_slot[2 * s + gl] = keep ? 0 : (cand_w ? -3 : -1);
         kept_own += keep;
@@ -1689,8 +1693,8 @@ void launch_nbr_waves(int mode, dim3 grid, size_t lds, hipStream_t s, const Call
                                     stat_nbr, cnt, lb);
 }
 
-void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* pos,
-                           const int32_t* orig, const int32_t* cell_sorted,
+void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp,
+                           const double4* pos, const int32_t* orig, const int32_t* cell_sorted,
                            const int32_t* cell_start, int32_t* deg,
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
@@ -1704,8 +1708,8 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
     if (mode == 0 && nbr_forward(d, bcount, block_sums)) {
       const size_t lds_f = sizeof(int32_t) * kFlatWaves * (64 / kFlatG) * (size_t)d.max_nbr;
       hipExtLaunchKernelGGL(k_neighbors_flat<kFwd>, grid_f, block_f, lds_f, s, ev_start,
-                            ev_stop, 0, d, rec, pos, orig, cell_sorted, cell_start, deg, nbr,
-                            slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb, bcount);
+                            ev_stop, 0, d, rec, recp, pos, orig, cell_sorted, cell_start, deg,
+                            nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb, bcount);
       int32_t* kcnt = bcount + d.n;
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
@@ -1713,10 +1717,10 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const double4* po
                          wall_slot, work_s, work_t, stat_nbr, cnt);
     } else if (mode == 0) {
       hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
-                            d, rec, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
+                            d, rec, recp, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
                             wall_slot, work_s, work_t, stat_nbr, cnt, lb, nullptr);
     } else {
-      hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, pos, orig,
+      hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, recp, pos, orig,
                          cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
                          stat_nbr, cnt, lb, nullptr);
     }
