@@ -59,9 +59,10 @@ struct lub_ctx {
   int64_t* stat_pair = nullptr;    // [kMaxPairBlocks][kStatPairWords]
   // warm start: two tables of (pair key, converged normal), the one of
   // counter set p written by calls using set p, read by the next call
-  uint64_t* warm_key[2] = {nullptr, nullptr};
+  // warm start, two sets swapped between calls: per input index the slot
+  // range of its pairs, per slot the normal and the partner's input index
+  int2* warm_range[2] = {nullptr, nullptr};
   float4* warm_val[2] = {nullptr, nullptr};
-  int64_t warm_size = 0;           // entries per table, a power of 2
   int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
   int32_t* deg = nullptr;          // [n] entries per segment
   int32_t* bcount = nullptr;       // [2n + 2] forward search: backward entries, slot
@@ -235,6 +236,14 @@ int ensure_particles(lub_ctx* c, int64_t n) {
       (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks_max((int)need))) ||
       (rc = realloc_buf(&c->wall_slot, 2 * need)))
     return rc;
+  if (c->opt.warm_start) {
+    // new ranges are empty
+    for (int k = 0; k < 2; ++k) {
+      if ((rc = realloc_buf(&c->warm_range[k], need))) return rc;
+      HIP_TRY(hipMemset(c->warm_range[k], 0, sizeof(int2) * need));
+    }
+    HIP_TRY(hipDeviceSynchronize());
+  }
   if (c->opt.skin > 0.0 &&
       ((rc = realloc_buf(&c->sup_deg, need)) || (rc = realloc_buf(&c->ref_pos, need)) ||
        (rc = realloc_buf(&c->inv, need)) || (rc = realloc_buf(&c->disp_blk, (need + 255) / 256))))
@@ -291,21 +300,13 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
       return rc;
     c->cap_work = work;
     if (c->opt.warm_start) {
-      // four entries per particle: dense suspensions evaluate one to two
-      // pairs per particle, so the load stays below one half (a fuller table
-      // only costs pairs their warm start).  New tables start empty: the
-      // seeds of earlier calls are dropped
-      int64_t size = 1024;
-      while (size < 4 * std::max<int64_t>(n, 1)) size *= 2;
-      c->warm_size = 0;
+      // new values hold no partner (-1): the seeds of earlier calls are
+      // dropped
       for (int k = 0; k < 2; ++k) {
-        if ((rc = realloc_buf(&c->warm_key[k], size)) ||
-            (rc = realloc_buf(&c->warm_val[k], size)))
-          return rc;
-        HIP_TRY(hipMemset(c->warm_key[k], 0xff, sizeof(uint64_t) * size));
+        if ((rc = realloc_buf(&c->warm_val[k], work))) return rc;
+        HIP_TRY(hipMemset(c->warm_val[k], 0xff, sizeof(float4) * work));
       }
       HIP_TRY(hipDeviceSynchronize());  // cleared before any stream uses them
-      c->warm_size = size;
     }
   }
   return LUB_OK;
@@ -437,12 +438,12 @@ CallDesc finalize_desc(lub_ctx* c, const CallDesc& d0) {
   // and join cost more than they save
   d.partner_codes = d.n >= (1 << 18);
   // Ladd's law has no closest-point iteration to start.  With reused lists
-  // the normals are kept per superset entry (no hashing), else in the hash
-  // tables
+  // the normals are kept per superset entry, else per slot with each
+  // particle's slot range
   const bool warm = c->opt.warm_start && d.model != LUB_MODEL_LADD && !is_link(d.model);
   d.warm_slots = warm && d.skin > 0.0 && c->sup_val && c->work_sup &&
                  (int64_t)std::max<int64_t>(d.n, 1) * d.max_nbr <= INT32_MAX;
-  d.warm_mask = warm && !d.warm_slots && c->warm_size > 0 ? c->warm_size - 1 : 0;
+  d.warm_ranges = warm && !d.warm_slots && c->warm_range[0] && c->warm_val[0];
   return d;
 }
 
@@ -480,13 +481,9 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   c->cnt = c->cnt_buf + c->cnt_idx;
   Counters* next_cnt = c->cnt_buf + (c->cnt_idx ^ 1);
   const bool small = d.n > 0 && cells_small_fits(d);
-  // warm-start tables of this call: written (empty on entry) and read
+  // warm-start sets of this call: written and read
   const int wc = c->cnt_idx, wp = c->cnt_idx ^ 1;
-  if (!c->zeroed) {
-    launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
-    if (d.warm_mask)
-      HIP_TRY(hipMemsetAsync(c->warm_key[wc], 0xff, sizeof(uint64_t) * c->warm_size, s));
-  }
+  if (!c->zeroed) launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
   c->zeroed = false;
   // reused neighbour lists: the device decides whether this call searches
   // (every particle within half the skin of its place and size at the last
@@ -496,7 +493,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   const Counters* gate = reuse ? c->cnt : nullptr;
   const ListBufs lists{c->sup_nbr,    c->sup_deg,    c->ref_pos,
                        c->inv,        c->disp_blk,   c->list_state,
-                       d.warm_slots ? c->work_sup : nullptr};
+                       d.warm_slots ? c->work_sup : nullptr,
+                       d.warm_ranges ? c->warm_range[wc] : nullptr};
   if (reuse) {
     launch_disp(d, r, q, semi, lists, c->cnt, s);
     launch_refresh(d, r, q, semi, v, w, lists, c->rec, c->recp, c->pos, c->kin, c->cnt, s);
@@ -533,7 +531,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     } else {
       launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
-                            c->work_t, c->stat_nbr, c->cnt, s, 0, nullptr, c->bcount,
+                            c->work_t, c->stat_nbr, c->cnt, s, 0, &lists, c->bcount,
                             c->block_sums, timing ? ev[7] : nullptr,
                             timing ? ev[8] : nullptr);
       c->list_builds++;
@@ -552,8 +550,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       mlp_forward_slots(c->cnt, d.cap_work, c->seedX, c->seedY, c->wt, c->th, s);
       seeds = c->seedY;
     }
-    WarmTables warm{c->warm_key[wp], c->warm_val[wp], c->warm_key[wc], c->warm_val[wc],
-                    c->sorted,       c->work_sup,     c->sup_val,      c->list_state};
+    WarmTables warm{c->warm_range[wp], c->warm_val[wp], c->warm_val[wc], c->sorted,
+                    c->work_sup,       c->sup_val,      c->list_state};
     if (is_link(d.model)) {
       launch_links(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h, c->out_status,
                    c->out_links, c->stat_pair, c->cnt, s);
@@ -570,8 +568,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     mark(3);
     if (d.partner_codes) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
-                  c->cnt, next_cnt, d.warm_mask ? c->warm_key[wp] : nullptr,
-                  d.warm_mask ? c->warm_size : 0, f, t, s);
+                  c->cnt, next_cnt, f, t, s);
     mark(4);
     if (timing) c->pending.push_back(ev);
   }
@@ -603,7 +600,7 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
           c->out_status,
           c->out_iters, c->cnt_buf, c->stat_nbr, c->stat_pair, c->seedX, c->seedY, c->wt, c->th,
-          c->warm_key[0], c->warm_key[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
+          c->warm_range[0], c->warm_range[1], c->warm_val[0], c->warm_val[1], c->sup_nbr,
           c->sup_deg, c->ref_pos, c->inv, c->disp_blk, c->list_state, c->sup_val, c->work_sup,
           c->detail};
 }
@@ -1493,7 +1490,7 @@ void lub_destroy(lub_handle_t h) {
                   h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
                   h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
-                  h->cnt_buf, h->scat, h->pos, h->warm_key[0], h->warm_key[1],
+                  h->cnt_buf, h->scat, h->pos, h->warm_range[0], h->warm_range[1],
                   h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY, h->grow_semi,
                   h->grow_f, h->grow_t, h->stage_in, h->stage_out, h->detail};

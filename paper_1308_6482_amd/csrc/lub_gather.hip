@@ -75,15 +75,10 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ deg,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ slot,
     const int32_t* __restrict__ wall_slot, const PairOut<R>* __restrict__ out,
-    const Counters* cnt, Counters* __restrict__ next_cnt,
-    uint64_t* __restrict__ warm_clear, int64_t warm_size, double* __restrict__ f,
+    const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
     double* __restrict__ t) {
   constexpr int kPerWave = 64 / kGroup;
   const int lane = threadIdx.x & 63;
-  // the warm-start table this call read becomes the one the next call writes
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < warm_size;
-       e += (int64_t)gridDim.x * blockDim.x)
-    warm_clear[e] = kWarmEmpty;
   const int g = lane % kGroup;  // lane within the particle's group
   const int s = (blockIdx.x * kWaves + (threadIdx.x >> 6)) * kPerWave + lane / kGroup;
   if (blockIdx.x == 0)
@@ -161,8 +156,8 @@ void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
-                   int64_t warm_size, double* f, double* t, hipStream_t s) {
+                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
+                   hipStream_t s) {
   if (d.n == 0) return;
   const bool large = d.n >= (1 << 18);
   const int per_block = kWaves * (64 / (large ? kGroupLarge : kGroupSmall));
@@ -172,18 +167,18 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
     const PairOut<float>* o = (const PairOut<float>*)out;
     if (large)
       hipLaunchKernelGGL((k_gather<float, kGroupLarge>), grid, block, 0, s, d, orig, deg, nbr,
-                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+                         slot, wall_slot, o, cnt, next_cnt, f, t);
     else
       hipLaunchKernelGGL((k_gather<float, kGroupSmall>), grid, block, 0, s, d, orig, deg, nbr,
-                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+                         slot, wall_slot, o, cnt, next_cnt, f, t);
   } else {
     const PairOut<double>* o = (const PairOut<double>*)out;
     if (large)
       hipLaunchKernelGGL((k_gather<double, kGroupLarge>), grid, block, 0, s, d, orig, deg, nbr,
-                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+                         slot, wall_slot, o, cnt, next_cnt, f, t);
     else
       hipLaunchKernelGGL((k_gather<double, kGroupSmall>), grid, block, 0, s, d, orig, deg, nbr,
-                         slot, wall_slot, o, cnt, next_cnt, warm_clear, warm_size, f, t);
+                         slot, wall_slot, o, cnt, next_cnt, f, t);
   }
 }
 

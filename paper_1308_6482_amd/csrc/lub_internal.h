@@ -109,6 +109,7 @@ struct ListBufs {
   double* disp_blk;
   ListState* state;
   int32_t* work_sup;  // per evaluation slot: its superset entry (warm start)
+  int2* warm_range;   // warm start: this call's slot range per input index
 };
 
 // Per-block partial statistics, written with plain stores and summed only
@@ -136,7 +137,7 @@ struct CallDesc {
                         // least 1/reach_max of the largest pair bound)
   int32_t model;        // LUB_MODEL_*
   double r_small;       // size classes: R_max <= r_small is small (own cells)
-  int64_t warm_mask;    // warm start: hash table size - 1; 0 = off
+  int32_t warm_ranges;  // warm start from the previous call's slot ranges
   int32_t periodic[3];
   int32_t n_walls;
   double wall_vel[2][3];
@@ -246,15 +247,17 @@ void launch_refresh(const CallDesc& d, const double* r, const double* q, const d
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the
 // line-of-centres start
-// Warm start: converged normals of evaluated particle pairs by (input
-// index i << 32 | input index j), open addressing with linear probing.
-constexpr uint64_t kWarmEmpty = ~0ull;
-constexpr int kWarmProbes = 32;
+// Warm start: every particle's evaluation slots are one contiguous range
+// (the search assigns them particle by particle).  Each call records, per
+// input index, the range of the pairs that particle evaluates, and per slot
+// the converged normal with the partner's input index; the next call finds a
+// pair's previous normal by scanning the owner's previous range (a few
+// consecutive slots).  Two sets, swapped between calls.
+constexpr int kWarmScan = 520;  // longest range scanned (segment + 2 walls)
 struct WarmTables {
-  const uint64_t* prev_key;  // read: the previous call's pairs
-  const float4* prev_val;
-  uint64_t* cur_key;         // written: this call's pairs (all empty on entry)
-  float4* cur_val;
+  const int2* prev_range;    // read: [first, end) slot of each input index
+  const float4* prev_val;    // read: (normal, partner input index as int bits)
+  float4* cur_val;           // written: this call's values per slot
   const int32_t* orig;       // cell order -> input index
   // with reused lists (CallDesc::warm_slots): the last normal of each
   // superset entry, tagged with the search that made the superset
@@ -302,8 +305,8 @@ void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
-                   const Counters* cnt, Counters* next_cnt, uint64_t* warm_clear,
-                   int64_t warm_size, double* f, double* t, hipStream_t s);
+                   const Counters* cnt, Counters* next_cnt, double* f, double* t,
+                   hipStream_t s);
 
 // ---- link-wise laws (lub_link.hip) ------------------------------------------
 int link_grid(const CallDesc& d);

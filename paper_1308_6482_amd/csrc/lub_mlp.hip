@@ -123,53 +123,113 @@ __device__ __forceinline__ void activate(f32x4 z[8], const float* __restrict__ b
   }
 }
 
-// Block-level grid-stride loop over 64-sample groups (uniform per block, so
-// the barriers are safe); m comes from the device counters when cnt is set.
+// Inference.  One wavefront per 64 samples (kFwdTiles tiles of 16), the
+// weights as the A operand (16 outputs x 32 inputs, loaded once per 64
+// samples), the activations as the B operand (32 inputs x 16 samples): the
+// output tile gives each lane 4 consecutive outputs of one sample, stored to
+// LDS as one 8-byte word and read back by the next layer as 16-byte words.
+// SiLU with the hardware exp2 and reciprocal (the result is rounded to BF16
+// anyway).  Block-level grid-stride loop (uniform per block, so the barriers
+// are safe); m comes from the device counters when cnt is set.
+constexpr int kFwdTiles = 4;
+constexpr int kFwdSamples = 16 * kFwdTiles;  // per wavefront
+
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+
+// bias + SiLU of one output tile, to LDS: outputs o0 .. o0 + 3 of sample row
+__device__ __forceinline__ void store_act4(f32x4 z, const float b[4], __bf16* row, int o0) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = (__bf16)silu_fast(z[i] + b[i]);
+  *reinterpret_cast<bf16x4*>(row + o0) = v;
+}
+
+// one hidden layer of the wavefront's 64 samples, in place in act
+__device__ __forceinline__ void forward_hidden(__bf16* act, const __bf16* __restrict__ W,
+                                               const float* __restrict__ bias, int g, int c) {
+  bf16x8 x[kFwdTiles][4];
+#pragma unroll
+  for (int st = 0; st < kFwdTiles; ++st)
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) x[st][kt] = ld8(act + (16 * st + c) * 128 + 32 * kt + 8 * g);
+  __syncthreads();  // every read of the layer's input is done
+#pragma unroll 2
+  for (int j = 0; j < 8; ++j) {
+    f32x4 z[kFwdTiles];
+#pragma unroll
+    for (int st = 0; st < kFwdTiles; ++st) z[st] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      const bf16x8 w = ld8(W + (16 * j + c) * 128 + 32 * kt + 8 * g);
+#pragma unroll
+      for (int st = 0; st < kFwdTiles; ++st) z[st] = mfma(w, x[st][kt], z[st]);
+    }
+    float b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = bias[16 * j + 4 * g + i];
+#pragma unroll
+    for (int st = 0; st < kFwdTiles; ++st)
+      store_act4(z[st], b, act + (16 * st + c) * 128, 16 * j + 4 * g);
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(64 * kWaves) k_forward(int64_t m_host, const Counters* cnt,
                                                         int cap, const float* __restrict__ X,
                                                         float* __restrict__ Y,
                                                         const __bf16* __restrict__ wt,
                                                         const float* __restrict__ th) {
-  __shared__ __attribute__((aligned(16))) __bf16 s_act[kWaves][16 * 128];
+  __shared__ __attribute__((aligned(16))) __bf16 s_act[kWaves][kFwdSamples * 128];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane / 16, c = lane % 16;
   const int64_t m = cnt ? (cnt->error == 0 ? min(cnt->work, cap) : 0) : m_host;
   __bf16* act = s_act[wv];
   const __bf16* W4 = wt + kWt1 + 2 * kWt2;
-  for (int64_t grp = blockIdx.x; grp * 16 * kWaves < m; grp += gridDim.x) {
-    const int64_t base = (grp * kWaves + wv) * 16;
-    f32x4 z[8];
-    // layer 1 (K = 10 padded to 32)
-    bf16x8 a0 = input_fragment(X, m, base + lane % 16, lane / 16);
+  for (int64_t grp = blockIdx.x; grp * kFwdSamples * kWaves < m; grp += gridDim.x) {
+    const int64_t base = (grp * kWaves + wv) * kFwdSamples;
+    // layer 1 (K = 10 padded to 32): the inputs as the B operand
+    bf16x8 x[kFwdTiles];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      f32x4 c = {0.f, 0.f, 0.f, 0.f};
-      z[j] = mfma(a0, ld8(wt + (16 * j + lane % 16) * 32 + 8 * (lane / 16)), c);
-    }
+    for (int st = 0; st < kFwdTiles; ++st) x[st] = input_fragment(X, m, base + 16 * st + c, g);
     __syncthreads();  // the previous group's reads of act are done
-    activate(z, th + kOffB1, act, lane);
-    __syncthreads();
-    hidden_layer(act, wt + kWt1, lane, z);
-    __syncthreads();
-    activate(z, th + kOffB2, act, lane);
-    __syncthreads();
-    hidden_layer(act, wt + kWt1 + kWt2, lane, z);
-    __syncthreads();
-    activate(z, th + kOffB3, act, lane);
-    __syncthreads();
-    // output layer (N = 4 padded to 16)
-    bf16x8 a[4];
+#pragma unroll 2
+    for (int j = 0; j < 8; ++j) {
+      const bf16x8 w = ld8(wt + (16 * j + c) * 32 + 8 * g);
+      float b[4];
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt) a[kt] = ld8(act + (lane % 16) * 128 + 32 * kt + 8 * (lane / 16));
-    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < 4; ++i) b[i] = th[kOffB1 + 16 * j + 4 * g + i];
 #pragma unroll
-    for (int kt = 0; kt < 4; ++kt)
-      c = mfma(a[kt], ld8(W4 + (lane % 16) * 128 + 32 * kt + 8 * (lane / 16)), c);
-    const int col = lane % 16;
-    if (col < 4) {
+      for (int st = 0; st < kFwdTiles; ++st) {
+        const f32x4 z = mfma(w, x[st], f32x4{0.f, 0.f, 0.f, 0.f});
+        store_act4(z, b, act + (16 * st + c) * 128, 16 * j + 4 * g);
+      }
+    }
+    __syncthreads();
+    forward_hidden(act, wt + kWt1, th + kOffB2, g, c);
+    forward_hidden(act, wt + kWt1 + kWt2, th + kOffB3, g, c);
+    // output layer (N = 4 padded to 16): lanes of g = 0 hold the 4 outputs
+    // of sample c of each tile
+    f32x4 z[kFwdTiles];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int64_t sidx = base + 4 * (lane / 16) + i;
-        if (sidx < m) Y[sidx * 4 + col] = c[i] + th[kOffB4 + col];
+    for (int st = 0; st < kFwdTiles; ++st) z[st] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+      const bf16x8 w = ld8(W4 + c * 128 + 32 * kt + 8 * g);
+#pragma unroll
+      for (int st = 0; st < kFwdTiles; ++st)
+        z[st] = mfma(w, ld8(act + (16 * st + c) * 128 + 32 * kt + 8 * g), z[st]);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int st = 0; st < kFwdTiles; ++st) {
+        const int64_t sidx = base + 16 * st + c;
+        if (sidx < m) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) Y[sidx * 4 + i] = z[st][i] + th[kOffB4 + i];
+        }
       }
     }
   }
@@ -445,7 +505,7 @@ void mlp_pack(const float* th, __bf16* wt, __bf16* wb, hipStream_t s) {
 }
 
 static unsigned forward_grid(int64_t m) {
-  int64_t groups = (m + 16 * kWaves - 1) / (16 * kWaves);
+  int64_t groups = (m + kFwdSamples * kWaves - 1) / (kFwdSamples * kWaves);
   if (groups > 8192) groups = 8192;
   return (unsigned)(groups < 1 ? 1 : groups);
 }

@@ -891,6 +891,17 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
     int y = __shfl_up(incl2, o, 64);
     if (lane >= o) incl2 += y;
   }
+  // warm start: this particle's slot range (its lanes' slots are
+  // consecutive), by input index
+  if (lb.warm_range) {
+    const int start = s_base[wv] + incl2 - nkeep;
+    int gsum = nkeep;
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) gsum += __shfl_xor(gsum, o, G);
+    const int first = __shfl(start, gbase, 64);
+    if (live && gl == 0)
+      lb.warm_range[me] = fits ? make_int2(first, first + gsum) : make_int2(0, 0);
+  }
   if (!live || !fits) return;
   int next = s_base[wv] + incl2 - nkeep;
   for (int k = 0; k < kMaxPerLane; ++k) {
@@ -1005,7 +1016,7 @@ __device__ __forceinline__ void evaluation_slots(
     int32_t* __restrict__ deg, int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
     int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
     int64_t* __restrict__ stat_nbr, Counters* cnt, int* s_keep, int* s_upper, int* s_wallc,
-    int* s_base, int* s_deg) {
+    int* s_base, int* s_deg, int2* __restrict__ warm_range) {
   constexpr int G = kFlatG;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -1100,6 +1111,17 @@ __device__ __forceinline__ void evaluation_slots(
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(incl2, o, 64);
     if (lane >= o) incl2 += y;
+  }
+  // warm start: this particle's slot range (its lanes' slots are
+  // consecutive), by input index
+  if (warm_range) {
+    const int start = s_base[wv] + incl2 - nkeep;
+    int gsum = nkeep;
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) gsum += __shfl_xor(gsum, o, G);
+    const int first = __shfl(start, lane - gl, 64);
+    if (live && gl == 0)
+      warm_range[me] = fits ? make_int2(first, first + gsum) : make_int2(0, 0);
   }
   if (!live || !fits) return;
   int next = s_base[wv] + incl2 - nkeep;
@@ -1420,7 +1442,7 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
   }
   evaluation_slots(d, rec, orig, blk, s, live, live ? count : 0, nent, seg, deg, slot,
                    wall_slot, work_s, work_t, stat_nbr, cnt, s_keep, s_upper, s_wallc, s_base,
-                   s_deg);
+                   s_deg, lb.warm_range);
 }
 
 // The merge of the forward search: each particle's segment is the sorted
@@ -1434,7 +1456,8 @@ __global__ void __launch_bounds__(64 * kFlatWaves)
 k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict__ deg,
             int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
             int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
-            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt) {
+            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
+            const int32_t* __restrict__ orig, int2* __restrict__ warm_range) {
   constexpr int G = kFlatG;
   constexpr int kPer = 64 / G;
   constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
@@ -1547,6 +1570,8 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
         work_s[k] = s;
         work_t[k] = -1;
       }
+    // warm start: this particle's slot range, by input index
+    if (warm_range && gl == 0) warm_range[orig[s]] = make_int2(base, (int)next);
     if (s == d.n - 1 && gl == 0) {
       cnt->work = (int32_t)min<int64_t>(total, INT32_MAX);
       if (total > d.cap_work) set_error(cnt, LUB_ECAPACITY);
@@ -1714,7 +1739,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
       hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, deg, nbr, slot,
-                         wall_slot, work_s, work_t, stat_nbr, cnt);
+                         wall_slot, work_s, work_t, stat_nbr, cnt, orig, lb.warm_range);
     } else if (mode == 0) {
       hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
                             d, rec, recp, pos, orig, cell_sorted, cell_start, deg, nbr, slot,

@@ -29,9 +29,10 @@
 //
 // Records.  The kernels gather a 64-B copy per particle (centre, axis, radii)
 // and form the support matrix M in registers with the staging's expression.
-// The previous call's normal (warm start) comes from hash tables keyed by the
-// input indices, or, with reused neighbour lists, from a slot per superset
-// entry tagged with the search that made the superset.
+// The previous call's normal (warm start) comes from the owner's previous
+// slot range (a few consecutive slots, each with its partner's input index),
+// or, with reused neighbour lists, from a slot per superset entry tagged with
+// the search that made the superset.
 //
 // Precision.  R = double: every step in FP64.  R = float: the Newton solve,
 // the gap, the frame vectors, the latitudes, the curvature radii and cubic
@@ -642,14 +643,6 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
 
 constexpr int kPairBlock = 64;
 
-// bucket of a warm-start key (a 64-bit mix; the table size is a power of 2)
-__device__ __forceinline__ uint64_t warm_hash(uint64_t k) {
-  k ^= k >> 31;
-  k *= 0x9E3779B97F4A7C15ull;
-  k ^= k >> 29;
-  return k;
-}
-
 // kTangent = false: the main pass over all slots; a particle pair whose
 // Newton solve fails from every start is put on fail_list and left to the
 // second pass (kTangent = true, a small grid over that list), which adds the
@@ -696,15 +689,15 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
       const int s = work_s[w], t = work_t[w];
       const bool pp = t >= 0;  // a particle pair, else a wall pair
       // warm start: the previous normal of the pair, kept per superset
-      // entry (reused lists) or in the hash tables.  One call site of the
-      // pair evaluation for every kind (inlined copies only cost
-      // instruction cache)
-      const bool warm_on = pp && (cd.warm_slots || cd.warm_mask != 0);
+      // entry (reused lists) or found in the owner's previous slot range.
+      // One call site of the pair evaluation for every kind (inlined copies
+      // only cost instruction cache)
+      const bool warm_on = pp && (cd.warm_slots || cd.warm_ranges);
       double nprev[3] = {0.0, 0.0, 0.0};
       double nnew[3] = {0.0, 0.0, 0.0};
       bool found = false;
       int e_sup = 0;
-      uint64_t key = 0, h0 = 0;
+      int jin = -1;  // the partner's input index (slot ranges)
       if (warm_on && cd.warm_slots) {
         // made under the current superset?
         e_sup = warm.slot_sup[w];
@@ -714,20 +707,19 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
         nprev[1] = v.y;
         nprev[2] = v.z;
       } else if (warm_on) {
-        key = ((uint64_t)warm.orig[s] << 32) | (uint64_t)warm.orig[t];
-        h0 = warm_hash(key);
-        for (int p = 0; p < kWarmProbes; ++p) {
-          const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
-          const uint64_t k = warm.prev_key[e];
-          if (k == key) {
-            const float4 v = warm.prev_val[e];
+        jin = warm.orig[t];
+        const int2 rg = warm.prev_range[warm.orig[s]];
+        const int lo = max(rg.x, 0);
+        const int hi = min(min(rg.y, cd.cap_work), lo + kWarmScan);
+        for (int k = lo; k < hi; ++k) {
+          const float4 v = warm.prev_val[k];
+          if (__float_as_int(v.w) == jin) {
             nprev[0] = v.x;
             nprev[1] = v.y;
             nprev[2] = v.z;
             found = true;
             break;
           }
-          if (k == kWarmEmpty) break;
         }
       }
       PairOut<R> o;
@@ -739,25 +731,17 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
                              pp && seedY ? seedY + 4 * (int64_t)w : nullptr, fb, nprev,
                              found, wu, nnew,
                              detail ? detail + (int64_t)kDetailWords * w : nullptr);
-      if (warm_on && status != 3) {
-        if (cd.warm_slots) {
-          warm.sup_val[e_sup] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
-                                            __int_as_float(tag));
-        } else {
-          // this call's normal for the next call (a full probe sequence
-          // only costs the pair its warm start)
-          for (int p = 0; p < kWarmProbes; ++p) {
-            const uint64_t e = (h0 + p) & (uint64_t)cd.warm_mask;
-            const unsigned long long old = atomicCAS(
-                (unsigned long long*)&warm.cur_key[e], (unsigned long long)kWarmEmpty,
-                (unsigned long long)key);
-            if (old == kWarmEmpty || old == key) {
-              warm.cur_val[e] = make_float4((float)nnew[0], (float)nnew[1],
-                                            (float)nnew[2], 0.f);
-              break;
-            }
-          }
-        }
+      if (warm_on && cd.warm_slots && status != 3) {
+        warm.sup_val[e_sup] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
+                                          __int_as_float(tag));
+      }
+      if (cd.warm_ranges && (!kTangent || status != 3)) {
+        // this call's value of the slot for the next call: the normal and
+        // the partner, or no partner (-1) for a wall or a failed solve (the
+        // tangent-sphere pass writes the slots it solves)
+        const bool keep = warm_on && status != 3;
+        warm.cur_val[w] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
+                                      __int_as_float(keep ? jin : -1));
       }
       out[w] = o;
       out_h[w] = h;
