@@ -72,9 +72,10 @@ def parse():
                     help="particle sample of the accuracy checks (full-scale system)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU oracle baseline (0: skip the oracle leg)")
-    ap.add_argument("--seed", choices=["plain", "mlp", "both"], default="both",
-                    help="Newton start: line of centres, learned network, or both "
-                         "(the JSON value is the plain form unless --seed mlp)")
+    ap.add_argument("--seed", choices=["plain", "mlp", "warm", "both"], default="both",
+                    help="Newton start: line of centres, learned network, previous "
+                         "evaluation's normal (warm), or all three (both); the JSON value "
+                         "is the plain form unless one form is chosen")
     ap.add_argument("--extras", type=int, default=1,
                     help="also run the variants (warm start, reused lists, normal-only "
                          "law), the 4096-prolate single-evaluation leg, the dynamics "
@@ -816,7 +817,12 @@ def main():
     if args.seed in ("mlp", "both"):
         forms["mlp"], snaps["mlp"], windows["mlp"] = measure_form(
             L, torch, wl, prec, args, cap, theta, sample=sample)
-    head = "mlp" if args.seed == "mlp" else "plain"
+    if args.seed in ("warm", "both"):
+        # the paper's continuation between time steps (Sec. III.A): each
+        # pair's solve starts from its normal of the previous evaluation
+        forms["warm"], snaps["warm"], windows["warm"] = measure_form(
+            L, torch, wl, prec, args, cap, sample=sample, warm_start=1)
+    head = {"mlp": "mlp", "warm": "warm"}.get(args.seed, "plain")
     hf = forms[head]
     pair_rl, nbr_rl = roofline_entries(hf, windows[head], args, args.workload)
     dominant = nbr_rl if nbr_rl["launch_ms"] >= pair_rl["launch_ms"] else pair_rl
@@ -858,8 +864,7 @@ def main():
 
     if args.extras:
         var = {}
-        for name, kw in (("warm_start", dict(warm_start=1)),
-                         ("reused_lists_skin4", dict(skin=4.0)),
+        for name, kw in (("reused_lists_skin4", dict(skin=4.0)),
                          ("reused_lists_warm_skin4", dict(skin=4.0, warm_start=1))):
             a2 = argparse.Namespace(**vars(args))
             a2.snap_every = 0

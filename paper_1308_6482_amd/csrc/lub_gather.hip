@@ -88,11 +88,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
   const bool live = s < d.n;
   const size_t stride = (size_t)d.max_nbr;
   double acc[6] = {0, 0, 0, 0, 0, 0};
+  // this lane's first slot code and wall slot, loaded beside the count
+  // (a segment row holds max_nbr >= kGroup entries): one dependent load less
+  const int sl_first = live ? slot[(size_t)s * stride + g] : 0;
+  const int ws = live && d.n_walls && g >= kGroup - 2 ? wall_slot[2 * s + (g - (kGroup - 2))]
+                                                      : -1;
   if (live && cnt->error == 0) {
     const int ns = deg[s];
     for (int k = g; k < ns; k += kGroup) {
       const size_t e = (size_t)s * stride + k;
-      const int sl = slot[e];
+      const int sl = k == g ? sl_first : slot[e];
       if (sl >= 0) {
         const PairOut<R>& o = out[sl];
         for (int c = 0; c < 3; ++c) {
@@ -118,7 +123,6 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
       }
     }
     if (d.n_walls && g >= kGroup - 2) {
-      const int ws = wall_slot[2 * s + (g - (kGroup - 2))];
       if (ws >= 0) {
         const PairOut<R>& o = out[ws];
         for (int c = 0; c < 3; ++c) {

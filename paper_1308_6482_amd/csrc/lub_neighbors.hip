@@ -1485,6 +1485,10 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
   const int64_t next = live ? (s + 1 < d.n ? (int64_t)kbase[s + 1] : total) : 0;
   const int w0 = live && d.n_walls ? wall_slot[2 * s] : -1;
   const int w1 = live && d.n_walls ? wall_slot[2 * s + 1] : -1;
+  // and this lane's first backward and forward entries (rows hold max_nbr
+  // >= G entries): one dependent load less
+  const int row_first = live ? nbr[(size_t)s * maxn + gl] : 0;
+  const int sl_first = live ? slot[(size_t)s * maxn + gl] : 0;
   const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
   const bool overflow = live && need > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
@@ -1492,8 +1496,8 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
   const int nbk = nent ? nb : 0, nfk = nent ? nf : 0;
   int32_t* row = nbr + (size_t)(live ? s : 0) * maxn;
   int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
-  for (int k = gl; k < nbk; k += G) stg[k] = row[k];
-  for (int k = gl; k < nfk; k += G) stg[nbk + k] = sl[k];
+  for (int k = gl; k < nbk; k += G) stg[k] = k == gl ? row_first : row[k];
+  for (int k = gl; k < nfk; k += G) stg[nbk + k] = k == gl ? sl_first : sl[k];
   __syncthreads();
   // the place of each entry in the segment: the backward entries below it
   // (counted over the unsorted ones) plus the forward entries below it (its
