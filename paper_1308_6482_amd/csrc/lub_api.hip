@@ -65,6 +65,8 @@ struct lub_ctx {
   float4* warm_val[2] = {nullptr, nullptr};
   int32_t* cell_sorted = nullptr;  // [n] cell of each cell-order particle
   int32_t* deg = nullptr;          // [n] entries per segment
+  int2* bstage = nullptr;          // [n * cur_nbr] forward search: backward entries
+                                   // with their place in the finder's slot range
   int32_t* bcount = nullptr;       // [2n + 2] forward search: backward entries, slot
                                    // offsets, their int64 total
   int32_t* block_sums = nullptr;   // scan scratch
@@ -274,7 +276,8 @@ int ensure_entries(lub_ctx* c, int64_t n, int64_t max_nbr) {
   int rc;
   if (c->cap_entries < entries || !c->nbr) {
     c->cap_entries = 0;
-    if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)))
+    if ((rc = realloc_buf(&c->nbr, entries)) || (rc = realloc_buf(&c->slot, entries)) ||
+        (rc = realloc_buf(&c->bstage, entries)))
       return rc;
     if (c->opt.skin > 0.0 && (rc = realloc_buf(&c->sup_nbr, entries))) return rc;
     if (c->opt.skin > 0.0 && c->opt.warm_start) {
@@ -433,10 +436,13 @@ CallDesc finalize_desc(lub_ctx* c, const CallDesc& d0) {
   d.list_epoch = c->list_epoch;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
-  // from about a quarter million particles the partner codes, written
-  // beside the pair kernel, save the gather its searches; below, the fork
-  // and join cost more than they save
-  d.partner_codes = d.n >= (1 << 18);
+  // the forward search's merge writes the partner codes itself; else, from
+  // about a quarter million particles, codes written beside the pair kernel
+  // save the gather its searches (below, the fork and join cost more than
+  // they save)
+  d.partner_codes = d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums, c->bstage)
+                        ? kPartnerMerge
+                        : (d.n >= (1 << 18) ? kPartnerSide : kPartnerSearch);
   // Ladd's law has no closest-point iteration to start.  With reused lists
   // the normals are kept per superset entry, else per slot with each
   // particle's slot range
@@ -510,7 +516,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                           c->cell_count, ncell, gate, s);
       // the 128-B records feed the lane-group search, the full search of
       // small systems, the learned seed's features and the link-wise laws
-      const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums)) ||
+      const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums,
+                                                           c->bstage)) ||
                             is_link(d.model) || c->opt.seed_mode == LUB_SEED_MLP;
       launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
                            q, semi, v, w, c->sorted, need_rec ? c->rec : nullptr, c->recp,
@@ -526,19 +533,19 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                             c->work_t, c->stat_nbr, c->cnt, s, 1, &lists);
       launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s, c->work_t,
-                            c->stat_nbr, c->cnt, s, 2, &lists, nullptr, nullptr,
+                            c->stat_nbr, c->cnt, s, 2, &lists, nullptr, nullptr, nullptr,
                             timing ? ev[7] : nullptr, timing ? ev[8] : nullptr);
     } else {
       launch_neighbors_wave(d, c->rec, c->recp, c->pos, c->sorted, c->cell_sorted, c->cell_start,
                             c->deg, c->nbr, c->slot, c->wall_slot, c->work_s,
                             c->work_t, c->stat_nbr, c->cnt, s, 0, &lists, c->bcount,
-                            c->block_sums, timing ? ev[7] : nullptr,
+                            c->block_sums, c->bstage, timing ? ev[7] : nullptr,
                             timing ? ev[8] : nullptr);
       c->list_builds++;
     }
     mark(2);
     // the partner-slot codes beside the pair kernel
-    if (d.partner_codes) {
+    if (d.partner_codes == kPartnerSide) {
       HIP_TRY(hipEventRecord(c->ev_fork, s));
       HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
       launch_partner_slots(d, c->work_s, c->work_t, c->deg, c->nbr, c->slot, c->cnt, c->side);
@@ -566,7 +573,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                    timing ? ev[5] : nullptr, timing ? ev[6] : nullptr, c->detail);
     }
     mark(3);
-    if (d.partner_codes) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+    if (d.partner_codes == kPartnerSide) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
                   c->cnt, next_cnt, f, t, s);
     mark(4);
@@ -594,7 +601,8 @@ int fetch_counters(lub_ctx* c) {
 // the device buffers a call's launch sequence uses
 std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
-          c->cell_sorted, c->deg, c->bcount, c->block_sums, c->wall_slot, c->rec, c->recp,
+          c->cell_sorted, c->deg, c->bcount, c->bstage, c->block_sums, c->wall_slot, c->rec,
+          c->recp,
           c->pos, c->kin,
           c->nbr,
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
@@ -1486,7 +1494,7 @@ void lub_destroy(lub_handle_t h) {
   hipSetDevice(h->device);
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
-                  h->sorted, h->cell_sorted, h->deg, h->bcount, h->block_sums,
+                  h->sorted, h->cell_sorted, h->deg, h->bcount, h->bstage, h->block_sums,
                   h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
                   h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,

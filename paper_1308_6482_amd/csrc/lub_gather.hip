@@ -104,9 +104,10 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
           acc[c] += (double)o.F[c];
           acc[3 + c] += (double)o.Ti[c];
         }
-      } else if (sl <= -3 || (sl == -2 && !d.partner_codes)) {
-        // the partner owns the pair: its slot code (k_partner_slots), or
-        // found in the partner's sorted segment
+      } else if (sl <= -3 || (sl == -2 && d.partner_codes == kPartnerSearch)) {
+        // the partner owns the pair: its slot code (from the forward
+        // search's merge or k_partner_slots), or found in the partner's
+        // sorted segment
         int sp = -3 - sl;
         if (sl == -2) {
           const int p = nbr[e];
@@ -190,7 +191,14 @@ namespace {
 
 // One block per statistic: the sum (or, for the largest iteration count,
 // the maximum) of that word over the rows the last call's blocks wrote.
-constexpr int kReduceThreads = 256;
+// Each thread keeps four loads in flight (the rows are strided, so the
+// block is bound by the latency of its loads, not by their bytes).
+constexpr int kReduceThreads = 1024;
+constexpr int kReduceUnroll = 4;
+
+__device__ __forceinline__ int64_t stat_combine(bool is_max, int64_t a, int64_t b) {
+  return is_max ? max(a, b) : a + b;
+}
 
 __global__ void __launch_bounds__(kReduceThreads)
 k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_blocks,
@@ -210,11 +218,20 @@ k_stats_reduce(Counters* cnt, const int64_t* __restrict__ stat_pair, int pair_bl
     stride = kStatNbrWords;
   }
   const bool is_max = word == 6 || word == kStatPairWords + 2;
-  int64_t acc = 0;
-  for (int r = threadIdx.x; r < rows; r += kReduceThreads) {
-    const int64_t v = base[(int64_t)r * stride];
-    acc = is_max ? max(acc, v) : acc + v;
+  int64_t a[kReduceUnroll] = {};
+  int r = threadIdx.x;
+  for (; r + (kReduceUnroll - 1) * kReduceThreads < rows; r += kReduceUnroll * kReduceThreads) {
+    int64_t v[kReduceUnroll];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u)
+      v[u] = base[(int64_t)(r + u * kReduceThreads) * stride];
+#pragma unroll
+    for (int u = 0; u < kReduceUnroll; ++u) a[u] = stat_combine(is_max, a[u], v[u]);
   }
+  for (; r < rows; r += kReduceThreads) a[0] = stat_combine(is_max, a[0], base[(int64_t)r * stride]);
+  int64_t acc = a[0];
+#pragma unroll
+  for (int u = 1; u < kReduceUnroll; ++u) acc = stat_combine(is_max, acc, a[u]);
   if (word < kStatPairWords) {
     // the rows of the tangent-sphere pass
     const int nfail = cnt->error == 0 ? min(cnt->failed, cap_work) : 0;

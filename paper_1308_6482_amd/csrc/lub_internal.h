@@ -158,10 +158,18 @@ struct CallDesc {
   int32_t cap_entries;
   int32_t cap_work;
   int32_t precision;
-  int32_t partner_codes;  // the partner's slot code is written into every
-                          // non-owned entry of an evaluated pair (large
-                          // systems); else the gather searches for it
+  int32_t partner_codes;  // kPartner*: who writes the slot code of an
+                          // evaluated pair into the partner's entry
 };
+
+// The partner's entry of an evaluated pair: the gather searches the
+// partner's segment for the slot (small systems), or the code -3 - slot is
+// written into it by a kernel beside the pair pass (large systems) or by
+// the forward search's merge, which gives each pair a slot in the range of
+// the particle that found it.
+constexpr int kPartnerSearch = 0;
+constexpr int kPartnerSide = 1;
+constexpr int kPartnerMerge = 2;
 
 // Pair output record: force on i, torque on i and torque on j about the
 // particle centres.
@@ -222,14 +230,16 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode = 0,
                            const ListBufs* lists = nullptr, int32_t* bcount = nullptr,
-                           int32_t* block_sums = nullptr, hipEvent_t ev_start = nullptr,
-                           hipEvent_t ev_stop = nullptr);
+                           int32_t* block_sums = nullptr, int2* bstage = nullptr,
+                           hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // whether the full search runs as forward search + merge (then the 128-B
 // records are not read by the search)
-bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums);
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums,
+                 const int2* bstage);
 // (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,
-// and block_sums, scan scratch for n entries; given, the full search of
-// large systems runs as a forward search, a scan and a merge; the events,
+// block_sums, scan scratch for n entries, and bstage, one int2 per segment
+// entry; given, the full search of large systems runs as a forward search, a
+// scan and a merge, which also writes the partner-slot codes; the events,
 // when given, take the search kernel's own start and end stamps: the full
 // search, the forward walk or the filter of reused lists)
 // reused neighbour lists: the displacement plus growth since the search
@@ -247,16 +257,18 @@ void launch_refresh(const CallDesc& d, const double* r, const double* q, const d
 // ---- pair kernel (lub_pair.hip) -------------------------------------------
 // seedY: network outputs per slot (p_i, q_i, p_j, q_j) or null for the
 // line-of-centres start
-// Warm start: every particle's evaluation slots are one contiguous range
-// (the search assigns them particle by particle).  Each call records, per
-// input index, the range of the pairs that particle evaluates, and per slot
-// the converged normal with the partner's input index; the next call finds a
-// pair's previous normal by scanning the owner's previous range (a few
-// consecutive slots).  Two sets, swapped between calls.
+// Warm start: the search assigns evaluation slots particle by particle (to
+// the particle that evaluates a pair, or, in the forward search, to the one
+// that found it), so every particle's slots are one contiguous range.  Each
+// call records, per input index, that range, and per slot the converged
+// normal with the xor of the pair's input indices; the next call finds a
+// pair's previous normal by scanning the previous ranges of its two
+// particles (a few consecutive slots each).  Two sets, swapped between
+// calls.
 constexpr int kWarmScan = 520;  // longest range scanned (segment + 2 walls)
 struct WarmTables {
   const int2* prev_range;    // read: [first, end) slot of each input index
-  const float4* prev_val;    // read: (normal, partner input index as int bits)
+  const float4* prev_val;    // read: (normal, xor of the pair's input indices)
   float4* cur_val;           // written: this call's values per slot
   const int32_t* orig;       // cell order -> input index
   // with reused lists (CallDesc::warm_slots): the last normal of each

@@ -1149,7 +1149,7 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
                  int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
                  int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
                  int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
-                 ListBufs lb, int32_t* __restrict__ bcount) {
+                 ListBufs lb, int32_t* __restrict__ bcount, int2* __restrict__ bstage) {
   if (kMode == 1 && !cnt->rebuild) return;  // the lists are reused
   constexpr int G = kFlatG;
   constexpr int kPer = 64 / G;
@@ -1358,14 +1358,16 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
   const int nent = (live && !overflow) ? count : 0;
   if (kMode == kFwd) {
-    // Each pair once: which side evaluates it (smaller input index) and the
-    // support-function bound along the line of centres, taken as the
-    // evaluating side would take it (same operands, same order).  The
-    // forward partners go to the slot segment (read by the merge) and this
-    // particle to each partner's segment at a place counted by bcount (the
-    // backward partners, in no particular order), both with the flags; the
-    // pairs each particle will evaluate, and its kept walls, are counted in
-    // kcnt (scanned into the merge's slot offsets).
+    // Each pair once, by the particle that found it (the finder): which side
+    // evaluates it (smaller input index) and the support-function bound
+    // along the line of centres, taken as the evaluating side would take it
+    // (same operands, same order).  The kept pairs get evaluation slots in
+    // the finder's range, in the order of its forward list, then its kept
+    // walls: slot = fbase[finder] + kk with fbase the scan of kcnt.  The
+    // forward partners go to the slot segment (read by the merge), and this
+    // particle, with the flags and its kk, to each partner's row of bstage
+    // at a place counted by bcount (the backward partners, in no particular
+    // order; one 8-B store per pair).
     if (live) {
       int32_t* kcnt = bcount + d.n;
       if (gl == 0) deg[s] = count;
@@ -1374,58 +1376,65 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
       // the 64-B geometry copies, M formed with the staging's expression
       const PRecP A = recp[s];
       int32_t* srow = slot + (size_t)s * maxn;
-      int kept_own = 0;
+      int kept = 0;  // kept forward pairs so far (uniform in the group)
       double ma[6];
       support_matrix(A.ax, A.Rpar, A.Rperp, ma);
       const double* ra = A.r;
-      for (int k = gl; k < nf; k += G) {
-        const int t = seg[k];
-        // the partner's data first, the atomic after it: its return is
-        // needed last (vector memory operations complete in order)
-        const int ot = orig[t];
-        const PRecP B = recp[t];
-        const int q = atomicAdd(&bcount[t], 1);
-        double mb[6];
-        support_matrix(B.ax, B.Rpar, B.Rperp, mb);
-        const double* rb = B.r;
-        const bool own = me < ot;
-        double dv[3];
-        if (own)
-          pair_image(d, ra, rb, dv);
-        else
-          pair_image(d, rb, ra, dv);
-        const double dx = dv[0], dy = dv[1], dz = dv[2];
-        const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-        bool keep = true;
-        if (dn > 0.0) {
-          const double idn = 1.0 / dn;
-          const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
-          const double* M1 = own ? ma : mb;
-          const double* M2 = own ? mb : ma;
-          const double g = dn - support(M1, ux, uy, uz) - support(M2, ux, uy, uz);
-          keep = g < d.dmax;
-        }
-        const int32_t fk = keep ? kKeepBit : 0;
-        srow[k] = t | (own ? kOwnBit : 0) | fk;
-        if (q < maxn) nbr[(size_t)t * maxn + q] = s | (own ? 0 : kOwnBit) | fk;
-        if (keep) {
+      for (int k0 = 0; k0 < nf; k0 += G) {
+        const int k = k0 + gl;
+        const bool on = k < nf;
+        bool keep = false, own = false;
+        int t = 0, q = 0;
+        if (on) {
+          t = seg[k];
+          // the partner's data first, the atomic after it: its return is
+          // needed last (vector memory operations complete in order)
+          const int ot = orig[t];
+          const PRecP B = recp[t];
+          q = atomicAdd(&bcount[t], 1);
+          double mb[6];
+          support_matrix(B.ax, B.Rpar, B.Rperp, mb);
+          const double* rb = B.r;
+          own = me < ot;
+          double dv[3];
           if (own)
-            ++kept_own;
+            pair_image(d, ra, rb, dv);
           else
-            atomicAdd(&kcnt[t], 1);
+            pair_image(d, rb, ra, dv);
+          const double dx = dv[0], dy = dv[1], dz = dv[2];
+          const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+          keep = true;
+          if (dn > 0.0) {
+            const double idn = 1.0 / dn;
+            const double ux = dx * idn, uy = dy * idn, uz = dz * idn;
+            const double* M1 = own ? ma : mb;
+            const double* M2 = own ? mb : ma;
+            const double g = dn - support(M1, ux, uy, uz) - support(M2, ux, uy, uz);
+            keep = g < d.dmax;
+          }
         }
+        const unsigned long long mk = (__ballot(keep) >> gbase) & kGroupMask;
+        if (on) {
+          const int32_t fk = keep ? kKeepBit : 0;
+          srow[k] = t | (own ? kOwnBit : 0) | fk;
+          if (q < maxn)
+            bstage[(size_t)t * maxn + q] =
+                make_int2(s | (own ? 0 : kOwnBit) | fk, keep ? kept + lane_prefix(mk, gl) : 0);
+        }
+        kept += __popcll(mk);
       }
+      int walls = 0;
       if (d.n_walls && gl < 2) {
         // -3: candidate beyond every cut-off, -1: no candidate, 0: kept
         const double dist = gl == 0 ? ra[2] : d.L[2] - ra[2];
         const bool cand_w = (dist - (A.Rpar > A.Rperp ? A.Rpar : A.Rperp)) < d.dmax;
         const bool keep = cand_w && (dist - sqrt(ma[5])) < d.dmax;
         wall_slot[2 * s + gl] = keep ? 0 : (cand_w ? -3 : -1);
-        kept_own += keep;
+        walls = keep;
       }
 #pragma unroll
-      for (int o = G / 2; o >= 1; o >>= 1) kept_own += __shfl_xor(kept_own, o, G);
-      if (gl == 0 && kept_own) atomicAdd(&kcnt[s], kept_own);
+      for (int o = G / 2; o >= 1; o >>= 1) walls += __shfl_xor(walls, o, G);
+      if (gl == 0) kcnt[s] = kept + walls;
     }
     return;
   }
@@ -1448,13 +1457,18 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
 // The merge of the forward search: each particle's segment is the sorted
 // union of its backward partners (written by the partners' forward searches
 // in no particular order) and its forward partners (sorted by the walk).
-// Its evaluation slots are the range the
-// scan of kcnt gave it, in entry order, then its walls: no atomics, and the
-// slot order does not depend on the schedule.  LDS: two max_nbr buffers per
-// group.  bcount: [n] backward counts, [n] slot offsets, the int64 total.
+// Every entry's slot code follows from its flags and the finder's range
+// (fbase[finder] + kk: the partner for a backward entry, this particle for a
+// forward one): the slot itself where this particle evaluates the pair, -3 -
+// slot where the partner does (the gather needs no search), -1 for a pair
+// the bound dropped.  The finder writes the evaluation list entries of
+// its kept pairs and walls.  No atomics, and a slot order that does not
+// depend on the schedule.  LDS: two max_nbr buffers per group (entries and
+// their slots).  bcount: [n] backward counts, [n] slot offsets, the int64
+// total; bstage: the backward entries with their kk, row by row.
 __global__ void __launch_bounds__(64 * kFlatWaves)
-k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict__ deg,
-            int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
+k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, const int2* __restrict__ bstage,
+            int32_t* __restrict__ deg, int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
             int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
             int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
             const int32_t* __restrict__ orig, int2* __restrict__ warm_range) {
@@ -1475,87 +1489,93 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
   const int32_t* kbase = bcount + d.n;
   const int64_t total = *reinterpret_cast<const int64_t*>(bcount + 2 * (size_t)d.n);
   // stg: the backward entries (any order) then the forward ones (sorted);
-  // fin: the segment
+  // stk: the slot of each (meaningful for a kept pair)
   int32_t* stg = reinterpret_cast<int32_t*>(s_merge) + (size_t)(wv * kPer + grp) * 2 * maxn;
-  int32_t* fin = stg + maxn;
-  // every per-particle word up front
+  int32_t* stk = stg + maxn;
+  // every per-particle word up front, with this lane's first backward and
+  // forward entries (rows hold max_nbr >= G entries), and right behind the
+  // first backward entry its finder's slot offset: two rounds of dependent
+  // loads in all
+  const size_t rbase = (size_t)(live ? s : 0) * maxn;
   const int nb = live ? bcount[s] : 0;
   const int nf = live ? deg[s] : 0;
   const int base = live ? kbase[s] : 0;
   const int64_t next = live ? (s + 1 < d.n ? (int64_t)kbase[s + 1] : total) : 0;
   const int w0 = live && d.n_walls ? wall_slot[2 * s] : -1;
   const int w1 = live && d.n_walls ? wall_slot[2 * s + 1] : -1;
-  // and this lane's first backward and forward entries (rows hold max_nbr
-  // >= G entries): one dependent load less
-  const int row_first = live ? nbr[(size_t)s * maxn + gl] : 0;
-  const int sl_first = live ? slot[(size_t)s * maxn + gl] : 0;
+  const int2 b_first = live ? bstage[rbase + gl] : make_int2(0, 0);
+  const int sl_first = live ? slot[rbase + gl] : 0;
+  const int me = live && warm_range ? orig[s] : 0;
+  const int kb_first = live && gl < nb ? kbase[b_first.x & kIndexMask] : 0;
   const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
   const bool overflow = live && need > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
   const int nent = (live && !overflow) ? need : 0;
   const int nbk = nent ? nb : 0, nfk = nent ? nf : 0;
-  int32_t* row = nbr + (size_t)(live ? s : 0) * maxn;
-  int32_t* sl = slot + (size_t)(live ? s : 0) * maxn;
-  for (int k = gl; k < nbk; k += G) stg[k] = k == gl ? row_first : row[k];
-  for (int k = gl; k < nfk; k += G) stg[nbk + k] = k == gl ? sl_first : sl[k];
-  __syncthreads();
-  // the place of each entry in the segment: the backward entries below it
-  // (counted over the unsorted ones) plus the forward entries below it (its
-  // own index in the forward list, else a binary search there)
-  for (int k = gl; k < nent; k += G) {
-    const int raw = stg[k];
-    const int key = raw & kIndexMask;
-    int below = 0, m = 0;
-    for (; m + 4 <= nbk; m += 4) {
-      const int4 v = *reinterpret_cast<const int4*>(stg + m);
-      below += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
-               ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
+  int32_t* row = nbr + rbase;
+  int32_t* sl = slot + rbase;
+  for (int k = gl; k < nbk; k += G) {
+    const int2 b = k == gl ? b_first : bstage[rbase + k];
+    stg[k] = b.x;
+    stk[k] = (k == gl ? kb_first : kbase[b.x & kIndexMask]) + b.y;
+  }
+  // the forward entries' slots: their rank among the kept ones, in order
+  int kept_fwd = 0;
+  for (int k0 = 0; k0 < nfk; k0 += G) {
+    const int k = k0 + gl;
+    const int raw = k < nfk ? (k == gl ? sl_first : sl[k]) : 0;
+    const bool kp = k < nfk && (raw & kKeepBit);
+    const unsigned long long mk = (__ballot(kp) >> gbase) & kGroupMask;
+    if (k < nfk) {
+      stg[nbk + k] = raw;
+      stk[nbk + k] = base + kept_fwd + lane_prefix(mk, gl);
     }
-    for (; m < nbk; ++m) below += (stg[m] & kIndexMask) < key;
-    if (k >= nbk) {
-      below += k - nbk;
-    } else {
-      int lo = 0, hi = nfk;  // forward entries below key: [0, lo)
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((stg[nbk + mid] & kIndexMask) < key)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      below += lo;
-    }
-    fin[below] = raw;
+    kept_fwd += __popcll(mk);
   }
   __syncthreads();
   int nupper = 0, nwallc = 0;
   if (live) {
-    for (int k = gl; k < nent; k += G) row[k] = fin[k] & kIndexMask;
-    if (gl == 0) deg[s] = nent;
-    // slots [base, next) of this particle: kept owned entries in entry
-    // order, then its kept walls
-    int at = base;
-    for (int e0 = 0; e0 < nent; e0 += G) {
-      const int e = e0 + gl;
-      const int raw = e < nent ? fin[e] : 0;
-      const bool own = e < nent && (raw & kOwnBit);
-      const bool kp = own && (raw & kKeepBit);
-      const unsigned long long mk = (__ballot(kp) >> gbase) & kGroupMask;
-      if (e < nent) {
-        int code = own ? -1 : -2;
-        if (kp) {
-          code = at + lane_prefix(mk, gl);
-          if (code < d.cap_work) {
-            work_s[code] = s;
-            work_t[code] = raw & kIndexMask;
-          }
+    // the place of each entry in the segment: the backward entries below it
+    // (counted over the unsorted ones) plus the forward entries below it
+    // (its own index in the forward list, else a binary search there)
+    for (int k = gl; k < nent; k += G) {
+      const int raw = stg[k];
+      const int key = raw & kIndexMask;
+      int below = 0, m = 0;
+      for (; m + 4 <= nbk; m += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(stg + m);
+        below += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
+                 ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
+      }
+      for (; m < nbk; ++m) below += (stg[m] & kIndexMask) < key;
+      const bool fwd = k >= nbk;
+      if (fwd) {
+        below += k - nbk;
+      } else {
+        int lo = 0, hi = nfk;  // forward entries below key: [0, lo)
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((stg[nbk + mid] & kIndexMask) < key)
+            lo = mid + 1;
+          else
+            hi = mid;
         }
-        sl[e] = code;
+        below += lo;
+      }
+      const bool own = raw & kOwnBit, kp = raw & kKeepBit;
+      const int sid = stk[k];
+      row[below] = key;
+      sl[below] = kp ? (own ? sid : -3 - sid) : -1;
+      if (kp && fwd && sid < d.cap_work) {
+        work_s[sid] = own ? s : key;
+        work_t[sid] = own ? key : s;
       }
       nupper += own;
-      at += __popcll(mk);
     }
-    if (d.n_walls) {
+    if (gl == 0) deg[s] = nent;
+    // the kept walls after the kept forward pairs
+    int at = base + kept_fwd;
+    if (d.n_walls && nent == need) {
       if (gl == 0) nwallc = (w0 != -1) + (w1 != -1);
       if (gl < 2 && (gl == 0 ? w0 : w1) == 0) {
         const int code = at + (gl == 1 && w0 == 0 ? 1 : 0);
@@ -1569,13 +1589,14 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, int32_t* __restrict_
     }
     // an overflowing segment leaves its range to harmless particle-wall
     // slots (the call reports the overflow)
+    if (overflow) at = base;
     for (int64_t k = at + gl; k < next; k += G)
       if (k < d.cap_work) {
         work_s[k] = s;
         work_t[k] = -1;
       }
     // warm start: this particle's slot range, by input index
-    if (warm_range && gl == 0) warm_range[orig[s]] = make_int2(base, (int)next);
+    if (warm_range && gl == 0) warm_range[me] = make_int2(base, (int)next);
     if (s == d.n - 1 && gl == 0) {
       cnt->work = (int32_t)min<int64_t>(total, INT32_MAX);
       if (total > d.cap_work) set_error(cnt, LUB_ECAPACITY);
@@ -1683,7 +1704,8 @@ void launch_cells_small(const CallDesc& d, const double* r, const double* q,
 int nbr_waves(const CallDesc& d);  // wavefronts per block of the neighbour kernel
 int nbr_blocks_group(const CallDesc& d);
 bool nbr_flat(const CallDesc& d);
-bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums);
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums,
+                 const int2* bstage);
 int nbr_blocks_flat(const CallDesc& d);
 
 template <int G, int W>
@@ -1728,30 +1750,31 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
                            int32_t* nbr, int32_t* slot, int32_t* wall_slot,
                            int32_t* work_s, int32_t* work_t, int64_t* stat_nbr,
                            Counters* cnt, hipStream_t s, int mode, const ListBufs* lists,
-                           int32_t* bcount, int32_t* block_sums, hipEvent_t ev_start,
-                           hipEvent_t ev_stop) {
+                           int32_t* bcount, int32_t* block_sums, int2* bstage,
+                           hipEvent_t ev_start, hipEvent_t ev_stop) {
   const ListBufs lb = lists ? *lists : ListBufs{};
   if (d.n == 0) return;
   if (mode != 2 && nbr_flat(d)) {
     const dim3 grid_f(nbr_blocks_flat(d)), block_f(64 * kFlatWaves);
-    if (mode == 0 && nbr_forward(d, bcount, block_sums)) {
+    if (mode == 0 && nbr_forward(d, bcount, block_sums, bstage)) {
       const size_t lds_f = sizeof(int32_t) * kFlatWaves * (64 / kFlatG) * (size_t)d.max_nbr;
       hipExtLaunchKernelGGL(k_neighbors_flat<kFwd>, grid_f, block_f, lds_f, s, ev_start,
                             ev_stop, 0, d, rec, recp, pos, orig, cell_sorted, cell_start, deg,
-                            nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb, bcount);
+                            nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb, bcount,
+                            bstage);
       int32_t* kcnt = bcount + d.n;
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
-      hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, deg, nbr, slot,
-                         wall_slot, work_s, work_t, stat_nbr, cnt, orig, lb.warm_range);
+      hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, bstage, deg, nbr,
+                         slot, wall_slot, work_s, work_t, stat_nbr, cnt, orig, lb.warm_range);
     } else if (mode == 0) {
       hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
                             d, rec, recp, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
-                            wall_slot, work_s, work_t, stat_nbr, cnt, lb, nullptr);
+                            wall_slot, work_s, work_t, stat_nbr, cnt, lb, nullptr, nullptr);
     } else {
       hipLaunchKernelGGL(k_neighbors_flat<1>, grid_f, block_f, 0, s, d, rec, recp, pos, orig,
                          cell_sorted, cell_start, deg, nbr, slot, wall_slot, work_s, work_t,
-                         stat_nbr, cnt, lb, nullptr);
+                         stat_nbr, cnt, lb, nullptr, nullptr);
     }
     return;
   }
@@ -1909,8 +1932,10 @@ bool nbr_flat(const CallDesc& d) { return !d.le; }
 
 // the full search of large systems as forward search + merge (needs the
 // backward counts, zeroed by the binning kernel)
-bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums) {
-  return bcount != nullptr && block_sums != nullptr && !d.le && d.n >= kFwdMinN &&
+bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums,
+                 const int2* bstage) {
+  return bcount != nullptr && block_sums != nullptr && bstage != nullptr && !d.le &&
+         d.n >= kFwdMinN &&
          d.n <= kIndexMask &&
          d.max_nbr <= kFwdMaxNbr;
 }

@@ -29,8 +29,9 @@
 //
 // Records.  The kernels gather a 64-B copy per particle (centre, axis, radii)
 // and form the support matrix M in registers with the staging's expression.
-// The previous call's normal (warm start) comes from the owner's previous
-// slot range (a few consecutive slots, each with its partner's input index),
+// The previous call's normal (warm start) comes from the previous slot range
+// of one of the pair's particles (a few consecutive slots, each with the
+// xor of its pair's input indices),
 // or, with reused neighbour lists, from a slot per superset entry tagged with
 // the search that made the superset.
 //
@@ -697,7 +698,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
       double nnew[3] = {0.0, 0.0, 0.0};
       bool found = false;
       int e_sup = 0;
-      int jin = -1;  // the partner's input index (slot ranges)
+      int key = -1;  // input index of s xor that of t (slot ranges)
       if (warm_on && cd.warm_slots) {
         // made under the current superset?
         e_sup = warm.slot_sup[w];
@@ -707,18 +708,28 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
         nprev[1] = v.y;
         nprev[2] = v.z;
       } else if (warm_on) {
-        jin = warm.orig[t];
-        const int2 rg = warm.prev_range[warm.orig[s]];
-        const int lo = max(rg.x, 0);
-        const int hi = min(min(rg.y, cd.cap_work), lo + kWarmScan);
-        for (int k = lo; k < hi; ++k) {
-          const float4 v = warm.prev_val[k];
-          if (__float_as_int(v.w) == jin) {
-            nprev[0] = v.x;
-            nprev[1] = v.y;
-            nprev[2] = v.z;
-            found = true;
-            break;
+        // the pair sat in the range of one of its two particles (the one
+        // that evaluated it, or the one whose search found it: the one
+        // earlier in cell order, which moves little between calls); that
+        // one's range first
+        const int is = warm.orig[s], it = warm.orig[t];
+        key = is ^ it;
+        const bool s_first = cd.partner_codes != kPartnerMerge || s < t;
+        const int2 ra = warm.prev_range[s_first ? is : it];
+        const int2 rb = warm.prev_range[s_first ? it : is];
+        for (int side = 0; side < 2 && !found; ++side) {
+          const int2 rg = side == 0 ? ra : rb;
+          const int lo = max(rg.x, 0);
+          const int hi = min(min(rg.y, cd.cap_work), lo + kWarmScan);
+          for (int k = lo; k < hi; ++k) {
+            const float4 v = warm.prev_val[k];
+            if (__float_as_int(v.w) == key) {
+              nprev[0] = v.x;
+              nprev[1] = v.y;
+              nprev[2] = v.z;
+              found = true;
+              break;
+            }
           }
         }
       }
@@ -737,11 +748,12 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
       }
       if (cd.warm_ranges && (!kTangent || status != 3)) {
         // this call's value of the slot for the next call: the normal and
-        // the partner, or no partner (-1) for a wall or a failed solve (the
+        // the pair's key, or -1 (no pair: the key of a pair is a xor of two
+        // distinct non-negative indices) for a wall or a failed solve (the
         // tangent-sphere pass writes the slots it solves)
         const bool keep = warm_on && status != 3;
         warm.cur_val[w] = make_float4((float)nnew[0], (float)nnew[1], (float)nnew[2],
-                                      __int_as_float(keep ? jin : -1));
+                                      __int_as_float(keep ? key : -1));
       }
       out[w] = o;
       out_h[w] = h;
