@@ -242,16 +242,11 @@ def train_seed(L, torch, n_train, epochs):
 # the trajectory
 # ---------------------------------------------------------------------------
 
-def advance(r, q, v, w, dt):
-    """One time step of the suspension in place: r += v dt, and the
-    orientation q <- normalise(q + dt/2 (0, w) * q) (quaternion product)."""
-    import torch
-    r.add_(v, alpha=dt)
-    qw, qv = q[:, :1], q[:, 1:]
-    dqw = -(w * qv).sum(dim=1, keepdim=True)
-    dqv = qw * w + torch.cross(w, qv, dim=1)
-    q.add_(torch.cat([dqw, dqv], dim=1), alpha=0.5 * dt)
-    q.div_(q.norm(dim=1, keepdim=True))
+def advance(lb, r, q, v, w, dt):
+    """One time step of the suspension in place, by the library's kinematic
+    advance (one kernel on the current stream): r += v dt, and the
+    orientation q <- normalise(q + dt/2 (0, w) q) (quaternion product)."""
+    lb.advance(r, q, v, w, dt)
 
 
 def neighbour_capacity(L, torch, wl, prec, skin=0.0):
@@ -307,7 +302,7 @@ def protocol_pass(L, torch, wl, prec, args, cap, theta=None, sample=None, **kw):
             sel = sample[ij[:, 0]] | ((ij[:, 1] >= 0) & sample[np.maximum(ij[:, 1], 0)])
             snaps.append(dict(step=k, r=r.cpu().numpy(), q=q.cpu().numpy(),
                               pairs={key: pr[key][sel] for key in pr}))
-        advance(r, q, v, w, args.dt)
+        advance(lb, r, q, v, w, args.dt)
     torch.cuda.synchronize()
     lb.close()
     act = np.array([s["active"] for s in steps], dtype=np.int64)
@@ -342,12 +337,12 @@ def timed_pass(L, torch, wl, prec, args, cap, theta=None, **kw):
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            advance(r, q, v, w, args.dt)
+            advance(lb, r, q, v, w, args.dt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            advance(r, q, v, w, args.dt)
+            advance(lb, r, q, v, w, args.dt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     st = lb.stats()
@@ -369,13 +364,13 @@ def eager_pass(L, torch, wl, prec, args, cap, theta=None, **kw):
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            advance(r, q, v, w, args.dt)
+            advance(lb, r, q, v, w, args.dt)
         torch.cuda.synchronize()
         lb.reset_timers()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             lb.compute(r, q, semi, v, w, f, t, stream=stream)
-            advance(r, q, v, w, args.dt)
+            advance(lb, r, q, v, w, args.dt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     st = lb.stats()

@@ -353,6 +353,21 @@ int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double*
                   double* v, double* w, const double* f_ext, const double* t_ext,
                   double* f, double* t, const lub_step_t* step, void* stream);
 
+/* Kinematic advance between evaluations: the particles follow their own
+ * velocities with no forces (a prescribed flow such as simple shear moves
+ * the suspension from one time step to the next, Sec. III.A), one step of
+ * length dt:
+ *   r <- r + dt v
+ *   q <- normalise(q + dt/2 (0, w) q)   (quaternion product; a rotation by
+ *                                         2 atan(dt |w| / 2) about w)
+ * FP64.  r (n x 3), q (n x 4): device arrays updated in place; v, w (n x 3):
+ * device arrays.  Periodic axes are not wrapped (evaluations take positions
+ * outside the box by their images).  Asynchronous on `stream`.  LUB_EINVAL
+ * for n < 0, non-finite dt, a null array with n > 0 or a handle with host
+ * pointers. */
+int lub_advance(lub_handle_t h, int64_t n, double* r, double* q, const double* v,
+                const double* w, double dt, void* stream);
+
 /* Growth stage of the packing generator (Sec. IV.C): particles placed
  * without overlap at a reduced size grow linearly from scale0 to scale1
  * times their semi-axes over n_steps sub-steps (scale1 slightly above 1

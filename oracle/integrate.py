@@ -99,6 +99,19 @@ def update(r, q, semi, v, w, F, T, dt, density, damping, domain):
     return r, q, v, w
 
 
+def advance(r, q, v, w, dt):
+    """Kinematic advance by the particles' own velocities, no forces (the
+    motion between evaluations of a prescribed flow): r + dt v, and the
+    orientation q + dt/2 (0, w) q normalised (first-order step of
+    dq/dt = 1/2 (0, w) q, world-frame angular velocity).  Returns (r, q)."""
+    r = np.asarray(r, dtype=np.float64) + dt * np.asarray(v, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    wq = np.concatenate([np.zeros((len(w), 1)), w], axis=1)
+    qn = q + 0.5 * dt * quat_mul(wq, q)
+    return r, qn / np.linalg.norm(qn, axis=1)[:, None]
+
+
 def _domain_args(domain):
     return dict(L=tuple(domain.L[:]), periodic=tuple(domain.periodic[:]),
                 n_walls=domain.n_walls,

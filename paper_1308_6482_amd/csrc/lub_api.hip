@@ -436,12 +436,12 @@ CallDesc finalize_desc(lub_ctx* c, const CallDesc& d0) {
   d.list_epoch = c->list_epoch;
   d.cap_entries = (int32_t)std::min<int64_t>(c->cap_entries, INT32_MAX);
   d.cap_work = (int32_t)std::min<int64_t>(c->cap_work, INT32_MAX);
-  // the forward search's merge writes the partner codes itself; else, from
-  // about a quarter million particles, codes written beside the pair kernel
-  // save the gather its searches (below, the fork and join cost more than
-  // they save)
+  // the forward search leaves slot ranges and backward lists, no segments;
+  // else, from about a quarter million particles, partner codes written
+  // beside the pair kernel save the gather its searches (below, the fork
+  // and join cost more than they save)
   d.partner_codes = d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums, c->bstage)
-                        ? kPartnerMerge
+                        ? kPartnerRanges
                         : (d.n >= (1 << 18) ? kPartnerSide : kPartnerSearch);
   // Ladd's law has no closest-point iteration to start.  With reused lists
   // the normals are kept per superset entry, else per slot with each
@@ -545,7 +545,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     }
     mark(2);
     // the partner-slot codes beside the pair kernel
-    if (d.partner_codes == kPartnerSide) {
+    const bool side = d.partner_codes == kPartnerSide;
+    if (side) {
       HIP_TRY(hipEventRecord(c->ev_fork, s));
       HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
       launch_partner_slots(d, c->work_s, c->work_t, c->deg, c->nbr, c->slot, c->cnt, c->side);
@@ -573,9 +574,9 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                    timing ? ev[5] : nullptr, timing ? ev[6] : nullptr, c->detail);
     }
     mark(3);
-    if (d.partner_codes == kPartnerSide) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+    if (side) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
-                  c->cnt, next_cnt, f, t, s);
+                  c->cnt, next_cnt, f, t, s, c->bcount, c->bstage, c->work_s, c->work_t);
     mark(4);
     if (timing) c->pending.push_back(ev);
   }
@@ -1145,6 +1146,17 @@ int lub_integrate(lub_handle_t h, int64_t n, double* r, double* q, const double*
   return LUB_OK;
 }
 
+int lub_advance(lub_handle_t h, int64_t n, double* r, double* q, const double* v,
+                const double* w, double dt, void* stream) {
+  if (!h || n < 0 || n > (int64_t)1 << 30 || !std::isfinite(dt)) return LUB_EINVAL;
+  if (n > 0 && (!r || !q || !v || !w)) return LUB_EINVAL;
+  if (h->opt.host_pointers) return LUB_EINVAL;  // device arrays only
+  HIP_TRY(hipSetDevice(h->device));
+  launch_advance((int)n, dt, r, q, v, w, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return LUB_OK;
+}
+
 int lub_grow(lub_handle_t h, int64_t n, double* r, double* q, const double* semi,
              double* v, double* w, const lub_grow_t* cfg, void* stream) {
   if (!h || !cfg || n < 0 || n > (int64_t)1 << 30) return LUB_EINVAL;
@@ -1252,12 +1264,18 @@ int lub_get_pairs(lub_handle_t h, int64_t cap, int32_t* ij, int64_t* n_pairs,
   std::vector<int32_t> deg(n), sorted(n), wall_slot(2 * n);
   HIP_TRY(hipMemcpy(deg.data(), h->deg, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(sorted.data(), h->sorted, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  // segments hold each pair from both sides; after the forward search the
+  // slot rows hold each pair once, in its finder's forward list (flagged)
+  const bool ranges = h->last.partner_codes == kPartnerRanges;
   std::vector<int32_t> nbr(stride * n);
-  HIP_TRY(hipMemcpy(nbr.data(), h->nbr, sizeof(int32_t) * stride * n, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(nbr.data(), ranges ? h->slot : h->nbr, sizeof(int32_t) * stride * n,
+                    hipMemcpyDeviceToHost));
   std::vector<std::pair<int32_t, int32_t>> pairs;
   for (int s = 0; s < n; ++s)
-    for (int k = 0; k < deg[s]; ++k) {
-      int a = sorted[s], b = sorted[nbr[stride * s + k]];
+    for (int k = 0; k < std::min<int64_t>(deg[s], (int64_t)stride); ++k) {
+      const int e = nbr[stride * s + k];
+      int a = sorted[s], b = sorted[ranges ? (e & kIndexMask) : e];
+      if (ranges && b < a) std::swap(a, b);
       if (a < b) pairs.emplace_back(a, b);
     }
   std::sort(pairs.begin(), pairs.end());

@@ -110,6 +110,32 @@ __global__ void k_integrate(StepDesc s, double* __restrict__ r, double* __restri
   for (int k = 0; k < 4; ++k) q[4 * i + k] = qi[k];
 }
 
+// Kinematic advance: the particles follow their given velocities, with no
+// forces: r <- r + dt v, and the first-order orientation step
+// q <- normalise(q + dt/2 (0, w) q) with (0, w) q the quaternion product
+// (a rotation by 2 atan(dt |w| / 2) about w).  One thread per particle,
+// FP64, the terms in a fixed order.
+__global__ void k_advance(int n, double dt, double* __restrict__ r, double* __restrict__ q,
+                          const double* __restrict__ v, const double* __restrict__ w) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < 3; ++k) r[3 * i + k] = r[3 * i + k] + dt * v[3 * i + k];
+  const double q0 = q[4 * i], q1 = q[4 * i + 1], q2 = q[4 * i + 2], q3 = q[4 * i + 3];
+  const double w0 = w[3 * i], w1 = w[3 * i + 1], w2 = w[3 * i + 2];
+  const double h = 0.5 * dt;
+  // (0, w) q = (-w . q_v, q_0 w + w x q_v)
+  const double p0 = q0 + h * -(w0 * q1 + w1 * q2 + w2 * q3);
+  const double p1 = q1 + h * (q0 * w0 + (w1 * q3 - w2 * q2));
+  const double p2 = q2 + h * (q0 * w1 + (w2 * q1 - w0 * q3));
+  const double p3 = q3 + h * (q0 * w2 + (w0 * q2 - w1 * q1));
+  const double pn = sqrt(p0 * p0 + p1 * p1 + p2 * p2 + p3 * p3);
+  q[4 * i] = p0 / pn;
+  q[4 * i + 1] = p1 / pn;
+  q[4 * i + 2] = p2 / pn;
+  q[4 * i + 3] = p3 / pn;
+}
+
 __global__ void k_scale(int n, const double* __restrict__ semi, double scale,
                         double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,6 +150,12 @@ void launch_integrate(const StepDesc& s, double* r, double* q, const double* sem
   if (s.n <= 0) return;
   hipLaunchKernelGGL(k_integrate, dim3((s.n + 255) / 256), dim3(256), 0, st, s, r, q, semi,
                      v, w, f_ext, t_ext, f, t);
+}
+
+void launch_advance(int n, double dt, double* r, double* q, const double* v, const double* w,
+                    hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_advance, dim3((n + 255) / 256), dim3(256), 0, st, n, dt, r, q, v, w);
 }
 
 void launch_scale(int n, const double* semi, double scale, double* out, hipStream_t st) {

@@ -158,18 +158,28 @@ struct CallDesc {
   int32_t cap_entries;
   int32_t cap_work;
   int32_t precision;
-  int32_t partner_codes;  // kPartner*: who writes the slot code of an
-                          // evaluated pair into the partner's entry
+  int32_t partner_codes;  // kPartner*: how a particle's sum finds the
+                          // results of the pairs its partners evaluate
 };
 
-// The partner's entry of an evaluated pair: the gather searches the
-// partner's segment for the slot (small systems), or the code -3 - slot is
-// written into it by a kernel beside the pair pass (large systems) or by
-// the forward search's merge, which gives each pair a slot in the range of
-// the particle that found it.
+// How the gather finds a pair's result from the particle that does not
+// evaluate it.  With segments (both directions of every pair, sorted by
+// partner): by a binary search of the partner's segment (small systems), or
+// through the code -3 - slot written into its own entry by a kernel beside
+// the pair pass (large systems).  After the forward search no segments are
+// built (kPartnerRanges): each pair has a slot in the range of the particle
+// that found it, and the other particle reads it through its backward list
+// (finder, rank of the pair among the finder's kept pairs).
 constexpr int kPartnerSearch = 0;
 constexpr int kPartnerSide = 1;
-constexpr int kPartnerMerge = 2;
+constexpr int kPartnerRanges = 2;
+
+// The forward search's entries carry two flags above the partner index
+// (cell order): this entry's particle evaluates the pair (the smaller input
+// index), and the support-function bound lets the pair through.
+constexpr int32_t kOwnBit = 1 << 29;
+constexpr int32_t kKeepBit = 1 << 30;
+constexpr int32_t kIndexMask = kOwnBit - 1;
 
 // Pair output record: force on i, torque on i and torque on j about the
 // particle centres.
@@ -239,9 +249,12 @@ bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_
 // (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,
 // block_sums, scan scratch for n entries, and bstage, one int2 per segment
 // entry; given, the full search of large systems runs as a forward search, a
-// scan and a merge, which also writes the partner-slot codes; the events,
-// when given, take the search kernel's own start and end stamps: the full
-// search, the forward walk or the filter of reused lists)
+// scan of the kept counts and the evaluation list, and leaves the layout
+// kPartnerRanges: deg and the slot rows hold each particle's forward list
+// (partners with the flags), bstage and the first n words of bcount its
+// backward list, bcount[n ..] the slot offsets; the events, when given, take
+// the search kernel's own start and end stamps: the full search, the
+// forward walk or the filter of reused lists)
 // reused neighbour lists: the displacement plus growth since the search
 // (skipped unless the lists are of this epoch), then the decision (a
 // search if the lists are of another epoch or the measure exceeds half the
@@ -314,11 +327,15 @@ void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
 void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_t* work_t,
                           const int32_t* deg, const int32_t* nbr, int32_t* slot,
                           const Counters* cnt, hipStream_t s);
+// (bcount, bstage, work_s, work_t: read in the layout kPartnerRanges, where
+// the segment arguments are not)
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
-                   hipStream_t s);
+                   hipStream_t s, const int32_t* bcount = nullptr,
+                   const int2* bstage = nullptr, const int32_t* work_s = nullptr,
+                   const int32_t* work_t = nullptr);
 
 // ---- link-wise laws (lub_link.hip) ------------------------------------------
 int link_grid(const CallDesc& d);
@@ -341,6 +358,9 @@ void launch_integrate(const StepDesc& s, double* r, double* q, const double* sem
                       const double* f, const double* t, hipStream_t st);
 // out = scale * semi (n x 2)
 void launch_scale(int n, const double* semi, double scale, double* out, hipStream_t st);
+// r <- r + dt v, q <- normalise(q + dt/2 (0, w) q)
+void launch_advance(int n, double dt, double* r, double* q, const double* v, const double* w,
+                    hipStream_t st);
 
 // grid of the pair kernel for a given slot capacity
 int pair_grid(const CallDesc& d);

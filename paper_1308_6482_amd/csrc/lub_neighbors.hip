@@ -937,24 +937,20 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
 // a pair of one size class by the particle that comes first in cell order
 // (its own class's rows from its own row on, the ranges cut to later
 // indices), a small-large pair by the large particle (the small class
-// whole); the particle is appended to each partner's segment through an
-// atomic count, and k_nbr_merge merges those backward entries with the
-// forward ones.  About half the centre tests of the full search, and the
-// small particles (most of them) walk no rows of the sparse large class.
+// whole); the particle is appended to each partner's backward list through
+// an atomic count.  After a scan of the kept counts, k_nbr_emit writes the
+// evaluation list; no segments are built (the gather reads each particle's
+// slot range and backward list).  About half the centre tests of the full
+// search, and the small particles (most of them) walk no rows of the sparse
+// large class.
 constexpr int kFlatG = 16;
 constexpr int kFlatWaves = 4;
 constexpr int kFlatBuf = 256;  // candidate indices per group
 constexpr int kFwd = 3;        // mode of the forward search (partners later in cell order)
-// the forward search and merge from this many particles, with segments of
-// at most kFwdMaxNbr entries (LDS of the merge: 2 x 16 x 4 B per entry)
+// the forward search from this many particles, with at most kFwdMaxNbr
+// entries per particle (the gather's LDS: 2 x 4 B per entry and particle)
 constexpr int kFwdMinN = 1 << 15;
 constexpr int kFwdMaxNbr = 256;
-// the forward search hands the merge each entry with two flags above the
-// partner index: this segment's particle evaluates the pair (smaller input
-// index), and the support-function bound lets the pair through
-constexpr int32_t kOwnBit = 1 << 29;
-constexpr int32_t kKeepBit = 1 << 30;
-constexpr int32_t kIndexMask = kOwnBit - 1;
 
 // Workgroups are dealt to the eight XCDs in turn.  Renumbered so that each
 // XCD takes runs of kXcdRun consecutive blocks (particles close in cell
@@ -1454,129 +1450,95 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
                    s_deg, lb.warm_range);
 }
 
-// The merge of the forward search: each particle's segment is the sorted
-// union of its backward partners (written by the partners' forward searches
-// in no particular order) and its forward partners (sorted by the walk).
-// Every entry's slot code follows from its flags and the finder's range
-// (fbase[finder] + kk: the partner for a backward entry, this particle for a
-// forward one): the slot itself where this particle evaluates the pair, -3 -
-// slot where the partner does (the gather needs no search), -1 for a pair
-// the bound dropped.  The finder writes the evaluation list entries of
-// its kept pairs and walls.  No atomics, and a slot order that does not
-// depend on the schedule.  LDS: two max_nbr buffers per group (entries and
-// their slots).  bcount: [n] backward counts, [n] slot offsets, the int64
-// total; bstage: the backward entries with their kk, row by row.
-__global__ void __launch_bounds__(64 * kFlatWaves)
-k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, const int2* __restrict__ bstage,
-            int32_t* __restrict__ deg, int32_t* __restrict__ nbr, int32_t* __restrict__ slot,
-            int32_t* __restrict__ wall_slot, int32_t* __restrict__ work_s,
-            int32_t* __restrict__ work_t, int64_t* __restrict__ stat_nbr, Counters* cnt,
-            const int32_t* __restrict__ orig, int2* __restrict__ warm_range) {
-  constexpr int G = kFlatG;
-  constexpr int kPer = 64 / G;
-  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
-  extern __shared__ int4 s_merge[];  // int4: 16-B aligned rows
-  __shared__ int s_upper[kFlatWaves], s_wallc[kFlatWaves], s_deg[kFlatWaves];
+// The evaluation list of the forward search, from the scan of the kept
+// counts: each particle's range [fbase[s], fbase[s + 1]) holds its kept
+// forward pairs in the order of its forward list (the evaluating side
+// first), then its kept walls.  Also the wall codes, the range by input
+// index for the next call's warm start, the number of slots and the
+// statistics row.  No atomics; the slot order does not depend on the
+// schedule.  kEmitG lanes per particle, four entries each (a forward list
+// holds about ten entries, a handful of them kept).  bcount: [n] backward counts, [n] slot offsets, the int64
+// total.
+constexpr int kEmitG = 4;
+constexpr int kEmitWaves = 4;
+constexpr int kEmitPerBlock = kEmitWaves * 64 / kEmitG;
+
+__global__ void __launch_bounds__(64 * kEmitWaves)
+k_nbr_emit(CallDesc d, const int32_t* __restrict__ bcount, const int32_t* __restrict__ deg,
+           const int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
+           int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
+           int64_t* __restrict__ stat_nbr, Counters* cnt, const int32_t* __restrict__ orig,
+           int2* __restrict__ warm_range) {
+  constexpr int G = kEmitG;
+  __shared__ int s_cand[kEmitWaves], s_wallc[kEmitWaves], s_deg[kEmitWaves];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int grp = lane / G;
   const int gl = lane % G;
-  const int gbase = grp * G;
-  const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int s = (blk * kFlatWaves + wv) * kPer + grp;
+  const int gbase = lane - gl;
+  const int s = blockIdx.x * kEmitPerBlock + (int)(threadIdx.x / G);
   const bool live = s < d.n;
   const int maxn = d.max_nbr;
   const int32_t* kbase = bcount + d.n;
   const int64_t total = *reinterpret_cast<const int64_t*>(bcount + 2 * (size_t)d.n);
-  // stg: the backward entries (any order) then the forward ones (sorted);
-  // stk: the slot of each (meaningful for a kept pair)
-  int32_t* stg = reinterpret_cast<int32_t*>(s_merge) + (size_t)(wv * kPer + grp) * 2 * maxn;
-  int32_t* stk = stg + maxn;
-  // every per-particle word up front, with this lane's first backward and
-  // forward entries (rows hold max_nbr >= G entries), and right behind the
-  // first backward entry its finder's slot offset: two rounds of dependent
-  // loads in all
+  // every per-particle word up front, with this lane's first four forward
+  // entries (one 16-B load; rows hold max_nbr >= 64 entries, a multiple of
+  // 64)
   const size_t rbase = (size_t)(live ? s : 0) * maxn;
   const int nb = live ? bcount[s] : 0;
-  const int nf = live ? deg[s] : 0;
+  const int nf = live ? deg[s] : 0;  // the walk's count (beyond max_nbr: overflow)
   const int base = live ? kbase[s] : 0;
   const int64_t next = live ? (s + 1 < d.n ? (int64_t)kbase[s + 1] : total) : 0;
   const int w0 = live && d.n_walls ? wall_slot[2 * s] : -1;
   const int w1 = live && d.n_walls ? wall_slot[2 * s + 1] : -1;
-  const int2 b_first = live ? bstage[rbase + gl] : make_int2(0, 0);
-  const int sl_first = live ? slot[rbase + gl] : 0;
+  const int32_t* sl = slot + rbase;
+  const int4 e_first = live ? *reinterpret_cast<const int4*>(sl + 4 * gl) : make_int4(0, 0, 0, 0);
   const int me = live && warm_range ? orig[s] : 0;
-  const int kb_first = live && gl < nb ? kbase[b_first.x & kIndexMask] : 0;
   const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
   const bool overflow = live && need > maxn;
   if (overflow && gl == 0) set_error(cnt, LUB_ECAPACITY);
-  const int nent = (live && !overflow) ? need : 0;
-  const int nbk = nent ? nb : 0, nfk = nent ? nf : 0;
-  int32_t* row = nbr + rbase;
-  int32_t* sl = slot + rbase;
-  for (int k = gl; k < nbk; k += G) {
-    const int2 b = k == gl ? b_first : bstage[rbase + k];
-    stg[k] = b.x;
-    stk[k] = (k == gl ? kb_first : kbase[b.x & kIndexMask]) + b.y;
-  }
-  // the forward entries' slots: their rank among the kept ones, in order
-  int kept_fwd = 0;
-  for (int k0 = 0; k0 < nfk; k0 += G) {
-    const int k = k0 + gl;
-    const int raw = k < nfk ? (k == gl ? sl_first : sl[k]) : 0;
-    const bool kp = k < nfk && (raw & kKeepBit);
-    const unsigned long long mk = (__ballot(kp) >> gbase) & kGroupMask;
-    if (k < nfk) {
-      stg[nbk + k] = raw;
-      stk[nbk + k] = base + kept_fwd + lane_prefix(mk, gl);
+  // the kept forward pairs (the walk counted them over these entries), in
+  // chunks of 4 G: four consecutive entries per lane
+  const int nfk = live ? min(max(nf, 0), maxn) : 0;
+  int at = base;
+  for (int k0 = 0; k0 < nfk; k0 += 4 * G) {
+    const int kl = k0 + 4 * gl;
+    const int4 e4 = k0 == 0 ? e_first : *reinterpret_cast<const int4*>(sl + kl);
+    const int ev[4] = {e4.x, e4.y, e4.z, e4.w};
+    bool kp[4];
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      kp[j] = kl + j < nfk && (ev[j] & kKeepBit);
+      c += kp[j];
     }
-    kept_fwd += __popcll(mk);
-  }
-  __syncthreads();
-  int nupper = 0, nwallc = 0;
-  if (live) {
-    // the place of each entry in the segment: the backward entries below it
-    // (counted over the unsorted ones) plus the forward entries below it
-    // (its own index in the forward list, else a binary search there)
-    for (int k = gl; k < nent; k += G) {
-      const int raw = stg[k];
-      const int key = raw & kIndexMask;
-      int below = 0, m = 0;
-      for (; m + 4 <= nbk; m += 4) {
-        const int4 v = *reinterpret_cast<const int4*>(stg + m);
-        below += ((v.x & kIndexMask) < key) + ((v.y & kIndexMask) < key) +
-                 ((v.z & kIndexMask) < key) + ((v.w & kIndexMask) < key);
-      }
-      for (; m < nbk; ++m) below += (stg[m] & kIndexMask) < key;
-      const bool fwd = k >= nbk;
-      if (fwd) {
-        below += k - nbk;
-      } else {
-        int lo = 0, hi = nfk;  // forward entries below key: [0, lo)
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if ((stg[nbk + mid] & kIndexMask) < key)
-            lo = mid + 1;
-          else
-            hi = mid;
+    // exclusive prefix of the kept counts over the group's lanes
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int y = __shfl_up(incl, o, G);
+      if (gl >= o) incl += y;
+    }
+    const int tot = __shfl(incl, gbase + G - 1, 64);
+    int sid = at + incl - c;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (kp[j]) {
+        if (sid < d.cap_work) {
+          const bool own = ev[j] & kOwnBit;
+          const int key = ev[j] & kIndexMask;
+          work_s[sid] = own ? s : key;
+          work_t[sid] = own ? key : s;
         }
-        below += lo;
+        ++sid;
       }
-      const bool own = raw & kOwnBit, kp = raw & kKeepBit;
-      const int sid = stk[k];
-      row[below] = key;
-      sl[below] = kp ? (own ? sid : -3 - sid) : -1;
-      if (kp && fwd && sid < d.cap_work) {
-        work_s[sid] = own ? s : key;
-        work_t[sid] = own ? key : s;
-      }
-      nupper += own;
     }
-    if (gl == 0) deg[s] = nent;
+    at += tot;
+  }
+  int ncand = 0, nwallc = 0;
+  if (live) {
     // the kept walls after the kept forward pairs
-    int at = base + kept_fwd;
-    if (d.n_walls && nent == need) {
-      if (gl == 0) nwallc = (w0 != -1) + (w1 != -1);
+    if (d.n_walls) {
+      if (gl == 0 && !overflow) nwallc = (w0 != -1) + (w1 != -1);
       if (gl < 2 && (gl == 0 ? w0 : w1) == 0) {
         const int code = at + (gl == 1 && w0 == 0 ? 1 : 0);
         if (code < d.cap_work) {
@@ -1587,9 +1549,8 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, const int2* __restri
       }
       at += (w0 == 0) + (w1 == 0);
     }
-    // an overflowing segment leaves its range to harmless particle-wall
-    // slots (the call reports the overflow)
-    if (overflow) at = base;
+    // the range holds exactly these (the walk counted the same flags);
+    // anything left would get harmless particle-wall slots
     for (int64_t k = at + gl; k < next; k += G)
       if (k < d.cap_work) {
         work_s[k] = s;
@@ -1601,31 +1562,34 @@ k_nbr_merge(CallDesc d, const int32_t* __restrict__ bcount, const int2* __restri
       cnt->work = (int32_t)min<int64_t>(total, INT32_MAX);
       if (total > d.cap_work) set_error(cnt, LUB_ECAPACITY);
     }
+    // each pair is in the forward list of exactly one of its particles
+    if (gl == 0 && !overflow) ncand = nf;
   }
-  // the block's statistics row
-  int wup = nupper, wwall = nwallc, wdeg = live ? need : 0;
+  // the block's statistics row: candidate pairs, wall candidates, the
+  // largest number of entries of one particle
+  int wc = ncand, ww = nwallc, wd = live && gl == 0 ? need : 0;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
-    wup += __shfl_xor(wup, o, 64);
-    wwall += __shfl_xor(wwall, o, 64);
-    wdeg = max(wdeg, __shfl_xor(wdeg, o, 64));
+    wc += __shfl_xor(wc, o, 64);
+    ww += __shfl_xor(ww, o, 64);
+    wd = max(wd, __shfl_xor(wd, o, 64));
   }
   if (lane == 0) {
-    s_upper[wv] = wup;
-    s_wallc[wv] = wwall;
-    s_deg[wv] = wdeg;
+    s_cand[wv] = wc;
+    s_wallc[wv] = ww;
+    s_deg[wv] = wd;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int up = 0, wc = 0, dg = 0;
-    for (int k = 0; k < kFlatWaves; ++k) {
-      up += s_upper[k];
-      wc += s_wallc[k];
+    int c = 0, w = 0, dg = 0;
+    for (int k = 0; k < kEmitWaves; ++k) {
+      c += s_cand[k];
+      w += s_wallc[k];
       dg = max(dg, s_deg[k]);
     }
-    stat_nbr[kStatNbrWords * blk] = up;
-    stat_nbr[kStatNbrWords * blk + 1] = wc;
-    stat_nbr[kStatNbrWords * blk + 2] = dg;
+    stat_nbr[kStatNbrWords * blockIdx.x] = c;
+    stat_nbr[kStatNbrWords * blockIdx.x + 1] = w;
+    stat_nbr[kStatNbrWords * blockIdx.x + 2] = dg;
   }
 }
 
@@ -1765,8 +1729,9 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
       int32_t* kcnt = bcount + d.n;
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
-      hipLaunchKernelGGL(k_nbr_merge, grid_f, block_f, 2 * lds_f, s, d, bcount, bstage, deg, nbr,
-                         slot, wall_slot, work_s, work_t, stat_nbr, cnt, orig, lb.warm_range);
+      hipLaunchKernelGGL(k_nbr_emit, dim3((d.n + kEmitPerBlock - 1) / kEmitPerBlock),
+                         dim3(64 * kEmitWaves), 0, s, d, bcount, deg, slot, wall_slot, work_s,
+                         work_t, stat_nbr, cnt, orig, lb.warm_range);
     } else if (mode == 0) {
       hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
                             d, rec, recp, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
@@ -1941,8 +1906,10 @@ bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_
 }
 
 // blocks of the kernel that writes a call's statistics rows: the filter of
-// reused lists, the Lees-Edwards search, else the flattened search
+// reused lists, the Lees-Edwards search, the evaluation list of the forward
+// search, else the flattened search
 int nbr_blocks(const CallDesc& d) {
+  if (d.partner_codes == kPartnerRanges) return (d.n + kEmitPerBlock - 1) / kEmitPerBlock;
   return d.skin > 0.0 || !nbr_flat(d) ? nbr_blocks_group(d) : nbr_blocks_flat(d);
 }
 

@@ -714,7 +714,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
         // one's range first
         const int is = warm.orig[s], it = warm.orig[t];
         key = is ^ it;
-        const bool s_first = cd.partner_codes != kPartnerMerge || s < t;
+        const bool s_first = cd.partner_codes != kPartnerRanges || s < t;
         const int2 ra = warm.prev_range[s_first ? is : it];
         const int2 rb = warm.prev_range[s_first ? it : is];
         for (int side = 0; side < 2 && !found; ++side) {

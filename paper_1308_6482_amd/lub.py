@@ -23,7 +23,8 @@ EXPORTS = ["lub_create", "lub_set_params", "lub_set_domain", "lub_compute",
            "lub_get_stats", "lub_reset_timers", "lub_get_pairs",
            "lub_get_pair_results", "lub_mlp_set_weights", "lub_mlp_get_weights",
            "lub_mlp_init", "lub_mlp_forward", "lub_mlp_grad", "lub_mlp_train",
-           "lub_get_domain", "lub_integrate", "lub_grow", "lub_compute_static",
+           "lub_get_domain", "lub_integrate", "lub_advance", "lub_grow",
+           "lub_compute_static",
            "lub_mlp_save", "lub_mlp_load", "lub_get_pair_detail",
            "lub_destroy", "lub_strerror"]
 LUB_MLP_PARAMS = 34948
@@ -139,6 +140,7 @@ def lib():
         L.lub_get_domain.argtypes = [_P, C.POINTER(lub_domain_t)]
         L.lub_integrate.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                     C.POINTER(lub_step_t), _P]
+        L.lub_advance.argtypes = [_P, C.c_int64, _P, _P, _P, _P, C.c_double, _P]
         L.lub_grow.argtypes = [_P, C.c_int64, _P, _P, _P, _P, _P, C.POINTER(lub_grow_t), _P]
         L.lub_compute_static.argtypes = [C.POINTER(lub_domain_t), C.POINTER(lub_params_t),
                                          C.POINTER(lub_opts_t), C.c_int64, _P, _P, _P, _P,
@@ -308,6 +310,17 @@ def lub_integrate(h, r, q, semi, v, w, f, t, dt, n_sub, density=1.0, damping=0.0
     st = lub_step_t(float(dt), int(n_sub), 0, float(density), float(damping))
     _check(lib().lub_integrate(h, n, *ptrs, *ext, *out, C.byref(st), _stream_handle(stream)),
            "lub_integrate")
+
+
+def lub_advance(h, r, q, v, w, dt, stream=None):
+    """Kinematic advance: r += dt v, q <- normalise(q + dt/2 (0, w) q), in
+    place (float64 torch.cuda tensors)."""
+    n = r.shape[0]
+    for a, cols in ((r, 3), (q, 4), (v, 3), (w, 3)):
+        if a.shape != (n, cols):
+            raise ValueError(f"bad shape {tuple(a.shape)}, expected ({n},{cols})")
+    ptrs = [_ptr(x) if n > 0 else 0 for x in (r, q, v, w)]
+    _check(lib().lub_advance(h, n, *ptrs, float(dt), _stream_handle(stream)), "lub_advance")
 
 
 def lub_grow(h, r, q, semi, v, w, n_steps, scale0, scale1, dt, density=1.0, damping=0.0,
@@ -516,6 +529,9 @@ class Lub:
         if d.lees_edwards:
             self.domain_args["lees_edwards"] = (d.le_offset, d.le_velocity)
         return f, t
+
+    def advance(self, r, q, v, w, dt, stream=None):
+        lub_advance(self.h, r, q, v, w, dt, stream)
 
     def grow(self, r, q, semi, v, w, **kw):
         lub_grow(self.h, r, q, semi, v, w, **kw)

@@ -109,7 +109,7 @@ def test_fullscale_warm_trajectory_sampled(ref):
         lb.compute(r, q, semi, v, w)
         st = lb.stats()
         if k < 2:
-            bench.advance(r, q, v, w, 1.0)
+            bench.advance(lb, r, q, v, w, 1.0)
     torch.cuda.synchronize()
     assert st["warm_seeded"] > 0.8 * (st["evaluated"] - st["wall_candidates"])
     res = lb.pair_results()

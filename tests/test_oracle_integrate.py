@@ -14,6 +14,11 @@ the contact-only law used by the growth stage (Sec. IV.C).
   and loses the image velocity; the offset advances by U dt per sub-step.
 * Contact-only law: sphere pair F = -eps_c (h_c - h) n on i for 0 < h <= h_c,
   -eps_c h_c for overlaps, nothing beyond h_c, no torque.
+* Kinematic advance with a constant angular velocity w: 1 + dt/2 (0, w) is
+  sqrt(1 + a^2) times the unit quaternion of a rotation by 2 atan(a) about
+  w (a = dt |w| / 2), so after N steps q_N = (cos N phi, sin N phi w/|w|) q_0
+  with phi = atan(a) (left product: the rotation acts in the world frame),
+  and r_N = r_0 + N dt v.
 """
 import numpy as np
 import pytest
@@ -167,3 +172,39 @@ def test_contact_only_law(ref, h):
     Fr = ec * (hc - h) if h > 0 else ec * hc
     assert np.allclose(o["F"], -Fr * u, rtol=1e-12, atol=1e-12)
     assert np.allclose(o["Ti"], 0, atol=1e-10 * Fr) and np.allclose(o["Tj"], 0, atol=1e-10 * Fr)
+
+
+def test_advance_closed_form():
+    rng = np.random.default_rng(7)
+    n, N, dt = 6, 25, 0.3
+    r0 = rng.normal(size=(n, 3)) * 50.0
+    q0 = rng.normal(size=(n, 4))
+    q0 /= np.linalg.norm(q0, axis=1)[:, None]
+    v = rng.normal(size=(n, 3))
+    w = rng.normal(size=(n, 3)) * 0.2
+    r, q = r0, q0
+    for _ in range(N):
+        r, q = I.advance(r, q, v, w, dt)
+    wn = np.linalg.norm(w, axis=1)
+    phi = N * np.arctan(0.5 * dt * wn)
+    rot = np.concatenate([np.cos(phi)[:, None], np.sin(phi)[:, None] * w / wn[:, None]], axis=1)
+    assert np.allclose(q, I.quat_mul(rot, q0), rtol=0, atol=1e-13)
+    # the right product (body-frame rotation) differs for these orientations
+    assert not np.allclose(q, I.quat_mul(q0, rot), rtol=0, atol=1e-3)
+    assert np.allclose(r, r0 + N * dt * v, rtol=1e-14, atol=1e-12)
+    # the symmetry axis turns about w by 2 N phi (Rodrigues)
+    a0, a = I.body_axes(q0), I.body_axes(q)
+    k = w / wn[:, None]
+    th = 2.0 * phi
+    rod = (a0 * np.cos(th)[:, None] + np.cross(k, a0) * np.sin(th)[:, None]
+           + k * (np.sum(k * a0, axis=1) * (1.0 - np.cos(th)))[:, None])
+    assert np.allclose(a, rod, rtol=0, atol=1e-12)
+
+
+def test_advance_zero_spin_keeps_orientation():
+    rng = np.random.default_rng(8)
+    q0 = rng.normal(size=(4, 4))
+    q0 /= np.linalg.norm(q0, axis=1)[:, None]
+    r, q = I.advance(np.zeros((4, 3)), q0, np.ones((4, 3)), np.zeros((4, 3)), 2.0)
+    assert np.array_equal(q, q0 / np.linalg.norm(q0, axis=1)[:, None])
+    assert np.array_equal(r, np.full((4, 3), 2.0))
