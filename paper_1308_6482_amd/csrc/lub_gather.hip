@@ -147,71 +147,48 @@ __global__ void __launch_bounds__(64 * kWaves) k_gather(
 
 // After the forward search (large systems): a particle's evaluation slots
 // [fbase[s], fbase[s + 1]) hold the pairs its forward search found (work_s
-// names the evaluating side) and its walls; the pairs its partners found
-// sit in their ranges, at fbase[finder] + kk, with (finder and flags, kk) in
-// this particle's row of bstage in an order set by the search's atomics.  A
-// group sums the own range in slot order, then ranks the kept backward
-// entries by finder index in LDS and sums them in that order, so that the
-// sums do not depend on the schedule.  LDS per group: max_nbr keys and
-// max_nbr ranked slot codes, shared by the group's own lanes only: a
-// wavefront-scope fence orders them (no workgroup barrier, which would also
-// wait for every global load in flight).
+// names the evaluating side) and its walls; the slot codes of the pairs its
+// partners found (slot where this particle evaluates, else -1 - slot) are
+// in its nbr row in increasing finder index, bcount[s] of them.  A group
+// sums the own range in slot order, then those codes in row order: sums
+// that do not depend on the search's schedule.
 constexpr int kRangeGroup = 8;
-constexpr int kRangeWaves = 1;
+constexpr int kRangeWaves = 4;
 constexpr int kRangePerBlock = kRangeWaves * 64 / kRangeGroup;
-
-// LDS written by lanes of this wavefront is visible to its other lanes
-// after this point
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename R>
 __global__ void __launch_bounds__(64 * kRangeWaves) k_gather_ranges(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ bcount,
-    const int2* __restrict__ bstage, const int32_t* __restrict__ work_s,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ work_s,
     const int32_t* __restrict__ work_t, const PairOut<R>* __restrict__ out,
     const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
     double* __restrict__ t) {
   constexpr int G = kRangeGroup;
-  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
-  extern __shared__ int32_t s_rank[];
   const int lane = threadIdx.x & 63;
   const int g = lane % G;
-  const int gbase = lane - g;
-  const int grp = (int)(threadIdx.x / G);
-  const int s = blockIdx.x * kRangePerBlock + grp;
+  const int s = blockIdx.x * kRangePerBlock + (int)(threadIdx.x / G);
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < (int)(sizeof(Counters) / sizeof(int32_t));
          i += blockDim.x)
       reinterpret_cast<int32_t*>(next_cnt)[i] = 0;
   const bool live = s < d.n;
-  // without an error every backward list fits its row and every slot the
-  // capacity (the search checked both)
+  // without an error every slot lies below the capacity (the search checked)
   const bool ok = live && cnt->error == 0;
   const int maxn = d.max_nbr;
   const int32_t* kbase = bcount + d.n;
-  int32_t* keys = s_rank + (size_t)grp * 2 * maxn;
-  int32_t* codes = keys + maxn;
-  // the per-particle words and this lane's first two backward entries up
-  // front (a row holds max_nbr >= 2 kRangeGroup entries; those past the
-  // count are not used), their finders' slot offsets right behind them
+  // the per-particle words and this lane's first two codes up front (a row
+  // holds max_nbr >= 2 kRangeGroup entries; those past the count are not
+  // used): one round of loads, then one for the records
   const size_t rbase = (size_t)(ok ? s : 0) * maxn;
-  const int nb = ok ? bcount[s] : 0;
+  const int nk = ok ? bcount[s] : 0;
   const int base = ok ? kbase[s] : 0;
   const int next =
       ok ? (s + 1 < d.n ? kbase[s + 1]
                         : (int)*reinterpret_cast<const int64_t*>(bcount + 2 * (size_t)d.n))
          : 0;
   const int p = live ? orig[s] : 0;
-  const int2 b0r = ok ? bstage[rbase + g] : make_int2(0, 0);
-  const int2 b1r = ok ? bstage[rbase + g + G] : make_int2(0, 0);
-  const int2 b0 = g < nb ? b0r : make_int2(0, 0);
-  const int2 b1 = g + G < nb ? b1r : make_int2(0, 0);
-  const int kb0 = (b0.x & kKeepBit) ? kbase[b0.x & kIndexMask] : 0;
-  const int kb1 = (b1.x & kKeepBit) ? kbase[b1.x & kIndexMask] : 0;
+  const int c0 = ok ? nbr[rbase + g] : 0;
+  const int c1 = ok ? nbr[rbase + g + G] : 0;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   // the own range: pairs this particle found (either side evaluates) and
   // its walls
@@ -219,32 +196,9 @@ __global__ void __launch_bounds__(64 * kRangeWaves) k_gather_ranges(
     const int ws = work_s[w], wt = work_t[w];
     add_pair(acc, out[w], wt < 0 || ws == s);
   }
-  // the backward entries' keys: kept ones by finder index, dropped ones
-  // after every index
-  int nkept = 0;
-  for (int k0 = 0; k0 < nb; k0 += G) {
-    const int k = k0 + g;
-    const int bx = k < nb ? (k0 == 0 ? b0.x : k0 == G ? b1.x : bstage[rbase + k].x) : 0;
-    const bool kp = k < nb && (bx & kKeepBit);
-    if (k < nb) keys[k] = kp ? (bx & kIndexMask) : INT32_MAX;
-    nkept += __popcll((__ballot(kp) >> gbase) & kGroupMask);
-  }
-  wave_lds_sync();
-  // each kept entry's rank among the kept ones (the finders are distinct):
-  // its slot code goes there (>= 0: this particle evaluates, else -1 - slot)
-  for (int k = g; k < nb; k += G) {
-    const int2 b = k < G ? b0 : k < 2 * G ? b1 : bstage[rbase + k];
-    if (b.x & kKeepBit) {
-      const int key = b.x & kIndexMask;
-      int r = 0;
-      for (int m = 0; m < nb; ++m) r += keys[m] < key;
-      const int sid = (k < G ? kb0 : k < 2 * G ? kb1 : kbase[key]) + b.y;
-      codes[r] = (b.x & kOwnBit) ? sid : -1 - sid;
-    }
-  }
-  wave_lds_sync();
-  for (int r = g; r < nkept; r += G) {
-    const int c = codes[r];
+  // the pairs its partners found
+  for (int r = g; r < nk; r += G) {
+    const int c = r < G ? c0 : r < 2 * G ? c1 : nbr[rbase + r];
     const int w = c >= 0 ? c : -1 - c;
     if (w < d.cap_work) add_pair(acc, out[w], c >= 0);
   }
@@ -276,17 +230,16 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
-                   hipStream_t s, const int32_t* bcount, const int2* bstage,
-                   const int32_t* work_s, const int32_t* work_t) {
+                   hipStream_t s, const int32_t* bcount, const int32_t* work_s,
+                   const int32_t* work_t) {
   if (d.n == 0) return;
   if (d.partner_codes == kPartnerRanges) {
     const dim3 grid((d.n + kRangePerBlock - 1) / kRangePerBlock), block(64 * kRangeWaves);
-    const size_t lds = 2 * sizeof(int32_t) * kRangePerBlock * (size_t)d.max_nbr;
     if (d.precision == LUB_MIXED)
-      hipLaunchKernelGGL(k_gather_ranges<float>, grid, block, lds, s, d, orig, bcount, bstage,
+      hipLaunchKernelGGL(k_gather_ranges<float>, grid, block, 0, s, d, orig, bcount, nbr,
                          work_s, work_t, (const PairOut<float>*)out, cnt, next_cnt, f, t);
     else
-      hipLaunchKernelGGL(k_gather_ranges<double>, grid, block, lds, s, d, orig, bcount, bstage,
+      hipLaunchKernelGGL(k_gather_ranges<double>, grid, block, 0, s, d, orig, bcount, nbr,
                          work_s, work_t, (const PairOut<double>*)out, cnt, next_cnt, f, t);
     return;
   }

@@ -251,8 +251,10 @@ bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_
 // entry; given, the full search of large systems runs as a forward search, a
 // scan of the kept counts and the evaluation list, and leaves the layout
 // kPartnerRanges: deg and the slot rows hold each particle's forward list
-// (partners with the flags), bstage and the first n words of bcount its
-// backward list, bcount[n ..] the slot offsets; the events, when given, take
+// (partners with the flags), bcount[n ..] the slot offsets, and the first n
+// words of bcount the number of its partners' kept pairs, whose slot codes
+// (slot, or -1 - slot where the partner evaluates) its nbr row holds in
+// increasing finder index; the events, when given, take
 // the search kernel's own start and end stamps: the full search, the
 // forward walk or the filter of reused lists)
 // reused neighbour lists: the displacement plus growth since the search
@@ -327,15 +329,14 @@ void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
 void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_t* work_t,
                           const int32_t* deg, const int32_t* nbr, int32_t* slot,
                           const Counters* cnt, hipStream_t s);
-// (bcount, bstage, work_s, work_t: read in the layout kPartnerRanges, where
-// the segment arguments are not)
+// (bcount, work_s, work_t: read in the layout kPartnerRanges, with the nbr
+// rows, where deg, slot and wall_slot are not)
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
                    hipStream_t s, const int32_t* bcount = nullptr,
-                   const int2* bstage = nullptr, const int32_t* work_s = nullptr,
-                   const int32_t* work_t = nullptr);
+                   const int32_t* work_s = nullptr, const int32_t* work_t = nullptr);
 
 // ---- link-wise laws (lub_link.hip) ------------------------------------------
 int link_grid(const CallDesc& d);
@@ -374,6 +375,15 @@ void launch_stats_reduce(const CallDesc& d, Counters* cnt, const int64_t* stat_p
                          const int64_t* stat_nbr, hipStream_t s);
 
 #ifdef __HIPCC__
+// LDS written by lanes of this wavefront is visible to its other lanes
+// after this point (no workgroup barrier: that would also wait for every
+// global load in flight)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Minimum-image displacement along a periodic axis, dx - L rint(dx / L),
 // with the quotient taken as dx (1/L): the two round to different integers
 // only next to a half-integer, and there the division itself decides.

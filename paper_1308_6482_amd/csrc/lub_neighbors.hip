@@ -1455,21 +1455,29 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
 // forward pairs in the order of its forward list (the evaluating side
 // first), then its kept walls.  Also the wall codes, the range by input
 // index for the next call's warm start, the number of slots and the
-// statistics row.  No atomics; the slot order does not depend on the
-// schedule.  kEmitG lanes per particle, four entries each (a forward list
-// holds about ten entries, a handful of them kept).  bcount: [n] backward counts, [n] slot offsets, the int64
-// total.
-constexpr int kEmitG = 4;
+// statistics row; and, for the gather, the slot codes of the kept pairs its
+// partners found (fbase[finder] + kk; -1 - slot where the partner
+// evaluates) in increasing finder index in its nbr row, with their number
+// in bcount[s]: the backward rows are in the order of the search's atomics,
+// the sums must not be.  No atomics; nothing depends on the schedule.
+// kEmitG lanes per particle, four entries each (a forward list holds about
+// ten entries, a handful of them kept; a backward list about as many, a few
+// dozen next to large particles), the backward entries ranked in registers.
+// No LDS.  bcount: [n] backward counts, [n] slot offsets,
+// the int64 total.
+constexpr int kEmitG = 8;
 constexpr int kEmitWaves = 4;
 constexpr int kEmitPerBlock = kEmitWaves * 64 / kEmitG;
 
 __global__ void __launch_bounds__(64 * kEmitWaves)
-k_nbr_emit(CallDesc d, const int32_t* __restrict__ bcount, const int32_t* __restrict__ deg,
-           const int32_t* __restrict__ slot, int32_t* __restrict__ wall_slot,
+k_nbr_emit(CallDesc d, int32_t* __restrict__ bcount, const int32_t* __restrict__ deg,
+           const int32_t* __restrict__ slot, const int2* __restrict__ bstage,
+           int32_t* __restrict__ nbr, int32_t* __restrict__ wall_slot,
            int32_t* __restrict__ work_s, int32_t* __restrict__ work_t,
            int64_t* __restrict__ stat_nbr, Counters* cnt, const int32_t* __restrict__ orig,
            int2* __restrict__ warm_range) {
   constexpr int G = kEmitG;
+  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
   __shared__ int s_cand[kEmitWaves], s_wallc[kEmitWaves], s_deg[kEmitWaves];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -1492,6 +1500,12 @@ k_nbr_emit(CallDesc d, const int32_t* __restrict__ bcount, const int32_t* __rest
   const int w1 = live && d.n_walls ? wall_slot[2 * s + 1] : -1;
   const int32_t* sl = slot + rbase;
   const int4 e_first = live ? *reinterpret_cast<const int4*>(sl + 4 * gl) : make_int4(0, 0, 0, 0);
+  // and its first four backward entries (two 16-B loads; a bstage row holds
+  // max_nbr entries, 16-B aligned)
+  const int4 bA = live ? *reinterpret_cast<const int4*>(bstage + rbase + 4 * gl)
+                       : make_int4(0, 0, 0, 0);
+  const int4 bB = live ? *reinterpret_cast<const int4*>(bstage + rbase + 4 * gl + 2)
+                       : make_int4(0, 0, 0, 0);
   const int me = live && warm_range ? orig[s] : 0;
   const int need = (nb < 0 || nf < 0) ? maxn + 1 : nb + nf;
   const bool overflow = live && need > maxn;
@@ -1565,6 +1579,90 @@ k_nbr_emit(CallDesc d, const int32_t* __restrict__ bcount, const int32_t* __rest
     // each pair is in the forward list of exactly one of its particles
     if (gl == 0 && !overflow) ncand = nf;
   }
+  // the partners' kept pairs: each kept entry's rank by finder index among
+  // the kept ones (the finders are distinct) is where its slot code goes.
+  // Chunks of 4 G entries, four consecutive ones per lane, compared chunk
+  // against chunk through shuffles within the group; the first chunk comes
+  // with the per-particle words, its finders' slot offsets loaded together.
+  const int nbk = live && !overflow ? nb : 0;
+  int key0[4], y0[4], kb0[4];  // key: INT32_MAX for a dropped or absent entry
+  bool own0[4];
+  {
+    const int ex[4] = {bA.x, bA.z, bB.x, bB.z};
+    const int ey[4] = {bA.y, bA.w, bB.y, bB.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool kp = 4 * gl + j < nbk && (ex[j] & kKeepBit);
+      key0[j] = kp ? (ex[j] & kIndexMask) : INT32_MAX;
+      kb0[j] = kp ? kbase[key0[j]] : 0;
+      y0[j] = ey[j];
+      own0[j] = ex[j] & kOwnBit;
+    }
+  }
+  int nkept = 0;
+  for (int c1 = 0; c1 < nbk; c1 += 4 * G) {
+    int key1[4], y1[4], kb1[4];
+    bool own1[4];
+    if (c1 == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        key1[j] = key0[j];
+        y1[j] = y0[j];
+        kb1[j] = kb0[j];
+        own1[j] = own0[j];
+      }
+    } else {
+      const int4 u = *reinterpret_cast<const int4*>(bstage + rbase + c1 + 4 * gl);
+      const int4 v = *reinterpret_cast<const int4*>(bstage + rbase + c1 + 4 * gl + 2);
+      const int ex[4] = {u.x, u.z, v.x, v.z};
+      const int ey[4] = {u.y, u.w, v.y, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool kp = c1 + 4 * gl + j < nbk && (ex[j] & kKeepBit);
+        key1[j] = kp ? (ex[j] & kIndexMask) : INT32_MAX;
+        kb1[j] = kp ? kbase[key1[j]] : 0;
+        y1[j] = ey[j];
+        own1[j] = ex[j] & kOwnBit;
+      }
+    }
+    int r[4] = {0, 0, 0, 0};
+    for (int c2 = 0; c2 < nbk; c2 += 4 * G) {
+      int key2[4];
+      if (c2 == c1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) key2[j] = key1[j];
+      } else if (c2 == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) key2[j] = key0[j];
+      } else {
+        const int4 u = *reinterpret_cast<const int4*>(bstage + rbase + c2 + 4 * gl);
+        const int4 v = *reinterpret_cast<const int4*>(bstage + rbase + c2 + 4 * gl + 2);
+        const int ex[4] = {u.x, u.z, v.x, v.z};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          key2[j] = c2 + 4 * gl + j < nbk && (ex[j] & kKeepBit) ? (ex[j] & kIndexMask)
+                                                                : INT32_MAX;
+      }
+#pragma unroll
+      for (int l = 0; l < G; ++l)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int kk = __shfl(key2[jj], gbase + l, 64);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) r[j] += kk < key1[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (key1[j] != INT32_MAX) {
+        const int sid = kb1[j] + y1[j];
+        nbr[rbase + r[j]] = own1[j] ? sid : -1 - sid;
+        ++nkept;
+      }
+  }
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) nkept += __shfl_xor(nkept, o, G);
+  if (live && gl == 0) bcount[s] = nkept;
   // the block's statistics row: candidate pairs, wall candidates, the
   // largest number of entries of one particle
   int wc = ncand, ww = nwallc, wd = live && gl == 0 ? need : 0;
@@ -1730,8 +1828,8 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
       launch_scan(kcnt, kcnt, d.n, block_sums,
                   reinterpret_cast<int64_t*>(bcount + 2 * (size_t)d.n), s);
       hipLaunchKernelGGL(k_nbr_emit, dim3((d.n + kEmitPerBlock - 1) / kEmitPerBlock),
-                         dim3(64 * kEmitWaves), 0, s, d, bcount, deg, slot, wall_slot, work_s,
-                         work_t, stat_nbr, cnt, orig, lb.warm_range);
+                         dim3(64 * kEmitWaves), 0, s, d, bcount, deg, slot, bstage, nbr,
+                         wall_slot, work_s, work_t, stat_nbr, cnt, orig, lb.warm_range);
     } else if (mode == 0) {
       hipExtLaunchKernelGGL(k_neighbors_flat<0>, grid_f, block_f, 0, s, ev_start, ev_stop, 0,
                             d, rec, recp, pos, orig, cell_sorted, cell_start, deg, nbr, slot,
