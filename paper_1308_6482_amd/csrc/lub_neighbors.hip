@@ -1643,8 +1643,10 @@ k_nbr_emit(CallDesc d, int32_t* __restrict__ bcount, const int32_t* __restrict__
           key2[j] = c2 + 4 * gl + j < nbk && (ex[j] & kKeepBit) ? (ex[j] & kIndexMask)
                                                                 : INT32_MAX;
       }
-#pragma unroll
-      for (int l = 0; l < G; ++l)
+      // only the lanes that hold entries of this chunk (a list holds about
+      // ten: most chunks end after three lanes)
+      const int lanes = min(G, (nbk - c2 + 3) >> 2);
+      for (int l = 0; l < lanes; ++l)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int kk = __shfl(key2[jj], gbase + l, 64);
