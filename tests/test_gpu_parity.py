@@ -203,6 +203,36 @@ def test_config3_full(ref):
     assert ef.max() < 1e-5 and et.max() < 1e-5, (ef.max(), et.max())
 
 
+@pytest.mark.timeout(600)
+def test_long_backward_lists(ref):
+    """33,000 unit spheres at volume fraction 0.25 with a cut-off of 5 (about
+    86 partners each, so that most particles find more than 32 of their
+    pairs in their partners' searches): the forward search's backward lists
+    are ranked over several chunks.  Every pair and particle against the
+    oracle."""
+    rng = np.random.default_rng(21)
+    n = 33000
+    semi = np.ones((n, 2))
+    Lx = (n * 4.0 / 3.0 * np.pi / 0.25) ** (1.0 / 3.0)
+    r, q, _ = W.rsa(rng, semi, (Lx, Lx, Lx), (1, 1, 1))
+    assert r.shape[0] == n
+    wl = small("spheres33000_cut5", r, q, semi, rng.normal(size=(n, 3)),
+               rng.normal(size=(n, 3)), L_=(Lx, Lx, Lx), delta_n=5.0, delta_t=5.0,
+               delta_r=2.0, h_c=0.01, eps_c=100.0)
+    g = run_gpu(wl, L.LUB_MIXED)
+    assert g["stats"]["error"] == 0
+    assert g["stats"]["max_degree"] > 80, g["stats"]["max_degree"]
+    o = run_oracle(ref, wl)
+    check_pairs(g, o)
+    eF, eT, ha, act = per_pair_errors(ref, wl, g, o)
+    gate = act & (ha >= 1e-3)
+    print(f"pairs evaluated={len(act)} active={act.sum()} max degree="
+          f"{g['stats']['max_degree']} max eF={eF[gate].max():.3e} eT={eT[gate].max():.3e}")
+    assert eF[gate].max() < 1e-5 and eT[gate].max() < 1e-5
+    ef, et = particle_errors(g, o, ref, wl)
+    assert ef.max() < 1e-5 and et.max() < 1e-5, (ef.max(), et.max())
+
+
 def small(name, r, q, semi, v, w, L_=(60.0, 60.0, 60.0), periodic=(1, 1, 1),
           n_walls=0, **params):
     p = dict(mu=1.0 / 6.0, delta_n=0.67, delta_t=0.5, delta_r=0.25, h_c=0.0, eps_c=0.0)
