@@ -479,7 +479,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     }
   }
   auto mark = [&](int k) {
-    if (timing) hipEventRecord(ev[k], s);
+    if (timing) (void)hipEventRecord(ev[k], s);  // timing only: best effort
   };
   mark(0);
   // this call's counters: the set the previous call's last kernel zeroed
@@ -564,8 +564,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_links(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h, c->out_status,
                    c->out_links, c->stat_pair, c->cnt, s);
       if (timing) {  // no separate kernel stamps: the stage time
-        hipEventRecord(ev[5], s);
-        hipEventRecord(ev[6], s);
+        (void)hipEventRecord(ev[5], s);
+        (void)hipEventRecord(ev[6], s);
       }
     } else {
       launch_pairs(d, c->recp, c->kin, c->work_s, c->work_t, seeds, c->out,
@@ -617,8 +617,9 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
 void drop_graphs(lub_ctx* c) {
   for (auto& g : c->graphs) {
     if (g.exec) {
-      hipStreamSynchronize((hipStream_t)g.args[7]);  // no replay in flight
-      hipGraphExecDestroy(g.exec);
+      // teardown: nothing to report an error to
+      (void)hipStreamSynchronize((hipStream_t)g.args[7]);  // no replay in flight
+      (void)hipGraphExecDestroy(g.exec);
     }
     g = lub_ctx::GraphSlot();
   }
@@ -650,12 +651,12 @@ int run_graph(lub_ctx* c, const CallDesc& d0, const double* r, const double* q,
     // the capture only recorded the launches: restore the state a replay sets
     c->zeroed = true;
     if (rc || e != hipSuccess) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);  // the capture's error is returned
       c->zeroed = false;
       return rc ? rc : hip_err(e);
     }
     const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);  // the instantiation's error is returned
     if (ei != hipSuccess) {
       g = lub_ctx::GraphSlot();
       c->zeroed = false;
@@ -934,7 +935,7 @@ int lub_compute(lub_handle_t h, int64_t n, const double* r, const double* q,
   HIP_TRY(hipMemcpyAsync(dw, w, 3 * b, hipMemcpyHostToDevice, s));
   const int rc = compute_device(h, n, dr, dq, ds, dv, dw, df, dt, s);
   if (rc) {
-    hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);  // the call's own error is returned
     return rc;
   }
   HIP_TRY(hipMemcpyAsync(f, df, 3 * b, hipMemcpyDeviceToHost, s));
@@ -1509,33 +1510,35 @@ int lub_mlp_train(lub_handle_t h, int64_t m, const float* X, const float* T,
 
 void lub_destroy(lub_handle_t h) {
   if (!h) return;
-  hipSetDevice(h->device);
+  // teardown (no error to report): every release is attempted
+  (void)hipSetDevice(h->device);
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->bcount, h->bstage, h->block_sums,
-                  h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s, h->fail_list,
-                  h->out_links,
+                  h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s,
+                  h->fail_list, h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
                   h->cnt_buf, h->scat, h->pos, h->warm_range[0], h->warm_range[1],
-                  h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1, h->m2, h->grad, h->wt, h->wb, h->dloss,
+                  h->warm_val[0], h->warm_val[1], h->stat_nbr, h->stat_pair, h->th, h->m1,
+                  h->m2, h->grad, h->wt, h->wb, h->dloss,
                   h->loss_parts, h->aT, h->dT, h->seedX, h->seedY, h->grow_semi,
                   h->grow_f, h->grow_t, h->stage_in, h->stage_out, h->detail};
   for (void* p : bufs)
-    if (p) hipFree(p);
-  if (h->host_cnt) hipHostFree(h->host_cnt);
+    if (p) (void)hipFree(p);
+  if (h->host_cnt) (void)hipHostFree(h->host_cnt);
   for (void* p : {(void*)h->sup_nbr, (void*)h->sup_deg, (void*)h->ref_pos, (void*)h->inv,
                   (void*)h->disp_blk, (void*)h->list_state, (void*)h->sup_val,
                   (void*)h->work_sup})
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   if (h->side) {
-    hipStreamSynchronize(h->side);
-    hipStreamDestroy(h->side);
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
   }
-  if (h->ev_fork) hipEventDestroy(h->ev_fork);
-  if (h->ev_join) hipEventDestroy(h->ev_join);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   for (auto& ev : h->pending)
     for (hipEvent_t e : ev) h->free_events.push_back(e);
-  for (hipEvent_t e : h->free_events) hipEventDestroy(e);
+  for (hipEvent_t e : h->free_events) (void)hipEventDestroy(e);
   delete h;
 }
 

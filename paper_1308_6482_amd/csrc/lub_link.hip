@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(64 * kLinkWaves)
   __shared__ int32_t s_list[kLinkWaves][64];   // per wavefront: the kept sites
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int nwork = cnt->error == 0 ? min(cnt->work, cd.cap_work) : 0;
-  if (blockIdx.x * kLinkSlots >= nwork) return;
+  if ((int)(blockIdx.x * kLinkSlots) >= nwork) return;
   const bool navg = cd.model == LUB_MODEL_LINK_NAVG;
   int64_t n_links = 0, n_active = 0, n_overlap = 0, max_links = 0;
   for (int c0 = blockIdx.x * kLinkSlots; c0 < nwork; c0 += gridDim.x * kLinkSlots) {

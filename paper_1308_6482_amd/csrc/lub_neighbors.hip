@@ -1477,7 +1477,6 @@ k_nbr_emit(CallDesc d, int32_t* __restrict__ bcount, const int32_t* __restrict__
            int64_t* __restrict__ stat_nbr, Counters* cnt, const int32_t* __restrict__ orig,
            int2* __restrict__ warm_range) {
   constexpr int G = kEmitG;
-  constexpr unsigned long long kGroupMask = (1ull << G) - 1ull;
   __shared__ int s_cand[kEmitWaves], s_wallc[kEmitWaves], s_deg[kEmitWaves];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -1847,7 +1846,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
   size_t lds = sizeof(int32_t) * 64 * nbr_waves(d) / nbr_group(d) * (size_t)d.max_nbr;
   if (mode == 2 && lists && lists->work_sup) lds *= 2;  // the superset positions too
   // (the lane-group kernels take stream-ordered stamps around their launch)
-  if (ev_start) hipEventRecord(ev_start, s);
+  if (ev_start) (void)hipEventRecord(ev_start, s);  // timing only
   if (nbr_group(d) == 16)
     launch_nbr_waves<16>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
@@ -1857,7 +1856,7 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
   else
     launch_nbr_waves<64>(mode, grid, lds, s, d, rec, pos, orig, cell_sorted, cell_start, deg,
                         nbr, slot, wall_slot, work_s, work_t, stat_nbr, cnt, lb);
-  if (ev_stop) hipEventRecord(ev_stop, s);
+  if (ev_stop) (void)hipEventRecord(ev_stop, s);
 }
 
 namespace {

@@ -673,7 +673,7 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
   const int nwork = cnt->error != 0 ? 0
                     : kTangent  ? min(cnt->failed, cd.cap_work)
                                 : min(cnt->work, cd.cap_work);
-  if (blockIdx.x * blockDim.x >= nwork) return;
+  if ((int)(blockIdx.x * blockDim.x) >= nwork) return;
   int64_t n_iters = 0, n_active = 0, n_overlap = 0, n_unres = 0, n_uncon = 0, n_fb = 0,
           n_warm = 0;
   // reused lists: normals stored per superset entry carry the number of the
