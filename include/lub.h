@@ -69,7 +69,9 @@ extern "C" {
                           /* ln h / 1/h terms; FP32 resistance coefficients, */
                           /* 6x6 product and transfer */
 
-#define LUB_SEED_PLAIN 0  /* Newton started from the line of centres */
+#define LUB_SEED_PLAIN 0  /* Newton started from the line of centres mapped by
+                             (M_i + M_j)^-1, M the support matrices: no
+                             learned input */
 #define LUB_SEED_MLP 1    /* Newton started from the learned predictor */
 
 /* Physical parameters (Sec. III.B-C). */
@@ -434,7 +436,7 @@ int lub_get_pair_detail(lub_handle_t h, int64_t cap, double* n, double* yi, doub
  * opts.seed_mode = LUB_SEED_MLP, lub_compute starts the closest-point Newton
  * iteration from the normal these parameters imply; the iteration always
  * runs to convergence from there, and a pair whose seeded iteration does not
- * converge is solved again from the line of centres (counted in
+ * converge is solved again from the plain start (counted in
  * lub_stats_t.fallbacks), so the results do not depend on the network.
  * Evaluation and training use BF16 MFMA with FP32 accumulation; the master
  * weights and the Adam moments are FP32.

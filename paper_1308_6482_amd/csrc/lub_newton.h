@@ -81,8 +81,36 @@ struct Solve {
   bool ok;
 };
 
+// The plain start: the line of centres mapped by (M_i + M_j)^-1, the
+// normal at d of the ellipsoid with matrix M_i + M_j, which stands in for
+// the Minkowski sum of the two bodies (whose normal at d - h n is the
+// answer).  Exact for spheres and for aligned bodies of one shape; for the
+// others about one Newton iteration closer than the line of centres.
+// Formed with the adjugate (S is positive definite: only the direction
+// counts), falling back to the line of centres for a degenerate d.
+__host__ __device__ __forceinline__ void plain_start(const double d[3], const double* Mi,
+                                                     const double* Mj, double n[3]) {
+  const double a = Mi[0] + Mj[0], b = Mi[1] + Mj[1], c = Mi[2] + Mj[2];
+  const double e = Mi[3] + Mj[3], f = Mi[4] + Mj[4], g = Mi[5] + Mj[5];
+  // adj(S) d for S = [a b c; b e f; c f g]
+  const double m0 = (e * g - f * f) * d[0] + (c * f - b * g) * d[1] + (b * f - c * e) * d[2];
+  const double m1 = (c * f - b * g) * d[0] + (a * g - c * c) * d[1] + (b * c - a * f) * d[2];
+  const double m2 = (b * f - c * e) * d[0] + (b * c - a * f) * d[1] + (a * e - b * b) * d[2];
+  const double mn = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+  if (mn > 0.0 && m0 * d[0] + m1 * d[1] + m2 * d[2] > 0.0) {
+    n[0] = m0 / mn;
+    n[1] = m1 / mn;
+    n[2] = m2 / mn;
+  } else {
+    const double dn = sqrt(dot3(d, d));
+    n[0] = d[0] / dn;
+    n[1] = d[1] / dn;
+    n[2] = d[2] / dn;
+  }
+}
+
 // Newton iteration for the stationary point of g(n) on the unit sphere,
-// started from n0 (unit) when use_n0, else from the line of centres (the
+// started from n0 (unit) when use_n0, else from the plain start above (the
 // start is selected by value: no pointer to a local escapes to memory);
 // converged when the tangential residual is below rel_tol (h_i + h_j)
 __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
@@ -91,8 +119,8 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
                                                 const double (&n0)[3], bool use_n0,
                                                 double rel_tol = 1e-14) {
   Solve o;
-  double dn = sqrt(dot3(d, d));
-  double n[3] = {d[0] / dn, d[1] / dn, d[2] / dn};
+  double n[3];
+  plain_start(d, Mi, Mj, n);
   for (int k = 0; k < 3; ++k) n[k] = use_n0 ? n0[k] : n[k];
   double prev = 1.0;
   bool last_full = false;

@@ -7,8 +7,9 @@
 // y_j = r_j - M_j n / h_j(n) (h_k(n) = sqrt(n.M_k n)), the stationary point
 // of g(n) = n.d - h_i(n) - h_j(n) on the unit sphere; g there is the signed
 // gap (negative for a small overlap).  It is found by Newton's method in the
-// tangent plane of n (two unknowns), started on the line of centres, in
-// FP64.  The Riemannian Hessian is shifted to stay negative definite far
+// tangent plane of n (two unknowns), started from the line of centres
+// mapped by (M_i + M_j)^-1 (the normal of an ellipsoid standing in for the
+// two bodies' Minkowski sum), in FP64.  The Riemannian Hessian is shifted to stay negative definite far
 // from the solution.  This replaces the paper's Lin-Han tangent-sphere
 // iteration (linear convergence, ~40 iterations for aspect ratio 1/3) by a
 // quadratically convergent one that needs no pole-safe parametrisation.
@@ -461,9 +462,9 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     double d[3];
     le_m = pair_image(cd, A.r, Bp.r, d);
     // start: the previous call's normal (warm start), else the learned
-    // prediction, else the line of centres.  The plain start judges a seeded
-    // one: if the seeded iteration does not converge, start again from the
-    // line of centres
+    // prediction, else the plain start (the line of centres mapped by
+    // (M_i + M_j)^-1).  The plain start judges a seeded one: if the seeded
+    // iteration does not converge, start again from the plain start
     double n0[3] = {0.0, 0.0, 0.0};
     bool seeded = false;
     if (use_nseed && dot3(nseed, d) > 0.0) {
