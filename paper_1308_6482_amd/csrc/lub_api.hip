@@ -559,7 +559,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       seeds = c->seedY;
     }
     WarmTables warm{c->warm_range[wp], c->warm_val[wp], c->warm_val[wc], c->sorted,
-                    c->work_sup,       c->sup_val,      c->list_state};
+                    c->work_sup,       c->sup_val,      c->list_state, c->warm_range[wc]};
     if (is_link(d.model)) {
       launch_links(d, c->rec, c->kin, c->work_s, c->work_t, c->out, c->out_h, c->out_status,
                    c->out_links, c->stat_pair, c->cnt, s);

@@ -291,6 +291,7 @@ struct WarmTables {
   const int32_t* slot_sup;   // evaluation slot -> superset entry
   float4* sup_val;           // normal (x, y, z), tag in w (int bits)
   const ListState* state;    // the current search count (the tag)
+  const int2* cur_range;     // read: this call's [first, end) slot of each input index
 };
 
 // detail (may be null): kDetailWords doubles per evaluation slot, the

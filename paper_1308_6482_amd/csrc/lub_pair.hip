@@ -716,10 +716,23 @@ __global__ void __launch_bounds__(kPairBlock) k_pairs(CallDesc cd,
         const int is = warm.orig[s], it = warm.orig[t];
         key = is ^ it;
         const bool s_first = cd.partner_codes != kPartnerRanges || s < t;
-        const int2 ra = warm.prev_range[s_first ? is : it];
-        const int2 rb = warm.prev_range[s_first ? it : is];
+        const int pa = s_first ? is : it;  // the particle whose range holds w
+        const int2 ra = warm.prev_range[pa];
+        // first the slot at the same place in that particle's previous range
+        // as w in its current one (the lists change little between calls),
+        // then the two previous ranges
+        const int g = ra.x + (w - warm.cur_range[pa].x);
+        if (g >= 0 && g >= ra.x && g < ra.y && g < cd.cap_work) {
+          const float4 v = warm.prev_val[g];
+          if (__float_as_int(v.w) == key) {
+            nprev[0] = v.x;
+            nprev[1] = v.y;
+            nprev[2] = v.z;
+            found = true;
+          }
+        }
         for (int side = 0; side < 2 && !found; ++side) {
-          const int2 rg = side == 0 ? ra : rb;
+          const int2 rg = side == 0 ? ra : warm.prev_range[s_first ? it : is];
           const int lo = max(rg.x, 0);
           const int hi = min(min(rg.y, cd.cap_work), lo + kWarmScan);
           for (int k = lo; k < hi; ++k) {
