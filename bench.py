@@ -37,10 +37,13 @@ sys.path.insert(0, ROOT)
 # Algorithmic work of the pair kernel per unit, counted from the kernel's
 # source by an operation-counting host build (adds and multiplies, FMA = 2;
 # divisions, square roots and logarithms listed apart and not counted):
-#   per evaluated pair (set-up and final evaluation): 100 FP64 flops
+#   per evaluated pair (set-up and final evaluation): 144 FP64 flops (the
+#     count of 100 with the line of centres as the start, plus 44 for the
+#     plain start (M_i + M_j)^-1 d: sums 6, cofactors 18, product 15, norm 5
+#     and sign check 5, against 5 for normalising d)
 #   per Newton iteration (incl. line-search trials):  306 FP64 flops
 #   per active pair, LUB_MIXED: 225 FP64 + 450 FP32 flops; LUB_FP64: 675 FP64
-FLOPS_EVAL = 100
+FLOPS_EVAL = 144
 FLOPS_ITER = 306
 FLOPS_POST = {"mixed": (225, 450), "fp64": (675, 0)}
 # Neighbour search per candidate pair (both directions of the centre test and
