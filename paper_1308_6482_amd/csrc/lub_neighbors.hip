@@ -1465,7 +1465,7 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
 // dozen next to large particles), the backward entries ranked in registers.
 // No LDS.  bcount: [n] backward counts, [n] slot offsets,
 // the int64 total.
-constexpr int kEmitG = 8;
+constexpr int kEmitG = 4;
 constexpr int kEmitWaves = 4;
 constexpr int kEmitPerBlock = kEmitWaves * 64 / kEmitG;
 
