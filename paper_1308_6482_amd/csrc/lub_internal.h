@@ -242,8 +242,8 @@ void launch_neighbors_wave(const CallDesc& d, const PRec* rec, const PRecP* recp
                            const ListBufs* lists = nullptr, int32_t* bcount = nullptr,
                            int32_t* block_sums = nullptr, int2* bstage = nullptr,
                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
-// whether the full search runs as forward search + merge (then the 128-B
-// records are not read by the search)
+// whether the full search runs as forward search + evaluation list (then
+// the 128-B records are not read by the search)
 bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums,
                  const int2* bstage);
 // (bcount: 2 n + 2 ints, the first 2 n zeroed by the binning of this call,

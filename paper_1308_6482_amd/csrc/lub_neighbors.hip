@@ -1360,8 +1360,9 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
     // (same operands, same order).  The kept pairs get evaluation slots in
     // the finder's range, in the order of its forward list, then its kept
     // walls: slot = fbase[finder] + kk with fbase the scan of kcnt.  The
-    // forward partners go to the slot segment (read by the merge), and this
-    // particle, with the flags and its kk, to each partner's row of bstage
+    // forward partners go to this particle's slot row (read by the
+    // evaluation-list kernel), and this particle, with the flags and its kk,
+    // to each partner's row of bstage
     // at a place counted by bcount (the backward partners, in no particular
     // order; one 8-B store per pair).
     if (live) {
@@ -1994,8 +1995,8 @@ int nbr_blocks_flat(const CallDesc& d) {
 // go through the flattened kernel
 bool nbr_flat(const CallDesc& d) { return !d.le; }
 
-// the full search of large systems as forward search + merge (needs the
-// backward counts, zeroed by the binning kernel)
+// the full search of large systems as forward search + evaluation list
+// (needs the backward counts, zeroed by the binning kernel)
 bool nbr_forward(const CallDesc& d, const int32_t* bcount, const int32_t* block_sums,
                  const int2* bstage) {
   return bcount != nullptr && block_sums != nullptr && bstage != nullptr && !d.le &&
