@@ -946,6 +946,7 @@ k_neighbors(CallDesc d, const PRec* __restrict__ rec, const double4* __restrict_
 constexpr int kFlatG = 16;
 constexpr int kFlatWaves = 4;
 constexpr int kFlatBuf = 256;  // candidate indices per group
+constexpr int kFlushK = 4;  // candidates per lane and round of the test
 constexpr int kFwd = 3;        // mode of the forward search (partners later in cell order)
 // the forward search from this many particles, with at most kFwdMaxNbr
 // entries per particle (the gather's LDS: 2 x 4 B per entry and particle)
@@ -1189,22 +1190,33 @@ k_neighbors_flat(CallDesc d, const PRec* __restrict__ rec, const PRecP* __restri
     int nbuf = 0;  // entries in the buffer (uniform in the group)
     // test the buffer's entries [0, m): accepted partners go to the segment
     auto flush = [&](int m) {
-      for (int base = 0; base < m; base += G) {
-        const int e = base + gl;
-        bool acc = false;
-        int t = -1;
-        if (e < m) {
-          t = cand[e];
-          const double4 pj = pos[t];
-          const double rj[3] = {pj.x, pj.y, pj.z};
-          acc = t != s && centre_test(ri, rj, rmi, pj.w, d, extra);
+      // kFlushK candidates per lane and round: their positions are loaded
+      // together (the walk waits on these loads)
+      for (int base = 0; base < m; base += kFlushK * G) {
+        int tk[kFlushK];
+        double4 pk[kFlushK];
+#pragma unroll
+        for (int u = 0; u < kFlushK; ++u) {
+          const int e = base + u * G + gl;
+          tk[u] = e < m ? cand[e] : -1;
         }
-        const unsigned long long mk = (__ballot(acc) >> gbase) & kGroupMask;
-        if (acc) {
-          const int at = count + lane_prefix(mk, gl);
-          if (at < maxn) seg[at] = t;
+#pragma unroll
+        for (int u = 0; u < kFlushK; ++u)
+          pk[u] = tk[u] >= 0 ? pos[tk[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < kFlushK; ++u) {
+          bool acc = false;
+          if (tk[u] >= 0) {
+            const double rj[3] = {pk[u].x, pk[u].y, pk[u].z};
+            acc = tk[u] != s && centre_test(ri, rj, rmi, pk[u].w, d, extra);
+          }
+          const unsigned long long mk = (__ballot(acc) >> gbase) & kGroupMask;
+          if (acc) {
+            const int at = count + lane_prefix(mk, gl);
+            if (at < maxn) seg[at] = tk[u];
+          }
+          count += __popcll(mk);
         }
-        count += __popcll(mk);
       }
     };
     // the forward search: a small particle searches its own class only,
