@@ -513,15 +513,15 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s, c->bcount);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
-                          c->cell_count, ncell, gate, s);
+                          c->cell_sorted, c->cell_count, ncell, gate, s);
       // the 128-B records feed the lane-group search, the full search of
       // small systems, the learned seed's features and the link-wise laws
       const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums,
                                                            c->bstage)) ||
                             is_link(d.model) || c->opt.seed_mode == LUB_SEED_MLP;
-      launch_build_records(d, c->scat, c->cell_id, c->cell_start, c->cell_fill, ncell, r,
-                           q, semi, v, w, c->sorted, need_rec ? c->rec : nullptr, c->recp,
-                           c->pos, c->kin, c->cell_sorted, gate, s);
+      launch_build_records(d, c->scat, c->cell_sorted, c->cell_start, c->cell_fill, ncell,
+                           r, q, semi, v, w, c->sorted, need_rec ? c->rec : nullptr, c->recp,
+                           c->pos, c->kin, gate, s);
     }
   }
   if (d.n > 0) {

@@ -212,19 +212,19 @@ void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
                       int32_t* bcount = nullptr);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
                  int64_t* total, hipStream_t s);
-// scatter into the cells' ranges (arbitrary order); zeroes cell_count
+// scatter into the cells' ranges (arbitrary order), with the cell of each
+// cell-order place into cell_sorted; zeroes cell_count
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* unsorted, int32_t* cell_count, int ncell,
-                         const Counters* gate, hipStream_t s);
+                         int32_t* unsorted, int32_t* cell_sorted, int32_t* cell_count,
+                         int ncell, const Counters* gate, hipStream_t s);
 // in-cell placement by input index and the records; zeroes cell_fill
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
-                          const int32_t* cell_id, const int32_t* cell_start,
+                          const int32_t* cell_sorted, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
                           const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
-                          double4* pos,
-                          KRec* kin, int32_t* cell_sorted, const Counters* gate, hipStream_t s);
+                          double4* pos, KRec* kin, const Counters* gate, hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,

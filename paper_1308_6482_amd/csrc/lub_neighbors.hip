@@ -255,13 +255,16 @@ __global__ void k_scan_add(int32_t* out, int n, const int32_t* block_sums) {
   }
 }
 
-// Particles into their cells' ranges in arbitrary order (atomic cursors).
-// The counts have been consumed by the scan: they are zeroed here for the
-// next call.
+// Particles into their cells' ranges in arbitrary order (atomic cursors),
+// with the cell of each place of the range (every place of a cell's range
+// holds one of its particles, whatever the order: the cell of each
+// cell-order place).  The counts have been consumed by the scan: they are
+// zeroed here for the next call.
 __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
                                const int32_t* __restrict__ cell_start,
                                int32_t* __restrict__ cell_fill,
                                int32_t* __restrict__ unsorted,
+                               int32_t* __restrict__ cell_sorted,
                                int32_t* __restrict__ cell_count, int ncell,
                                const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists: the counts stayed zero
@@ -269,7 +272,9 @@ __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
   if (i >= d.n) return;
   const int c = cell_id[i];
-  unsorted[cell_start[c] + atomicAdd(&cell_fill[c], 1)] = i;
+  const int at = cell_start[c] + atomicAdd(&cell_fill[c], 1);
+  unsorted[at] = i;
+  cell_sorted[at] = c;
 }
 
 // One particle's inputs for its records, loaded at once.
@@ -344,10 +349,12 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
 
 // Each cell's members in increasing input index (the position of a particle
 // is its cell's start plus the number of members with a smaller index), so
-// that every later step is deterministic, and their records.  The cursors
-// of the scatter are zeroed here for the next call.
+// that every later step is deterministic, and their records.  The cell of
+// each place comes from the scatter, beside the particle: no dependent
+// look-up of the particle's cell.  The cursors of the scatter are zeroed
+// here for the next call.
 __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
-                                const int32_t* __restrict__ cell_id,
+                                const int32_t* __restrict__ cell_sorted,
                                 const int32_t* __restrict__ cell_start,
                                 int32_t* __restrict__ cell_fill, int ncell,
                                 const double* __restrict__ r,
@@ -357,21 +364,21 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 const double* __restrict__ w, int32_t* __restrict__ sorted,
                                 PRec* __restrict__ rec, PRecP* __restrict__ recp,
                                 double4* __restrict__ pos, KRec* __restrict__ kin,
-                                int32_t* __restrict__ cell_sorted, const Counters* gate) {
+                                const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists: the cursors stayed zero
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
   if (i >= d.n) return;
   const int p = unsorted[i];
+  const int c = cell_sorted[i];  // the cell of place i is the cell of place s
   // the inputs are fetched while the rank within the cell is counted
   const RecIn in = load_record_input(r, q, semi, v, w, p);
-  const int c = cell_id[p];
   const int b = cell_start[c], e = cell_start[c + 1];
   int rank = 0;
   for (int k = b; k < e; ++k) rank += unsorted[k] < p;
   const int s = b + rank;
   sorted[s] = p;
-  make_record_from(s, in, c, rec, recp, pos, kin, cell_sorted);
+  make_record_from(s, in, c, rec, recp, pos, kin, nullptr);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
@@ -1738,25 +1745,24 @@ void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
 
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
                          const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* unsorted, int32_t* cell_count, int ncell,
-                         const Counters* gate, hipStream_t s) {
+                         int32_t* unsorted, int32_t* cell_sorted, int32_t* cell_count,
+                         int ncell, const Counters* gate, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_cell_scatter, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, cell_id, cell_start, cell_fill, unsorted, cell_count, ncell, gate);
+                     d, cell_id, cell_start, cell_fill, unsorted, cell_sorted, cell_count,
+                     ncell, gate);
 }
 
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
-                          const int32_t* cell_id, const int32_t* cell_start,
+                          const int32_t* cell_sorted, const int32_t* cell_start,
                           int32_t* cell_fill, int ncell, const double* r,
                           const double* q, const double* semi, const double* v,
                           const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
-                          double4* pos,
-                          KRec* kin, int32_t* cell_sorted, const Counters* gate,
-                          hipStream_t s) {
+                          double4* pos, KRec* kin, const Counters* gate, hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, unsorted, cell_id, cell_start, cell_fill, ncell, r, q, semi,
-                     v, w, sorted, rec, recp, pos, kin, cell_sorted, gate);
+                     d, unsorted, cell_sorted, cell_start, cell_fill, ncell, r, q, semi,
+                     v, w, sorted, rec, recp, pos, kin, gate);
 }
 
 bool cells_small_fits(const CallDesc& d) {
