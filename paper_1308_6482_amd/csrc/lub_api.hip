@@ -51,7 +51,6 @@ struct lub_ctx {
   int32_t cur_nbr = 64;            // neighbour-segment stride in use
   int32_t* cell_id = nullptr;      // [n] by input index
   int32_t* cell_count = nullptr;   // [ncell]
-  int32_t* cell_fill = nullptr;    // [ncell]
   int32_t* cell_start = nullptr;   // [ncell + 1]
   int32_t* sorted = nullptr;       // [n] cell order -> input index
   int32_t* scat = nullptr;         // [n] scatter output (cell ranges, any order)
@@ -260,8 +259,7 @@ int ensure_cells(lub_ctx* c, int64_t ncell) {
   int rc;
   c->cap_cells = 0;
   c->zeroed = false;
-  if ((rc = realloc_buf(&c->cell_count, ncell)) || (rc = realloc_buf(&c->cell_fill, ncell)) ||
-      (rc = realloc_buf(&c->cell_start, ncell + 1)))
+  if ((rc = realloc_buf(&c->cell_count, ncell)) || (rc = realloc_buf(&c->cell_start, ncell + 1)))
     return rc;
   c->cap_cells = ncell;
   return LUB_OK;
@@ -489,7 +487,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
   const bool small = d.n > 0 && cells_small_fits(d);
   // warm-start sets of this call: written and read
   const int wc = c->cnt_idx, wp = c->cnt_idx ^ 1;
-  if (!c->zeroed) launch_reset(c->cnt, c->cell_count, c->cell_fill, ncell, s);
+  if (!c->zeroed) launch_reset(c->cnt, c->cell_count, ncell, s);
   c->zeroed = false;
   // reused neighbour lists: the device decides whether this call searches
   // (every particle within half the skin of its place and size at the last
@@ -510,17 +508,19 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       launch_cells_small(d, r, q, semi, v, w, c->cell_start, c->sorted, c->rec, c->recp, c->pos,
                          c->kin, c->cell_sorted, c->cnt, gate, s);
     } else {
-      launch_stage_bin(d, r, q, semi, c->cell_id, c->cell_count, c->cnt, gate, s, c->bcount);
+      // the tickets are kept in `sorted` until the record build writes it
+      launch_stage_bin(d, r, q, semi, c->cell_id, c->sorted, c->cell_count, c->cnt, gate, s,
+                       c->bcount);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
-      launch_cell_scatter(d, c->cell_id, c->cell_start, c->cell_fill, c->scat,
-                          c->cell_sorted, c->cell_count, ncell, gate, s);
+      launch_cell_scatter(d, c->cell_id, c->sorted, c->cell_start, c->scat, c->cell_sorted,
+                          c->cell_count, ncell, gate, s);
       // the 128-B records feed the lane-group search, the full search of
       // small systems, the learned seed's features and the link-wise laws
       const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums,
                                                            c->bstage)) ||
                             is_link(d.model) || c->opt.seed_mode == LUB_SEED_MLP;
-      launch_build_records(d, c->scat, c->cell_sorted, c->cell_start, c->cell_fill, ncell,
-                           r, q, semi, v, w, c->sorted, need_rec ? c->rec : nullptr, c->recp,
+      launch_build_records(d, c->scat, c->cell_sorted, c->cell_start, r, q, semi, v, w,
+                           c->sorted, need_rec ? c->rec : nullptr, c->recp,
                            c->pos, c->kin, gate, s);
     }
   }
@@ -601,7 +601,7 @@ int fetch_counters(lub_ctx* c) {
 
 // the device buffers a call's launch sequence uses
 std::vector<const void*> workspace_signature(const lub_ctx* c) {
-  return {c->cell_id, c->cell_count, c->cell_fill, c->cell_start, c->sorted, c->scat,
+  return {c->cell_id, c->cell_count, c->cell_start, c->sorted, c->scat,
           c->cell_sorted, c->deg, c->bcount, c->bstage, c->block_sums, c->wall_slot, c->rec,
           c->recp,
           c->pos, c->kin,
@@ -1040,7 +1040,6 @@ int lub_compute_static(const lub_domain_t* domain, const lub_params_t* params,
   c.stat_nbr = cv.take<int64_t>((int64_t)kStatNbrWords * nbr_blocks_max((int)np));
   c.stat_pair = cv.take<int64_t>((int64_t)kStatPairWords * (kMaxPairBlocks + kTangentBlocks));
   c.cell_count = cv.take<int32_t>(ncell);
-  c.cell_fill = cv.take<int32_t>(ncell);
   c.cell_start = cv.take<int32_t>(ncell + 1);
   c.block_sums = cv.take<int32_t>(std::max<int64_t>(ncell, np) / 1024 + 64);
   c.nbr = cv.take<int32_t>(entries);
@@ -1513,7 +1512,7 @@ void lub_destroy(lub_handle_t h) {
   // teardown (no error to report): every release is attempted
   (void)hipSetDevice(h->device);
   drop_graphs(h);
-  void* bufs[] = {h->cell_id, h->cell_count, h->cell_fill, h->cell_start,
+  void* bufs[] = {h->cell_id, h->cell_count, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->bcount, h->bstage, h->block_sums,
                   h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s,
                   h->fail_list, h->out_links,

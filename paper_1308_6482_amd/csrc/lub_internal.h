@@ -200,31 +200,31 @@ constexpr int kWtTotal = kWt1 + 2 * kWt2 + 16 * 128;
 constexpr int kWbTotal = 2 * kWt2 + 128 * 32;
 
 // ---- launch wrappers (lub_neighbors.hip) --------------------------------
-void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
-                  int ncell, hipStream_t s);
+void launch_reset(Counters* c, int32_t* cell_count, int ncell, hipStream_t s);
 // The cell-build launchers take `gate`: null, or this call's counters, whose
 // `rebuild` flag (set on the device) turns the kernels into no-ops when the
-// neighbour lists are reused.  The binning also zeroes `bcount` (2 n
-// entries) when given.
+// neighbour lists are reused.  The binning writes each particle's cell and
+// its ticket in the cell (a distinct place among the cell's members), counts
+// the cells, and zeroes `bcount` (2 n entries) when given.
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
-                      const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, const Counters* gate, hipStream_t s,
-                      int32_t* bcount = nullptr);
+                      const double* semi, int32_t* cell_id, int32_t* ticket,
+                      int32_t* cell_count, Counters* cnt, const Counters* gate,
+                      hipStream_t s, int32_t* bcount = nullptr);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
                  int64_t* total, hipStream_t s);
-// scatter into the cells' ranges (arbitrary order), with the cell of each
-// cell-order place into cell_sorted; zeroes cell_count
-void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
-                         const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* unsorted, int32_t* cell_sorted, int32_t* cell_count,
-                         int ncell, const Counters* gate, hipStream_t s);
-// in-cell placement by input index and the records; zeroes cell_fill
+// scatter into the cells' ranges (at the binning's tickets), with the cell
+// of each cell-order place into cell_sorted; zeroes cell_count
+void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id, const int32_t* ticket,
+                         const int32_t* cell_start, int32_t* unsorted, int32_t* cell_sorted,
+                         int32_t* cell_count, int ncell, const Counters* gate,
+                         hipStream_t s);
+// in-cell placement by input index and the records
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_sorted, const int32_t* cell_start,
-                          int32_t* cell_fill, int ncell, const double* r,
-                          const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
-                          double4* pos, KRec* kin, const Counters* gate, hipStream_t s);
+                          const double* r, const double* q, const double* semi,
+                          const double* v, const double* w, int32_t* sorted, PRec* rec,
+                          PRecP* recp, double4* pos, KRec* kin, const Counters* gate,
+                          hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough
 bool cells_small_fits(const CallDesc& d);
 void launch_cells_small(const CallDesc& d, const double* r, const double* q,

@@ -101,13 +101,9 @@ __device__ int block_inclusive_scan(int x, int* lds, int* total) {
   return res;
 }
 
-__global__ void k_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
-                        int ncell) {
+__global__ void k_reset(Counters* c, int32_t* cell_count, int ncell) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncell) {
-    cell_count[i] = 0;
-    cell_fill[i] = 0;
-  }
+  if (i < ncell) cell_count[i] = 0;
   if (i < (int)(sizeof(Counters) / sizeof(int32_t)))
     reinterpret_cast<int32_t*>(c)[i] = 0;
 }
@@ -162,10 +158,12 @@ __device__ int validate_bin(const CallDesc& d, const PIn& u, const double inv_ce
   return (cz * d.nc[1] + cy) * d.nc[0] + cx + big;
 }
 
+// Each particle's cell and its ticket in that cell (the count of the cell
+// before its own increment: distinct within the cell, in arbitrary order).
 __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
                             const double* __restrict__ q,
                             const double* __restrict__ semi,
-                            int32_t* __restrict__ cell_id,
+                            int32_t* __restrict__ cell_id, int32_t* __restrict__ ticket,
                             int32_t* __restrict__ cell_count, Counters* cnt,
                             const Counters* gate, int32_t* __restrict__ bcount) {
   if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
@@ -178,7 +176,7 @@ __global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
   const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
   int c = validate_bin(d, load_input(r, q, semi, p), inv_cell, cnt);
   cell_id[p] = c;
-  atomicAdd(&cell_count[c], 1);
+  ticket[p] = atomicAdd(&cell_count[c], 1);
 }
 
 // Exclusive scan of in[0, n) into out[0, n) (the two may be the same
@@ -255,14 +253,14 @@ __global__ void k_scan_add(int32_t* out, int n, const int32_t* block_sums) {
   }
 }
 
-// Particles into their cells' ranges in arbitrary order (atomic cursors),
-// with the cell of each place of the range (every place of a cell's range
-// holds one of its particles, whatever the order: the cell of each
-// cell-order place).  The counts have been consumed by the scan: they are
-// zeroed here for the next call.
+// Particles into their cells' ranges in arbitrary order (the binning's
+// tickets), with the cell of each place of the range (every place of a
+// cell's range holds one of its particles, whatever the order: the cell of
+// each cell-order place).  The counts have been consumed by the scan: they
+// are zeroed here for the next call.
 __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
+                               const int32_t* __restrict__ ticket,
                                const int32_t* __restrict__ cell_start,
-                               int32_t* __restrict__ cell_fill,
                                int32_t* __restrict__ unsorted,
                                int32_t* __restrict__ cell_sorted,
                                int32_t* __restrict__ cell_count, int ncell,
@@ -272,7 +270,7 @@ __global__ void k_cell_scatter(CallDesc d, const int32_t* __restrict__ cell_id,
   for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_count[c] = 0;
   if (i >= d.n) return;
   const int c = cell_id[i];
-  const int at = cell_start[c] + atomicAdd(&cell_fill[c], 1);
+  const int at = cell_start[c] + ticket[i];
   unsorted[at] = i;
   cell_sorted[at] = c;
 }
@@ -351,12 +349,10 @@ __device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
 // is its cell's start plus the number of members with a smaller index), so
 // that every later step is deterministic, and their records.  The cell of
 // each place comes from the scatter, beside the particle: no dependent
-// look-up of the particle's cell.  The cursors of the scatter are zeroed
-// here for the next call.
+// look-up of the particle's cell.
 __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
                                 const int32_t* __restrict__ cell_sorted,
                                 const int32_t* __restrict__ cell_start,
-                                int32_t* __restrict__ cell_fill, int ncell,
                                 const double* __restrict__ r,
                                 const double* __restrict__ q,
                                 const double* __restrict__ semi,
@@ -365,9 +361,8 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 PRec* __restrict__ rec, PRecP* __restrict__ recp,
                                 double4* __restrict__ pos, KRec* __restrict__ kin,
                                 const Counters* gate) {
-  if (gate && !gate->rebuild) return;  // reused lists: the cursors stayed zero
+  if (gate && !gate->rebuild) return;  // reused lists: nothing to build
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int c = i; c < ncell; c += gridDim.x * blockDim.x) cell_fill[c] = 0;
   if (i >= d.n) return;
   const int p = unsorted[i];
   const int c = cell_sorted[i];  // the cell of place i is the cell of place s
@@ -1714,19 +1709,19 @@ k_nbr_emit(CallDesc d, int32_t* __restrict__ bcount, const int32_t* __restrict__
 
 }  // namespace
 
-void launch_reset(Counters* c, int32_t* cell_count, int32_t* cell_fill,
-                  int ncell, hipStream_t s) {
+void launch_reset(Counters* c, int32_t* cell_count, int ncell, hipStream_t s) {
   int n = ncell > 128 ? ncell : 128;
   hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, c,
-                     cell_count, cell_fill, ncell);
+                     cell_count, ncell);
 }
 
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
-                      const double* semi, int32_t* cell_id, int32_t* cell_count,
-                      Counters* cnt, const Counters* gate, hipStream_t s, int32_t* bcount) {
+                      const double* semi, int32_t* cell_id, int32_t* ticket,
+                      int32_t* cell_count, Counters* cnt, const Counters* gate,
+                      hipStream_t s, int32_t* bcount) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_stage_bin, dim3((d.n + 255) / 256), dim3(256), 0, s, d,
-                     r, q, semi, cell_id, cell_count, cnt, gate, bcount);
+                     r, q, semi, cell_id, ticket, cell_count, cnt, gate, bcount);
 }
 
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
@@ -1743,25 +1738,25 @@ void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
   }
 }
 
-void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id,
-                         const int32_t* cell_start, int32_t* cell_fill,
-                         int32_t* unsorted, int32_t* cell_sorted, int32_t* cell_count,
-                         int ncell, const Counters* gate, hipStream_t s) {
+void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id, const int32_t* ticket,
+                         const int32_t* cell_start, int32_t* unsorted, int32_t* cell_sorted,
+                         int32_t* cell_count, int ncell, const Counters* gate,
+                         hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_cell_scatter, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, cell_id, cell_start, cell_fill, unsorted, cell_sorted, cell_count,
+                     d, cell_id, ticket, cell_start, unsorted, cell_sorted, cell_count,
                      ncell, gate);
 }
 
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_sorted, const int32_t* cell_start,
-                          int32_t* cell_fill, int ncell, const double* r,
-                          const double* q, const double* semi, const double* v,
-                          const double* w, int32_t* sorted, PRec* rec, PRecP* recp,
-                          double4* pos, KRec* kin, const Counters* gate, hipStream_t s) {
+                          const double* r, const double* q, const double* semi,
+                          const double* v, const double* w, int32_t* sorted, PRec* rec,
+                          PRecP* recp, double4* pos, KRec* kin, const Counters* gate,
+                          hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, unsorted, cell_sorted, cell_start, cell_fill, ncell, r, q, semi,
+                     d, unsorted, cell_sorted, cell_start, r, q, semi,
                      v, w, sorted, rec, recp, pos, kin, gate);
 }
 
