@@ -74,6 +74,7 @@ struct lub_ctx {
   PRecP* recp = nullptr;           // [n] the pair kernels' copy
   double4* pos = nullptr;          // [n] centre and largest semi-axis (centre test)
   KRec* kin = nullptr;             // [n]
+  RecStage* staged = nullptr;      // [n] record copies in input order (binning)
   int32_t* nbr = nullptr;          // [n * cur_nbr] partner (cell order)
   int32_t* slot = nullptr;         // [n * cur_nbr] evaluation slot, -1, -2
   int32_t* work_s = nullptr;       // [work]
@@ -232,6 +233,7 @@ int ensure_particles(lub_ctx* c, int64_t n) {
       (rc = realloc_buf(&c->cell_sorted, need)) || (rc = realloc_buf(&c->deg, need)) ||
       (rc = realloc_buf(&c->bcount, 2 * need + 2)) ||
       (rc = realloc_buf(&c->rec, need)) || (rc = realloc_buf(&c->recp, need)) || (rc = realloc_buf(&c->kin, need)) ||
+      (rc = realloc_buf(&c->staged, need)) ||
       (rc = realloc_buf(&c->pos, need)) ||
       (rc = realloc_buf(&c->scat, need)) ||
       (rc = realloc_buf(&c->stat_nbr, (int64_t)kStatNbrWords * nbr_blocks_max((int)need))) ||
@@ -509,8 +511,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
                          c->kin, c->cell_sorted, c->cnt, gate, s);
     } else {
       // the tickets are kept in `sorted` until the record build writes it
-      launch_stage_bin(d, r, q, semi, c->cell_id, c->sorted, c->cell_count, c->cnt, gate, s,
-                       c->bcount);
+      launch_stage_bin(d, r, q, semi, v, w, c->cell_id, c->sorted, c->staged, c->cell_count,
+                       c->cnt, gate, s, c->bcount);
       launch_scan(c->cell_count, c->cell_start, ncell, c->block_sums, nullptr, s);
       launch_cell_scatter(d, c->cell_id, c->sorted, c->cell_start, c->scat, c->cell_sorted,
                           c->cell_count, ncell, gate, s);
@@ -519,9 +521,8 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
       const bool need_rec = !(d.skin == 0.0 && nbr_forward(d, c->bcount, c->block_sums,
                                                            c->bstage)) ||
                             is_link(d.model) || c->opt.seed_mode == LUB_SEED_MLP;
-      launch_build_records(d, c->scat, c->cell_sorted, c->cell_start, r, q, semi, v, w,
-                           c->sorted, need_rec ? c->rec : nullptr, c->recp,
-                           c->pos, c->kin, gate, s);
+      launch_build_records(d, c->scat, c->cell_sorted, c->cell_start, c->staged, c->sorted,
+                           need_rec ? c->rec : nullptr, c->recp, c->pos, c->kin, gate, s);
     }
   }
   if (d.n > 0) {
@@ -604,7 +605,7 @@ std::vector<const void*> workspace_signature(const lub_ctx* c) {
   return {c->cell_id, c->cell_count, c->cell_start, c->sorted, c->scat,
           c->cell_sorted, c->deg, c->bcount, c->bstage, c->block_sums, c->wall_slot, c->rec,
           c->recp,
-          c->pos, c->kin,
+          c->pos, c->kin, c->staged,
           c->nbr,
           c->slot, c->work_s, c->work_t, c->fail_list, c->out_links, c->out, c->out_h,
           c->out_status,
@@ -1036,6 +1037,7 @@ int lub_compute_static(const lub_domain_t* domain, const lub_params_t* params,
   c.rec = cv.take<PRec>(np);
   c.recp = cv.take<PRecP>(np);
   c.kin = cv.take<KRec>(np);
+  c.staged = cv.take<RecStage>(np);
   c.pos = cv.take<double4>(np);
   c.stat_nbr = cv.take<int64_t>((int64_t)kStatNbrWords * nbr_blocks_max((int)np));
   c.stat_pair = cv.take<int64_t>((int64_t)kStatPairWords * (kMaxPairBlocks + kTangentBlocks));
@@ -1514,7 +1516,7 @@ void lub_destroy(lub_handle_t h) {
   drop_graphs(h);
   void* bufs[] = {h->cell_id, h->cell_count, h->cell_start,
                   h->sorted, h->cell_sorted, h->deg, h->bcount, h->bstage, h->block_sums,
-                  h->wall_slot, h->rec, h->recp, h->kin, h->nbr, h->slot, h->work_s,
+                  h->wall_slot, h->rec, h->recp, h->kin, h->staged, h->nbr, h->slot, h->work_s,
                   h->fail_list, h->out_links,
                   h->work_t, h->out, h->out_h, h->out_status, h->out_iters,
                   h->cnt_buf, h->scat, h->pos, h->warm_range[0], h->warm_range[1],

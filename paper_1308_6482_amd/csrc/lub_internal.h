@@ -65,6 +65,14 @@ struct alignas(64) KRec {
   double pad[2];
 };
 
+// A particle's two cell-order copies, formed where its inputs are read in
+// input order: one 128-B line, which the record build moves into cell order
+// instead of gathering the five input arrays from random places.
+struct alignas(128) RecStage {
+  PRecP p;
+  KRec k;
+};
+
 // Device-side counters of one call.
 struct Counters {
   int32_t work;          // evaluated pair slots (particle + wall)
@@ -203,11 +211,13 @@ constexpr int kWbTotal = 2 * kWt2 + 128 * 32;
 void launch_reset(Counters* c, int32_t* cell_count, int ncell, hipStream_t s);
 // The cell-build launchers take `gate`: null, or this call's counters, whose
 // `rebuild` flag (set on the device) turns the kernels into no-ops when the
-// neighbour lists are reused.  The binning writes each particle's cell and
-// its ticket in the cell (a distinct place among the cell's members), counts
-// the cells, and zeroes `bcount` (2 n entries) when given.
+// neighbour lists are reused.  The binning writes each particle's cell, its
+// ticket in the cell (a distinct place among the cell's members) and its
+// staged record copies (input order), counts the cells, and zeroes `bcount`
+// (2 n entries) when given.
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
-                      const double* semi, int32_t* cell_id, int32_t* ticket,
+                      const double* semi, const double* v, const double* w,
+                      int32_t* cell_id, int32_t* ticket, RecStage* staged,
                       int32_t* cell_count, Counters* cnt, const Counters* gate,
                       hipStream_t s, int32_t* bcount = nullptr);
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
@@ -218,11 +228,10 @@ void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id, const int32_
                          const int32_t* cell_start, int32_t* unsorted, int32_t* cell_sorted,
                          int32_t* cell_count, int ncell, const Counters* gate,
                          hipStream_t s);
-// in-cell placement by input index and the records
+// in-cell placement by input index and the records, from the staged copies
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_sorted, const int32_t* cell_start,
-                          const double* r, const double* q, const double* semi,
-                          const double* v, const double* w, int32_t* sorted, PRec* rec,
+                          const RecStage* staged, int32_t* sorted, PRec* rec,
                           PRecP* recp, double4* pos, KRec* kin, const Counters* gate,
                           hipStream_t s);
 // the whole cell build in one workgroup, when n and the grid are small enough

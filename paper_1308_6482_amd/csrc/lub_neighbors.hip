@@ -158,27 +158,6 @@ __device__ int validate_bin(const CallDesc& d, const PIn& u, const double inv_ce
   return (cz * d.nc[1] + cy) * d.nc[0] + cx + big;
 }
 
-// Each particle's cell and its ticket in that cell (the count of the cell
-// before its own increment: distinct within the cell, in arbitrary order).
-__global__ void k_stage_bin(CallDesc d, const double* __restrict__ r,
-                            const double* __restrict__ q,
-                            const double* __restrict__ semi,
-                            int32_t* __restrict__ cell_id, int32_t* __restrict__ ticket,
-                            int32_t* __restrict__ cell_count, Counters* cnt,
-                            const Counters* gate, int32_t* __restrict__ bcount) {
-  if (gate && !gate->rebuild) return;  // reused lists: nothing to bin
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n) return;
-  if (bcount) {  // backward counts and kept pairs of the forward search
-    bcount[p] = 0;
-    bcount[d.n + p] = 0;
-  }
-  const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
-  int c = validate_bin(d, load_input(r, q, semi, p), inv_cell, cnt);
-  cell_id[p] = c;
-  ticket[p] = atomicAdd(&cell_count[c], 1);
-}
-
 // Exclusive scan of in[0, n) into out[0, n) (the two may be the same
 // array) by one block of kScanThreads, chunk by chunk: coalesced loads into
 // LDS, kScanItems consecutive elements per thread, block scan, coalesced
@@ -295,13 +274,9 @@ __device__ __forceinline__ RecIn load_record_input(const double* __restrict__ r,
   return in;
 }
 
-// Per-particle records in cell order.  M = Rperp^2 I + (Rpar^2 - Rperp^2) a a^T
-// with a the symmetry axis (third column of the rotation of q).  `cell` is
-// written to cell_sorted when that is given; the 128-B record only when rec
-// is given (the forward search of large systems reads the 64-B copy).
-__device__ void make_record_from(int s, const RecIn& in, int cell, PRec* __restrict__ rec,
-                                 PRecP* __restrict__ recp, double4* __restrict__ pos,
-                                 KRec* __restrict__ kin, int32_t* __restrict__ cell_sorted) {
+// One particle's 64-B geometry copy and kinematics from its inputs: the
+// symmetry axis a is the third column of the rotation of the normalised q.
+__device__ __forceinline__ RecStage stage_record(const RecIn& in) {
   double qw = in.u.qw, qx = in.u.qx, qy = in.u.qy, qz = in.u.qz;
   double inv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= inv;
@@ -311,53 +286,108 @@ __device__ void make_record_from(int s, const RecIn& in, int cell, PRec* __restr
   double ax = 2.0 * (qx * qz + qw * qy);
   double ay = 2.0 * (qy * qz - qw * qx);
   double az = 1.0 - 2.0 * (qx * qx + qy * qy);
-  PRecP c;
-  c.r[0] = in.u.x;
-  c.r[1] = in.u.y;
-  c.r[2] = in.u.z;
-  c.ax[0] = ax;
-  c.ax[1] = ay;
-  c.ax[2] = az;
-  c.Rpar = in.u.a;
-  c.Rperp = in.u.b;
-  recp[s] = c;
-  const PRec o = expand_record(c);
-  if (rec) rec[s] = o;
-  pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
-  KRec k;
+  RecStage o;
+  o.p.r[0] = in.u.x;
+  o.p.r[1] = in.u.y;
+  o.p.r[2] = in.u.z;
+  o.p.ax[0] = ax;
+  o.p.ax[1] = ay;
+  o.p.ax[2] = az;
+  o.p.Rpar = in.u.a;
+  o.p.Rperp = in.u.b;
   for (int m = 0; m < 3; ++m) {
-    k.v[m] = in.v[m];
-    k.w[m] = in.w[m];
+    o.k.v[m] = in.v[m];
+    o.k.w[m] = in.w[m];
   }
-  k.pad[0] = k.pad[1] = 0.0;
-  kin[s] = k;
-  if (cell_sorted) cell_sorted[s] = cell;
+  o.k.pad[0] = o.k.pad[1] = 0.0;
+  return o;
 }
 
-__device__ void make_record(int s, int p, const int32_t* __restrict__ cell_id,
-                            const double* __restrict__ r, const double* __restrict__ q,
-                            const double* __restrict__ semi,
+// Per-particle records of place s in cell order.  M = Rperp^2 I + (Rpar^2 -
+// Rperp^2) a a^T; the 128-B record only when rec is given (the forward
+// search of large systems reads the 64-B copy).
+__device__ __forceinline__ void store_record(int s, const RecStage& st,
+                                             PRec* __restrict__ rec, PRecP* __restrict__ recp,
+                                             double4* __restrict__ pos,
+                                             KRec* __restrict__ kin) {
+  recp[s] = st.p;
+  const PRec o = expand_record(st.p);
+  if (rec) rec[s] = o;
+  pos[s] = make_double4(o.r[0], o.r[1], o.r[2], o.Rmax);
+  kin[s] = st.k;
+}
+
+__device__ void make_record(int s, int p, const double* __restrict__ r,
+                            const double* __restrict__ q, const double* __restrict__ semi,
                             const double* __restrict__ v, const double* __restrict__ w,
                             PRec* __restrict__ rec, PRecP* __restrict__ recp,
-                            double4* __restrict__ pos, KRec* __restrict__ kin,
-                            int32_t* __restrict__ cell_sorted) {
-  make_record_from(s, load_record_input(r, q, semi, v, w, p), cell_sorted ? cell_id[p] : 0,
-                   rec, recp, pos, kin, cell_sorted);
+                            double4* __restrict__ pos, KRec* __restrict__ kin) {
+  store_record(s, stage_record(load_record_input(r, q, semi, v, w, p)), rec, recp, pos, kin);
+}
+
+// Each particle's cell, its ticket in that cell (the count of the cell
+// before its own increment: distinct within the cell, in arbitrary order)
+// and its staged record copies, in input order.  The copies go out through
+// LDS, so that the block's stores are contiguous 16-B pieces rather than
+// one 128-B record per lane (a store instruction would touch 64 lines).
+constexpr int kBinThreads = 256;
+constexpr int kStagePieces = (int)(sizeof(RecStage) / 16);  // 16-B pieces of a copy
+constexpr int kStageStride = kStagePieces + 1;  // LDS stride: no bank conflicts
+static_assert(sizeof(RecStage) == 128, "staged copy: 16 doubles");
+
+__global__ void __launch_bounds__(kBinThreads)
+k_stage_bin(CallDesc d, const double* __restrict__ r,
+                            const double* __restrict__ q,
+                            const double* __restrict__ semi,
+                            const double* __restrict__ v, const double* __restrict__ w,
+                            int32_t* __restrict__ cell_id, int32_t* __restrict__ ticket,
+                            RecStage* __restrict__ staged,
+                            int32_t* __restrict__ cell_count, Counters* cnt,
+                            const Counters* gate, int32_t* __restrict__ bcount) {
+  if (gate && !gate->rebuild) return;  // reused lists: nothing to bin (uniform)
+  __shared__ double2 lds[kBinThreads * kStageStride];
+  const int p0 = blockIdx.x * kBinThreads;
+  const int p = p0 + threadIdx.x;
+  if (p < d.n) {
+    if (bcount) {  // backward counts and kept pairs of the forward search
+      bcount[p] = 0;
+      bcount[d.n + p] = 0;
+    }
+    const double inv_cell[3] = {1.0 / d.cell[0], 1.0 / d.cell[1], 1.0 / d.cell[2]};
+    const RecIn in = load_record_input(r, q, semi, v, w, p);
+    const int c = validate_bin(d, in.u, inv_cell, cnt);
+    cell_id[p] = c;
+    ticket[p] = atomicAdd(&cell_count[c], 1);
+    // the copy in its memory order: r, ax, Rpar, Rperp, then v, w, pad
+    const RecStage st = stage_record(in);
+    double2* row = lds + threadIdx.x * kStageStride;
+    row[0] = make_double2(st.p.r[0], st.p.r[1]);
+    row[1] = make_double2(st.p.r[2], st.p.ax[0]);
+    row[2] = make_double2(st.p.ax[1], st.p.ax[2]);
+    row[3] = make_double2(st.p.Rpar, st.p.Rperp);
+    row[4] = make_double2(st.k.v[0], st.k.v[1]);
+    row[5] = make_double2(st.k.v[2], st.k.w[0]);
+    row[6] = make_double2(st.k.w[1], st.k.w[2]);
+    row[7] = make_double2(st.k.pad[0], st.k.pad[1]);
+  }
+  __syncthreads();
+  const int pieces = min(kBinThreads, d.n - p0) * kStagePieces;
+  double2* out = reinterpret_cast<double2*>(staged + p0);
+  for (int m = threadIdx.x; m < pieces; m += kBinThreads)
+    out[m] = lds[(m / kStagePieces) * kStageStride + m % kStagePieces];
 }
 
 // Each cell's members in increasing input index (the position of a particle
 // is its cell's start plus the number of members with a smaller index), so
-// that every later step is deterministic, and their records.  The cell of
-// each place comes from the scatter, beside the particle: no dependent
-// look-up of the particle's cell.
+// that every later step is deterministic, and their records, moved from the
+// binning's staged copies (one line per particle).  The cell of each place
+// comes from the scatter, beside the particle: no dependent look-up of the
+// particle's cell.
 __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
                                 const int32_t* __restrict__ cell_sorted,
                                 const int32_t* __restrict__ cell_start,
-                                const double* __restrict__ r,
-                                const double* __restrict__ q,
-                                const double* __restrict__ semi,
-                                const double* __restrict__ v,
-                                const double* __restrict__ w, int32_t* __restrict__ sorted,
+                                const RecStage* __restrict__ staged,
+                                int32_t* __restrict__ sorted,
                                 PRec* __restrict__ rec, PRecP* __restrict__ recp,
                                 double4* __restrict__ pos, KRec* __restrict__ kin,
                                 const Counters* gate) {
@@ -366,14 +396,14 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
   if (i >= d.n) return;
   const int p = unsorted[i];
   const int c = cell_sorted[i];  // the cell of place i is the cell of place s
-  // the inputs are fetched while the rank within the cell is counted
-  const RecIn in = load_record_input(r, q, semi, v, w, p);
+  // the staged copy is fetched while the rank within the cell is counted
+  const RecStage st = staged[p];
   const int b = cell_start[c], e = cell_start[c + 1];
   int rank = 0;
   for (int k = b; k < e; ++k) rank += unsorted[k] < p;
   const int s = b + rank;
   sorted[s] = p;
-  make_record_from(s, in, c, rec, recp, pos, kin, nullptr);
+  store_record(s, st, rec, recp, pos, kin);
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
@@ -504,7 +534,7 @@ k_cells_small(CallDesc d, const double* __restrict__ r, const double* __restrict
     sorted[s] = p;
     cell_sorted[s] = c;
     if (d.n <= kSmallRecN)
-      make_record(s, p, nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
+      make_record(s, p, r, q, semi, v, w, rec, recp, pos, kin);
   }
 }
 
@@ -520,7 +550,7 @@ __global__ void k_records_sorted(CallDesc d, const int32_t* __restrict__ sorted,
   if (gate && !gate->rebuild) return;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= d.n) return;
-  make_record(s, sorted[s], nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
+  make_record(s, sorted[s], r, q, semi, v, w, rec, recp, pos, kin);
 }
 
 // A group of G lanes per particle (G = 64: one wavefront; G = 32 or 16: two
@@ -1716,12 +1746,15 @@ void launch_reset(Counters* c, int32_t* cell_count, int ncell, hipStream_t s) {
 }
 
 void launch_stage_bin(const CallDesc& d, const double* r, const double* q,
-                      const double* semi, int32_t* cell_id, int32_t* ticket,
+                      const double* semi, const double* v, const double* w,
+                      int32_t* cell_id, int32_t* ticket, RecStage* staged,
                       int32_t* cell_count, Counters* cnt, const Counters* gate,
                       hipStream_t s, int32_t* bcount) {
   if (d.n == 0) return;
-  hipLaunchKernelGGL(k_stage_bin, dim3((d.n + 255) / 256), dim3(256), 0, s, d,
-                     r, q, semi, cell_id, ticket, cell_count, cnt, gate, bcount);
+  hipLaunchKernelGGL(k_stage_bin, dim3((d.n + kBinThreads - 1) / kBinThreads),
+                     dim3(kBinThreads), 0, s, d,
+                     r, q, semi, v, w, cell_id, ticket, staged, cell_count, cnt, gate,
+                     bcount);
 }
 
 void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
@@ -1750,14 +1783,13 @@ void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id, const int32_
 
 void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           const int32_t* cell_sorted, const int32_t* cell_start,
-                          const double* r, const double* q, const double* semi,
-                          const double* v, const double* w, int32_t* sorted, PRec* rec,
+                          const RecStage* staged, int32_t* sorted, PRec* rec,
                           PRecP* recp, double4* pos, KRec* kin, const Counters* gate,
                           hipStream_t s) {
   if (d.n == 0) return;
   hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
-                     d, unsorted, cell_sorted, cell_start, r, q, semi,
-                     v, w, sorted, rec, recp, pos, kin, gate);
+                     d, unsorted, cell_sorted, cell_start, staged, sorted, rec, recp, pos,
+                     kin, gate);
 }
 
 bool cells_small_fits(const CallDesc& d) {
@@ -1959,7 +1991,7 @@ __global__ void k_refresh(CallDesc d, const double* __restrict__ r,
   if (cnt->rebuild) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
-  make_record(lb.inv[p], p, nullptr, r, q, semi, v, w, rec, recp, pos, kin, nullptr);
+  make_record(lb.inv[p], p, r, q, semi, v, w, rec, recp, pos, kin);
 }
 
 }  // namespace
