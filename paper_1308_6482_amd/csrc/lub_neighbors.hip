@@ -382,8 +382,18 @@ k_stage_bin(CallDesc d, const double* __restrict__ r,
 // that every later step is deterministic, and their records, moved from the
 // binning's staged copies (one line per particle).  The cell of each place
 // comes from the scatter, beside the particle: no dependent look-up of the
-// particle's cell.
-__global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
+// particle's cell.  A particle's position s lies in its cell's range, which
+// holds its own place: almost always inside the block's places, whose 64-B
+// and 32-B copies then go out through LDS as contiguous 16-B pieces (one
+// copy per lane would make each store touch up to 64 lines); a particle
+// whose position lies outside (a cell across the block's edge) is written
+// directly, and its place left out of the block's stores.
+constexpr int kBuildThreads = 256;
+constexpr int kBuildPieces = 10;  // 16-B pieces: the 64-B copy, kinematics, position
+constexpr int kBuildStride = kBuildPieces + 1;  // LDS stride: no bank conflicts
+
+__global__ void __launch_bounds__(kBuildThreads)
+k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
                                 const int32_t* __restrict__ cell_sorted,
                                 const int32_t* __restrict__ cell_start,
                                 const RecStage* __restrict__ staged,
@@ -391,19 +401,55 @@ __global__ void k_build_records(CallDesc d, const int32_t* __restrict__ unsorted
                                 PRec* __restrict__ rec, PRecP* __restrict__ recp,
                                 double4* __restrict__ pos, KRec* __restrict__ kin,
                                 const Counters* gate) {
-  if (gate && !gate->rebuild) return;  // reused lists: nothing to build
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  const int p = unsorted[i];
-  const int c = cell_sorted[i];  // the cell of place i is the cell of place s
-  // the staged copy is fetched while the rank within the cell is counted
-  const RecStage st = staged[p];
-  const int b = cell_start[c], e = cell_start[c + 1];
-  int rank = 0;
-  for (int k = b; k < e; ++k) rank += unsorted[k] < p;
-  const int s = b + rank;
-  sorted[s] = p;
-  store_record(s, st, rec, recp, pos, kin);
+  if (gate && !gate->rebuild) return;  // reused lists: nothing to build (uniform)
+  __shared__ double2 lds[kBuildThreads * kBuildStride];
+  __shared__ int filled[kBuildThreads];
+  const int p0 = blockIdx.x * kBuildThreads;
+  const int nrec = min(kBuildThreads, d.n - p0);
+  const int i = p0 + threadIdx.x;
+  filled[threadIdx.x] = 0;
+  __syncthreads();
+  if (i < d.n) {
+    const int p = unsorted[i];
+    const int c = cell_sorted[i];  // the cell of place i is the cell of place s
+    // the staged copy is fetched while the rank within the cell is counted
+    const RecStage st = staged[p];
+    const int b = cell_start[c], e = cell_start[c + 1];
+    int rank = 0;
+    for (int k = b; k < e; ++k) rank += unsorted[k] < p;
+    const int s = b + rank;
+    sorted[s] = p;
+    const int row = s - p0;
+    if (row >= 0 && row < nrec) {
+      const PRec o = expand_record(st.p);
+      if (rec) rec[s] = o;
+      double2* q = lds + row * kBuildStride;
+      q[0] = make_double2(st.p.r[0], st.p.r[1]);
+      q[1] = make_double2(st.p.r[2], st.p.ax[0]);
+      q[2] = make_double2(st.p.ax[1], st.p.ax[2]);
+      q[3] = make_double2(st.p.Rpar, st.p.Rperp);
+      q[4] = make_double2(st.k.v[0], st.k.v[1]);
+      q[5] = make_double2(st.k.v[2], st.k.w[0]);
+      q[6] = make_double2(st.k.w[1], st.k.w[2]);
+      q[7] = make_double2(st.k.pad[0], st.k.pad[1]);
+      q[8] = make_double2(o.r[0], o.r[1]);
+      q[9] = make_double2(o.r[2], o.Rmax);
+      filled[row] = 1;
+    } else {
+      store_record(s, st, rec, recp, pos, kin);
+    }
+  }
+  __syncthreads();
+  // the block's places, array by array: 64-B copies, kinematics, positions
+  double2* out_p = reinterpret_cast<double2*>(recp + p0);
+  for (int m = threadIdx.x; m < 4 * nrec; m += kBuildThreads)
+    if (filled[m >> 2]) out_p[m] = lds[(m >> 2) * kBuildStride + (m & 3)];
+  double2* out_k = reinterpret_cast<double2*>(kin + p0);
+  for (int m = threadIdx.x; m < 4 * nrec; m += kBuildThreads)
+    if (filled[m >> 2]) out_k[m] = lds[(m >> 2) * kBuildStride + 4 + (m & 3)];
+  double2* out_q = reinterpret_cast<double2*>(pos + p0);
+  for (int m = threadIdx.x; m < 2 * nrec; m += kBuildThreads)
+    if (filled[m >> 1]) out_q[m] = lds[(m >> 1) * kBuildStride + 8 + (m & 1)];
 }
 
 // neighbour offsets along one axis: distinct cells only (a periodic axis
@@ -1787,7 +1833,8 @@ void launch_build_records(const CallDesc& d, const int32_t* unsorted,
                           PRecP* recp, double4* pos, KRec* kin, const Counters* gate,
                           hipStream_t s) {
   if (d.n == 0) return;
-  hipLaunchKernelGGL(k_build_records, dim3((d.n + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_build_records, dim3((d.n + kBuildThreads - 1) / kBuildThreads),
+                     dim3(kBuildThreads), 0, s,
                      d, unsorted, cell_sorted, cell_start, staged, sorted, rec, recp, pos,
                      kin, gate);
 }
