@@ -211,23 +211,34 @@ k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out, int n,
   }
 }
 
-// exclusive scan of the tile totals, in place
-__global__ void __launch_bounds__(kScanThreads)
-k_scan_top(int32_t* block_sums, int nb, int32_t* out, int n, int64_t* total) {
-  __shared__ int chunk[kScanChunk];
-  __shared__ int lds[16];
-  const int tot = block_scan_range(block_sums, block_sums, nb, chunk, lds);
-  if (threadIdx.x == 0) {
-    out[n] = tot;
-    if (total) *total = tot;
-  }
-}
+// Each tile plus the sum of the tile totals before it: every block sums
+// those totals itself (a few hundred, from L2) instead of waiting for a
+// separate scan of them; the last block, which sums them all, writes the
+// grand total.
+constexpr int kAddThreads = 256;
 
-__global__ void k_scan_add(int32_t* out, int n, const int32_t* block_sums) {
-  int add = block_sums[blockIdx.x];
-  const int base = blockIdx.x * kScanTile;
-  for (int k = threadIdx.x; k < kScanTile; k += blockDim.x) {
-    int idx = base + k;
+__global__ void __launch_bounds__(kAddThreads)
+k_scan_add(int32_t* out, int n, const int32_t* block_sums, int nb, int64_t* total) {
+  __shared__ int lds[kAddThreads / 64];
+  const int b = blockIdx.x;
+  const bool last = b == nb - 1;
+  int part = 0;
+  for (int k = threadIdx.x; k < (last ? nb : b); k += kAddThreads) part += block_sums[k];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = part;
+  __syncthreads();
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kAddThreads / 64; ++k) sum += lds[k];
+  const int add = last ? sum - block_sums[b] : sum;
+  if (last && threadIdx.x == 0) {
+    out[n] = sum;
+    if (total) *total = sum;
+  }
+  const int base = b * kScanTile;
+  for (int k = threadIdx.x; k < kScanTile; k += kAddThreads) {
+    const int idx = base + k;
     if (idx < n) out[idx] += add;
   }
 }
@@ -1809,12 +1820,9 @@ void launch_scan(const int32_t* in, int32_t* out, int n, int32_t* block_sums,
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_scan_tile, dim3(nb), dim3(kScanThreads), 0, s, in, out,
                      n, block_sums, total);
-  if (nb > 1) {
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s,
-                       block_sums, nb, out, n, total);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(256), 0, s, out, n,
-                       block_sums);
-  }
+  if (nb > 1)
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kAddThreads), 0, s, out, n, block_sums,
+                       nb, total);
 }
 
 void launch_cell_scatter(const CallDesc& d, const int32_t* cell_id, const int32_t* ticket,
