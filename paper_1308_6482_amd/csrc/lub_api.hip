@@ -86,9 +86,9 @@ struct lub_ctx {
   int8_t* out_status = nullptr;    // [work]
   uint8_t* out_iters = nullptr;    // [work]
   // Two sets of device counters, used by alternate calls: the last kernel
-  // of a call zeroes the other set, and the scatter and record kernels zero
-  // the cell counts and cursors, so a call needs no reset launch when the
-  // previous one ran to the end (`zeroed`).
+  // of a call zeroes the other set, and the scatter zeroes the cell counts,
+  // so a call needs no reset launch when the previous one ran to the end
+  // (`zeroed`).
   Counters* cnt_buf = nullptr;     // device [2]
   Counters* cnt = nullptr;         // the set of the current / last call
   int cnt_idx = 0;
