@@ -52,6 +52,27 @@ def test_static_matches_handle_two_calls():
         assert np.abs(ts - th).max() <= tol * scale_t
 
 
+def test_static_large_path_matches_handle():
+    """Systems beyond the one-workgroup cell build (binning, staged records,
+    scatter, record build): 12,000 then 6,000 prolates, as above."""
+    import torch
+    from paper_1308_6482_amd import lub as L
+    from paper_1308_6482_amd import workloads as W
+    assert torch.cuda.is_available()
+    for n, prec in ((12000, L.LUB_MIXED), (6000, L.LUB_FP64)):
+        wl = W.config2(n=n)
+        print(f"no-alloc: {wl.name} n={wl.n} precision={prec}", flush=True)
+        fs, ts, ss = _static_result(L, wl, prec, torch)
+        fh, th, sh = _handle_result(L, wl, prec, torch)
+        for k in ("candidates", "evaluated", "active", "overlaps", "unconverged"):
+            assert ss[k] == sh[k], (k, ss[k], sh[k])
+        assert ss["error"] == 0 and ss["active"] > 0
+        tol = 1e-12 if prec == L.LUB_FP64 else 1e-6
+        assert np.all(np.isfinite(fs)) and np.all(np.isfinite(ts))
+        assert np.abs(fs - fh).max() <= tol * np.abs(fh).max()
+        assert np.abs(ts - th).max() <= tol * np.abs(th).max()
+
+
 def test_static_rejects_sizes_beyond_the_maximum():
     import torch
     from paper_1308_6482_amd import lub as L
