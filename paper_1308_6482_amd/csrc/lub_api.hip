@@ -577,7 +577,7 @@ int run_desc(lub_ctx* c, const CallDesc& d, const double* r, const double* q,
     mark(3);
     if (side) HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
     launch_gather(d, c->sorted, c->deg, c->nbr, c->slot, c->wall_slot, c->out,
-                  c->cnt, next_cnt, f, t, s, c->bcount, c->work_s, c->work_t);
+                  c->cnt, next_cnt, f, t, s, c->bcount, c->work_s);
     mark(4);
     if (timing) c->pending.push_back(ev);
   }

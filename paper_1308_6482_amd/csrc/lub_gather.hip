@@ -160,9 +160,8 @@ template <typename R>
 __global__ void __launch_bounds__(64 * kRangeWaves) k_gather_ranges(
     CallDesc d, const int32_t* __restrict__ orig, const int32_t* __restrict__ bcount,
     const int32_t* __restrict__ nbr, const int32_t* __restrict__ work_s,
-    const int32_t* __restrict__ work_t, const PairOut<R>* __restrict__ out,
-    const Counters* cnt, Counters* __restrict__ next_cnt, double* __restrict__ f,
-    double* __restrict__ t) {
+    const PairOut<R>* __restrict__ out, const Counters* cnt,
+    Counters* __restrict__ next_cnt, double* __restrict__ f, double* __restrict__ t) {
   constexpr int G = kRangeGroup;
   const int lane = threadIdx.x & 63;
   const int g = lane % G;
@@ -191,11 +190,8 @@ __global__ void __launch_bounds__(64 * kRangeWaves) k_gather_ranges(
   const int c1 = ok ? nbr[rbase + g + G] : 0;
   double acc[6] = {0, 0, 0, 0, 0, 0};
   // the own range: pairs this particle found (either side evaluates) and
-  // its walls
-  for (int w = base + g; w < next; w += G) {
-    const int ws = work_s[w], wt = work_t[w];
-    add_pair(acc, out[w], wt < 0 || ws == s);
-  }
+  // its walls; the evaluating side of each is work_s (s itself for a wall)
+  for (int w = base + g; w < next; w += G) add_pair(acc, out[w], work_s[w] == s);
   // the pairs its partners found
   for (int r = g; r < nk; r += G) {
     const int c = r < G ? c0 : r < 2 * G ? c1 : nbr[rbase + r];
@@ -230,17 +226,16 @@ void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
-                   hipStream_t s, const int32_t* bcount, const int32_t* work_s,
-                   const int32_t* work_t) {
+                   hipStream_t s, const int32_t* bcount, const int32_t* work_s) {
   if (d.n == 0) return;
   if (d.partner_codes == kPartnerRanges) {
     const dim3 grid((d.n + kRangePerBlock - 1) / kRangePerBlock), block(64 * kRangeWaves);
     if (d.precision == LUB_MIXED)
       hipLaunchKernelGGL(k_gather_ranges<float>, grid, block, 0, s, d, orig, bcount, nbr,
-                         work_s, work_t, (const PairOut<float>*)out, cnt, next_cnt, f, t);
+                         work_s, (const PairOut<float>*)out, cnt, next_cnt, f, t);
     else
       hipLaunchKernelGGL(k_gather_ranges<double>, grid, block, 0, s, d, orig, bcount, nbr,
-                         work_s, work_t, (const PairOut<double>*)out, cnt, next_cnt, f, t);
+                         work_s, (const PairOut<double>*)out, cnt, next_cnt, f, t);
     return;
   }
   const bool large = d.n >= (1 << 18);

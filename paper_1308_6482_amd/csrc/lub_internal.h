@@ -339,14 +339,14 @@ void mlp_forward_slots(const Counters* cnt, int cap, const float* X, float* Y,
 void launch_partner_slots(const CallDesc& d, const int32_t* work_s, const int32_t* work_t,
                           const int32_t* deg, const int32_t* nbr, int32_t* slot,
                           const Counters* cnt, hipStream_t s);
-// (bcount, work_s, work_t: read in the layout kPartnerRanges, with the nbr
-// rows, where deg, slot and wall_slot are not)
+// (bcount, work_s: read in the layout kPartnerRanges, with the nbr rows,
+// where deg, slot and wall_slot are not)
 void launch_gather(const CallDesc& d, const int32_t* orig, const int32_t* deg,
                    const int32_t* nbr, const int32_t* slot,
                    const int32_t* wall_slot, const void* out,
                    const Counters* cnt, Counters* next_cnt, double* f, double* t,
                    hipStream_t s, const int32_t* bcount = nullptr,
-                   const int32_t* work_s = nullptr, const int32_t* work_t = nullptr);
+                   const int32_t* work_s = nullptr);
 
 // ---- link-wise laws (lub_link.hip) ------------------------------------------
 int link_grid(const CallDesc& d);
