@@ -347,14 +347,12 @@ constexpr int kStageStride = kStagePieces + 1;  // LDS stride: no bank conflicts
 static_assert(sizeof(RecStage) == 128, "staged copy: 16 doubles");
 
 __global__ void __launch_bounds__(kBinThreads)
-k_stage_bin(CallDesc d, const double* __restrict__ r,
-                            const double* __restrict__ q,
-                            const double* __restrict__ semi,
-                            const double* __restrict__ v, const double* __restrict__ w,
-                            int32_t* __restrict__ cell_id, int32_t* __restrict__ ticket,
-                            RecStage* __restrict__ staged,
-                            int32_t* __restrict__ cell_count, Counters* cnt,
-                            const Counters* gate, int32_t* __restrict__ bcount) {
+k_stage_bin(CallDesc d, const double* __restrict__ r, const double* __restrict__ q,
+            const double* __restrict__ semi, const double* __restrict__ v,
+            const double* __restrict__ w, int32_t* __restrict__ cell_id,
+            int32_t* __restrict__ ticket, RecStage* __restrict__ staged,
+            int32_t* __restrict__ cell_count, Counters* cnt, const Counters* gate,
+            int32_t* __restrict__ bcount) {
   if (gate && !gate->rebuild) return;  // reused lists: nothing to bin (uniform)
   __shared__ double2 lds[kBinThreads * kStageStride];
   const int p0 = blockIdx.x * kBinThreads;
@@ -405,13 +403,10 @@ constexpr int kBuildStride = kBuildPieces + 1;  // LDS stride: no bank conflicts
 
 __global__ void __launch_bounds__(kBuildThreads)
 k_build_records(CallDesc d, const int32_t* __restrict__ unsorted,
-                                const int32_t* __restrict__ cell_sorted,
-                                const int32_t* __restrict__ cell_start,
-                                const RecStage* __restrict__ staged,
-                                int32_t* __restrict__ sorted,
-                                PRec* __restrict__ rec, PRecP* __restrict__ recp,
-                                double4* __restrict__ pos, KRec* __restrict__ kin,
-                                const Counters* gate) {
+                const int32_t* __restrict__ cell_sorted, const int32_t* __restrict__ cell_start,
+                const RecStage* __restrict__ staged, int32_t* __restrict__ sorted,
+                PRec* __restrict__ rec, PRecP* __restrict__ recp, double4* __restrict__ pos,
+                KRec* __restrict__ kin, const Counters* gate) {
   if (gate && !gate->rebuild) return;  // reused lists: nothing to build (uniform)
   __shared__ double2 lds[kBuildThreads * kBuildStride];
   __shared__ int filled[kBuildThreads];
