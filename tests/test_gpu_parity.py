@@ -270,6 +270,38 @@ def test_edge_cases(ref):
     assert ef.max() < 1e-9 and et.max() < 1e-9
 
 
+def test_sparse_large_grid(ref):
+    """96 prolates in close pairs scattered over a periodic 3000^3 box: a
+    grid of millions of cells for few particles, so the multi-kernel cell
+    build runs on one partial block and the cell scan on hundreds of tiles;
+    some pairs straddle the periodic faces."""
+    rng = np.random.default_rng(11)
+    L_ = 3000.0
+    r, q = [], []
+    for k in range(48):
+        c = rng.uniform(0.0, L_, size=3)
+        if k % 8 == 0:
+            c[k % 3] = L_ - 2.0  # the partner lies across the face
+        h = rng.uniform(0.005, 0.6)
+        off = np.zeros(3)
+        ax = (k + 1) % 3
+        off[ax] = (16.0 if ax == 2 else 8.0) + h  # tip to tip along the axis z
+        for x in (c, np.mod(c + off, L_)):
+            r.append(x)
+            q.append([1.0, 0.0, 0.0, 0.0])
+    n = len(r)
+    wl = small("sparse", r, q, [[8.0, 4.0]] * n, rng.normal(size=(n, 3)),
+               rng.normal(size=(n, 3)), L_=(L_, L_, L_), h_c=0.01, eps_c=100.0)
+    for prec, tol in ((L.LUB_FP64, 1e-9), (L.LUB_MIXED, 1e-5)):
+        g = run_gpu(wl, prec)
+        o = run_oracle(ref, wl)
+        check_pairs(g, o)
+        assert g["stats"]["error"] == 0
+        assert g["stats"]["active"] == o["stats"]["active"] > 0
+        ef, et = particle_errors(g, o)
+        assert ef.max() < tol and et.max() < tol, (prec, ef.max(), et.max())
+
+
 def test_empty_input():
     lb = L.Lub((50, 50, 50), (1, 1, 1), dict(mu=1, delta_n=0.67, delta_t=0.5,
                                              delta_r=0.25), 4.0)
