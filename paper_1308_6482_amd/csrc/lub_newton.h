@@ -20,6 +20,17 @@
 #define __forceinline__ inline
 #endif
 
+// 1 / sqrt(x): on the device the reciprocal square root, one correctly
+// refined sequence instead of a square root and a division; the host build
+// of the header divides.
+__host__ __device__ __forceinline__ double inv_sqrt(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return rsqrt(x);
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
 // backtracking trials and sufficient-increase constant of the line search
 // (a host test build overrides them to force an exhausted search)
 #ifndef LUB_LINE_SEARCH_TRIALS
@@ -66,7 +77,7 @@ __host__ __device__ __forceinline__ void perp(const double n[3], double t[3]) {
     t[1] = -n[0];
     t[2] = 0.0;
   }
-  double inv = 1.0 / sqrt(dot3(t, t));
+  double inv = inv_sqrt(dot3(t, t));
   t[0] *= inv;
   t[1] *= inv;
   t[2] *= inv;
@@ -131,9 +142,10 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     double a[3], b[3];
     symv(Mi, n, a);
     symv(Mj, n, b);
-    hi = sqrt(dot3(n, a));
-    hj = sqrt(dot3(n, b));
-    double ih = 1.0 / hi, jh = 1.0 / hj;
+    const double qi = dot3(n, a), qj = dot3(n, b);
+    hi = sqrt(qi);
+    hj = sqrt(qj);
+    const double ih = inv_sqrt(qi), jh = inv_sqrt(qj);
     for (int k = 0; k < 3; ++k) {
       ai[k] = a[k] * ih;
       bj[k] = b[k] * jh;
@@ -172,9 +184,9 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
       H11 -= lmax + floor_;
       H22 -= lmax + floor_;
     }
-    double det = H11 * H22 - H12 * H12;
-    double s1 = -(H22 * r1 - H12 * r2) / det;
-    double s2 = -(H11 * r2 - H12 * r1) / det;
+    const double idet = 1.0 / (H11 * H22 - H12 * H12);
+    double s1 = -(H22 * r1 - H12 * r2) * idet;
+    double s2 = -(H11 * r2 - H12 * r1) * idet;
     double len = sqrt(s1 * s1 + s2 * s2);
     if (len > 0.5) {
       s1 *= 0.5 / len;
@@ -211,7 +223,7 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     last_full = alpha == 1.0;
     double m[3];
     for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
-    double inv = 1.0 / sqrt(dot3(m, m));
+    const double inv = inv_sqrt(dot3(m, m));
     for (int k = 0; k < 3; ++k) n[k] = m[k] * inv;
   }
   for (int k = 0; k < 3; ++k) {

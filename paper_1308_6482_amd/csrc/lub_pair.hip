@@ -124,16 +124,17 @@ __host__ __device__ __forceinline__ bool seed_normal(const double d[3], const PR
   const double nbj[3] = {cos((double)Y[2]) * cos((double)Y[3]) / B.Rperp,
                          cos((double)Y[2]) * sin((double)Y[3]) / B.Rperp,
                          sin((double)Y[2]) / B.Rpar};
-  const double li = sqrt(dot3(nbi, nbi)), lj = sqrt(dot3(nbj, nbj));
+  const double ili = inv_sqrt(dot3(nbi, nbi)), ilj = inv_sqrt(dot3(nbj, nbj));
   for (int a = 0; a < 3; ++a)
     for (int k = 0; k < 3; ++k) {
-      ni[k] += Fi[a][k] * nbi[a] / li;
-      nj[k] += Fj[a][k] * nbj[a] / lj;
+      ni[k] += Fi[a][k] * (nbi[a] * ili);
+      nj[k] += Fj[a][k] * (nbj[a] * ilj);
     }
   double m[3] = {ni[0] - nj[0], ni[1] - nj[1], ni[2] - nj[2]};
-  const double mn = sqrt(dot3(m, m));
-  if (!(mn > 1e-6) || !(dot3(m, d) > 0.0)) return false;
-  for (int k = 0; k < 3; ++k) n0[k] = m[k] / mn;
+  const double mn2 = dot3(m, m);
+  if (!(mn2 > 1e-12) || !(dot3(m, d) > 0.0)) return false;
+  const double imn = inv_sqrt(mn2);
+  for (int k = 0; k < 3; ++k) n0[k] = m[k] * imn;
   return true;
 }
 
@@ -149,13 +150,14 @@ __host__ __device__ __forceinline__ void latitude(const double n[3],
   cross3(n, ax, x);
   double rho = sqrt(dot3(x, x));
   double a = Rpe * rho, b = Rpa * c;
-  double nr = sqrt(a * a + b * b);
-  *cp = a / nr;
-  *sp = b / nr;
+  const double inr = inv_sqrt(a * a + b * b);
+  *cp = a * inr;
+  *sp = b * inr;
   double t[3] = {ax[0] - c * n[0], ax[1] - c * n[1], ax[2] - c * n[2]};
-  double tl = sqrt(dot3(t, t));
-  if (tl > 1e-12) {
-    for (int k = 0; k < 3; ++k) e1[k] = t[k] / tl;
+  const double tl2 = dot3(t, t);
+  if (tl2 > 1e-24) {
+    const double itl = inv_sqrt(tl2);
+    for (int k = 0; k < 3; ++k) e1[k] = t[k] * itl;
   } else {
     perp(n, e1);  // pole: S1 = S2 and Gamma = 0, any tangent will do
   }
@@ -167,12 +169,15 @@ __host__ __device__ __forceinline__ void radii(R Rpa, R Rpe, R cp, R sp, R* S1, 
                                       R* G0, R* G2) {
   R s1sq = Rpe * Rpe * sp * sp + Rpa * Rpa * cp * cp;
   R s1 = sqrt(s1sq);
-  *S1 = s1sq * s1 / (Rpa * Rpe);
-  *S2 = Rpe * s1 / Rpa;
+  // two divisions: 1 / (Rpa Rpe) and 1 / (2 Rpe s1^6)
+  const R iab = R(1) / (Rpa * Rpe);
+  *S1 = s1sq * s1 * iab;
+  *S2 = Rpe * Rpe * s1 * iab;
   R num = (Rpa * Rpa - Rpe * Rpe) * Rpa * sp * cp;
   R s4 = s1sq * s1sq;
-  *G0 = num * Rpe / (R(2) * s4 * s1sq);
-  *G2 = num / (R(2) * Rpe * s4);
+  const R iw = R(1) / (R(2) * Rpe * s4 * s1sq);
+  *G0 = num * Rpe * Rpe * iw;
+  *G2 = num * s1sq * iw;
 }
 
 // cubic coefficients a (given in axes rotated by +alpha) in unrotated axes
