@@ -332,7 +332,8 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
   // chi: eigenvector of l1 is (cos chi, -sin chi)
   double dc = 1.0, ds = 0.0;
   if (rad > 0.0) {
-    double c2x = half / rad, s2x = -m12 / rad;
+    const double irad = 1.0 / rad;
+    double c2x = half * irad, s2x = -m12 * irad;
     if (c2x >= 0.0) {
       dc = sqrt(0.5 * (1.0 + c2x));
       ds = s2x / (2.0 * dc);
@@ -349,15 +350,19 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
   R kk[4] = {G0 + beta[0], beta[1], G2 + beta[2], beta[3]};
   R mk[4];
   rotate_cubic(c, s, kk, mk);
+  // the divisions by sqrt(l), l, A and B as products with their reciprocals
   R q1 = sqrt(l1), q2 = sqrt(l2);
-  R k0 = mk[0] / (q1 * q1 * q1), k1 = mk[1] / (q1 * q1 * q2);
-  R k2 = mk[2] / (q1 * q2 * q2), k3 = mk[3] / (q2 * q2 * q2);
+  const R iq1 = R(1) / q1, iq2 = R(1) / q2;
+  const R il1 = iq1 * iq1, il2 = iq2 * iq2;
+  R k0 = mk[0] * (il1 * iq1), k1 = mk[1] * (il1 * iq2);
+  R k2 = mk[2] * (iq1 * il2), k3 = mk[3] * (il2 * iq2);
 
-  R sl = q1 * q2, lsum = l1 + l2;
+  R lsum = l1 + l2;
   R A = R(3) * l1 + R(2) * l2, B = R(2) * l1 + R(3) * l2;
-  R p1 = R(1) / (A * l1), p2 = R(1) / (B * l2);
+  const R iA = R(1) / A, iB = R(1) / B;
+  R p1 = iA * il1, p2 = iB * il2;
   R cc = c * c, ss = s * s, sc = s * c;
-  R isl = R(1) / sl;
+  R isl = iq1 * iq2;
   R u1 = R(1) - l1 * S1, u2 = R(1) - l2 * S1;
   R w1 = R(1) - l1 * S2, w2 = R(1) - l2 * S2;
   R iS1 = R(1) / S1, iS2 = R(1) / S2;
@@ -377,17 +382,17 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
   R Qb = (R(2) * l1 + l2) * k1 + (R(2) * l1 + R(7) * l2) * k3;
   R Pa = R(3) * k0 * l1 + k2 * l2;
   R Pb = k1 * l1 + R(3) * k3 * l2;
-  R ra = Qa / (q1 * A), rb = Qb / (q2 * B);
+  R ra = Qa * (iq1 * iA), rb = Qb * (iq2 * iB);
   C[10] = R(0.75) * f3 * (rb * c - ra * s);
   C[11] = -R(0.75) * f3 * (ra * c + rb * s);
-  R g0 = cc / l1 + ss / l2, g2 = ss / l1 + cc / l2, gx = sc * (R(1) / l2 - R(1) / l1);
-  R t13 = (R(2) * q1 * Pa - R(1.5) * iS1 * Qa / q1) * c / A +
-          (R(2) * q2 * Pb - R(1.5) * iS1 * Qb / q2) * s / B + R(3) * G0 * g0 + G2 * g2;
-  R t23 = (-R(2) * q1 * Pa + R(1.5) * iS2 * Qa / q1) * s / A +
-          (R(2) * q2 * Pb - R(1.5) * iS2 * Qb / q2) * c / B + R(2) * G2 * gx;
+  R g0 = cc * il1 + ss * il2, g2 = ss * il1 + cc * il2, gx = sc * (il2 - il1);
+  R t13 = (R(2) * q1 * Pa - R(1.5) * iS1 * Qa * iq1) * c * iA +
+          (R(2) * q2 * Pb - R(1.5) * iS1 * Qb * iq2) * s * iB + R(3) * G0 * g0 + G2 * g2;
+  R t23 = (-R(2) * q1 * Pa + R(1.5) * iS2 * Qa * iq1) * s * iA +
+          (R(2) * q2 * Pb - R(1.5) * iS2 * Qb * iq2) * c * iB + R(2) * G2 * gx;
   C[2] = -R(0.5) * f3 * t13;
   C[6] = -R(0.5) * f3 * t23;
-  C[12] = -R(0.5) * f3 * sc * (iS1 - iS2) * (R(1) / l1 - R(1) / l2);
+  C[12] = -R(0.5) * f3 * sc * (iS1 - iS2) * (il1 - il2);
   // rotation-rotation
   C[13] = -R(3) * pi * isl * (ss * p1 + cc * p2);
   C[14] = R(3) * pi * isl * sc * (p2 - p1);
