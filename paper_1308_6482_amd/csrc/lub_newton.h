@@ -133,7 +133,7 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
   double n[3];
   plain_start(d, Mi, Mj, n);
   for (int k = 0; k < 3; ++k) n[k] = use_n0 ? n0[k] : n[k];
-  double prev = 1.0;
+  double prev2 = 1.0;  // squared length of the last step
   bool last_full = false;
   o.ok = false;
   int it = 0;
@@ -142,10 +142,11 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     double a[3], b[3];
     symv(Mi, n, a);
     symv(Mj, n, b);
+    // h = q / sqrt(q): one reciprocal square root per body
     const double qi = dot3(n, a), qj = dot3(n, b);
-    hi = sqrt(qi);
-    hj = sqrt(qj);
     const double ih = inv_sqrt(qi), jh = inv_sqrt(qj);
+    hi = qi * ih;
+    hj = qj * jh;
     for (int k = 0; k < 3; ++k) {
       ai[k] = a[k] * ih;
       bj[k] = b[k] * jh;
@@ -160,7 +161,7 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     // converged: the tangential residual at round-off, or a full Newton step
     // below 1e-8 (quadratic convergence leaves an error of its square); a
     // step shortened by the line search says nothing about convergence
-    if ((prev < 1e-8 && last_full) || r1 * r1 + r2 * r2 <= tol * tol) {
+    if ((prev2 < 1e-16 && last_full) || r1 * r1 + r2 * r2 <= tol * tol) {
       o.ok = true;
       break;
     }
@@ -187,16 +188,18 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
     const double idet = 1.0 / (H11 * H22 - H12 * H12);
     double s1 = -(H22 * r1 - H12 * r2) * idet;
     double s2 = -(H11 * r2 - H12 * r1) * idet;
-    double len = sqrt(s1 * s1 + s2 * s2);
-    if (len > 0.5) {
-      s1 *= 0.5 / len;
-      s2 *= 0.5 / len;
-      len = 0.5;
+    // the step's length is compared squared: a square root only to shorten it
+    double len2 = s1 * s1 + s2 * s2;
+    if (len2 > 0.25) {
+      const double f = 0.5 * inv_sqrt(len2);
+      s1 *= f;
+      s2 *= f;
+      len2 = 0.25;
     }
     // Armijo backtracking on g along the (ascent) direction; skipped in the
     // quadratic basin where the full step is always taken
     double alpha = 1.0;
-    if (len > 1e-3) {
+    if (len2 > 1e-6) {
       const double g0 = gn;  // g(n) = n.d - h_i - h_j
       const double slope = r1 * s1 + r2 * s2;
       bool ascent = false;
@@ -219,7 +222,7 @@ __host__ __device__ __forceinline__ Solve closest_points(const double d[3],
       // starts again from another seed or takes the tangent-sphere pass)
       if (!ascent) break;
     }
-    prev = alpha * len;
+    prev2 = alpha * alpha * len2;
     last_full = alpha == 1.0;
     double m[3];
     for (int k = 0; k < 3; ++k) m[k] = n[k] + alpha * (s1 * t1[k] + s2 * t2[k]);
