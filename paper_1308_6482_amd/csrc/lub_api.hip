@@ -374,6 +374,7 @@ int build_desc(lub_ctx* c, int64_t n, CallDesc* d) {
   d->q_bar = c->prm.q_bar;
   d->ln_delta_t = std::log(c->prm.delta_t);
   d->ln_delta_r = std::log(c->prm.delta_r);
+  d->inv_delta_n = 1.0 / c->prm.delta_n;
   if (is_link(d->model)) {
     // FP64 outputs; lattice images need integer periodic lengths
     d->precision = LUB_FP64;

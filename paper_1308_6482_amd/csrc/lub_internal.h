@@ -160,6 +160,7 @@ struct CallDesc {
   double mu, delta_n, delta_t, delta_r, h_c, eps_c;
   double q_bar;          // weight of the link-wise laws
   double ln_delta_t, ln_delta_r;  // log of the cut-offs (host-evaluated once)
+  double inv_delta_n;             // 1 / Delta_n (host-evaluated once)
   int32_t max_iter;
   int32_t max_nbr;       // neighbour-segment stride (entries per particle)
   double newton_tol;     // relative tangential residual of the Newton solve

@@ -107,16 +107,17 @@ __host__ __device__ __forceinline__ void plain_start(const double d[3], const do
   const double m0 = (e * g - f * f) * d[0] + (c * f - b * g) * d[1] + (b * f - c * e) * d[2];
   const double m1 = (c * f - b * g) * d[0] + (a * g - c * c) * d[1] + (b * c - a * f) * d[2];
   const double m2 = (b * f - c * e) * d[0] + (b * c - a * f) * d[1] + (a * e - b * b) * d[2];
-  const double mn = sqrt(m0 * m0 + m1 * m1 + m2 * m2);
-  if (mn > 0.0 && m0 * d[0] + m1 * d[1] + m2 * d[2] > 0.0) {
-    n[0] = m0 / mn;
-    n[1] = m1 / mn;
-    n[2] = m2 / mn;
+  const double mn2 = m0 * m0 + m1 * m1 + m2 * m2;
+  if (mn2 > 0.0 && m0 * d[0] + m1 * d[1] + m2 * d[2] > 0.0) {
+    const double im = inv_sqrt(mn2);
+    n[0] = m0 * im;
+    n[1] = m1 * im;
+    n[2] = m2 * im;
   } else {
-    const double dn = sqrt(dot3(d, d));
-    n[0] = d[0] / dn;
-    n[1] = d[1] / dn;
-    n[2] = d[2] / dn;
+    const double id = inv_sqrt(dot3(d, d));
+    n[0] = d[0] * id;
+    n[1] = d[1] * id;
+    n[2] = d[2] * id;
   }
 }
 

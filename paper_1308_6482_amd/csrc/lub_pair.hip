@@ -316,14 +316,14 @@ __host__ __device__ __forceinline__ void rotate_cubic(R c, R s, const R a[4], R 
 // The 16 singular coefficients: K = C ln h (C33 / h for the normal one).
 // Index order 11 12 13 14 15 22 23 24 25 33 34 35 36 44 45 55.
 template <typename R>
-__host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p,
-                                         R iS2p, R G0p, R G2p, R cph, R sph,
-                                         R C[16]) {
+__host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, double iS1d, double iS2d, R G0,
+                                         R G2, R iS1p, R iS2p, R G0p, R G2p, R cph,
+                                         R sph, R C[16]) {
   const R pi = R(kPi);
   // quadratic gap matrix and its eigen-decomposition: a few flops, in FP64
   // (errors in chi propagate into every coupling term)
-  double m11 = 0.5 / (double)S1 + 0.5 * ((double)cph * cph * iS1p + (double)sph * sph * iS2p);
-  double m22 = 0.5 / (double)S2 + 0.5 * ((double)sph * sph * iS1p + (double)cph * cph * iS2p);
+  double m11 = 0.5 * iS1d + 0.5 * ((double)cph * cph * iS1p + (double)sph * sph * iS2p);
+  double m22 = 0.5 * iS2d + 0.5 * ((double)sph * sph * iS1p + (double)cph * cph * iS2p);
   double m12 = 0.5 * (double)sph * cph * ((double)iS1p - iS2p);
   double half = 0.5 * (m11 - m22);
   double rad = sqrt(half * half + m12 * m12);
@@ -365,7 +365,7 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, R G0, R G2, R iS1p
   R isl = iq1 * iq2;
   R u1 = R(1) - l1 * S1, u2 = R(1) - l2 * S1;
   R w1 = R(1) - l1 * S2, w2 = R(1) - l2 * S2;
-  R iS1 = R(1) / S1, iS2 = R(1) / S2;
+  const R iS1 = R(iS1d), iS2 = R(iS2d);
   // translation-translation and translation-rotation (curvature only)
   C[0] = -pi * isl * iS1 * iS1 * (R(3) * cc * u1 * u1 * p1 + R(3) * ss * u2 * u2 * p2 + S1 * S1);
   C[1] = R(3) * pi * isl * iS1 * iS2 * sc * (u1 * w1 * p1 - u2 * w2 * p2);
@@ -443,7 +443,7 @@ __host__ __device__ void ladd_pair(const CallDesc& cd, const PRec& A, const KRec
   status = 0;
   const double un = n[0] * (vj[0] - KA.v[0]) + n[1] * (vj[1] - KA.v[1]) +
                     n[2] * (vj[2] - KA.v[2]);
-  double fn = cd.mu * 6.0 * kPi * g * g * (1.0 / heff - 1.0 / cd.delta_n) * un;
+  double fn = cd.mu * 6.0 * kPi * g * g * (1.0 / heff - cd.inv_delta_n) * un;
   if (h <= cd.h_c) fn -= h > 0.0 ? cd.eps_c * (cd.h_c - h) : cd.eps_c * cd.h_c;
   for (int k = 0; k < 3; ++k) out.F[k] = R(fn * n[k]);
 }
@@ -576,8 +576,8 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
     sph = dot3(e1p, e2);
   }
   R C[16];
-  k_coeffs<R>(R(S1), R(S2), R(G0), R(G2), R(iS1p), R(iS2p), R(G0p), R(G2p),
-              R(cph), R(sph), C);
+  k_coeffs<R>(R(S1), R(S2), 1.0 / S1, 1.0 / S2, R(G0), R(G2), R(iS1p), R(iS2p), R(G0p),
+              R(G2p), R(cph), R(sph), C);
 
   // cut-off factors (FP64), Eq. lub:resistance-correction; the "normal
   // only" model drops every element but K33
@@ -587,7 +587,7 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   double Lr = full && heff < cd.delta_r ? lh - cd.ln_delta_r : 0.0;
   // the contact-only law has no resistance: the repulsion below acts alone
   const bool lub = cd.model != LUB_MODEL_CONTACT;
-  double Ln = lub && heff < cd.delta_n ? 1.0 / heff - 1.0 / cd.delta_n : 0.0;
+  double Ln = lub && heff < cd.delta_n ? 1.0 / heff - cd.inv_delta_n : 0.0;
   if (det) {
     // the frame's x1 axis and the corrective elements K~ = C (ln h_eff - ln
     // Delta) or C33 (1/h_eff - 1/Delta_n), as the transfer below uses them
