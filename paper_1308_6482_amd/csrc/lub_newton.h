@@ -30,6 +30,13 @@ __host__ __device__ __forceinline__ double inv_sqrt(double x) {
   return 1.0 / sqrt(x);
 #endif
 }
+__host__ __device__ __forceinline__ float inv_sqrt(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return rsqrtf(x);
+#else
+  return 1.0f / sqrtf(x);
+#endif
+}
 
 // backtracking trials and sufficient-increase constant of the line search
 // (a host test build overrides them to force an exhausted search)

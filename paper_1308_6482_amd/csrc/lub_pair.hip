@@ -163,21 +163,24 @@ __host__ __device__ __forceinline__ void latitude(const double n[3],
   }
 }
 
-// principal radii and the two non-zero cubic coefficients of a spheroid
+// principal radii, their reciprocals and the two non-zero cubic
+// coefficients of a spheroid (two divisions: 1 / (Rpa Rpe), 1 / (s1^3 Rpe))
 template <typename R>
 __host__ __device__ __forceinline__ void radii(R Rpa, R Rpe, R cp, R sp, R* S1, R* S2,
-                                      R* G0, R* G2) {
+                                      R* iS1, R* iS2, R* G0, R* G2) {
   R s1sq = Rpe * Rpe * sp * sp + Rpa * Rpa * cp * cp;
   R s1 = sqrt(s1sq);
-  // two divisions: 1 / (Rpa Rpe) and 1 / (2 Rpe s1^6)
+  const R s3 = s1sq * s1;
   const R iab = R(1) / (Rpa * Rpe);
-  *S1 = s1sq * s1 * iab;
-  *S2 = Rpe * Rpe * s1 * iab;
+  const R x = R(1) / (s3 * Rpe);
+  *S1 = s3 * iab;                 // s1^3 / (Rpa Rpe)
+  *S2 = Rpe * Rpe * s1 * iab;     // Rpe s1 / Rpa
+  *iS1 = Rpa * Rpe * Rpe * x;     // Rpa Rpe / s1^3
+  *iS2 = Rpa * s1sq * x;          // Rpa / (Rpe s1)
   R num = (Rpa * Rpa - Rpe * Rpe) * Rpa * sp * cp;
-  R s4 = s1sq * s1sq;
-  const R iw = R(1) / (R(2) * Rpe * s4 * s1sq);
-  *G0 = num * Rpe * Rpe * iw;
-  *G2 = num * s1sq * iw;
+  const R x2 = x * x;             // 1 / (s1^6 Rpe^2)
+  *G0 = R(0.5) * num * Rpe * Rpe * Rpe * x2;  // num Rpe / (2 s1^6)
+  *G2 = R(0.5) * num * s1sq * Rpe * x2;       // num / (2 Rpe s1^4)
 }
 
 // cubic coefficients a (given in axes rotated by +alpha) in unrotated axes
@@ -236,8 +239,8 @@ __host__ __device__ __forceinline__ double sph_radius(const PRec& P, const doubl
   const double l = sqrt(sp * sp + cp * cp);
   sp /= l;
   cp /= l;
-  double S1, S2, G0, G2;
-  radii<double>(P.Rpar, P.Rperp, cp, sp, &S1, &S2, &G0, &G2);
+  double S1, S2, iS1, iS2, G0, G2;
+  radii<double>(P.Rpar, P.Rperp, cp, sp, &S1, &S2, &iS1, &iS2, &G0, &G2);
   return fmin(S1, S2);
 }
 
@@ -351,8 +354,8 @@ __host__ __device__ __forceinline__ void k_coeffs(R S1, R S2, double iS1d, doubl
   R mk[4];
   rotate_cubic(c, s, kk, mk);
   // the divisions by sqrt(l), l, A and B as products with their reciprocals
-  R q1 = sqrt(l1), q2 = sqrt(l2);
-  const R iq1 = R(1) / q1, iq2 = R(1) / q2;
+  const R iq1 = inv_sqrt(l1), iq2 = inv_sqrt(l2);
+  const R q1 = l1 * iq1, q2 = l2 * iq2;
   const R il1 = iq1 * iq1, il2 = iq2 * iq2;
   R k0 = mk[0] * (il1 * iq1), k1 = mk[1] * (il1 * iq2);
   R k2 = mk[2] * (iq1 * il2), k3 = mk[3] * (il2 * iq2);
@@ -562,21 +565,20 @@ __host__ __device__ void eval_pair(const CallDesc& cd, const PRec& A, const KRec
   cross3(n, e1, e2);
   double S1, S2, G0, G2, iS1p = 0.0, iS2p = 0.0, G0p = 0.0, G2p = 0.0;
   double cph = 1.0, sph = 0.0;
-  radii<double>(A.Rpar, A.Rperp, cpi, spi, &S1, &S2, &G0, &G2);
+  double iS1, iS2;
+  radii<double>(A.Rpar, A.Rperp, cpi, spi, &S1, &S2, &iS1, &iS2, &G0, &G2);
   if (pair) {
     // surface j: outward normal -n; its x1' lies in the same tangent plane
     double cpj, spj, e1p[3];
     const double nj[3] = {-n[0], -n[1], -n[2]};
     latitude(nj, Bp.ax, Bp.Rpar, Bp.Rperp, &cpj, &spj, e1p);
     double S1p, S2p;
-    radii<double>(Bp.Rpar, Bp.Rperp, cpj, spj, &S1p, &S2p, &G0p, &G2p);
-    iS1p = 1.0 / S1p;
-    iS2p = 1.0 / S2p;
+    radii<double>(Bp.Rpar, Bp.Rperp, cpj, spj, &S1p, &S2p, &iS1p, &iS2p, &G0p, &G2p);
     cph = dot3(e1p, e1);
     sph = dot3(e1p, e2);
   }
   R C[16];
-  k_coeffs<R>(R(S1), R(S2), 1.0 / S1, 1.0 / S2, R(G0), R(G2), R(iS1p), R(iS2p), R(G0p),
+  k_coeffs<R>(R(S1), R(S2), iS1, iS2, R(G0), R(G2), R(iS1p), R(iS2p), R(G0p),
               R(G2p), R(cph), R(sph), C);
 
   // cut-off factors (FP64), Eq. lub:resistance-correction; the "normal
